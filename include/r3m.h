@@ -1,0 +1,241 @@
+/*
+ * r3m.h -- C ABI of the retrieved-matvec library for MI355X (gfx950).
+ *
+ * Method: recurrence rebuild and retrieval with hierarchical pattern
+ * exploitation (R3M-HPE, arXiv 2112.05082).  Every coding unit of a digital
+ * coding metasurface is replaced by the macro unit, the union of all its
+ * coding states (Sec. III-A), so the array is rigorously periodic and the
+ * Galerkin EFIE matrix of eq. (1) -- the global matrix Z -- depends only on
+ * the lattice displacement d = (dx, dy) between observer and source units.
+ * The global matrix is therefore stored once as unique displacement blocks,
+ * the finest 1x1 pattern (offset, src, obs) of eq. (7) (Sec. III-C): dense
+ * near blocks and low-rank far blocks U V^H (Sec. II-B).  A codebook k is
+ * applied through implicit retrieval, y_k = P_k^T Z P_k x_k (eq. (3)), i.e.
+ * the D_k mask of eq. (6), realised as a per-unit state byte that selects
+ * the active rows and columns of each block.  The retrieved system is solved
+ * with an MVP-based Krylov method (Sec. III-A, last paragraph).
+ *
+ * Conventions
+ *  - Every function returns an int status (R3M_OK or a negative R3M_ERR_*).
+ *    No C++ exception crosses the ABI.  r3m_last_error() gives detail.
+ *  - The library never allocates user-visible device memory.  Outputs and
+ *    workspaces are caller-owned device pointers sized by the *_bytes
+ *    queries; host arrays are caller-owned and only read during the call.
+ *  - Every call takes a caller-owned hipStream_t and is asynchronous on it,
+ *    except calls that return host data (noted), which synchronise it.
+ *  - Shapes, ranges and pointers are validated on the host before any launch.
+ *  - Complex values are interleaved (re, im): R3M_C128 = 2 x double,
+ *    R3M_C64 = 2 x float.
+ *  - Units: metres, hertz.  Time convention exp(+j w t).
+ *  - Unit index u = iy*L + ix; unit u sits at (ix*period_x, iy*period_y, 0).
+ *  - Displacement slot of d = (dx, dy) in a store of half-extent (Dx, Dy):
+ *        slot(d) = (dy + Dy)*(2*Dx + 1) + (dx + Dx).
+ *  - Macro basis order is state-major: state s owns the contiguous RWG range
+ *    [state_off[s], state_off[s+1]); all states must own n_a = n/n_states.
+ *  - Reduced (retrieved) vectors are [unit][n_a]: the column order of P_k.
+ */
+#ifndef R3M_H
+#define R3M_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  R3M_OK = 0,
+  R3M_ERR_INVALID_ARG = -1,
+  R3M_ERR_BUFFER_TOO_SMALL = -2,
+  R3M_ERR_HIP = -3,
+  R3M_ERR_NOT_CONVERGED = -4, /* outputs are still written */
+  R3M_ERR_NONFINITE = -5,
+  R3M_ERR_UNSUPPORTED = -6
+};
+
+typedef enum {
+  R3M_C128 = 0,   /* complex double */
+  R3M_C64 = 1,    /* complex float, FP32 accumulation */
+  R3M_BF16X2 = 2, /* far factors only: hi/lo bfloat16 split, FP32 accumulation */
+  R3M_F16X2 = 3   /* far factors only: hi/lo float16 split with a per-column scale */
+} r3m_dtype;
+
+typedef struct r3m_ctx_s* r3m_ctx;
+
+/* Creates a context bound to HIP device `device`.  Returns R3M_ERR_HIP if the
+ * device cannot be selected (e.g. no GPU visible). */
+int r3m_ctx_create(r3m_ctx* out, int device);
+int r3m_ctx_destroy(r3m_ctx ctx);
+/* Last error message of ctx (or of the calling thread when ctx is NULL). */
+const char* r3m_last_error(r3m_ctx ctx);
+/* Library version string. */
+const char* r3m_version(void);
+
+/* Geometry of the macro unit (host memory, read during the call).
+ * The macro unit is the union of its coding states (Sec. III-A): state s owns
+ * RWG [state_off[s], state_off[s+1]).  rwg[m] = {T+, T-, edge vertex 0, edge
+ * vertex 1} with T+ carrying +(l/2A)(r - free vertex) (RWG basis, Sec. II-A).
+ * All vertices lie in the unit's local frame; unit centres are on the lattice.
+ * Triangle pairs whose units are within Chebyshev distance extract_radius
+ * use closed-form 1/R singularity extraction. */
+typedef struct {
+  double freq_hz;
+  double period_x, period_y;
+  int32_t n_states;
+  const int32_t* state_off; /* [n_states + 1] */
+  int32_t n_vert;
+  const double* vert; /* [n_vert][3] */
+  int32_t n_tri;
+  const int32_t* tri; /* [n_tri][3] */
+  int32_t n_rwg;
+  const int32_t* rwg; /* [n_rwg][4] */
+  int32_t extract_radius;
+} r3m_unit_geom;
+
+/* ---------------------------------------------------------------- fill -- */
+
+/* Bytes of (2Dx+1)(2Dy+1) dense n x n blocks of `dtype` (C128 or C64). */
+size_t r3m_blocks_bytes(int32_t n, int32_t Dx, int32_t Dy, r3m_dtype dtype);
+
+/* Fills the global-matrix blocks Z(d) for every |dx| <= Dx, |dy| <= Dy:
+ * out[slot(d)][m][n] = Z_mn between observer macro RWG m of the unit at d
+ * and source macro RWG n of the unit at the origin (eq. (1), Galerkin EFIE:
+ * Z_mn = j k eta int int [f_m.f_n - k^-2 div f_m div' f_n] G dS' dS,
+ * G = exp(-jkR)/(4 pi R), 7-point rule on both triangles).  Computed in FP64
+ * and rounded to `dtype` (C128 or C64).  Sets R3M_ERR_NONFINITE if any entry
+ * is not finite (checked before returning; this call synchronises). */
+int r3m_fill_unique_blocks(r3m_ctx ctx, const r3m_unit_geom* geom, int32_t Dx, int32_t Dy,
+                           r3m_dtype dtype, void* blocks_dev, size_t blocks_bytes,
+                           hipStream_t stream);
+
+/* ------------------------------------------------------------ compress -- */
+
+/* Far displacements are those with max(|dx|,|dy|) > near_radius.  They are
+ * numbered in slot order, skipping near slots:
+ *   far_index(d) = slot(d) - #near slots before slot(d).
+ * Far buffer layout: int32 ranks[n_far] (padded to 256 B), then per far
+ * block f the factors U_f [max_rank][n] followed by V_f [max_rank][n]
+ * (column rho contiguous over rows) so that Z(d) ~ U V^H.  Unused columns
+ * (rho >= rank) are zero.  Element type: C128 or C64. */
+int32_t r3m_far_count(int32_t Dx, int32_t Dy, int32_t near_radius);
+size_t r3m_far_bytes(int32_t n, int32_t n_far, int32_t max_rank, r3m_dtype dtype);
+/* Workspace of r3m_compress_far (FP64 residual blocks, processed in batches). */
+size_t r3m_compress_work_bytes(int32_t n, int32_t max_rank, int32_t blocks_per_batch);
+
+/* Fully pivoted adaptive cross approximation of every far block of a C128
+ * dense store (as written by r3m_fill_unique_blocks with the same Dx, Dy):
+ * repeat {pivot = argmax|R|; u = R[:,j*]; v = conj(R[i*,:]/R[i*,j*]);
+ * R -= u v^H} until ||R||_F <= tol ||Z(d)||_F or rank == max_rank (Sec. II-B,
+ * ACA of admissible blocks).  Work in FP64, output rounded to far_dtype.
+ * ranks_host[n_far] and rel_err_host[n_far] (achieved relative Frobenius
+ * error, exact) are returned; this call synchronises. */
+int r3m_compress_far(r3m_ctx ctx, const void* dense_dev, int32_t n, int32_t Dx, int32_t Dy,
+                     int32_t near_radius, double tol, int32_t max_rank, r3m_dtype far_dtype,
+                     void* far_dev, size_t far_bytes, int32_t* ranks_host, double* rel_err_host,
+                     void* work_dev, size_t work_bytes, hipStream_t stream);
+
+/* --------------------------------------------------------------- store -- */
+
+/* A global matrix as unique displacement blocks.
+ * near: dense blocks for max(|dx|,|dy|) <= near_radius, laid out as a block
+ *       store of half-extent (Nx, Ny) = (min(near_radius, Dx), min(near_radius, Dy)).
+ * far : r3m_far layout above (ignored when near covers the whole store). */
+typedef struct {
+  int32_t n;        /* macro RWG per unit */
+  int32_t n_states; /* coding states; n_a = n / n_states */
+  int32_t Dx, Dy;   /* half-extent of the displacement set */
+  int32_t near_radius;
+  r3m_dtype near_dtype;
+  const void* near;
+  r3m_dtype far_dtype;
+  const void* far;
+  int32_t max_rank;
+} r3m_store;
+
+/* A batch of right-hand sides sharing one store (Sec. III-A: the global
+ * matrix is computed once and shared across codebooks).  RHS b is an
+ * L[2b] x L[2b+1] array (Lx, Ly <= Dx+1, Dy+1) whose codebook is
+ * states[state_off[b] ...] (uint8, device, one byte per unit, < n_states),
+ * and whose reduced vectors start at unit unit_off[b] of x/y.  Several RHS
+ * may share one codebook (e.g. several incidence angles). */
+typedef struct {
+  int32_t B;
+  const int32_t* L;         /* host [B][2] */
+  const int64_t* unit_off;  /* host [B] */
+  const int64_t* state_off; /* host [B] */
+  const uint8_t* states;    /* device */
+} r3m_batch;
+
+/* -------------------------------------------------------------- matvec -- */
+
+size_t r3m_matvec_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch,
+                             r3m_dtype vec_dtype);
+
+/* y_b = P_k^T Z P_k x_b for every RHS b (eq. (3); eq. (6) in reduced form):
+ * y[i] = sum over units j of Z(i - j)[A(s_i), A(s_j)] x[j], with A(s) the
+ * basis range of state s.  Far blocks use U (V^H x).  Vectors are C128 or C64
+ * (vec_dtype), accumulation is in the store's precision (FP64 for a C128
+ * store, FP32 otherwise).  The sum over displacements is reduced in a fixed
+ * order (bitwise reproducible run to run).  work: r3m_matvec_work_bytes. */
+int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch,
+                         r3m_dtype vec_dtype, const void* x_dev, void* y_dev, void* work_dev,
+                         size_t work_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------- GMRES -- */
+
+typedef struct {
+  double tol;         /* relative residual target of the (inner) solve */
+  int32_t restart;    /* Krylov dimension m */
+  int32_t max_iter;   /* total inner iterations per solve */
+  double refine_tol;  /* > 0: FP64 refinement with Z64 until ||b - Z64 x||/||b|| <= refine_tol */
+  int32_t max_refine; /* outer refinement steps */
+} r3m_gmres_opts;
+
+typedef struct {
+  int32_t iters;       /* inner iterations (summed over refinement steps) */
+  int32_t refine_steps;
+  double rel_residual; /* true relative residual at exit (Z64 if given, else Z) */
+  int32_t converged;
+} r3m_gmres_report;
+
+size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch,
+                            const r3m_gmres_opts* opts);
+
+/* Solves the retrieved systems Z_k x_b = b_b (C128 vectors) with restarted
+ * GMRES(m): zero initial guess, Gram-Schmidt Arnoldi (classical, repeated
+ * once) in FP64, complex Givens rotations in FP64, convergence flags on the
+ * device.  The matvec runs in the precision of Z.  If Z64 (a C128 store of the
+ * same matrix) is given and opts->refine_tol > 0, an outer FP64 iterative
+ * refinement computes r = b - Z64 x and solves Z d = r with the inner GMRES.
+ * rep_host[B] is written; returns R3M_ERR_NOT_CONVERGED if any RHS missed the
+ * tolerance (x still holds the last iterate).  Synchronises the stream. */
+int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
+                    const r3m_batch* batch, const void* b_dev, void* x_dev,
+                    const r3m_gmres_opts* opts, r3m_gmres_report* rep_host, void* work_dev,
+                    size_t work_bytes, hipStream_t stream);
+
+/* --------------------------------------------------- excitation and RCS -- */
+
+/* Plane-wave right-hand sides U_k (eq. (1)), C128 [unit][n_a] per RHS:
+ * U_m = int f_m . E_inc dS, E_inc = e0 e_hat exp(-j k k_hat . r),
+ * k_hat = -(sin t cos p, sin t sin p, cos t), e_hat = theta_hat(t, p).
+ * inc_host: [B][3] = (theta, phi, e0). */
+int r3m_plane_wave_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch,
+                       const double* inc_host, void* b_dev, hipStream_t stream);
+
+/* Bistatic RCS sigma[b][dir] (m^2, FP64) of currents I (C128 reduced vectors):
+ * N(r_hat) = sum_n I_n int f_n exp(j k r_hat . r') dS',
+ * sigma = (k^2 eta^2 / 4 pi) |N - (N.r_hat) r_hat|^2 / |e0|^2.
+ * dirs_host: [n_dir][2] = (theta, phi) in radians. */
+int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, const void* I_dev,
+            int32_t n_dir, const double* dirs_host, double e0, double* sigma_dev,
+            hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* R3M_H */

@@ -1,0 +1,248 @@
+// Context, error reporting, geometry upload and batch descriptors.
+#include "r3m_common.h"
+
+#include <algorithm>
+
+namespace r3m {
+
+static thread_local std::string g_thread_error;
+
+void set_thread_error(const std::string& msg) { g_thread_error = msg; }
+
+void DevBuf::ensure(size_t want) {
+  if (want <= bytes) return;
+  if (ptr) {
+    // the previous contents may still be read by queued work
+    R3M_CHECK_HIP(hipDeviceSynchronize());
+    R3M_CHECK_HIP(hipFree(ptr));
+  }
+  ptr = nullptr;
+  bytes = 0;
+  size_t b = std::max<size_t>(want, 4096);
+  R3M_CHECK_HIP(hipMalloc(&ptr, b));
+  bytes = b;
+}
+
+void DevBuf::release() {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = 0;
+}
+
+size_t dtype_size(r3m_dtype t) {
+  switch (t) {
+    case R3M_C128: return 16;
+    case R3M_C64: return 8;
+    default: return 0;
+  }
+}
+
+void validate_geom(const r3m_unit_geom* g) {
+  R3M_REQUIRE(g, R3M_ERR_INVALID_ARG, "geometry is NULL");
+  R3M_REQUIRE(g->freq_hz > 0 && std::isfinite(g->freq_hz), R3M_ERR_INVALID_ARG, "freq_hz must be > 0");
+  R3M_REQUIRE(g->period_x > 0 && g->period_y > 0, R3M_ERR_INVALID_ARG, "periods must be > 0");
+  R3M_REQUIRE(g->n_states >= 1 && g->n_states <= 256, R3M_ERR_INVALID_ARG, "n_states out of range");
+  R3M_REQUIRE(g->state_off && g->vert && g->tri && g->rwg, R3M_ERR_INVALID_ARG, "NULL geometry array");
+  R3M_REQUIRE(g->n_vert > 0 && g->n_tri > 0 && g->n_rwg > 0, R3M_ERR_INVALID_ARG, "empty mesh");
+  R3M_REQUIRE(g->state_off[0] == 0 && g->state_off[g->n_states] == g->n_rwg, R3M_ERR_INVALID_ARG,
+              "state_off must run from 0 to n_rwg");
+  int na = g->state_off[1] - g->state_off[0];
+  for (int s = 0; s < g->n_states; ++s)
+    R3M_REQUIRE(g->state_off[s + 1] - g->state_off[s] == na && na > 0, R3M_ERR_UNSUPPORTED,
+                "every state must own the same number of RWG");
+  R3M_REQUIRE(g->extract_radius >= 0, R3M_ERR_INVALID_ARG, "extract_radius must be >= 0");
+  for (int t = 0; t < 3 * g->n_tri; ++t)
+    R3M_REQUIRE(g->tri[t] >= 0 && g->tri[t] < g->n_vert, R3M_ERR_INVALID_ARG, "triangle vertex out of range");
+  for (int m = 0; m < g->n_rwg; ++m) {
+    const int32_t* r = g->rwg + 4 * m;
+    R3M_REQUIRE(r[0] >= 0 && r[0] < g->n_tri && r[1] >= 0 && r[1] < g->n_tri && r[0] != r[1],
+                R3M_ERR_INVALID_ARG, "RWG triangle out of range");
+    R3M_REQUIRE(r[2] >= 0 && r[2] < g->n_vert && r[3] >= 0 && r[3] < g->n_vert && r[2] != r[3],
+                R3M_ERR_INVALID_ARG, "RWG edge vertex out of range");
+  }
+  for (int v = 0; v < 3 * g->n_vert; ++v)
+    R3M_REQUIRE(std::isfinite(g->vert[v]), R3M_ERR_INVALID_ARG, "non-finite vertex");
+}
+
+GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
+  validate_geom(g);
+  const int nt = g->n_tri, nr = g->n_rwg;
+  std::vector<double> tri_v(9 * (size_t)nt), area(nt), len(nr);
+  std::vector<int32_t> rtri(2 * (size_t)nr), rfree(2 * (size_t)nr);
+  for (int t = 0; t < nt; ++t) {
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) tri_v[9 * t + 3 * a + c] = g->vert[3 * g->tri[3 * t + a] + c];
+    const double* v = &tri_v[9 * t];
+    double e1[3] = {v[3] - v[0], v[4] - v[1], v[5] - v[2]};
+    double e2[3] = {v[6] - v[0], v[7] - v[1], v[8] - v[2]};
+    double cx = e1[1] * e2[2] - e1[2] * e2[1];
+    double cy = e1[2] * e2[0] - e1[0] * e2[2];
+    double cz = e1[0] * e2[1] - e1[1] * e2[0];
+    area[t] = 0.5 * std::sqrt(cx * cx + cy * cy + cz * cz);
+    R3M_REQUIRE(area[t] > 0, R3M_ERR_INVALID_ARG, "degenerate triangle");
+  }
+  for (int m = 0; m < nr; ++m) {
+    const int32_t* r = g->rwg + 4 * m;
+    for (int s = 0; s < 2; ++s) {
+      int t = r[s];
+      int loc = -1, cnt = 0;
+      for (int a = 0; a < 3; ++a) {
+        int vid = g->tri[3 * t + a];
+        if (vid != r[2] && vid != r[3]) {
+          loc = a;
+          ++cnt;
+        }
+      }
+      R3M_REQUIRE(cnt == 1, R3M_ERR_INVALID_ARG, "RWG edge is not an edge of its triangle");
+      rtri[2 * m + s] = t;
+      rfree[2 * m + s] = loc;
+    }
+    double dx = g->vert[3 * r[2]] - g->vert[3 * r[3]];
+    double dy = g->vert[3 * r[2] + 1] - g->vert[3 * r[3] + 1];
+    double dz = g->vert[3 * r[2] + 2] - g->vert[3 * r[3] + 2];
+    len[m] = std::sqrt(dx * dx + dy * dy + dz * dz);
+  }
+  size_t off_tv = 0;
+  size_t off_ar = off_tv + tri_v.size() * 8;
+  size_t off_len = off_ar + area.size() * 8;
+  size_t off_rt = off_len + len.size() * 8;
+  size_t off_rf = off_rt + rtri.size() * 4;
+  size_t total = off_rf + rfree.size() * 4;
+  std::vector<char> host(total);
+  std::memcpy(host.data() + off_tv, tri_v.data(), tri_v.size() * 8);
+  std::memcpy(host.data() + off_ar, area.data(), area.size() * 8);
+  std::memcpy(host.data() + off_len, len.data(), len.size() * 8);
+  std::memcpy(host.data() + off_rt, rtri.data(), rtri.size() * 4);
+  std::memcpy(host.data() + off_rf, rfree.data(), rfree.size() * 4);
+  // previous users of the table may still be queued on this stream
+  R3M_CHECK_HIP(hipStreamSynchronize(stream));
+  ctx->geom.ensure(total);
+  R3M_CHECK_HIP(hipMemcpyAsync(ctx->geom.ptr, host.data(), total, hipMemcpyHostToDevice, stream));
+  R3M_CHECK_HIP(hipStreamSynchronize(stream));
+  char* base = (char*)ctx->geom.ptr;
+  GeomDev d;
+  d.tri_v = (const double*)(base + off_tv);
+  d.tri_area = (const double*)(base + off_ar);
+  d.rwg_len = (const double*)(base + off_len);
+  d.rwg_tri = (const int32_t*)(base + off_rt);
+  d.rwg_free = (const int32_t*)(base + off_rf);
+  d.n_tri = nt;
+  d.n_rwg = nr;
+  return d;
+}
+
+void validate_batch(const r3m_batch* batch, int Dx, int Dy) {
+  R3M_REQUIRE(batch, R3M_ERR_INVALID_ARG, "batch is NULL");
+  R3M_REQUIRE(batch->B >= 0, R3M_ERR_INVALID_ARG, "batch size < 0");
+  if (batch->B == 0) return;
+  R3M_REQUIRE(batch->L && batch->unit_off && batch->state_off && batch->states, R3M_ERR_INVALID_ARG,
+              "NULL batch array");
+  for (int b = 0; b < batch->B; ++b) {
+    int Lx = batch->L[2 * b], Ly = batch->L[2 * b + 1];
+    R3M_REQUIRE(Lx >= 1 && Ly >= 1, R3M_ERR_INVALID_ARG, "array size must be >= 1");
+    R3M_REQUIRE(Lx <= Dx + 1 && Ly <= Dy + 1, R3M_ERR_INVALID_ARG,
+                "array larger than the displacement set of the store");
+    R3M_REQUIRE(batch->unit_off[b] >= 0 && batch->state_off[b] >= 0, R3M_ERR_INVALID_ARG,
+                "negative offset");
+  }
+}
+
+const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int tile_h,
+                           hipStream_t stream) {
+  BatchKey key;
+  key.states = nullptr;  // the descriptor holds offsets only
+  key.v.push_back(tile_w);
+  key.v.push_back(tile_h);
+  for (int b = 0; b < batch->B; ++b) {
+    key.v.push_back(batch->L[2 * b]);
+    key.v.push_back(batch->L[2 * b + 1]);
+    key.v.push_back(batch->unit_off[b]);
+    key.v.push_back(batch->state_off[b]);
+  }
+  auto it = ctx->batches.find(key);
+  if (it != ctx->batches.end()) return *it->second;
+
+  auto* d = new BatchDesc();
+  d->B = batch->B;
+  std::vector<RhsDev> rhs(batch->B);
+  std::vector<TileDev> tiles;
+  int64_t total = 0;
+  for (int b = 0; b < batch->B; ++b) {
+    int Lx = batch->L[2 * b], Ly = batch->L[2 * b + 1];
+    rhs[b] = RhsDev{batch->unit_off[b], batch->state_off[b], Lx, Ly};
+    d->Lx.push_back(Lx);
+    d->Ly.push_back(Ly);
+    d->unit_off.push_back(batch->unit_off[b]);
+    d->n_units.push_back((int64_t)Lx * Ly);
+    total = std::max<int64_t>(total, batch->unit_off[b] + (int64_t)Lx * Ly);
+    d->max_L = std::max(d->max_L, std::max(Lx, Ly));
+    for (int ty = 0; ty < Ly; ty += tile_h)
+      for (int tx = 0; tx < Lx; tx += tile_w) tiles.push_back(TileDev{b, tx, ty, 0});
+  }
+  d->total_units = total;
+  d->n_tiles = (int32_t)tiles.size();
+  size_t bytes = rhs.size() * sizeof(RhsDev) + tiles.size() * sizeof(TileDev);
+  std::vector<char> host(std::max<size_t>(bytes, 16));
+  std::memcpy(host.data(), rhs.data(), rhs.size() * sizeof(RhsDev));
+  std::memcpy(host.data() + rhs.size() * sizeof(RhsDev), tiles.data(), tiles.size() * sizeof(TileDev));
+  d->dev.ensure(host.size());
+  R3M_CHECK_HIP(hipMemcpyAsync(d->dev.ptr, host.data(), host.size(), hipMemcpyHostToDevice, stream));
+  R3M_CHECK_HIP(hipStreamSynchronize(stream));
+  d->rhs = (const RhsDev*)d->dev.ptr;
+  d->tiles = (const TileDev*)((char*)d->dev.ptr + rhs.size() * sizeof(RhsDev));
+  ctx->batches[key] = d;
+  return *d;
+}
+
+}  // namespace r3m
+
+using namespace r3m;
+
+extern "C" {
+
+int r3m_ctx_create(r3m_ctx* out, int device) {
+  if (!out) {
+    set_thread_error("out is NULL");
+    return R3M_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  r3m_ctx ctx = new r3m_ctx_s();
+  int rc = guarded(nullptr, [&] {
+    int count = 0;
+    R3M_CHECK_HIP(hipGetDeviceCount(&count));
+    R3M_REQUIRE(device >= 0 && device < count, R3M_ERR_HIP, "no such HIP device");
+    R3M_CHECK_HIP(hipSetDevice(device));
+    ctx->device = device;
+    ctx->flag.ensure(256);
+    R3M_CHECK_HIP(hipMemset(ctx->flag.ptr, 0, 256));
+  });
+  if (rc != R3M_OK) {
+    delete ctx;
+    return rc;
+  }
+  *out = ctx;
+  return R3M_OK;
+}
+
+int r3m_ctx_destroy(r3m_ctx ctx) {
+  if (!ctx) return R3M_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  ctx->flag.release();
+  ctx->geom.release();
+  for (auto& kv : ctx->batches) {
+    kv.second->dev.release();
+    delete kv.second;
+  }
+  delete ctx;
+  return R3M_OK;
+}
+
+const char* r3m_last_error(r3m_ctx ctx) {
+  if (ctx) return ctx->last_error.c_str();
+  return g_thread_error.c_str();
+}
+
+const char* r3m_version(void) { return "r3m 0.1 gfx950"; }
+
+}  // extern "C"

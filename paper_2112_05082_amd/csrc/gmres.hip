@@ -1,0 +1,649 @@
+// Batched restarted GMRES(m) around the retrieved matvec, with optional FP64
+// iterative refinement (MVP-based Krylov solution of the retrieved system,
+// Sec. III-A; the paper itself used BiCGStab, Sec. IV).
+//
+// All Krylov vectors, Gram-Schmidt coefficients and Givens rotations are FP64
+// (complex double).  Arnoldi uses classical Gram-Schmidt repeated once
+// (CGS2: two projections per step, orthogonality at the level of modified
+// Gram-Schmidt with two reductions instead of j+1).  Reductions are two-stage
+// with fixed order (bitwise reproducible).  Convergence flags live on the
+// device and are read by the host once every few iterations.
+#include "r3m_common.h"
+
+#include <algorithm>
+
+namespace r3m {
+
+void validate_store(const r3m_store* Z);
+int choose_chunks(const BatchDesc& bd, int max_chunks);
+size_t matvec_partial_bytes(const BatchDesc& bd, int n_a, int chunks, r3m_dtype store_dtype);
+void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
+                   r3m_dtype vec_dtype, const void* x, void* y, void* partial, int chunks,
+                   hipStream_t stream);
+
+namespace {
+
+constexpr int kTW = 4, kTH = 4;
+constexpr int kDotChunk = 8192;
+constexpr int kDotThreads = 256;
+constexpr int kCheckEvery = 4;
+
+struct RhsVec {
+  int64_t off;  // offset (elements) of this RHS in user-layout vectors
+  int64_t N;    // unknowns
+};
+
+struct RhsState {
+  double bnorm;  // norm of the right-hand side of the current (inner) solve
+  double beta;   // norm of the residual at the start of the cycle
+  double res;    // latest relative residual estimate
+  int jdone;     // iteration at which this cycle converged, -1 while running
+  int active;    // 1 while the RHS is being solved
+};
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// partial[b][i][p] = sum over chunk p of conj(A_i) B
+__global__ void __launch_bounds__(kDotThreads)
+dots_kernel(const double2* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
+            const RhsVec* __restrict__ rv, int nvec_max, const int* __restrict__ nvec_dev, int maxP,
+            double2* __restrict__ partial) {
+  __shared__ double2 sh[kDotThreads / 64];
+  const int p = blockIdx.x, i = blockIdx.y, b = blockIdx.z;
+  const RhsVec r = rv[b];
+  const int nvec = nvec_dev ? *nvec_dev : nvec_max;
+  if (i >= nvec) return;
+  const int64_t P = (r.N + kDotChunk - 1) / kDotChunk;
+  if (p >= P) return;
+  const double2* a = A + (int64_t)i * a_stride + r.off;
+  const double2* bb = Bv + r.off;
+  const int64_t lo = (int64_t)p * kDotChunk;
+  const int64_t hi = min(r.N, lo + kDotChunk);
+  double2 s = make_double2(0.0, 0.0);
+  for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+    double2 t = cmulc(a[k], bb[k]);
+    s.x += t.x;
+    s.y += t.y;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    s.x += __shfl_xor(s.x, o);
+    s.y += __shfl_xor(s.y, o);
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 t = sh[0];
+    for (int w = 1; w < kDotThreads / 64; ++w) {
+      t.x += sh[w].x;
+      t.y += sh[w].y;
+    }
+    partial[((size_t)b * nvec_max + i) * maxP + p] = t;
+  }
+}
+
+// out[b][i] = sum_p partial[b][i][p] (fixed order); mode 0: store, 1: add to
+// H[i][j] (CGS pass 2 accumulation) while also storing the pass value in hbuf
+__global__ void dots_finish_kernel(const double2* __restrict__ partial, const RhsVec* __restrict__ rv,
+                                   int nvec, int maxP, double2* __restrict__ hbuf) {
+  const int b = blockIdx.x, i = threadIdx.x;
+  if (i >= nvec) return;
+  const int64_t P = (rv[b].N + kDotChunk - 1) / kDotChunk;
+  double2 s = make_double2(0.0, 0.0);
+  for (int p = 0; p < P; ++p) {
+    double2 t = partial[((size_t)b * nvec + i) * maxP + p];
+    s.x += t.x;
+    s.y += t.y;
+  }
+  hbuf[(size_t)b * nvec + i] = s;
+}
+
+// w -= sum_{i<=j} h[i] V_i ; H[i][j] (+)= h[i]
+__global__ void gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w,
+                                 const RhsVec* __restrict__ rv, const RhsState* __restrict__ st,
+                                 const double2* __restrict__ hbuf, int nvec, int64_t ut) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= r.N || !st[b].active) return;
+  double2 acc = w[r.off + k];
+  for (int i = 0; i < nvec; ++i) {
+    double2 t = cmul(hbuf[(size_t)b * nvec + i], V[(int64_t)i * ut + r.off + k]);
+    acc.x -= t.x;
+    acc.y -= t.y;
+  }
+  w[r.off + k] = acc;
+}
+
+__global__ void accumulate_h_kernel(double2* __restrict__ H, const double2* __restrict__ hbuf, int nvec,
+                                    int m, int j, int first) {
+  const int b = blockIdx.x, i = threadIdx.x;
+  if (i >= nvec) return;
+  double2* h = H + (size_t)b * (m + 1) * m;
+  double2 v = hbuf[(size_t)b * nvec + i];
+  if (first) {
+    h[i * m + j] = v;
+  } else {
+    h[i * m + j].x += v.x;
+    h[i * m + j].y += v.y;
+  }
+}
+
+// H[j+1][j] = ||w||, V_{j+1} = w / ||w|| (zeros for finished RHS or breakdown)
+__global__ void normalize_kernel(const double2* __restrict__ w, double2* __restrict__ V,
+                                 const RhsVec* __restrict__ rv, const RhsState* __restrict__ st,
+                                 const double2* __restrict__ nrm2, double2* __restrict__ H, int m,
+                                 int j, int64_t ut) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double nv = sqrt(fmax(nrm2[b].x, 0.0));
+  if (k == 0) H[(size_t)b * (m + 1) * m + (j + 1) * m + j] = make_double2(nv, 0.0);
+  if (k >= r.N) return;
+  const bool ok = st[b].active && st[b].jdone < 0 && nv > 0.0;
+  double2 v = w[r.off + k];
+  V[(int64_t)(j + 1) * ut + r.off + k] = ok ? make_double2(v.x / nv, v.y / nv) : make_double2(0.0, 0.0);
+}
+
+// Givens update of column j of H for each RHS; convergence check
+__global__ void givens_kernel(double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
+                              double2* __restrict__ sn, RhsState* __restrict__ st, int B, int m, int j,
+                              double tol, int* __restrict__ n_running) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  RhsState s = st[b];
+  if (!s.active || s.jdone >= 0) return;
+  double2* h = H + (size_t)b * (m + 1) * m;
+  double* c = cs + (size_t)b * m;
+  double2* sv = sn + (size_t)b * m;
+  double2* gg = g + (size_t)b * (m + 1);
+  for (int i = 0; i < j; ++i) {
+    const double2 hi = h[i * m + j], hi1 = h[(i + 1) * m + j];
+    // [c s; -conj(s) c] [hi; hi1]
+    const double2 a = make_double2(c[i] * hi.x + (sv[i].x * hi1.x - sv[i].y * hi1.y),
+                                   c[i] * hi.y + (sv[i].x * hi1.y + sv[i].y * hi1.x));
+    const double2 bnew = make_double2(-(sv[i].x * hi.x + sv[i].y * hi.y) + c[i] * hi1.x,
+                                      -(sv[i].x * hi.y - sv[i].y * hi.x) + c[i] * hi1.y);
+    h[i * m + j] = a;
+    h[(i + 1) * m + j] = bnew;
+  }
+  const double2 a = h[j * m + j], bb = h[(j + 1) * m + j];
+  const double na = hypot(a.x, a.y), nb = hypot(bb.x, bb.y);
+  double cj;
+  double2 sj, rj;
+  if (nb == 0.0) {
+    cj = 1.0;
+    sj = make_double2(0.0, 0.0);
+    rj = a;
+  } else if (na == 0.0) {
+    cj = 0.0;
+    sj = make_double2(1.0, 0.0);
+    rj = bb;
+  } else {
+    const double nu = hypot(na, nb);
+    const double2 ph = make_double2(a.x / na, a.y / na);
+    cj = na / nu;
+    // s = ph * conj(b) / nu
+    sj = make_double2((ph.x * bb.x + ph.y * bb.y) / nu, (ph.y * bb.x - ph.x * bb.y) / nu);
+    rj = make_double2(ph.x * nu, ph.y * nu);
+  }
+  c[j] = cj;
+  sv[j] = sj;
+  h[j * m + j] = rj;
+  h[(j + 1) * m + j] = make_double2(0.0, 0.0);
+  const double2 gj = gg[j];
+  // g[j+1] = -conj(s) g[j];  g[j] = c g[j]
+  gg[j + 1] = make_double2(-(sj.x * gj.x + sj.y * gj.y), -(sj.x * gj.y - sj.y * gj.x));
+  gg[j] = make_double2(cj * gj.x, cj * gj.y);
+  const double res = s.bnorm > 0.0 ? hypot(gg[j + 1].x, gg[j + 1].y) / s.bnorm : 0.0;
+  s.res = res;
+  if (!(res > tol) || nb == 0.0 || j == m - 1) {
+    s.jdone = j + 1;
+  } else {
+    atomicAdd(n_running, 1);
+  }
+  st[b] = s;
+}
+
+// y = R^{-1} g (upper triangular, size jdone), stored in place of g
+__global__ void backsolve_kernel(const double2* __restrict__ H, double2* __restrict__ g,
+                                 const RhsState* __restrict__ st, int B, int m) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const RhsState s = st[b];
+  if (!s.active) return;
+  const int J = s.jdone;
+  const double2* h = H + (size_t)b * (m + 1) * m;
+  double2* y = g + (size_t)b * (m + 1);
+  for (int i = J - 1; i >= 0; --i) {
+    double2 acc = y[i];
+    for (int k = i + 1; k < J; ++k) {
+      double2 t = cmul(h[i * m + k], y[k]);
+      acc.x -= t.x;
+      acc.y -= t.y;
+    }
+    const double2 d = h[i * m + i];
+    const double dd = d.x * d.x + d.y * d.y;
+    y[i] = dd > 0.0 ? make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd)
+                    : make_double2(0.0, 0.0);
+  }
+}
+
+// x += V y (first jdone columns)
+__global__ void update_x_kernel(const double2* __restrict__ V, const double2* __restrict__ g,
+                                double2* __restrict__ x, const RhsVec* __restrict__ rv,
+                                const RhsState* __restrict__ st, int m, int64_t ut) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const RhsState s = st[b];
+  if (k >= r.N || !s.active) return;
+  double2 acc = x[r.off + k];
+  const double2* y = g + (size_t)b * (m + 1);
+  for (int i = 0; i < s.jdone; ++i) {
+    double2 t = cmul(y[i], V[(int64_t)i * ut + r.off + k]);
+    acc.x += t.x;
+    acc.y += t.y;
+  }
+  x[r.off + k] = acc;
+}
+
+// out = a - b (user layout, per RHS)
+__global__ void sub_kernel(const double2* __restrict__ a, const double2* __restrict__ bvec,
+                           double2* __restrict__ out, const RhsVec* __restrict__ rv) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= r.N) return;
+  double2 u = a[r.off + k], v = bvec[r.off + k];
+  out[r.off + k] = make_double2(u.x - v.x, u.y - v.y);
+}
+
+__global__ void add_kernel(double2* __restrict__ x, const double2* __restrict__ d,
+                           const RhsVec* __restrict__ rv) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= r.N) return;
+  double2 u = x[r.off + k], v = d[r.off + k];
+  x[r.off + k] = make_double2(u.x + v.x, u.y + v.y);
+}
+
+__global__ void zero_kernel(double2* __restrict__ x, const RhsVec* __restrict__ rv) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= r.N) return;
+  x[r.off + k] = make_double2(0.0, 0.0);
+}
+
+// start of a cycle: beta = ||r||, V_0 = r / beta, g = (beta, 0, ...), jdone = -1
+__global__ void cycle_start_kernel(const double2* __restrict__ r, double2* __restrict__ V,
+                                   const RhsVec* __restrict__ rv, RhsState* __restrict__ st,
+                                   const double2* __restrict__ nrm2, double2* __restrict__ g, int m) {
+  const int b = blockIdx.y;
+  const RhsVec rr = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double beta = sqrt(fmax(nrm2[b].x, 0.0));
+  const bool act = st[b].active && beta > 0.0;
+  if (k < rr.N)
+    V[rr.off + k] = act ? make_double2(r[rr.off + k].x / beta, r[rr.off + k].y / beta)
+                        : make_double2(0.0, 0.0);
+  if (k <= m) g[(size_t)b * (m + 1) + k] = (k == 0 && act) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
+}
+
+__global__ void states_check_kernel(const uint8_t* __restrict__ states, const RhsVec* __restrict__ rv,
+                                    const int64_t* __restrict__ soff, int n_a, int n_states,
+                                    int* __restrict__ flag) {
+  const int b = blockIdx.y;
+  const int64_t units = rv[b].N / n_a;
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= units) return;
+  if (states[soff[b] + u] >= n_states) atomicOr(flag, 2);
+}
+
+__global__ void nonfinite_kernel(const double2* __restrict__ v, const RhsVec* __restrict__ rv,
+                                 int* __restrict__ flag) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= r.N) return;
+  double2 t = v[r.off + k];
+  if (!(isfinite(t.x) && isfinite(t.y))) atomicOr(flag, 4);
+}
+
+__global__ void finalize_kernel(RhsState* __restrict__ st, int B, int J) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  if (st[b].active && st[b].jdone < 0) st[b].jdone = J;
+}
+
+struct Work {
+  double2* V;
+  double2* w;
+  double2* r;
+  double2* d;
+  double2* ro;
+  void* mv_partial;
+  double2* H;
+  double2* g;
+  double* cs;
+  double2* sn;
+  double2* dpart;
+  double2* hbuf;
+  double2* nrm;
+  RhsState* st;
+  RhsVec* rv;
+  int64_t* soff;
+  int* counters;
+  size_t bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+Work layout_work(char* base, const BatchDesc& bd, int n_a, int m, size_t mv_bytes) {
+  Work w{};
+  const int B = bd.B;
+  int64_t maxN = 0;
+  for (int b = 0; b < B; ++b) maxN = std::max<int64_t>(maxN, bd.n_units[b] * n_a);
+  const size_t ut = (size_t)bd.total_units * n_a;
+  const int64_t vtot = (int64_t)(m + 1) * ut;
+  const int maxP = (int)((maxN + kDotChunk - 1) / kDotChunk);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align256(o + bytes);
+    return base ? (void*)(base + at) : nullptr;
+  };
+  w.V = (double2*)take((size_t)vtot * 16);
+  w.w = (double2*)take(ut * 16);
+  w.r = (double2*)take(ut * 16);
+  w.d = (double2*)take(ut * 16);
+  w.ro = (double2*)take(ut * 16);
+  w.mv_partial = take(mv_bytes);
+  w.H = (double2*)take((size_t)B * (m + 1) * m * 16);
+  w.g = (double2*)take((size_t)B * (m + 1) * 16);
+  w.cs = (double*)take((size_t)B * m * 8);
+  w.sn = (double2*)take((size_t)B * m * 16);
+  w.dpart = (double2*)take((size_t)B * (m + 1) * std::max(maxP, 1) * 16);
+  w.hbuf = (double2*)take((size_t)B * (m + 1) * 16);
+  w.nrm = (double2*)take((size_t)B * 16);
+  w.st = (RhsState*)take((size_t)B * sizeof(RhsState));
+  w.rv = (RhsVec*)take((size_t)B * sizeof(RhsVec));
+  w.soff = (int64_t*)take((size_t)B * 8);
+  w.counters = (int*)take(256);
+  w.bytes = o;
+  return w;
+}
+
+}  // namespace
+
+
+struct GmresRun {
+  r3m_ctx ctx;
+  const BatchDesc* bd;
+  const r3m_batch* batch;
+  int n_a, m, maxP, B;
+  int64_t maxN, ut;
+  Work W;
+  hipStream_t s;
+
+  dim3 vgrid() const { return dim3(ceil_div((size_t)maxN, 256), B); }
+
+  void dots(const double2* A, int64_t a_stride, const double2* Bv, int nvec) {
+    dim3 grid(maxP, nvec, B);
+    hipLaunchKernelGGL(dots_kernel, grid, dim3(kDotThreads), 0, s, A, a_stride, Bv, W.rv, nvec,
+                       (const int*)nullptr, maxP, W.dpart);
+    hipLaunchKernelGGL(dots_finish_kernel, dim3(B), dim3(((nvec + 63) / 64) * 64), 0, s, W.dpart, W.rv,
+                       nvec, maxP, W.hbuf);
+  }
+
+  // W.nrm[b].x = ||v_b||^2
+  void norms(const double2* v) {
+    dots(v, 0, v, 1);
+    R3M_CHECK_HIP(hipMemcpyAsync(W.nrm, W.hbuf, (size_t)B * 16, hipMemcpyDeviceToDevice, s));
+  }
+
+  std::vector<double> host_norms(const double2* v) {
+    norms(v);
+    std::vector<double2> h(B);
+    R3M_CHECK_HIP(hipMemcpyAsync(h.data(), W.nrm, (size_t)B * 16, hipMemcpyDeviceToHost, s));
+    R3M_CHECK_HIP(hipStreamSynchronize(s));
+    std::vector<double> out(B);
+    for (int b = 0; b < B; ++b) out[b] = std::sqrt(std::max(h[b].x, 0.0));
+    return out;
+  }
+
+  void matvec(const r3m_store* Z, const double2* x, double2* y) {
+    const int chunks = choose_chunks(*bd, 64);
+    launch_matvec(ctx, Z, *bd, batch->states, R3M_C128, x, y, W.mv_partial, chunks, s);
+  }
+
+  void residual(const r3m_store* Z, const double2* rhs, const double2* sol, double2* out) {
+    matvec(Z, sol, W.w);
+    hipLaunchKernelGGL(sub_kernel, vgrid(), dim3(256), 0, s, rhs, W.w, out, W.rv);
+  }
+
+  void arnoldi_step(const r3m_store* Z, int j, double tol) {
+    matvec(Z, W.V + (int64_t)j * ut, W.w);
+    for (int pass = 0; pass < 2; ++pass) {
+      dots(W.V, ut, W.w, j + 1);
+      hipLaunchKernelGGL(gs_update_kernel, vgrid(), dim3(256), 0, s, W.V, W.w, W.rv, W.st, W.hbuf, j + 1, ut);
+      hipLaunchKernelGGL(accumulate_h_kernel, dim3(B), dim3(((j + 1 + 63) / 64) * 64), 0, s, W.H, W.hbuf,
+                         j + 1, m, j, pass == 0 ? 1 : 0);
+    }
+    norms(W.w);
+    hipLaunchKernelGGL(normalize_kernel, vgrid(), dim3(256), 0, s, W.w, W.V, W.rv, W.st, W.nrm, W.H, m, j, ut);
+    R3M_CHECK_HIP(hipMemsetAsync(W.counters, 0, sizeof(int), s));
+    hipLaunchKernelGGL(givens_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.H, W.g, W.cs, W.sn, W.st, B, m,
+                       j, tol, W.counters);
+    R3M_CHECK_HIP(hipGetLastError());
+  }
+
+  // GMRES(m) on Z for rhs into sol (initial guess kept), for RHS with running[b];
+  // the tolerance is relative to rhs_norm[b]; iters[b] accumulates iterations.
+  void solve(const r3m_store* Z, const double2* rhs, double2* sol, std::vector<int> running,
+             const std::vector<double>& rhs_norm, double tol, int max_iter, std::vector<int>& iters) {
+    std::vector<RhsState> hst(B);
+    while (true) {
+      residual(Z, rhs, sol, W.r);
+      norms(W.r);
+      std::vector<double2> nr(B);
+      R3M_CHECK_HIP(hipMemcpyAsync(nr.data(), W.nrm, (size_t)B * 16, hipMemcpyDeviceToHost, s));
+      R3M_CHECK_HIP(hipStreamSynchronize(s));
+      bool any = false;
+      int min_used = max_iter;
+      for (int b = 0; b < B; ++b) {
+        const double rel = rhs_norm[b] > 0 ? std::sqrt(std::max(nr[b].x, 0.0)) / rhs_norm[b] : 0.0;
+        if (running[b] && (!(rel > tol) || iters[b] >= max_iter)) running[b] = 0;
+        hst[b] = RhsState{rhs_norm[b], 0.0, rel, -1, running[b]};
+        if (running[b]) {
+          any = true;
+          min_used = std::min(min_used, iters[b]);
+        }
+      }
+      if (!any) break;
+      R3M_CHECK_HIP(hipMemcpyAsync(W.st, hst.data(), (size_t)B * sizeof(RhsState), hipMemcpyHostToDevice, s));
+      dim3 g0(std::max(ceil_div((size_t)maxN, 256), ceil_div((size_t)m + 1, 256)), B);
+      hipLaunchKernelGGL(cycle_start_kernel, g0, dim3(256), 0, s, W.r, W.V, W.rv, W.st, W.nrm, W.g, m);
+      const int steps = std::max(1, std::min(m, max_iter - min_used));
+      int j = 0;
+      for (; j < steps; ++j) {
+        arnoldi_step(Z, j, tol);
+        if ((j + 1) % kCheckEvery == 0 && j + 1 < steps) {
+          int nrun = 0;
+          R3M_CHECK_HIP(hipMemcpyAsync(&nrun, W.counters, sizeof(int), hipMemcpyDeviceToHost, s));
+          R3M_CHECK_HIP(hipStreamSynchronize(s));
+          if (nrun == 0) {
+            ++j;
+            break;
+          }
+        }
+      }
+      hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.st, B, j);
+      hipLaunchKernelGGL(backsolve_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.H, W.g, W.st, B, m);
+      hipLaunchKernelGGL(update_x_kernel, vgrid(), dim3(256), 0, s, W.V, W.g, sol, W.rv, W.st, m, ut);
+      R3M_CHECK_HIP(hipMemcpyAsync(hst.data(), W.st, (size_t)B * sizeof(RhsState), hipMemcpyDeviceToHost, s));
+      R3M_CHECK_HIP(hipStreamSynchronize(s));
+      for (int b = 0; b < B; ++b)
+        if (hst[b].active) iters[b] += hst[b].jdone;
+    }
+  }
+
+  int flag_check(int mask) {
+    int f = 0;
+    R3M_CHECK_HIP(hipMemcpyAsync(&f, W.counters + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    R3M_CHECK_HIP(hipStreamSynchronize(s));
+    return f & mask;
+  }
+};
+
+void validate_store(const r3m_store* Z);
+
+size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m) {
+  const int n_a = Z->n / Z->n_states;
+  const int chunks = choose_chunks(bd, 64);
+  size_t mv = matvec_partial_bytes(bd, n_a, chunks, Z->near_dtype);
+  if (Z64) mv = std::max(mv, matvec_partial_bytes(bd, n_a, chunks, Z64->near_dtype));
+  return layout_work(nullptr, bd, n_a, m, mv).bytes;
+}
+
+}  // namespace r3m
+
+using namespace r3m;
+
+extern "C" {
+
+size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch,
+                            const r3m_gmres_opts* opts) {
+  size_t out = 0;
+  int rc = guarded(ctx, [&] {
+    R3M_REQUIRE(ctx && opts, R3M_ERR_INVALID_ARG, "NULL argument");
+    validate_store(Z);
+    validate_batch(batch, Z->Dx, Z->Dy);
+    R3M_REQUIRE(opts->restart >= 1 && opts->restart <= 1024, R3M_ERR_INVALID_ARG, "restart out of range");
+    if (batch->B == 0) return;
+    const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, 0);
+    // the refinement store shares the partial layout; its dtype may be wider
+    r3m_store wide = *Z;
+    wide.near_dtype = R3M_C128;
+    out = gmres_bytes(ctx, Z, &wide, bd, opts->restart);
+  });
+  return rc == R3M_OK ? out : 0;
+}
+
+int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
+                    const r3m_batch* batch, const void* b_dev, void* x_dev,
+                    const r3m_gmres_opts* opts, r3m_gmres_report* rep_host, void* work_dev,
+                    size_t work_bytes, hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx && opts, R3M_ERR_INVALID_ARG, "NULL argument");
+    validate_store(Z);
+    validate_batch(batch, Z->Dx, Z->Dy);
+    const bool refine = Z64 != nullptr && opts->refine_tol > 0.0;
+    if (refine) {
+      validate_store(Z64);
+      R3M_REQUIRE(Z64->near_dtype == R3M_C128, R3M_ERR_INVALID_ARG, "refinement store must be C128");
+      R3M_REQUIRE(Z64->n == Z->n && Z64->n_states == Z->n_states && Z64->Dx >= Z->Dx && Z64->Dy >= Z->Dy,
+                  R3M_ERR_INVALID_ARG, "refinement store does not match");
+    }
+    R3M_REQUIRE(opts->restart >= 1 && opts->restart <= 1024, R3M_ERR_INVALID_ARG, "restart out of range");
+    R3M_REQUIRE(opts->max_iter >= 1, R3M_ERR_INVALID_ARG, "max_iter must be >= 1");
+    R3M_REQUIRE(opts->tol > 0.0 && opts->tol < 1.0, R3M_ERR_INVALID_ARG, "tol must be in (0, 1)");
+    if (batch->B == 0) return;
+    R3M_REQUIRE(b_dev && x_dev && work_dev && rep_host, R3M_ERR_INVALID_ARG, "NULL buffer");
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, stream);
+    const int m = opts->restart;
+    const int n_a = Z->n / Z->n_states;
+    const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m);
+    R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "GMRES workspace too small");
+
+    const int mv_chunks = choose_chunks(bd, 64);
+    size_t mv = matvec_partial_bytes(bd, n_a, mv_chunks, Z->near_dtype);
+    if (refine) mv = std::max(mv, matvec_partial_bytes(bd, n_a, mv_chunks, Z64->near_dtype));
+    GmresRun run;
+    run.ctx = ctx;
+    run.bd = &bd;
+    run.batch = batch;
+    run.n_a = n_a;
+    run.m = m;
+    run.B = bd.B;
+    run.s = stream;
+    run.W = layout_work((char*)work_dev, bd, n_a, m, mv);
+    run.ut = (int64_t)bd.total_units * n_a;
+    run.maxN = 0;
+    std::vector<RhsVec> rv(bd.B);
+    std::vector<int64_t> soff(bd.B);
+    for (int b = 0; b < bd.B; ++b) {
+      rv[b] = RhsVec{bd.unit_off[b] * n_a, bd.n_units[b] * n_a};
+      run.maxN = std::max(run.maxN, rv[b].N);
+      soff[b] = batch->state_off[b];
+    }
+    run.maxP = (int)((run.maxN + kDotChunk - 1) / kDotChunk);
+    R3M_CHECK_HIP(hipMemcpyAsync(run.W.rv, rv.data(), rv.size() * sizeof(RhsVec), hipMemcpyHostToDevice, stream));
+    R3M_CHECK_HIP(hipMemcpyAsync(run.W.soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice, stream));
+    R3M_CHECK_HIP(hipMemsetAsync(run.W.counters, 0, 256, stream));
+
+    // input checks on the device: state bytes and finite right-hand sides
+    const int64_t maxU = run.maxN / n_a;
+    hipLaunchKernelGGL(states_check_kernel, dim3(ceil_div((size_t)maxU, 256), bd.B), dim3(256), 0, stream,
+                       batch->states, run.W.rv, run.W.soff, n_a, Z->n_states, run.W.counters + 1);
+    hipLaunchKernelGGL(nonfinite_kernel, run.vgrid(), dim3(256), 0, stream, (const double2*)b_dev, run.W.rv,
+                       run.W.counters + 1);
+    const int f = run.flag_check(6);
+    R3M_REQUIRE(!(f & 2), R3M_ERR_INVALID_ARG, "codebook state out of range");
+    R3M_REQUIRE(!(f & 4), R3M_ERR_NONFINITE, "non-finite right-hand side");
+
+    const double2* b = (const double2*)b_dev;
+    double2* x = (double2*)x_dev;
+    std::vector<double> bnorm = run.host_norms(b);
+    hipLaunchKernelGGL(zero_kernel, run.vgrid(), dim3(256), 0, stream, x, run.W.rv);
+    std::vector<int> iters(bd.B, 0), refine_steps(bd.B, 0);
+    std::vector<double> rel(bd.B, 0.0);
+    double target = opts->tol;
+    if (refine) {
+      target = opts->refine_tol;
+      const int max_refine = std::max(1, opts->max_refine);
+      for (int step = 0; step <= max_refine; ++step) {
+        run.residual(Z64, b, x, run.W.ro);
+        std::vector<double> rn = run.host_norms(run.W.ro);
+        std::vector<int> act(bd.B, 0);
+        bool any = false;
+        for (int i = 0; i < bd.B; ++i) {
+          rel[i] = bnorm[i] > 0 ? rn[i] / bnorm[i] : 0.0;
+          act[i] = (rel[i] > target && iters[i] < opts->max_iter) ? 1 : 0;
+          any = any || act[i];
+        }
+        if (!any || step == max_refine) break;
+        hipLaunchKernelGGL(zero_kernel, run.vgrid(), dim3(256), 0, stream, run.W.d, run.W.rv);
+        run.solve(Z, run.W.ro, run.W.d, act, rn, opts->tol, opts->max_iter, iters);
+        hipLaunchKernelGGL(add_kernel, run.vgrid(), dim3(256), 0, stream, x, run.W.d, run.W.rv);
+        for (int i = 0; i < bd.B; ++i) refine_steps[i] += act[i];
+      }
+    } else {
+      run.solve(Z, b, x, std::vector<int>(bd.B, 1), bnorm, opts->tol, opts->max_iter, iters);
+      run.residual(Z, b, x, run.W.r);
+      std::vector<double> rn = run.host_norms(run.W.r);
+      for (int i = 0; i < bd.B; ++i) rel[i] = bnorm[i] > 0 ? rn[i] / bnorm[i] : 0.0;
+    }
+    hipLaunchKernelGGL(nonfinite_kernel, run.vgrid(), dim3(256), 0, stream, (const double2*)x, run.W.rv,
+                       run.W.counters + 1);
+    R3M_REQUIRE(!run.flag_check(4), R3M_ERR_NONFINITE, "non-finite solution");
+    bool all = true;
+    for (int i = 0; i < bd.B; ++i) {
+      rep_host[i].iters = iters[i];
+      rep_host[i].refine_steps = refine_steps[i];
+      rep_host[i].rel_residual = rel[i];
+      rep_host[i].converged = rel[i] <= target ? 1 : 0;
+      all = all && rep_host[i].converged;
+    }
+    R3M_REQUIRE(all, R3M_ERR_NOT_CONVERGED, "some right-hand sides did not converge");
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// Internal declarations shared by the translation units of libr3m.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "r3m.h"
+
+namespace r3m {
+
+// ----------------------------------------------------------------- errors
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+void set_thread_error(const std::string& msg);
+
+#define R3M_CHECK_HIP(expr)                                                          \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      throw ::r3m::Error{R3M_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define R3M_REQUIRE(cond, code, text)                                     \
+  do {                                                                    \
+    if (!(cond)) throw ::r3m::Error{(code), std::string(text)};           \
+  } while (0)
+
+// ------------------------------------------------------------- constants
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC0 = 299792458.0;
+constexpr double kMu0 = 4.0e-7 * kPi;
+constexpr double kEta0 = kMu0 * kC0;
+
+// ----------------------------------------------------------- device pool
+
+// Small device tables owned by the context (geometry, batch descriptors).
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  void ensure(size_t want);
+  void release();
+};
+
+struct BatchKey {
+  std::vector<int64_t> v;
+  const void* states;
+  bool operator<(const BatchKey& o) const {
+    if (states != o.states) return states < o.states;
+    return v < o.v;
+  }
+};
+
+// Device descriptor of a batch for a given unit-tile shape and chunk count.
+struct BatchDesc {
+  int32_t B = 0;
+  int64_t total_units = 0;
+  int32_t n_tiles = 0;
+  int32_t max_L = 0;
+  DevBuf dev;  // rhs table [B] then tile table [n_tiles]
+  const struct RhsDev* rhs = nullptr;
+  const struct TileDev* tiles = nullptr;
+  std::vector<int64_t> unit_off, n_units;
+  std::vector<int32_t> Lx, Ly;
+};
+
+struct RhsDev {
+  int64_t unit_off;
+  int64_t state_off;
+  int32_t Lx, Ly;
+};
+
+struct TileDev {
+  int32_t b;   // RHS
+  int32_t tx;  // first unit column
+  int32_t ty;  // first unit row
+  int32_t pad;
+};
+
+}  // namespace r3m
+
+struct r3m_ctx_s {
+  int device = 0;
+  std::string last_error;
+  std::mutex mu;
+  r3m::DevBuf flag;  // int32 flags for device-side checks
+  r3m::DevBuf geom;  // geometry tables
+  std::map<r3m::BatchKey, r3m::BatchDesc*> batches;
+};
+
+namespace r3m {
+
+// Host-side geometry preprocessing (connectivity only) and upload.
+struct GeomDev {
+  const double* tri_v;    // [n_tri][9]
+  const double* tri_area; // [n_tri]
+  const int32_t* rwg_tri; // [n_rwg][2]
+  const int32_t* rwg_free;// [n_rwg][2] local index of the free vertex
+  const double* rwg_len;  // [n_rwg]
+  int32_t n_tri, n_rwg;
+};
+
+void validate_geom(const r3m_unit_geom* g);
+GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream);
+
+const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int tile_h,
+                           hipStream_t stream);
+void validate_batch(const r3m_batch* batch, int Dx, int Dy);
+
+inline int32_t slot_of(int dx, int dy, int Dx, int Dy) { return (dy + Dy) * (2 * Dx + 1) + (dx + Dx); }
+
+// far index of displacement d among far slots (near = Chebyshev <= nr)
+__host__ __device__ inline int32_t far_index(int dx, int dy, int Dx, int Dy, int nr) {
+  int Nx = nr < Dx ? nr : Dx;
+  int Ny = nr < Dy ? nr : Dy;
+  int slot = (dy + Dy) * (2 * Dx + 1) + (dx + Dx);
+  int before;
+  if (dy > Ny) {
+    before = (2 * Ny + 1) * (2 * Nx + 1);
+  } else if (dy < -Ny) {
+    before = 0;
+  } else {
+    before = (dy + Ny) * (2 * Nx + 1) + (dx < -Nx ? 0 : (2 * Nx + 1));
+  }
+  return slot - before;
+}
+
+size_t dtype_size(r3m_dtype t);
+
+// Seven-point degree-5 triangle rule (Radon; Dunavant degree 5): barycentric
+// point i and its weight (weights sum to one).
+__host__ __device__ inline void quad7_point(int i, double& b0, double& b1, double& b2, double& w) {
+  const double s15 = sqrt(15.0);
+  const double a1 = (6.0 - s15) / 21.0, c1 = 1.0 - 2.0 * a1;
+  const double a2 = (6.0 + s15) / 21.0, c2 = 1.0 - 2.0 * a2;
+  if (i == 0) {
+    b0 = b1 = b2 = 1.0 / 3.0;
+    w = 9.0 / 40.0;
+    return;
+  }
+  const bool first = i <= 3;
+  const double a = first ? a1 : a2, c = first ? c1 : c2;
+  const int k = (i - 1) % 3;
+  b0 = k == 0 ? c : a;
+  b1 = k == 1 ? c : a;
+  b2 = k == 2 ? c : a;
+  w = first ? (155.0 - s15) / 1200.0 : (155.0 + s15) / 1200.0;
+}
+
+// guarded entry: converts exceptions into status codes
+template <class F>
+int guarded(r3m_ctx ctx, F&& f) {
+  try {
+    f();
+    return R3M_OK;
+  } catch (const Error& e) {
+    if (ctx) ctx->last_error = e.msg;
+    set_thread_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    if (ctx) ctx->last_error = e.what();
+    set_thread_error(e.what());
+    return R3M_ERR_INVALID_ARG;
+  }
+}
+
+inline unsigned ceil_div(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace r3m

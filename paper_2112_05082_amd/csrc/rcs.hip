@@ -1,0 +1,231 @@
+// Plane-wave excitation U_k of eq. (1) and bistatic RCS of the retrieved
+// currents (post-processing of Sec. IV-A), FP64.
+//
+// Excitation: U_m = int f_m . E_inc dS, E_inc = e0 e_hat exp(-j k k_hat . r),
+// 7-point rule, one thread per (RHS, unit, active RWG).
+// RCS: radiation vectors of the macro RWGs of the unit at the origin,
+// F_m(r_hat) = int f_m exp(j k r_hat . r) dS, are formed once per direction;
+// then N(r_hat) = sum_u exp(j k r_hat . c_u) sum_{m in A(s_u)} I_{u,m} F_m and
+// sigma = (k^2 eta^2 / 4 pi) |N - (N . r_hat) r_hat|^2 / |e0|^2.
+#include "r3m_common.h"
+
+#include <algorithm>
+
+namespace r3m {
+namespace {
+
+struct IncDev {
+  double kx, ky, kz;  // propagation direction k_hat
+  double ex, ey, ez;  // polarisation e_hat (theta_hat)
+  double e0;
+  double pad;
+};
+
+__global__ void plane_wave_kernel(GeomDev g, const RhsDev* __restrict__ rhs, const IncDev* __restrict__ inc,
+                                  const uint8_t* __restrict__ states, int n_a, int n_states, double k,
+                                  double px, double py, double2* __restrict__ out) {
+  const int b = blockIdx.y;
+  const RhsDev R = rhs[b];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t units = (int64_t)R.Lx * R.Ly;
+  if (e >= units * n_a) return;
+  const int64_t u = e / n_a;
+  const int m = (int)(e % n_a);
+  int s = states[R.state_off + u];
+  s = s < n_states ? s : n_states - 1;
+  const int mm = s * n_a + m;
+  const double cx = (double)(u % R.Lx) * px, cy = (double)(u / R.Lx) * py;
+  const IncDev I = inc[b];
+  double re = 0.0, im = 0.0;
+  for (int a = 0; a < 2; ++a) {
+    const int t = g.rwg_tri[2 * mm + a];
+    const int fv = g.rwg_free[2 * mm + a];
+    const double* v = g.tri_v + 9 * t;
+    const double A = g.tri_area[t];
+    const double c = (a == 0 ? 1.0 : -1.0) * g.rwg_len[mm] / (2.0 * A);
+    const double vx = v[3 * fv] + cx, vy = v[3 * fv + 1] + cy, vz = v[3 * fv + 2];
+    for (int i = 0; i < 7; ++i) {
+      double b0, b1, b2, w;
+      quad7_point(i, b0, b1, b2, w);
+      const double rx = b0 * v[0] + b1 * v[3] + b2 * v[6] + cx;
+      const double ry = b0 * v[1] + b1 * v[4] + b2 * v[7] + cy;
+      const double rz = b0 * v[2] + b1 * v[5] + b2 * v[8];
+      const double proj = (rx - vx) * I.ex + (ry - vy) * I.ey + (rz - vz) * I.ez;
+      double sn, cs;
+      sincos(-k * (I.kx * rx + I.ky * ry + I.kz * rz), &sn, &cs);
+      re += c * w * A * proj * cs;
+      im += c * w * A * proj * sn;
+    }
+  }
+  out[R.unit_off * n_a + e] = make_double2(I.e0 * re, I.e0 * im);
+}
+
+// F[dir][m][3] for the macro unit at the origin
+__global__ void macro_radiation_kernel(GeomDev g, const double* __restrict__ dirs, int n_dir, double k,
+                                       double2* __restrict__ F) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_dir * g.n_rwg) return;
+  const int d = e / g.n_rwg, m = e % g.n_rwg;
+  const double th = dirs[2 * d], ph = dirs[2 * d + 1];
+  const double rx = sin(th) * cos(ph), ry = sin(th) * sin(ph), rz = cos(th);
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int a = 0; a < 2; ++a) {
+    const int t = g.rwg_tri[2 * m + a];
+    const int fv = g.rwg_free[2 * m + a];
+    const double* v = g.tri_v + 9 * t;
+    const double A = g.tri_area[t];
+    const double c = (a == 0 ? 1.0 : -1.0) * g.rwg_len[m] / (2.0 * A);
+    for (int i = 0; i < 7; ++i) {
+      double b0, b1, b2, w;
+      quad7_point(i, b0, b1, b2, w);
+      double p[3];
+      for (int q = 0; q < 3; ++q) p[q] = b0 * v[q] + b1 * v[3 + q] + b2 * v[6 + q];
+      double sn, cs;
+      sincos(k * (rx * p[0] + ry * p[1] + rz * p[2]), &sn, &cs);
+      for (int q = 0; q < 3; ++q) {
+        const double f = c * w * A * (p[q] - v[3 * fv + q]);
+        acc[2 * q] += f * cs;
+        acc[2 * q + 1] += f * sn;
+      }
+    }
+  }
+  for (int q = 0; q < 3; ++q) F[(size_t)e * 3 + q] = make_double2(acc[2 * q], acc[2 * q + 1]);
+}
+
+constexpr int kRcsThreads = 256;
+
+__global__ void __launch_bounds__(kRcsThreads)
+rcs_kernel(const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, const double2* __restrict__ I,
+           const double2* __restrict__ F, const double* __restrict__ dirs, int n_dir, int n, int n_a,
+           int n_states, double k, double px, double py, double scale, double* __restrict__ sigma) {
+  __shared__ double sh[kRcsThreads / 64][6];
+  const int d = blockIdx.x, b = blockIdx.y;
+  const RhsDev R = rhs[b];
+  const double th = dirs[2 * d], ph = dirs[2 * d + 1];
+  const double rx = sin(th) * cos(ph), ry = sin(th) * sin(ph), rz = cos(th);
+  const int64_t units = (int64_t)R.Lx * R.Ly;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const double2* Fd = F + (size_t)d * n * 3;
+  for (int64_t u = threadIdx.x; u < units; u += blockDim.x) {
+    int s = states[R.state_off + u];
+    s = s < n_states ? s : n_states - 1;
+    const double cx = (double)(u % R.Lx) * px, cy = (double)(u / R.Lx) * py;
+    double sn, cs;
+    sincos(k * (rx * cx + ry * cy), &sn, &cs);
+    double loc[6] = {0, 0, 0, 0, 0, 0};
+    const double2* Iu = I + (R.unit_off + u) * n_a;
+    for (int m = 0; m < n_a; ++m) {
+      const double2 cur = Iu[m];
+      const double2* f = Fd + (size_t)(s * n_a + m) * 3;
+      for (int q = 0; q < 3; ++q) {
+        loc[2 * q] += cur.x * f[q].x - cur.y * f[q].y;
+        loc[2 * q + 1] += cur.x * f[q].y + cur.y * f[q].x;
+      }
+    }
+    for (int q = 0; q < 3; ++q) {
+      acc[2 * q] += loc[2 * q] * cs - loc[2 * q + 1] * sn;
+      acc[2 * q + 1] += loc[2 * q] * sn + loc[2 * q + 1] * cs;
+    }
+  }
+  for (int q = 0; q < 6; ++q)
+    for (int o = 32; o >= 1; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 6; ++q) sh[threadIdx.x >> 6][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double N[6];
+    for (int q = 0; q < 6; ++q) {
+      N[q] = sh[0][q];
+      for (int w = 1; w < kRcsThreads / 64; ++w) N[q] += sh[w][q];
+    }
+    const double rr[3] = {rx, ry, rz};
+    const double dre = N[0] * rx + N[2] * ry + N[4] * rz;
+    const double dim = N[1] * rx + N[3] * ry + N[5] * rz;
+    double p2 = 0.0;
+    for (int q = 0; q < 3; ++q) {
+      const double pr = N[2 * q] - dre * rr[q], pi = N[2 * q + 1] - dim * rr[q];
+      p2 += pr * pr + pi * pi;
+    }
+    sigma[(size_t)b * n_dir + d] = scale * p2;
+  }
+}
+
+}  // namespace
+}  // namespace r3m
+
+using namespace r3m;
+
+extern "C" {
+
+int r3m_plane_wave_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch,
+                       const double* inc_host, void* b_dev, hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_geom(geom);
+    validate_batch(batch, 1 << 20, 1 << 20);
+    if (batch->B == 0) return;
+    R3M_REQUIRE(inc_host && b_dev, R3M_ERR_INVALID_ARG, "NULL argument");
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    const int n_a = geom->state_off[1] - geom->state_off[0];
+    GeomDev g = upload_geom(ctx, geom, stream);
+    const BatchDesc& bd = get_batch(ctx, batch, 4, 4, stream);
+    std::vector<IncDev> inc(bd.B);
+    for (int b = 0; b < bd.B; ++b) {
+      const double th = inc_host[3 * b], ph = inc_host[3 * b + 1];
+      R3M_REQUIRE(std::isfinite(th) && std::isfinite(ph) && std::isfinite(inc_host[3 * b + 2]),
+                  R3M_ERR_INVALID_ARG, "non-finite incidence");
+      inc[b] = IncDev{-std::sin(th) * std::cos(ph), -std::sin(th) * std::sin(ph), -std::cos(th),
+                      std::cos(th) * std::cos(ph), std::cos(th) * std::sin(ph), -std::sin(th),
+                      inc_host[3 * b + 2], 0.0};
+    }
+    DevBuf tmp;
+    tmp.ensure(inc.size() * sizeof(IncDev));
+    R3M_CHECK_HIP(hipMemcpyAsync(tmp.ptr, inc.data(), inc.size() * sizeof(IncDev), hipMemcpyHostToDevice, stream));
+    int64_t maxU = 0;
+    for (int b = 0; b < bd.B; ++b) maxU = std::max<int64_t>(maxU, bd.n_units[b]);
+    const double k = 2.0 * kPi * geom->freq_hz / kC0;
+    dim3 grid(ceil_div((size_t)maxU * n_a, 256), bd.B);
+    hipLaunchKernelGGL(plane_wave_kernel, grid, dim3(256), 0, stream, g, bd.rhs, (const IncDev*)tmp.ptr,
+                       batch->states, n_a, geom->n_states, k, geom->period_x, geom->period_y, (double2*)b_dev);
+    R3M_CHECK_HIP(hipGetLastError());
+    R3M_CHECK_HIP(hipStreamSynchronize(stream));
+    tmp.release();
+  });
+}
+
+int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, const void* I_dev,
+            int32_t n_dir, const double* dirs_host, double e0, double* sigma_dev, hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_geom(geom);
+    validate_batch(batch, 1 << 20, 1 << 20);
+    R3M_REQUIRE(n_dir >= 0, R3M_ERR_INVALID_ARG, "n_dir < 0");
+    R3M_REQUIRE(e0 != 0.0 && std::isfinite(e0), R3M_ERR_INVALID_ARG, "e0 must be finite and non-zero");
+    if (batch->B == 0 || n_dir == 0) return;
+    R3M_REQUIRE(I_dev && dirs_host && sigma_dev, R3M_ERR_INVALID_ARG, "NULL argument");
+    for (int d = 0; d < 2 * n_dir; ++d)
+      R3M_REQUIRE(std::isfinite(dirs_host[d]), R3M_ERR_INVALID_ARG, "non-finite direction");
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    const int n_a = geom->state_off[1] - geom->state_off[0];
+    GeomDev g = upload_geom(ctx, geom, stream);
+    const BatchDesc& bd = get_batch(ctx, batch, 4, 4, stream);
+    const double k = 2.0 * kPi * geom->freq_hz / kC0;
+    DevBuf tmp;
+    const size_t fbytes = (size_t)n_dir * geom->n_rwg * 3 * sizeof(double2);
+    tmp.ensure(fbytes + (size_t)n_dir * 16 + 256);
+    double* ddev = (double*)((char*)tmp.ptr + fbytes);
+    R3M_CHECK_HIP(hipMemcpyAsync(ddev, dirs_host, (size_t)n_dir * 16, hipMemcpyHostToDevice, stream));
+    double2* F = (double2*)tmp.ptr;
+    hipLaunchKernelGGL(macro_radiation_kernel, dim3(ceil_div((size_t)n_dir * geom->n_rwg, 128)), dim3(128), 0,
+                       stream, g, ddev, n_dir, k, F);
+    const double scale = k * k * kEta0 * kEta0 / (4.0 * kPi) / (e0 * e0);
+    hipLaunchKernelGGL(rcs_kernel, dim3(n_dir, bd.B), dim3(kRcsThreads), 0, stream, bd.rhs, batch->states,
+                       (const double2*)I_dev, F, ddev, n_dir, geom->n_rwg, n_a, geom->n_states, k,
+                       geom->period_x, geom->period_y, scale, sigma_dev);
+    R3M_CHECK_HIP(hipGetLastError());
+    R3M_CHECK_HIP(hipStreamSynchronize(stream));
+    tmp.release();
+  });
+}
+
+}  // extern "C"
