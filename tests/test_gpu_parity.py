@@ -263,8 +263,11 @@ def test_plain_6x6_solve_and_rcs(r3m, ctx):
     assert rel_max(b.cpu().numpy(), U) <= 1e-13
     x = torch.zeros_like(b)
     work = torch.empty(r3m.gmres_work_bytes(ctx, store, batch, 100), dtype=torch.uint8, device=DEV)
-    rc, rep = r3m.r3m_gmres_solve(ctx, store, None, batch, b, x, 1e-12, 100, 500, work)
+    rc, rep = r3m.r3m_gmres_solve(ctx, store, None, batch, b, x, 1e-12, 100, 1500, work)
     assert rep[0][3] and rep[0][2] <= 1e-12
+    # same algorithm family as the oracle's GMRES(100): similar iteration count
+    ref_it = solve.gmres(lambda v: Zk @ v, U, tol=1e-12, restart=100, max_iter=3000)
+    assert abs(rep[0][0] - ref_it.iters) <= max(10, 0.05 * ref_it.iters)
     I_ref = solve.lu_solve(Zk, U)
     xs = x.cpu().numpy()
     assert rel_l2(xs, I_ref) <= 1e-8
