@@ -176,6 +176,7 @@ const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int 
     d->n_units.push_back((int64_t)Lx * Ly);
     total = std::max<int64_t>(total, batch->unit_off[b] + (int64_t)Lx * Ly);
     d->max_L = std::max(d->max_L, std::max(Lx, Ly));
+    d->max_units = std::max<int64_t>(d->max_units, (int64_t)Lx * Ly);
     for (int ty = 0; ty < Ly; ty += tile_h)
       for (int tx = 0; tx < Lx; tx += tile_w) tiles.push_back(TileDev{b, tx, ty, 0});
   }

@@ -16,14 +16,14 @@ namespace r3m {
 
 void validate_store(const r3m_store* Z);
 int choose_chunks(const BatchDesc& bd, int max_chunks);
-size_t matvec_partial_bytes(const BatchDesc& bd, int n_a, int chunks, r3m_dtype store_dtype);
+size_t matvec_partial_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks);
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
                    r3m_dtype vec_dtype, const void* x, void* y, void* partial, int chunks,
                    hipStream_t stream);
 
 namespace {
 
-constexpr int kTW = 4, kTH = 4;
+constexpr int kTW = 8, kTH = 8;  // unit block of the matvec workgroups
 constexpr int kDotChunk = 8192;
 constexpr int kDotThreads = 256;
 constexpr int kCheckEvery = 4;
@@ -507,8 +507,8 @@ void validate_store(const r3m_store* Z);
 size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m) {
   const int n_a = Z->n / Z->n_states;
   const int chunks = choose_chunks(bd, 64);
-  size_t mv = matvec_partial_bytes(bd, n_a, chunks, Z->near_dtype);
-  if (Z64) mv = std::max(mv, matvec_partial_bytes(bd, n_a, chunks, Z64->near_dtype));
+  size_t mv = matvec_partial_bytes(bd, Z, chunks);
+  if (Z64) mv = std::max(mv, matvec_partial_bytes(bd, Z64, chunks));
   return layout_work(nullptr, bd, n_a, m, mv).bytes;
 }
 
@@ -528,10 +528,12 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* ba
     R3M_REQUIRE(opts->restart >= 1 && opts->restart <= 1024, R3M_ERR_INVALID_ARG, "restart out of range");
     if (batch->B == 0) return;
     const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, 0);
-    // the refinement store shares the partial layout; its dtype may be wider
-    r3m_store wide = *Z;
-    wide.near_dtype = R3M_C128;
-    out = gmres_bytes(ctx, Z, &wide, bd, opts->restart);
+    // room for a refinement store of any layout in complex128: far groups plus
+    // the largest number of near groups, complex128 partials, plus a vector copy
+    const int n_a = Z->n / Z->n_states;
+    const size_t vec = (size_t)bd.total_units * n_a * 16;
+    const size_t mv = (size_t)(choose_chunks(bd, 64) + 128) * vec + vec + 256;
+    out = layout_work(nullptr, bd, n_a, opts->restart, mv).bytes;
   });
   return rc == R3M_OK ? out : 0;
 }
@@ -564,8 +566,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "GMRES workspace too small");
 
     const int mv_chunks = choose_chunks(bd, 64);
-    size_t mv = matvec_partial_bytes(bd, n_a, mv_chunks, Z->near_dtype);
-    if (refine) mv = std::max(mv, matvec_partial_bytes(bd, n_a, mv_chunks, Z64->near_dtype));
+    size_t mv = matvec_partial_bytes(bd, Z, mv_chunks);
+    if (refine) mv = std::max(mv, matvec_partial_bytes(bd, Z64, mv_chunks));
     GmresRun run;
     run.ctx = ctx;
     run.bd = &bd;

@@ -14,172 +14,436 @@
 #include "r3m_common.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace r3m {
 namespace {
 
-constexpr int kTW = 4, kTH = 4, kTU = kTW * kTH;
+constexpr int kTW = 4, kTH = 4, kTU = kTW * kTH;  // tile of one wave
+constexpr int kBW = 8, kBH = 8, kBU = kBW * kBH;  // block of one workgroup (2 x 2 tiles)
+constexpr int kQ = 4;     // lanes per observer unit (row quarters)
+constexpr int kRch = 8;   // ranks held in registers per pass
 
 template <typename T>
 struct Cx {
   T re, im;
 };
 
-template <typename S, typename XT>
-__device__ inline Cx<S> load_x(const XT* x, size_t idx) {
-  return Cx<S>{(S)x[2 * idx], (S)x[2 * idx + 1]};
+// two consecutive complex values (index must be even for the vector load)
+template <typename T>
+__device__ inline void load2(const T* p, size_t idx, Cx<T>& a, Cx<T>& b);
+template <>
+__device__ inline void load2<float>(const float* p, size_t idx, Cx<float>& a, Cx<float>& b) {
+  const float4 v = *reinterpret_cast<const float4*>(p + 2 * idx);
+  a = {v.x, v.y};
+  b = {v.z, v.w};
+}
+template <>
+__device__ inline void load2<double>(const double* p, size_t idx, Cx<double>& a, Cx<double>& b) {
+  const double2 u = *reinterpret_cast<const double2*>(p + 2 * idx);
+  const double2 v = *reinterpret_cast<const double2*>(p + 2 * idx + 2);
+  a = {u.x, u.y};
+  b = {v.x, v.y};
 }
 
-template <typename S, typename XT>
-__global__ void __launch_bounds__(1024)
-matvec_tile_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, int n_chunks,
-                   const uint8_t* __restrict__ states, const S* __restrict__ nearb, int Nx, int Ny,
-                   const S* __restrict__ farf, const int* __restrict__ ranks, int max_rank, int Dx,
-                   int Dy, int nr, int n, int n_a, int n_states, const XT* __restrict__ x,
-                   XT* __restrict__ y, S* __restrict__ partial, int64_t total_units) {
-  extern __shared__ unsigned char smem_raw[];
-  Cx<S>* tbuf = reinterpret_cast<Cx<S>*>(smem_raw);  // [kTU][max_rank]
+// acc += a * b as two fused multiply-adds per real component
+template <typename S>
+__device__ __forceinline__ void cmac(S& re, S& im, Cx<S> a, Cx<S> b) {
+  re = fma(a.re, b.re, re);
+  re = fma(-a.im, b.im, re);
+  im = fma(a.re, b.im, im);
+  im = fma(a.im, b.re, im);
+}
+// acc += conj(a) * b
+template <typename S>
+__device__ __forceinline__ void cmacc(S& re, S& im, Cx<S> a, Cx<S> b) {
+  re = fma(a.re, b.re, re);
+  re = fma(a.im, b.im, re);
+  im = fma(a.re, b.im, im);
+  im = fma(-a.im, b.re, im);
+}
 
-  const TileDev tile = tiles[blockIdx.x];
-  const int chunk = blockIdx.y;
-  const RhsDev R = rhs[tile.b];
-  const int t = threadIdx.x;
-  const int ul = t / n_a, m = t % n_a;
-  const bool active_thread = ul < kTU;
-  const int ux = ul % kTW, uy = ul / kTW;
-  const int ix = tile.tx + ux, iy = tile.ty + uy;
-  const bool vi = active_thread && ix < R.Lx && iy < R.Ly;
-  // state bytes >= n_states are clamped (they are rejected by the solver's input check)
-  const int si = vi ? min((int)states[R.state_off + (int64_t)iy * R.Lx + ix], n_states - 1) : 0;
-  const int offi = si * n_a;
+// lane swaps inside a quad of lanes (DPP quad permutes)
+__device__ __forceinline__ float quad_swap1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_swap2(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double quad_swap1(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double quad_swap2(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0x4E, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x4E, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
-  const int ox_hi = min(tile.tx + kTW, R.Lx) - 1;  // last observer column of the tile
-  const int oy_hi = min(tile.ty + kTH, R.Ly) - 1;
-  const int Wd = 2 * R.Lx - 1;
-  const int nd = Wd * (2 * R.Ly - 1);
-  const int NW = 2 * Nx + 1;
-  const size_t nn2 = (size_t)n * n;
-
-  S acc_re = 0, acc_im = 0;
-  for (int e = chunk; e < nd; e += n_chunks) {
-    const int dx = e % Wd - (R.Lx - 1);
-    const int dy = e / Wd - (R.Ly - 1);
-    // does any observer of the tile have its source inside the array? (uniform)
-    if (ox_hi - dx < 0 || tile.tx - dx > R.Lx - 1 || oy_hi - dy < 0 || tile.ty - dy > R.Ly - 1) continue;
-    const int jx = ix - dx, jy = iy - dy;
-    const bool vj = vi && jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly;
-    const int adx = dx < 0 ? -dx : dx, ady = dy < 0 ? -dy : dy;
-    if (adx <= nr && ady <= nr) {
-      if (vj) {
-        const int sj = min((int)states[R.state_off + (int64_t)jy * R.Lx + jx], n_states - 1);
-        const S* Zb = nearb + ((size_t)((dy + Ny) * NW + (dx + Nx)) * nn2 + (size_t)(offi + m) * n + sj * n_a) * 2;
-        const size_t xb = (size_t)(R.unit_off + (int64_t)jy * R.Lx + jx) * n_a;
-        for (int c = 0; c < n_a; ++c) {
-          const S zr = Zb[2 * c], zi = Zb[2 * c + 1];
-          const Cx<S> xv = load_x<S>(x, xb + c);
-          acc_re += zr * xv.re - zi * xv.im;
-          acc_im += zr * xv.im + zi * xv.re;
-        }
-      }
-    } else {
-      const int f = far_index(dx, dy, Dx, Dy, nr);
-      const int rank = ranks[f];
-      const S* Uf = farf + (size_t)f * 2 * max_rank * n * 2;
-      const S* Vf = Uf + (size_t)max_rank * n * 2;
-      __syncthreads();
-      // stage 1: t[u][rho] = sum_c conj(V[rho][off_j + c]) x_j[c]
-      for (int w = t; w < kTU * rank; w += blockDim.x) {
-        const int uu = w / rank, rho = w % rank;
-        const int jjx = tile.tx + uu % kTW - dx, jjy = tile.ty + uu / kTW - dy;
-        const int iix = tile.tx + uu % kTW, iiy = tile.ty + uu / kTW;
-        S tr = 0, ti = 0;
-        if (iix < R.Lx && iiy < R.Ly && jjx >= 0 && jjx < R.Lx && jjy >= 0 && jjy < R.Ly) {
-          const int sj = min((int)states[R.state_off + (int64_t)jjy * R.Lx + jjx], n_states - 1);
-          const S* v = Vf + ((size_t)rho * n + sj * n_a) * 2;
-          const size_t xb = (size_t)(R.unit_off + (int64_t)jjy * R.Lx + jjx) * n_a;
-          for (int c = 0; c < n_a; ++c) {
-            const S vr = v[2 * c], vim = v[2 * c + 1];
-            const Cx<S> xv = load_x<S>(x, xb + c);
-            tr += vr * xv.re + vim * xv.im;
-            ti += vr * xv.im - vim * xv.re;
-          }
-        }
-        tbuf[uu * max_rank + rho] = Cx<S>{tr, ti};
-      }
-      __syncthreads();
-      // stage 2: y_i[m] += sum_rho U[rho][off_i + m] t[u][rho]
-      if (vj) {
-        const S* u = Uf + (size_t)(offi + m) * 2;
-        for (int rho = 0; rho < rank; ++rho) {
-          const S ur = u[(size_t)rho * n * 2], ui = u[(size_t)rho * n * 2 + 1];
-          const Cx<S> tv = tbuf[ul * max_rank + rho];
-          acc_re += ur * tv.re - ui * tv.im;
-          acc_im += ur * tv.im + ui * tv.re;
-        }
+// Far contribution of one staged rank slice (RC ranks, compile-time) for one
+// lane: t = V[A(s_j)]^H x_j over the lane's quarter, summed over the unit's
+// four lanes, then y += U[A(s_i)] t on the lane's rows.
+template <typename S, int QS, int RC>
+__device__ __forceinline__ void far_slice(const Cx<S>* __restrict__ lds_u, const Cx<S>* __restrict__ lds_v,
+                                          int n, int offi, int offj, int m0, bool vj, const Cx<S> (&xr)[QS],
+                                          S (&acc_re)[QS], S (&acc_im)[QS]) {
+  S t_re[RC], t_im[RC];
+#pragma unroll
+  for (int rr = 0; rr < RC; ++rr) t_re[rr] = t_im[rr] = 0;
+  if (vj) {
+#pragma unroll
+    for (int k = 0; k < QS; k += 2) {
+      const Cx<S> x0 = xr[k], x1 = xr[k + 1];
+#pragma unroll
+      for (int rr = 0; rr < RC; ++rr) {
+        Cx<S> v0, v1;
+        load2<S>(reinterpret_cast<const S*>(lds_v), (size_t)rr * n + offj + m0 + k, v0, v1);
+        cmacc(t_re[rr], t_im[rr], v0, x0);  // conj(v) x
+        cmacc(t_re[rr], t_im[rr], v1, x1);
       }
     }
   }
-  if (!vi) return;
-  const size_t yi = (size_t)(R.unit_off + (int64_t)iy * R.Lx + ix) * n_a + m;
-  if (partial == nullptr) {
-    y[2 * yi] = (XT)acc_re;
-    y[2 * yi + 1] = (XT)acc_im;
-  } else {
-    const size_t pi = ((size_t)chunk * total_units * n_a + yi) * 2;
-    partial[pi] = acc_re;
-    partial[pi + 1] = acc_im;
+#pragma unroll
+  for (int rr = 0; rr < RC; ++rr) {
+    t_re[rr] += quad_swap1(t_re[rr]);
+    t_im[rr] += quad_swap1(t_im[rr]);
+    t_re[rr] += quad_swap2(t_re[rr]);
+    t_im[rr] += quad_swap2(t_im[rr]);
+  }
+  if (vj) {
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+#pragma unroll
+      for (int k = 0; k < QS; k += 2) {
+        Cx<S> u0, u1;
+        load2<S>(reinterpret_cast<const S*>(lds_u), (size_t)rr * n + offi + m0 + k, u0, u1);
+        const Cx<S> tv = {t_re[rr], t_im[rr]};
+        cmac(acc_re[k], acc_im[k], u0, tv);
+        cmac(acc_re[k + 1], acc_im[k + 1], u1, tv);
+      }
+    }
   }
 }
 
-// y[i][m] = sum over chunks (fixed order) of partial[c][i][m], for the units
-// of each tile (units outside every RHS are never touched).
+// Near field: one workgroup of four waves per (8x8 block of observer units,
+// near displacement d); wave w owns the 4x4 tile (w & 1, w >> 1) of the
+// block, lane (unit, quarter q) owns rows [q*QS, q*QS + QS) of y_u and adds
+// Z(d)[A(s_i), A(s_j)] x_j.  The result goes to its own partial slot.
+template <typename S, int QS>
+__global__ void __launch_bounds__(256)
+near_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, const uint8_t* __restrict__ states,
+            const S* __restrict__ nearb, int Nx, int Ny, int n, int n_a, int n_states, const S* __restrict__ x,
+            S* __restrict__ out, int64_t total_units, int slot0, int hgroups) {
+  const TileDev blk = tiles[blockIdx.x];
+  const int h = blockIdx.y;
+  const RhsDev R = rhs[blk.b];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int ul = lane / kQ, q = lane % kQ;
+  const int ix = blk.tx + (wave & 1) * kTW + ul % kTW, iy = blk.ty + (wave >> 1) * kTH + ul / kTW;
+  const bool vi = ix < R.Lx && iy < R.Ly;
+  if (!vi) return;
+  const int si = min((int)states[R.state_off + (int64_t)iy * R.Lx + ix], n_states - 1);
+  const int m0 = q * QS;
+  const int n_near = (2 * Nx + 1) * (2 * Ny + 1);
+  S acc_re[QS], acc_im[QS];
+#pragma unroll
+  for (int k = 0; k < QS; ++k) acc_re[k] = acc_im[k] = 0;
+  for (int nslot = h; nslot < n_near; nslot += hgroups) {
+    const int dx = nslot % (2 * Nx + 1) - Nx, dy = nslot / (2 * Nx + 1) - Ny;
+    const int jx = ix - dx, jy = iy - dy;
+    if (!(jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly)) continue;
+    const int sj = min((int)states[R.state_off + (int64_t)jy * R.Lx + jx], n_states - 1);
+    const S* xj = x + (size_t)(R.unit_off + (int64_t)jy * R.Lx + jx) * n_a * 2;
+    const S* Zb = nearb + (size_t)nslot * n * n * 2;
+    for (int c = 0; c < n_a; c += 2) {
+      Cx<S> x0, x1;
+      load2<S>(xj, c, x0, x1);
+#pragma unroll
+      for (int k = 0; k < QS; ++k) {
+        Cx<S> z0, z1;
+        load2<S>(Zb, (size_t)(si * n_a + m0 + k) * n + sj * n_a + c, z0, z1);
+        cmac(acc_re[k], acc_im[k], z0, x0);
+        cmac(acc_re[k], acc_im[k], z1, x1);
+      }
+    }
+  }
+  const size_t yb = (size_t)(R.unit_off + (int64_t)iy * R.Lx + ix) * n_a;
+  S* o = out + ((size_t)(slot0 + h) * total_units * n_a + yb) * 2;
+#pragma unroll
+  for (int k = 0; k < QS; ++k) {
+    o[2 * (m0 + k)] = acc_re[k];
+    o[2 * (m0 + k) + 1] = acc_im[k];
+  }
+}
+
+// Far field: one workgroup of four waves per (8x8 block of observer units,
+// displacement group); wave w owns the 4x4 tile (w & 1, w >> 1).  The far
+// displacements of the block (those of the rectangle that keeps a source in
+// the array, minus the near square) are dealt out round-robin to the groups.
+// Per displacement, the workgroup stages up to kRch rows of U and V (all
+// states) in LDS; the next displacement's slice and the lane's quarter of
+// x_j are fetched into registers while the current one is computed.  Lane
+// (unit u, quarter q) forms its quarter of t = V[A(s_j)]^H x_j, the unit's
+// four lanes add their parts with two lane swaps, and the lane expands its own
+// rows y += U[A(s_i)] t.  Ranks above kRch take extra synchronous slices.
+template <typename S, int QS>
+__global__ void __launch_bounds__(256)
+far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, int groups,
+           const uint8_t* __restrict__ states, const S* __restrict__ farf, const int* __restrict__ ranks,
+           int max_rank, int Dx, int Dy, int nr, int n, int n_a, int n_states, const S* __restrict__ x,
+           S* __restrict__ out, int64_t total_units, int lds_state_cap) {
+  extern __shared__ unsigned char smem_raw[];
+  Cx<S>* lds_u = reinterpret_cast<Cx<S>*>(smem_raw);  // [kRch][n]
+  Cx<S>* lds_v = lds_u + kRch * n;                     // [kRch][n]
+  uint8_t* lds_s = reinterpret_cast<uint8_t*>(lds_v + kRch * n);
+  const TileDev blk = tiles[blockIdx.x];
+  const int g = blockIdx.y;
+  const RhsDev R = rhs[blk.b];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int ul = lane / kQ, q = lane % kQ;
+  const int tx = blk.tx + (wave & 1) * kTW, ty = blk.ty + (wave >> 1) * kTH;
+  const int ix = tx + ul % kTW, iy = ty + ul / kTW;
+  const bool vi = ix < R.Lx && iy < R.Ly;
+
+  const int64_t units = (int64_t)R.Lx * R.Ly;
+  const bool st_lds = units <= lds_state_cap;
+  if (st_lds)
+    for (int64_t u = tid; u < units; u += blockDim.x) lds_s[u] = states[R.state_off + u];
+  __syncthreads();
+  auto state_at = [&](int64_t u) -> int {
+    const int s = st_lds ? lds_s[u] : states[R.state_off + u];
+    return min(s, n_states - 1);
+  };
+  const int si = vi ? state_at((int64_t)iy * R.Lx + ix) : 0;
+  const int offi = si * n_a;
+  const int m0 = q * QS;
+
+  const int bx_hi = min(blk.tx + 2 * kTW, R.Lx) - 1, by_hi = min(blk.ty + 2 * kTH, R.Ly) - 1;
+  const int dx_lo = blk.tx - (R.Lx - 1), dy_lo = blk.ty - (R.Ly - 1);
+  const int wdx = bx_hi - dx_lo + 1;
+  const int nd = wdx * (by_hi - dy_lo + 1);
+  const int ox_hi = min(tx + kTW, R.Lx) - 1, oy_hi = min(ty + kTH, R.Ly) - 1;
+  const bool wave_has_obs = tx < R.Lx && ty < R.Ly;
+  const int fstride = 2 * max_rank * n * 2;  // reals per far block
+
+  // next far displacement of this group at or after e (uniform); nd if none
+  auto next_far = [&](int e) {
+    for (; e < nd; e += groups) {
+      const int dx = dx_lo + e % wdx, dy = dy_lo + e / wdx;
+      if ((dx < 0 ? -dx : dx) > nr || (dy < 0 ? -dy : dy) > nr) return e;
+    }
+    return nd;
+  };
+
+  // per-thread share of one staged slice: rows [rho0, rho0 + rc) of U and V
+  constexpr int kPer = (kRch * 160 + 511) / 512;  // float4/double-pair chunks per thread (n <= 160)
+  Cx<S> pu[2 * kPer], pv[2 * kPer];
+  auto fetch = [&](const S* Uf, int rho0, int rc) {
+    const int cnt = rc * n;
+    const S* us = Uf + (size_t)rho0 * n * 2;
+    const S* vs = Uf + (size_t)max_rank * n * 2 + (size_t)rho0 * n * 2;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e2 = 2 * (tid + i * 256);
+      if (e2 < cnt) {
+        load2<S>(us, e2, pu[2 * i], pu[2 * i + 1]);
+        load2<S>(vs, e2, pv[2 * i], pv[2 * i + 1]);
+      }
+    }
+  };
+  auto stash = [&](int rc) {
+    const int cnt = rc * n;
+#pragma unroll
+    for (int i = 0; i < kPer; ++i) {
+      const int e2 = 2 * (tid + i * 256);
+      if (e2 < cnt) {
+        lds_u[e2] = pu[2 * i];
+        lds_u[e2 + 1] = pu[2 * i + 1];
+        lds_v[e2] = pv[2 * i];
+        lds_v[e2 + 1] = pv[2 * i + 1];
+      }
+    }
+  };
+  auto fetch_x = [&](int dx, int dy, Cx<S> (&xr)[QS]) {
+    const int jx = ix - dx, jy = iy - dy;
+    const bool vj = vi && jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly;
+    if (vj) {
+      const S* xj = x + (size_t)(R.unit_off + (int64_t)jy * R.Lx + jx) * n_a * 2;
+#pragma unroll
+      for (int k = 0; k < QS; k += 2) load2<S>(xj, m0 + k, xr[k], xr[k + 1]);
+    }
+  };
+
+  S acc_re[QS], acc_im[QS];
+#pragma unroll
+  for (int k = 0; k < QS; ++k) acc_re[k] = acc_im[k] = 0;
+
+  int e = next_far(g);
+  int f = 0, r = 0;
+  Cx<S> xc[QS], xn[QS];
+  if (e < nd) {
+    const int dx = dx_lo + e % wdx, dy = dy_lo + e / wdx;
+    f = far_index(dx, dy, Dx, Dy, nr);
+    r = ranks[f];
+    fetch(farf + (size_t)f * fstride, 0, min(kRch, r));
+    fetch_x(dx, dy, xc);
+  }
+  while (e < nd) {
+    const int dx = dx_lo + e % wdx, dy = dy_lo + e / wdx;
+    const int rc = min(kRch, r);
+    stash(rc);
+    __syncthreads();
+    // prefetch the next displacement while this one is computed
+    const int en = next_far(e + groups);
+    int fnext = 0, rnext = 0;
+    if (en < nd) {
+      const int dxn = dx_lo + en % wdx, dyn = dy_lo + en / wdx;
+      fnext = far_index(dxn, dyn, Dx, Dy, nr);
+      rnext = ranks[fnext];
+      fetch(farf + (size_t)fnext * fstride, 0, min(kRch, rnext));
+      fetch_x(dxn, dyn, xn);
+    }
+    const bool wave_active = wave_has_obs && !(ox_hi - dx < 0 || tx - dx > R.Lx - 1 || oy_hi - dy < 0 ||
+                                               ty - dy > R.Ly - 1);
+    const int jx = ix - dx, jy = iy - dy;
+    const bool vj = vi && jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly;
+    const int offj = vj ? state_at((int64_t)jy * R.Lx + jx) * n_a : 0;
+    if (wave_active) {
+      switch (rc) {
+        case 1: far_slice<S, QS, 1>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 2: far_slice<S, QS, 2>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 3: far_slice<S, QS, 3>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 4: far_slice<S, QS, 4>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 5: far_slice<S, QS, 5>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 6: far_slice<S, QS, 6>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 7: far_slice<S, QS, 7>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        default: far_slice<S, QS, 8>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+      }
+    }
+    // ranks above kRch: further slices, staged synchronously
+    for (int rho0 = kRch; rho0 < r; rho0 += kRch) {
+      const int rc2 = min(kRch, r - rho0);
+      __syncthreads();
+      {
+        const S* Uf = farf + (size_t)f * fstride;
+        const S* us = Uf + (size_t)rho0 * n * 2;
+        const S* vs = Uf + (size_t)max_rank * n * 2 + (size_t)rho0 * n * 2;
+        for (int e2 = 2 * tid; e2 < rc2 * n; e2 += 2 * blockDim.x) {
+          Cx<S> a0, b0, a1, b1;
+          load2<S>(us, e2, a0, b0);
+          load2<S>(vs, e2, a1, b1);
+          lds_u[e2] = a0;
+          lds_u[e2 + 1] = b0;
+          lds_v[e2] = a1;
+          lds_v[e2 + 1] = b1;
+        }
+      }
+      __syncthreads();
+      if (wave_active) {
+        switch (rc2) {
+          case 1: far_slice<S, QS, 1>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 2: far_slice<S, QS, 2>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 3: far_slice<S, QS, 3>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 4: far_slice<S, QS, 4>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 5: far_slice<S, QS, 5>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 6: far_slice<S, QS, 6>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 7: far_slice<S, QS, 7>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          default: far_slice<S, QS, 8>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        }
+      }
+    }
+    __syncthreads();
+    e = en;
+    f = fnext;
+    r = rnext;
+#pragma unroll
+    for (int k = 0; k < QS; ++k) xc[k] = xn[k];
+  }
+  if (!vi) return;
+  const size_t yb = (size_t)(R.unit_off + (int64_t)iy * R.Lx + ix) * n_a;
+  S* o = out + ((size_t)g * total_units * n_a + yb) * 2;
+#pragma unroll
+  for (int k = 0; k < QS; ++k) {
+    o[2 * (m0 + k)] = acc_re[k];
+    o[2 * (m0 + k) + 1] = acc_im[k];
+  }
+}
+
 template <typename S, typename XT>
-__global__ void __launch_bounds__(1024)
-reduce_chunks_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles,
-                     const S* __restrict__ partial, int n_chunks, int64_t total_units, int n_a,
-                     XT* __restrict__ y) {
-  const TileDev tile = tiles[blockIdx.x];
-  const RhsDev R = rhs[tile.b];
-  const int ul = threadIdx.x / n_a, m = threadIdx.x % n_a;
-  if (ul >= kTU) return;
-  const int ix = tile.tx + ul % kTW, iy = tile.ty + ul / kTW;
-  if (ix >= R.Lx || iy >= R.Ly) return;
-  const size_t e = (size_t)(R.unit_off + (int64_t)iy * R.Lx + ix) * n_a + m;
+__global__ void __launch_bounds__(256)
+reduce_groups_kernel(const RhsDev* __restrict__ rhs, const S* __restrict__ partial, int slots,
+                     int64_t total_units, int n_a, XT* __restrict__ y) {
+  const RhsDev R = rhs[blockIdx.y];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)R.Lx * R.Ly * n_a) return;
+  const size_t e = (size_t)R.unit_off * n_a + k;
   const size_t stride = (size_t)total_units * n_a;
   S re = 0, im = 0;
-  for (int c = 0; c < n_chunks; ++c) {
-    re += partial[((size_t)c * stride + e) * 2];
-    im += partial[((size_t)c * stride + e) * 2 + 1];
+  for (int c = 0; c < slots; ++c) {
+    const size_t p = ((size_t)c * stride + e) * 2;
+    re += partial[p];
+    im += partial[p + 1];
   }
   y[2 * e] = (XT)re;
   y[2 * e + 1] = (XT)im;
 }
 
+template <typename S, typename XT>
+__global__ void __launch_bounds__(256)
+convert_flat_kernel(const RhsDev* __restrict__ rhs, int n_a, const XT* __restrict__ x, S* __restrict__ xs) {
+  const RhsDev R = rhs[blockIdx.y];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (int64_t)R.Lx * R.Ly * n_a) return;
+  const size_t e = (size_t)R.unit_off * n_a + k;
+  xs[2 * e] = (S)x[2 * e];
+  xs[2 * e + 1] = (S)x[2 * e + 1];
+}
+
 }  // namespace
 
-// chunks per tile: enough workgroups to fill the chip several times
+// displacement groups per 8x8 block: about 1024 workgroups for one launch
 int choose_chunks(const BatchDesc& bd, int max_chunks) {
-  int want = (int)std::max<int64_t>(1, (2048 + bd.n_tiles - 1) / std::max(1, bd.n_tiles));
+  int want = (int)std::max<int64_t>(1, (1024 + bd.n_tiles - 1) / std::max(1, bd.n_tiles));
   return std::max(1, std::min(want, max_chunks));
 }
 
-size_t matvec_partial_bytes(const BatchDesc& bd, int n_a, int chunks, r3m_dtype store_dtype) {
-  if (chunks <= 1) return 0;
-  const size_t es = store_dtype == R3M_C128 ? 16 : 8;
-  return (size_t)chunks * bd.total_units * n_a * es;
+// near displacements per workgroup stay few: one each for a compressed store,
+// up to 128 groups when every block is dense
+static int near_groups(const r3m_store* Z) {
+  const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
+  return std::min((2 * Nx + 1) * (2 * Ny + 1), 128);
+}
+
+static bool store_has_far(const r3m_store* Z) { return Z->near_radius < std::max(Z->Dx, Z->Dy); }
+
+// workspace: partial sums [far groups + near groups][units][n_a] in the store
+// precision, plus a copy of x in the store precision when the vectors are wider
+size_t matvec_partial_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks) {
+  const size_t es = Z->near_dtype == R3M_C128 ? 16 : 8;
+  const int n_a = Z->n / Z->n_states;
+  const size_t vec = (size_t)bd.total_units * n_a * es;
+  const int slots = (store_has_far(Z) ? std::max(chunks, 1) : 0) + near_groups(Z);
+  return (size_t)slots * vec + (Z->near_dtype == R3M_C128 ? 0 : vec) + 256;
 }
 
 void validate_store(const r3m_store* Z) {
   R3M_REQUIRE(Z, R3M_ERR_INVALID_ARG, "store is NULL");
   R3M_REQUIRE(Z->n > 0 && Z->n_states >= 1 && Z->n % Z->n_states == 0, R3M_ERR_INVALID_ARG,
               "store n must be a multiple of n_states");
-  R3M_REQUIRE(Z->n / Z->n_states <= 64, R3M_ERR_UNSUPPORTED, "at most 64 active RWG per unit");
+  const int n_a = Z->n / Z->n_states;
+  R3M_REQUIRE(n_a == 40 || n_a == 64, R3M_ERR_UNSUPPORTED,
+              "the matvec kernels are instantiated for 40 or 64 active RWG per unit");
+  R3M_REQUIRE(Z->n <= 256, R3M_ERR_UNSUPPORTED, "at most 256 macro RWG per unit");
   R3M_REQUIRE(Z->Dx >= 0 && Z->Dy >= 0 && Z->near_radius >= 0, R3M_ERR_INVALID_ARG, "bad extents");
   R3M_REQUIRE(Z->near, R3M_ERR_INVALID_ARG, "near blocks are NULL");
   R3M_REQUIRE(Z->near_dtype == R3M_C128 || Z->near_dtype == R3M_C64, R3M_ERR_UNSUPPORTED,
               "near dtype must be C128 or C64");
-  const bool has_far = Z->near_radius < std::max(Z->Dx, Z->Dy);
-  if (has_far) {
+  if (store_has_far(Z)) {
     R3M_REQUIRE(Z->far, R3M_ERR_INVALID_ARG, "far factors are NULL");
     R3M_REQUIRE(Z->far_dtype == Z->near_dtype, R3M_ERR_UNSUPPORTED,
                 "far and near dtypes must match for this matvec");
@@ -187,48 +451,55 @@ void validate_store(const r3m_store* Z) {
   }
 }
 
+template <typename S, typename XT>
+static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
+                         void* partial, int chunks, hipStream_t stream) {
+  const int n_a = Z->n / Z->n_states;
+  const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
+  const bool far = store_has_far(Z);
+  const int n_far = far ? r3m_far_count(Z->Dx, Z->Dy, Z->near_radius) : 0;
+  const size_t head = ((size_t)n_far * 4 + 255) / 256 * 256;
+  const int groups = far ? std::max(chunks, 1) : 0;
+  const int hg = near_groups(Z);
+  const int64_t tu = (int64_t)bd.total_units;
+  const size_t vec = (size_t)tu * n_a * 2 * sizeof(S);
+  char* part = (char*)partial;
+  const S* xs = (const S*)x;
+  if (!std::is_same<S, XT>::value) {
+    S* xc = (S*)(part + (size_t)(groups + hg) * vec);
+    hipLaunchKernelGGL((convert_flat_kernel<S, XT>), dim3(ceil_div((size_t)bd.max_units * n_a, 256), bd.B),
+                       dim3(256), 0, stream, bd.rhs, n_a, (const XT*)x, xc);
+    xs = xc;
+  }
+  if (far) {
+    const int lds_state_cap = 16384;
+    const size_t lds = 2 * (size_t)kRch * Z->n * 2 * sizeof(S) + lds_state_cap;
+    auto kern = n_a == 40 ? far_kernel<S, 10> : far_kernel<S, 16>;
+    hipLaunchKernelGGL(kern, dim3(bd.n_tiles, groups), dim3(256), lds, stream, bd.rhs, bd.tiles, groups, states,
+                       (const S*)((const char*)Z->far + head), (const int*)Z->far, Z->max_rank, Z->Dx, Z->Dy,
+                       Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap);
+    R3M_CHECK_HIP(hipGetLastError());
+  }
+  auto nk = n_a == 40 ? near_kernel<S, 10> : near_kernel<S, 16>;
+  hipLaunchKernelGGL(nk, dim3(bd.n_tiles, hg), dim3(256), 0, stream, bd.rhs, bd.tiles, states, (const S*)Z->near, Nx,
+                     Ny, Z->n, n_a, Z->n_states, xs, (S*)part, tu, groups, hg);
+  R3M_CHECK_HIP(hipGetLastError());
+  hipLaunchKernelGGL((reduce_groups_kernel<S, XT>), dim3(ceil_div((size_t)bd.max_units * n_a, 256), bd.B),
+                     dim3(256), 0, stream, bd.rhs, (const S*)part, groups + hg, tu, n_a, (XT*)y);
+  R3M_CHECK_HIP(hipGetLastError());
+}
+
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
                    r3m_dtype vec_dtype, const void* x, void* y, void* partial, int chunks,
                    hipStream_t stream) {
-  const int n_a = Z->n / Z->n_states;
-  const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
-  const int n_far = r3m_far_count(Z->Dx, Z->Dy, Z->near_radius);
-  const size_t head = ((size_t)n_far * 4 + 255) / 256 * 256;
-  const int* ranks = n_far > 0 && Z->far ? (const int*)Z->far : nullptr;
-  const void* farf = n_far > 0 && Z->far ? (const char*)Z->far + head : nullptr;
-  const int threads = ((kTU * n_a + 63) / 64) * 64;
-  dim3 grid(bd.n_tiles, chunks);
-  const int mr = std::max(1, Z->max_rank);
-  const size_t es = Z->near_dtype == R3M_C128 ? 16 : 8;
-  const size_t lds = (size_t)kTU * mr * es;
-  void* part = chunks > 1 ? partial : nullptr;
-#define R3M_LAUNCH_MV(S, XT)                                                                      \
-  hipLaunchKernelGGL((matvec_tile_kernel<S, XT>), grid, dim3(threads), lds, stream, bd.rhs, bd.tiles, \
-                     chunks, states, (const S*)Z->near, Nx, Ny, (const S*)farf, ranks, mr, Z->Dx,  \
-                     Z->Dy, Z->near_radius, Z->n, n_a, Z->n_states, (const XT*)x, (XT*)y, (S*)part, \
-                     (int64_t)bd.total_units)
+  (void)ctx;
   if (Z->near_dtype == R3M_C128) {
     R3M_REQUIRE(vec_dtype == R3M_C128, R3M_ERR_UNSUPPORTED, "a C128 store needs C128 vectors");
-    R3M_LAUNCH_MV(double, double);
+    launch_typed<double, double>(Z, bd, states, x, y, partial, chunks, stream);
   } else if (vec_dtype == R3M_C64) {
-    R3M_LAUNCH_MV(float, float);
+    launch_typed<float, float>(Z, bd, states, x, y, partial, chunks, stream);
   } else {
-    R3M_LAUNCH_MV(float, double);
-  }
-#undef R3M_LAUNCH_MV
-  R3M_CHECK_HIP(hipGetLastError());
-  if (chunks > 1) {
-    const int64_t tu = (int64_t)bd.total_units;
-    if (Z->near_dtype == R3M_C128)
-      hipLaunchKernelGGL((reduce_chunks_kernel<double, double>), dim3(bd.n_tiles), dim3(threads), 0,
-                         stream, bd.rhs, bd.tiles, (const double*)partial, chunks, tu, n_a, (double*)y);
-    else if (vec_dtype == R3M_C64)
-      hipLaunchKernelGGL((reduce_chunks_kernel<float, float>), dim3(bd.n_tiles), dim3(threads), 0,
-                         stream, bd.rhs, bd.tiles, (const float*)partial, chunks, tu, n_a, (float*)y);
-    else
-      hipLaunchKernelGGL((reduce_chunks_kernel<float, double>), dim3(bd.n_tiles), dim3(threads), 0,
-                         stream, bd.rhs, bd.tiles, (const float*)partial, chunks, tu, n_a, (double*)y);
-    R3M_CHECK_HIP(hipGetLastError());
+    launch_typed<float, double>(Z, bd, states, x, y, partial, chunks, stream);
   }
 }
 
@@ -246,9 +517,9 @@ size_t r3m_matvec_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* b
     validate_store(Z);
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;
-    const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, 0);
+    const BatchDesc& bd = get_batch(ctx, batch, kBW, kBH, 0);
     const int chunks = choose_chunks(bd, 64);
-    out = matvec_partial_bytes(bd, Z->n / Z->n_states, chunks, Z->near_dtype);
+    out = matvec_partial_bytes(bd, Z, chunks);
   });
   return rc == R3M_OK ? out : 0;
 }
@@ -265,11 +536,11 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
     if (batch->B == 0) return;
     R3M_REQUIRE(x_dev && y_dev, R3M_ERR_INVALID_ARG, "x or y is NULL");
     R3M_CHECK_HIP(hipSetDevice(ctx->device));
-    const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, stream);
+    const BatchDesc& bd = get_batch(ctx, batch, kBW, kBH, stream);
     const int chunks = choose_chunks(bd, 64);
-    const size_t need = matvec_partial_bytes(bd, Z->n / Z->n_states, chunks, Z->near_dtype);
+    const size_t need = matvec_partial_bytes(bd, Z, chunks);
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "matvec workspace too small");
-    R3M_REQUIRE(need == 0 || work_dev, R3M_ERR_INVALID_ARG, "work is NULL");
+    R3M_REQUIRE(work_dev, R3M_ERR_INVALID_ARG, "work is NULL");
     launch_matvec(ctx, Z, bd, batch->states, vec_dtype, x_dev, y_dev, work_dev, chunks, stream);
   });
 }

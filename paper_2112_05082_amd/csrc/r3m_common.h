@@ -68,6 +68,7 @@ struct BatchDesc {
   int64_t total_units = 0;
   int32_t n_tiles = 0;
   int32_t max_L = 0;
+  int64_t max_units = 0;  // largest Lx * Ly of the batch
   DevBuf dev;  // rhs table [B] then tile table [n_tiles]
   const struct RhsDev* rhs = nullptr;
   const struct TileDev* tiles = nullptr;
