@@ -186,12 +186,22 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
 
 /* ---------------------------------------------------------------- GMRES -- */
 
+typedef enum {
+  R3M_PRECOND_NONE = 0,
+  /* right block-Jacobi preconditioner retrieved from the near field: the
+   * inverse of each unit's self block Z(0)[A(s_u), A(s_u)] (one inverse per
+   * coding state, FP64).  It is the diagonal-block special case of the
+   * near-field block-ILU preconditioner built after retrieval (Sec. III-D). */
+  R3M_PRECOND_BLOCK_JACOBI = 1
+} r3m_precond;
+
 typedef struct {
   double tol;         /* relative residual target of the (inner) solve */
   int32_t restart;    /* Krylov dimension m */
   int32_t max_iter;   /* total inner iterations per solve */
   double refine_tol;  /* > 0: FP64 refinement with Z64 until ||b - Z64 x||/||b|| <= refine_tol */
   int32_t max_refine; /* outer refinement steps */
+  int32_t precond;    /* r3m_precond */
 } r3m_gmres_opts;
 
 typedef struct {

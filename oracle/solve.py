@@ -41,8 +41,30 @@ class GmresResult:
     basis_orth_err: float = 0.0
 
 
+def block_jacobi(Zk: np.ndarray, block: int):
+    """Right preconditioner M^{-1} from the inverses of the diagonal unit blocks
+    of the retrieved matrix (the diagonal-block case of the near-field
+    preconditioner built after retrieval, Sec. III-D)."""
+    nb = Zk.shape[0] // block
+    inv = [np.linalg.inv(Zk[i * block:(i + 1) * block, i * block:(i + 1) * block]) for i in range(nb)]
+
+    def apply(v):
+        v = np.asarray(v).reshape(nb, block)
+        return np.concatenate([inv[i] @ v[i] for i in range(nb)])
+    return apply
+
+
 def gmres(matvec, b: np.ndarray, tol: float = 1e-8, restart: int = 100,
-          max_iter: int = 1000) -> GmresResult:
+          max_iter: int = 1000, precond=None) -> GmresResult:
+    """Right-preconditioned when precond (x -> M^{-1} x) is given: the Krylov
+    space is built for A M^{-1} and the iterate is x = M^{-1} u."""
+    if precond is not None:
+        res = gmres(lambda v: matvec(precond(v)), b, tol, restart, max_iter, None)
+        # the unpreconditioned solution and its true residual
+        res.x = precond_solution(res, precond)
+        r = b - matvec(res.x)
+        res.rel_residual = float(np.linalg.norm(r) / np.linalg.norm(b))
+        return res
     b = np.asarray(b, dtype=np.complex128)
     n = len(b)
     bnorm = np.linalg.norm(b)
@@ -91,3 +113,7 @@ def gmres(matvec, b: np.ndarray, tol: float = 1e-8, restart: int = 100,
         orth = max(orth, np.abs(Vm.conj().T @ Vm - np.eye(j_end + 1)).max())
         y = np.linalg.solve(np.triu(H[:j_end, :j_end]), g[:j_end])
         x = x + V[:, :j_end] @ y
+
+
+def precond_solution(res: GmresResult, precond) -> np.ndarray:
+    return precond(res.x)

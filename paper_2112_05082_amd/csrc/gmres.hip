@@ -316,6 +316,120 @@ __global__ void nonfinite_kernel(const double2* __restrict__ v, const RhsVec* __
   if (!(isfinite(t.x) && isfinite(t.y))) atomicOr(flag, 4);
 }
 
+// Inverse of the self block Z(0)[A(s), A(s)] of each state s by Gauss-Jordan
+// elimination with partial pivoting in FP64 (one workgroup per state).
+template <typename S>
+__global__ void __launch_bounds__(256)
+selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a, double2* __restrict__ Minv,
+                         int* __restrict__ flag) {
+  extern __shared__ double2 aug[];  // [n_a][2 n_a], then column k [n_a]
+  __shared__ int piv_row;
+  double2* colk = aug + 2 * n_a * n_a;
+  const int st = blockIdx.x;
+  const int w = 2 * n_a;
+  const S* Z0 = nearb + (size_t)slot0 * n * n * 2;
+  for (int e = threadIdx.x; e < n_a * w; e += blockDim.x) {
+    const int i = e / w, j = e % w;
+    double2 v;
+    if (j < n_a) {
+      const size_t idx = (size_t)(st * n_a + i) * n + st * n_a + j;
+      v = make_double2((double)Z0[2 * idx], (double)Z0[2 * idx + 1]);
+    } else {
+      v = make_double2(j - n_a == i ? 1.0 : 0.0, 0.0);
+    }
+    aug[e] = v;
+  }
+  __syncthreads();
+  for (int k = 0; k < n_a; ++k) {
+    if (threadIdx.x == 0) {
+      int p = k;
+      double best = -1.0;
+      for (int i = k; i < n_a; ++i) {
+        const double2 a = aug[i * w + k];
+        const double m = a.x * a.x + a.y * a.y;
+        if (m > best) {
+          best = m;
+          p = i;
+        }
+      }
+      piv_row = best > 0.0 ? p : -1;
+      if (best <= 0.0) atomicOr(flag, 8);
+    }
+    __syncthreads();
+    const int p = piv_row;
+    if (p < 0) return;
+    if (p != k)
+      for (int j = threadIdx.x; j < w; j += blockDim.x) {
+        const double2 t = aug[k * w + j];
+        aug[k * w + j] = aug[p * w + j];
+        aug[p * w + j] = t;
+      }
+    __syncthreads();
+    const double2 d = aug[k * w + k];
+    const double dd = d.x * d.x + d.y * d.y;
+    const double2 inv = make_double2(d.x / dd, -d.y / dd);
+    __syncthreads();
+    for (int j = threadIdx.x; j < w; j += blockDim.x) aug[k * w + j] = cmul(aug[k * w + j], inv);
+    // multipliers of column k, read before any row update touches that column
+    for (int i = threadIdx.x; i < n_a; i += blockDim.x) colk[i] = aug[i * w + k];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n_a * w; e += blockDim.x) {
+      const int i = e / w, j = e % w;
+      if (i == k) continue;
+      const double2 t = cmul(colk[i], aug[k * w + j]);
+      aug[e] = make_double2(aug[e].x - t.x, aug[e].y - t.y);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n_a * n_a; e += blockDim.x) {
+    const int i = e / n_a, j = e % n_a;
+    Minv[(size_t)st * n_a * n_a + e] = aug[i * w + n_a + j];
+  }
+}
+
+// out_u = Minv[s_u] in_u for every unit (user layout)
+__global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
+                                     const int64_t* __restrict__ soff, const RhsVec* __restrict__ rv, int n_a,
+                                     int n_states, const double2* __restrict__ in, double2* __restrict__ out) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= r.N) return;
+  const int64_t u = k / n_a;
+  const int m = (int)(k % n_a);
+  const int s = min((int)states[soff[b] + u], n_states - 1);
+  const double2* M = Minv + ((size_t)s * n_a + m) * n_a;
+  const double2* v = in + r.off + u * n_a;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int c = 0; c < n_a; ++c) {
+    const double2 t = cmul(M[c], v[c]);
+    acc.x += t.x;
+    acc.y += t.y;
+  }
+  out[r.off + k] = acc;
+}
+
+// z = V y (first jdone columns)
+__global__ void combine_basis_kernel(const double2* __restrict__ V, const double2* __restrict__ g,
+                                     double2* __restrict__ z, const RhsVec* __restrict__ rv,
+                                     const RhsState* __restrict__ st, int m, int64_t ut) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const RhsState s = st[b];
+  if (k >= r.N) return;
+  double2 acc = make_double2(0.0, 0.0);
+  if (s.active) {
+    const double2* y = g + (size_t)b * (m + 1);
+    for (int i = 0; i < s.jdone; ++i) {
+      double2 t = cmul(y[i], V[(int64_t)i * ut + r.off + k]);
+      acc.x += t.x;
+      acc.y += t.y;
+    }
+  }
+  z[r.off + k] = acc;
+}
+
 __global__ void finalize_kernel(RhsState* __restrict__ st, int B, int J) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
@@ -328,6 +442,8 @@ struct Work {
   double2* r;
   double2* d;
   double2* ro;
+  double2* pz;
+  double2* Minv;
   void* mv_partial;
   double2* H;
   double2* g;
@@ -345,7 +461,7 @@ struct Work {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-Work layout_work(char* base, const BatchDesc& bd, int n_a, int m, size_t mv_bytes) {
+Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, size_t mv_bytes) {
   Work w{};
   const int B = bd.B;
   int64_t maxN = 0;
@@ -364,6 +480,8 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int m, size_t mv_byte
   w.r = (double2*)take(ut * 16);
   w.d = (double2*)take(ut * 16);
   w.ro = (double2*)take(ut * 16);
+  w.pz = (double2*)take(ut * 16);
+  w.Minv = (double2*)take((size_t)n_states * n_a * n_a * 16);
   w.mv_partial = take(mv_bytes);
   w.H = (double2*)take((size_t)B * (m + 1) * m * 16);
   w.g = (double2*)take((size_t)B * (m + 1) * 16);
@@ -388,6 +506,8 @@ struct GmresRun {
   const BatchDesc* bd;
   const r3m_batch* batch;
   int n_a, m, maxP, B;
+  int n_states = 1;
+  bool pre = false;
   int64_t maxN, ut;
   Work W;
   hipStream_t s;
@@ -428,8 +548,18 @@ struct GmresRun {
     hipLaunchKernelGGL(sub_kernel, vgrid(), dim3(256), 0, s, rhs, W.w, out, W.rv);
   }
 
+  void precond(const double2* in, double2* out) {
+    hipLaunchKernelGGL(apply_precond_kernel, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff, W.rv, n_a,
+                       n_states, in, out);
+  }
+
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
-    matvec(Z, W.V + (int64_t)j * ut, W.w);
+    if (pre) {
+      precond(W.V + (int64_t)j * ut, W.pz);
+      matvec(Z, W.pz, W.w);
+    } else {
+      matvec(Z, W.V + (int64_t)j * ut, W.w);
+    }
     for (int pass = 0; pass < 2; ++pass) {
       dots(W.V, ut, W.w, j + 1);
       hipLaunchKernelGGL(gs_update_kernel, vgrid(), dim3(256), 0, s, W.V, W.w, W.rv, W.st, W.hbuf, j + 1, ut);
@@ -486,7 +616,14 @@ struct GmresRun {
       }
       hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.st, B, j);
       hipLaunchKernelGGL(backsolve_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.H, W.g, W.st, B, m);
-      hipLaunchKernelGGL(update_x_kernel, vgrid(), dim3(256), 0, s, W.V, W.g, sol, W.rv, W.st, m, ut);
+      if (pre) {
+        // x += M^{-1} (V y)
+        hipLaunchKernelGGL(combine_basis_kernel, vgrid(), dim3(256), 0, s, W.V, W.g, W.pz, W.rv, W.st, m, ut);
+        precond(W.pz, W.w);
+        hipLaunchKernelGGL(add_kernel, vgrid(), dim3(256), 0, s, sol, W.w, W.rv);
+      } else {
+        hipLaunchKernelGGL(update_x_kernel, vgrid(), dim3(256), 0, s, W.V, W.g, sol, W.rv, W.st, m, ut);
+      }
       R3M_CHECK_HIP(hipMemcpyAsync(hst.data(), W.st, (size_t)B * sizeof(RhsState), hipMemcpyDeviceToHost, s));
       R3M_CHECK_HIP(hipStreamSynchronize(s));
       for (int b = 0; b < B; ++b)
@@ -509,7 +646,7 @@ size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const 
   const int chunks = choose_chunks(bd, 64);
   size_t mv = matvec_partial_bytes(bd, Z, chunks);
   if (Z64) mv = std::max(mv, matvec_partial_bytes(bd, Z64, chunks));
-  return layout_work(nullptr, bd, n_a, m, mv).bytes;
+  return layout_work(nullptr, bd, n_a, Z->n_states, m, mv).bytes;
 }
 
 }  // namespace r3m
@@ -533,7 +670,7 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* ba
     const int n_a = Z->n / Z->n_states;
     const size_t vec = (size_t)bd.total_units * n_a * 16;
     const size_t mv = (size_t)(choose_chunks(bd, 64) + 128) * vec + vec + 256;
-    out = layout_work(nullptr, bd, n_a, opts->restart, mv).bytes;
+    out = layout_work(nullptr, bd, n_a, Z->n_states, opts->restart, mv).bytes;
   });
   return rc == R3M_OK ? out : 0;
 }
@@ -576,7 +713,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     run.m = m;
     run.B = bd.B;
     run.s = stream;
-    run.W = layout_work((char*)work_dev, bd, n_a, m, mv);
+    run.W = layout_work((char*)work_dev, bd, n_a, Z->n_states, m, mv);
     run.ut = (int64_t)bd.total_units * n_a;
     run.maxN = 0;
     std::vector<RhsVec> rv(bd.B);
@@ -601,6 +738,23 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     R3M_REQUIRE(!(f & 2), R3M_ERR_INVALID_ARG, "codebook state out of range");
     R3M_REQUIRE(!(f & 4), R3M_ERR_NONFINITE, "non-finite right-hand side");
 
+    R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE || opts->precond == R3M_PRECOND_BLOCK_JACOBI,
+                R3M_ERR_INVALID_ARG, "unknown preconditioner");
+    run.n_states = Z->n_states;
+    if (opts->precond == R3M_PRECOND_BLOCK_JACOBI) {
+      run.pre = true;
+      const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
+      const int slot0 = Ny * (2 * Nx + 1) + Nx;
+      const size_t lds = ((size_t)n_a * 2 * n_a + n_a) * sizeof(double2);
+      if (Z->near_dtype == R3M_C128)
+        hipLaunchKernelGGL(selfblock_inverse_kernel<double>, dim3(Z->n_states), dim3(256), lds, stream,
+                           (const double*)Z->near, slot0, Z->n, n_a, run.W.Minv, run.W.counters + 1);
+      else
+        hipLaunchKernelGGL(selfblock_inverse_kernel<float>, dim3(Z->n_states), dim3(256), lds, stream,
+                           (const float*)Z->near, slot0, Z->n, n_a, run.W.Minv, run.W.counters + 1);
+      R3M_CHECK_HIP(hipGetLastError());
+      R3M_REQUIRE(!run.flag_check(8), R3M_ERR_NONFINITE, "singular self block in the preconditioner");
+    }
     const double2* b = (const double2*)b_dev;
     double2* x = (double2*)x_dev;
     std::vector<double> bnorm = run.host_norms(b);
