@@ -202,7 +202,11 @@ typedef struct {
   double refine_tol;  /* > 0: FP64 refinement with Z64 until ||b - Z64 x||/||b|| <= refine_tol */
   int32_t max_refine; /* outer refinement steps */
   int32_t precond;    /* r3m_precond */
+  int32_t flags;      /* bit 0 (R3M_GMRES_EAGER): launch every Arnoldi step eagerly instead of
+                         replaying captured HIP graphs of blocks of steps */
 } r3m_gmres_opts;
+
+#define R3M_GMRES_EAGER 1
 
 typedef struct {
   int32_t iters;       /* inner iterations (summed over refinement steps) */
@@ -217,7 +221,9 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* ba
 /* Solves the retrieved systems Z_k x_b = b_b (C128 vectors) with restarted
  * GMRES(m): zero initial guess, Gram-Schmidt Arnoldi (classical, repeated
  * once) in FP64, complex Givens rotations in FP64, convergence flags on the
- * device.  The matvec runs in the precision of Z.  If Z64 (a C128 store of the
+ * device.  Blocks of Arnoldi steps run as HIP graphs captured once per
+ * (store, batch, workspace, m) and replayed on a context-owned stream that is
+ * ordered after `stream`; the call returns with `stream` ordered after it.  The matvec runs in the precision of Z.  If Z64 (a C128 store of the
  * same matrix) is given and opts->refine_tol > 0, an outer FP64 iterative
  * refinement computes r = b - Z64 x and solves Z d = r with the inner GMRES.
  * rep_host[B] is written; returns R3M_ERR_NOT_CONVERGED if any RHS missed the

@@ -229,6 +229,10 @@ int r3m_ctx_destroy(r3m_ctx ctx) {
   if (!ctx) return R3M_OK;
   (void)hipSetDevice(ctx->device);
   (void)hipDeviceSynchronize();
+  for (auto& kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (ctx->work_stream) (void)hipStreamDestroy(ctx->work_stream);
+  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
   ctx->flag.release();
   ctx->geom.release();
   for (auto& kv : ctx->batches) {

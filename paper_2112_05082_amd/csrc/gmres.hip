@@ -20,11 +20,13 @@ size_t matvec_partial_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks)
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
                    r3m_dtype vec_dtype, const void* x, void* y, void* partial, int chunks,
                    hipStream_t stream);
+void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
+                       void* partial, int chunks, hipStream_t stream);
 
 namespace {
 
 constexpr int kTW = 8, kTH = 8;  // unit block of the matvec workgroups
-constexpr int kDotChunk = 8192;
+constexpr int kDotChunk = 2048;
 constexpr int kDotThreads = 256;
 constexpr int kCheckEvery = 4;
 
@@ -133,28 +135,25 @@ __global__ void accumulate_h_kernel(double2* __restrict__ H, const double2* __re
   }
 }
 
-// H[j+1][j] = ||w||, V_{j+1} = w / ||w|| (zeros for finished RHS or breakdown)
+// V_{j+1} = w / ||w|| with ||w|| = H[j+1][j] as set before the rotation
+// (zeros for finished RHS or breakdown); the norm is kept in wn[b]
 __global__ void normalize_kernel(const double2* __restrict__ w, double2* __restrict__ V,
                                  const RhsVec* __restrict__ rv, const RhsState* __restrict__ st,
-                                 const double2* __restrict__ nrm2, double2* __restrict__ H, int m,
-                                 int j, int64_t ut) {
+                                 const double* __restrict__ wn, int m, int j, int64_t ut) {
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const double nv = sqrt(fmax(nrm2[b].x, 0.0));
-  if (k == 0) H[(size_t)b * (m + 1) * m + (j + 1) * m + j] = make_double2(nv, 0.0);
   if (k >= r.N) return;
+  const double nv = wn[b];
   const bool ok = st[b].active && st[b].jdone < 0 && nv > 0.0;
   double2 v = w[r.off + k];
   V[(int64_t)(j + 1) * ut + r.off + k] = ok ? make_double2(v.x / nv, v.y / nv) : make_double2(0.0, 0.0);
 }
 
-// Givens update of column j of H for each RHS; convergence check
-__global__ void givens_kernel(double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
-                              double2* __restrict__ sn, RhsState* __restrict__ st, int B, int m, int j,
-                              double tol, int* __restrict__ n_running) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
+// Givens update of column j of H for RHS b; convergence check
+__device__ void givens_update(int b, double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
+                              double2* __restrict__ sn, RhsState* __restrict__ st, int m, int j, double tol,
+                              int* __restrict__ n_running) {
   RhsState s = st[b];
   if (!s.active || s.jdone >= 0) return;
   double2* h = H + (size_t)b * (m + 1) * m;
@@ -207,6 +206,162 @@ __global__ void givens_kernel(double2* __restrict__ H, double2* __restrict__ g, 
     atomicAdd(n_running, 1);
   }
   st[b] = s;
+}
+
+__global__ void givens_kernel(double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
+                              double2* __restrict__ sn, RhsState* __restrict__ st, int B, int m, int j,
+                              double tol, int* __restrict__ n_running) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  givens_update(b, H, g, cs, sn, st, m, j, tol, n_running);
+}
+
+// Sum of n partials by the 64 lanes of one wave: lane t adds entries t, t+64,
+// ... in order, then a fixed butterfly; every lane returns the total.
+__device__ double wave_sum_partials(const volatile double* p, int n) {
+  double acc = 0.0;
+  for (int q = (int)(threadIdx.x & 63); q < n; q += 64) acc += p[q];
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o);
+  return acc;
+}
+__device__ double2 wave_sum_partials2(const volatile double2* p, int n) {
+  double2 acc = make_double2(0.0, 0.0);
+  for (int q = (int)(threadIdx.x & 63); q < n; q += 64) {
+    acc.x += p[q].x;
+    acc.y += p[q].y;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    acc.x += __shfl_xor(acc.x, o);
+    acc.y += __shfl_xor(acc.y, o);
+  }
+  return acc;
+}
+
+// Block sum of a double2 over the 256 threads (fixed order).
+__device__ double2 block_sum2(double2 v, double2* sh) {
+  for (int o = 32; o >= 1; o >>= 1) {
+    v.x += __shfl_xor(v.x, o);
+    v.y += __shfl_xor(v.y, o);
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double2 t = sh[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+    t.x += sh[w].x;
+    t.y += sh[w].y;
+  }
+  __syncthreads();
+  return t;
+}
+
+// <A_i, B> for i < nvec with the final sum done by the last block of each
+// (RHS, i) in fixed chunk order.  mode 0: H[i][j] = s, 1: H[i][j] += s;
+// always hbuf[b][i] = s.
+__global__ void __launch_bounds__(kDotThreads)
+dots_fused_kernel(const double2* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
+                  const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
+                  int* __restrict__ counters, double2* __restrict__ H, int m, int j, int mode,
+                  double2* __restrict__ hbuf, int* __restrict__ n_running) {
+  __shared__ double2 sh[kDotThreads / 64];
+  __shared__ int last;
+  const int p = blockIdx.x, i = blockIdx.y, b = blockIdx.z;
+  if (n_running && p == 0 && i == 0 && b == 0 && threadIdx.x == 0) *n_running = 0;
+  const RhsVec r = rv[b];
+  const int64_t P = (r.N + kDotChunk - 1) / kDotChunk;
+  if (p >= P) return;
+  const double2* a = A + (int64_t)i * a_stride + r.off;
+  const double2* bb = Bv + r.off;
+  const int64_t lo = (int64_t)p * kDotChunk, hi = min(r.N, lo + kDotChunk);
+  double2 acc = make_double2(0.0, 0.0);
+  for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+    const double2 t = cmulc(a[k], bb[k]);
+    acc.x += t.x;
+    acc.y += t.y;
+  }
+  const double2 t = block_sum2(acc, sh);
+  const size_t pi = ((size_t)b * nvec + i) * maxP;
+  if (threadIdx.x == 0) {
+    partial[pi + p] = t;
+    __threadfence();
+    last = atomicAdd(&counters[b * nvec + i], 1) == (int)P - 1;
+  }
+  __syncthreads();
+  if (!last || threadIdx.x >= 64) return;
+  __threadfence();
+  const double2 sum = wave_sum_partials2(partial + pi, (int)P);
+  if (threadIdx.x != 0) return;
+  counters[b * nvec + i] = 0;
+  hbuf[(size_t)b * nvec + i] = sum;
+  double2* h = H + (size_t)b * (m + 1) * m + (size_t)i * m + j;
+  if (mode == 0) {
+    *h = sum;
+  } else {
+    h->x += sum.x;
+    h->y += sum.y;
+  }
+}
+
+// w -= sum_{i<nvec} hbuf[i] V_i.  With do_norm, also ||w||^2 per block; the
+// last block of each RHS sets H[j+1][j] = ||w|| and applies the Givens step.
+__global__ void __launch_bounds__(256)
+gs_update_fused_kernel(const double2* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
+                       RhsState* __restrict__ st, const double2* __restrict__ hbuf, int nvec, int64_t ut,
+                       int do_norm, double* __restrict__ npart, int* __restrict__ counters, int maxB,
+                       double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
+                       double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
+                       double* __restrict__ wn) {
+  __shared__ double2 sh[4];
+  __shared__ int last;
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t nb = (r.N + blockDim.x - 1) / blockDim.x;
+  if ((int64_t)blockIdx.x >= nb) return;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double nrm2 = 0.0;
+  if (k < r.N && st[b].active) {
+    double2 acc = w[r.off + k];
+    const double2* hb = hbuf + (size_t)b * nvec;
+    const double2* vk = V + r.off + k;
+    int i = 0;
+    for (; i + 4 <= nvec; i += 4) {
+      const double2 v0 = vk[(int64_t)i * ut], v1 = vk[(int64_t)(i + 1) * ut];
+      const double2 v2 = vk[(int64_t)(i + 2) * ut], v3 = vk[(int64_t)(i + 3) * ut];
+      const double2 t0 = cmul(hb[i], v0), t1 = cmul(hb[i + 1], v1);
+      const double2 t2 = cmul(hb[i + 2], v2), t3 = cmul(hb[i + 3], v3);
+      acc.x -= t0.x;
+      acc.y -= t0.y;
+      acc.x -= t1.x;
+      acc.y -= t1.y;
+      acc.x -= t2.x;
+      acc.y -= t2.y;
+      acc.x -= t3.x;
+      acc.y -= t3.y;
+    }
+    for (; i < nvec; ++i) {
+      const double2 t = cmul(hb[i], vk[(int64_t)i * ut]);
+      acc.x -= t.x;
+      acc.y -= t.y;
+    }
+    w[r.off + k] = acc;
+    nrm2 = acc.x * acc.x + acc.y * acc.y;
+  }
+  if (!do_norm) return;
+  const double2 t = block_sum2(make_double2(nrm2, 0.0), sh);
+  if (threadIdx.x == 0) {
+    npart[(size_t)b * maxB + blockIdx.x] = t.x;
+    __threadfence();
+    last = atomicAdd(&counters[b], 1) == (int)nb - 1;
+  }
+  __syncthreads();
+  if (!last || threadIdx.x >= 64) return;
+  __threadfence();
+  const double sum = wave_sum_partials(npart + (size_t)b * maxB, (int)nb);
+  if (threadIdx.x != 0) return;
+  counters[b] = 0;
+  const double nv = sqrt(fmax(sum, 0.0));
+  wn[b] = nv;
+  H[(size_t)b * (m + 1) * m + (size_t)(j + 1) * m + j] = make_double2(nv, 0.0);
+  givens_update(b, H, g, cs, sn, st, m, j, tol, n_running);
 }
 
 // y = R^{-1} g (upper triangular, size jdone), stored in place of g
@@ -387,10 +542,11 @@ selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a,
   }
 }
 
-// out_u = Minv[s_u] in_u for every unit (user layout)
+// out_u = Minv[s_u] in_u for every unit (user layout); OT is the output real type
+template <typename OT>
 __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
                                      const int64_t* __restrict__ soff, const RhsVec* __restrict__ rv, int n_a,
-                                     int n_states, const double2* __restrict__ in, double2* __restrict__ out) {
+                                     int n_states, const double2* __restrict__ in, OT* __restrict__ out) {
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -406,7 +562,20 @@ __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uin
     acc.x += t.x;
     acc.y += t.y;
   }
-  out[r.off + k] = acc;
+  out[2 * (r.off + k)] = (OT)acc.x;
+  out[2 * (r.off + k) + 1] = (OT)acc.y;
+}
+
+template <typename OT>
+__global__ void convert_vec_kernel(const RhsVec* __restrict__ rv, const double2* __restrict__ in,
+                                   OT* __restrict__ out) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= r.N) return;
+  const double2 v = in[r.off + k];
+  out[2 * (r.off + k)] = (OT)v.x;
+  out[2 * (r.off + k) + 1] = (OT)v.y;
 }
 
 // z = V y (first jdone columns)
@@ -443,7 +612,11 @@ struct Work {
   double2* d;
   double2* ro;
   double2* pz;
+  double2* xs;   // matvec input in the store precision
   double2* Minv;
+  double* wn;
+  double* npart;
+  int* cnt;
   void* mv_partial;
   double2* H;
   double2* g;
@@ -481,6 +654,10 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, 
   w.d = (double2*)take(ut * 16);
   w.ro = (double2*)take(ut * 16);
   w.pz = (double2*)take(ut * 16);
+  w.xs = (double2*)take(ut * 16);
+  w.wn = (double*)take((size_t)B * 8);
+  w.npart = (double*)take((size_t)B * ((maxN + 63) / 64 + 1) * 8);
+  w.cnt = (int*)take((size_t)B * (m + 2) * 4);
   w.Minv = (double2*)take((size_t)n_states * n_a * n_a * 16);
   w.mv_partial = take(mv_bytes);
   w.H = (double2*)take((size_t)B * (m + 1) * m * 16);
@@ -503,6 +680,8 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, 
 
 struct GmresRun {
   r3m_ctx ctx;
+  bool use_graph = true;
+  std::vector<int64_t> graph_key;
   const BatchDesc* bd;
   const r3m_batch* batch;
   int n_a, m, maxP, B;
@@ -549,29 +728,80 @@ struct GmresRun {
   }
 
   void precond(const double2* in, double2* out) {
-    hipLaunchKernelGGL(apply_precond_kernel, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff, W.rv, n_a,
-                       n_states, in, out);
+    hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff, W.rv,
+                       n_a, n_states, in, (double*)out);
+  }
+
+  // w = Z M^{-1} v (or Z v): the preconditioner writes the matvec input in
+  // the store precision directly
+  void apply_operator(const r3m_store* Z, const double2* v) {
+    const bool c64 = Z->near_dtype == R3M_C64;
+    const void* xin = v;
+    if (pre) {
+      if (c64)
+        hipLaunchKernelGGL(apply_precond_kernel<float>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
+                           W.rv, n_a, n_states, v, (float*)W.xs);
+      else
+        hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
+                           W.rv, n_a, n_states, v, (double*)W.xs);
+      xin = W.xs;
+    } else if (c64) {
+      hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs);
+      xin = W.xs;
+    }
+    launch_matvec_pre(Z, *bd, batch->states, xin, W.w, W.mv_partial, choose_chunks(*bd, 64), s);
   }
 
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
-    if (pre) {
-      precond(W.V + (int64_t)j * ut, W.pz);
-      matvec(Z, W.pz, W.w);
-    } else {
-      matvec(Z, W.V + (int64_t)j * ut, W.w);
-    }
+    apply_operator(Z, W.V + (int64_t)j * ut);
+    const dim3 dgrid(maxP, j + 1, B);
+    int* dcnt = W.cnt;
+    int* ncnt = W.cnt + (size_t)B * (m + 1);
+    const int maxB = (int)((maxN + 63) / 64 + 1);
     for (int pass = 0; pass < 2; ++pass) {
-      dots(W.V, ut, W.w, j + 1);
-      hipLaunchKernelGGL(gs_update_kernel, vgrid(), dim3(256), 0, s, W.V, W.w, W.rv, W.st, W.hbuf, j + 1, ut);
-      hipLaunchKernelGGL(accumulate_h_kernel, dim3(B), dim3(((j + 1 + 63) / 64) * 64), 0, s, W.H, W.hbuf,
-                         j + 1, m, j, pass == 0 ? 1 : 0);
+      hipLaunchKernelGGL(dots_fused_kernel, dgrid, dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, j + 1, maxP,
+                         W.dpart, dcnt, W.H, m, j, pass, W.hbuf, pass == 0 ? W.counters : (int*)nullptr);
+      hipLaunchKernelGGL(gs_update_fused_kernel, dim3(ceil_div((size_t)maxN, 64), B), dim3(64), 0, s, W.V, W.w,
+                         W.rv, W.st, W.hbuf, j + 1, ut, pass, W.npart, ncnt, maxB, W.H, W.g, W.cs, W.sn, m, j, tol,
+                         W.counters, W.wn);
     }
-    norms(W.w);
-    hipLaunchKernelGGL(normalize_kernel, vgrid(), dim3(256), 0, s, W.w, W.V, W.rv, W.st, W.nrm, W.H, m, j, ut);
-    R3M_CHECK_HIP(hipMemsetAsync(W.counters, 0, sizeof(int), s));
-    hipLaunchKernelGGL(givens_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.H, W.g, W.cs, W.sn, W.st, B, m,
-                       j, tol, W.counters);
+    hipLaunchKernelGGL(normalize_kernel, vgrid(), dim3(256), 0, s, W.w, W.V, W.rv, W.st, W.wn, m, j, ut);
     R3M_CHECK_HIP(hipGetLastError());
+  }
+
+  // Arnoldi steps [j0, j1): replayed from a cached HIP graph (captured on the
+  // context stream the first time this block is met), or launched eagerly
+  void run_steps(const r3m_store* Z, int j0, int j1, double tol) {
+    if (!use_graph) {
+      for (int j = j0; j < j1; ++j) arnoldi_step(Z, j, tol);
+      return;
+    }
+    std::vector<int64_t> key = graph_key;
+    key.push_back((int64_t)(intptr_t)Z->near);
+    key.push_back((int64_t)(intptr_t)Z->far);
+    key.push_back(Z->near_dtype);
+    key.push_back(j0);
+    key.push_back(j1);
+    int64_t tb;
+    std::memcpy(&tb, &tol, sizeof(tb));
+    key.push_back(tb);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+      if (ctx->graphs.size() > 512) {
+        R3M_CHECK_HIP(hipStreamSynchronize(s));
+        for (auto& kv : ctx->graphs) R3M_CHECK_HIP(hipGraphExecDestroy(kv.second));
+        ctx->graphs.clear();
+      }
+      hipGraph_t g;
+      R3M_CHECK_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      for (int j = j0; j < j1; ++j) arnoldi_step(Z, j, tol);
+      R3M_CHECK_HIP(hipStreamEndCapture(s, &g));
+      hipGraphExec_t ex;
+      R3M_CHECK_HIP(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+      R3M_CHECK_HIP(hipGraphDestroy(g));
+      it = ctx->graphs.emplace(key, ex).first;
+    }
+    R3M_CHECK_HIP(hipGraphLaunch(it->second, s));
   }
 
   // GMRES(m) on Z for rhs into sol (initial guess kept), for RHS with running[b];
@@ -602,16 +832,15 @@ struct GmresRun {
       hipLaunchKernelGGL(cycle_start_kernel, g0, dim3(256), 0, s, W.r, W.V, W.rv, W.st, W.nrm, W.g, m);
       const int steps = std::max(1, std::min(m, max_iter - min_used));
       int j = 0;
-      for (; j < steps; ++j) {
-        arnoldi_step(Z, j, tol);
-        if ((j + 1) % kCheckEvery == 0 && j + 1 < steps) {
+      for (int j0 = 0; j0 < steps; j0 += kCheckEvery) {
+        const int j1 = std::min(j0 + kCheckEvery, steps);
+        run_steps(Z, j0, j1, tol);
+        j = j1;
+        if (j1 < steps) {
           int nrun = 0;
           R3M_CHECK_HIP(hipMemcpyAsync(&nrun, W.counters, sizeof(int), hipMemcpyDeviceToHost, s));
           R3M_CHECK_HIP(hipStreamSynchronize(s));
-          if (nrun == 0) {
-            ++j;
-            break;
-          }
+          if (nrun == 0) break;
         }
       }
       hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.st, B, j);
@@ -705,8 +934,29 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     const int mv_chunks = choose_chunks(bd, 64);
     size_t mv = matvec_partial_bytes(bd, Z, mv_chunks);
     if (refine) mv = std::max(mv, matvec_partial_bytes(bd, Z64, mv_chunks));
+    // all work runs on the context stream, ordered after the caller's stream
+    if (!ctx->work_stream) {
+      R3M_CHECK_HIP(hipStreamCreateWithFlags(&ctx->work_stream, hipStreamNonBlocking));
+      R3M_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+      R3M_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+    }
+    R3M_CHECK_HIP(hipEventRecord(ctx->ev_in, stream));
+    R3M_CHECK_HIP(hipStreamWaitEvent(ctx->work_stream, ctx->ev_in, 0));
+    const hipStream_t user_stream = stream;
+    stream = ctx->work_stream;
+    struct Rejoin {
+      r3m_ctx c;
+      hipStream_t us;
+      ~Rejoin() {
+        (void)hipEventRecord(c->ev_out, c->work_stream);
+        (void)hipStreamWaitEvent(us, c->ev_out, 0);
+      }
+    } rejoin{ctx, user_stream};
     GmresRun run;
     run.ctx = ctx;
+    run.use_graph = !(opts->flags & R3M_GMRES_EAGER);
+    run.graph_key = {(int64_t)(intptr_t)&bd, (int64_t)(intptr_t)batch->states, (int64_t)(intptr_t)work_dev,
+                     (int64_t)m, (int64_t)opts->precond, (int64_t)bd.B};
     run.bd = &bd;
     run.batch = batch;
     run.n_a = n_a;
@@ -727,6 +977,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     R3M_CHECK_HIP(hipMemcpyAsync(run.W.rv, rv.data(), rv.size() * sizeof(RhsVec), hipMemcpyHostToDevice, stream));
     R3M_CHECK_HIP(hipMemcpyAsync(run.W.soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice, stream));
     R3M_CHECK_HIP(hipMemsetAsync(run.W.counters, 0, 256, stream));
+    R3M_CHECK_HIP(hipMemsetAsync(run.W.cnt, 0, (size_t)bd.B * (m + 2) * 4, stream));
 
     // input checks on the device: state bytes and finite right-hand sides
     const int64_t maxU = run.maxN / n_a;

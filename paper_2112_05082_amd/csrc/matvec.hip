@@ -46,6 +46,22 @@ __device__ inline void load2<double>(const double* p, size_t idx, Cx<double>& a,
   b = {v.x, v.y};
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (id % 8).  The 1D grid
+// is decoded so that the n_blocks workgroups sharing a displacement group sit
+// on one XCD and meet its factor blocks in that XCD's L2.  Returns false for
+// padding workgroups.
+constexpr int kXcd = 8;
+__device__ __forceinline__ bool decode_wg(int n_blocks, int n_groups, int& blk, int& grp) {
+  const int total = n_blocks * n_groups;
+  const int per = (total + kXcd - 1) / kXcd;
+  const int id = blockIdx.x;
+  const int t = (id % kXcd) * per + id / kXcd;
+  if (t >= total) return false;
+  grp = t / n_blocks;
+  blk = t % n_blocks;
+  return true;
+}
+
 // acc += a * b as two fused multiply-adds per real component
 template <typename S>
 __device__ __forceinline__ void cmac(S& re, S& im, Cx<S> a, Cx<S> b) {
@@ -136,9 +152,10 @@ template <typename S, int QS>
 __global__ void __launch_bounds__(256)
 near_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, const uint8_t* __restrict__ states,
             const S* __restrict__ nearb, int Nx, int Ny, int n, int n_a, int n_states, const S* __restrict__ x,
-            S* __restrict__ out, int64_t total_units, int slot0, int hgroups) {
-  const TileDev blk = tiles[blockIdx.x];
-  const int h = blockIdx.y;
+            S* __restrict__ out, int64_t total_units, int slot0, int hgroups, int n_blocks) {
+  int bi, h;
+  if (!decode_wg(n_blocks, hgroups, bi, h)) return;
+  const TileDev blk = tiles[bi];
   const RhsDev R = rhs[blk.b];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -190,18 +207,22 @@ near_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, c
 // (unit u, quarter q) forms its quarter of t = V[A(s_j)]^H x_j, the unit's
 // four lanes add their parts with two lane swaps, and the lane expands its own
 // rows y += U[A(s_i)] t.  Ranks above kRch take extra synchronous slices.
+#ifndef R3M_FAR_WAVES_PER_EU
+#define R3M_FAR_WAVES_PER_EU 2
+#endif
 template <typename S, int QS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R3M_FAR_WAVES_PER_EU)))
 far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, int groups,
            const uint8_t* __restrict__ states, const S* __restrict__ farf, const int* __restrict__ ranks,
            int max_rank, int Dx, int Dy, int nr, int n, int n_a, int n_states, const S* __restrict__ x,
-           S* __restrict__ out, int64_t total_units, int lds_state_cap) {
+           S* __restrict__ out, int64_t total_units, int lds_state_cap, int n_blocks) {
   extern __shared__ unsigned char smem_raw[];
   Cx<S>* lds_u = reinterpret_cast<Cx<S>*>(smem_raw);  // [kRch][n]
   Cx<S>* lds_v = lds_u + kRch * n;                     // [kRch][n]
   uint8_t* lds_s = reinterpret_cast<uint8_t*>(lds_v + kRch * n);
-  const TileDev blk = tiles[blockIdx.x];
-  const int g = blockIdx.y;
+  int bi, g;
+  if (!decode_wg(n_blocks, groups, bi, g)) return;
+  const TileDev blk = tiles[bi];
   const RhsDev R = rhs[blk.b];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -383,8 +404,24 @@ reduce_groups_kernel(const RhsDev* __restrict__ rhs, const S* __restrict__ parti
   if (k >= (int64_t)R.Lx * R.Ly * n_a) return;
   const size_t e = (size_t)R.unit_off * n_a + k;
   const size_t stride = (size_t)total_units * n_a;
+  // slots are added in order; loads are issued eight at a time
   S re = 0, im = 0;
-  for (int c = 0; c < slots; ++c) {
+  int c = 0;
+  for (; c + 8 <= slots; c += 8) {
+    S pr[8], pi[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const size_t p = ((size_t)(c + q) * stride + e) * 2;
+      pr[q] = partial[p];
+      pi[q] = partial[p + 1];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      re += pr[q];
+      im += pi[q];
+    }
+  }
+  for (; c < slots; ++c) {
     const size_t p = ((size_t)c * stride + e) * 2;
     re += partial[p];
     im += partial[p + 1];
@@ -452,8 +489,8 @@ void validate_store(const r3m_store* Z) {
 }
 
 template <typename S, typename XT>
-static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
-                         void* partial, int chunks, hipStream_t stream) {
+static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const S* xs, XT* y,
+                        char* part, int chunks, hipStream_t stream) {
   const int n_a = Z->n / Z->n_states;
   const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
   const bool far = store_has_far(Z);
@@ -462,7 +499,34 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
   const int groups = far ? std::max(chunks, 1) : 0;
   const int hg = near_groups(Z);
   const int64_t tu = (int64_t)bd.total_units;
-  const size_t vec = (size_t)tu * n_a * 2 * sizeof(S);
+  if (far) {
+    const int lds_state_cap = 16384;
+    const size_t lds = 2 * (size_t)kRch * Z->n * 2 * sizeof(S) + lds_state_cap;
+    auto kern = n_a == 40 ? far_kernel<S, 10> : far_kernel<S, 16>;
+    const int nwg = (bd.n_tiles * groups + kXcd - 1) / kXcd * kXcd;
+    hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), lds, stream, bd.rhs, bd.tiles, groups, states,
+                       (const S*)((const char*)Z->far + head), (const int*)Z->far, Z->max_rank, Z->Dx, Z->Dy,
+                       Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles);
+    R3M_CHECK_HIP(hipGetLastError());
+  }
+  auto nk = n_a == 40 ? near_kernel<S, 10> : near_kernel<S, 16>;
+  const int nwg_near = (bd.n_tiles * hg + kXcd - 1) / kXcd * kXcd;
+  hipLaunchKernelGGL(nk, dim3(nwg_near), dim3(256), 0, stream, bd.rhs, bd.tiles, states, (const S*)Z->near, Nx,
+                     Ny, Z->n, n_a, Z->n_states, xs, (S*)part, tu, groups, hg, bd.n_tiles);
+  R3M_CHECK_HIP(hipGetLastError());
+  hipLaunchKernelGGL((reduce_groups_kernel<S, XT>), dim3(ceil_div((size_t)bd.max_units * n_a, 64), bd.B),
+                     dim3(64), 0, stream, bd.rhs, (const S*)part, groups + hg, tu, n_a, y);
+  R3M_CHECK_HIP(hipGetLastError());
+}
+
+template <typename S, typename XT>
+static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
+                         void* partial, int chunks, hipStream_t stream) {
+  const int n_a = Z->n / Z->n_states;
+  const bool far = store_has_far(Z);
+  const int groups = far ? std::max(chunks, 1) : 0;
+  const int hg = near_groups(Z);
+  const size_t vec = (size_t)bd.total_units * n_a * 2 * sizeof(S);
   char* part = (char*)partial;
   const S* xs = (const S*)x;
   if (!std::is_same<S, XT>::value) {
@@ -471,22 +535,17 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
                        dim3(256), 0, stream, bd.rhs, n_a, (const XT*)x, xc);
     xs = xc;
   }
-  if (far) {
-    const int lds_state_cap = 16384;
-    const size_t lds = 2 * (size_t)kRch * Z->n * 2 * sizeof(S) + lds_state_cap;
-    auto kern = n_a == 40 ? far_kernel<S, 10> : far_kernel<S, 16>;
-    hipLaunchKernelGGL(kern, dim3(bd.n_tiles, groups), dim3(256), lds, stream, bd.rhs, bd.tiles, groups, states,
-                       (const S*)((const char*)Z->far + head), (const int*)Z->far, Z->max_rank, Z->Dx, Z->Dy,
-                       Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap);
-    R3M_CHECK_HIP(hipGetLastError());
-  }
-  auto nk = n_a == 40 ? near_kernel<S, 10> : near_kernel<S, 16>;
-  hipLaunchKernelGGL(nk, dim3(bd.n_tiles, hg), dim3(256), 0, stream, bd.rhs, bd.tiles, states, (const S*)Z->near, Nx,
-                     Ny, Z->n, n_a, Z->n_states, xs, (S*)part, tu, groups, hg);
-  R3M_CHECK_HIP(hipGetLastError());
-  hipLaunchKernelGGL((reduce_groups_kernel<S, XT>), dim3(ceil_div((size_t)bd.max_units * n_a, 256), bd.B),
-                     dim3(256), 0, stream, bd.rhs, (const S*)part, groups + hg, tu, n_a, (XT*)y);
-  R3M_CHECK_HIP(hipGetLastError());
+  launch_core<S, XT>(Z, bd, states, xs, (XT*)y, part, chunks, stream);
+}
+
+// matvec with x already in the store precision (float for C64, double for
+// C128); y is C128
+void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
+                       void* partial, int chunks, hipStream_t stream) {
+  if (Z->near_dtype == R3M_C128)
+    launch_core<double, double>(Z, bd, states, (const double*)xs, (double*)y, (char*)partial, chunks, stream);
+  else
+    launch_core<float, double>(Z, bd, states, (const float*)xs, (double*)y, (char*)partial, chunks, stream);
 }
 
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,

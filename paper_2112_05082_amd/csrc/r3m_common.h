@@ -98,6 +98,9 @@ struct r3m_ctx_s {
   r3m::DevBuf flag;  // int32 flags for device-side checks
   r3m::DevBuf geom;  // geometry tables
   std::map<r3m::BatchKey, r3m::BatchDesc*> batches;
+  hipStream_t work_stream = nullptr;  // default-priority stream for graph replays
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
 };
 
 namespace r3m {

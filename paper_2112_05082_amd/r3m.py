@@ -72,6 +72,7 @@ class GmresOptsC(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
         ("refine_tol", C.c_double), ("max_refine", C.c_int32), ("precond", C.c_int32),
+        ("flags", C.c_int32),
     ]
 
 
@@ -302,13 +303,15 @@ def r3m_retrieved_matvec(ctx: Context, store: Store, batch: Batch, vec_dtype: in
 
 def r3m_gmres_solve(ctx: Context, store: Store, store64: Store | None, batch: Batch, b, x, tol: float,
                     restart: int, max_iter: int, work, refine_tol: float = 0.0, max_refine: int = 0,
-                    stream=None, allow_not_converged: bool = False, precond: int = PRECOND_NONE):
+                    stream=None, allow_not_converged: bool = False, precond: int = PRECOND_NONE,
+                    eager: bool = False):
     lib = load()
     _need_vec(b, batch, store.n // store.n_states, "b")
     _need_vec(x, batch, store.n // store.n_states, "x")
     sc = store.c()
     s64 = store64.c() if store64 is not None else None
-    opts = GmresOptsC(float(tol), int(restart), int(max_iter), float(refine_tol), int(max_refine), int(precond))
+    opts = GmresOptsC(float(tol), int(restart), int(max_iter), float(refine_tol), int(max_refine), int(precond),
+                      1 if eager else 0)
     rep = (GmresReportC * max(batch.B, 1))()
     rc = lib.r3m_gmres_solve(ctx.handle, C.byref(sc), C.byref(s64) if s64 is not None else None,
                              C.byref(batch.cs), C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
@@ -363,5 +366,5 @@ def matvec_work_bytes(ctx, store: Store, batch: Batch, vec_dtype):
 
 def gmres_work_bytes(ctx, store: Store, batch: Batch, restart: int):
     sc = store.c()
-    opts = GmresOptsC(1e-6, int(restart), 1, 0.0, 0, 0)
+    opts = GmresOptsC(1e-6, int(restart), 1, 0.0, 0, 0, 0)
     return load().r3m_gmres_work_bytes(ctx.handle, C.byref(sc), C.byref(batch.cs), C.byref(opts))

@@ -364,3 +364,31 @@ def test_mixed_refinement_to_fp64(r3m, ctx, stores_2bit_8):
     work2 = torch.empty(r3m.gmres_work_bytes(ctx, s128, batch, 60), dtype=torch.uint8, device=DEV)
     r3m.r3m_gmres_solve(ctx, s128, None, batch, b, x64, 1e-11, 60, 3000, work2, precond=r3m.PRECOND_BLOCK_JACOBI)
     assert rel_l2(x.cpu().numpy(), x64.cpu().numpy()) <= 1e-8
+
+
+def test_graph_replays_match_eager(r3m, ctx, stores_2bit_8):
+    """Blocks of Arnoldi steps replayed from captured HIP graphs give bitwise the
+    eager result, on the first capture and on later replays with eager work and
+    synchronisations in between."""
+    _, s64, _ = stores_2bit_8
+    g = geom(r3m, 2)
+    batch = batch_for(r3m, [cb.uniform(8, 4, 21)], [8])
+    b = torch.zeros(2560, dtype=torch.complex128, device=DEV)
+    r3m.r3m_plane_wave_rhs(ctx, g, batch, [[0.2, 0.1, 1.0]], b)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, s64, batch, 20), dtype=torch.uint8, device=DEV)
+
+    def run(eager):
+        x = torch.zeros_like(b)
+        _, rep = r3m.r3m_gmres_solve(ctx, s64, None, batch, b, x, 1e-6, 20, 400, work,
+                                     precond=r3m.PRECOND_BLOCK_JACOBI, eager=eager)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), rep
+
+    x_e, rep_e = run(True)
+    for _ in range(3):
+        x_g, rep_g = run(False)
+        assert np.array_equal(x_g, x_e) and rep_g[0][0] == rep_e[0][0]
+        # eager work in between: an unrelated matvec and a synchronisation
+        run_matvec(r3m, ctx, s64, batch, b.to(torch.complex64), r3m.C64)
+    x_e2, _ = run(True)
+    assert np.array_equal(x_e2, x_e)
