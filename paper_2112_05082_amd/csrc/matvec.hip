@@ -22,7 +22,7 @@ namespace {
 constexpr int kTW = 4, kTH = 4, kTU = kTW * kTH;  // tile of one wave
 constexpr int kBW = 8, kBH = 8, kBU = kBW * kBH;  // block of one workgroup (2 x 2 tiles)
 constexpr int kQ = 4;     // lanes per observer unit (row quarters)
-constexpr int kRch = 8;   // ranks held in registers per pass
+
 
 template <typename T>
 struct Cx {
@@ -148,52 +148,130 @@ __device__ __forceinline__ void far_slice(const Cx<S>* __restrict__ lds_u, const
 // near displacement d); wave w owns the 4x4 tile (w & 1, w >> 1) of the
 // block, lane (unit, quarter q) owns rows [q*QS, q*QS + QS) of y_u and adds
 // Z(d)[A(s_i), A(s_j)] x_j.  The result goes to its own partial slot.
-template <typename S, int QS>
+// Near field: one workgroup per (8x8 block of observer units, near group h);
+// the group's near displacements are taken in turn.  Per displacement the
+// block's 64 shifted sources (x_j and state) are staged in LDS; then for each
+// observer state a, rows of the slab Z(d)[A(a), :] are staged in LDS with
+// coalesced loads (SR rows per pass) and every (unit, row) task of the units
+// in state a adds slab[row][A(s_j)] . x_j into an LDS accumulator.  Each
+// accumulator entry is written by one task per pass, so the sum is in fixed
+// order.  The block's result goes to partial slot slot0 + h.
+template <typename S, int SR>
 __global__ void __launch_bounds__(256)
 near_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, const uint8_t* __restrict__ states,
             const S* __restrict__ nearb, int Nx, int Ny, int n, int n_a, int n_states, const S* __restrict__ x,
             S* __restrict__ out, int64_t total_units, int slot0, int hgroups, int n_blocks) {
+  extern __shared__ unsigned char smem_raw[];
+  // slab rows padded to n + 2 so that lanes reading consecutive rows fall in
+  // different LDS banks
+  const int ns = n + 2;
+  Cx<S>* slab = reinterpret_cast<Cx<S>*>(smem_raw);  // [SR][n + 2]
+  Cx<S>* yacc = slab + (size_t)SR * ns;               // [kBU][n_a]
+  Cx<S>* xl = yacc + (size_t)kBU * n_a;               // [kBU][n_a]
+  __shared__ uint8_t list[kBU];
+  __shared__ int cnt[17];
+  __shared__ int start[17];
+  __shared__ uint8_t ust[kBU];
+  __shared__ int sst[kBU];
   int bi, h;
   if (!decode_wg(n_blocks, hgroups, bi, h)) return;
   const TileDev blk = tiles[bi];
   const RhsDev R = rhs[blk.b];
   const int tid = threadIdx.x;
-  const int wave = tid >> 6, lane = tid & 63;
-  const int ul = lane / kQ, q = lane % kQ;
-  const int ix = blk.tx + (wave & 1) * kTW + ul % kTW, iy = blk.ty + (wave >> 1) * kTH + ul / kTW;
-  const bool vi = ix < R.Lx && iy < R.Ly;
-  if (!vi) return;
-  const int si = min((int)states[R.state_off + (int64_t)iy * R.Lx + ix], n_states - 1);
-  const int m0 = q * QS;
+  for (int e = tid; e < kBU * n_a; e += blockDim.x) yacc[e] = Cx<S>{0, 0};
+  if (tid <= 16) cnt[tid] = 0;
+  __syncthreads();
+  if (tid < kBU) {
+    const int ix = blk.tx + tid % kBW, iy = blk.ty + tid / kBW;
+    const int st = (ix < R.Lx && iy < R.Ly) ? min((int)states[R.state_off + (int64_t)iy * R.Lx + ix], n_states - 1)
+                                            : 255;
+    ust[tid] = (uint8_t)st;
+    if (st != 255) atomicAdd(&cnt[st], 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int c = 0;
+    for (int a = 0; a < n_states; ++a) {
+      start[a] = c;
+      c += cnt[a];
+      cnt[a] = 0;
+    }
+    start[n_states] = c;
+  }
+  __syncthreads();
+  if (tid < kBU && ust[tid] != 255) {
+    const int pos = atomicAdd(&cnt[ust[tid]], 1);
+    list[start[ust[tid]] + pos] = (uint8_t)tid;
+  }
   const int n_near = (2 * Nx + 1) * (2 * Ny + 1);
-  S acc_re[QS], acc_im[QS];
-#pragma unroll
-  for (int k = 0; k < QS; ++k) acc_re[k] = acc_im[k] = 0;
+  const int bx_hi = min(blk.tx + kBW, R.Lx) - 1, by_hi = min(blk.ty + kBH, R.Ly) - 1;
   for (int nslot = h; nslot < n_near; nslot += hgroups) {
     const int dx = nslot % (2 * Nx + 1) - Nx, dy = nslot / (2 * Nx + 1) - Ny;
-    const int jx = ix - dx, jy = iy - dy;
-    if (!(jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly)) continue;
-    const int sj = min((int)states[R.state_off + (int64_t)jy * R.Lx + jx], n_states - 1);
-    const S* xj = x + (size_t)(R.unit_off + (int64_t)jy * R.Lx + jx) * n_a * 2;
+    if (bx_hi - dx < 0 || blk.tx - dx > R.Lx - 1 || by_hi - dy < 0 || blk.ty - dy > R.Ly - 1) continue;
+    __syncthreads();
+    // the block's shifted sources
+    if (tid < kBU) {
+      const int jx = blk.tx + tid % kBW - dx, jy = blk.ty + tid / kBW - dy;
+      const bool v = ust[tid] != 255 && jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly;
+      sst[tid] = v ? min((int)states[R.state_off + (int64_t)jy * R.Lx + jx], n_states - 1) : -1;
+    }
+    for (int e2 = 2 * tid; e2 < kBU * n_a; e2 += 2 * blockDim.x) {
+      const int u = e2 / n_a, c = e2 % n_a;
+      const int jx = blk.tx + u % kBW - dx, jy = blk.ty + u / kBW - dy;
+      Cx<S> x0{0, 0}, x1{0, 0};
+      if (jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly)
+        load2<S>(x + (size_t)(R.unit_off + (int64_t)jy * R.Lx + jx) * n_a * 2, c, x0, x1);
+      xl[e2] = x0;
+      xl[e2 + 1] = x1;
+    }
     const S* Zb = nearb + (size_t)nslot * n * n * 2;
-    for (int c = 0; c < n_a; c += 2) {
-      Cx<S> x0, x1;
-      load2<S>(xj, c, x0, x1);
-#pragma unroll
-      for (int k = 0; k < QS; ++k) {
-        Cx<S> z0, z1;
-        load2<S>(Zb, (size_t)(si * n_a + m0 + k) * n + sj * n_a + c, z0, z1);
-        cmac(acc_re[k], acc_im[k], z0, x0);
-        cmac(acc_re[k], acc_im[k], z1, x1);
+    for (int a = 0; a < n_states; ++a) {
+      const int c0 = start[a], c1 = start[a + 1];
+      if (c1 == c0) continue;
+      for (int r0 = 0; r0 < n_a; r0 += SR) {
+        __syncthreads();
+        {
+          const S* src = Zb + ((size_t)a * n_a + r0) * n * 2;  // rows A(a)[r0, r0 + SR), contiguous
+          for (int e2 = 2 * tid; e2 < SR * n; e2 += 2 * blockDim.x) {
+            Cx<S> z0, z1;
+            load2<S>(src, e2, z0, z1);
+            const int d2 = (e2 / n) * ns + e2 % n;
+            slab[d2] = z0;
+            slab[d2 + 1] = z1;
+          }
+        }
+        __syncthreads();
+        const int ntask = (c1 - c0) * SR;
+        for (int t = tid; t < ntask; t += blockDim.x) {
+          const int u = list[c0 + t / SR], row = t % SR;
+          const int sj = sst[u];
+          if (sj < 0) continue;
+          const S* xr = reinterpret_cast<const S*>(xl + u * n_a);
+          const S* zr = reinterpret_cast<const S*>(slab) + ((size_t)row * ns + sj * n_a) * 2;
+          S re = 0, im = 0;
+          for (int c = 0; c < n_a; c += 2) {
+            Cx<S> x0, x1, z0, z1;
+            load2<S>(xr, c, x0, x1);
+            load2<S>(zr, c, z0, z1);
+            cmac(re, im, z0, x0);
+            cmac(re, im, z1, x1);
+          }
+          Cx<S>& yv = yacc[u * n_a + r0 + row];
+          yv.re += re;
+          yv.im += im;
+        }
       }
     }
   }
-  const size_t yb = (size_t)(R.unit_off + (int64_t)iy * R.Lx + ix) * n_a;
-  S* o = out + ((size_t)(slot0 + h) * total_units * n_a + yb) * 2;
-#pragma unroll
-  for (int k = 0; k < QS; ++k) {
-    o[2 * (m0 + k)] = acc_re[k];
-    o[2 * (m0 + k) + 1] = acc_im[k];
+  __syncthreads();
+  for (int e = tid; e < kBU * n_a; e += blockDim.x) {
+    const int u = e / n_a, m = e % n_a;
+    const int ix = blk.tx + u % kBW, iy = blk.ty + u / kBW;
+    if (ix >= R.Lx || iy >= R.Ly) continue;
+    const size_t yb = (size_t)(R.unit_off + (int64_t)iy * R.Lx + ix) * n_a + m;
+    S* o = out + ((size_t)(slot0 + h) * total_units * n_a + yb) * 2;
+    o[0] = yacc[e].re;
+    o[1] = yacc[e].im;
   }
 }
 
@@ -210,16 +288,16 @@ near_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, c
 #ifndef R3M_FAR_WAVES_PER_EU
 #define R3M_FAR_WAVES_PER_EU 2
 #endif
-template <typename S, int QS>
+template <typename S, int QS, int kRch>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R3M_FAR_WAVES_PER_EU)))
 far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, int groups,
            const uint8_t* __restrict__ states, const S* __restrict__ farf, const int* __restrict__ ranks,
            int max_rank, int Dx, int Dy, int nr, int n, int n_a, int n_states, const S* __restrict__ x,
            S* __restrict__ out, int64_t total_units, int lds_state_cap, int n_blocks) {
   extern __shared__ unsigned char smem_raw[];
-  Cx<S>* lds_u = reinterpret_cast<Cx<S>*>(smem_raw);  // [kRch][n]
-  Cx<S>* lds_v = lds_u + kRch * n;                     // [kRch][n]
-  uint8_t* lds_s = reinterpret_cast<uint8_t*>(lds_v + kRch * n);
+  Cx<S>* lds_u = reinterpret_cast<Cx<S>*>(smem_raw);  // [2][kRch][n]
+  Cx<S>* lds_v = lds_u + 2 * kRch * n;                 // [2][kRch][n]
+  uint8_t* lds_s = reinterpret_cast<uint8_t*>(lds_v + 2 * kRch * n);
   int bi, g;
   if (!decode_wg(n_blocks, groups, bi, g)) return;
   const TileDev blk = tiles[bi];
@@ -262,7 +340,7 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
   };
 
   // per-thread share of one staged slice: rows [rho0, rho0 + rc) of U and V
-  constexpr int kPer = (kRch * 160 + 511) / 512;  // float4/double-pair chunks per thread (n <= 160)
+  constexpr int kPer = (kRch * 256 + 511) / 512;  // pairs per thread for one slice (n <= 256)
   Cx<S> pu[2 * kPer], pv[2 * kPer];
   auto fetch = [&](const S* Uf, int rho0, int rc) {
     const int cnt = rc * n;
@@ -277,16 +355,18 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
       }
     }
   };
-  auto stash = [&](int rc) {
+  auto stash = [&](int rc, int bsel) {
     const int cnt = rc * n;
+    Cx<S>* du = lds_u + bsel * kRch * n;
+    Cx<S>* dv = lds_v + bsel * kRch * n;
 #pragma unroll
     for (int i = 0; i < kPer; ++i) {
       const int e2 = 2 * (tid + i * 256);
       if (e2 < cnt) {
-        lds_u[e2] = pu[2 * i];
-        lds_u[e2 + 1] = pu[2 * i + 1];
-        lds_v[e2] = pv[2 * i];
-        lds_v[e2 + 1] = pv[2 * i + 1];
+        du[e2] = pu[2 * i];
+        du[e2 + 1] = pu[2 * i + 1];
+        dv[e2] = pv[2 * i];
+        dv[e2 + 1] = pv[2 * i + 1];
       }
     }
   };
@@ -304,22 +384,23 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
 #pragma unroll
   for (int k = 0; k < QS; ++k) acc_re[k] = acc_im[k] = 0;
 
+  // double-buffered slices: the next displacement's slice is fetched and
+  // stashed into the other buffer while this one is computed (one barrier
+  // per displacement)
+  int buf = 0;
   int e = next_far(g);
   int f = 0, r = 0;
-  Cx<S> xc[QS], xn[QS];
   if (e < nd) {
     const int dx = dx_lo + e % wdx, dy = dy_lo + e / wdx;
     f = far_index(dx, dy, Dx, Dy, nr);
     r = ranks[f];
     fetch(farf + (size_t)f * fstride, 0, min(kRch, r));
-    fetch_x(dx, dy, xc);
+    stash(min(kRch, r), 0);
   }
+  __syncthreads();
   while (e < nd) {
     const int dx = dx_lo + e % wdx, dy = dy_lo + e / wdx;
     const int rc = min(kRch, r);
-    stash(rc);
-    __syncthreads();
-    // prefetch the next displacement while this one is computed
     const int en = next_far(e + groups);
     int fnext = 0, rnext = 0;
     if (en < nd) {
@@ -327,63 +408,74 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
       fnext = far_index(dxn, dyn, Dx, Dy, nr);
       rnext = ranks[fnext];
       fetch(farf + (size_t)fnext * fstride, 0, min(kRch, rnext));
-      fetch_x(dxn, dyn, xn);
     }
     const bool wave_active = wave_has_obs && !(ox_hi - dx < 0 || tx - dx > R.Lx - 1 || oy_hi - dy < 0 ||
                                                ty - dy > R.Ly - 1);
     const int jx = ix - dx, jy = iy - dy;
     const bool vj = vi && jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly;
     const int offj = vj ? state_at((int64_t)jy * R.Lx + jx) * n_a : 0;
+    Cx<S> xc[QS];
+    fetch_x(dx, dy, xc);
+    const Cx<S>* bu = lds_u + buf * kRch * n;
+    const Cx<S>* bv = lds_v + buf * kRch * n;
     if (wave_active) {
       switch (rc) {
-        case 1: far_slice<S, QS, 1>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-        case 2: far_slice<S, QS, 2>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-        case 3: far_slice<S, QS, 3>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-        case 4: far_slice<S, QS, 4>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-        case 5: far_slice<S, QS, 5>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-        case 6: far_slice<S, QS, 6>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-        case 7: far_slice<S, QS, 7>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-        default: far_slice<S, QS, 8>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 1: far_slice<S, QS, 1>(bu, bv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 2: far_slice<S, QS, 2>(bu, bv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 3: far_slice<S, QS, 3>(bu, bv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 4: far_slice<S, QS, 4>(bu, bv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 5: far_slice<S, QS, (5 < kRch ? 5 : kRch)>(bu, bv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 6: far_slice<S, QS, (6 < kRch ? 6 : kRch)>(bu, bv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        case 7: far_slice<S, QS, (7 < kRch ? 7 : kRch)>(bu, bv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+        default: far_slice<S, QS, kRch>(bu, bv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
       }
     }
-    // ranks above kRch: further slices, staged synchronously
+    // ranks above kRch: further slices through the other buffer, synchronously
     for (int rho0 = kRch; rho0 < r; rho0 += kRch) {
       const int rc2 = min(kRch, r - rho0);
+      const int ob = 1 - buf;
       __syncthreads();
       {
         const S* Uf = farf + (size_t)f * fstride;
         const S* us = Uf + (size_t)rho0 * n * 2;
         const S* vs = Uf + (size_t)max_rank * n * 2 + (size_t)rho0 * n * 2;
+        Cx<S>* du = lds_u + ob * kRch * n;
+        Cx<S>* dv = lds_v + ob * kRch * n;
         for (int e2 = 2 * tid; e2 < rc2 * n; e2 += 2 * blockDim.x) {
           Cx<S> a0, b0, a1, b1;
           load2<S>(us, e2, a0, b0);
           load2<S>(vs, e2, a1, b1);
-          lds_u[e2] = a0;
-          lds_u[e2 + 1] = b0;
-          lds_v[e2] = a1;
-          lds_v[e2 + 1] = b1;
+          du[e2] = a0;
+          du[e2 + 1] = b0;
+          dv[e2] = a1;
+          dv[e2 + 1] = b1;
         }
       }
       __syncthreads();
       if (wave_active) {
+        const Cx<S>* cu = lds_u + ob * kRch * n;
+        const Cx<S>* cv = lds_v + ob * kRch * n;
         switch (rc2) {
-          case 1: far_slice<S, QS, 1>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-          case 2: far_slice<S, QS, 2>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-          case 3: far_slice<S, QS, 3>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-          case 4: far_slice<S, QS, 4>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-          case 5: far_slice<S, QS, 5>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-          case 6: far_slice<S, QS, 6>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-          case 7: far_slice<S, QS, 7>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
-          default: far_slice<S, QS, 8>(lds_u, lds_v, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 1: far_slice<S, QS, 1>(cu, cv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 2: far_slice<S, QS, 2>(cu, cv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 3: far_slice<S, QS, 3>(cu, cv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 4: far_slice<S, QS, 4>(cu, cv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 5: far_slice<S, QS, (5 < kRch ? 5 : kRch)>(cu, cv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 6: far_slice<S, QS, (6 < kRch ? 6 : kRch)>(cu, cv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          case 7: far_slice<S, QS, (7 < kRch ? 7 : kRch)>(cu, cv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
+          default: far_slice<S, QS, kRch>(cu, cv, n, offi, offj, m0, vj, xc, acc_re, acc_im); break;
         }
       }
+      __syncthreads();
     }
+    // the other buffer receives the next slice; one barrier separates it from
+    // this displacement's readers
+    if (en < nd) stash(min(kRch, rnext), 1 - buf);
     __syncthreads();
+    buf = 1 - buf;
     e = en;
     f = fnext;
     r = rnext;
-#pragma unroll
-    for (int k = 0; k < QS; ++k) xc[k] = xn[k];
   }
   if (!vi) return;
   const size_t yb = (size_t)(R.unit_off + (int64_t)iy * R.Lx + ix) * n_a;
@@ -501,18 +593,22 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
   const int64_t tu = (int64_t)bd.total_units;
   if (far) {
     const int lds_state_cap = 16384;
-    const size_t lds = 2 * (size_t)kRch * Z->n * 2 * sizeof(S) + lds_state_cap;
-    auto kern = n_a == 40 ? far_kernel<S, 10> : far_kernel<S, 16>;
+    constexpr int rch = sizeof(S) == 4 ? 8 : 4;
+    const size_t lds = 4 * (size_t)rch * Z->n * 2 * sizeof(S) + lds_state_cap;
+    auto kern = n_a == 40 ? far_kernel<S, 10, rch> : far_kernel<S, 16, rch>;
     const int nwg = (bd.n_tiles * groups + kXcd - 1) / kXcd * kXcd;
     hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), lds, stream, bd.rhs, bd.tiles, groups, states,
                        (const S*)((const char*)Z->far + head), (const int*)Z->far, Z->max_rank, Z->Dx, Z->Dy,
                        Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles);
     R3M_CHECK_HIP(hipGetLastError());
   }
-  auto nk = n_a == 40 ? near_kernel<S, 10> : near_kernel<S, 16>;
   const int nwg_near = (bd.n_tiles * hg + kXcd - 1) / kXcd * kXcd;
-  hipLaunchKernelGGL(nk, dim3(nwg_near), dim3(256), 0, stream, bd.rhs, bd.tiles, states, (const S*)Z->near, Nx,
-                     Ny, Z->n, n_a, Z->n_states, xs, (S*)part, tu, groups, hg, bd.n_tiles);
+  // row-slab height: the whole state for complex64, half of it for complex128
+  constexpr int sr = sizeof(S) == 4 ? 40 : 20;
+  const size_t lds_near = ((size_t)sr * (Z->n + 2) + 2 * (size_t)kBU * n_a) * 2 * sizeof(S);
+  R3M_REQUIRE(n_a % sr == 0 && lds_near <= 160 * 1024, R3M_ERR_UNSUPPORTED, "near row slab does not fit in LDS");
+  hipLaunchKernelGGL((near_kernel<S, sr>), dim3(nwg_near), dim3(256), lds_near, stream, bd.rhs, bd.tiles, states,
+                     (const S*)Z->near, Nx, Ny, Z->n, n_a, Z->n_states, xs, (S*)part, tu, groups, hg, bd.n_tiles);
   R3M_CHECK_HIP(hipGetLastError());
   hipLaunchKernelGGL((reduce_groups_kernel<S, XT>), dim3(ceil_div((size_t)bd.max_units * n_a, 64), bd.B),
                      dim3(64), 0, stream, bd.rhs, (const S*)part, groups + hg, tu, n_a, y);
