@@ -184,6 +184,15 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
                          r3m_dtype vec_dtype, const void* x_dev, void* y_dev, void* work_dev,
                          size_t work_bytes, hipStream_t stream);
 
+/* Number of displacement groups the matvec splits the unique blocks into for
+ * this (store, batch) (a launch-shape choice; results do not depend on it
+ * beyond rounding order).  The first C128 r3m_retrieved_matvec or
+ * r3m_gmres_solve on a (store, batch) times a few candidates on the caller's
+ * stream and keeps the fastest in the context; before that the default is
+ * returned.  Returns the count (>= 1), 0 for an empty batch, or a negative
+ * r3m_status. */
+int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch);
+
 /* ---------------------------------------------------------------- GMRES -- */
 
 typedef enum {

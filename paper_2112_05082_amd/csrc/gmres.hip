@@ -16,6 +16,10 @@ namespace r3m {
 
 void validate_store(const r3m_store* Z);
 int choose_chunks(const BatchDesc& bd, int max_chunks);
+int max_groups(const BatchDesc& bd);
+int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd);
+int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
+                 void* y, void* partial, hipStream_t stream);
 size_t matvec_partial_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks);
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
                    r3m_dtype vec_dtype, const void* x, void* y, void* partial, int chunks,
@@ -687,6 +691,7 @@ struct GmresRun {
   int n_a, m, maxP, B;
   int n_states = 1;
   bool pre = false;
+  int G = 1;  // displacement groups of the matvec (autotuned)
   int64_t maxN, ut;
   Work W;
   hipStream_t s;
@@ -718,8 +723,7 @@ struct GmresRun {
   }
 
   void matvec(const r3m_store* Z, const double2* x, double2* y) {
-    const int chunks = choose_chunks(*bd, 64);
-    launch_matvec(ctx, Z, *bd, batch->states, R3M_C128, x, y, W.mv_partial, chunks, s);
+    launch_matvec(ctx, Z, *bd, batch->states, R3M_C128, x, y, W.mv_partial, plan_groups(ctx, Z, *bd), s);
   }
 
   void residual(const r3m_store* Z, const double2* rhs, const double2* sol, double2* out) {
@@ -749,7 +753,7 @@ struct GmresRun {
       hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs);
       xin = W.xs;
     }
-    launch_matvec_pre(Z, *bd, batch->states, xin, W.w, W.mv_partial, choose_chunks(*bd, 64), s);
+    launch_matvec_pre(Z, *bd, batch->states, xin, W.w, W.mv_partial, G, s);
   }
 
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
@@ -872,9 +876,8 @@ void validate_store(const r3m_store* Z);
 
 size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m) {
   const int n_a = Z->n / Z->n_states;
-  const int chunks = choose_chunks(bd, 64);
-  size_t mv = matvec_partial_bytes(bd, Z, chunks);
-  if (Z64) mv = std::max(mv, matvec_partial_bytes(bd, Z64, chunks));
+  size_t mv = matvec_partial_bytes(bd, Z, max_groups(bd));
+  if (Z64) mv = std::max(mv, matvec_partial_bytes(bd, Z64, max_groups(bd)));
   return layout_work(nullptr, bd, n_a, Z->n_states, m, mv).bytes;
 }
 
@@ -898,7 +901,7 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* ba
     // the largest number of near groups, complex128 partials, plus a vector copy
     const int n_a = Z->n / Z->n_states;
     const size_t vec = (size_t)bd.total_units * n_a * 16;
-    const size_t mv = (size_t)(choose_chunks(bd, 64) + 128) * vec + vec + 256;
+    const size_t mv = (size_t)(max_groups(bd) + 128) * vec + vec + 256;
     out = layout_work(nullptr, bd, n_a, Z->n_states, opts->restart, mv).bytes;
   });
   return rc == R3M_OK ? out : 0;
@@ -931,9 +934,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m);
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "GMRES workspace too small");
 
-    const int mv_chunks = choose_chunks(bd, 64);
-    size_t mv = matvec_partial_bytes(bd, Z, mv_chunks);
-    if (refine) mv = std::max(mv, matvec_partial_bytes(bd, Z64, mv_chunks));
+    size_t mv = matvec_partial_bytes(bd, Z, max_groups(bd));
+    if (refine) mv = std::max(mv, matvec_partial_bytes(bd, Z64, max_groups(bd)));
     // all work runs on the context stream, ordered after the caller's stream
     if (!ctx->work_stream) {
       R3M_CHECK_HIP(hipStreamCreateWithFlags(&ctx->work_stream, hipStreamNonBlocking));
@@ -956,7 +958,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     run.ctx = ctx;
     run.use_graph = !(opts->flags & R3M_GMRES_EAGER);
     run.graph_key = {(int64_t)(intptr_t)&bd, (int64_t)(intptr_t)batch->states, (int64_t)(intptr_t)work_dev,
-                     (int64_t)m, (int64_t)opts->precond, (int64_t)bd.B};
+                     (int64_t)m, (int64_t)opts->precond, (int64_t)bd.B, (int64_t)n_a};
     run.bd = &bd;
     run.batch = batch;
     run.n_a = n_a;
@@ -1008,6 +1010,16 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     }
     const double2* b = (const double2*)b_dev;
     double2* x = (double2*)x_dev;
+    // autotune the matvec's displacement groups on the right-hand side (before any capture)
+    {
+      const void* xin = b;
+      if (Z->near_dtype == R3M_C64) {
+        hipLaunchKernelGGL(convert_vec_kernel<float>, run.vgrid(), dim3(256), 0, stream, run.W.rv, b,
+                           (float*)run.W.xs);
+        xin = run.W.xs;
+      }
+      run.G = tuned_groups(ctx, Z, bd, batch->states, xin, run.W.w, run.W.mv_partial, stream);
+    }
     std::vector<double> bnorm = run.host_norms(b);
     hipLaunchKernelGGL(zero_kernel, run.vgrid(), dim3(256), 0, stream, x, run.W.rv);
     std::vector<int> iters(bd.B, 0), refine_steps(bd.B, 0);

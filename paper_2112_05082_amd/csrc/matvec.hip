@@ -535,20 +535,24 @@ convert_flat_kernel(const RhsDev* __restrict__ rhs, int n_a, const XT* __restric
 
 }  // namespace
 
-// displacement groups per 8x8 block: about 1024 workgroups for one launch
+// default displacement groups per 8x8 block: about 1024 workgroups per launch
 int choose_chunks(const BatchDesc& bd, int max_chunks) {
   int want = (int)std::max<int64_t>(1, (1024 + bd.n_tiles - 1) / std::max(1, bd.n_tiles));
   return std::max(1, std::min(want, max_chunks));
 }
 
-// near displacements per workgroup stay few: one each for a compressed store,
-// up to 128 groups when every block is dense
-static int near_groups(const r3m_store* Z) {
-  const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
-  return std::min((2 * Nx + 1) * (2 * Ny + 1), 128);
-}
+// largest group count the autotuner may try (the workspace is sized for it)
+int max_groups(const BatchDesc& bd) { return std::min(128, 4 * choose_chunks(bd, 64)); }
 
 static bool store_has_far(const r3m_store* Z) { return Z->near_radius < std::max(Z->Dx, Z->Dy); }
+
+// near displacement groups: one displacement per workgroup for small batches,
+// fewer groups (longer loops) when the batch already fills the chip
+static int near_groups(const r3m_store* Z, const BatchDesc& bd) {
+  const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
+  const int want = (int)std::max<int64_t>(1, (2048 + bd.n_tiles - 1) / std::max(1, bd.n_tiles));
+  return std::max(1, std::min({(2 * Nx + 1) * (2 * Ny + 1), 128, want}));
+}
 
 // workspace: partial sums [far groups + near groups][units][n_a] in the store
 // precision, plus a copy of x in the store precision when the vectors are wider
@@ -556,7 +560,7 @@ size_t matvec_partial_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks)
   const size_t es = Z->near_dtype == R3M_C128 ? 16 : 8;
   const int n_a = Z->n / Z->n_states;
   const size_t vec = (size_t)bd.total_units * n_a * es;
-  const int slots = (store_has_far(Z) ? std::max(chunks, 1) : 0) + near_groups(Z);
+  const int slots = (store_has_far(Z) ? std::max(chunks, 1) : 0) + near_groups(Z, bd);
   return (size_t)slots * vec + (Z->near_dtype == R3M_C128 ? 0 : vec) + 256;
 }
 
@@ -589,7 +593,7 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
   const int n_far = far ? r3m_far_count(Z->Dx, Z->Dy, Z->near_radius) : 0;
   const size_t head = ((size_t)n_far * 4 + 255) / 256 * 256;
   const int groups = far ? std::max(chunks, 1) : 0;
-  const int hg = near_groups(Z);
+  const int hg = near_groups(Z, bd);
   const int64_t tu = (int64_t)bd.total_units;
   if (far) {
     const int lds_state_cap = 16384;
@@ -621,12 +625,12 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
   const int n_a = Z->n / Z->n_states;
   const bool far = store_has_far(Z);
   const int groups = far ? std::max(chunks, 1) : 0;
-  const int hg = near_groups(Z);
+  const int hg = near_groups(Z, bd);
   const size_t vec = (size_t)bd.total_units * n_a * 2 * sizeof(S);
   char* part = (char*)partial;
   const S* xs = (const S*)x;
   if (!std::is_same<S, XT>::value) {
-    S* xc = (S*)(part + (size_t)(groups + hg) * vec);
+    S* xc = (S*)(part + (size_t)((far ? max_groups(bd) : 0) + hg) * vec);
     hipLaunchKernelGGL((convert_flat_kernel<S, XT>), dim3(ceil_div((size_t)bd.max_units * n_a, 256), bd.B),
                        dim3(256), 0, stream, bd.rhs, n_a, (const XT*)x, xc);
     xs = xc;
@@ -642,6 +646,51 @@ void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* s
     launch_core<double, double>(Z, bd, states, (const double*)xs, (double*)y, (char*)partial, chunks, stream);
   else
     launch_core<float, double>(Z, bd, states, (const float*)xs, (double*)y, (char*)partial, chunks, stream);
+}
+
+// Autotuner: the first time a (store, batch) pair is seen, time the matvec for
+// a few displacement-group counts around the default and keep the fastest.
+// xs is the input in the store precision, y a C128 output (overwritten).
+int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
+                 void* y, void* partial, hipStream_t stream) {
+  if (!store_has_far(Z)) return 1;
+  const std::vector<int64_t> key = {(int64_t)(intptr_t)Z->near, (int64_t)(intptr_t)Z->far, Z->near_dtype, Z->Dx,
+                                    Z->Dy, Z->near_radius, Z->max_rank, (int64_t)(intptr_t)&bd};
+  auto it = ctx->tuned_groups.find(key);
+  if (it != ctx->tuned_groups.end()) return it->second;
+  const int g0 = choose_chunks(bd, 64), gcap = max_groups(bd);
+  std::vector<int> cand;
+  for (int g = std::max(1, g0 / 4); g <= gcap; g *= 2) cand.push_back(g);
+  hipEvent_t e0, e1;
+  R3M_CHECK_HIP(hipEventCreate(&e0));
+  R3M_CHECK_HIP(hipEventCreate(&e1));
+  int best = g0;
+  float best_ms = 1e30f;
+  for (int g : cand) {
+    launch_matvec_pre(Z, bd, states, xs, y, partial, g, stream);  // warm
+    R3M_CHECK_HIP(hipEventRecord(e0, stream));
+    for (int rep = 0; rep < 2; ++rep) launch_matvec_pre(Z, bd, states, xs, y, partial, g, stream);
+    R3M_CHECK_HIP(hipEventRecord(e1, stream));
+    R3M_CHECK_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    R3M_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = g;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  ctx->tuned_groups[key] = best;
+  return best;
+}
+
+// displacement groups for (store, batch): the autotuned value when known
+int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd) {
+  const std::vector<int64_t> key = {(int64_t)(intptr_t)Z->near, (int64_t)(intptr_t)Z->far, Z->near_dtype, Z->Dx,
+                                    Z->Dy, Z->near_radius, Z->max_rank, (int64_t)(intptr_t)&bd};
+  auto it = ctx->tuned_groups.find(key);
+  return it != ctx->tuned_groups.end() ? it->second : choose_chunks(bd, 64);
 }
 
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
@@ -673,8 +722,7 @@ size_t r3m_matvec_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* b
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;
     const BatchDesc& bd = get_batch(ctx, batch, kBW, kBH, 0);
-    const int chunks = choose_chunks(bd, 64);
-    out = matvec_partial_bytes(bd, Z, chunks);
+    out = matvec_partial_bytes(bd, Z, max_groups(bd));
   });
   return rc == R3M_OK ? out : 0;
 }
@@ -692,12 +740,39 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
     R3M_REQUIRE(x_dev && y_dev, R3M_ERR_INVALID_ARG, "x or y is NULL");
     R3M_CHECK_HIP(hipSetDevice(ctx->device));
     const BatchDesc& bd = get_batch(ctx, batch, kBW, kBH, stream);
-    const int chunks = choose_chunks(bd, 64);
-    const size_t need = matvec_partial_bytes(bd, Z, chunks);
+    const size_t need = matvec_partial_bytes(bd, Z, max_groups(bd));
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "matvec workspace too small");
     R3M_REQUIRE(work_dev, R3M_ERR_INVALID_ARG, "work is NULL");
-    launch_matvec(ctx, Z, bd, batch->states, vec_dtype, x_dev, y_dev, work_dev, chunks, stream);
+    // first C128 call on this (store, batch): tune the group count on this x
+    // (the tuner writes y as C128, so C64 vectors take the tuned or default value)
+    if (vec_dtype == R3M_C128 && store_has_far(Z)) {
+      const void* xs = x_dev;
+      if (Z->near_dtype == R3M_C64) {
+        const int n_a = Z->n / Z->n_states;
+        const size_t vec = (size_t)bd.total_units * n_a * 2 * sizeof(float);
+        float* xc = (float*)((char*)work_dev + (size_t)(max_groups(bd) + near_groups(Z, bd)) * vec);
+        hipLaunchKernelGGL((convert_flat_kernel<float, double>),
+                           dim3(ceil_div((size_t)bd.max_units * n_a, 256), bd.B), dim3(256), 0, stream, bd.rhs,
+                           n_a, (const double*)x_dev, xc);
+        R3M_CHECK_HIP(hipGetLastError());
+        xs = xc;
+      }
+      tuned_groups(ctx, Z, bd, batch->states, xs, y_dev, work_dev, stream);
+    }
+    launch_matvec(ctx, Z, bd, batch->states, vec_dtype, x_dev, y_dev, work_dev, plan_groups(ctx, Z, bd), stream);
   });
 }
 
 }  // extern "C"
+
+extern "C" int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch) {
+  int32_t out = 0;
+  int rc = guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_store(Z);
+    validate_batch(batch, Z->Dx, Z->Dy);
+    if (batch->B == 0) return;
+    out = plan_groups(ctx, Z, get_batch(ctx, batch, kBW, kBH, 0));
+  });
+  return rc == R3M_OK ? out : rc;
+}

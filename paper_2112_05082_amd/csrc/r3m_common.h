@@ -101,6 +101,7 @@ struct r3m_ctx_s {
   hipStream_t work_stream = nullptr;  // default-priority stream for graph replays
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
+  std::map<std::vector<int64_t>, int> tuned_groups;  // autotuned displacement groups per (store, batch)
 };
 
 namespace r3m {

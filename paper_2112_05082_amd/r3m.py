@@ -30,7 +30,7 @@ EXPORTED = (
     "r3m_ctx_create", "r3m_ctx_destroy", "r3m_last_error", "r3m_version",
     "r3m_blocks_bytes", "r3m_fill_unique_blocks",
     "r3m_far_count", "r3m_far_bytes", "r3m_compress_work_bytes", "r3m_compress_far",
-    "r3m_matvec_work_bytes", "r3m_retrieved_matvec",
+    "r3m_matvec_work_bytes", "r3m_retrieved_matvec", "r3m_matvec_groups",
     "r3m_gmres_work_bytes", "r3m_gmres_solve",
     "r3m_plane_wave_rhs", "r3m_rcs",
 )
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
         "r3m_matvec_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int]),
         "r3m_retrieved_matvec": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int, vp, vp, vp,
                                            sz, vp]),
+        "r3m_matvec_groups": (i32, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
         "r3m_gmres_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.POINTER(GmresOptsC)]),
         "r3m_gmres_solve": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(StoreC), C.POINTER(BatchC), vp, vp,
                                       C.POINTER(GmresOptsC), C.POINTER(GmresReportC), vp, sz, vp]),
@@ -362,6 +363,14 @@ def compress_work_bytes(n, max_rank, per_batch):
 def matvec_work_bytes(ctx, store: Store, batch: Batch, vec_dtype):
     sc = store.c()
     return load().r3m_matvec_work_bytes(ctx.handle, C.byref(sc), C.byref(batch.cs), vec_dtype)
+
+
+def matvec_groups(ctx, store: Store, batch: Batch) -> int:
+    sc = store.c()
+    g = load().r3m_matvec_groups(ctx.handle, C.byref(sc), C.byref(batch.cs))
+    if g < 0:
+        _check(g, ctx.handle)
+    return g
 
 
 def gmres_work_bytes(ctx, store: Store, batch: Batch, restart: int):

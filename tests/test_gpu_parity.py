@@ -392,3 +392,21 @@ def test_graph_replays_match_eager(r3m, ctx, stores_2bit_8):
         run_matvec(r3m, ctx, s64, batch, b.to(torch.complex64), r3m.C64)
     x_e2, _ = run(True)
     assert np.array_equal(x_e2, x_e)
+
+
+def test_tuned_group_count(r3m, ctx, stores_2bit_8):
+    """The first C128 matvec on a (store, batch) tunes the displacement-group
+    count; the chosen count is within the workspace bound, later calls reuse
+    it (bitwise equal results), and the result stays at C64 accuracy."""
+    s128, s64, _ = stores_2bit_8
+    books = [cb.uniform(8, 4, 31), cb.uniform(8, 4, 32), cb.uniform(8, 4, 33)]
+    batch = batch_for(r3m, books, [8, 8, 8])
+    x = cb.random_complex(3 * 2560, 6)
+    y1 = run_matvec(r3m, ctx, s64, batch, to_dev(x), r3m.C128).cpu().numpy()
+    g = r3m.matvec_groups(ctx, s64, batch)
+    assert 1 <= g <= 128
+    y2 = run_matvec(r3m, ctx, s64, batch, to_dev(x), r3m.C128).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    assert r3m.matvec_groups(ctx, s64, batch) == g
+    y128 = run_matvec(r3m, ctx, s128, batch, to_dev(x), r3m.C128).cpu().numpy()
+    assert rel_max(y1, y128) <= 1e-6
