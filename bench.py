@@ -31,6 +31,13 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VALU_TFLOPS = 157.3
 RCS_TARGET = 1e-4
 
+# HBM bytes of one r3m_retrieved_matvec call on this workload (complex128
+# vectors), from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 summed over its
+# four launches, with the copy-kernel calibration; valid only for the launch
+# shape it was taken at (displacement groups) and the kernels as they were then.
+# Source: profiles/retrieved_matvec_2bit_32x32.md
+PROFILED_TRAFFIC = {"groups": 32, "bytes": 343140 * 1024}
+
 
 def parse():
     p = argparse.ArgumentParser()
@@ -189,6 +196,8 @@ def main():
     torch.cuda.synchronize()
     mv_s = e0.elapsed_time(e1) / 1e3 / args.matvec_reps
     byt, flops, mean_rank = algorithmic(store, L, n_a)
+    groups = r3m.matvec_groups(ctx, store, batch)
+    traffic = PROFILED_TRAFFIC["bytes"] if (L == 32 and groups == PROFILED_TRAFFIC["groups"]) else None
 
     # plain path matvec for context
     wbp = r3m.matvec_work_bytes(ctx, plain, batch, r3m.C128)
@@ -229,9 +238,10 @@ def main():
         "matvec_ms": mv_s * 1e3,
         "matvec_tflops": achieved_tf,
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": PEAK_FP32_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved_tf / PEAK_FP32_VALU_TFLOPS, "traffic": None,
-                     "kernel": "r3m_retrieved_matvec (convert_flat + far_kernel<float,10> + near_kernel<float,10> "
+                     "unit": "TFLOP/s", "frac": achieved_tf / PEAK_FP32_VALU_TFLOPS, "traffic": traffic,
+                     "kernel": "r3m_retrieved_matvec (convert_flat + far_kernel<float,10,8> + near_kernel<float,40> "
                                "+ reduce_groups_kernel launches, timed together)",
+                     "displacement_groups": groups,
                      "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": byt},
         "rcs_rel_err": max(errs),
         "gmres_iters": iters,

@@ -11,6 +11,7 @@
 // (unit, row) pairs.  The partial sums of the chunks are added in a fixed
 // order by a second kernel, so the result is bitwise reproducible (no float
 // atomics).
+#include <cstdlib>
 #include "r3m_common.h"
 
 #include <algorithm>
@@ -659,6 +660,13 @@ int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uin
   auto it = ctx->tuned_groups.find(key);
   if (it != ctx->tuned_groups.end()) return it->second;
   const int g0 = choose_chunks(bd, 64), gcap = max_groups(bd);
+  // R3M_MATVEC_GROUPS fixes the count instead (clamped to [1, gcap]); used to
+  // hold the launch shape constant across profiler runs
+  if (const char* env = std::getenv("R3M_MATVEC_GROUPS")) {
+    const int forced = std::max(1, std::min(gcap, std::atoi(env)));
+    ctx->tuned_groups[key] = forced;
+    return forced;
+  }
   std::vector<int> cand;
   for (int g = std::max(1, g0 / 4); g <= gcap; g *= 2) cand.push_back(g);
   hipEvent_t e0, e1;
@@ -674,7 +682,9 @@ int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uin
     R3M_CHECK_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
     R3M_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best_ms) {
+    // candidates come in increasing order; a larger count must win by 3% (keeps
+    // the choice stable between runs when two counts are within noise)
+    if (ms < 0.97f * best_ms) {
       best_ms = ms;
       best = g;
     }

@@ -1,0 +1,167 @@
+"""Full-size parity: the 2-bit 32 x 32 workload in the configuration the
+benchmark times (complex-FP32 near blocks, ACA far factors at tol 1e-4 in
+complex FP32, block-Jacobi GMRES(60) to 1e-5, 360-direction RCS).
+
+The oracle cannot form the 40,960-unknown system, so it computes the rows of
+Z_k that belong to three sampled observer units (two corners and one interior
+unit) directly from the physical mesh of the codebook (Sec. III-A, explicit
+retrieval), and the checks are made on those rows:
+  * plain store (all 3,969 blocks dense complex128): matvec rows within 1e-10
+    of the oracle rows times x;
+  * compressed complex-FP32 store: matvec rows within 1e-6 of the retrieval
+    definition applied to the same near blocks and far factors (the store is
+    the operator's input), and within the ACA tolerance (1e-4) of the oracle rows;
+  * solves: the plain FP64 GMRES solution satisfies the oracle rows to 1e-7
+    relative to the right-hand side rows, and the mixed solve's RCS is within
+    1e-4 of the plain solve's.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import K, FREQ, rel_l2, unit  # noqa: E402
+from oracle import efie, excitation, retrieval  # noqa: E402
+from workloads import codebooks as cb  # noqa: E402
+
+DEV = "cuda:0"
+L = 32
+OBS = (0, 517, 1023)
+N_A = 40
+
+
+@functools.lru_cache(None)
+def oracle_rows():
+    states = cb.uniform(L, 4, 1)
+    Zr = efie.direct_system(unit(2), states, L, K, 1, obs_units=list(OBS))
+    mesh, owner = efie.active_array_mesh(unit(2), states, L)
+    rows = np.concatenate([np.nonzero(owner == u)[0] for u in OBS])
+    b = excitation.plane_wave(mesh, K)
+    return states, Zr, b[rows]
+
+
+def sample(v):
+    v = np.asarray(v)
+    return np.concatenate([v[u * N_A:(u + 1) * N_A] for u in OBS])
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_05082_amd import pipeline, r3m
+    r3m.load()
+    ctx = r3m.Context(0)
+    geom = r3m.UnitGeom.from_macro(unit(2), FREQ, 1)
+    states = cb.uniform(L, 4, 1)
+    batch = r3m.Batch.from_codebooks([states], [L], DEV)
+    dense = pipeline.fill_blocks(ctx, geom, L - 1, r3m.C128, DEV)
+    store = pipeline.compressed_store(ctx, geom, L, 2, r3m.C64, r3m.C64, 1e-4, 40, DEV, dense_c128=dense)
+    plain = r3m.Store(160, 4, L - 1, L - 1, L - 1, r3m.C128, dense)
+    yield r3m, ctx, geom, states, batch, store, plain
+    ctx.close()
+
+
+def matvec(r3m, ctx, store, batch, x, dtype):
+    y = torch.zeros_like(x)
+    work = torch.empty(max(r3m.matvec_work_bytes(ctx, store, batch, dtype), 16), dtype=torch.uint8, device=DEV)
+    r3m.r3m_retrieved_matvec(ctx, store, batch, dtype, x, y, work)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def test_fullsize_plain_matvec_rows(setup):
+    r3m, ctx, _, states, batch, _, plain = setup
+    st, Zr, _ = oracle_rows()
+    assert np.array_equal(st, states)
+    x = cb.random_complex(L * L * N_A, 11)
+    y = matvec(r3m, ctx, plain, batch, torch.from_numpy(x).to(DEV), r3m.C128)
+    err = rel_l2(sample(y), Zr @ x)
+    print(f"plain c128 matvec rows vs oracle: {err:.3e}")
+    assert err <= 1e-10
+
+
+def store_rows(r3m, store, states, x):
+    """Rows of the sampled observer units from the store's own blocks: near
+    blocks as stored, far blocks as U V^H (retrieval definition, eq. (3))."""
+    from test_gpu_parity import far_factors
+    near = store.near.cpu().numpy().astype(np.complex128)
+    U, V = far_factors(r3m, store)
+    U = U.astype(np.complex128)
+    V = V.astype(np.complex128)
+    D, nr = L - 1, store.near_radius
+    fidx = {}
+    fi = 0
+    for dy in range(-D, D + 1):
+        for dx in range(-D, D + 1):
+            if max(abs(dx), abs(dy)) > nr:
+                fidx[(dx, dy)] = fi
+                fi += 1
+    s = states.reshape(-1)
+    xs = x.reshape(L * L, N_A)
+    out = []
+    for i in OBS:
+        ix, iy = i % L, i // L
+        ai = slice(s[i] * N_A, (s[i] + 1) * N_A)
+        acc = np.zeros(N_A, np.complex128)
+        for j in range(L * L):
+            jx, jy = j % L, j // L
+            dx, dy = ix - jx, iy - jy
+            aj = slice(s[j] * N_A, (s[j] + 1) * N_A)
+            if max(abs(dx), abs(dy)) <= nr:
+                blk = near[retrieval.slot(dx, dy, nr, nr)][ai, aj]
+                acc += blk @ xs[j]
+            else:
+                f = fidx[(dx, dy)]
+                acc += U[f][ai, :] @ (V[f][aj, :].conj().T @ xs[j])
+        out.append(acc)
+    return np.concatenate(out)
+
+
+def test_fullsize_compressed_matvec_rows(setup):
+    r3m, ctx, _, states, batch, store, _ = setup
+    _, Zr, _ = oracle_rows()
+    x = cb.random_complex(L * L * N_A, 12)
+    xd = torch.from_numpy(x).to(DEV)
+    y = matvec(r3m, ctx, store, batch, xd, r3m.C128)
+    ref = store_rows(r3m, store, states, x)
+    e_store = rel_l2(sample(y), ref)
+    e_oracle = rel_l2(sample(y), Zr @ x)
+    # complex64 vectors, as inside the mixed solve
+    y64 = matvec(r3m, ctx, store, batch, xd.to(torch.complex64), r3m.C64)
+    e64 = rel_l2(sample(y64), ref)
+    print(f"c64 store rows: vs store definition {e_store:.3e}, c64 vectors {e64:.3e}, vs oracle {e_oracle:.3e}")
+    assert e_store <= 1e-6 and e64 <= 1e-6
+    assert e_oracle <= 1e-4
+
+
+def test_fullsize_solves(setup):
+    r3m, ctx, geom, _, batch, store, plain = setup
+    _, Zr, b_rows = oracle_rows()
+    N = L * L * N_A
+    dirs = cb.phi0_cut(1.0)
+
+    def solve(st, tol, restart, precond):
+        b = torch.zeros(N, dtype=torch.complex128, device=DEV)
+        r3m.r3m_plane_wave_rhs(ctx, geom, batch, [[0.0, 0.0, 1.0]], b)
+        x = torch.zeros_like(b)
+        work = torch.empty(r3m.gmres_work_bytes(ctx, st, batch, restart), dtype=torch.uint8, device=DEV)
+        _, rep = r3m.r3m_gmres_solve(ctx, st, None, batch, b, x, tol, restart, 6000, work, precond=precond)
+        sig = torch.zeros(len(dirs), dtype=torch.float64, device=DEV)
+        r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
+        torch.cuda.synchronize()
+        return b.cpu().numpy(), x.cpu().numpy(), sig.cpu().numpy(), rep
+
+    b, x_ref, s_ref, rep_ref = solve(plain, 1e-10, 60, r3m.PRECOND_BLOCK_JACOBI)
+    assert rel_l2(sample(b), b_rows) <= 1e-12
+    res = rel_l2(Zr @ x_ref, b_rows)
+    print(f"plain solve: iters {rep_ref[0][0]}, oracle-row residual {res:.3e}")
+    assert rep_ref[0][3] and res <= 1e-7
+    _, _, s_mix, rep = solve(store, 1e-5, 60, r3m.PRECOND_BLOCK_JACOBI)
+    err = rel_l2(s_mix, s_ref)
+    print(f"mixed solve: iters {rep[0][0]}, RCS error vs plain {err:.3e}")
+    assert rep[0][3] and err <= 1e-4
