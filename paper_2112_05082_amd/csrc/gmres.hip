@@ -30,8 +30,10 @@ void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* s
 namespace {
 
 constexpr int kTW = 8, kTH = 8;  // unit block of the matvec workgroups
-constexpr int kDotChunk = 2048;
+constexpr int kDotChunk = 1024;
 constexpr int kDotThreads = 256;
+constexpr int kDotPer = kDotChunk / kDotThreads;  // elements per thread in a chunk
+constexpr int kDotVec = 4;                        // basis vectors per fused-dot block
 constexpr int kCheckEvery = 4;
 
 struct RhsVec {
@@ -139,85 +141,79 @@ __global__ void accumulate_h_kernel(double2* __restrict__ H, const double2* __re
   }
 }
 
-// V_{j+1} = w / ||w|| with ||w|| = H[j+1][j] as set before the rotation
-// (zeros for finished RHS or breakdown); the norm is kept in wn[b]
-__global__ void normalize_kernel(const double2* __restrict__ w, double2* __restrict__ V,
-                                 const RhsVec* __restrict__ rv, const RhsState* __restrict__ st,
-                                 const double* __restrict__ wn, int m, int j, int64_t ut) {
-  const int b = blockIdx.y;
-  const RhsVec r = rv[b];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= r.N) return;
-  const double nv = wn[b];
-  const bool ok = st[b].active && st[b].jdone < 0 && nv > 0.0;
-  double2 v = w[r.off + k];
-  V[(int64_t)(j + 1) * ut + r.off + k] = ok ? make_double2(v.x / nv, v.y / nv) : make_double2(0.0, 0.0);
-}
-
-// Givens update of column j of H for RHS b; convergence check
-__device__ void givens_update(int b, double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
-                              double2* __restrict__ sn, RhsState* __restrict__ st, int m, int j, double tol,
-                              int* __restrict__ n_running) {
+// Givens step on column j of H for RHS b, run by one whole block: the column
+// (with H[j+1][j] = hn) and the previous rotations are staged in LDS by all
+// threads, thread 0 applies the rotations in order, forms the new one, updates
+// g and the convergence state, and the block writes the column back.
+// lds: (m + 2) + m double2 and m double.  Every thread must call it.
+__device__ void givens_step_block(int b, double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
+                                  double2* __restrict__ sn, RhsState* __restrict__ st, int m, int j, double tol,
+                                  int* __restrict__ n_running, double hn, double2* lds) {
   RhsState s = st[b];
-  if (!s.active || s.jdone >= 0) return;
+  if (!s.active || s.jdone >= 0) return;  // uniform over the block
   double2* h = H + (size_t)b * (m + 1) * m;
   double* c = cs + (size_t)b * m;
   double2* sv = sn + (size_t)b * m;
   double2* gg = g + (size_t)b * (m + 1);
-  for (int i = 0; i < j; ++i) {
-    const double2 hi = h[i * m + j], hi1 = h[(i + 1) * m + j];
-    // [c s; -conj(s) c] [hi; hi1]
-    const double2 a = make_double2(c[i] * hi.x + (sv[i].x * hi1.x - sv[i].y * hi1.y),
-                                   c[i] * hi.y + (sv[i].x * hi1.y + sv[i].y * hi1.x));
-    const double2 bnew = make_double2(-(sv[i].x * hi.x + sv[i].y * hi.y) + c[i] * hi1.x,
-                                      -(sv[i].x * hi.y - sv[i].y * hi.x) + c[i] * hi1.y);
-    h[i * m + j] = a;
-    h[(i + 1) * m + j] = bnew;
+  double2* col = lds;
+  double2* ssv = lds + (m + 2);
+  double* cc = reinterpret_cast<double*>(ssv + m);
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h[i * m + j];
+  for (int i = threadIdx.x; i < j; i += blockDim.x) {
+    cc[i] = c[i];
+    ssv[i] = sv[i];
   }
-  const double2 a = h[j * m + j], bb = h[(j + 1) * m + j];
-  const double na = hypot(a.x, a.y), nb = hypot(bb.x, bb.y);
-  double cj;
-  double2 sj, rj;
-  if (nb == 0.0) {
-    cj = 1.0;
-    sj = make_double2(0.0, 0.0);
-    rj = a;
-  } else if (na == 0.0) {
-    cj = 0.0;
-    sj = make_double2(1.0, 0.0);
-    rj = bb;
-  } else {
-    const double nu = hypot(na, nb);
-    const double2 ph = make_double2(a.x / na, a.y / na);
-    cj = na / nu;
-    // s = ph * conj(b) / nu
-    sj = make_double2((ph.x * bb.x + ph.y * bb.y) / nu, (ph.y * bb.x - ph.x * bb.y) / nu);
-    rj = make_double2(ph.x * nu, ph.y * nu);
+  if (threadIdx.x == 0) col[j + 1] = make_double2(hn, 0.0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < j; ++i) {
+      const double2 hi = col[i], hi1 = col[i + 1];
+      const double ci = cc[i];
+      const double2 si = ssv[i];
+      // [c s; -conj(s) c] [hi; hi1]
+      col[i] = make_double2(ci * hi.x + (si.x * hi1.x - si.y * hi1.y), ci * hi.y + (si.x * hi1.y + si.y * hi1.x));
+      col[i + 1] = make_double2(-(si.x * hi.x + si.y * hi.y) + ci * hi1.x, -(si.x * hi.y - si.y * hi.x) + ci * hi1.y);
+    }
+    const double2 a = col[j], bb = col[j + 1];
+    const double na = hypot(a.x, a.y), nb = hypot(bb.x, bb.y);
+    double cj;
+    double2 sj, rj;
+    if (nb == 0.0) {
+      cj = 1.0;
+      sj = make_double2(0.0, 0.0);
+      rj = a;
+    } else if (na == 0.0) {
+      cj = 0.0;
+      sj = make_double2(1.0, 0.0);
+      rj = bb;
+    } else {
+      const double nu = hypot(na, nb);
+      const double2 ph = make_double2(a.x / na, a.y / na);
+      cj = na / nu;
+      // s = ph * conj(b) / nu
+      sj = make_double2((ph.x * bb.x + ph.y * bb.y) / nu, (ph.y * bb.x - ph.x * bb.y) / nu);
+      rj = make_double2(ph.x * nu, ph.y * nu);
+    }
+    c[j] = cj;
+    sv[j] = sj;
+    col[j] = rj;
+    col[j + 1] = make_double2(0.0, 0.0);
+    const double2 gj = gg[j];
+    // g[j+1] = -conj(s) g[j];  g[j] = c g[j]
+    const double2 gj1 = make_double2(-(sj.x * gj.x + sj.y * gj.y), -(sj.x * gj.y - sj.y * gj.x));
+    gg[j + 1] = gj1;
+    gg[j] = make_double2(cj * gj.x, cj * gj.y);
+    const double res = s.bnorm > 0.0 ? hypot(gj1.x, gj1.y) / s.bnorm : 0.0;
+    s.res = res;
+    if (!(res > tol) || nb == 0.0 || j == m - 1) {
+      s.jdone = j + 1;
+    } else {
+      atomicAdd(n_running, 1);
+    }
+    st[b] = s;
   }
-  c[j] = cj;
-  sv[j] = sj;
-  h[j * m + j] = rj;
-  h[(j + 1) * m + j] = make_double2(0.0, 0.0);
-  const double2 gj = gg[j];
-  // g[j+1] = -conj(s) g[j];  g[j] = c g[j]
-  gg[j + 1] = make_double2(-(sj.x * gj.x + sj.y * gj.y), -(sj.x * gj.y - sj.y * gj.x));
-  gg[j] = make_double2(cj * gj.x, cj * gj.y);
-  const double res = s.bnorm > 0.0 ? hypot(gg[j + 1].x, gg[j + 1].y) / s.bnorm : 0.0;
-  s.res = res;
-  if (!(res > tol) || nb == 0.0 || j == m - 1) {
-    s.jdone = j + 1;
-  } else {
-    atomicAdd(n_running, 1);
-  }
-  st[b] = s;
-}
-
-__global__ void givens_kernel(double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
-                              double2* __restrict__ sn, RhsState* __restrict__ st, int B, int m, int j,
-                              double tol, int* __restrict__ n_running) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  givens_update(b, H, g, cs, sn, st, m, j, tol, n_running);
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) h[i * m + j] = col[i];
 }
 
 // Sum of n partials by the 64 lanes of one wave: lane t adds entries t, t+64,
@@ -258,137 +254,226 @@ __device__ double2 block_sum2(double2 v, double2* sh) {
   return t;
 }
 
-// <A_i, B> for i < nvec with the final sum done by the last block of each
-// (RHS, i) in fixed chunk order.  mode 0: H[i][j] = s, 1: H[i][j] += s;
-// always hbuf[b][i] = s.
+// Chunk partials of <A_i, B> for i < nvec: partial[b][i][p].  Block
+// (p, grp, b) takes chunk p of RHS b against the kDotVec vectors of group
+// grp; B's chunk is loaded once and all loads are issued before the products.
+// The consumer kernel sums the partials itself (no grid-wide fence here).
 __global__ void __launch_bounds__(kDotThreads)
-dots_fused_kernel(const double2* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
-                  const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
-                  int* __restrict__ counters, double2* __restrict__ H, int m, int j, int mode,
-                  double2* __restrict__ hbuf, int* __restrict__ n_running) {
-  __shared__ double2 sh[kDotThreads / 64];
-  __shared__ int last;
-  const int p = blockIdx.x, i = blockIdx.y, b = blockIdx.z;
-  if (n_running && p == 0 && i == 0 && b == 0 && threadIdx.x == 0) *n_running = 0;
+dots_partials_kernel(const double2* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
+                     const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
+                     int* __restrict__ n_running) {
+  __shared__ double2 sh[kDotThreads / 64][kDotVec];
+  const int p = blockIdx.x, grp = blockIdx.y, b = blockIdx.z;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  if (n_running && p == 0 && grp == 0 && b == 0 && tid == 0) *n_running = 0;
   const RhsVec r = rv[b];
   const int64_t P = (r.N + kDotChunk - 1) / kDotChunk;
   if (p >= P) return;
-  const double2* a = A + (int64_t)i * a_stride + r.off;
+  const int i0 = grp * kDotVec;
+  const int nv = min(kDotVec, nvec - i0);
   const double2* bb = Bv + r.off;
-  const int64_t lo = (int64_t)p * kDotChunk, hi = min(r.N, lo + kDotChunk);
-  double2 acc = make_double2(0.0, 0.0);
-  for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-    const double2 t = cmulc(a[k], bb[k]);
-    acc.x += t.x;
-    acc.y += t.y;
+  const int64_t lo = (int64_t)p * kDotChunk + tid;
+  double2 wv[kDotPer];
+#pragma unroll
+  for (int e = 0; e < kDotPer; ++e) {
+    const int64_t k = lo + (int64_t)e * kDotThreads;
+    wv[e] = k < r.N ? bb[k] : make_double2(0.0, 0.0);
   }
-  const double2 t = block_sum2(acc, sh);
-  const size_t pi = ((size_t)b * nvec + i) * maxP;
-  if (threadIdx.x == 0) {
-    partial[pi + p] = t;
-    __threadfence();
-    last = atomicAdd(&counters[b * nvec + i], 1) == (int)P - 1;
+  double2 av[kDotVec][kDotPer];
+#pragma unroll
+  for (int q = 0; q < kDotVec; ++q) {
+    const double2* a = A + (int64_t)(i0 + min(q, nv - 1)) * a_stride + r.off;
+#pragma unroll
+    for (int e = 0; e < kDotPer; ++e) {
+      const int64_t k = lo + (int64_t)e * kDotThreads;
+      av[q][e] = k < r.N ? a[k] : make_double2(0.0, 0.0);
+    }
+  }
+  double2 acc[kDotVec];
+#pragma unroll
+  for (int q = 0; q < kDotVec; ++q) {
+    acc[q] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int e = 0; e < kDotPer; ++e) {
+      const double2 t = cmulc(av[q][e], wv[e]);
+      acc[q].x += t.x;
+      acc[q].y += t.y;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      acc[q].x += __shfl_xor(acc[q].x, o);
+      acc[q].y += __shfl_xor(acc[q].y, o);
+    }
+  }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int q = 0; q < kDotVec; ++q) sh[wave][q] = acc[q];
   }
   __syncthreads();
-  if (!last || threadIdx.x >= 64) return;
-  __threadfence();
-  const double2 sum = wave_sum_partials2(partial + pi, (int)P);
-  if (threadIdx.x != 0) return;
-  counters[b * nvec + i] = 0;
-  hbuf[(size_t)b * nvec + i] = sum;
-  double2* h = H + (size_t)b * (m + 1) * m + (size_t)i * m + j;
-  if (mode == 0) {
-    *h = sum;
-  } else {
-    h->x += sum.x;
-    h->y += sum.y;
+  if (tid < nv) {
+    double2 t = sh[0][tid];
+    for (int w = 1; w < kDotThreads / 64; ++w) {
+      t.x += sh[w][tid].x;
+      t.y += sh[w][tid].y;
+    }
+    partial[((size_t)b * nvec + i0 + tid) * maxP + p] = t;
   }
 }
 
-// w -= sum_{i<nvec} hbuf[i] V_i.  With do_norm, also ||w||^2 per block; the
-// last block of each RHS sets H[j+1][j] = ||w|| and applies the Givens step.
+// w -= sum_{i<nvec} h_i V_i with h_i the sum of the chunk partials of the
+// preceding dots_partials_kernel launch, taken by every block in the same
+// fixed order (block 0 also records them in H: mode 0 H[i][j] = h_i, mode 1
+// H[i][j] += h_i).  A block takes 64 elements; its four waves take the vectors
+// i = q mod 4 (q = wave) and their sums are added in wave order.  With
+// do_norm, each block also writes its part of ||w||^2 to npart[b][block].
+// Dynamic LDS: nvec double2.
 __global__ void __launch_bounds__(256)
-gs_update_fused_kernel(const double2* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
-                       RhsState* __restrict__ st, const double2* __restrict__ hbuf, int nvec, int64_t ut,
-                       int do_norm, double* __restrict__ npart, int* __restrict__ counters, int maxB,
-                       double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
-                       double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
-                       double* __restrict__ wn) {
+gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
+                 const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int nvec,
+                 int64_t ut, int do_norm, double* __restrict__ npart, int maxB, double2* __restrict__ H, int m,
+                 int j, int mode) {
+  extern __shared__ double2 hb[];
   __shared__ double2 sh[4];
-  __shared__ int last;
+  __shared__ double2 part[3][64];
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
-  const int64_t nb = (r.N + blockDim.x - 1) / blockDim.x;
+  const int64_t nb = (r.N + 63) / 64;
   if ((int64_t)blockIdx.x >= nb) return;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  double nrm2 = 0.0;
-  if (k < r.N && st[b].active) {
-    double2 acc = w[r.off + k];
-    const double2* hb = hbuf + (size_t)b * nvec;
+  const int P = (int)((r.N + kDotChunk - 1) / kDotChunk);
+  for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
+    const double2* pp = partial + ((size_t)b * nvec + i) * maxP;
+    double2 t = make_double2(0.0, 0.0);
+    for (int p = 0; p < P; ++p) {
+      const double2 v = pp[p];
+      t.x += v.x;
+      t.y += v.y;
+    }
+    hb[i] = t;
+    if (blockIdx.x == 0) {
+      double2* h = H + (size_t)b * (m + 1) * m + (size_t)i * m + j;
+      if (mode == 0) {
+        *h = t;
+      } else {
+        h->x += t.x;
+        h->y += t.y;
+      }
+    }
+  }
+  __syncthreads();
+  const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t k = (int64_t)blockIdx.x * 64 + e;
+  const bool live = k < r.N && st[b].active;
+  double2 acc = make_double2(0.0, 0.0);
+  if (live) {
     const double2* vk = V + r.off + k;
-    int i = 0;
-    for (; i + 4 <= nvec; i += 4) {
-      const double2 v0 = vk[(int64_t)i * ut], v1 = vk[(int64_t)(i + 1) * ut];
-      const double2 v2 = vk[(int64_t)(i + 2) * ut], v3 = vk[(int64_t)(i + 3) * ut];
-      const double2 t0 = cmul(hb[i], v0), t1 = cmul(hb[i + 1], v1);
-      const double2 t2 = cmul(hb[i + 2], v2), t3 = cmul(hb[i + 3], v3);
-      acc.x -= t0.x;
-      acc.y -= t0.y;
-      acc.x -= t1.x;
-      acc.y -= t1.y;
-      acc.x -= t2.x;
-      acc.y -= t2.y;
-      acc.x -= t3.x;
-      acc.y -= t3.y;
+    int i = q;
+    for (; i + 12 < nvec; i += 16) {
+      const double2 v0 = vk[(int64_t)i * ut], v1 = vk[(int64_t)(i + 4) * ut];
+      const double2 v2 = vk[(int64_t)(i + 8) * ut], v3 = vk[(int64_t)(i + 12) * ut];
+      const double2 t0 = cmul(hb[i], v0), t1 = cmul(hb[i + 4], v1);
+      const double2 t2 = cmul(hb[i + 8], v2), t3 = cmul(hb[i + 12], v3);
+      acc.x += t0.x;
+      acc.y += t0.y;
+      acc.x += t1.x;
+      acc.y += t1.y;
+      acc.x += t2.x;
+      acc.y += t2.y;
+      acc.x += t3.x;
+      acc.y += t3.y;
     }
-    for (; i < nvec; ++i) {
+    for (; i < nvec; i += 4) {
       const double2 t = cmul(hb[i], vk[(int64_t)i * ut]);
-      acc.x -= t.x;
-      acc.y -= t.y;
+      acc.x += t.x;
+      acc.y += t.y;
     }
-    w[r.off + k] = acc;
-    nrm2 = acc.x * acc.x + acc.y * acc.y;
+  }
+  if (q > 0) part[q - 1][e] = acc;
+  __syncthreads();
+  double nrm2 = 0.0;
+  if (q == 0 && live) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      acc.x += part[t][e].x;
+      acc.y += part[t][e].y;
+    }
+    double2 wk = w[r.off + k];
+    wk.x -= acc.x;
+    wk.y -= acc.y;
+    w[r.off + k] = wk;
+    nrm2 = wk.x * wk.x + wk.y * wk.y;
   }
   if (!do_norm) return;
   const double2 t = block_sum2(make_double2(nrm2, 0.0), sh);
-  if (threadIdx.x == 0) {
-    npart[(size_t)b * maxB + blockIdx.x] = t.x;
-    __threadfence();
-    last = atomicAdd(&counters[b], 1) == (int)nb - 1;
-  }
-  __syncthreads();
-  if (!last || threadIdx.x >= 64) return;
-  __threadfence();
-  const double sum = wave_sum_partials(npart + (size_t)b * maxB, (int)nb);
-  if (threadIdx.x != 0) return;
-  counters[b] = 0;
-  const double nv = sqrt(fmax(sum, 0.0));
-  wn[b] = nv;
-  H[(size_t)b * (m + 1) * m + (size_t)(j + 1) * m + j] = make_double2(nv, 0.0);
-  givens_update(b, H, g, cs, sn, st, m, j, tol, n_running);
+  if (threadIdx.x == 0) npart[(size_t)b * maxB + blockIdx.x] = t.x;
 }
 
-// y = R^{-1} g (upper triangular, size jdone), stored in place of g
-__global__ void backsolve_kernel(const double2* __restrict__ H, double2* __restrict__ g,
-                                 const RhsState* __restrict__ st, int B, int m) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
+// ||w|| from the per-block parts of the preceding gs_update_kernel (summed by
+// every block in the same fixed order); block 0 sets H[j+1][j] = ||w|| and
+// applies the Givens step; every block writes V_{j+1} = w / ||w|| (zeros for
+// a finished RHS or a breakdown).
+__global__ void __launch_bounds__(256)
+normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, const RhsVec* __restrict__ rv,
+                      RhsState* __restrict__ st, const double* __restrict__ npart, int maxB,
+                      double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
+                      double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
+                      double* __restrict__ wn, int64_t ut) {
+  __shared__ double nv_s;
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t nb = (r.N + 63) / 64;
+  if ((int64_t)blockIdx.x * blockDim.x >= r.N) return;
+  if (threadIdx.x < 64) {
+    const double sum = wave_sum_partials(npart + (size_t)b * maxB, (int)nb);
+    if (threadIdx.x == 0) nv_s = sqrt(fmax(sum, 0.0));
+  }
+  __syncthreads();
+  const double nv = nv_s;
+  // the running test reads only fields the Givens step below leaves alone or
+  // changes to a value with the same outcome (jdone: -1 -> j + 1)
+  const RhsState s0 = st[b];
+  const bool ok = s0.active && (s0.jdone < 0 || s0.jdone == j + 1) && nv > 0.0;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < r.N) {
+    const double2 v = w[r.off + k];
+    V[(int64_t)(j + 1) * ut + r.off + k] = ok ? make_double2(v.x / nv, v.y / nv) : make_double2(0.0, 0.0);
+  }
+  if (blockIdx.x == 0) {  // uniform over the block
+    if (threadIdx.x == 0) wn[b] = nv;
+    extern __shared__ double2 glds[];
+    givens_step_block(b, H, g, cs, sn, st, m, j, tol, n_running, nv, glds);
+  }
+}
+
+// y = R^{-1} g (upper triangular, size jdone), stored in place of g.  One
+// block per RHS, column-oriented: y_i = r_i / R_ii, then every lane k < i
+// updates its own r_k -= R_ki y_i (fixed order per entry).
+__global__ void __launch_bounds__(256)
+backsolve_kernel(const double2* __restrict__ H, double2* __restrict__ g, const RhsState* __restrict__ st, int m) {
+  __shared__ double2 yi_s;
+  const int b = blockIdx.x;
   const RhsState s = st[b];
   if (!s.active) return;
   const int J = s.jdone;
   const double2* h = H + (size_t)b * (m + 1) * m;
   double2* y = g + (size_t)b * (m + 1);
   for (int i = J - 1; i >= 0; --i) {
-    double2 acc = y[i];
-    for (int k = i + 1; k < J; ++k) {
-      double2 t = cmul(h[i * m + k], y[k]);
-      acc.x -= t.x;
-      acc.y -= t.y;
+    if (threadIdx.x == 0) {
+      const double2 acc = y[i];
+      const double2 d = h[i * m + i];
+      const double dd = d.x * d.x + d.y * d.y;
+      const double2 v = dd > 0.0 ? make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd)
+                                 : make_double2(0.0, 0.0);
+      y[i] = v;
+      yi_s = v;
     }
-    const double2 d = h[i * m + i];
-    const double dd = d.x * d.x + d.y * d.y;
-    y[i] = dd > 0.0 ? make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd)
-                    : make_double2(0.0, 0.0);
+    __syncthreads();
+    const double2 v = yi_s;
+    for (int k = threadIdx.x; k < i; k += blockDim.x) {
+      const double2 t = cmul(h[k * m + i], v);
+      y[k].x -= t.x;
+      y[k].y -= t.y;
+    }
+    __syncthreads();
   }
 }
 
@@ -620,7 +705,6 @@ struct Work {
   double2* Minv;
   double* wn;
   double* npart;
-  int* cnt;
   void* mv_partial;
   double2* H;
   double2* g;
@@ -661,7 +745,6 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, 
   w.xs = (double2*)take(ut * 16);
   w.wn = (double*)take((size_t)B * 8);
   w.npart = (double*)take((size_t)B * ((maxN + 63) / 64 + 1) * 8);
-  w.cnt = (int*)take((size_t)B * (m + 2) * 4);
   w.Minv = (double2*)take((size_t)n_states * n_a * n_a * 16);
   w.mv_partial = take(mv_bytes);
   w.H = (double2*)take((size_t)B * (m + 1) * m * 16);
@@ -758,18 +841,18 @@ struct GmresRun {
 
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
     apply_operator(Z, W.V + (int64_t)j * ut);
-    const dim3 dgrid(maxP, j + 1, B);
-    int* dcnt = W.cnt;
-    int* ncnt = W.cnt + (size_t)B * (m + 1);
+    const dim3 dgrid(maxP, (j + 1 + kDotVec - 1) / kDotVec, B);
     const int maxB = (int)((maxN + 63) / 64 + 1);
     for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(dots_fused_kernel, dgrid, dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, j + 1, maxP,
-                         W.dpart, dcnt, W.H, m, j, pass, W.hbuf, pass == 0 ? W.counters : (int*)nullptr);
-      hipLaunchKernelGGL(gs_update_fused_kernel, dim3(ceil_div((size_t)maxN, 64), B), dim3(64), 0, s, W.V, W.w,
-                         W.rv, W.st, W.hbuf, j + 1, ut, pass, W.npart, ncnt, maxB, W.H, W.g, W.cs, W.sn, m, j, tol,
-                         W.counters, W.wn);
+      hipLaunchKernelGGL(dots_partials_kernel, dgrid, dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, j + 1, maxP,
+                         W.dpart, pass == 0 ? W.counters : (int*)nullptr);
+      hipLaunchKernelGGL(gs_update_kernel, dim3(ceil_div((size_t)maxN, 64), B), dim3(256),
+                         (size_t)(j + 1) * sizeof(double2), s, W.V, W.w, W.rv, W.st, W.dpart, maxP, j + 1, ut, pass,
+                         W.npart, maxB, W.H, m, j, pass);
     }
-    hipLaunchKernelGGL(normalize_kernel, vgrid(), dim3(256), 0, s, W.w, W.V, W.rv, W.st, W.wn, m, j, ut);
+    hipLaunchKernelGGL(normalize_step_kernel, vgrid(), dim3(256), (size_t)(2 * m + 2) * 16 + (size_t)m * 8, s, W.w,
+                       W.V, W.rv, W.st, W.npart, maxB, W.H,
+                       W.g, W.cs, W.sn, m, j, tol, W.counters, W.wn, ut);
     R3M_CHECK_HIP(hipGetLastError());
   }
 
@@ -784,6 +867,14 @@ struct GmresRun {
     key.push_back((int64_t)(intptr_t)Z->near);
     key.push_back((int64_t)(intptr_t)Z->far);
     key.push_back(Z->near_dtype);
+    key.push_back(Z->far_dtype);
+    key.push_back(Z->n);
+    key.push_back(Z->n_states);
+    key.push_back(Z->Dx);
+    key.push_back(Z->Dy);
+    key.push_back(Z->near_radius);
+    key.push_back(Z->max_rank);
+    key.push_back(G);
     key.push_back(j0);
     key.push_back(j1);
     int64_t tb;
@@ -848,7 +939,7 @@ struct GmresRun {
         }
       }
       hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.st, B, j);
-      hipLaunchKernelGGL(backsolve_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.H, W.g, W.st, B, m);
+      hipLaunchKernelGGL(backsolve_kernel, dim3(B), dim3(256), 0, s, W.H, W.g, W.st, m);
       if (pre) {
         // x += M^{-1} (V y)
         hipLaunchKernelGGL(combine_basis_kernel, vgrid(), dim3(256), 0, s, W.V, W.g, W.pz, W.rv, W.st, m, ut);
@@ -979,7 +1070,6 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     R3M_CHECK_HIP(hipMemcpyAsync(run.W.rv, rv.data(), rv.size() * sizeof(RhsVec), hipMemcpyHostToDevice, stream));
     R3M_CHECK_HIP(hipMemcpyAsync(run.W.soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice, stream));
     R3M_CHECK_HIP(hipMemsetAsync(run.W.counters, 0, 256, stream));
-    R3M_CHECK_HIP(hipMemsetAsync(run.W.cnt, 0, (size_t)bd.B * (m + 2) * 4, stream));
 
     // input checks on the device: state bytes and finite right-hand sides
     const int64_t maxU = run.maxN / n_a;

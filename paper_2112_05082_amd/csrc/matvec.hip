@@ -649,14 +649,18 @@ void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* s
     launch_core<float, double>(Z, bd, states, (const float*)xs, (double*)y, (char*)partial, chunks, stream);
 }
 
+static std::vector<int64_t> tune_key(const r3m_store* Z, const BatchDesc& bd) {
+  return {(int64_t)(intptr_t)Z->near, (int64_t)(intptr_t)Z->far, Z->near_dtype, Z->far_dtype, Z->n, Z->n_states,
+          Z->Dx, Z->Dy, Z->near_radius, Z->max_rank, (int64_t)(intptr_t)&bd};
+}
+
 // Autotuner: the first time a (store, batch) pair is seen, time the matvec for
 // a few displacement-group counts around the default and keep the fastest.
 // xs is the input in the store precision, y a C128 output (overwritten).
 int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
                  void* y, void* partial, hipStream_t stream) {
   if (!store_has_far(Z)) return 1;
-  const std::vector<int64_t> key = {(int64_t)(intptr_t)Z->near, (int64_t)(intptr_t)Z->far, Z->near_dtype, Z->Dx,
-                                    Z->Dy, Z->near_radius, Z->max_rank, (int64_t)(intptr_t)&bd};
+  const std::vector<int64_t> key = tune_key(Z, bd);
   auto it = ctx->tuned_groups.find(key);
   if (it != ctx->tuned_groups.end()) return it->second;
   const int g0 = choose_chunks(bd, 64), gcap = max_groups(bd);
@@ -697,8 +701,7 @@ int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uin
 
 // displacement groups for (store, batch): the autotuned value when known
 int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd) {
-  const std::vector<int64_t> key = {(int64_t)(intptr_t)Z->near, (int64_t)(intptr_t)Z->far, Z->near_dtype, Z->Dx,
-                                    Z->Dy, Z->near_radius, Z->max_rank, (int64_t)(intptr_t)&bd};
+  const std::vector<int64_t> key = tune_key(Z, bd);
   auto it = ctx->tuned_groups.find(key);
   return it != ctx->tuned_groups.end() ? it->second : choose_chunks(bd, 64);
 }
