@@ -160,13 +160,19 @@ typedef struct {
  * L[2b] x L[2b+1] array (Lx, Ly <= Dx+1, Dy+1) whose codebook is
  * states[state_off[b] ...] (uint8, device, one byte per unit, < n_states),
  * and whose reduced vectors start at unit unit_off[b] of x/y.  Several RHS
- * may share one codebook (e.g. several incidence angles). */
+ * may share one codebook (e.g. several incidence angles).
+ * flags: R3M_BATCH_INDEX_READY tells r3m_retrieved_matvec that the retrieval
+ * index inside its workspace is current (built by an earlier call with the
+ * same store, batch shape, codebook bytes and workspace), so the call skips
+ * rebuilding it; with 0 every call rebuilds it. */
+#define R3M_BATCH_INDEX_READY 1u
 typedef struct {
   int32_t B;
   const int32_t* L;         /* host [B][2] */
   const int64_t* unit_off;  /* host [B] */
   const int64_t* state_off; /* host [B] */
   const uint8_t* states;    /* device */
+  uint32_t flags;           /* R3M_BATCH_* */
 } r3m_batch;
 
 /* -------------------------------------------------------------- matvec -- */

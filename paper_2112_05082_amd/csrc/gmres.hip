@@ -8,24 +8,11 @@
 // Gram-Schmidt with two reductions instead of j+1).  Reductions are two-stage
 // with fixed order (bitwise reproducible).  Convergence flags live on the
 // device and are read by the host once every few iterations.
-#include "r3m_common.h"
+#include "matvec_internal.h"
 
 #include <algorithm>
 
 namespace r3m {
-
-void validate_store(const r3m_store* Z);
-int choose_chunks(const BatchDesc& bd, int max_chunks);
-int max_groups(const BatchDesc& bd);
-int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd);
-int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
-                 void* y, void* partial, hipStream_t stream);
-size_t matvec_partial_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks);
-void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
-                   r3m_dtype vec_dtype, const void* x, void* y, void* partial, int chunks,
-                   hipStream_t stream);
-void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
-                       void* partial, int chunks, hipStream_t stream);
 
 namespace {
 
@@ -706,6 +693,8 @@ struct Work {
   double* wn;
   double* npart;
   void* mv_partial;
+  void* lists;    // near retrieval lists of the solve's store
+  void* lists64;  // and of the refinement store
   double2* H;
   double2* g;
   double* cs;
@@ -722,7 +711,8 @@ struct Work {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, size_t mv_bytes) {
+Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, size_t mv_bytes,
+                 size_t lists_bytes, size_t lists64_bytes) {
   Work w{};
   const int B = bd.B;
   int64_t maxN = 0;
@@ -747,6 +737,8 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, 
   w.npart = (double*)take((size_t)B * ((maxN + 63) / 64 + 1) * 8);
   w.Minv = (double2*)take((size_t)n_states * n_a * n_a * 16);
   w.mv_partial = take(mv_bytes);
+  w.lists = take(lists_bytes);
+  w.lists64 = take(lists64_bytes);
   w.H = (double2*)take((size_t)B * (m + 1) * m * 16);
   w.g = (double2*)take((size_t)B * (m + 1) * 16);
   w.cs = (double*)take((size_t)B * m * 8);
@@ -805,8 +797,12 @@ struct GmresRun {
     return out;
   }
 
+  const r3m_store* Zsolve = nullptr;
+  const void* lists_for(const r3m_store* Z) const { return Z == Zsolve ? W.lists : W.lists64; }
+
   void matvec(const r3m_store* Z, const double2* x, double2* y) {
-    launch_matvec(ctx, Z, *bd, batch->states, R3M_C128, x, y, W.mv_partial, plan_groups(ctx, Z, *bd), s);
+    launch_matvec(ctx, Z, *bd, batch->states, R3M_C128, x, y, W.mv_partial, lists_for(Z), plan_groups(ctx, Z, *bd),
+                  s);
   }
 
   void residual(const r3m_store* Z, const double2* rhs, const double2* sol, double2* out) {
@@ -836,7 +832,7 @@ struct GmresRun {
       hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs);
       xin = W.xs;
     }
-    launch_matvec_pre(Z, *bd, batch->states, xin, W.w, W.mv_partial, G, s);
+    launch_matvec_pre(Z, *bd, batch->states, xin, W.w, W.mv_partial, lists_for(Z), G, s);
   }
 
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
@@ -963,13 +959,12 @@ struct GmresRun {
   }
 };
 
-void validate_store(const r3m_store* Z);
-
 size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m) {
   const int n_a = Z->n / Z->n_states;
-  size_t mv = matvec_partial_bytes(bd, Z, max_groups(bd));
-  if (Z64) mv = std::max(mv, matvec_partial_bytes(bd, Z64, max_groups(bd)));
-  return layout_work(nullptr, bd, n_a, Z->n_states, m, mv).bytes;
+  size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
+  if (Z64) mv = std::max(mv, partials_and_x_bytes(bd, Z64, max_groups(bd)));
+  return layout_work(nullptr, bd, n_a, Z->n_states, m, mv, near_lists_bytes(Z, bd),
+                     Z64 ? near_lists_bytes(Z64, bd) : 0).bytes;
 }
 
 }  // namespace r3m
@@ -992,8 +987,10 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* ba
     // the largest number of near groups, complex128 partials, plus a vector copy
     const int n_a = Z->n / Z->n_states;
     const size_t vec = (size_t)bd.total_units * n_a * 16;
-    const size_t mv = (size_t)(max_groups(bd) + 128) * vec + vec + 256;
-    out = layout_work(nullptr, bd, n_a, Z->n_states, opts->restart, mv).bytes;
+    const size_t mv = std::max(partials_and_x_bytes(bd, Z, max_groups(bd)),
+                               (size_t)(max_groups(bd) + 128) * vec + vec + 256);
+    out = layout_work(nullptr, bd, n_a, Z->n_states, opts->restart, mv, near_lists_bytes(Z, bd),
+                      near_lists_bytes_bound(Z->n_states, bd)).bytes;
   });
   return rc == R3M_OK ? out : 0;
 }
@@ -1025,8 +1022,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m);
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "GMRES workspace too small");
 
-    size_t mv = matvec_partial_bytes(bd, Z, max_groups(bd));
-    if (refine) mv = std::max(mv, matvec_partial_bytes(bd, Z64, max_groups(bd)));
+    size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
+    if (refine) mv = std::max(mv, partials_and_x_bytes(bd, Z64, max_groups(bd)));
     // all work runs on the context stream, ordered after the caller's stream
     if (!ctx->work_stream) {
       R3M_CHECK_HIP(hipStreamCreateWithFlags(&ctx->work_stream, hipStreamNonBlocking));
@@ -1056,7 +1053,9 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     run.m = m;
     run.B = bd.B;
     run.s = stream;
-    run.W = layout_work((char*)work_dev, bd, n_a, Z->n_states, m, mv);
+    run.W = layout_work((char*)work_dev, bd, n_a, Z->n_states, m, mv, near_lists_bytes(Z, bd),
+                        refine ? near_lists_bytes(Z64, bd) : 0);
+    run.Zsolve = Z;
     run.ut = (int64_t)bd.total_units * n_a;
     run.maxN = 0;
     std::vector<RhsVec> rv(bd.B);
@@ -1100,6 +1099,9 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     }
     const double2* b = (const double2*)b_dev;
     double2* x = (double2*)x_dev;
+    // near retrieval lists of this codebook (fixed for the whole solve)
+    build_near_lists(Z, bd, batch->states, run.W.lists, stream);
+    if (refine) build_near_lists(Z64, bd, batch->states, run.W.lists64, stream);
     // autotune the matvec's displacement groups on the right-hand side (before any capture)
     {
       const void* xin = b;
@@ -1108,7 +1110,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
                            (float*)run.W.xs);
         xin = run.W.xs;
       }
-      run.G = tuned_groups(ctx, Z, bd, batch->states, xin, run.W.w, run.W.mv_partial, stream);
+      run.G = tuned_groups(ctx, Z, bd, batch->states, xin, run.W.w, run.W.mv_partial, run.W.lists, stream);
     }
     std::vector<double> bnorm = run.host_norms(b);
     hipLaunchKernelGGL(zero_kernel, run.vgrid(), dim3(256), 0, stream, x, run.W.rv);

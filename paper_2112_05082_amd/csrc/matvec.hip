@@ -12,7 +12,7 @@
 // order by a second kernel, so the result is bitwise reproducible (no float
 // atomics).
 #include <cstdlib>
-#include "r3m_common.h"
+#include "matvec_internal.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -286,6 +286,9 @@ near_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, c
 // (unit u, quarter q) forms its quarter of t = V[A(s_j)]^H x_j, the unit's
 // four lanes add their parts with two lane swaps, and the lane expands its own
 // rows y += U[A(s_i)] t.  Ranks above kRch take extra synchronous slices.
+#ifndef R3M_FAR_RCH_F32
+#define R3M_FAR_RCH_F32 8
+#endif
 #ifndef R3M_FAR_WAVES_PER_EU
 #define R3M_FAR_WAVES_PER_EU 2
 #endif
@@ -523,6 +526,227 @@ reduce_groups_kernel(const RhsDev* __restrict__ rhs, const S* __restrict__ parti
   y[2 * e + 1] = (XT)im;
 }
 
+// ---------------------------------------------------------------- near field
+// on the matrix cores.
+//
+// Retrieval lists (built per batch and codebook, reused by every matvec):
+// each (observer unit i, near displacement slot d) falls in one class
+// c = (d * S + s_i) * (S + 1) + s_j, where s_j is the state of the source
+// unit j = i - d, or S when j is outside the array.  Within a class every pair
+// is multiplied by the same sub-block Z(d)[A(s_i), A(s_j)], so a class is a
+// dense complex GEMM: Y[:, cols] = Z(d)[A(a), A(b)] X[:, cols] (eq. (3) with
+// the columns of one state pair gathered).  Classes are cut into items of
+// kNearCols pairs; an item's result goes to the partial slot of d, one write per
+// (unit, d), so the order of pairs in a list does not change any result.
+
+constexpr int kNearCols = 64;  // pairs per item: 4 waves x 16 MFMA columns
+
+struct NearItem {
+  int32_t cls, start, len, pad;
+};
+struct NearPair {
+  int32_t tgt, src;  // global unit indices (src = -1: no source)
+};
+
+__global__ void __launch_bounds__(256) zero_ints_kernel(int* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Block (slot d, chunk of 256 observer units, RHS): the classes of its pairs
+// are counted in LDS first, then one global atomic per class present.
+// pass 0: class counts; pass 1: pair placement at offsets[c] + cursor[c] + rank.
+// Dynamic LDS: 2 S (S + 1) ints.
+__global__ void __launch_bounds__(256)
+near_classify_kernel(const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, int n_states, int Nx,
+                     int Ny, int chunks, int* __restrict__ counts, int* __restrict__ cursor,
+                     const int* __restrict__ offsets, NearPair* __restrict__ pairs, int pass) {
+  extern __shared__ int cl_lds[];
+  const int S = n_states, SS = S * (S + 1);
+  int* local = cl_lds;       // per-class count in this block
+  int* base = cl_lds + SS;   // global base of this block's pairs per class
+  const RhsDev R = rhs[blockIdx.y];
+  const int slot = blockIdx.x / chunks;
+  const int64_t u = (int64_t)(blockIdx.x % chunks) * blockDim.x + threadIdx.x;
+  for (int c = threadIdx.x; c < SS; c += blockDim.x) local[c] = 0;
+  __syncthreads();
+  const bool live = u < (int64_t)R.Lx * R.Ly;
+  int lc = 0, rank = 0, tgt = 0, src = -1;
+  if (live) {
+    const int ix = (int)(u % R.Lx), iy = (int)(u / R.Lx);
+    const int dx = slot % (2 * Nx + 1) - Nx, dy = slot / (2 * Nx + 1) - Ny;
+    const int jx = ix - dx, jy = iy - dy;
+    const bool valid = jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly;
+    const int64_t j = (int64_t)jy * R.Lx + jx;
+    const int a = min((int)states[R.state_off + u], S - 1);
+    const int bs = valid ? min((int)states[R.state_off + j], S - 1) : S;
+    lc = a * (S + 1) + bs;
+    rank = atomicAdd(&local[lc], 1);
+    tgt = (int)(R.unit_off + u);
+    src = valid ? (int)(R.unit_off + j) : -1;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < SS; c += blockDim.x) {
+    const int k = local[c];
+    if (k > 0) base[c] = atomicAdd(pass == 0 ? &counts[slot * SS + c] : &cursor[slot * SS + c], k);
+  }
+  if (pass == 0) return;
+  __syncthreads();
+  if (live) pairs[offsets[slot * SS + lc] + base[lc] + rank] = NearPair{tgt, src};
+}
+
+// One block: exclusive scans of the class counts (pairs and items), the item
+// table, and cleared cursors.
+__global__ void __launch_bounds__(1024)
+near_scan_kernel(const int* __restrict__ counts, int n_cls, int* __restrict__ offsets, int* __restrict__ cursor,
+                 NearItem* __restrict__ items, int* __restrict__ n_items) {
+  __shared__ int sp[1024], si[1024];
+  const int tid = threadIdx.x;
+  const int per = (n_cls + 1023) / 1024;
+  const int c0 = min(n_cls, tid * per), c1 = min(n_cls, c0 + per);
+  int np = 0, ni = 0;
+  for (int c = c0; c < c1; ++c) {
+    np += counts[c];
+    ni += (counts[c] + kNearCols - 1) / kNearCols;
+  }
+  sp[tid] = np;
+  si[tid] = ni;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int vp = tid >= o ? sp[tid - o] : 0, vi = tid >= o ? si[tid - o] : 0;
+    __syncthreads();
+    sp[tid] += vp;
+    si[tid] += vi;
+    __syncthreads();
+  }
+  int po = sp[tid] - np, io = si[tid] - ni;
+  for (int c = c0; c < c1; ++c) {
+    const int cnt = counts[c];
+    offsets[c] = po;
+    cursor[c] = 0;
+    for (int k = 0; k * kNearCols < cnt; ++k)
+      items[io++] = NearItem{c, po + k * kNearCols, min(kNearCols, cnt - k * kNearCols), 0};
+    po += cnt;
+  }
+  if (tid == 1023) *n_items = si[1023];
+}
+
+template <typename S>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // row of the 16 x 16 result held in register r of lane l
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+template <>
+struct MfmaAcc<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int l, int r) { return 4 * r + (l >> 4); }
+};
+
+// One item per workgroup.  Complex GEMM in real form: row 2m + c of Y' is
+// the c-th real component of row m, column 2k + c' of Z' multiplies component
+// c' of x[k], so Z' holds [[Re, -Im], [Im, Re]] blocks and Y' = Z' X' is a
+// real (2 NA) x (2 NA) x 16 product per wave on 16x16x4 MFMA tiles (lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]).  Dynamic LDS: Z' as
+// [2 NA][2 NA + 1] reals, then the gathered columns [kNearCols][2 NA + 1].
+template <typename S, int NA>
+__global__ void __launch_bounds__(256)
+near_mfma_kernel(const NearItem* __restrict__ items, const int* __restrict__ n_items,
+                 const NearPair* __restrict__ pairs, const S* __restrict__ near, int n, int n_states,
+                 const S* __restrict__ x, S* __restrict__ out, int64_t total_units) {
+  constexpr int K2 = 2 * NA, MT = K2 / 16, KT = K2 / 4, XS = K2 + 1;
+  constexpr int KC = 4;  // K steps whose operands are read before their MFMAs
+  static_assert(KT % KC == 0, "K steps per chunk");
+  extern __shared__ unsigned char smem_raw[];
+  S* a_lds = reinterpret_cast<S*>(smem_raw);  // Z' [K2][XS]
+  S* x_lds = a_lds + (size_t)K2 * XS;         // X' [kNearCols][XS]
+  __shared__ int tgt_s[kNearCols], src_s[kNearCols];
+  if ((int)blockIdx.x >= *n_items) return;
+  const NearItem item = items[blockIdx.x];
+  const int S1 = n_states + 1;
+  const int bsrc = item.cls % S1, a = (item.cls / S1) % n_states, slot = item.cls / (S1 * n_states);
+  const int tid = threadIdx.x;
+  if (tid < kNearCols) {
+    const NearPair pr = tid < item.len ? pairs[item.start + tid] : NearPair{-1, -1};
+    tgt_s[tid] = pr.tgt;
+    src_s[tid] = pr.src;
+  }
+  __syncthreads();
+  S* dst = out + (size_t)slot * total_units * K2;
+  if (bsrc == n_states) {  // no source at this displacement: the slot holds zero
+    for (int e = tid; e < item.len * K2; e += blockDim.x) dst[(size_t)tgt_s[e / K2] * K2 + e % K2] = S(0);
+    return;
+  }
+  // sub-block and gathered columns: every load is issued before the LDS stores
+  const Cx<S>* zb = reinterpret_cast<const Cx<S>*>(near) + (size_t)slot * n * n;
+  constexpr int kZ = (NA * NA + 255) / 256, kX = kNearCols * NA / 256;
+  Cx<S> zv[kZ], xv[kX];
+#pragma unroll
+  for (int q = 0; q < kZ; ++q) {
+    const int e = tid + q * 256;
+    if (e < NA * NA) zv[q] = zb[(size_t)(a * NA + e / NA) * n + bsrc * NA + e % NA];
+  }
+#pragma unroll
+  for (int q = 0; q < kX; ++q) {
+    const int e = tid + q * 256;
+    const int c = e / NA, src = src_s[c];
+    xv[q] = src >= 0 ? reinterpret_cast<const Cx<S>*>(x)[(size_t)src * NA + e % NA] : Cx<S>{0, 0};
+  }
+#pragma unroll
+  for (int q = 0; q < kZ; ++q) {
+    const int e = tid + q * 256;
+    if (e < NA * NA) {
+      const int r = 2 * (e / NA), c = 2 * (e % NA);
+      a_lds[r * XS + c] = zv[q].re;
+      a_lds[r * XS + c + 1] = -zv[q].im;
+      a_lds[(r + 1) * XS + c] = zv[q].im;
+      a_lds[(r + 1) * XS + c + 1] = zv[q].re;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kX; ++q) {
+    const int e = tid + q * 256;
+    x_lds[(e / NA) * XS + 2 * (e % NA)] = xv[q].re;
+    x_lds[(e / NA) * XS + 2 * (e % NA) + 1] = xv[q].im;
+  }
+  __syncthreads();
+  const int wave = tid >> 6, l = tid & 63;
+  if (wave * 16 >= item.len) return;
+  const int col = wave * 16 + (l & 15), kq = l >> 4, mr = l & 15;
+  typename MfmaAcc<S>::v4 acc[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) acc[mt] = typename MfmaAcc<S>::v4{0, 0, 0, 0};
+  for (int k0 = 0; k0 < KT; k0 += KC) {
+    S bv[KC], av[KC][MT];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      const int kp = 4 * (k0 + q) + kq;
+      bv[q] = x_lds[col * XS + kp];
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) av[q][mt] = a_lds[(16 * mt + mr) * XS + kp];
+    }
+#pragma unroll
+    for (int q = 0; q < KC; ++q)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[mt] = MfmaAcc<S>::mma(av[q][mt], bv[q], acc[mt]);
+  }
+  const int tgt = tgt_s[col];
+  if (tgt < 0) return;
+  S* o = dst + (size_t)tgt * K2;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) o[16 * mt + MfmaAcc<S>::row(l, r)] = acc[mt][r];
+}
+
 template <typename S, typename XT>
 __global__ void __launch_bounds__(256)
 convert_flat_kernel(const RhsDev* __restrict__ rhs, int n_a, const XT* __restrict__ x, S* __restrict__ xs) {
@@ -547,22 +771,110 @@ int max_groups(const BatchDesc& bd) { return std::min(128, 4 * choose_chunks(bd,
 
 static bool store_has_far(const r3m_store* Z) { return Z->near_radius < std::max(Z->Dx, Z->Dy); }
 
-// near displacement groups: one displacement per workgroup for small batches,
-// fewer groups (longer loops) when the batch already fills the chip
-static int near_groups(const r3m_store* Z, const BatchDesc& bd) {
+static int near_count(const r3m_store* Z) {
   const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
+  return (2 * Nx + 1) * (2 * Ny + 1);
+}
+
+// near field on the matrix cores (one partial slot per near displacement)
+// unless the near set is large (an all-dense store), where the LDS-slab kernel
+// groups displacements
+static bool near_on_mfma(const r3m_store* Z) {
+  const int n_a = Z->n / Z->n_states;
+  const size_t es = Z->near_dtype == R3M_C128 ? 8 : 4;
+  return near_count(Z) <= 128 && ((size_t)2 * n_a + kNearCols) * (2 * n_a + 1) * es <= 96 * 1024;
+}
+
+// near partial slots: one per displacement on the matrix-core path; otherwise
+// one displacement per workgroup for small batches, fewer groups (longer
+// loops) when the batch already fills the chip
+static int near_groups(const r3m_store* Z, const BatchDesc& bd) {
+  if (near_on_mfma(Z)) return near_count(Z);
   const int want = (int)std::max<int64_t>(1, (2048 + bd.n_tiles - 1) / std::max(1, bd.n_tiles));
-  return std::max(1, std::min({(2 * Nx + 1) * (2 * Ny + 1), 128, want}));
+  return std::max(1, std::min({near_count(Z), 128, want}));
+}
+
+// retrieval lists of the near field (matrix-core path): counts, offsets and
+// cursors per class, the item count, the item table and the pair table
+struct NearLists {
+  int* counts = nullptr;
+  int* offsets = nullptr;
+  int* cursor = nullptr;
+  int* n_items = nullptr;
+  NearItem* items = nullptr;
+  NearPair* pairs = nullptr;
+  int n_cls = 0;
+  int64_t max_items = 0;
+  size_t bytes = 0;
+};
+
+static NearLists near_lists(char* base, int n_near, int S, const BatchDesc& bd) {
+  NearLists L;
+  const int64_t pairs = (int64_t)n_near * bd.total_units;
+  L.n_cls = n_near * S * (S + 1);
+  L.max_items = (pairs + kNearCols - 1) / kNearCols + L.n_cls;
+  size_t o = 0;
+  auto take = [&](size_t b) {
+    const size_t at = o;
+    o = (o + b + 255) / 256 * 256;
+    return base ? (void*)(base + at) : nullptr;
+  };
+  L.counts = (int*)take((size_t)L.n_cls * 4);
+  L.offsets = (int*)take((size_t)L.n_cls * 4);
+  L.cursor = (int*)take((size_t)L.n_cls * 4);
+  L.n_items = (int*)take(4);
+  L.items = (NearItem*)take((size_t)L.max_items * sizeof(NearItem));
+  L.pairs = (NearPair*)take((size_t)pairs * sizeof(NearPair));
+  L.bytes = o;
+  return L;
+}
+
+static NearLists near_lists(char* base, const r3m_store* Z, const BatchDesc& bd) {
+  return near_on_mfma(Z) ? near_lists(base, near_count(Z), Z->n_states, bd) : NearLists{};
+}
+
+size_t near_lists_bytes(const r3m_store* Z, const BatchDesc& bd) { return near_lists(nullptr, Z, bd).bytes; }
+// the most any store with n_states states can need on this batch
+size_t near_lists_bytes_bound(int n_states, const BatchDesc& bd) {
+  return near_lists(nullptr, 128, n_states, bd).bytes;
+}
+
+// builds the near retrieval lists of (batch, codebook states) at lists_dev
+void build_near_lists(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, void* lists_dev,
+                      hipStream_t stream) {
+  if (!near_on_mfma(Z)) return;
+  NearLists L = near_lists((char*)lists_dev, Z, bd);
+  const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(ceil_div((size_t)L.n_cls, 256)), dim3(256), 0, stream, L.counts,
+                     L.n_cls);
+  const int chunks = (int)ceil_div((size_t)bd.max_units, 256);
+  const dim3 grid((unsigned)(chunks * near_count(Z)), bd.B);
+  const size_t lds = (size_t)2 * Z->n_states * (Z->n_states + 1) * sizeof(int);
+  hipLaunchKernelGGL(near_classify_kernel, grid, dim3(256), lds, stream, bd.rhs, states, Z->n_states, Nx, Ny,
+                     chunks, L.counts, L.cursor, (const int*)L.offsets, L.pairs, 0);
+  hipLaunchKernelGGL(near_scan_kernel, dim3(1), dim3(1024), 0, stream, (const int*)L.counts, L.n_cls, L.offsets,
+                     L.cursor, L.items, L.n_items);
+  hipLaunchKernelGGL(near_classify_kernel, grid, dim3(256), lds, stream, bd.rhs, states, Z->n_states, Nx, Ny,
+                     chunks, L.counts, L.cursor, (const int*)L.offsets, L.pairs, 1);
+  R3M_CHECK_HIP(hipGetLastError());
 }
 
 // workspace: partial sums [far groups + near groups][units][n_a] in the store
-// precision, plus a copy of x in the store precision when the vectors are wider
-size_t matvec_partial_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks) {
+// precision, a copy of x in the store precision when the vectors are wider,
+// then the near retrieval lists
+size_t partials_and_x_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks) {
   const size_t es = Z->near_dtype == R3M_C128 ? 16 : 8;
   const int n_a = Z->n / Z->n_states;
   const size_t vec = (size_t)bd.total_units * n_a * es;
   const int slots = (store_has_far(Z) ? std::max(chunks, 1) : 0) + near_groups(Z, bd);
-  return (size_t)slots * vec + (Z->near_dtype == R3M_C128 ? 0 : vec) + 256;
+  return ((size_t)slots * vec + (Z->near_dtype == R3M_C128 ? 0 : vec) + 255) / 256 * 256;
+}
+size_t matvec_partial_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks) {
+  return partials_and_x_bytes(bd, Z, chunks) + near_lists_bytes(Z, bd) + 256;
+}
+// the lists of a workspace sized with max_groups(bd)
+void* workspace_lists(void* work, const BatchDesc& bd, const r3m_store* Z) {
+  return (char*)work + partials_and_x_bytes(bd, Z, max_groups(bd));
 }
 
 void validate_store(const r3m_store* Z) {
@@ -587,7 +899,7 @@ void validate_store(const r3m_store* Z) {
 
 template <typename S, typename XT>
 static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const S* xs, XT* y,
-                        char* part, int chunks, hipStream_t stream) {
+                        char* part, const void* lists, int chunks, hipStream_t stream) {
   const int n_a = Z->n / Z->n_states;
   const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
   const bool far = store_has_far(Z);
@@ -597,8 +909,9 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
   const int hg = near_groups(Z, bd);
   const int64_t tu = (int64_t)bd.total_units;
   if (far) {
-    const int lds_state_cap = 16384;
-    constexpr int rch = sizeof(S) == 4 ? 8 : 4;
+    // the batch's largest state array, when it fits, is staged in LDS
+    const int lds_state_cap = bd.max_units <= 16384 ? (int)((bd.max_units + 15) / 16 * 16) : 0;
+    constexpr int rch = sizeof(S) == 4 ? R3M_FAR_RCH_F32 : 4;
     const size_t lds = 4 * (size_t)rch * Z->n * 2 * sizeof(S) + lds_state_cap;
     auto kern = n_a == 40 ? far_kernel<S, 10, rch> : far_kernel<S, 16, rch>;
     const int nwg = (bd.n_tiles * groups + kXcd - 1) / kXcd * kXcd;
@@ -607,13 +920,22 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
                        Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles);
     R3M_CHECK_HIP(hipGetLastError());
   }
-  const int nwg_near = (bd.n_tiles * hg + kXcd - 1) / kXcd * kXcd;
-  // row-slab height: the whole state for complex64, half of it for complex128
-  constexpr int sr = sizeof(S) == 4 ? 40 : 20;
-  const size_t lds_near = ((size_t)sr * (Z->n + 2) + 2 * (size_t)kBU * n_a) * 2 * sizeof(S);
-  R3M_REQUIRE(n_a % sr == 0 && lds_near <= 160 * 1024, R3M_ERR_UNSUPPORTED, "near row slab does not fit in LDS");
-  hipLaunchKernelGGL((near_kernel<S, sr>), dim3(nwg_near), dim3(256), lds_near, stream, bd.rhs, bd.tiles, states,
-                     (const S*)Z->near, Nx, Ny, Z->n, n_a, Z->n_states, xs, (S*)part, tu, groups, hg, bd.n_tiles);
+  if (near_on_mfma(Z)) {
+    NearLists L = near_lists((char*)lists, Z, bd);
+    const size_t lds = ((size_t)2 * n_a + kNearCols) * (2 * n_a + 1) * sizeof(S);
+    auto kern = n_a == 40 ? near_mfma_kernel<S, 40> : near_mfma_kernel<S, 64>;
+    hipLaunchKernelGGL(kern, dim3((unsigned)L.max_items), dim3(256), lds, stream, (const NearItem*)L.items,
+                       (const int*)L.n_items, (const NearPair*)L.pairs, (const S*)Z->near, Z->n, Z->n_states, xs,
+                       (S*)part + (size_t)groups * tu * n_a * 2, tu);
+  } else {
+    const int nwg_near = (bd.n_tiles * hg + kXcd - 1) / kXcd * kXcd;
+    // row-slab height: the whole state for complex64, half of it for complex128
+    constexpr int sr = sizeof(S) == 4 ? 40 : 20;
+    const size_t lds_near = ((size_t)sr * (Z->n + 2) + 2 * (size_t)kBU * n_a) * 2 * sizeof(S);
+    R3M_REQUIRE(n_a % sr == 0 && lds_near <= 160 * 1024, R3M_ERR_UNSUPPORTED, "near row slab does not fit in LDS");
+    hipLaunchKernelGGL((near_kernel<S, sr>), dim3(nwg_near), dim3(256), lds_near, stream, bd.rhs, bd.tiles, states,
+                       (const S*)Z->near, Nx, Ny, Z->n, n_a, Z->n_states, xs, (S*)part, tu, groups, hg, bd.n_tiles);
+  }
   R3M_CHECK_HIP(hipGetLastError());
   hipLaunchKernelGGL((reduce_groups_kernel<S, XT>), dim3(ceil_div((size_t)bd.max_units * n_a, 64), bd.B),
                      dim3(64), 0, stream, bd.rhs, (const S*)part, groups + hg, tu, n_a, y);
@@ -622,7 +944,7 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
 
 template <typename S, typename XT>
 static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
-                         void* partial, int chunks, hipStream_t stream) {
+                         void* partial, const void* lists, int chunks, hipStream_t stream) {
   const int n_a = Z->n / Z->n_states;
   const bool far = store_has_far(Z);
   const int groups = far ? std::max(chunks, 1) : 0;
@@ -636,17 +958,18 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
                        dim3(256), 0, stream, bd.rhs, n_a, (const XT*)x, xc);
     xs = xc;
   }
-  launch_core<S, XT>(Z, bd, states, xs, (XT*)y, part, chunks, stream);
+  launch_core<S, XT>(Z, bd, states, xs, (XT*)y, part, lists, chunks, stream);
 }
 
 // matvec with x already in the store precision (float for C64, double for
 // C128); y is C128
+// the near retrieval lists (build_near_lists) must be current at lists
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
-                       void* partial, int chunks, hipStream_t stream) {
+                       void* partial, const void* lists, int chunks, hipStream_t stream) {
   if (Z->near_dtype == R3M_C128)
-    launch_core<double, double>(Z, bd, states, (const double*)xs, (double*)y, (char*)partial, chunks, stream);
+    launch_core<double, double>(Z, bd, states, (const double*)xs, (double*)y, (char*)partial, lists, chunks, stream);
   else
-    launch_core<float, double>(Z, bd, states, (const float*)xs, (double*)y, (char*)partial, chunks, stream);
+    launch_core<float, double>(Z, bd, states, (const float*)xs, (double*)y, (char*)partial, lists, chunks, stream);
 }
 
 static std::vector<int64_t> tune_key(const r3m_store* Z, const BatchDesc& bd) {
@@ -658,7 +981,7 @@ static std::vector<int64_t> tune_key(const r3m_store* Z, const BatchDesc& bd) {
 // a few displacement-group counts around the default and keep the fastest.
 // xs is the input in the store precision, y a C128 output (overwritten).
 int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
-                 void* y, void* partial, hipStream_t stream) {
+                 void* y, void* partial, const void* lists, hipStream_t stream) {
   if (!store_has_far(Z)) return 1;
   const std::vector<int64_t> key = tune_key(Z, bd);
   auto it = ctx->tuned_groups.find(key);
@@ -679,9 +1002,9 @@ int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uin
   int best = g0;
   float best_ms = 1e30f;
   for (int g : cand) {
-    launch_matvec_pre(Z, bd, states, xs, y, partial, g, stream);  // warm
+    launch_matvec_pre(Z, bd, states, xs, y, partial, lists, g, stream);  // warm
     R3M_CHECK_HIP(hipEventRecord(e0, stream));
-    for (int rep = 0; rep < 2; ++rep) launch_matvec_pre(Z, bd, states, xs, y, partial, g, stream);
+    for (int rep = 0; rep < 2; ++rep) launch_matvec_pre(Z, bd, states, xs, y, partial, lists, g, stream);
     R3M_CHECK_HIP(hipEventRecord(e1, stream));
     R3M_CHECK_HIP(hipEventSynchronize(e1));
     float ms = 0.f;
@@ -706,17 +1029,20 @@ int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd) {
   return it != ctx->tuned_groups.end() ? it->second : choose_chunks(bd, 64);
 }
 
+// partial: a workspace of matvec_partial_bytes(bd, Z, max_groups(bd)); lists:
+// current near lists (build_near_lists), or NULL for the ones inside partial
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
-                   r3m_dtype vec_dtype, const void* x, void* y, void* partial, int chunks,
+                   r3m_dtype vec_dtype, const void* x, void* y, void* partial, const void* lists, int chunks,
                    hipStream_t stream) {
   (void)ctx;
+  if (!lists) lists = workspace_lists(partial, bd, Z);
   if (Z->near_dtype == R3M_C128) {
     R3M_REQUIRE(vec_dtype == R3M_C128, R3M_ERR_UNSUPPORTED, "a C128 store needs C128 vectors");
-    launch_typed<double, double>(Z, bd, states, x, y, partial, chunks, stream);
+    launch_typed<double, double>(Z, bd, states, x, y, partial, lists, chunks, stream);
   } else if (vec_dtype == R3M_C64) {
-    launch_typed<float, float>(Z, bd, states, x, y, partial, chunks, stream);
+    launch_typed<float, float>(Z, bd, states, x, y, partial, lists, chunks, stream);
   } else {
-    launch_typed<float, double>(Z, bd, states, x, y, partial, chunks, stream);
+    launch_typed<float, double>(Z, bd, states, x, y, partial, lists, chunks, stream);
   }
 }
 
@@ -756,6 +1082,10 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
     const size_t need = matvec_partial_bytes(bd, Z, max_groups(bd));
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "matvec workspace too small");
     R3M_REQUIRE(work_dev, R3M_ERR_INVALID_ARG, "work is NULL");
+    // the retrieval index of this codebook (near lists), unless the caller
+    // declares the one in the workspace current
+    if (!(batch->flags & R3M_BATCH_INDEX_READY))
+      build_near_lists(Z, bd, batch->states, workspace_lists(work_dev, bd, Z), stream);
     // first C128 call on this (store, batch): tune the group count on this x
     // (the tuner writes y as C128, so C64 vectors take the tuned or default value)
     if (vec_dtype == R3M_C128 && store_has_far(Z)) {
@@ -770,9 +1100,10 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
         R3M_CHECK_HIP(hipGetLastError());
         xs = xc;
       }
-      tuned_groups(ctx, Z, bd, batch->states, xs, y_dev, work_dev, stream);
+      tuned_groups(ctx, Z, bd, batch->states, xs, y_dev, work_dev, workspace_lists(work_dev, bd, Z), stream);
     }
-    launch_matvec(ctx, Z, bd, batch->states, vec_dtype, x_dev, y_dev, work_dev, plan_groups(ctx, Z, bd), stream);
+    launch_matvec(ctx, Z, bd, batch->states, vec_dtype, x_dev, y_dev, work_dev, nullptr, plan_groups(ctx, Z, bd),
+                  stream);
   });
 }
 

@@ -1,0 +1,32 @@
+// Library-internal interface of the retrieved matvec (used by the solver).
+#pragma once
+#include "r3m_common.h"
+
+namespace r3m {
+
+void validate_store(const r3m_store* Z);
+int choose_chunks(const BatchDesc& bd, int max_chunks);
+// largest displacement-group count the autotuner may pick (workspaces are sized for it)
+int max_groups(const BatchDesc& bd);
+// the autotuned group count of (store, batch) if known, else the default
+int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd);
+// times candidate group counts once per (store, batch); xs in the store precision, y C128
+int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
+                 void* y, void* partial, const void* lists, hipStream_t stream);
+// matvec workspace: partial slots, converted x, near retrieval lists
+size_t matvec_partial_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks);
+// the same without the lists (for callers that keep the lists elsewhere)
+size_t partials_and_x_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks);
+size_t near_lists_bytes(const r3m_store* Z, const BatchDesc& bd);
+size_t near_lists_bytes_bound(int n_states, const BatchDesc& bd);
+void build_near_lists(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, void* lists_dev,
+                      hipStream_t stream);
+// y (C128 or C64 vectors); lists NULL: the ones inside partial
+void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
+                   r3m_dtype vec_dtype, const void* x, void* y, void* partial, const void* lists, int chunks,
+                   hipStream_t stream);
+// xs already in the store precision; y C128
+void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
+                       void* partial, const void* lists, int chunks, hipStream_t stream);
+
+}  // namespace r3m

@@ -24,6 +24,7 @@ R3M_ERR_NONFINITE = -5
 R3M_ERR_UNSUPPORTED = -6
 
 C128, C64, BF16X2, F16X2 = 0, 1, 2, 3
+BATCH_INDEX_READY = 1
 PRECOND_NONE, PRECOND_BLOCK_JACOBI = 0, 1
 
 EXPORTED = (
@@ -64,7 +65,7 @@ class StoreC(C.Structure):
 class BatchC(C.Structure):
     _fields_ = [
         ("B", C.c_int32), ("L", C.POINTER(C.c_int32)), ("unit_off", C.POINTER(C.c_int64)),
-        ("state_off", C.POINTER(C.c_int64)), ("states", C.c_void_p),
+        ("state_off", C.POINTER(C.c_int64)), ("states", C.c_void_p), ("flags", C.c_uint32),
     ]
 
 
@@ -290,16 +291,22 @@ def _need_vec(t, batch: Batch, n_a: int, what: str):
 
 
 def r3m_retrieved_matvec(ctx: Context, store: Store, batch: Batch, vec_dtype: int, x, y, work=None,
-                         stream=None):
+                         stream=None, index_ready: bool = False):
+    """index_ready: the retrieval index in `work` is current (an earlier call
+    with this store, batch and codebook built it there): skip rebuilding it."""
     lib = load()
     _need_vec(x, batch, store.n // store.n_states, "x")
     _need_vec(y, batch, store.n // store.n_states, "y")
     sc = store.c()
     wb = 0 if work is None else work.numel() * work.element_size()
     wp = C.c_void_p(0 if work is None else work.data_ptr())
-    _check(lib.r3m_retrieved_matvec(ctx.handle, C.byref(sc), C.byref(batch.cs), vec_dtype,
-                                    C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), wp, wb,
-                                    _stream(stream)), ctx.handle)
+    batch.cs.flags = BATCH_INDEX_READY if index_ready else 0
+    try:
+        _check(lib.r3m_retrieved_matvec(ctx.handle, C.byref(sc), C.byref(batch.cs), vec_dtype,
+                                        C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), wp, wb,
+                                        _stream(stream)), ctx.handle)
+    finally:
+        batch.cs.flags = 0
 
 
 def r3m_gmres_solve(ctx: Context, store: Store, store64: Store | None, batch: Batch, b, x, tol: float,

@@ -410,3 +410,31 @@ def test_tuned_group_count(r3m, ctx, stores_2bit_8):
     assert r3m.matvec_groups(ctx, s64, batch) == g
     y128 = run_matvec(r3m, ctx, s128, batch, to_dev(x), r3m.C128).cpu().numpy()
     assert rel_max(y1, y128) <= 1e-6
+
+
+def test_index_ready_reuses_retrieval_index(r3m, ctx, stores_2bit_8):
+    """A matvec that declares the workspace's retrieval index current gives
+    bitwise the result of the call that built it; a new codebook through the
+    same workspace (index rebuilt) matches the oracle product."""
+    s128, s64, sden = stores_2bit_8
+    x = cb.random_complex(2 * 2560, 13)
+    xd = to_dev(x)
+    for store in (s64, s128):
+        books = [cb.uniform(8, 4, 41), cb.uniform(8, 4, 42)]
+        batch = batch_for(r3m, books, [8, 8])
+        wb = r3m.matvec_work_bytes(ctx, store, batch, r3m.C128)
+        work = torch.empty(wb, dtype=torch.uint8, device=DEV)
+        y1 = torch.zeros_like(xd)
+        y2 = torch.zeros_like(xd)
+        r3m.r3m_retrieved_matvec(ctx, store, batch, r3m.C128, xd, y1, work)
+        r3m.r3m_retrieved_matvec(ctx, store, batch, r3m.C128, xd, y2, work, index_ready=True)
+        torch.cuda.synchronize()
+        assert torch.equal(y1, y2)
+    # new codebook, same workspace and shapes: the index is rebuilt
+    books = [cb.uniform(8, 4, 43), cb.uniform(8, 4, 44)]
+    batch = batch_for(r3m, books, [8, 8])
+    y3 = torch.zeros_like(xd)
+    r3m.r3m_retrieved_matvec(ctx, s128, batch, r3m.C128, xd, y3, work)
+    yd = run_matvec(r3m, ctx, sden, batch, xd, r3m.C128)
+    torch.cuda.synchronize()
+    assert rel_l2(y3.cpu().numpy(), yd.cpu().numpy()) <= 1e-4
