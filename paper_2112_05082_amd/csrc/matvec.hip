@@ -102,7 +102,20 @@ __device__ __forceinline__ double quad_swap2(double v) {
 
 // Far contribution of one staged rank slice (RC ranks, compile-time) for one
 // lane: t = V[A(s_j)]^H x_j over the lane's quarter, summed over the unit's
-// four lanes, then y += U[A(s_i)] t on the lane's rows.
+// four lanes, then y += U[A(s_i)] t on the lane's rows.  The LDS reads of the
+// next rank are issued before the products of the current one (scheduling
+// barriers keep that order), so one rank of FMAs covers their latency.
+#ifndef R3M_FAR_DEPTH
+#define R3M_FAR_DEPTH 2
+#endif
+constexpr int kFarDepth = R3M_FAR_DEPTH;  // factor rows read ahead of their products
+
+template <typename S, int QS>
+__device__ __forceinline__ void lds_row(const Cx<S>* __restrict__ lds, size_t at, Cx<S> (&v)[QS]) {
+#pragma unroll
+  for (int k = 0; k < QS; k += 2) load2<S>(reinterpret_cast<const S*>(lds), at + k, v[k], v[k + 1]);
+}
+
 template <typename S, int QS, int RC>
 __device__ __forceinline__ void far_slice(const Cx<S>* __restrict__ lds_u, const Cx<S>* __restrict__ lds_v,
                                           int n, int offi, int offj, int m0, bool vj, const Cx<S> (&xr)[QS],
@@ -110,17 +123,55 @@ __device__ __forceinline__ void far_slice(const Cx<S>* __restrict__ lds_u, const
   S t_re[RC], t_im[RC];
 #pragma unroll
   for (int rr = 0; rr < RC; ++rr) t_re[rr] = t_im[rr] = 0;
-  if (vj) {
+  if constexpr (sizeof(S) == 8) {  // complex128: no room for a second row in registers
+    if (vj) {
 #pragma unroll
-    for (int k = 0; k < QS; k += 2) {
-      const Cx<S> x0 = xr[k], x1 = xr[k + 1];
+      for (int k = 0; k < QS; k += 2) {
+        const Cx<S> x0 = xr[k], x1 = xr[k + 1];
+#pragma unroll
+        for (int rr = 0; rr < RC; ++rr) {
+          Cx<S> v0, v1;
+          load2<S>(reinterpret_cast<const S*>(lds_v), (size_t)rr * n + offj + m0 + k, v0, v1);
+          cmacc(t_re[rr], t_im[rr], v0, x0);
+          cmacc(t_re[rr], t_im[rr], v1, x1);
+        }
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+      t_re[rr] += quad_swap1(t_re[rr]);
+      t_im[rr] += quad_swap1(t_im[rr]);
+      t_re[rr] += quad_swap2(t_re[rr]);
+      t_im[rr] += quad_swap2(t_im[rr]);
+    }
+    if (vj) {
 #pragma unroll
       for (int rr = 0; rr < RC; ++rr) {
-        Cx<S> v0, v1;
-        load2<S>(reinterpret_cast<const S*>(lds_v), (size_t)rr * n + offj + m0 + k, v0, v1);
-        cmacc(t_re[rr], t_im[rr], v0, x0);  // conj(v) x
-        cmacc(t_re[rr], t_im[rr], v1, x1);
+#pragma unroll
+        for (int k = 0; k < QS; k += 2) {
+          Cx<S> u0, u1;
+          load2<S>(reinterpret_cast<const S*>(lds_u), (size_t)rr * n + offi + m0 + k, u0, u1);
+          const Cx<S> tv = {t_re[rr], t_im[rr]};
+          cmac(acc_re[k], acc_im[k], u0, tv);
+          cmac(acc_re[k + 1], acc_im[k + 1], u1, tv);
+        }
       }
+    }
+    return;
+  }
+  constexpr int NB = kFarDepth + 1;  // rows in flight + the one in use
+  Cx<S> vb[NB][QS];
+  if (vj) {
+#pragma unroll
+    for (int rr = 0; rr < kFarDepth && rr < RC; ++rr) lds_row<S, QS>(lds_v, (size_t)rr * n + offj + m0, vb[rr]);
+#pragma unroll
+    for (int rr = 0; rr < RC; ++rr) {
+      if (rr + kFarDepth < RC)
+        lds_row<S, QS>(lds_v, (size_t)(rr + kFarDepth) * n + offj + m0, vb[(rr + kFarDepth) % NB]);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int k = 0; k < QS; ++k) cmacc(t_re[rr], t_im[rr], vb[rr % NB][k], xr[k]);  // conj(v) x
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 #pragma unroll
@@ -132,15 +183,16 @@ __device__ __forceinline__ void far_slice(const Cx<S>* __restrict__ lds_u, const
   }
   if (vj) {
 #pragma unroll
-    for (int rr = 0; rr < RC; ++rr) {
+    for (int rr = 0; rr < kFarDepth && rr < RC; ++rr) lds_row<S, QS>(lds_u, (size_t)rr * n + offi + m0, vb[rr]);
 #pragma unroll
-      for (int k = 0; k < QS; k += 2) {
-        Cx<S> u0, u1;
-        load2<S>(reinterpret_cast<const S*>(lds_u), (size_t)rr * n + offi + m0 + k, u0, u1);
-        const Cx<S> tv = {t_re[rr], t_im[rr]};
-        cmac(acc_re[k], acc_im[k], u0, tv);
-        cmac(acc_re[k + 1], acc_im[k + 1], u1, tv);
-      }
+    for (int rr = 0; rr < RC; ++rr) {
+      if (rr + kFarDepth < RC)
+        lds_row<S, QS>(lds_u, (size_t)(rr + kFarDepth) * n + offi + m0, vb[(rr + kFarDepth) % NB]);
+      __builtin_amdgcn_sched_barrier(0);
+      const Cx<S> tv = {t_re[rr], t_im[rr]};
+#pragma unroll
+      for (int k = 0; k < QS; ++k) cmac(acc_re[k], acc_im[k], vb[rr % NB][k], tv);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 }
