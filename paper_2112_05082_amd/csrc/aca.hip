@@ -8,6 +8,8 @@
 // The achieved relative error ||R||_F / ||Z||_F is exact.
 #include "r3m_common.h"
 
+#include <hip/hip_fp16.h>
+
 #include <algorithm>
 
 namespace r3m {
@@ -78,12 +80,82 @@ __device__ inline int far_to_slot(int f, int Dx, int Dy, int nr) {
   return -1;
 }
 
-template <typename OutT>
+// Split storage of one real value v (already scaled): hi = RNE(v) in the
+// 16-bit format, lo = RNE(v - hi); returned as the two 16-bit patterns.
+__device__ inline void split_bf16(float v, uint32_t& hi, uint32_t& lo) {
+  auto rne = [](float x) -> uint32_t {
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;  // finite inputs only
+  };
+  hi = rne(v);
+  lo = rne(v - __uint_as_float(hi << 16));
+}
+__device__ inline void split_f16(float v, uint32_t& hi, uint32_t& lo) {
+  const __half h = __float2half_rn(v);
+  const __half l = __float2half_rn(v - __half2float(h));
+  hi = __half_as_ushort(h);
+  lo = __half_as_ushort(l);
+}
+
+// Writes the FP64 factors [2 cap][n] (U columns then V columns) of far block
+// f in the store format: C128, C64, or an 8-byte split element
+// {re_hi | im_hi << 16, re_lo | im_lo << 16} (BF16X2, F16X2).  F16X2 columns
+// are scaled by 2^-e with 2^e >= the column's largest real or imaginary
+// magnitude; scales[f][2 cap] holds 2^e.
+__device__ void store_factors(const double2* __restrict__ UV, int n, int cap, int f, int mode, void* far_out,
+                              float* scales, MaxSum* sh) {
+  const int tot = 2 * cap * n;
+  if (mode == R3M_C128) {
+    double2* o = reinterpret_cast<double2*>(far_out) + (size_t)f * tot;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) o[e] = UV[e];
+    return;
+  }
+  if (mode == R3M_C64) {
+    float2* o = reinterpret_cast<float2*>(far_out) + (size_t)f * tot;
+    for (int e = threadIdx.x; e < tot; e += blockDim.x) o[e] = make_float2((float)UV[e].x, (float)UV[e].y);
+    return;
+  }
+  uint2* o = reinterpret_cast<uint2*>(far_out) + (size_t)f * tot;
+  for (int c = 0; c < 2 * cap; ++c) {
+    float sc = 1.0f, inv = 1.0f;
+    if (mode == R3M_F16X2) {
+      MaxSum m{0.0, 0, 0.0};
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double2 v = UV[(size_t)c * n + i];
+        m.v = fmax(m.v, fmax(fabs(v.x), fabs(v.y)));
+      }
+      // block maximum (the index field is unused here)
+      for (int o2 = 32; o2 >= 1; o2 >>= 1) m.v = fmax(m.v, __shfl_xor(m.v, o2));
+      if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+      __syncthreads();
+      double mx = 0.0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = fmax(mx, sh[w].v);
+      __syncthreads();
+      const int e = mx > 0.0 ? (int)ceil(log2(mx)) : 0;
+      sc = ldexpf(1.0f, e);
+      inv = ldexpf(1.0f, -e);
+      if (threadIdx.x == 0) scales[(size_t)f * 2 * cap + c] = sc;
+    }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const double2 v = UV[(size_t)c * n + i];
+      uint32_t rh, rl, ih, il;
+      if (mode == R3M_BF16X2) {
+        split_bf16((float)v.x, rh, rl);
+        split_bf16((float)v.y, ih, il);
+      } else {
+        split_f16((float)v.x * inv, rh, rl);
+        split_f16((float)v.y * inv, ih, il);
+      }
+      o[(size_t)c * n + i] = make_uint2(rh | (ih << 16), rl | (il << 16));
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kAcaThreads) aca_kernel(const double2* __restrict__ dense, int n,
                                                           int Dx, int Dy, int nr, int f_begin,
                                                           int f_count, double tol, int cap,
-                                                          double2* work, OutT* far_out,
-                                                          int* ranks_out, double* err_out) {
+                                                          double2* work, int mode, void* far_out,
+                                                          float* scales, int* ranks_out, double* err_out) {
   __shared__ MaxSum sh[kAcaThreads / 64];
   extern __shared__ double2 lds[];  // [n] column u, [n] pivot row
   double2* ucol = lds;
@@ -151,12 +223,7 @@ __global__ void __launch_bounds__(kAcaThreads) aca_kernel(const double2* __restr
   }
   __syncthreads();
   // factors: U_f [cap][n] then V_f [cap][n]
-  OutT* out = far_out + (size_t)f * 2 * cap * n * 2;
-  for (int e = threadIdx.x; e < 2 * cap * n; e += blockDim.x) {
-    double2 v = U[e];
-    out[2 * e] = (OutT)v.x;
-    out[2 * e + 1] = (OutT)v.y;
-  }
+  store_factors(U, n, cap, f, mode, far_out, scales, sh);
   if (threadIdx.x == 0) {
     ranks_out[f] = rank;
     err_out[f] = err;
@@ -179,7 +246,11 @@ int32_t r3m_far_count(int32_t Dx, int32_t Dy, int32_t near_radius) {
 size_t r3m_far_bytes(int32_t n, int32_t n_far, int32_t max_rank, r3m_dtype dtype) {
   if (n <= 0 || n_far < 0 || max_rank < 0) return 0;
   const size_t head = ((size_t)n_far * 4 + 255) / 256 * 256;
-  return head + (size_t)n_far * 2 * max_rank * n * dtype_size(dtype);
+  const size_t es = dtype == R3M_C128 ? 16 : (dtype == R3M_C64 || dtype == R3M_BF16X2 || dtype == R3M_F16X2) ? 8 : 0;
+  if (es == 0) return 0;
+  const size_t body = (size_t)n_far * 2 * max_rank * n * es;
+  const size_t scales = dtype == R3M_F16X2 ? (size_t)n_far * 2 * max_rank * 4 : 0;
+  return head + (body + 255) / 256 * 256 + scales;
 }
 
 size_t r3m_compress_work_bytes(int32_t n, int32_t max_rank, int32_t blocks_per_batch) {
@@ -200,8 +271,9 @@ int r3m_compress_far(r3m_ctx ctx, const void* dense_dev, int32_t n, int32_t Dx, 
                 "bad block shape");
     R3M_REQUIRE(tol >= 0.0 && std::isfinite(tol), R3M_ERR_INVALID_ARG, "tol must be >= 0");
     R3M_REQUIRE(max_rank >= 1 && max_rank <= n, R3M_ERR_INVALID_ARG, "max_rank must be in [1, n]");
-    R3M_REQUIRE(far_dtype == R3M_C128 || far_dtype == R3M_C64, R3M_ERR_UNSUPPORTED,
-                "far dtype must be C128 or C64");
+    R3M_REQUIRE(far_dtype == R3M_C128 || far_dtype == R3M_C64 || far_dtype == R3M_BF16X2 ||
+                    far_dtype == R3M_F16X2,
+                R3M_ERR_UNSUPPORTED, "unknown far dtype");
     const int n_far = r3m_far_count(Dx, Dy, near_radius);
     R3M_REQUIRE(far_bytes >= r3m_far_bytes(n, n_far, max_rank, far_dtype), R3M_ERR_BUFFER_TOO_SMALL,
                 "far buffer too small");
@@ -217,6 +289,10 @@ int r3m_compress_far(r3m_ctx ctx, const void* dense_dev, int32_t n, int32_t Dx, 
     const size_t head = ((size_t)n_far * 4 + 255) / 256 * 256;
     int32_t* ranks_dev = (int32_t*)far_dev;
     char* factors = (char*)far_dev + head;
+    const size_t es = far_dtype == R3M_C128 ? 16 : 8;
+    float* scales = far_dtype == R3M_F16X2
+                        ? (float*)(factors + ((size_t)n_far * 2 * max_rank * n * es + 255) / 256 * 256)
+                        : nullptr;
     char* wbase = (char*)work_dev;
     double2* rwork = (double2*)wbase;
     double* err_dev = (double*)(wbase + per * bpb);
@@ -225,14 +301,9 @@ int r3m_compress_far(r3m_ctx ctx, const void* dense_dev, int32_t n, int32_t Dx, 
     for (int f0 = 0; f0 < n_far; f0 += bpb) {
       const int cnt = std::min(bpb, n_far - f0);
       const size_t lds = 2 * (size_t)n * sizeof(double2);
-      if (far_dtype == R3M_C128)
-        hipLaunchKernelGGL(aca_kernel<double>, dim3(cnt), dim3(kAcaThreads), lds, stream,
-                           (const double2*)dense_dev, n, Dx, Dy, near_radius, f0, cnt, tol, max_rank,
-                           rwork, (double*)factors, ranks_dev, err_dev - f0);
-      else
-        hipLaunchKernelGGL(aca_kernel<float>, dim3(cnt), dim3(kAcaThreads), lds, stream,
-                           (const double2*)dense_dev, n, Dx, Dy, near_radius, f0, cnt, tol, max_rank,
-                           rwork, (float*)factors, ranks_dev, err_dev - f0);
+      hipLaunchKernelGGL(aca_kernel, dim3(cnt), dim3(kAcaThreads), lds, stream, (const double2*)dense_dev, n, Dx,
+                         Dy, near_radius, f0, cnt, tol, max_rank, rwork, (int)far_dtype, (void*)factors, scales,
+                         ranks_dev, err_dev - f0);
       R3M_CHECK_HIP(hipGetLastError());
       R3M_CHECK_HIP(hipMemcpyAsync(rel_err_host + f0, err_dev, cnt * sizeof(double),
                                    hipMemcpyDeviceToHost, stream));

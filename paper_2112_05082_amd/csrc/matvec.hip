@@ -15,6 +15,7 @@
 #include "matvec_internal.h"
 
 #include <algorithm>
+#include <hip/hip_fp16.h>
 #include <type_traits>
 
 namespace r3m {
@@ -344,12 +345,37 @@ near_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, c
 #ifndef R3M_FAR_WAVES_PER_EU
 #define R3M_FAR_WAVES_PER_EU 2
 #endif
-template <typename S, int QS, int kRch>
+// Two consecutive factor entries (complex index idx, even) in storage format
+// FT: the store precision itself, or an 8-byte split element
+// {re_hi | im_hi << 16, re_lo | im_lo << 16} decoded to hi + lo in FP32
+// (BF16X2), times the column scale sc (F16X2).
+template <typename S, int FT>
+__device__ __forceinline__ void load_factor2(const S* p, size_t idx, float sc, Cx<S>& a, Cx<S>& b) {
+  if constexpr (FT == R3M_BF16X2 || FT == R3M_F16X2) {
+    static_assert(sizeof(S) == 4, "split factors decode to FP32");
+    const uint4 w = *reinterpret_cast<const uint4*>(p + 2 * idx);
+    if constexpr (FT == R3M_BF16X2) {
+      a = {__uint_as_float(w.x << 16) + __uint_as_float(w.y << 16),
+           __uint_as_float(w.x & 0xffff0000u) + __uint_as_float(w.y & 0xffff0000u)};
+      b = {__uint_as_float(w.z << 16) + __uint_as_float(w.w << 16),
+           __uint_as_float(w.z & 0xffff0000u) + __uint_as_float(w.w & 0xffff0000u)};
+    } else {
+      auto h = [](uint32_t bits) { return __half2float(__ushort_as_half((unsigned short)(bits & 0xffffu))); };
+      a = {(h(w.x) + h(w.y)) * sc, (h(w.x >> 16) + h(w.y >> 16)) * sc};
+      b = {(h(w.z) + h(w.w)) * sc, (h(w.z >> 16) + h(w.w >> 16)) * sc};
+    }
+  } else {
+    (void)sc;
+    load2<S>(p, idx, a, b);
+  }
+}
+
+template <typename S, int QS, int kRch, int FT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R3M_FAR_WAVES_PER_EU)))
 far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, int groups,
            const uint8_t* __restrict__ states, const S* __restrict__ farf, const int* __restrict__ ranks,
-           int max_rank, int Dx, int Dy, int nr, int n, int n_a, int n_states, const S* __restrict__ x,
-           S* __restrict__ out, int64_t total_units, int lds_state_cap, int n_blocks) {
+           const float* __restrict__ fscale, int max_rank, int Dx, int Dy, int nr, int n, int n_a, int n_states,
+           const S* __restrict__ x, S* __restrict__ out, int64_t total_units, int lds_state_cap, int n_blocks) {
   extern __shared__ unsigned char smem_raw[];
   Cx<S>* lds_u = reinterpret_cast<Cx<S>*>(smem_raw);  // [2][kRch][n]
   Cx<S>* lds_v = lds_u + 2 * kRch * n;                 // [2][kRch][n]
@@ -398,7 +424,12 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
   // per-thread share of one staged slice: rows [rho0, rho0 + rc) of U and V
   constexpr int kPer = (kRch * 256 + 511) / 512;  // pairs per thread for one slice (n <= 256)
   Cx<S> pu[2 * kPer], pv[2 * kPer];
-  auto fetch = [&](const S* Uf, int rho0, int rc) {
+  // column scales of far block f (F16X2 only): U columns, then V columns
+  auto col_scale = [&](int f, int col) -> float {
+    return FT == R3M_F16X2 ? fscale[(size_t)f * 2 * max_rank + col] : 1.0f;
+  };
+  auto fetch = [&](int f, int rho0, int rc) {
+    const S* Uf = farf + (size_t)f * fstride;
     const int cnt = rc * n;
     const S* us = Uf + (size_t)rho0 * n * 2;
     const S* vs = Uf + (size_t)max_rank * n * 2 + (size_t)rho0 * n * 2;
@@ -406,8 +437,9 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
     for (int i = 0; i < kPer; ++i) {
       const int e2 = 2 * (tid + i * 256);
       if (e2 < cnt) {
-        load2<S>(us, e2, pu[2 * i], pu[2 * i + 1]);
-        load2<S>(vs, e2, pv[2 * i], pv[2 * i + 1]);
+        const int col = rho0 + e2 / n;
+        load_factor2<S, FT>(us, e2, col_scale(f, col), pu[2 * i], pu[2 * i + 1]);
+        load_factor2<S, FT>(vs, e2, col_scale(f, max_rank + col), pv[2 * i], pv[2 * i + 1]);
       }
     }
   };
@@ -450,7 +482,7 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
     const int dx = dx_lo + e % wdx, dy = dy_lo + e / wdx;
     f = far_index(dx, dy, Dx, Dy, nr);
     r = ranks[f];
-    fetch(farf + (size_t)f * fstride, 0, min(kRch, r));
+    fetch(f, 0, min(kRch, r));
     stash(min(kRch, r), 0);
   }
   __syncthreads();
@@ -463,7 +495,7 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
       const int dxn = dx_lo + en % wdx, dyn = dy_lo + en / wdx;
       fnext = far_index(dxn, dyn, Dx, Dy, nr);
       rnext = ranks[fnext];
-      fetch(farf + (size_t)fnext * fstride, 0, min(kRch, rnext));
+      fetch(fnext, 0, min(kRch, rnext));
     }
     const bool wave_active = wave_has_obs && !(ox_hi - dx < 0 || tx - dx > R.Lx - 1 || oy_hi - dy < 0 ||
                                                ty - dy > R.Ly - 1);
@@ -499,8 +531,9 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
         Cx<S>* dv = lds_v + ob * kRch * n;
         for (int e2 = 2 * tid; e2 < rc2 * n; e2 += 2 * blockDim.x) {
           Cx<S> a0, b0, a1, b1;
-          load2<S>(us, e2, a0, b0);
-          load2<S>(vs, e2, a1, b1);
+          const int col = rho0 + e2 / n;
+          load_factor2<S, FT>(us, e2, col_scale(f, col), a0, b0);
+          load_factor2<S, FT>(vs, e2, col_scale(f, max_rank + col), a1, b1);
           du[e2] = a0;
           du[e2 + 1] = b0;
           dv[e2] = a1;
@@ -943,8 +976,9 @@ void validate_store(const r3m_store* Z) {
               "near dtype must be C128 or C64");
   if (store_has_far(Z)) {
     R3M_REQUIRE(Z->far, R3M_ERR_INVALID_ARG, "far factors are NULL");
-    R3M_REQUIRE(Z->far_dtype == Z->near_dtype, R3M_ERR_UNSUPPORTED,
-                "far and near dtypes must match for this matvec");
+    R3M_REQUIRE(Z->far_dtype == Z->near_dtype ||
+                    (Z->near_dtype == R3M_C64 && (Z->far_dtype == R3M_BF16X2 || Z->far_dtype == R3M_F16X2)),
+                R3M_ERR_UNSUPPORTED, "far dtype must match the near dtype (or be split with a C64 near store)");
     R3M_REQUIRE(Z->max_rank >= 1 && Z->max_rank <= Z->n, R3M_ERR_INVALID_ARG, "bad max_rank");
   }
 }
@@ -965,11 +999,24 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
     const int lds_state_cap = bd.max_units <= 16384 ? (int)((bd.max_units + 15) / 16 * 16) : 0;
     constexpr int rch = sizeof(S) == 4 ? R3M_FAR_RCH_F32 : 4;
     const size_t lds = 4 * (size_t)rch * Z->n * 2 * sizeof(S) + lds_state_cap;
-    auto kern = n_a == 40 ? far_kernel<S, 10, rch> : far_kernel<S, 16, rch>;
+    decltype(&far_kernel<S, 10, rch, 0>) kern;
+    if constexpr (sizeof(S) == 4) {
+      if (Z->far_dtype == R3M_BF16X2)
+        kern = n_a == 40 ? far_kernel<S, 10, rch, R3M_BF16X2> : far_kernel<S, 16, rch, R3M_BF16X2>;
+      else if (Z->far_dtype == R3M_F16X2)
+        kern = n_a == 40 ? far_kernel<S, 10, rch, R3M_F16X2> : far_kernel<S, 16, rch, R3M_F16X2>;
+      else
+        kern = n_a == 40 ? far_kernel<S, 10, rch, 0> : far_kernel<S, 16, rch, 0>;
+    } else {
+      kern = n_a == 40 ? far_kernel<S, 10, rch, 0> : far_kernel<S, 16, rch, 0>;
+    }
+    const size_t body = ((size_t)n_far * 2 * Z->max_rank * Z->n * 2 * sizeof(S) + 255) / 256 * 256;
+    const float* fscale =
+        Z->far_dtype == R3M_F16X2 ? (const float*)((const char*)Z->far + head + body) : nullptr;
     const int nwg = (bd.n_tiles * groups + kXcd - 1) / kXcd * kXcd;
     hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), lds, stream, bd.rhs, bd.tiles, groups, states,
-                       (const S*)((const char*)Z->far + head), (const int*)Z->far, Z->max_rank, Z->Dx, Z->Dy,
-                       Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles);
+                       (const S*)((const char*)Z->far + head), (const int*)Z->far, fscale, Z->max_rank, Z->Dx,
+                       Z->Dy, Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles);
     R3M_CHECK_HIP(hipGetLastError());
   }
   if (near_on_mfma(Z)) {
