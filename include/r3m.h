@@ -230,7 +230,10 @@ typedef struct {
   int32_t converged;
 } r3m_gmres_report;
 
-size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch,
+/* Workspace of r3m_gmres_solve for (Z, Z64, batch, opts).  Z64 (nullable) is
+ * the refinement store the solve will be given; pass NULL when it runs
+ * without refinement. */
+size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const r3m_batch* batch,
                             const r3m_gmres_opts* opts);
 
 /* Solves the retrieved systems Z_k x_b = b_b (C128 vectors) with restarted

@@ -973,24 +973,18 @@ using namespace r3m;
 
 extern "C" {
 
-size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch,
+size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const r3m_batch* batch,
                             const r3m_gmres_opts* opts) {
   size_t out = 0;
   int rc = guarded(ctx, [&] {
     R3M_REQUIRE(ctx && opts, R3M_ERR_INVALID_ARG, "NULL argument");
     validate_store(Z);
+    if (Z64) validate_store(Z64);
     validate_batch(batch, Z->Dx, Z->Dy);
     R3M_REQUIRE(opts->restart >= 1 && opts->restart <= 1024, R3M_ERR_INVALID_ARG, "restart out of range");
     if (batch->B == 0) return;
     const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, 0);
-    // room for a refinement store of any layout in complex128: far groups plus
-    // the largest number of near groups, complex128 partials, plus a vector copy
-    const int n_a = Z->n / Z->n_states;
-    const size_t vec = (size_t)bd.total_units * n_a * 16;
-    const size_t mv = std::max(partials_and_x_bytes(bd, Z, max_groups(bd)),
-                               (size_t)(max_groups(bd) + 128) * vec + vec + 256);
-    out = layout_work(nullptr, bd, n_a, Z->n_states, opts->restart, mv, near_lists_bytes(Z, bd),
-                      near_lists_bytes_bound(Z->n_states, bd)).bytes;
+    out = gmres_bytes(ctx, Z, Z64, bd, opts->restart);
   });
   return rc == R3M_OK ? out : 0;
 }

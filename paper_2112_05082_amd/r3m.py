@@ -112,7 +112,8 @@ def load(path: str = LIB_PATH):
         "r3m_retrieved_matvec": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int, vp, vp, vp,
                                            sz, vp]),
         "r3m_matvec_groups": (i32, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
-        "r3m_gmres_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.POINTER(GmresOptsC)]),
+        "r3m_gmres_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(StoreC), C.POINTER(BatchC),
+                                      C.POINTER(GmresOptsC)]),
         "r3m_gmres_solve": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(StoreC), C.POINTER(BatchC), vp, vp,
                                       C.POINTER(GmresOptsC), C.POINTER(GmresReportC), vp, sz, vp]),
         "r3m_plane_wave_rhs": (C.c_int, [vp, C.POINTER(UnitGeomC), C.POINTER(BatchC), C.POINTER(C.c_double),
@@ -380,7 +381,10 @@ def matvec_groups(ctx, store: Store, batch: Batch) -> int:
     return g
 
 
-def gmres_work_bytes(ctx, store: Store, batch: Batch, restart: int):
+def gmres_work_bytes(ctx, store: Store, batch: Batch, restart: int, store64: Store | None = None):
+    """store64: the refinement store the solve will use (None: no refinement)."""
     sc = store.c()
+    s64 = store64.c() if store64 is not None else None
     opts = GmresOptsC(1e-6, int(restart), 1, 0.0, 0, 0, 0)
-    return load().r3m_gmres_work_bytes(ctx.handle, C.byref(sc), C.byref(batch.cs), C.byref(opts))
+    return load().r3m_gmres_work_bytes(ctx.handle, C.byref(sc), C.byref(s64) if s64 is not None else None,
+                                       C.byref(batch.cs), C.byref(opts))

@@ -1,0 +1,177 @@
+"""Batched and large workloads: many codebooks, array sizes and incidence
+angles sharing one store (Sec. III-A: one global matrix, many retrievals).
+
+  * reduced batch, solved: 1-bit codebooks of sizes 4, 6 and 8 from the three
+    families (Bernoulli, 4x4 checkerboard, stripes), each at four incidence
+    angles sharing its mask, one store sized for 8 x 8 (complex64 near blocks,
+    split BF16 far factors), FP64 refinement to 1e-6 on the complex128 store
+    of the same ACA, all right-hand sides in one solver call.  Reference: the
+    plain FP64 GPU path (all blocks dense complex128, solved to 1e-10), and for
+    the 4 x 4 codebooks dense LU on the oracle's direct system;
+  * full-size batch, one matvec: 384 codebooks (128 each at 32 x 32, 48 x 48
+    and 64 x 64) x 4 angles = 1,536 right-hand sides over one store sized for
+    64 x 64, split BF16 far factors; three right-hand sides checked against
+    the plain complex128 path (the same codebooks in a batch of their own);
+  * large array, one matvec: 16 Bernoulli codebooks of 128 x 128 units,
+    split FP16 far factors of rank <= 12; two right-hand sides checked against
+    the plain complex128 path.
+Tolerances: RCS 1e-4 (the workload's bar) and refinement residual 1e-6 for the
+solve; for the matvecs the ACA level, 3x the largest achieved block error
+plus the split-format error (1e-5).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import FREQ, K, rel_l2, unit  # noqa: E402
+from oracle import efie, excitation, farfield, solve  # noqa: E402
+from workloads import codebooks as cb  # noqa: E402
+from workloads.configs import batched_1bit, large_128x128  # noqa: E402
+
+DEV = "cuda:0"
+ANGLES = (0.0, 20.0, 40.0, 60.0)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_05082_amd import pipeline, r3m
+    r3m.load()
+    ctx = r3m.Context(0)
+    geom = r3m.UnitGeom.from_macro(unit(1), FREQ, 1)
+    yield r3m, pipeline, ctx, geom
+    ctx.close()
+
+
+def incidences(n_books):
+    return [[np.deg2rad(a), 0.0, 1.0] for _ in range(n_books) for a in ANGLES]
+
+
+def test_batched_solve_reduced(lib):
+    r3m, pipeline, ctx, geom = lib
+    books, sizes = [], []
+    for L in (4, 6, 8):
+        for c in range(3):
+            books.append(cb.family(c, L, 2000 + 10 * L))
+            sizes.append(L)
+    batch = r3m.Batch.from_codebooks(books, sizes, DEV, repeat=len(ANGLES))
+    D = 7
+    dense = pipeline.fill_blocks(ctx, geom, D, r3m.C128, DEV)
+    s_bf = pipeline.compressed_store(ctx, geom, 8, 2, r3m.C64, r3m.BF16X2, 1e-4, 12, DEV, dense_c128=dense)
+    s_64 = pipeline.compressed_store(ctx, geom, 8, 2, r3m.C128, r3m.C128, 1e-4, 12, DEV, dense_c128=dense)
+    plain = r3m.Store(80, 2, D, D, D, r3m.C128, dense)
+    N = batch.total_units * 40
+    b = torch.zeros(N, dtype=torch.complex128, device=DEV)
+    r3m.r3m_plane_wave_rhs(ctx, geom, batch, incidences(len(books)), b)
+    dirs = cb.phi0_cut(5.0)
+
+    def run(st, st64, tol, refine_tol, restart):
+        x = torch.zeros_like(b)
+        work = torch.empty(r3m.gmres_work_bytes(ctx, st, batch, restart, st64), dtype=torch.uint8, device=DEV)
+        _, rep = r3m.r3m_gmres_solve(ctx, st, st64, batch, b, x, tol, restart, 3000, work, refine_tol=refine_tol,
+                                     max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI)
+        sig = torch.zeros(batch.B * len(dirs), dtype=torch.float64, device=DEV)
+        r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), sig.cpu().numpy().reshape(batch.B, -1), rep
+
+    _, s_ref, rep_ref = run(plain, None, 1e-10, 0.0, 60)
+    assert all(r[3] for r in rep_ref)
+    x_mix, s_mix, rep = run(s_bf, s_64, 1e-3, 1e-6, 30)
+    assert all(r[3] and r[2] <= 1e-6 for r in rep)
+    errs = [rel_l2(s_mix[i], s_ref[i]) for i in range(batch.B)]
+    print(f"batched reduced: {batch.B} RHS, max RCS error {max(errs):.2e}, "
+          f"refine steps {sorted(set(r[1] for r in rep))}")
+    assert max(errs) <= 1e-4
+    # oracle anchor: the 4 x 4 codebooks at every angle, dense LU on the direct system
+    u1 = unit(1)
+    for c in range(3):
+        st = books[c]
+        Zk = efie.direct_system(u1, st, 4, K, 1)
+        mesh, _ = efie.active_array_mesh(u1, st, 4)
+        for a, ang in enumerate(ANGLES):
+            r = c * len(ANGLES) + a
+            I = solve.lu_solve(Zk, excitation.plane_wave(mesh, K, np.deg2rad(ang), 0.0))
+            sref = farfield.rcs(mesh, I, K, dirs)
+            assert rel_l2(s_mix[r], sref) <= 1e-4
+
+
+def aca_bound(store):
+    return 3.0 * float(store.rel_err.max()) + 1e-5
+
+
+def sub_batch(r3m, books, sizes, rhs, repeat):
+    """The codebooks of the chosen right-hand sides in a batch of their own."""
+    return r3m.Batch.from_codebooks([books[r // repeat] for r in rhs], [sizes[r // repeat] for r in rhs], DEV)
+
+
+def test_batched_fullsize_matvec(lib):
+    r3m, pipeline, ctx, geom = lib
+    w = batched_1bit(128)
+    rep = len(w.angles_deg)
+    batch = r3m.Batch.from_codebooks(w.codebooks, w.sizes, DEV, repeat=rep)
+    assert batch.B == 1536
+    D = 63
+    dense = pipeline.fill_blocks(ctx, geom, D, r3m.C128, DEV)
+    store = pipeline.compressed_store(ctx, geom, 64, 2, r3m.C64, r3m.BF16X2, 1e-4, 12, DEV, dense_c128=dense)
+    plain = r3m.Store(80, 2, D, D, D, r3m.C128, dense)
+    N = batch.total_units * 40
+    g = torch.Generator(device=DEV).manual_seed(7)
+    x = torch.complex(torch.randn(N, generator=g, device=DEV), torch.randn(N, generator=g, device=DEV))
+    y = torch.zeros_like(x)
+    work = torch.empty(r3m.matvec_work_bytes(ctx, store, batch, r3m.C64), dtype=torch.uint8, device=DEV)
+    r3m.r3m_retrieved_matvec(ctx, store, batch, r3m.C64, x, y, work)
+    torch.cuda.synchronize()
+    del work
+    rhs = [5, 512 + 6, 1024 + 7]  # one right-hand side of each array size
+    sub = sub_batch(r3m, w.codebooks, w.sizes, rhs, rep)
+    offs = batch.unit_off[rhs] * 40
+    lens = np.array([w.sizes[r // rep] ** 2 * 40 for r in rhs])
+    xs = torch.cat([x[o:o + n] for o, n in zip(offs, lens)]).to(torch.complex128)
+    ys = torch.zeros_like(xs)
+    wp = torch.empty(max(r3m.matvec_work_bytes(ctx, plain, sub, r3m.C128), 16), dtype=torch.uint8, device=DEV)
+    r3m.r3m_retrieved_matvec(ctx, plain, sub, r3m.C128, xs, ys, wp)
+    torch.cuda.synchronize()
+    ys = ys.cpu().numpy()
+    yb = np.concatenate([y[o:o + n].cpu().numpy() for o, n in zip(offs, lens)])
+    so = np.concatenate([[0], np.cumsum(lens)])
+    errs = [rel_l2(yb[so[i]:so[i + 1]], ys[so[i]:so[i + 1]]) for i in range(3)]
+    print(f"batched full size: 1536 RHS, errors vs plain {['%.2e' % e for e in errs]}, "
+          f"max ACA error {store.rel_err.max():.2e}, mean rank {store.ranks.mean():.2f}")
+    assert max(errs) <= aca_bound(store)
+
+
+def test_large_matvec(lib):
+    r3m, pipeline, ctx, geom = lib
+    w = large_128x128(16)
+    batch = r3m.Batch.from_codebooks(w.codebooks, w.sizes, DEV)
+    D = 127
+    dense = pipeline.fill_blocks(ctx, geom, D, r3m.C128, DEV)
+    store = pipeline.compressed_store(ctx, geom, 128, 2, r3m.C64, r3m.F16X2, 1e-4, 12, DEV, dense_c128=dense)
+    plain = r3m.Store(80, 2, D, D, D, r3m.C128, dense)
+    N = batch.total_units * 40
+    g = torch.Generator(device=DEV).manual_seed(8)
+    x = torch.complex(torch.randn(N, generator=g, device=DEV), torch.randn(N, generator=g, device=DEV))
+    y = torch.zeros_like(x)
+    work = torch.empty(r3m.matvec_work_bytes(ctx, store, batch, r3m.C64), dtype=torch.uint8, device=DEV)
+    r3m.r3m_retrieved_matvec(ctx, store, batch, r3m.C64, x, y, work)
+    torch.cuda.synchronize()
+    del work
+    n1 = 128 * 128 * 40
+    errs = []
+    for r in (0, 15):
+        sub = sub_batch(r3m, w.codebooks, w.sizes, [r], 1)
+        xs = x[r * n1:(r + 1) * n1].to(torch.complex128)
+        ys = torch.zeros_like(xs)
+        wp = torch.empty(max(r3m.matvec_work_bytes(ctx, plain, sub, r3m.C128), 16), dtype=torch.uint8,
+                         device=DEV)
+        r3m.r3m_retrieved_matvec(ctx, plain, sub, r3m.C128, xs, ys, wp)
+        torch.cuda.synchronize()
+        errs.append(rel_l2(y[r * n1:(r + 1) * n1].cpu().numpy(), ys.cpu().numpy()))
+    print(f"large 128x128 x16: errors vs plain {['%.2e' % e for e in errs]}, max ACA error "
+          f"{store.rel_err.max():.2e}, ranks at cap {(store.ranks == 12).sum()} of {len(store.ranks)}")
+    assert max(errs) <= aca_bound(store)

@@ -147,7 +147,7 @@ def test_split_refined_solve(stores):
 
     def run(st, st64, tol, refine_tol):
         x = torch.zeros_like(b)
-        work = torch.empty(r3m.gmres_work_bytes(ctx, st, batch, 30), dtype=torch.uint8, device=DEV)
+        work = torch.empty(r3m.gmres_work_bytes(ctx, st, batch, 30, st64), dtype=torch.uint8, device=DEV)
         _, rep = r3m.r3m_gmres_solve(ctx, st, st64, batch, b, x, tol, 30, 2000, work, refine_tol=refine_tol,
                                      max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI)
         sig = torch.zeros(2 * len(dirs), dtype=torch.float64, device=DEV)

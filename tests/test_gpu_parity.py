@@ -356,7 +356,7 @@ def test_mixed_refinement_to_fp64(r3m, ctx, stores_2bit_8):
     b = torch.zeros(2 * 2560, dtype=torch.complex128, device=DEV)
     r3m.r3m_plane_wave_rhs(ctx, g, batch, [[0.0, 0.0, 1.0], [0.3, 0.0, 1.0]], b)
     x = torch.zeros_like(b)
-    work = torch.empty(r3m.gmres_work_bytes(ctx, s64, batch, 60), dtype=torch.uint8, device=DEV)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, s64, batch, 60, s128), dtype=torch.uint8, device=DEV)
     rc, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, 1e-4, 60, 3000, work, refine_tol=1e-10,
                                   max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI)
     assert all(r[3] and r[2] <= 1e-10 and r[1] >= 2 for r in rep)
