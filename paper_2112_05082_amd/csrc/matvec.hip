@@ -107,7 +107,7 @@ __device__ __forceinline__ double quad_swap2(double v) {
 // next rank are issued before the products of the current one (scheduling
 // barriers keep that order), so one rank of FMAs covers their latency.
 #ifndef R3M_FAR_DEPTH
-#define R3M_FAR_DEPTH 2
+#define R3M_FAR_DEPTH 1
 #endif
 constexpr int kFarDepth = R3M_FAR_DEPTH;  // factor rows read ahead of their products
 
@@ -339,11 +339,17 @@ near_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, c
 // (unit u, quarter q) forms its quarter of t = V[A(s_j)]^H x_j, the unit's
 // four lanes add their parts with two lane swaps, and the lane expands its own
 // rows y += U[A(s_i)] t.  Ranks above kRch take extra synchronous slices.
+// complex64: 4-rank slices (most ranks are 4 at tol 1e-4), three waves per
+// SIMD at 40 rows per state; complex128 and 64 rows per state: two waves
+// per SIMD (register bound)
 #ifndef R3M_FAR_RCH_F32
-#define R3M_FAR_RCH_F32 8
+#define R3M_FAR_RCH_F32 4
 #endif
-#ifndef R3M_FAR_WAVES_PER_EU
-#define R3M_FAR_WAVES_PER_EU 2
+#ifndef R3M_FAR_WAVES_PER_EU_F32
+#define R3M_FAR_WAVES_PER_EU_F32 3
+#endif
+#ifndef R3M_FAR_WAVES_PER_EU_F64
+#define R3M_FAR_WAVES_PER_EU_F64 2
 #endif
 // Two consecutive factor entries (complex index idx, even) in storage format
 // FT: the store precision itself, or an 8-byte split element
@@ -371,7 +377,9 @@ __device__ __forceinline__ void load_factor2(const S* p, size_t idx, float sc, C
 }
 
 template <typename S, int QS, int kRch, int FT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(R3M_FAR_WAVES_PER_EU)))
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((sizeof(S) == 4 && QS <= 10) ? R3M_FAR_WAVES_PER_EU_F32
+                                                                : R3M_FAR_WAVES_PER_EU_F64)))
 far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, int groups,
            const uint8_t* __restrict__ states, const S* __restrict__ farf, const int* __restrict__ ranks,
            const float* __restrict__ fscale, int max_rank, int Dx, int Dy, int nr, int n, int n_a, int n_states,
