@@ -146,14 +146,20 @@ def main():
     t_compress = time.perf_counter() - t0
     plain = r3m.Store(n, 4, L - 1, L - 1, L - 1, r3m.C128, dense)
 
+    # device buffers of a solve, allocated once per store (a serving loop reuses them)
+    bufs = {}
+
     def solve(st, tol, restart):
-        b = torch.zeros(N, dtype=torch.complex128, device=dev)
+        key = id(st)
+        if key not in bufs:
+            bufs[key] = (torch.zeros(N, dtype=torch.complex128, device=dev),
+                         torch.empty(r3m.gmres_work_bytes(ctx, st, batch, restart), dtype=torch.uint8, device=dev))
+        b, work = bufs[key]
         r3m.r3m_plane_wave_rhs(ctx, geom, batch, inc, b)
-        x = torch.zeros_like(b)
-        work = torch.empty(r3m.gmres_work_bytes(ctx, st, batch, restart), dtype=torch.uint8, device=dev)
+        x = torch.empty_like(b)
         _, rep = r3m.r3m_gmres_solve(ctx, st, None, batch, b, x, tol, restart, args.max_iter, work,
                                      allow_not_converged=True, precond=args.precond)
-        sig = torch.zeros(len(dirs), dtype=torch.float64, device=dev)
+        sig = torch.empty(len(dirs), dtype=torch.float64, device=dev)
         r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
         return x, sig, rep
 

@@ -233,6 +233,9 @@ int r3m_ctx_destroy(r3m_ctx ctx) {
   if (ctx->work_stream) (void)hipStreamDestroy(ctx->work_stream);
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  for (hipEvent_t e : ctx->ev_run)
+    if (e) (void)hipEventDestroy(e);
+  if (ctx->run_host) (void)hipHostFree(ctx->run_host);
   ctx->flag.release();
   ctx->geom.release();
   for (auto& kv : ctx->batches) {

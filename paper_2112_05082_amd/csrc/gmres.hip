@@ -248,11 +248,14 @@ __device__ double2 block_sum2(double2 v, double2* sh) {
 __global__ void __launch_bounds__(kDotThreads)
 dots_partials_kernel(const double2* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
                      const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
-                     int* __restrict__ n_running) {
+                     int* __restrict__ reset, const int* __restrict__ live) {
   __shared__ double2 sh[kDotThreads / 64][kDotVec];
   const int p = blockIdx.x, grp = blockIdx.y, b = blockIdx.z;
   const int tid = threadIdx.x, wave = tid >> 6;
-  if (n_running && p == 0 && grp == 0 && b == 0 && tid == 0) *n_running = 0;
+  // this step's running count starts at zero (done before the exit test, so a
+  // skipped step still leaves it zero for the next one)
+  if (reset && p == 0 && grp == 0 && b == 0 && tid == 0) *reset = 0;
+  if (live && *live == 0) return;
   const RhsVec r = rv[b];
   const int64_t P = (r.N + kDotChunk - 1) / kDotChunk;
   if (p >= P) return;
@@ -318,7 +321,8 @@ __global__ void __launch_bounds__(256)
 gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
                  const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int nvec,
                  int64_t ut, int do_norm, double* __restrict__ npart, int maxB, double2* __restrict__ H, int m,
-                 int j, int mode) {
+                 int j, int mode, const int* __restrict__ run_prev) {
+  if (run_prev && *run_prev == 0) return;
   extern __shared__ double2 hb[];
   __shared__ double2 sh[4];
   __shared__ double2 part[3][64];
@@ -403,7 +407,8 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
                       RhsState* __restrict__ st, const double* __restrict__ npart, int maxB,
                       double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
                       double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
-                      double* __restrict__ wn, int64_t ut) {
+                      double* __restrict__ wn, int64_t ut, const int* __restrict__ live) {
+  if (live && *live == 0) return;
   __shared__ double nv_s;
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
@@ -515,8 +520,10 @@ __global__ void zero_kernel(double2* __restrict__ x, const RhsVec* __restrict__ 
 // start of a cycle: beta = ||r||, V_0 = r / beta, g = (beta, 0, ...), jdone = -1
 __global__ void cycle_start_kernel(const double2* __restrict__ r, double2* __restrict__ V,
                                    const RhsVec* __restrict__ rv, RhsState* __restrict__ st,
-                                   const double2* __restrict__ nrm2, double2* __restrict__ g, int m) {
+                                   const double2* __restrict__ nrm2, double2* __restrict__ g, int m,
+                                   int* __restrict__ live0) {
   const int b = blockIdx.y;
+  if (blockIdx.x == 0 && b == 0 && threadIdx.x == 0) *live0 = 1;  // step 0 runs
   const RhsVec rr = rv[b];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double beta = sqrt(fmax(nrm2[b].x, 0.0));
@@ -622,7 +629,9 @@ selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a,
 template <typename OT>
 __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
                                      const int64_t* __restrict__ soff, const RhsVec* __restrict__ rv, int n_a,
-                                     int n_states, const double2* __restrict__ in, OT* __restrict__ out) {
+                                     int n_states, const double2* __restrict__ in, OT* __restrict__ out,
+                                     const int* __restrict__ live) {
+  if (live && *live == 0) return;
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -644,7 +653,8 @@ __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uin
 
 template <typename OT>
 __global__ void convert_vec_kernel(const RhsVec* __restrict__ rv, const double2* __restrict__ in,
-                                   OT* __restrict__ out) {
+                                   OT* __restrict__ out, const int* __restrict__ live) {
+  if (live && *live == 0) return;
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -812,43 +822,49 @@ struct GmresRun {
 
   void precond(const double2* in, double2* out) {
     hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff, W.rv,
-                       n_a, n_states, in, (double*)out);
+                       n_a, n_states, in, (double*)out, (const int*)nullptr);
   }
+
+  // Running-RHS counts of Arnoldi step j live in two slots used in turn: step
+  // j's Givens steps count into run_slot(j); every kernel of step j + 1 returns
+  // at once if run_slot(j) is zero (all right-hand sides converged), so steps
+  // launched past convergence cost only their launches.
+  int* run_slot(int j) const { return W.counters + 4 + (j & 1); }
 
   // w = Z M^{-1} v (or Z v): the preconditioner writes the matvec input in
   // the store precision directly
-  void apply_operator(const r3m_store* Z, const double2* v) {
+  void apply_operator(const r3m_store* Z, const double2* v, const int* live) {
     const bool c64 = Z->near_dtype == R3M_C64;
     const void* xin = v;
     if (pre) {
       if (c64)
         hipLaunchKernelGGL(apply_precond_kernel<float>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (float*)W.xs);
+                           W.rv, n_a, n_states, v, (float*)W.xs, live);
       else
         hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (double*)W.xs);
+                           W.rv, n_a, n_states, v, (double*)W.xs, live);
       xin = W.xs;
     } else if (c64) {
-      hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs);
+      hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs, live);
       xin = W.xs;
     }
-    launch_matvec_pre(Z, *bd, batch->states, xin, W.w, W.mv_partial, lists_for(Z), G, s);
+    launch_matvec_pre(Z, *bd, batch->states, xin, W.w, W.mv_partial, lists_for(Z), G, s, live);
   }
 
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
-    apply_operator(Z, W.V + (int64_t)j * ut);
+    const int* live = run_slot(j - 1);  // j = 0: set by the cycle start
+    apply_operator(Z, W.V + (int64_t)j * ut, live);
     const dim3 dgrid(maxP, (j + 1 + kDotVec - 1) / kDotVec, B);
     const int maxB = (int)((maxN + 63) / 64 + 1);
     for (int pass = 0; pass < 2; ++pass) {
       hipLaunchKernelGGL(dots_partials_kernel, dgrid, dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, j + 1, maxP,
-                         W.dpart, pass == 0 ? W.counters : (int*)nullptr);
+                         W.dpart, pass == 0 ? run_slot(j) : (int*)nullptr, live);
       hipLaunchKernelGGL(gs_update_kernel, dim3(ceil_div((size_t)maxN, 64), B), dim3(256),
                          (size_t)(j + 1) * sizeof(double2), s, W.V, W.w, W.rv, W.st, W.dpart, maxP, j + 1, ut, pass,
-                         W.npart, maxB, W.H, m, j, pass);
+                         W.npart, maxB, W.H, m, j, pass, live);
     }
     hipLaunchKernelGGL(normalize_step_kernel, vgrid(), dim3(256), (size_t)(2 * m + 2) * 16 + (size_t)m * 8, s, W.w,
-                       W.V, W.rv, W.st, W.npart, maxB, W.H,
-                       W.g, W.cs, W.sn, m, j, tol, W.counters, W.wn, ut);
+                       W.V, W.rv, W.st, W.npart, maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live);
     R3M_CHECK_HIP(hipGetLastError());
   }
 
@@ -895,21 +911,34 @@ struct GmresRun {
     R3M_CHECK_HIP(hipGraphLaunch(it->second, s));
   }
 
-  // GMRES(m) on Z for rhs into sol (initial guess kept), for RHS with running[b];
-  // the tolerance is relative to rhs_norm[b]; iters[b] accumulates iterations.
-  void solve(const r3m_store* Z, const double2* rhs, double2* sol, std::vector<int> running,
-             const std::vector<double>& rhs_norm, double tol, int max_iter, std::vector<int>& iters) {
+  // GMRES(m) on Z for rhs into sol, for RHS with running[b]; sol is zero on
+  // entry when x_zero (the first residual is then rhs itself).  The tolerance
+  // is relative to rhs_norm[b]; iters[b] accumulates iterations.  Returns the
+  // residual norms ||rhs - Z sol|| at exit.
+  std::vector<double> solve(const r3m_store* Z, const double2* rhs, double2* sol, std::vector<int> running,
+                            const std::vector<double>& rhs_norm, double tol, int max_iter, std::vector<int>& iters,
+                            bool x_zero) {
     std::vector<RhsState> hst(B);
+    std::vector<double> rnorm(B, 0.0);
+    bool first = true;
     while (true) {
-      residual(Z, rhs, sol, W.r);
-      norms(W.r);
-      std::vector<double2> nr(B);
-      R3M_CHECK_HIP(hipMemcpyAsync(nr.data(), W.nrm, (size_t)B * 16, hipMemcpyDeviceToHost, s));
-      R3M_CHECK_HIP(hipStreamSynchronize(s));
+      if (first && x_zero) {
+        R3M_CHECK_HIP(hipMemcpyAsync(W.r, rhs, (size_t)ut * 16, hipMemcpyDeviceToDevice, s));
+        norms(W.r);
+        rnorm = rhs_norm;
+      } else {
+        residual(Z, rhs, sol, W.r);
+        norms(W.r);
+        std::vector<double2> nr(B);
+        R3M_CHECK_HIP(hipMemcpyAsync(nr.data(), W.nrm, (size_t)B * 16, hipMemcpyDeviceToHost, s));
+        R3M_CHECK_HIP(hipStreamSynchronize(s));
+        for (int b = 0; b < B; ++b) rnorm[b] = std::sqrt(std::max(nr[b].x, 0.0));
+      }
+      first = false;
       bool any = false;
       int min_used = max_iter;
       for (int b = 0; b < B; ++b) {
-        const double rel = rhs_norm[b] > 0 ? std::sqrt(std::max(nr[b].x, 0.0)) / rhs_norm[b] : 0.0;
+        const double rel = rhs_norm[b] > 0 ? rnorm[b] / rhs_norm[b] : 0.0;
         if (running[b] && (!(rel > tol) || iters[b] >= max_iter)) running[b] = 0;
         hst[b] = RhsState{rhs_norm[b], 0.0, rel, -1, running[b]};
         if (running[b]) {
@@ -920,18 +949,25 @@ struct GmresRun {
       if (!any) break;
       R3M_CHECK_HIP(hipMemcpyAsync(W.st, hst.data(), (size_t)B * sizeof(RhsState), hipMemcpyHostToDevice, s));
       dim3 g0(std::max(ceil_div((size_t)maxN, 256), ceil_div((size_t)m + 1, 256)), B);
-      hipLaunchKernelGGL(cycle_start_kernel, g0, dim3(256), 0, s, W.r, W.V, W.rv, W.st, W.nrm, W.g, m);
+      hipLaunchKernelGGL(cycle_start_kernel, g0, dim3(256), 0, s, W.r, W.V, W.rv, W.st, W.nrm, W.g, m, run_slot(-1));
       const int steps = std::max(1, std::min(m, max_iter - min_used));
-      int j = 0;
-      for (int j0 = 0; j0 < steps; j0 += kCheckEvery) {
+      // Blocks of kCheckEvery steps.  The running count after a block is read
+      // back asynchronously while the next block is already queued: the host
+      // stops launching once a read-back shows zero, and the steps launched
+      // past that point return at once on the device.
+      int j = 0, k = 0;
+      for (int j0 = 0; j0 < steps; j0 += kCheckEvery, ++k) {
         const int j1 = std::min(j0 + kCheckEvery, steps);
         run_steps(Z, j0, j1, tol);
         j = j1;
         if (j1 < steps) {
-          int nrun = 0;
-          R3M_CHECK_HIP(hipMemcpyAsync(&nrun, W.counters, sizeof(int), hipMemcpyDeviceToHost, s));
-          R3M_CHECK_HIP(hipStreamSynchronize(s));
-          if (nrun == 0) break;
+          R3M_CHECK_HIP(hipMemcpyAsync(ctx->run_host + (k & 1), run_slot(j1 - 1), sizeof(int),
+                                       hipMemcpyDeviceToHost, s));
+          R3M_CHECK_HIP(hipEventRecord(ctx->ev_run[k & 1], s));
+        }
+        if (k >= 1) {
+          R3M_CHECK_HIP(hipEventSynchronize(ctx->ev_run[(k - 1) & 1]));
+          if (ctx->run_host[(k - 1) & 1] == 0) break;
         }
       }
       hipLaunchKernelGGL(finalize_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, W.st, B, j);
@@ -949,6 +985,7 @@ struct GmresRun {
       for (int b = 0; b < B; ++b)
         if (hst[b].active) iters[b] += hst[b].jdone;
     }
+    return rnorm;
   }
 
   int flag_check(int mask) {
@@ -1024,6 +1061,10 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
       R3M_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
       R3M_CHECK_HIP(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
     }
+    if (!ctx->run_host) {
+      R3M_CHECK_HIP(hipHostMalloc((void**)&ctx->run_host, 2 * sizeof(int), hipHostMallocDefault));
+      for (hipEvent_t& e : ctx->ev_run) R3M_CHECK_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
     R3M_CHECK_HIP(hipEventRecord(ctx->ev_in, stream));
     R3M_CHECK_HIP(hipStreamWaitEvent(ctx->work_stream, ctx->ev_in, 0));
     const hipStream_t user_stream = stream;
@@ -1064,18 +1105,14 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     R3M_CHECK_HIP(hipMemcpyAsync(run.W.soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice, stream));
     R3M_CHECK_HIP(hipMemsetAsync(run.W.counters, 0, 256, stream));
 
+    R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE || opts->precond == R3M_PRECOND_BLOCK_JACOBI,
+                R3M_ERR_INVALID_ARG, "unknown preconditioner");
     // input checks on the device: state bytes and finite right-hand sides
     const int64_t maxU = run.maxN / n_a;
     hipLaunchKernelGGL(states_check_kernel, dim3(ceil_div((size_t)maxU, 256), bd.B), dim3(256), 0, stream,
                        batch->states, run.W.rv, run.W.soff, n_a, Z->n_states, run.W.counters + 1);
     hipLaunchKernelGGL(nonfinite_kernel, run.vgrid(), dim3(256), 0, stream, (const double2*)b_dev, run.W.rv,
                        run.W.counters + 1);
-    const int f = run.flag_check(6);
-    R3M_REQUIRE(!(f & 2), R3M_ERR_INVALID_ARG, "codebook state out of range");
-    R3M_REQUIRE(!(f & 4), R3M_ERR_NONFINITE, "non-finite right-hand side");
-
-    R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE || opts->precond == R3M_PRECOND_BLOCK_JACOBI,
-                R3M_ERR_INVALID_ARG, "unknown preconditioner");
     run.n_states = Z->n_states;
     if (opts->precond == R3M_PRECOND_BLOCK_JACOBI) {
       run.pre = true;
@@ -1089,8 +1126,12 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
         hipLaunchKernelGGL(selfblock_inverse_kernel<float>, dim3(Z->n_states), dim3(256), lds, stream,
                            (const float*)Z->near, slot0, Z->n, n_a, run.W.Minv, run.W.counters + 1);
       R3M_CHECK_HIP(hipGetLastError());
-      R3M_REQUIRE(!run.flag_check(8), R3M_ERR_NONFINITE, "singular self block in the preconditioner");
     }
+    // one read-back for the input checks and the preconditioner's pivots
+    const int f = run.flag_check(14);
+    R3M_REQUIRE(!(f & 2), R3M_ERR_INVALID_ARG, "codebook state out of range");
+    R3M_REQUIRE(!(f & 4), R3M_ERR_NONFINITE, "non-finite right-hand side");
+    R3M_REQUIRE(!(f & 8), R3M_ERR_NONFINITE, "singular self block in the preconditioner");
     const double2* b = (const double2*)b_dev;
     double2* x = (double2*)x_dev;
     // near retrieval lists of this codebook (fixed for the whole solve)
@@ -1101,7 +1142,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
       const void* xin = b;
       if (Z->near_dtype == R3M_C64) {
         hipLaunchKernelGGL(convert_vec_kernel<float>, run.vgrid(), dim3(256), 0, stream, run.W.rv, b,
-                           (float*)run.W.xs);
+                           (float*)run.W.xs, (const int*)nullptr);
         xin = run.W.xs;
       }
       run.G = tuned_groups(ctx, Z, bd, batch->states, xin, run.W.w, run.W.mv_partial, run.W.lists, stream);
@@ -1126,14 +1167,14 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
         }
         if (!any || step == max_refine) break;
         hipLaunchKernelGGL(zero_kernel, run.vgrid(), dim3(256), 0, stream, run.W.d, run.W.rv);
-        run.solve(Z, run.W.ro, run.W.d, act, rn, opts->tol, opts->max_iter, iters);
+        run.solve(Z, run.W.ro, run.W.d, act, rn, opts->tol, opts->max_iter, iters, true);
         hipLaunchKernelGGL(add_kernel, run.vgrid(), dim3(256), 0, stream, x, run.W.d, run.W.rv);
         for (int i = 0; i < bd.B; ++i) refine_steps[i] += act[i];
       }
     } else {
-      run.solve(Z, b, x, std::vector<int>(bd.B, 1), bnorm, opts->tol, opts->max_iter, iters);
-      run.residual(Z, b, x, run.W.r);
-      std::vector<double> rn = run.host_norms(run.W.r);
+      // the true residual at exit comes back from the solve's last check
+      const std::vector<double> rn =
+          run.solve(Z, b, x, std::vector<int>(bd.B, 1), bnorm, opts->tol, opts->max_iter, iters, true);
       for (int i = 0; i < bd.B; ++i) rel[i] = bnorm[i] > 0 ? rn[i] / bnorm[i] : 0.0;
     }
     hipLaunchKernelGGL(nonfinite_kernel, run.vgrid(), dim3(256), 0, stream, (const double2*)x, run.W.rv,

@@ -383,7 +383,9 @@ __attribute__((amdgpu_waves_per_eu((sizeof(S) == 4 && QS <= 10) ? R3M_FAR_WAVES_
 far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, int groups,
            const uint8_t* __restrict__ states, const S* __restrict__ farf, const int* __restrict__ ranks,
            const float* __restrict__ fscale, int max_rank, int Dx, int Dy, int nr, int n, int n_a, int n_states,
-           const S* __restrict__ x, S* __restrict__ out, int64_t total_units, int lds_state_cap, int n_blocks) {
+           const S* __restrict__ x, S* __restrict__ out, int64_t total_units, int lds_state_cap, int n_blocks,
+           const int* __restrict__ live) {
+  if (live && *live == 0) return;  // every right-hand side has converged
   extern __shared__ unsigned char smem_raw[];
   Cx<S>* lds_u = reinterpret_cast<Cx<S>*>(smem_raw);  // [2][kRch][n]
   Cx<S>* lds_v = lds_u + 2 * kRch * n;                 // [2][kRch][n]
@@ -587,7 +589,8 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
 template <typename S, typename XT>
 __global__ void __launch_bounds__(256)
 reduce_groups_kernel(const RhsDev* __restrict__ rhs, const S* __restrict__ partial, int slots,
-                     int64_t total_units, int n_a, XT* __restrict__ y) {
+                     int64_t total_units, int n_a, XT* __restrict__ y, const int* __restrict__ live) {
+  if (live && *live == 0) return;  // every right-hand side has converged
   const RhsDev R = rhs[blockIdx.y];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= (int64_t)R.Lx * R.Ly * n_a) return;
@@ -754,7 +757,8 @@ template <typename S, int NA>
 __global__ void __launch_bounds__(256)
 near_mfma_kernel(const NearItem* __restrict__ items, const int* __restrict__ n_items,
                  const NearPair* __restrict__ pairs, const S* __restrict__ near, int n, int n_states,
-                 const S* __restrict__ x, S* __restrict__ out, int64_t total_units) {
+                 const S* __restrict__ x, S* __restrict__ out, int64_t total_units, const int* __restrict__ live) {
+  if (live && *live == 0) return;  // every right-hand side has converged
   constexpr int K2 = 2 * NA, MT = K2 / 16, KT = K2 / 4, XS = K2 + 1;
   constexpr int KC = 4;  // K steps whose operands are read before their MFMAs
   static_assert(KT % KC == 0, "K steps per chunk");
@@ -993,7 +997,8 @@ void validate_store(const r3m_store* Z) {
 
 template <typename S, typename XT>
 static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const S* xs, XT* y,
-                        char* part, const void* lists, int chunks, hipStream_t stream) {
+                        char* part, const void* lists, int chunks, hipStream_t stream,
+                        const int* live = nullptr) {
   const int n_a = Z->n / Z->n_states;
   const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
   const bool far = store_has_far(Z);
@@ -1024,7 +1029,8 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
     const int nwg = (bd.n_tiles * groups + kXcd - 1) / kXcd * kXcd;
     hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), lds, stream, bd.rhs, bd.tiles, groups, states,
                        (const S*)((const char*)Z->far + head), (const int*)Z->far, fscale, Z->max_rank, Z->Dx,
-                       Z->Dy, Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles);
+                       Z->Dy, Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles,
+                       live);
     R3M_CHECK_HIP(hipGetLastError());
   }
   if (near_on_mfma(Z)) {
@@ -1033,7 +1039,7 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
     auto kern = n_a == 40 ? near_mfma_kernel<S, 40> : near_mfma_kernel<S, 64>;
     hipLaunchKernelGGL(kern, dim3((unsigned)L.max_items), dim3(256), lds, stream, (const NearItem*)L.items,
                        (const int*)L.n_items, (const NearPair*)L.pairs, (const S*)Z->near, Z->n, Z->n_states, xs,
-                       (S*)part + (size_t)groups * tu * n_a * 2, tu);
+                       (S*)part + (size_t)groups * tu * n_a * 2, tu, live);
   } else {
     const int nwg_near = (bd.n_tiles * hg + kXcd - 1) / kXcd * kXcd;
     // row-slab height: the whole state for complex64, half of it for complex128
@@ -1045,7 +1051,7 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
   }
   R3M_CHECK_HIP(hipGetLastError());
   hipLaunchKernelGGL((reduce_groups_kernel<S, XT>), dim3(ceil_div((size_t)bd.max_units * n_a, 64), bd.B),
-                     dim3(64), 0, stream, bd.rhs, (const S*)part, groups + hg, tu, n_a, y);
+                     dim3(64), 0, stream, bd.rhs, (const S*)part, groups + hg, tu, n_a, y, live);
   R3M_CHECK_HIP(hipGetLastError());
 }
 
@@ -1072,11 +1078,13 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
 // C128); y is C128
 // the near retrieval lists (build_near_lists) must be current at lists
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
-                       void* partial, const void* lists, int chunks, hipStream_t stream) {
+                       void* partial, const void* lists, int chunks, hipStream_t stream, const int* live) {
   if (Z->near_dtype == R3M_C128)
-    launch_core<double, double>(Z, bd, states, (const double*)xs, (double*)y, (char*)partial, lists, chunks, stream);
+    launch_core<double, double>(Z, bd, states, (const double*)xs, (double*)y, (char*)partial, lists, chunks, stream,
+                                live);
   else
-    launch_core<float, double>(Z, bd, states, (const float*)xs, (double*)y, (char*)partial, lists, chunks, stream);
+    launch_core<float, double>(Z, bd, states, (const float*)xs, (double*)y, (char*)partial, lists, chunks, stream,
+                               live);
 }
 
 static std::vector<int64_t> tune_key(const r3m_store* Z, const BatchDesc& bd) {
@@ -1109,9 +1117,9 @@ int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uin
   int best = g0;
   float best_ms = 1e30f;
   for (int g : cand) {
-    launch_matvec_pre(Z, bd, states, xs, y, partial, lists, g, stream);  // warm
+    launch_matvec_pre(Z, bd, states, xs, y, partial, lists, g, stream, nullptr);  // warm
     R3M_CHECK_HIP(hipEventRecord(e0, stream));
-    for (int rep = 0; rep < 2; ++rep) launch_matvec_pre(Z, bd, states, xs, y, partial, lists, g, stream);
+    for (int rep = 0; rep < 2; ++rep) launch_matvec_pre(Z, bd, states, xs, y, partial, lists, g, stream, nullptr);
     R3M_CHECK_HIP(hipEventRecord(e1, stream));
     R3M_CHECK_HIP(hipEventSynchronize(e1));
     float ms = 0.f;

@@ -25,8 +25,10 @@ void build_near_lists(const r3m_store* Z, const BatchDesc& bd, const uint8_t* st
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
                    r3m_dtype vec_dtype, const void* x, void* y, void* partial, const void* lists, int chunks,
                    hipStream_t stream);
-// xs already in the store precision; y C128
+// xs already in the store precision; y C128.  live (device, nullable): the
+// kernels return at once when *live == 0 (used to skip Arnoldi steps after
+// every right-hand side has converged)
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
-                       void* partial, const void* lists, int chunks, hipStream_t stream);
+                       void* partial, const void* lists, int chunks, hipStream_t stream, const int* live);
 
 }  // namespace r3m

@@ -100,6 +100,8 @@ struct r3m_ctx_s {
   std::map<r3m::BatchKey, r3m::BatchDesc*> batches;
   hipStream_t work_stream = nullptr;  // default-priority stream for graph replays
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  int* run_host = nullptr;                   // pinned [2]: running counts read back without a stall
+  hipEvent_t ev_run[2] = {nullptr, nullptr};  // completion of those read-backs
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
   std::map<std::vector<int64_t>, int> tuned_groups;  // autotuned displacement groups per (store, batch)
 };
