@@ -53,10 +53,9 @@ __device__ inline void load2<double>(const double* p, size_t idx, Cx<double>& a,
 // on one XCD and meet its factor blocks in that XCD's L2.  Returns false for
 // padding workgroups.
 constexpr int kXcd = 8;
-__device__ __forceinline__ bool decode_wg(int n_blocks, int n_groups, int& blk, int& grp) {
+__device__ __forceinline__ bool decode_wg(int id, int n_blocks, int n_groups, int& blk, int& grp) {
   const int total = n_blocks * n_groups;
   const int per = (total + kXcd - 1) / kXcd;
-  const int id = blockIdx.x;
   const int t = (id % kXcd) * per + id / kXcd;
   if (t >= total) return false;
   grp = t / n_blocks;
@@ -228,7 +227,7 @@ near_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, c
   __shared__ uint8_t ust[kBU];
   __shared__ int sst[kBU];
   int bi, h;
-  if (!decode_wg(n_blocks, hgroups, bi, h)) return;
+  if (!decode_wg(blockIdx.x, n_blocks, hgroups, bi, h)) return;
   const TileDev blk = tiles[bi];
   const RhsDev R = rhs[blk.b];
   const int tid = threadIdx.x;
@@ -376,22 +375,43 @@ __device__ __forceinline__ void load_factor2(const S* p, size_t idx, float sc, C
   }
 }
 
+template <typename S>
+struct FarArgs {
+  const RhsDev* rhs;
+  const TileDev* tiles;
+  int groups;
+  const uint8_t* states;
+  const S* farf;        // factors (store precision or split elements)
+  const int* ranks;
+  const float* fscale;  // F16X2 column scales, else NULL
+  int max_rank, Dx, Dy, nr, n, n_a, n_states;
+  const S* x;
+  S* out;
+  int64_t total_units;
+  int lds_state_cap, n_blocks;
+};
+
+// far field of workgroup wg (see far_kernel)
 template <typename S, int QS, int kRch, int FT>
-__global__ void __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu((sizeof(S) == 4 && QS <= 10) ? R3M_FAR_WAVES_PER_EU_F32
-                                                                : R3M_FAR_WAVES_PER_EU_F64)))
-far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, int groups,
-           const uint8_t* __restrict__ states, const S* __restrict__ farf, const int* __restrict__ ranks,
-           const float* __restrict__ fscale, int max_rank, int Dx, int Dy, int nr, int n, int n_a, int n_states,
-           const S* __restrict__ x, S* __restrict__ out, int64_t total_units, int lds_state_cap, int n_blocks,
-           const int* __restrict__ live) {
-  if (live && *live == 0) return;  // every right-hand side has converged
+__device__ __forceinline__ void far_body(const FarArgs<S>& A, int wg) {
+  const RhsDev* __restrict__ rhs = A.rhs;
+  const TileDev* __restrict__ tiles = A.tiles;
+  const int groups = A.groups;
+  const uint8_t* __restrict__ states = A.states;
+  const S* __restrict__ farf = A.farf;
+  const int* __restrict__ ranks = A.ranks;
+  const float* __restrict__ fscale = A.fscale;
+  const int max_rank = A.max_rank, Dx = A.Dx, Dy = A.Dy, nr = A.nr, n = A.n, n_a = A.n_a, n_states = A.n_states;
+  const S* __restrict__ x = A.x;
+  S* __restrict__ out = A.out;
+  const int64_t total_units = A.total_units;
+  const int lds_state_cap = A.lds_state_cap, n_blocks = A.n_blocks;
   extern __shared__ unsigned char smem_raw[];
   Cx<S>* lds_u = reinterpret_cast<Cx<S>*>(smem_raw);  // [2][kRch][n]
   Cx<S>* lds_v = lds_u + 2 * kRch * n;                 // [2][kRch][n]
   uint8_t* lds_s = reinterpret_cast<uint8_t*>(lds_v + 2 * kRch * n);
   int bi, g;
-  if (!decode_wg(n_blocks, groups, bi, g)) return;
+  if (!decode_wg(wg, n_blocks, groups, bi, g)) return;
   const TileDev blk = tiles[bi];
   const RhsDev R = rhs[blk.b];
   const int tid = threadIdx.x;
@@ -586,6 +606,17 @@ far_kernel(const RhsDev* __restrict__ rhs, const TileDev* __restrict__ tiles, in
   }
 }
 
+#define R3M_FAR_WAVES(S, QS)                                                                  \
+  __attribute__((amdgpu_waves_per_eu((sizeof(S) == 4 && (QS) <= 10) ? R3M_FAR_WAVES_PER_EU_F32 \
+                                                                     : R3M_FAR_WAVES_PER_EU_F64)))
+
+template <typename S, int QS, int kRch, int FT>
+__global__ void __launch_bounds__(256) R3M_FAR_WAVES(S, QS)
+far_kernel(FarArgs<S> A, const int* __restrict__ live) {
+  if (live && *live == 0) return;  // every right-hand side has converged
+  far_body<S, QS, kRch, FT>(A, blockIdx.x);
+}
+
 template <typename S, typename XT>
 __global__ void __launch_bounds__(256)
 reduce_groups_kernel(const RhsDev* __restrict__ rhs, const S* __restrict__ partial, int slots,
@@ -753,12 +784,28 @@ struct MfmaAcc<double> {
 // real (2 NA) x (2 NA) x 16 product per wave on 16x16x4 MFMA tiles (lane l
 // holds A[l % 16][l / 16] and B[l / 16][l % 16]).  Dynamic LDS: Z' as
 // [2 NA][2 NA + 1] reals, then the gathered columns [kNearCols][2 NA + 1].
+template <typename S>
+struct NearArgs {
+  const NearItem* items;
+  const int* n_items;
+  const NearPair* pairs;
+  const S* near;
+  int n, n_states;
+  const S* x;
+  S* out;  // near slot 0
+  int64_t total_units;
+};
+
+// near-field item wg (see near_mfma_kernel)
 template <typename S, int NA>
-__global__ void __launch_bounds__(256)
-near_mfma_kernel(const NearItem* __restrict__ items, const int* __restrict__ n_items,
-                 const NearPair* __restrict__ pairs, const S* __restrict__ near, int n, int n_states,
-                 const S* __restrict__ x, S* __restrict__ out, int64_t total_units, const int* __restrict__ live) {
-  if (live && *live == 0) return;  // every right-hand side has converged
+__device__ __forceinline__ void near_body(const NearArgs<S>& A, int wg) {
+  const NearItem* __restrict__ items = A.items;
+  const NearPair* __restrict__ pairs = A.pairs;
+  const S* __restrict__ near = A.near;
+  const int n = A.n, n_states = A.n_states;
+  const S* __restrict__ x = A.x;
+  S* __restrict__ out = A.out;
+  const int64_t total_units = A.total_units;
   constexpr int K2 = 2 * NA, MT = K2 / 16, KT = K2 / 4, XS = K2 + 1;
   constexpr int KC = 4;  // K steps whose operands are read before their MFMAs
   static_assert(KT % KC == 0, "K steps per chunk");
@@ -766,8 +813,8 @@ near_mfma_kernel(const NearItem* __restrict__ items, const int* __restrict__ n_i
   S* a_lds = reinterpret_cast<S*>(smem_raw);  // Z' [K2][XS]
   S* x_lds = a_lds + (size_t)K2 * XS;         // X' [kNearCols][XS]
   __shared__ int tgt_s[kNearCols], src_s[kNearCols];
-  if ((int)blockIdx.x >= *n_items) return;
-  const NearItem item = items[blockIdx.x];
+  if (wg >= *A.n_items) return;
+  const NearItem item = items[wg];
   const int S1 = n_states + 1;
   const int bsrc = item.cls % S1, a = (item.cls / S1) % n_states, slot = item.cls / (S1 * n_states);
   const int tid = threadIdx.x;
@@ -842,6 +889,26 @@ near_mfma_kernel(const NearItem* __restrict__ items, const int* __restrict__ n_i
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int r = 0; r < 4; ++r) o[16 * mt + MfmaAcc<S>::row(l, r)] = acc[mt][r];
+}
+
+template <typename S, int NA>
+__global__ void __launch_bounds__(256) near_mfma_kernel(NearArgs<S> A, const int* __restrict__ live) {
+  if (live && *live == 0) return;  // every right-hand side has converged
+  near_body<S, NA>(A, blockIdx.x);
+}
+
+// Far and near field in one launch: the first near_wgs workgroups take the
+// near items (matrix cores), the rest the far tiles (vector units), so the
+// two kinds of work share the chip.  near_wgs is a multiple of 8, which keeps
+// the far workgroups' XCD placement.
+template <typename S, int QS, int kRch, int FT, int NA>
+__global__ void __launch_bounds__(256) R3M_FAR_WAVES(S, QS)
+far_near_kernel(FarArgs<S> F, NearArgs<S> N, int near_wgs, const int* __restrict__ live) {
+  if (live && *live == 0) return;  // every right-hand side has converged
+  if ((int)blockIdx.x < near_wgs)
+    near_body<S, NA>(N, blockIdx.x);
+  else
+    far_body<S, QS, kRch, FT>(F, blockIdx.x - near_wgs);
 }
 
 template <typename S, typename XT>
@@ -1007,39 +1074,64 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
   const int groups = far ? std::max(chunks, 1) : 0;
   const int hg = near_groups(Z, bd);
   const int64_t tu = (int64_t)bd.total_units;
+  const bool mfma_near = near_on_mfma(Z);
+  const bool fuse = mfma_near && far && sizeof(S) == 4;
+  NearArgs<S> NA_{};
+  size_t lds_nearm = 0;
+  int near_wgs = 0;
+  if (mfma_near) {
+    NearLists L = near_lists((char*)lists, Z, bd);
+    NA_ = NearArgs<S>{(const NearItem*)L.items, (const int*)L.n_items, (const NearPair*)L.pairs, (const S*)Z->near,
+                      Z->n, Z->n_states, xs, (S*)part + (size_t)groups * tu * n_a * 2, tu};
+    lds_nearm = ((size_t)2 * n_a + kNearCols) * (2 * n_a + 1) * sizeof(S);
+    near_wgs = (int)((L.max_items + kXcd - 1) / kXcd * kXcd);
+  }
   if (far) {
     // the batch's largest state array, when it fits, is staged in LDS
     const int lds_state_cap = bd.max_units <= 16384 ? (int)((bd.max_units + 15) / 16 * 16) : 0;
     constexpr int rch = sizeof(S) == 4 ? R3M_FAR_RCH_F32 : 4;
     const size_t lds = 4 * (size_t)rch * Z->n * 2 * sizeof(S) + lds_state_cap;
-    decltype(&far_kernel<S, 10, rch, 0>) kern;
-    if constexpr (sizeof(S) == 4) {
-      if (Z->far_dtype == R3M_BF16X2)
-        kern = n_a == 40 ? far_kernel<S, 10, rch, R3M_BF16X2> : far_kernel<S, 16, rch, R3M_BF16X2>;
-      else if (Z->far_dtype == R3M_F16X2)
-        kern = n_a == 40 ? far_kernel<S, 10, rch, R3M_F16X2> : far_kernel<S, 16, rch, R3M_F16X2>;
-      else
-        kern = n_a == 40 ? far_kernel<S, 10, rch, 0> : far_kernel<S, 16, rch, 0>;
-    } else {
-      kern = n_a == 40 ? far_kernel<S, 10, rch, 0> : far_kernel<S, 16, rch, 0>;
-    }
     const size_t body = ((size_t)n_far * 2 * Z->max_rank * Z->n * 2 * sizeof(S) + 255) / 256 * 256;
     const float* fscale =
         Z->far_dtype == R3M_F16X2 ? (const float*)((const char*)Z->far + head + body) : nullptr;
+    const FarArgs<S> FA{bd.rhs, bd.tiles, groups, states, (const S*)((const char*)Z->far + head),
+                        (const int*)Z->far, fscale, Z->max_rank, Z->Dx, Z->Dy, Z->near_radius, Z->n, n_a,
+                        Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles};
     const int nwg = (bd.n_tiles * groups + kXcd - 1) / kXcd * kXcd;
-    hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), lds, stream, bd.rhs, bd.tiles, groups, states,
-                       (const S*)((const char*)Z->far + head), (const int*)Z->far, fscale, Z->max_rank, Z->Dx,
-                       Z->Dy, Z->near_radius, Z->n, n_a, Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles,
-                       live);
+    const int ft = sizeof(S) == 4 ? (int)Z->far_dtype : 0;
+    if (fuse) {
+      // one launch for both fields (complex64: the matrix-core near items run
+      // beside the vector-unit far tiles; complex128 is faster as two launches)
+      decltype(&far_near_kernel<S, 10, rch, 0, 40>) kern;
+      if (n_a == 40)
+        kern = ft == R3M_BF16X2 ? far_near_kernel<S, 10, rch, sizeof(S) == 4 ? R3M_BF16X2 : 0, 40>
+             : ft == R3M_F16X2  ? far_near_kernel<S, 10, rch, sizeof(S) == 4 ? R3M_F16X2 : 0, 40>
+                                : far_near_kernel<S, 10, rch, 0, 40>;
+      else
+        kern = ft == R3M_BF16X2 ? far_near_kernel<S, 16, rch, sizeof(S) == 4 ? R3M_BF16X2 : 0, 64>
+             : ft == R3M_F16X2  ? far_near_kernel<S, 16, rch, sizeof(S) == 4 ? R3M_F16X2 : 0, 64>
+                                : far_near_kernel<S, 16, rch, 0, 64>;
+      hipLaunchKernelGGL(kern, dim3(near_wgs + nwg), dim3(256), std::max(lds, lds_nearm), stream, FA, NA_,
+                         near_wgs, live);
+    } else {
+      decltype(&far_kernel<S, 10, rch, 0>) kern;
+      if (n_a == 40)
+        kern = ft == R3M_BF16X2 ? far_kernel<S, 10, rch, sizeof(S) == 4 ? R3M_BF16X2 : 0>
+             : ft == R3M_F16X2  ? far_kernel<S, 10, rch, sizeof(S) == 4 ? R3M_F16X2 : 0>
+                                : far_kernel<S, 10, rch, 0>;
+      else
+        kern = ft == R3M_BF16X2 ? far_kernel<S, 16, rch, sizeof(S) == 4 ? R3M_BF16X2 : 0>
+             : ft == R3M_F16X2  ? far_kernel<S, 16, rch, sizeof(S) == 4 ? R3M_F16X2 : 0>
+                                : far_kernel<S, 16, rch, 0>;
+      hipLaunchKernelGGL(kern, dim3(nwg), dim3(256), lds, stream, FA, live);
+    }
     R3M_CHECK_HIP(hipGetLastError());
   }
-  if (near_on_mfma(Z)) {
-    NearLists L = near_lists((char*)lists, Z, bd);
-    const size_t lds = ((size_t)2 * n_a + kNearCols) * (2 * n_a + 1) * sizeof(S);
-    auto kern = n_a == 40 ? near_mfma_kernel<S, 40> : near_mfma_kernel<S, 64>;
-    hipLaunchKernelGGL(kern, dim3((unsigned)L.max_items), dim3(256), lds, stream, (const NearItem*)L.items,
-                       (const int*)L.n_items, (const NearPair*)L.pairs, (const S*)Z->near, Z->n, Z->n_states, xs,
-                       (S*)part + (size_t)groups * tu * n_a * 2, tu, live);
+  if (mfma_near) {
+    if (!fuse) {
+      auto kern = n_a == 40 ? near_mfma_kernel<S, 40> : near_mfma_kernel<S, 64>;
+      hipLaunchKernelGGL(kern, dim3((unsigned)near_wgs), dim3(256), lds_nearm, stream, NA_, live);
+    }
   } else {
     const int nwg_near = (bd.n_tiles * hg + kXcd - 1) / kXcd * kXcd;
     // row-slab height: the whole state for complex64, half of it for complex128
