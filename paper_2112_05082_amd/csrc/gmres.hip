@@ -401,19 +401,25 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
 // ||w|| from the per-block parts of the preceding gs_update_kernel (summed by
 // every block in the same fixed order); block 0 sets H[j+1][j] = ||w|| and
 // applies the Givens step; every block writes V_{j+1} = w / ||w|| (zeros for
-// a finished RHS or a breakdown).
+// a finished RHS or a breakdown) and, for the next step's matvec, its input
+// in the store precision OT: V_{j+1} itself (MODE 1) or M^{-1} V_{j+1}
+// (MODE 2, block-Jacobi; a block holds whole units).  MODE 0 writes V only.
+template <typename OT, int MODE>
 __global__ void __launch_bounds__(256)
 normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, const RhsVec* __restrict__ rv,
                       RhsState* __restrict__ st, const double* __restrict__ npart, int maxB,
                       double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
                       double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
-                      double* __restrict__ wn, int64_t ut, const int* __restrict__ live) {
+                      double* __restrict__ wn, int64_t ut, const int* __restrict__ live,
+                      const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
+                      const int64_t* __restrict__ soff, int n_a, int n_states, OT* __restrict__ xs) {
   if (live && *live == 0) return;
   __shared__ double nv_s;
+  __shared__ double2 v_s[256];
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
   const int64_t nb = (r.N + 63) / 64;
-  if ((int64_t)blockIdx.x * blockDim.x >= r.N) return;
+  if ((int64_t)blockIdx.x * blockDim.x >= r.N) return;  // uniform over the block
   if (threadIdx.x < 64) {
     const double sum = wave_sum_partials(npart + (size_t)b * maxB, (int)nb);
     if (threadIdx.x == 0) nv_s = sqrt(fmax(sum, 0.0));
@@ -425,9 +431,35 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
   const RhsState s0 = st[b];
   const bool ok = s0.active && (s0.jdone < 0 || s0.jdone == j + 1) && nv > 0.0;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < r.N) {
-    const double2 v = w[r.off + k];
-    V[(int64_t)(j + 1) * ut + r.off + k] = ok ? make_double2(v.x / nv, v.y / nv) : make_double2(0.0, 0.0);
+  const bool in = k < r.N;
+  double2 v = make_double2(0.0, 0.0);
+  if (in) {
+    const double2 wk = w[r.off + k];
+    if (ok) v = make_double2(wk.x / nv, wk.y / nv);
+    V[(int64_t)(j + 1) * ut + r.off + k] = v;
+  }
+  if (MODE == 1 && in) {
+    xs[2 * (r.off + k)] = (OT)v.x;
+    xs[2 * (r.off + k) + 1] = (OT)v.y;
+  }
+  if (MODE == 2) {
+    v_s[threadIdx.x] = v;
+    __syncthreads();
+    if (in) {
+      const int64_t u = k / n_a;
+      const int mr = (int)(k % n_a);
+      const int sidx = min((int)states[soff[b] + u], n_states - 1);
+      const double2* M = Minv + ((size_t)sidx * n_a + mr) * n_a;
+      const double2* vu = v_s + (threadIdx.x / n_a) * n_a;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int c = 0; c < n_a; ++c) {
+        const double2 t = cmul(M[c], vu[c]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      xs[2 * (r.off + k)] = (OT)acc.x;
+      xs[2 * (r.off + k) + 1] = (OT)acc.y;
+    }
   }
   if (blockIdx.x == 0) {  // uniform over the block
     if (threadIdx.x == 0) wn[b] = nv;
@@ -831,29 +863,31 @@ struct GmresRun {
   // launched past convergence cost only their launches.
   int* run_slot(int j) const { return W.counters + 4 + (j & 1); }
 
-  // w = Z M^{-1} v (or Z v): the preconditioner writes the matvec input in
-  // the store precision directly
-  void apply_operator(const r3m_store* Z, const double2* v, const int* live) {
+  // The matvec input of an Arnoldi step, M^{-1} V_j (block-Jacobi) or V_j,
+  // in the store precision: written into W.xs by the previous step's
+  // normalisation, or by prepare_input for V_0.  A complex128 store without
+  // preconditioner reads V_j itself.
+  bool input_in_xs(const r3m_store* Z) const { return pre || Z->near_dtype == R3M_C64; }
+  void prepare_input(const r3m_store* Z, const double2* v) {
     const bool c64 = Z->near_dtype == R3M_C64;
-    const void* xin = v;
     if (pre) {
       if (c64)
         hipLaunchKernelGGL(apply_precond_kernel<float>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (float*)W.xs, live);
+                           W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr);
       else
         hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (double*)W.xs, live);
-      xin = W.xs;
+                           W.rv, n_a, n_states, v, (double*)W.xs, (const int*)nullptr);
     } else if (c64) {
-      hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs, live);
-      xin = W.xs;
+      hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs,
+                         (const int*)nullptr);
     }
-    launch_matvec_pre(Z, *bd, batch->states, xin, W.w, W.mv_partial, lists_for(Z), G, s, live);
   }
 
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
     const int* live = run_slot(j - 1);  // j = 0: set by the cycle start
-    apply_operator(Z, W.V + (int64_t)j * ut, live);
+    const double2* vj = W.V + (int64_t)j * ut;
+    launch_matvec_pre(Z, *bd, batch->states, input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, W.w,
+                      W.mv_partial, lists_for(Z), G, s, live);
     const dim3 dgrid(maxP, (j + 1 + kDotVec - 1) / kDotVec, B);
     const int maxB = (int)((maxN + 63) / 64 + 1);
     for (int pass = 0; pass < 2; ++pass) {
@@ -863,8 +897,27 @@ struct GmresRun {
                          (size_t)(j + 1) * sizeof(double2), s, W.V, W.w, W.rv, W.st, W.dpart, maxP, j + 1, ut, pass,
                          W.npart, maxB, W.H, m, j, pass, live);
     }
-    hipLaunchKernelGGL(normalize_step_kernel, vgrid(), dim3(256), (size_t)(2 * m + 2) * 16 + (size_t)m * 8, s, W.w,
-                       W.V, W.rv, W.st, W.npart, maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live);
+    // blocks of whole units (the preconditioner multiplies per unit)
+    const int nthr = (256 / n_a) * n_a;
+    const dim3 ngrid(ceil_div((size_t)maxN, nthr), B);
+    const size_t glds = (size_t)(2 * m + 2) * 16 + (size_t)m * 8;
+    const bool c64 = Z->near_dtype == R3M_C64;
+    if (pre && c64)
+      hipLaunchKernelGGL((normalize_step_kernel<float, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, W.npart,
+                         maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
+                         W.soff, n_a, n_states, (float*)W.xs);
+    else if (pre)
+      hipLaunchKernelGGL((normalize_step_kernel<double, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
+                         W.npart, maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
+                         batch->states, W.soff, n_a, n_states, (double*)W.xs);
+    else if (c64)
+      hipLaunchKernelGGL((normalize_step_kernel<float, 1>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, W.npart,
+                         maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
+                         W.soff, n_a, n_states, (float*)W.xs);
+    else
+      hipLaunchKernelGGL((normalize_step_kernel<double, 0>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
+                         W.npart, maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
+                         batch->states, W.soff, n_a, n_states, (double*)nullptr);
     R3M_CHECK_HIP(hipGetLastError());
   }
 
@@ -950,6 +1003,7 @@ struct GmresRun {
       R3M_CHECK_HIP(hipMemcpyAsync(W.st, hst.data(), (size_t)B * sizeof(RhsState), hipMemcpyHostToDevice, s));
       dim3 g0(std::max(ceil_div((size_t)maxN, 256), ceil_div((size_t)m + 1, 256)), B);
       hipLaunchKernelGGL(cycle_start_kernel, g0, dim3(256), 0, s, W.r, W.V, W.rv, W.st, W.nrm, W.g, m, run_slot(-1));
+      prepare_input(Z, W.V);
       const int steps = std::max(1, std::min(m, max_iter - min_used));
       // Blocks of kCheckEvery steps.  The running count after a block is read
       // back asynchronously while the next block is already queued: the host
