@@ -60,7 +60,9 @@ typedef enum {
   R3M_C128 = 0,   /* complex double */
   R3M_C64 = 1,    /* complex float, FP32 accumulation */
   R3M_BF16X2 = 2, /* far factors only: hi/lo bfloat16 split, FP32 accumulation */
-  R3M_F16X2 = 3   /* far factors only: hi/lo float16 split with a per-column scale */
+  R3M_F16X2 = 3,  /* far factors only: hi/lo float16 split with a per-column scale */
+  R3M_SPEC_C64 = 4, /* store far part only: block spectra (r3m_build_spectral), complex float */
+  R3M_SPEC_C128 = 5 /* store far part only: block spectra, complex double */
 } r3m_dtype;
 
 typedef struct r3m_ctx_s* r3m_ctx;
@@ -137,12 +139,37 @@ int r3m_compress_far(r3m_ctx ctx, const void* dense_dev, int32_t n, int32_t Dx, 
                      void* far_dev, size_t far_bytes, int32_t* ranks_host, double* rel_err_host,
                      void* work_dev, size_t work_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------ spectra -- */
+
+/* The unique blocks Z(d) as spectra of their circulant embedding: the
+ * two-level block-Toeplitz structure of the macro system (every block a
+ * function of the displacement, Sec. III-C) makes the retrieved product of
+ * eq. (6) a 2-D convolution over units, evaluated by FFT.  With
+ * Gx = smallest power of two >= 2Dx+1 (>= 2), Gy likewise:
+ *   spec[m][n][gy][gx] = sum over |dx| <= Dx, |dy| <= Dy of
+ *       Z(d)[m][n] exp(-2 pi i (gx dx / Gx + gy dy / Gy)),
+ * complex float (R3M_SPEC_C64) or double (R3M_SPEC_C128), row-major grids.
+ * Bytes: n * n * Gx * Gy * (8 or 16); 0 for bad arguments. */
+size_t r3m_spectral_bytes(int32_t n, int32_t Dx, int32_t Dy, r3m_dtype dtype);
+
+/* Computes the spectra above from a C128 dense store of the same (n, Dx, Dy)
+ * (as written by r3m_fill_unique_blocks), transforms in the output precision.
+ * n <= 256; Gx, Gy < 4096 (float) or 2048 (double), else
+ * R3M_ERR_UNSUPPORTED.  Asynchronous on `stream`. */
+int r3m_build_spectral(r3m_ctx ctx, const void* dense_dev, int32_t n, int32_t Dx, int32_t Dy, r3m_dtype dtype,
+                       void* spec_dev, size_t spec_bytes, hipStream_t stream);
+
 /* --------------------------------------------------------------- store -- */
 
 /* A global matrix as unique displacement blocks.
  * near: dense blocks for max(|dx|,|dy|) <= near_radius, laid out as a block
  *       store of half-extent (Nx, Ny) = (min(near_radius, Dx), min(near_radius, Dy)).
- * far : r3m_far layout above (ignored when near covers the whole store). */
+ * far : r3m_far layout above (ignored when near covers the whole store).
+ * far_dtype R3M_SPEC_C64 / R3M_SPEC_C128: far holds the spectra of every
+ *       block (r3m_build_spectral, same Dx, Dy) and the matvec evaluates the
+ *       whole product from them; near (precision C64 / C128 to match) then
+ *       only feeds the solver's block-Jacobi preconditioner (its d = 0 block),
+ *       and max_rank is ignored. */
 typedef struct {
   int32_t n;        /* macro RWG per unit */
   int32_t n_states; /* coding states; n_a = n / n_states */

@@ -944,6 +944,7 @@ static int near_count(const r3m_store* Z) {
 // unless the near set is large (an all-dense store), where the LDS-slab kernel
 // groups displacements
 static bool near_on_mfma(const r3m_store* Z) {
+  if (store_is_spectral(Z)) return false;
   const int n_a = Z->n / Z->n_states;
   const size_t es = Z->near_dtype == R3M_C128 ? 8 : 4;
   return near_count(Z) <= 128 && ((size_t)2 * n_a + kNearCols) * (2 * n_a + 1) * es <= 96 * 1024;
@@ -1027,6 +1028,7 @@ void build_near_lists(const r3m_store* Z, const BatchDesc& bd, const uint8_t* st
 // precision, a copy of x in the store precision when the vectors are wider,
 // then the near retrieval lists
 size_t partials_and_x_bytes(const BatchDesc& bd, const r3m_store* Z, int chunks) {
+  if (store_is_spectral(Z)) return spectral_work_bytes(bd, Z);
   const size_t es = Z->near_dtype == R3M_C128 ? 16 : 8;
   const int n_a = Z->n / Z->n_states;
   const size_t vec = (size_t)bd.total_units * n_a * es;
@@ -1053,7 +1055,9 @@ void validate_store(const r3m_store* Z) {
   R3M_REQUIRE(Z->near, R3M_ERR_INVALID_ARG, "near blocks are NULL");
   R3M_REQUIRE(Z->near_dtype == R3M_C128 || Z->near_dtype == R3M_C64, R3M_ERR_UNSUPPORTED,
               "near dtype must be C128 or C64");
-  if (store_has_far(Z)) {
+  if (store_is_spectral(Z)) {
+    validate_spectral(Z);
+  } else if (store_has_far(Z)) {
     R3M_REQUIRE(Z->far, R3M_ERR_INVALID_ARG, "far factors are NULL");
     R3M_REQUIRE(Z->far_dtype == Z->near_dtype ||
                     (Z->near_dtype == R3M_C64 && (Z->far_dtype == R3M_BF16X2 || Z->far_dtype == R3M_F16X2)),
@@ -1171,6 +1175,10 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
 // the near retrieval lists (build_near_lists) must be current at lists
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
                        void* partial, const void* lists, int chunks, hipStream_t stream, const int* live) {
+  if (store_is_spectral(Z)) {
+    launch_spectral(Z, bd, states, Z->near_dtype, xs, R3M_C128, y, partial, stream, live);
+    return;
+  }
   if (Z->near_dtype == R3M_C128)
     launch_core<double, double>(Z, bd, states, (const double*)xs, (double*)y, (char*)partial, lists, chunks, stream,
                                 live);
@@ -1189,7 +1197,7 @@ static std::vector<int64_t> tune_key(const r3m_store* Z, const BatchDesc& bd) {
 // xs is the input in the store precision, y a C128 output (overwritten).
 int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
                  void* y, void* partial, const void* lists, hipStream_t stream) {
-  if (!store_has_far(Z)) return 1;
+  if (!store_has_far(Z) || store_is_spectral(Z)) return 1;
   const std::vector<int64_t> key = tune_key(Z, bd);
   auto it = ctx->tuned_groups.find(key);
   if (it != ctx->tuned_groups.end()) return it->second;
@@ -1231,6 +1239,7 @@ int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uin
 
 // displacement groups for (store, batch): the autotuned value when known
 int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd) {
+  if (store_is_spectral(Z)) return 1;
   const std::vector<int64_t> key = tune_key(Z, bd);
   auto it = ctx->tuned_groups.find(key);
   return it != ctx->tuned_groups.end() ? it->second : choose_chunks(bd, 64);
@@ -1242,6 +1251,10 @@ void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
                    r3m_dtype vec_dtype, const void* x, void* y, void* partial, const void* lists, int chunks,
                    hipStream_t stream) {
   (void)ctx;
+  if (store_is_spectral(Z)) {
+    launch_spectral(Z, bd, states, vec_dtype, x, vec_dtype, y, partial, stream, nullptr);
+    return;
+  }
   if (!lists) lists = workspace_lists(partial, bd, Z);
   if (Z->near_dtype == R3M_C128) {
     R3M_REQUIRE(vec_dtype == R3M_C128, R3M_ERR_UNSUPPORTED, "a C128 store needs C128 vectors");
@@ -1295,7 +1308,7 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
       build_near_lists(Z, bd, batch->states, workspace_lists(work_dev, bd, Z), stream);
     // first C128 call on this (store, batch): tune the group count on this x
     // (the tuner writes y as C128, so C64 vectors take the tuned or default value)
-    if (vec_dtype == R3M_C128 && store_has_far(Z)) {
+    if (vec_dtype == R3M_C128 && store_has_far(Z) && !store_is_spectral(Z)) {
       const void* xs = x_dev;
       if (Z->near_dtype == R3M_C64) {
         const int n_a = Z->n / Z->n_states;

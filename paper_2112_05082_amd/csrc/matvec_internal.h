@@ -31,4 +31,12 @@ void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
                        void* partial, const void* lists, int chunks, hipStream_t stream, const int* live);
 
+// spectral stores (far_dtype R3M_SPEC_*): the whole product by FFT
+bool store_is_spectral(const r3m_store* Z);
+void validate_spectral(const r3m_store* Z);
+size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z);
+// x (x_type) to y (y_type); work: spectral_work_bytes; live as above
+void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
+                     const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live);
+
 }  // namespace r3m

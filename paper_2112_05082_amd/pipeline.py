@@ -54,3 +54,23 @@ def compressed_store(ctx, geom, L: int, near_radius: int, near_dtype: int, far_d
     if own_dense:
         del dense_c128
     return r3m.Store(n, geom.n_states, D, D, nr, near_dtype, near, far_dtype, far, max_rank, ranks, err)
+
+
+def spectral_store(ctx, geom, L: int, near_radius: int, dtype: int, device,
+                   dense_c128: torch.Tensor | None = None) -> r3m.Store:
+    """Block spectra of every displacement (the whole product by FFT) plus the
+    dense near blocks (Chebyshev <= near_radius) the preconditioner reads.
+    dtype: r3m.C64 or r3m.C128 (spectra and near blocks alike)."""
+    D = L - 1
+    n = geom.n
+    nr = min(near_radius, D)
+    near = fill_blocks(ctx, geom, nr, dtype, device)
+    own_dense = dense_c128 is None
+    if own_dense:
+        dense_c128 = fill_blocks(ctx, geom, D, r3m.C128, device)
+    sd = r3m.SPEC_C64 if dtype == r3m.C64 else r3m.SPEC_C128
+    spec = empty_bytes(r3m.spectral_bytes(n, D, D, sd), device)
+    r3m.r3m_build_spectral(ctx, dense_c128, n, D, D, sd, spec)
+    if own_dense:
+        del dense_c128
+    return r3m.Store(n, geom.n_states, D, D, nr, dtype, near, sd, spec)

@@ -23,7 +23,7 @@ R3M_ERR_NOT_CONVERGED = -4
 R3M_ERR_NONFINITE = -5
 R3M_ERR_UNSUPPORTED = -6
 
-C128, C64, BF16X2, F16X2 = 0, 1, 2, 3
+C128, C64, BF16X2, F16X2, SPEC_C64, SPEC_C128 = 0, 1, 2, 3, 4, 5
 BATCH_INDEX_READY = 1
 PRECOND_NONE, PRECOND_BLOCK_JACOBI = 0, 1
 
@@ -31,6 +31,7 @@ EXPORTED = (
     "r3m_ctx_create", "r3m_ctx_destroy", "r3m_last_error", "r3m_version",
     "r3m_blocks_bytes", "r3m_fill_unique_blocks",
     "r3m_far_count", "r3m_far_bytes", "r3m_compress_work_bytes", "r3m_compress_far",
+    "r3m_spectral_bytes", "r3m_build_spectral",
     "r3m_matvec_work_bytes", "r3m_retrieved_matvec", "r3m_matvec_groups",
     "r3m_gmres_work_bytes", "r3m_gmres_solve",
     "r3m_plane_wave_rhs", "r3m_rcs",
@@ -108,6 +109,8 @@ def load(path: str = LIB_PATH):
         "r3m_compress_work_bytes": (sz, [i32, i32, i32]),
         "r3m_compress_far": (C.c_int, [vp, vp, i32, i32, i32, i32, dbl, i32, C.c_int, vp, sz,
                                        C.POINTER(C.c_int32), C.POINTER(C.c_double), vp, sz, vp]),
+        "r3m_spectral_bytes": (sz, [i32, i32, i32, C.c_int]),
+        "r3m_build_spectral": (C.c_int, [vp, vp, i32, i32, i32, C.c_int, vp, sz, vp]),
         "r3m_matvec_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int]),
         "r3m_retrieved_matvec": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int, vp, vp, vp,
                                            sz, vp]),
@@ -286,6 +289,14 @@ def r3m_compress_far(ctx: Context, dense, n: int, Dx: int, Dy: int, near_radius:
     return ranks[:n_far], err[:n_far]
 
 
+def r3m_build_spectral(ctx: Context, dense, n: int, Dx: int, Dy: int, dtype: int, out, stream=None):
+    """Block spectra of a C128 dense store into `out` (r3m_spectral_bytes)."""
+    lib = load()
+    _check(lib.r3m_build_spectral(ctx.handle, C.c_void_p(dense.data_ptr()), n, Dx, Dy, dtype,
+                                  C.c_void_p(out.data_ptr()), out.numel() * out.element_size(), _stream(stream)),
+           ctx.handle)
+
+
 def _need_vec(t, batch: Batch, n_a: int, what: str):
     if batch.B and t.numel() < batch.total_units * n_a:
         raise ValueError(f"{what} holds {t.numel()} complex entries, the batch needs {batch.total_units * n_a}")
@@ -362,6 +373,10 @@ def far_count(Dx, Dy, nr):
 
 def far_bytes(n, n_far, max_rank, dtype):
     return load().r3m_far_bytes(n, n_far, max_rank, dtype)
+
+
+def spectral_bytes(n, Dx, Dy, dtype):
+    return load().r3m_spectral_bytes(n, Dx, Dy, dtype)
 
 
 def compress_work_bytes(n, max_rank, per_batch):

@@ -46,6 +46,11 @@ def test_version_and_size_queries():
     head = ((3944 * 4 + 255) // 256) * 256
     assert r3m.far_bytes(160, 3944, 12, r3m.C64) == head + 3944 * 2 * 12 * 160 * 8
     assert r3m.blocks_bytes(0, 1, 1, r3m.C128) == 0
+    # spectra: n^2 grids of next_pow2(2D + 1) per axis
+    assert r3m.spectral_bytes(160, 31, 31, r3m.SPEC_C64) == 160 * 160 * 64 * 64 * 8
+    assert r3m.spectral_bytes(80, 3, 2, r3m.SPEC_C128) == 80 * 80 * 8 * 8 * 16
+    assert r3m.spectral_bytes(80, 0, 4, r3m.SPEC_C64) == 80 * 80 * 2 * 16 * 8
+    assert r3m.spectral_bytes(80, 3, 3, r3m.C64) == 0
 
 
 def test_ctx_create_without_gpu_reports_hip_error():

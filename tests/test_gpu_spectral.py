@@ -1,0 +1,206 @@
+"""Spectral (FFT) evaluation of the retrieved product against the oracle.
+
+The retrieved product of eq. (6) over a block-Toeplitz macro system is a 2-D
+convolution over units; a spectral store holds the transforms of the
+circulant-embedded blocks Z(d) and evaluates it per spatial frequency.  Its
+result is the dense retrieval product itself (no compression), so the
+references are:
+  * oracle blocks uploaded (rectangular store Dx = 3, Dy = 2, ragged and
+    rectangular arrays): the oracle's retrieval product, element by element;
+  * 2-bit 32 x 32 (the benchmark array): the oracle's rows of Z_k for three
+    sampled observer units, computed from the codebook's physical mesh, and
+    the plain complex128 path on every row;
+  * 128 x 128 x 16: the plain complex128 path on two right-hand sides;
+  * solves: the plain FP64 solve's RCS.
+Tolerances: complex128 spectra 1e-12 (max-abs, relative to the largest
+entry; rounding of O(log2(Gx Gy)) butterfly stages and n-term products in
+FP64, ~1e-14 expected) and 1e-10 on sampled rows as for the plain path;
+complex64 spectra 2e-6 element-wise and 1e-6 in the 2-norm (the same in FP32:
+~12 stages x 6e-8 per transform, two transforms, ~1e-6 at worst); solves
+1e-4 RCS (the workload's bar) and 1e-7 after FP64 refinement.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import FREQ, K, rel_l2, rel_max, unit  # noqa: E402
+from oracle import efie, retrieval  # noqa: E402
+from workloads import codebooks as cb  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_05082_amd import pipeline, r3m
+    r3m.load()
+    ctx = r3m.Context(0)
+    yield r3m, pipeline, ctx
+    ctx.close()
+
+
+def to_dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV).to(dtype)
+
+
+def spectra_of(r3m, ctx, dense_dev, n, Dx, Dy, dtype):
+    sd = r3m.SPEC_C64 if dtype == r3m.C64 else r3m.SPEC_C128
+    out = torch.empty(r3m.spectral_bytes(n, Dx, Dy, sd), dtype=torch.uint8, device=DEV)
+    r3m.r3m_build_spectral(ctx, dense_dev, n, Dx, Dy, sd, out)
+    return sd, out
+
+
+def matvec(r3m, ctx, store, batch, x, vec_dtype):
+    y = torch.zeros_like(x)
+    work = torch.empty(max(r3m.matvec_work_bytes(ctx, store, batch, vec_dtype), 16), dtype=torch.uint8,
+                       device=DEV)
+    r3m.r3m_retrieved_matvec(ctx, store, batch, vec_dtype, x, y, work)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def oracle_rect(blocks, Dx, Dy, n_a, state_off, book, lx, ly, x):
+    """Oracle product of an lx x ly array: the array embedded in the oracle's
+    square layout with zero x on the padding units (which then add nothing)."""
+    Ls = max(lx, ly)
+    full = np.zeros(Ls * Ls, np.uint8)
+    mask = np.zeros(Ls * Ls, bool)
+    for iy in range(ly):
+        for ix in range(lx):
+            full[iy * Ls + ix] = book[iy * lx + ix]
+            mask[iy * Ls + ix] = True
+    xf = np.zeros((Ls * Ls, n_a), complex)
+    xf[mask] = x.reshape(-1, n_a)
+    n = blocks.shape[1]
+    sub = np.zeros(((2 * Ls - 1) ** 2, n, n), complex)
+    for dy in range(-(Ls - 1), Ls):
+        for dx in range(-(Ls - 1), Ls):
+            if abs(dx) <= Dx and abs(dy) <= Dy:
+                sub[retrieval.slot(dx, dy, Ls - 1, Ls - 1)] = blocks[retrieval.slot(dx, dy, Dx, Dy)]
+    yf = retrieval.retrieved_matvec(sub, Ls - 1, Ls - 1, state_off, full, Ls, xf.reshape(-1))
+    return yf.reshape(-1, n_a)[mask].reshape(-1)
+
+
+@pytest.mark.parametrize("dtype,vec,tol", [("c128", "c128", 1e-12), ("c64", "c128", 2e-6), ("c64", "c64", 2e-6)])
+def test_spectral_oracle_blocks(lib, dtype, vec, tol):
+    r3m, _, ctx = lib
+    Dx, Dy = 3, 2
+    blocks = efie.displacement_blocks(unit(1), Dx, Dy, K, extract=1)
+    st = r3m.C128 if dtype == "c128" else r3m.C64
+    vt = r3m.C128 if vec == "c128" else r3m.C64
+    sd, spec = spectra_of(r3m, ctx, to_dev(blocks), 80, Dx, Dy, st)
+    self_blk = to_dev(blocks[retrieval.slot(0, 0, Dx, Dy)][None], torch.complex128 if st == r3m.C128 else
+                      torch.complex64)
+    store = r3m.Store(80, 2, Dx, Dy, 0, st, self_blk, sd, spec)
+    L = np.array([[4, 3], [1, 1], [3, 2], [2, 3], [4, 1]], np.int32)
+    books, uo = [], []
+    u = 0
+    for b, (lx, ly) in enumerate(L):
+        books.append(cb.bernoulli(4, 70 + b)[: lx * ly])
+        uo.append(u)
+        u += lx * ly
+    batch = r3m.Batch(L, uo, uo, torch.from_numpy(np.concatenate(books)).to(DEV))
+    x = cb.random_complex(u * 40, 31)
+    y = matvec(r3m, ctx, store, batch, to_dev(x, torch.complex128 if vt == r3m.C128 else torch.complex64), vt)
+    if vt == r3m.C64:
+        x = x.astype(np.complex64).astype(np.complex128)
+    worst = 0.0
+    for b, (lx, ly) in enumerate(L):
+        sl = slice(uo[b] * 40, (uo[b] + lx * ly) * 40)
+        ref = oracle_rect(blocks, Dx, Dy, 40, unit(1).state_off, books[b], lx, ly, x[sl])
+        worst = max(worst, rel_max(y[sl], ref))
+    print(f"spectral {dtype} spectra, {vec} vectors: worst element error {worst:.2e}")
+    assert worst <= tol
+
+
+@pytest.fixture(scope="module")
+def fullsize(lib):
+    r3m, pipeline, ctx = lib
+    geom = r3m.UnitGeom.from_macro(unit(2), FREQ, 1)
+    states = cb.uniform(32, 4, 1)
+    batch = r3m.Batch.from_codebooks([states], [32], DEV)
+    dense = pipeline.fill_blocks(ctx, geom, 31, r3m.C128, DEV)
+    s128 = pipeline.spectral_store(ctx, geom, 32, 2, r3m.C128, DEV, dense_c128=dense)
+    s64 = pipeline.spectral_store(ctx, geom, 32, 2, r3m.C64, DEV, dense_c128=dense)
+    plain = r3m.Store(160, 4, 31, 31, 31, r3m.C128, dense)
+    yield geom, states, batch, s128, s64, plain
+
+
+def test_spectral_fullsize_rows(lib, fullsize):
+    from test_gpu_fullsize import oracle_rows, sample
+    r3m, _, ctx = lib
+    geom, states, batch, s128, s64, plain = fullsize
+    st, Zr, _ = oracle_rows()
+    assert np.array_equal(st, states)
+    x = cb.random_complex(32 * 32 * 40, 11)
+    xd = to_dev(x)
+    y_plain = matvec(r3m, ctx, plain, batch, xd, r3m.C128)
+    y128 = matvec(r3m, ctx, s128, batch, xd, r3m.C128)
+    y64 = matvec(r3m, ctx, s64, batch, xd, r3m.C128)
+    e_rows128 = rel_l2(sample(y128), Zr @ x)
+    e_rows64 = rel_l2(sample(y64), Zr @ x)
+    e128 = rel_max(y128, y_plain)
+    e64 = rel_max(y64, y_plain)
+    e64_l2 = rel_l2(y64, y_plain)
+    print(f"32x32 spectral: c128 rows vs oracle {e_rows128:.2e}, vs plain {e128:.2e}; c64 rows vs oracle "
+          f"{e_rows64:.2e}, vs plain max {e64:.2e} l2 {e64_l2:.2e}")
+    assert e_rows128 <= 1e-10 and e128 <= 1e-12
+    assert e64 <= 2e-6 and e64_l2 <= 1e-6
+
+
+def test_spectral_solves(lib, fullsize):
+    r3m, _, ctx = lib
+    geom, _, batch, s128, s64, plain = fullsize
+    N = 32 * 32 * 40
+    dirs = cb.phi0_cut(1.0)
+    b = torch.zeros(N, dtype=torch.complex128, device=DEV)
+    r3m.r3m_plane_wave_rhs(ctx, geom, batch, [[0.0, 0.0, 1.0]], b)
+
+    def solve(st, st64, tol, refine_tol):
+        x = torch.zeros_like(b)
+        work = torch.empty(r3m.gmres_work_bytes(ctx, st, batch, 60, st64), dtype=torch.uint8, device=DEV)
+        _, rep = r3m.r3m_gmres_solve(ctx, st, st64, batch, b, x, tol, 60, 6000, work, refine_tol=refine_tol,
+                                     max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI)
+        sig = torch.zeros(len(dirs), dtype=torch.float64, device=DEV)
+        r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
+        torch.cuda.synchronize()
+        return sig.cpu().numpy(), rep
+
+    s_ref, rep_ref = solve(plain, None, 1e-10, 0.0)
+    assert rep_ref[0][3]
+    s_mix, rep = solve(s64, None, 1e-5, 0.0)
+    s_ref_spec, rep2 = solve(s64, s128, 1e-4, 1e-9)
+    e_mix = rel_l2(s_mix, s_ref)
+    e_ref = rel_l2(s_ref_spec, s_ref)
+    print(f"spectral solves: c64 iters {rep[0][0]} RCS error {e_mix:.2e}; refined to 1e-9 on c128 spectra "
+          f"(steps {rep2[0][1]}) RCS error {e_ref:.2e}")
+    assert rep[0][3] and e_mix <= 1e-4
+    assert rep2[0][3] and rep2[0][2] <= 1e-9 and e_ref <= 1e-7
+
+
+def test_spectral_large(lib):
+    from workloads.configs import large_128x128
+    r3m, pipeline, ctx = lib
+    geom = r3m.UnitGeom.from_macro(unit(1), FREQ, 1)
+    w = large_128x128(16)
+    batch = r3m.Batch.from_codebooks(w.codebooks, w.sizes, DEV)
+    dense = pipeline.fill_blocks(ctx, geom, 127, r3m.C128, DEV)
+    store = pipeline.spectral_store(ctx, geom, 128, 2, r3m.C64, DEV, dense_c128=dense)
+    plain = r3m.Store(80, 2, 127, 127, 127, r3m.C128, dense)
+    N = batch.total_units * 40
+    g = torch.Generator(device=DEV).manual_seed(8)
+    x = torch.complex(torch.randn(N, generator=g, device=DEV), torch.randn(N, generator=g, device=DEV))
+    y = torch.from_numpy(matvec(r3m, ctx, store, batch, x, r3m.C64))
+    n1 = 128 * 128 * 40
+    errs = []
+    for r in (0, 15):
+        sub = r3m.Batch.from_codebooks([w.codebooks[r]], [128], DEV)
+        ys = matvec(r3m, ctx, plain, sub, x[r * n1:(r + 1) * n1].to(torch.complex128), r3m.C128)
+        errs.append(rel_l2(y[r * n1:(r + 1) * n1].numpy(), ys))
+    print(f"large 128x128 x16 spectral c64: errors vs plain {['%.2e' % e for e in errs]}")
+    assert max(errs) <= 1e-6
