@@ -46,67 +46,273 @@ int next_pow2(int v) {
   return p;
 }
 
-// Radix-2 Stockham transforms of lpw lines of length G staged in LDS
-// (forward: exp(-2 pi i j k / G); inverse: exp(+...), unnormalised).  Line l
-// starts at (l / lines_per_grid) * grid_stride + (l % lines_per_grid) *
-// line_step and its elements lie elem_stride apart.  With elem_stride == 1
-// consecutive threads move consecutive elements of a line; otherwise they
-// move the same element of consecutive lines (columns of a row-major grid),
-// so both passes read and write HBM coalesced.  LDS lines are padded to G + 1
-// entries so that the column-order staging does not fall on one bank.
-// Dynamic LDS: 2 * lpw * (G + 1) complex.
-template <typename T>
-__global__ void __launch_bounds__(256)
-fft_lines_kernel(C2<T>* __restrict__ data, int G, int64_t n_lines, int lines_per_grid, int64_t grid_stride,
-                 int line_step, int elem_stride, int lpw, int inverse, const int* __restrict__ live) {
-  if (live && *live == 0) return;
-  extern __shared__ unsigned char smem_raw[];
-  const int P = G + 1;
-  C2<T>* bufa = reinterpret_cast<C2<T>*>(smem_raw);
-  C2<T>* bufb = bufa + (size_t)lpw * P;
-  const int64_t l0 = (int64_t)blockIdx.x * lpw;
-  const int tot = lpw * G;
-  const bool rows = elem_stride == 1;
-  auto addr = [&](int li, int e) -> int64_t {
-    const int64_t l = l0 + li;
-    return (l / lines_per_grid) * grid_stride + (l % lines_per_grid) * (int64_t)line_step + (int64_t)e * elem_stride;
-  };
-  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int li = rows ? t / G : t % lpw;
-    const int e = rows ? t % G : t / lpw;
-    C2<T> v = {0, 0};
-    if (l0 + li < n_lines) v = data[addr(li, e)];
-    bufa[li * P + e] = v;
+// cos and sin of 2 pi m / 16
+constexpr double kC1 = 0.92387953251128674;  // cos(pi / 8)
+constexpr double kC2 = 0.70710678118654752;  // cos(pi / 4)
+constexpr double kC3 = 0.38268343236508977;  // sin(pi / 8)
+constexpr double kCos16[16] = {1, kC1, kC2, kC3, 0, -kC3, -kC2, -kC1, -1, -kC1, -kC2, -kC3, 0, kC3, kC2, kC1};
+constexpr double kSin16[16] = {0, kC3, kC2, kC1, 1, kC1, kC2, kC3, 0, -kC3, -kC2, -kC1, -1, -kC1, -kC2, -kC3};
+
+template <int LG>
+__host__ __device__ constexpr int bitrev(int i) {
+  int r = 0;
+  for (int b = 0; b < LG; ++b) r |= ((i >> b) & 1) << (LG - 1 - b);
+  return r;
+}
+
+// in-register DFT of R <= 16 points, b_q = sum_r a_r exp(sgn 2 pi i r q / R)
+// (iterative radix-2 decimation in time on the bit-reversed input)
+template <typename T, int R, int SGN>
+__device__ __forceinline__ void dft_regs(C2<T>* a) {
+  constexpr int LG = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+  C2<T> b[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) b[bitrev<LG>(i)] = a[i];
+#pragma unroll
+  for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+    for (int i = 0; i < R; i += len) {
+#pragma unroll
+      for (int j = 0; j < len / 2; ++j) {
+        const int m = j * (16 / len);  // twiddle exp(sgn 2 pi i m / 16)
+        const C2<T> u = b[i + j], v = b[i + j + len / 2];
+        C2<T> t;
+        if (m == 0) {
+          t = v;
+        } else if (m == 4) {
+          t = {-SGN * v.im, SGN * v.re};
+        } else {
+          const T c = (T)kCos16[m], sn = (T)(SGN * kSin16[m]);
+          t = {v.re * c - v.im * sn, v.re * sn + v.im * c};
+        }
+        b[i + j] = {u.re + t.re, u.im + t.im};
+        b[i + j + len / 2] = {u.re - t.re, u.im - t.im};
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < R; ++i) a[i] = b[i];
+}
+
+// LDS position of element e of staged line li: lines S = G + G / 16 + 1
+// apart (odd, so column staging spreads over the banks), one pad entry
+// after every 16 elements (spreads the strided writes of the first stage)
+__device__ __forceinline__ int lds_at(int li, int e, int S) { return li * S + e + (e >> 4); }
+
+// One Stockham stage of radix R on the lines staged in LDS: with Ns the
+// product of the earlier radices, item j < G / R of a line takes the inputs
+// j + r G / R, multiplies input r by exp(sgn 2 pi i r k / (Ns R)) with
+// k = j mod Ns, applies the R-point DFT and writes output q to
+// (j / Ns) Ns R + k + q Ns.  A thread holds KE / R items in registers; the
+// barrier between the reads and the writes lets the stage work in place.
+template <typename T, int R, int KE, int SGN>
+__device__ __forceinline__ void stockham_stage(C2<T>* buf, const C2<T>* tw, int lgG, int lgNs, int n_items, int S) {
+  constexpr int LR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+  constexpr int IT = KE / R;
+  const int lgQ = lgG - LR;  // items per line = G / R
+  const int Ns = 1 << lgNs;
+  C2<T> a[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int item = threadIdx.x + it * 256;
+    if (item < n_items) {
+      const int li = item >> lgQ, j = item & ((1 << lgQ) - 1);
+      const int k = j & (Ns - 1);
+      const int tws = lgG - lgNs - LR;  // exp(sgn 2 pi i r k / (Ns R)) = tw[r k G / (Ns R)]
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C2<T> v = buf[lds_at(li, j + (r << lgQ), S)];
+        if (r > 0) {
+          const C2<T> w = tw[(r * k) << tws];
+          v = {v.re * w.re - v.im * w.im, v.re * w.im + v.im * w.re};
+        }
+        a[it][r] = v;
+      }
+      dft_regs<T, R, SGN>(a[it]);
+    }
   }
   __syncthreads();
-  C2<T>* in = bufa;
-  C2<T>* out = bufb;
-  const int half = G >> 1;
-  const T sgn = inverse ? T(1) : T(-1);
-  for (int Ns = 1; Ns < G; Ns <<= 1) {
-    for (int t = threadIdx.x; t < lpw * half; t += blockDim.x) {
-      const int li = t / half, j = t - li * half;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int item = threadIdx.x + it * 256;
+    if (item < n_items) {
+      const int li = item >> lgQ, j = item & ((1 << lgQ) - 1);
       const int k = j & (Ns - 1);
-      const C2<T> u = in[li * P + j];
-      const C2<T> c = in[li * P + j + half];
-      T s, co;
-      sincospi_t<T>((T)k / (T)Ns, &s, &co);
-      s *= sgn;  // w = cos(pi k / Ns) + sgn i sin(pi k / Ns)
-      const C2<T> cw = {c.re * co - c.im * s, c.re * s + c.im * co};
-      const int o = li * P + (j / Ns) * 2 * Ns + k;
-      out[o] = {u.re + cw.re, u.im + cw.im};
-      out[o + Ns] = {u.re - cw.re, u.im - cw.im};
+      const int o = ((j >> lgNs) << (lgNs + LR)) + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) buf[lds_at(li, o + (q << lgNs), S)] = a[it][q];
     }
-    __syncthreads();
-    C2<T>* tmp = in;
-    in = out;
-    out = tmp;
   }
+  __syncthreads();
+}
+
+// Mixed-radix Stockham transforms of grid lines staged in LDS (forward:
+// exp(-2 pi i j k / G); inverse: exp(+...), unnormalised), radix KE stages
+// (16 in single, 8 in double precision) and one smaller stage for the rest
+// of log2 G.  Grids are row-major Gy x Gx (element (gx, gy) at gy Gx + gx);
+// a pass transforms every row (elements adjacent) or every column (elements
+// Gx apart) of n_grids grids.  A workgroup takes lpw <= 256 KE / G adjacent
+// lines of one grid: along rows consecutive threads move consecutive
+// elements of a line, along columns the same element of consecutive lines,
+// so both passes read and write HBM coalesced.  The twiddles exp(-+ 2 pi i m
+// / G), m < G, are tabulated in LDS once per workgroup.  All extents are
+// powers of two and the index arithmetic is shifts and masks.
+//
+// The retrieval passes fuse the masking of the product into the transforms
+// (grid g = b n + c holds macro channel c of right-hand side b, whose array is
+// Lx x Ly units at the grid's origin):
+//   kFwdRows  rows from the compact input: entry (gx, gy) is x of unit
+//             u = gy Lx + gx at row c - s_u n_a when that row is active
+//             (0 <= c - s_u n_a < n_a), else zero; only rows gy < Ly are
+//             written (the others are zero and never read);
+//   kFwdCols  columns, rows gy >= Ly taken as zero;
+//   kInvCols  columns, only rows gy < Ly written back;
+//   kInvRows  rows gy < Ly, written straight to the compact output
+//             (active rows only, times 1 / (Gx Gy)).
+enum FftMode { kPlainRows, kPlainCols, kFwdRows, kFwdCols, kInvCols, kInvRows };
+
+template <typename T>
+struct FftArgs {
+  C2<T>* data;
+  int lgG;      // log2 of the transform length
+  int lg_lpg;   // log2 of the lines per grid (the other extent)
+  int lg_lpw;   // log2 of the lines per workgroup (<= lg_lpg)
+  const RhsDev* rhs;  // retrieval passes only
+  const uint8_t* states;
+  int n_states, n, n_a;
+  const void* x;  // kFwdRows
+  void* y;        // kInvRows
+  const int* live;
+};
+
+template <typename T>
+constexpr int fft_ke() {
+  return sizeof(T) == 4 ? 16 : 8;
+}
+
+template <typename T, int MODE, typename VT>
+__global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
+  if (A.live && *A.live == 0) return;
+  constexpr bool rows = MODE == kPlainRows || MODE == kFwdRows || MODE == kInvRows;
+  constexpr bool masked = MODE >= kFwdRows;
+  constexpr int SGN = MODE == kInvCols || MODE == kInvRows ? 1 : -1;
+  constexpr int KE = fft_ke<T>();
+  extern __shared__ unsigned char smem_raw[];
+  const int lgG = A.lgG, G = 1 << lgG;
+  const int S = G + (G >> 4) + 1;
+  const int lpw = 1 << A.lg_lpw;
+  const int64_t l0 = (int64_t)blockIdx.x << A.lg_lpw;
+  const int64_t g = l0 >> A.lg_lpg;
+  const int lig0 = (int)(l0 & ((1 << A.lg_lpg) - 1));
+  const int lgGx = rows ? lgG : A.lg_lpg;
+  C2<T>* grid = A.data + (g << (lgG + A.lg_lpg));
+  int Lx = 0, Ly = 0, c = 0;
+  RhsDev R{};
+  if (masked) {
+    const int b = (int)(g / A.n);
+    c = (int)(g - (int64_t)b * A.n);
+    R = A.rhs[b];
+    Lx = R.Lx;
+    Ly = R.Ly;
+    if ((MODE == kFwdRows || MODE == kInvRows) && lig0 >= Ly) return;  // rows past the array
+  }
+  // the active macro row of unit u in channel c, or -1
+  auto active = [&](int64_t u) -> int {
+    const int s = min((int)A.states[R.state_off + u], A.n_states - 1);
+    const int r = c - s * A.n_a;
+    return r >= 0 && r < A.n_a ? r : -1;
+  };
+  C2<T>* buf = reinterpret_cast<C2<T>*>(smem_raw);
+  C2<T>* tw = buf + (size_t)lpw * S;
+  for (int m = threadIdx.x; m < G; m += blockDim.x) {
+    T sn, cs;
+    sincospi_t<T>((T)(2 * m) / (T)G, &sn, &cs);
+    tw[m] = {cs, (T)SGN * sn};
+  }
+  const int tot = lpw << lgG;
   for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int li = rows ? t / G : t % lpw;
-    const int e = rows ? t % G : t / lpw;
-    if (l0 + li < n_lines) data[addr(li, e)] = in[li * P + e];
+    const int li = rows ? t >> lgG : t & (lpw - 1);
+    const int e = rows ? t & (G - 1) : t >> A.lg_lpw;
+    const int line = lig0 + li;
+    const int gx = rows ? e : line, gy = rows ? line : e;
+    C2<T> v = {0, 0};
+    if (MODE == kFwdRows) {
+      if (gx < Lx && gy < Ly) {
+        const int64_t u = (int64_t)gy * Lx + gx;
+        const int r = active(u);
+        if (r >= 0) {
+          const VT* xv = (const VT*)A.x + ((R.unit_off + u) * A.n_a + r) * 2;
+          v = {(T)xv[0], (T)xv[1]};
+        }
+      }
+    } else if (MODE == kFwdCols || MODE == kInvRows) {
+      if (gy < Ly) v = grid[((int64_t)gy << lgGx) + gx];
+    } else {
+      v = grid[((int64_t)gy << lgGx) + gx];
+    }
+    buf[lds_at(li, e, S)] = v;
   }
+  __syncthreads();
+  constexpr int LKE = KE == 16 ? 4 : 3;
+  int lgNs = 0;
+  for (; lgNs + LKE <= lgG; lgNs += LKE) stockham_stage<T, KE, KE, SGN>(buf, tw, lgG, lgNs, tot >> LKE, S);
+  switch (lgG - lgNs) {
+    case 1: stockham_stage<T, 2, KE, SGN>(buf, tw, lgG, lgNs, tot >> 1, S); break;
+    case 2: stockham_stage<T, 4, KE, SGN>(buf, tw, lgG, lgNs, tot >> 2, S); break;
+    case 3: stockham_stage<T, 8, KE, SGN>(buf, tw, lgG, lgNs, tot >> 3, S); break;
+    default: break;
+  }
+  const T scale = T(1) / (T)((int64_t)1 << (lgG + A.lg_lpg));
+  for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+    const int li = rows ? t >> lgG : t & (lpw - 1);
+    const int e = rows ? t & (G - 1) : t >> A.lg_lpw;
+    const int line = lig0 + li;
+    const int gx = rows ? e : line, gy = rows ? line : e;
+    const C2<T> v = buf[lds_at(li, e, S)];
+    if (MODE == kInvRows) {
+      if (gx < Lx && gy < Ly) {
+        const int64_t u = (int64_t)gy * Lx + gx;
+        const int r = active(u);
+        if (r >= 0) {
+          VT* yv = (VT*)A.y + ((R.unit_off + u) * A.n_a + r) * 2;
+          yv[0] = (VT)(v.re * scale);
+          yv[1] = (VT)(v.im * scale);
+        }
+      }
+    } else if (MODE == kFwdRows || MODE == kInvCols) {
+      if (gy < Ly) grid[((int64_t)gy << lgGx) + gx] = v;
+    } else {
+      grid[((int64_t)gy << lgGx) + gx] = v;
+    }
+  }
+}
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
+
+// lines per workgroup (log2): up to 256 KE elements per workgroup, at most
+// the lines of one grid
+template <typename T>
+int fft_lpw_log(int lgG, int lg_lpg) {
+  constexpr int LKE = fft_ke<T>() == 16 ? 4 : 3;
+  return std::max(0, std::min(8 + LKE - lgG, lg_lpg));
+}
+
+// one pass over every row or column (by MODE) of n_grids Gy x Gx grids
+template <typename T, int MODE, typename VT>
+void fft_pass(FftArgs<T> A, int lgGx, int lgGy, int64_t n_grids, hipStream_t s) {
+  constexpr bool rows = MODE == kPlainRows || MODE == kFwdRows || MODE == kInvRows;
+  A.lgG = rows ? lgGx : lgGy;
+  A.lg_lpg = rows ? lgGy : lgGx;
+  A.lg_lpw = fft_lpw_log<T>(A.lgG, A.lg_lpg);
+  const int G = 1 << A.lgG;
+  const int64_t n_wg = (n_grids << A.lg_lpg) >> A.lg_lpw;
+  const size_t lds = ((size_t)((size_t)1 << A.lg_lpw) * (G + (G >> 4) + 1) + G) * sizeof(C2<T>);
+  hipLaunchKernelGGL((fft_kernel<T, MODE, VT>), dim3((unsigned)n_wg), dim3(256), lds, s, A);
+  R3M_CHECK_HIP(hipGetLastError());
 }
 
 // Circulant embedding of the displacement blocks dense[slot][m][n]
@@ -134,152 +340,113 @@ spec_embed_kernel(const double2* __restrict__ dense, int n, int Dx, int Dy, int 
   }
 }
 
-// x~ of right-hand side b on its grid (blockIdx.y = b)
-template <typename T, typename XT>
-__global__ void __launch_bounds__(256)
-spec_expand_kernel(const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, int n_states, int n, int n_a,
-                   const XT* __restrict__ x, int Gx, int Gy, C2<T>* __restrict__ X, const int* __restrict__ live) {
-  if (live && *live == 0) return;
-  const int b = blockIdx.y;
-  const RhsDev R = rhs[b];
-  const int64_t G2 = (int64_t)Gx * Gy;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)n * G2) return;
-  const int ch = (int)(e / G2);
-  const int64_t k = e - (int64_t)ch * G2;
-  const int gy = (int)(k / Gx), gx = (int)(k - (int64_t)gy * Gx);
-  C2<T> v = {0, 0};
-  if (gx < R.Lx && gy < R.Ly) {
-    const int64_t u = (int64_t)gy * R.Lx + gx;
-    const int s = min((int)states[R.state_off + u], n_states - 1);
-    const int r = ch - s * n_a;
-    if (r >= 0 && r < n_a) {
-      const size_t xi = ((size_t)(R.unit_off + u) * n_a + r) * 2;
-      v = {(T)x[xi], (T)x[xi + 1]};
-    }
-  }
-  X[(size_t)b * n * G2 + e] = v;
-}
-
-// Y^[b][m][k] = sum_c Z^[m][c][k] X^[b][c][k].  A thread owns one frequency k
-// of one row m for a chunk of kBC right-hand sides (each Z^ entry is loaded
-// once per chunk).  The chunk index varies fastest over workgroup ids, so the
-// chunks that share a slice of Z^ run together and meet it in cache.
-constexpr int kBC = 8;
-template <typename T>
+// Y^[b][m][k] = sum_c Z^[m][c][k] X^[b][c][k]: one n x n product per
+// frequency k.  A thread owns one frequency, MT rows and BC right-hand sides
+// (2 MT BC accumulators); per column c it loads MT spectra entries and BC
+// inputs.  The four waves of a workgroup take adjacent row tiles of the same
+// 64 frequencies, so they read the same inputs close together (cache hits),
+// and workgroup ids run over RHS chunks first, then row tiles, then
+// frequency blocks, so the workgroups that share a slice of X^ or Z^ are in
+// flight together.
+template <typename T, int MT, int BC>
 __global__ void __launch_bounds__(256)
 spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, C2<T>* __restrict__ Yh, int n,
-                    int64_t K, int B, int n_kb, const int* __restrict__ live) {
+                    int64_t K, int B, int n_mg, const int* __restrict__ live) {
   if (live && *live == 0) return;
-  const int nz = (B + kBC - 1) / kBC;
+  const int nz = (B + BC - 1) / BC;
   const int64_t id = blockIdx.x;
   const int z = (int)(id % nz);
   const int64_t rest = id / nz;
-  const int kb = (int)(rest % n_kb);
-  const int m = (int)(rest / n_kb);
-  const int64_t k = (int64_t)kb * blockDim.x + threadIdx.x;
-  if (k >= K) return;
-  const int b0 = z * kBC;
-  const int nb = min(kBC, B - b0);
-  T ar[kBC], ai[kBC];
+  const int mg = (int)(rest % n_mg);
+  const int64_t kb = rest / n_mg;
+  const int64_t k = kb * 64 + (threadIdx.x & 63);
+  const int m0 = (mg * 4 + (threadIdx.x >> 6)) * MT;
+  if (k >= K || m0 >= n) return;
+  const int b0 = z * BC;
+  const int nb = min(BC, B - b0);
+  T ar[MT][BC], ai[MT][BC];
 #pragma unroll
-  for (int q = 0; q < kBC; ++q) ar[q] = ai[q] = 0;
-  const C2<T>* zr = Zh + (size_t)m * n * K + k;
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int q = 0; q < BC; ++q) ar[i][q] = ai[i][q] = 0;
+  const C2<T>* zr = Zh + (size_t)m0 * n * K + k;
   const C2<T>* xr = Xh + (size_t)b0 * n * K + k;
-#pragma unroll 2
+  const int mt = min(MT, n - m0);
+  constexpr int kUnroll = MT * BC <= 4 ? 4 : 2;
+#pragma unroll kUnroll
   for (int c = 0; c < n; ++c) {
-    const C2<T> zv = zr[(size_t)c * K];
+    C2<T> zv[MT], xv[BC];
 #pragma unroll
-    for (int q = 0; q < kBC; ++q) {
-      if (q < nb) {
-        const C2<T> xv = xr[((size_t)q * n + c) * K];
-        ar[q] = fma(zv.re, xv.re, ar[q]);
-        ar[q] = fma(-zv.im, xv.im, ar[q]);
-        ai[q] = fma(zv.re, xv.im, ai[q]);
-        ai[q] = fma(zv.im, xv.re, ai[q]);
+    for (int i = 0; i < MT; ++i) zv[i] = i < mt ? zr[((size_t)i * n + c) * K] : C2<T>{0, 0};
+#pragma unroll
+    for (int q = 0; q < BC; ++q) xv[q] = q < nb ? xr[((size_t)q * n + c) * K] : C2<T>{0, 0};
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+      for (int q = 0; q < BC; ++q) {
+        ar[i][q] = fma(zv[i].re, xv[q].re, ar[i][q]);
+        ar[i][q] = fma(-zv[i].im, xv[q].im, ar[i][q]);
+        ai[i][q] = fma(zv[i].re, xv[q].im, ai[i][q]);
+        ai[i][q] = fma(zv[i].im, xv[q].re, ai[i][q]);
       }
-    }
   }
 #pragma unroll
-  for (int q = 0; q < kBC; ++q)
-    if (q < nb) Yh[((size_t)(b0 + q) * n + m) * K + k] = {ar[q], ai[q]};
+  for (int i = 0; i < MT; ++i)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+      if (i < mt && q < nb) Yh[((size_t)(b0 + q) * n + m0 + i) * K + k] = {ar[i][q], ai[i][q]};
 }
 
-// y_i = y~_i[A(s_i)] / (Gx Gy): the active rows of each unit, with the
-// normalisation of the unnormalised inverse transform (blockIdx.y = b)
-template <typename T, typename YT>
-__global__ void __launch_bounds__(256)
-spec_gather_kernel(const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, int n_states, int n, int n_a,
-                   const C2<T>* __restrict__ Y, int Gx, int Gy, YT* __restrict__ y, const int* __restrict__ live) {
-  if (live && *live == 0) return;
-  const int b = blockIdx.y;
-  const RhsDev R = rhs[b];
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)R.Lx * R.Ly * n_a) return;
-  const int64_t u = e / n_a;
-  const int r = (int)(e - u * n_a);
-  const int gy = (int)(u / R.Lx), gx = (int)(u - (int64_t)gy * R.Lx);
-  const int s = min((int)states[R.state_off + u], n_states - 1);
-  const int64_t G2 = (int64_t)Gx * Gy;
-  const C2<T> v = Y[((size_t)b * n + s * n_a + r) * G2 + (int64_t)gy * Gx + gx];
-  const T sc = T(1) / (T)G2;
-  const size_t yi = ((size_t)R.unit_off * n_a + e) * 2;
-  y[yi] = (YT)(v.re * sc);
-  y[yi + 1] = (YT)(v.im * sc);
+template <typename T, int MT, int BC>
+void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, hipStream_t s,
+                    const int* live) {
+  const int n_mg = (n + 4 * MT - 1) / (4 * MT);
+  const int64_t nwg = (G2 + 63) / 64 * n_mg * ((B + BC - 1) / BC);
+  hipLaunchKernelGGL((spec_product_kernel<T, MT, BC>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y, n, G2, B,
+                     n_mg, live);
 }
 
-// lines per workgroup: as many as fill one LDS buffer of `cap` entries, fewer
-// while the launch has under 2048 workgroups, down to min_lpw
-int lines_per_wg(int G, int other, int64_t lines, int cap, int min_lpw) {
-  int lpw = std::max(1, std::min(cap / (G + 1), other));
-  int p = 1;
-  while (p * 2 <= lpw) p *= 2;  // a power of two, so a workgroup stays inside one grid
-  lpw = p;
-  while (lpw > min_lpw && (lines + lpw - 1) / lpw < 2048) lpw /= 2;
-  return lpw;
-}
-
+// register tile by batch width: 2 rows for one or two right-hand sides (a
+// stream of the spectra wants many waves in flight), 4 rows x 4 or 8
+// right-hand sides otherwise (arithmetic per load)
 template <typename T>
-void fft2(C2<T>* data, int64_t n_grids, int Gx, int Gy, int inverse, hipStream_t s, const int* live) {
-  const int cap = sizeof(T) == 4 ? 4096 : 2048;  // complex entries per LDS buffer (two buffers)
-  {  // along x: lines are rows
-    const int64_t lines = n_grids * Gy;
-    const int lpw = lines_per_wg(Gx, Gy, lines, cap, 1);
-    const size_t lds = 2 * (size_t)lpw * (Gx + 1) * sizeof(C2<T>);
-    hipLaunchKernelGGL(fft_lines_kernel<T>, dim3((unsigned)((lines + lpw - 1) / lpw)), dim3(256), lds, s, data, Gx,
-                       lines, Gy, (int64_t)Gx * Gy, Gx, 1, lpw, inverse, live);
-  }
-  {  // along y: lines are columns; a workgroup takes lpw adjacent columns of one grid
-    const int64_t lines = n_grids * Gx;
-    const int lpw = lines_per_wg(Gy, Gx, lines, cap, std::min(Gx, 16));
-    const size_t lds = 2 * (size_t)lpw * (Gy + 1) * sizeof(C2<T>);
-    hipLaunchKernelGGL(fft_lines_kernel<T>, dim3((unsigned)((lines + lpw - 1) / lpw)), dim3(256), lds, s, data, Gy,
-                       lines, Gx, (int64_t)Gx * Gy, 1, Gx, lpw, inverse, live);
-  }
-  R3M_CHECK_HIP(hipGetLastError());
+void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, hipStream_t s, const int* live) {
+  if (B == 1)
+    launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, s, live);
+  else if (B == 2)
+    launch_product<T, 2, 2>(Zh, X, Y, n, G2, B, s, live);
+  else if (B <= 4)
+    launch_product<T, 4, 4>(Zh, X, Y, n, G2, B, s, live);
+  else
+    launch_product<T, 4, 8>(Zh, X, Y, n, G2, B, s, live);
 }
 
 template <typename T, typename XT, typename YT>
 void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
                     void* work, hipStream_t s, const int* live) {
-  const int n = Z->n, n_a = Z->n / Z->n_states;
-  const int Gx = next_pow2(2 * Z->Dx + 1), Gy = next_pow2(2 * Z->Dy + 1);
-  const int64_t G2 = (int64_t)Gx * Gy;
+  const int n = Z->n;
+  const int lgGx = ilog2(next_pow2(2 * Z->Dx + 1)), lgGy = ilog2(next_pow2(2 * Z->Dy + 1));
+  const int64_t G2 = (int64_t)1 << (lgGx + lgGy);
   const int B = bd.B;
   C2<T>* X = (C2<T>*)work;
   C2<T>* Y = X + (size_t)B * n * G2;
-  const C2<T>* Zh = (const C2<T>*)Z->far;
-  hipLaunchKernelGGL((spec_expand_kernel<T, XT>), dim3(ceil_div((size_t)n * G2, 256), B), dim3(256), 0, s, bd.rhs,
-                     states, Z->n_states, n, n_a, (const XT*)x, Gx, Gy, X, live);
-  fft2<T>(X, (int64_t)B * n, Gx, Gy, 0, s, live);
-  const int n_kb = (int)ceil_div((size_t)G2, 256);
-  const int64_t nwg = (int64_t)n_kb * n * ((B + kBC - 1) / kBC);
-  hipLaunchKernelGGL(spec_product_kernel<T>, dim3((unsigned)nwg), dim3(256), 0, s, Zh, (const C2<T>*)X, Y, n, G2, B,
-                     n_kb, live);
-  fft2<T>(Y, (int64_t)B * n, Gx, Gy, 1, s, live);
-  hipLaunchKernelGGL((spec_gather_kernel<T, YT>), dim3(ceil_div((size_t)bd.max_units * n_a, 256), B), dim3(256), 0,
-                     s, bd.rhs, states, Z->n_states, n, n_a, (const C2<T>*)Y, Gx, Gy, (YT*)y, live);
-  R3M_CHECK_HIP(hipGetLastError());
+  FftArgs<T> A{};
+  A.rhs = bd.rhs;
+  A.states = states;
+  A.n_states = Z->n_states;
+  A.n = n;
+  A.n_a = n / Z->n_states;
+  A.x = x;
+  A.y = y;
+  A.live = live;
+  const int64_t ng = (int64_t)B * n;
+  A.data = X;
+  fft_pass<T, kFwdRows, XT>(A, lgGx, lgGy, ng, s);
+  fft_pass<T, kFwdCols, XT>(A, lgGx, lgGy, ng, s);
+  product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, s, live);
+  A.data = Y;
+  fft_pass<T, kInvCols, YT>(A, lgGx, lgGy, ng, s);
+  fft_pass<T, kInvRows, YT>(A, lgGx, lgGy, ng, s);
 }
 
 size_t spectra_bytes(int n, int Dx, int Dy, r3m_dtype dtype) {
@@ -356,11 +523,17 @@ int r3m_build_spectral(r3m_ctx ctx, const void* dense_dev, int32_t n, int32_t Dx
     if (dtype == R3M_SPEC_C128) {
       hipLaunchKernelGGL(spec_embed_kernel<double>, dim3(blocks), dim3(256), 0, stream, (const double2*)dense_dev, n,
                          Dx, Dy, Gx, Gy, (C2<double>*)spec_dev);
-      fft2<double>((C2<double>*)spec_dev, (int64_t)n * n, Gx, Gy, 0, stream, nullptr);
+      FftArgs<double> A{};
+      A.data = (C2<double>*)spec_dev;
+      fft_pass<double, kPlainRows, double>(A, ilog2(Gx), ilog2(Gy), (int64_t)n * n, stream);
+      fft_pass<double, kPlainCols, double>(A, ilog2(Gx), ilog2(Gy), (int64_t)n * n, stream);
     } else {
       hipLaunchKernelGGL(spec_embed_kernel<float>, dim3(blocks), dim3(256), 0, stream, (const double2*)dense_dev, n,
                          Dx, Dy, Gx, Gy, (C2<float>*)spec_dev);
-      fft2<float>((C2<float>*)spec_dev, (int64_t)n * n, Gx, Gy, 0, stream, nullptr);
+      FftArgs<float> A{};
+      A.data = (C2<float>*)spec_dev;
+      fft_pass<float, kPlainRows, float>(A, ilog2(Gx), ilog2(Gy), (int64_t)n * n, stream);
+      fft_pass<float, kPlainCols, float>(A, ilog2(Gx), ilog2(Gy), (int64_t)n * n, stream);
     }
     R3M_CHECK_HIP(hipGetLastError());
   });
