@@ -52,6 +52,8 @@ def parse():
     p.add_argument("--max-iter", type=int, default=6000)
     p.add_argument("--ref-tol", type=float, default=1e-10)
     p.add_argument("--precond", type=int, default=1, help="0 none, 1 block-Jacobi (self blocks)")
+    p.add_argument("--no-spectral", action="store_true",
+                   help="skip the FFT-path legs (2-bit 32x32 spectral solve, 1-bit 128x128 x 16 refined solve)")
     return p.parse_args()
 
 
@@ -108,6 +110,129 @@ def cpu_baseline(L, n, n_a, n_matvec):
                    f"scaled by the {n_matvec} matvecs of one GPU solve"),
         "matvec_s": dt,
     }
+
+
+def spectral_cost(n, D, B):
+    """Algorithmic bytes and flops of one spectral matvec (complex64 spectra):
+    the spectra read once, the compact x read and y written once; flops of
+    the per-frequency products (8 n^2 per frequency per RHS) and of the four
+    transform passes (5 G log2 G per line, real flops of a radix-2 count)."""
+    import math
+    G = 1
+    while G < 2 * D + 1:
+        G *= 2
+    G2 = G * G
+    byt = n * n * G2 * 8
+    flops = 8.0 * n * n * G2 * B + 4 * 5.0 * G2 * math.log2(G) * n * B
+    return byt, flops, G
+
+
+def timed_matvec(r3m, ctx, store, batch, x, vt, reps):
+    import torch
+    y = torch.zeros_like(x)
+    work = torch.empty(max(r3m.matvec_work_bytes(ctx, store, batch, vt), 16), dtype=torch.uint8, device=x.device)
+    r3m.r3m_retrieved_matvec(ctx, store, batch, vt, x, y, work)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        r3m.r3m_retrieved_matvec(ctx, store, batch, vt, x, y, work, index_ready=True)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def spectral_leg(ctx, geom, batch, dense, sig_ref, dirs, inc, N, args):
+    """The same 2-bit 32x32 workload through the FFT form of the matvec
+    (complex64 block spectra: the dense operator, no compression)."""
+    import numpy as np
+    import torch
+    from paper_2112_05082_amd import pipeline, r3m
+    dev = "cuda:0"
+    L = args.L
+    t0 = time.perf_counter()
+    spec = pipeline.spectral_store(ctx, geom, L, 2, r3m.C64, dev, dense_c128=dense)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    b = torch.zeros(N, dtype=torch.complex128, device=dev)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, spec, batch, args.restart), dtype=torch.uint8, device=dev)
+
+    def solve():
+        r3m.r3m_plane_wave_rhs(ctx, geom, batch, inc, b)
+        x = torch.empty_like(b)
+        _, rep = r3m.r3m_gmres_solve(ctx, spec, None, batch, b, x, args.gmres_tol, args.restart, args.max_iter,
+                                     work, allow_not_converged=True, precond=args.precond)
+        sig = torch.empty(len(dirs), dtype=torch.float64, device=dev)
+        r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
+        return x, sig, rep
+
+    solve()
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    outs = [solve() for _ in range(reps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    err = max(float(np.linalg.norm(o[1].cpu().numpy() - sig_ref) / np.linalg.norm(sig_ref)) for o in outs)
+    mv = timed_matvec(r3m, ctx, spec, batch, outs[-1][0], r3m.C128, 20)
+    byt, flops, G = spectral_cost(spec.n, L - 1, 1)
+    return {"solves_per_s": reps / dt, "rcs_rel_err": err, "gmres_iters": outs[-1][2][0][0],
+            "matvec_ms": mv * 1e3, "matvec_gbps": byt / mv / 1e9, "matvec_tflops": flops / mv / 1e12,
+            "grid": [G, G], "spectra_bytes": byt, "build_s": t_build}
+
+
+def large_leg(ctx, args):
+    """1-bit 128x128 units x 16 Bernoulli codebooks, normal incidence: inner
+    GMRES on complex64 block spectra, FP64 refinement residual on complex128
+    spectra of the same blocks, to 1e-5 (the large workload)."""
+    import torch
+    from paper_2112_05082_amd import pipeline, r3m
+    from workloads.configs import FREQ_HZ, SIDES_1BIT, large_128x128
+    from workloads.mesh import macro_unit
+    dev = "cuda:0"
+    w = large_128x128(16)
+    unit = macro_unit(SIDES_1BIT)
+    geom = r3m.UnitGeom.from_macro(unit, FREQ_HZ, 1)
+    batch = r3m.Batch.from_codebooks(w.codebooks, w.sizes, dev)
+    t0 = time.perf_counter()
+    dense = pipeline.fill_blocks(ctx, geom, 127, r3m.C128, dev)
+    torch.cuda.synchronize()
+    t_fill = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    s64 = pipeline.spectral_store(ctx, geom, 128, 2, r3m.C64, dev, dense_c128=dense)
+    s128 = pipeline.spectral_store(ctx, geom, 128, 2, r3m.C128, dev, dense_c128=dense)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    del dense
+    torch.cuda.empty_cache()
+    N = batch.total_units * unit.n_a
+    g = torch.Generator(device=dev).manual_seed(5)
+    xr = torch.complex(torch.randn(N, generator=g, device=dev), torch.randn(N, generator=g, device=dev))
+    mv64 = timed_matvec(r3m, ctx, s64, batch, xr.to(torch.complex64), r3m.C64, 10)
+    mv128 = timed_matvec(r3m, ctx, s128, batch, xr.to(torch.complex128), r3m.C128, 5)
+    del xr
+    torch.cuda.empty_cache()
+    b = torch.zeros(N, dtype=torch.complex128, device=dev)
+    r3m.r3m_plane_wave_rhs(ctx, geom, batch, [[0.0, 0.0, 1.0]] * batch.B, b)
+    x = torch.zeros_like(b)
+    restart = 30
+    work = torch.empty(r3m.gmres_work_bytes(ctx, s64, batch, restart, s128), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, 1e-3, restart, 3000, work, refine_tol=w.refine_tol,
+                                 max_refine=20, precond=args.precond, allow_not_converged=True)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    byt, flops, G = spectral_cost(80, 127, batch.B)
+    return {"workload": "1-bit 128x128 units x 16 Bernoulli codebooks, normal incidence, block spectra "
+                        "(complex64 inner GMRES(30) to 1e-3, complex128 refinement residual to 1e-5)",
+            "rhs": batch.B, "retrieved_unknowns_per_rhs": 128 * 128 * unit.n_a,
+            "matvec_ms_c64": mv64 * 1e3, "matvec_ms_c128": mv128 * 1e3,
+            "matvec_gbps_c64": byt / mv64 / 1e9, "matvec_tflops_c64": flops / mv64 / 1e12,
+            "solve_s": t_solve, "solves_per_s": batch.B / t_solve,
+            "converged": all(r[3] for r in rep), "max_rel_residual": max(r[2] for r in rep),
+            "inner_iters_max": max(r[0] for r in rep), "refine_steps_max": max(r[1] for r in rep),
+            "setup_s": {"fill_c128_all_blocks": t_fill, "spectra_c64_c128": t_build}}
 
 
 def main():
@@ -270,6 +395,13 @@ def main():
         "speedup_vs_plain_fp64": value * t_plain,
         "setup_s": {"fill_c128_all_blocks": t_fill, "near_fill_and_aca": t_compress},
     }
+    if not args.no_spectral:
+        del work, workp, cal, cal2, bufs
+        torch.cuda.empty_cache()
+        out["spectral_32x32"] = spectral_leg(ctx, geom, batch, dense, sig_ref, dirs, inc, N, args)
+        del dense, plain, store
+        torch.cuda.empty_cache()
+        out["large_128x128"] = large_leg(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, n, n_a, iters + 2)
     ctx.close()

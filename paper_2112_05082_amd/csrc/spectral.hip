@@ -13,6 +13,8 @@
 // frequency: Y^(k) = Z^(k) X^(k) with X^ = FFT2[x~], y~ = IFFT2[Y^].  The
 // result is the dense retrieval product up to rounding (no far-field
 // compression); the store carries the spectra Z^ in place of far factors.
+// (Sec. I cites this block-Toeplitz FFT route for periodic arrays, the array
+// decomposition method.)
 //
 // Layouts (complex, interleaved; grids row-major, k = gy * Gx + gx):
 //   spectra  Z^[m][n][Gy][Gx]     (m, n macro rows and columns)
@@ -397,6 +399,107 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
       if (i < mt && q < nb) Yh[((size_t)(b0 + q) * n + m0 + i) * K + k] = {ar[i][q], ai[i][q]};
 }
 
+// Matrix-core form of the same product for complex64 spectra and wide
+// batches: per frequency Y^(k) = Z^(k) X^(k) is an (n x n) x (n x B) complex
+// GEMM, taken as four real GEMMs (Re Y = Re Z Re X - Im Z Im X, Im Y = Re Z
+// Im X + Im Z Re X) on 16x16x4 FP32 MFMA tiles (lane l holds A[l % 16][l / 16]
+// and B[l / 16][l % 16]; result rows 4 (l / 16) + r, column l % 16).  A
+// workgroup owns 16 frequencies x 80 rows x 16 right-hand sides; wave w takes
+// frequencies 4w .. 4w + 3 for all five row tiles.  Columns are consumed in
+// chunks of 4: the chunk is staged in LDS as [c][k][m] and [c][k][b] (rows
+// contiguous per frequency, padded strides) while the next chunk is already
+// in flight from global memory (128-byte runs of 16 frequencies).  Results
+// leave through LDS one row tile at a time, again as 16-frequency runs.
+// Workgroup ids run over RHS tiles first, so the tiles that share a slice of
+// the spectra are in flight together.
+constexpr int kPK = 16, kPM = 80, kPB = 16, kPC = 4;
+constexpr int kZP = kPM + 1, kXP = kPB + 1, kYP = kPK + 1;
+
+__global__ void __launch_bounds__(256)
+spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __restrict__ Xh, C2<float>* __restrict__ Yh,
+                         int n, int64_t K, int B, int n_mg, int n_bt, const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __shared__ C2<float> Zs[kPC * kPK * kZP];  // [c][k][m]; reused as the output tile [b][m][k]
+  __shared__ C2<float> Xs[kPC * kPK * kXP];  // [c][k][b]
+  const int64_t id = blockIdx.x;
+  const int bt = (int)(id % n_bt);
+  const int64_t r1 = id / n_bt;
+  const int mg = (int)(r1 % n_mg);
+  const int64_t k0 = (r1 / n_mg) * kPK;
+  const int m0 = mg * kPM, b0 = bt * kPB;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  v4 are[4][5], aim[4][5];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int t = 0; t < 5; ++t) are[q][t] = aim[q][t] = v4{0, 0, 0, 0};
+  constexpr int NZ = kPC * kPK * kPM / 256, NX = kPC * kPK * kPB / 256;  // 20, 4 entries per thread
+  C2<float> zp[NZ], xp[NX];
+  auto load_chunk = [&](int c0) {
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+      const int e = tid + 256 * i, k = e & 15, c = (e >> 4) & 3, m = e >> 6;
+      const bool ok = m0 + m < n && c0 + c < n && k0 + k < K;
+      zp[i] = ok ? Zh[((int64_t)(m0 + m) * n + c0 + c) * K + k0 + k] : C2<float>{0, 0};
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int e = tid + 256 * i, k = e & 15, c = (e >> 4) & 3, b = e >> 6;
+      const bool ok = b0 + b < B && c0 + c < n && k0 + k < K;
+      xp[i] = ok ? Xh[((int64_t)(b0 + b) * n + c0 + c) * K + k0 + k] : C2<float>{0, 0};
+    }
+  };
+  load_chunk(0);
+  for (int c0 = 0; c0 < n; c0 += kPC) {
+    __syncthreads();  // the previous chunk's fragments have been read
+#pragma unroll
+    for (int i = 0; i < NZ; ++i) {
+      const int e = tid + 256 * i, k = e & 15, c = (e >> 4) & 3, m = e >> 6;
+      Zs[(c * kPK + k) * kZP + m] = zp[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NX; ++i) {
+      const int e = tid + 256 * i, k = e & 15, c = (e >> 4) & 3, b = e >> 6;
+      Xs[(c * kPK + k) * kXP + b] = xp[i];
+    }
+    __syncthreads();
+    if (c0 + kPC < n) load_chunk(c0 + kPC);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = w * 4 + q;
+      const C2<float> bv = Xs[((lane >> 4) * kPK + kk) * kXP + (lane & 15)];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        const C2<float> av = Zs[((lane >> 4) * kPK + kk) * kZP + t * 16 + (lane & 15)];
+        are[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.re, are[q][t], 0, 0, 0);
+        are[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.im, bv.im, are[q][t], 0, 0, 0);
+        aim[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.im, aim[q][t], 0, 0, 0);
+        aim[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.im, bv.re, aim[q][t], 0, 0, 0);
+      }
+    }
+  }
+  C2<float>* Ys = Zs;  // [b 16][m 16][k kYP]
+#pragma unroll
+  for (int t = 0; t < 5; ++t) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = 4 * (lane >> 4) + r, b = lane & 15;
+        Ys[(b * 16 + m) * kYP + w * 4 + q] = {are[q][t][r], aim[q][t][r]};
+      }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int e = tid + 256 * i, k = e & 15, m = (e >> 4) & 15, b = e >> 8;
+      const int row = m0 + t * 16 + m;
+      if (b0 + b < B && row < n && k0 + k < K) Yh[((int64_t)(b0 + b) * n + row) * K + k0 + k] = Ys[(b * 16 + m) * kYP + k];
+    }
+  }
+}
+
 template <typename T, int MT, int BC>
 void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, hipStream_t s,
                     const int* live) {
@@ -411,7 +514,12 @@ void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2
 // right-hand sides otherwise (arithmetic per load)
 template <typename T>
 void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, hipStream_t s, const int* live) {
-  if (B == 1)
+  if (sizeof(T) == 4 && B >= 12) {  // matrix cores once a 16-wide RHS tile is mostly full
+    const int n_mg = (n + kPM - 1) / kPM, n_bt = (B + kPB - 1) / kPB;
+    const int64_t nwg = (G2 + kPK - 1) / kPK * n_mg * n_bt;
+    hipLaunchKernelGGL(spec_product_mfma_kernel, dim3((unsigned)nwg), dim3(256), 0, s, (const C2<float>*)Zh,
+                       (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg, n_bt, live);
+  } else if (B == 1)
     launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, s, live);
   else if (B == 2)
     launch_product<T, 2, 2>(Zh, X, Y, n, G2, B, s, live);

@@ -86,8 +86,12 @@ def oracle_rect(blocks, Dx, Dy, n_a, state_off, book, lx, ly, x):
     return yf.reshape(-1, n_a)[mask].reshape(-1)
 
 
-@pytest.mark.parametrize("dtype,vec,tol", [("c128", "c128", 1e-12), ("c64", "c128", 2e-6), ("c64", "c64", 2e-6)])
-def test_spectral_oracle_blocks(lib, dtype, vec, tol):
+@pytest.mark.parametrize("dtype,vec,tol,rep", [("c128", "c128", 1e-12, 1), ("c64", "c128", 2e-6, 1),
+                                               ("c64", "c64", 2e-6, 1), ("c64", "c64", 2e-6, 3),
+                                               ("c128", "c128", 1e-12, 3)])
+def test_spectral_oracle_blocks(lib, dtype, vec, tol, rep):
+    """rep = 3: every array three times (15 right-hand sides, the matrix-core
+    product for complex64 spectra, with a partial 16-wide tile)."""
     r3m, _, ctx = lib
     Dx, Dy = 3, 2
     blocks = efie.displacement_blocks(unit(1), Dx, Dy, K, extract=1)
@@ -97,14 +101,18 @@ def test_spectral_oracle_blocks(lib, dtype, vec, tol):
     self_blk = to_dev(blocks[retrieval.slot(0, 0, Dx, Dy)][None], torch.complex128 if st == r3m.C128 else
                       torch.complex64)
     store = r3m.Store(80, 2, Dx, Dy, 0, st, self_blk, sd, spec)
-    L = np.array([[4, 3], [1, 1], [3, 2], [2, 3], [4, 1]], np.int32)
-    books, uo = [], []
-    u = 0
-    for b, (lx, ly) in enumerate(L):
+    L1 = np.array([[4, 3], [1, 1], [3, 2], [2, 3], [4, 1]], np.int32)
+    books, so = [], []
+    s_at = 0
+    for b, (lx, ly) in enumerate(L1):
         books.append(cb.bernoulli(4, 70 + b)[: lx * ly])
-        uo.append(u)
-        u += lx * ly
-    batch = r3m.Batch(L, uo, uo, torch.from_numpy(np.concatenate(books)).to(DEV))
+        so.append(s_at)
+        s_at += lx * ly
+    L = np.concatenate([L1] * rep)
+    book_of = list(range(len(L1))) * rep
+    uo = np.concatenate([[0], np.cumsum(L[:, 0] * L[:, 1])[:-1]])
+    u = int((L[:, 0] * L[:, 1]).sum())
+    batch = r3m.Batch(L, uo, [so[i] for i in book_of], torch.from_numpy(np.concatenate(books)).to(DEV))
     x = cb.random_complex(u * 40, 31)
     y = matvec(r3m, ctx, store, batch, to_dev(x, torch.complex128 if vt == r3m.C128 else torch.complex64), vt)
     if vt == r3m.C64:
@@ -112,9 +120,9 @@ def test_spectral_oracle_blocks(lib, dtype, vec, tol):
     worst = 0.0
     for b, (lx, ly) in enumerate(L):
         sl = slice(uo[b] * 40, (uo[b] + lx * ly) * 40)
-        ref = oracle_rect(blocks, Dx, Dy, 40, unit(1).state_off, books[b], lx, ly, x[sl])
+        ref = oracle_rect(blocks, Dx, Dy, 40, unit(1).state_off, books[book_of[b]], lx, ly, x[sl])
         worst = max(worst, rel_max(y[sl], ref))
-    print(f"spectral {dtype} spectra, {vec} vectors: worst element error {worst:.2e}")
+    print(f"spectral {dtype} spectra, {vec} vectors, {len(L)} RHS: worst element error {worst:.2e}")
     assert worst <= tol
 
 
@@ -183,24 +191,73 @@ def test_spectral_solves(lib, fullsize):
     assert rep2[0][3] and rep2[0][2] <= 1e-9 and e_ref <= 1e-7
 
 
-def test_spectral_large(lib):
+@pytest.fixture(scope="module")
+def large(lib):
     from workloads.configs import large_128x128
     r3m, pipeline, ctx = lib
     geom = r3m.UnitGeom.from_macro(unit(1), FREQ, 1)
     w = large_128x128(16)
     batch = r3m.Batch.from_codebooks(w.codebooks, w.sizes, DEV)
     dense = pipeline.fill_blocks(ctx, geom, 127, r3m.C128, DEV)
-    store = pipeline.spectral_store(ctx, geom, 128, 2, r3m.C64, DEV, dense_c128=dense)
+    s64 = pipeline.spectral_store(ctx, geom, 128, 2, r3m.C64, DEV, dense_c128=dense)
+    s128 = pipeline.spectral_store(ctx, geom, 128, 2, r3m.C128, DEV, dense_c128=dense)
     plain = r3m.Store(80, 2, 127, 127, 127, r3m.C128, dense)
+    yield w, geom, batch, s64, s128, plain
+
+
+def test_spectral_large(lib, large):
+    """16 RHS of 128 x 128 units (the matrix-core product for complex64
+    spectra); two RHS against the plain complex128 path."""
+    r3m, _, ctx = lib
+    w, _, batch, s64, s128, plain = large
     N = batch.total_units * 40
     g = torch.Generator(device=DEV).manual_seed(8)
     x = torch.complex(torch.randn(N, generator=g, device=DEV), torch.randn(N, generator=g, device=DEV))
-    y = torch.from_numpy(matvec(r3m, ctx, store, batch, x, r3m.C64))
+    y64 = matvec(r3m, ctx, s64, batch, x, r3m.C64)
+    y128 = matvec(r3m, ctx, s128, batch, x.to(torch.complex128), r3m.C128)
     n1 = 128 * 128 * 40
-    errs = []
+    e64, e128 = [], []
     for r in (0, 15):
         sub = r3m.Batch.from_codebooks([w.codebooks[r]], [128], DEV)
         ys = matvec(r3m, ctx, plain, sub, x[r * n1:(r + 1) * n1].to(torch.complex128), r3m.C128)
-        errs.append(rel_l2(y[r * n1:(r + 1) * n1].numpy(), ys))
-    print(f"large 128x128 x16 spectral c64: errors vs plain {['%.2e' % e for e in errs]}")
-    assert max(errs) <= 1e-6
+        e64.append(rel_l2(y64[r * n1:(r + 1) * n1], ys))
+        e128.append(rel_max(y128[r * n1:(r + 1) * n1], ys))
+    print(f"large 128x128 x16 spectral: c64 errors vs plain {['%.2e' % e for e in e64]}, c128 "
+          f"{['%.2e' % e for e in e128]}")
+    assert max(e64) <= 1e-6 and max(e128) <= 1e-12
+
+
+def test_spectral_large_refined_solve(lib, large):
+    """The large workload solved: inner GMRES on complex64 spectra,
+    refinement residual on complex128 spectra (the dense operator in FP64),
+    every RHS to 1e-5; one RHS re-solved on its own in FP64 to 1e-9 as the
+    reference for its RCS."""
+    r3m, _, ctx = lib
+    w, geom, batch, s64, s128, _ = large
+    N = batch.total_units * 40
+    b = torch.zeros(N, dtype=torch.complex128, device=DEV)
+    r3m.r3m_plane_wave_rhs(ctx, geom, batch, [[0.0, 0.0, 1.0]] * batch.B, b)
+    x = torch.zeros_like(b)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, s64, batch, 30, s128), dtype=torch.uint8, device=DEV)
+    _, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, 1e-3, 30, 3000, work, refine_tol=w.refine_tol,
+                                 max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI)
+    del work
+    assert all(r[3] and r[2] <= w.refine_tol for r in rep)
+    dirs = cb.phi0_cut(5.0)
+    sig = torch.zeros(batch.B * len(dirs), dtype=torch.float64, device=DEV)
+    r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
+    sub = r3m.Batch.from_codebooks([w.codebooks[3]], [128], DEV)
+    n1 = 128 * 128 * 40
+    b1 = b[3 * n1:4 * n1].clone()
+    x1 = torch.zeros_like(b1)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, s128, sub, 30), dtype=torch.uint8, device=DEV)
+    _, rep1 = r3m.r3m_gmres_solve(ctx, s128, None, sub, b1, x1, 1e-9, 30, 6000, work,
+                                  precond=r3m.PRECOND_BLOCK_JACOBI)
+    sig1 = torch.zeros(len(dirs), dtype=torch.float64, device=DEV)
+    r3m.r3m_rcs(ctx, geom, sub, x1, dirs, 1.0, sig1)
+    torch.cuda.synchronize()
+    err = rel_l2(sig.cpu().numpy().reshape(batch.B, -1)[3], sig1.cpu().numpy())
+    print(f"large refined solve: inner iters max {max(r[0] for r in rep)}, refine steps "
+          f"{sorted(set(r[1] for r in rep))}, max residual {max(r[2] for r in rep):.2e}; FP64 reference "
+          f"{rep1[0][0]} iters, RCS error {err:.2e}")
+    assert rep1[0][3] and err <= 1e-4
