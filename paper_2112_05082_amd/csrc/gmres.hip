@@ -97,37 +97,6 @@ __global__ void dots_finish_kernel(const double2* __restrict__ partial, const Rh
   hbuf[(size_t)b * nvec + i] = s;
 }
 
-// w -= sum_{i<=j} h[i] V_i ; H[i][j] (+)= h[i]
-__global__ void gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w,
-                                 const RhsVec* __restrict__ rv, const RhsState* __restrict__ st,
-                                 const double2* __restrict__ hbuf, int nvec, int64_t ut) {
-  const int b = blockIdx.y;
-  const RhsVec r = rv[b];
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= r.N || !st[b].active) return;
-  double2 acc = w[r.off + k];
-  for (int i = 0; i < nvec; ++i) {
-    double2 t = cmul(hbuf[(size_t)b * nvec + i], V[(int64_t)i * ut + r.off + k]);
-    acc.x -= t.x;
-    acc.y -= t.y;
-  }
-  w[r.off + k] = acc;
-}
-
-__global__ void accumulate_h_kernel(double2* __restrict__ H, const double2* __restrict__ hbuf, int nvec,
-                                    int m, int j, int first) {
-  const int b = blockIdx.x, i = threadIdx.x;
-  if (i >= nvec) return;
-  double2* h = H + (size_t)b * (m + 1) * m;
-  double2 v = hbuf[(size_t)b * nvec + i];
-  if (first) {
-    h[i * m + j] = v;
-  } else {
-    h[i * m + j].x += v.x;
-    h[i * m + j].y += v.y;
-  }
-}
-
 // Givens step on column j of H for RHS b, run by one whole block: the column
 // (with H[j+1][j] = hn) and the previous rotations are staged in LDS by all
 // threads, thread 0 applies the rotations in order, forms the new one, updates
@@ -310,18 +279,52 @@ dots_partials_kernel(const double2* __restrict__ A, int64_t a_stride, const doub
   }
 }
 
+// Long vectors: the chunk partials of dots_partials_kernel summed once, in a
+// fixed order, into out[b][i] (grid (nvec, B)), so that the update kernel's
+// blocks read one value per vector instead of every partial.
+__global__ void __launch_bounds__(256)
+finish_partials_kernel(const double2* __restrict__ partial, int maxP, int nvec, const RhsVec* __restrict__ rv,
+                       double2* __restrict__ out, const int* __restrict__ run_prev) {
+  if (run_prev && *run_prev == 0) return;
+  __shared__ double2 sh[4];
+  const int i = blockIdx.x, b = blockIdx.y;
+  const int64_t P = (rv[b].N + kDotChunk - 1) / kDotChunk;
+  const double2* pp = partial + ((size_t)b * nvec + i) * maxP;
+  double2 t = make_double2(0.0, 0.0);
+  for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
+    t.x += pp[p].x;
+    t.y += pp[p].y;
+  }
+  t = block_sum2(t, sh);
+  if (threadIdx.x == 0) out[(size_t)b * nvec + i] = t;
+}
+
+// the per-block parts of ||w||^2 summed once into out[b] (grid B)
+__global__ void __launch_bounds__(256)
+finish_norm_kernel(const double* __restrict__ npart, int maxB, const RhsVec* __restrict__ rv,
+                   double* __restrict__ out, const int* __restrict__ run_prev) {
+  if (run_prev && *run_prev == 0) return;
+  __shared__ double2 sh[4];
+  const int b = blockIdx.x;
+  const int64_t nb = (rv[b].N + 63) / 64;
+  double t = 0.0;
+  for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) t += npart[(size_t)b * maxB + q];
+  const double2 s2 = block_sum2(make_double2(t, 0.0), sh);
+  if (threadIdx.x == 0) out[b] = s2.x;
+}
+
 // w -= sum_{i<nvec} h_i V_i with h_i the sum of the chunk partials of the
-// preceding dots_partials_kernel launch, taken by every block in the same
-// fixed order (block 0 also records them in H: mode 0 H[i][j] = h_i, mode 1
+// preceding dots_partials_kernel launch (n_part of them per vector; 0: one
+// per 1024 elements), taken by every block in the same fixed order (block 0 also records them in H: mode 0 H[i][j] = h_i, mode 1
 // H[i][j] += h_i).  A block takes 64 elements; its four waves take the vectors
 // i = q mod 4 (q = wave) and their sums are added in wave order.  With
 // do_norm, each block also writes its part of ||w||^2 to npart[b][block].
 // Dynamic LDS: nvec double2.
 __global__ void __launch_bounds__(256)
 gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
-                 const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int nvec,
-                 int64_t ut, int do_norm, double* __restrict__ npart, int maxB, double2* __restrict__ H, int m,
-                 int j, int mode, const int* __restrict__ run_prev) {
+                 const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int n_part,
+                 int nvec, int64_t ut, int do_norm, double* __restrict__ npart, int maxB, double2* __restrict__ H,
+                 int m, int j, int mode, const int* __restrict__ run_prev) {
   if (run_prev && *run_prev == 0) return;
   extern __shared__ double2 hb[];
   __shared__ double2 sh[4];
@@ -330,7 +333,7 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
   const RhsVec r = rv[b];
   const int64_t nb = (r.N + 63) / 64;
   if ((int64_t)blockIdx.x >= nb) return;
-  const int P = (int)((r.N + kDotChunk - 1) / kDotChunk);
+  const int P = n_part > 0 ? n_part : (int)((r.N + kDotChunk - 1) / kDotChunk);
   for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
     const double2* pp = partial + ((size_t)b * nvec + i) * maxP;
     double2 t = make_double2(0.0, 0.0);
@@ -398,8 +401,9 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
   if (threadIdx.x == 0) npart[(size_t)b * maxB + blockIdx.x] = t.x;
 }
 
-// ||w|| from the per-block parts of the preceding gs_update_kernel (summed by
-// every block in the same fixed order); block 0 sets H[j+1][j] = ||w|| and
+// ||w|| from the per-block parts of the preceding gs_update_kernel (n_npart
+// of them; 0: one per 64 elements), summed by every block in the same fixed
+// order; block 0 sets H[j+1][j] = ||w|| and
 // applies the Givens step; every block writes V_{j+1} = w / ||w|| (zeros for
 // a finished RHS or a breakdown) and, for the next step's matvec, its input
 // in the store precision OT: V_{j+1} itself (MODE 1) or M^{-1} V_{j+1}
@@ -407,7 +411,7 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
 template <typename OT, int MODE>
 __global__ void __launch_bounds__(256)
 normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, const RhsVec* __restrict__ rv,
-                      RhsState* __restrict__ st, const double* __restrict__ npart, int maxB,
+                      RhsState* __restrict__ st, const double* __restrict__ npart, int maxB, int n_npart,
                       double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
                       double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
                       double* __restrict__ wn, int64_t ut, const int* __restrict__ live,
@@ -421,7 +425,7 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
   const int64_t nb = (r.N + 63) / 64;
   if ((int64_t)blockIdx.x * blockDim.x >= r.N) return;  // uniform over the block
   if (threadIdx.x < 64) {
-    const double sum = wave_sum_partials(npart + (size_t)b * maxB, (int)nb);
+    const double sum = wave_sum_partials(npart + (size_t)b * maxB, n_npart > 0 ? n_npart : (int)nb);
     if (threadIdx.x == 0) nv_s = sqrt(fmax(sum, 0.0));
   }
   __syncthreads();
@@ -743,6 +747,8 @@ struct Work {
   double2* sn;
   double2* dpart;
   double2* hbuf;
+  double2* hsum;  // Gram-Schmidt coefficients summed from dpart (long vectors)
+  double* nsum;   // ||w||^2 summed from npart (long vectors)
   double2* nrm;
   RhsState* st;
   RhsVec* rv;
@@ -787,6 +793,8 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, 
   w.sn = (double2*)take((size_t)B * m * 16);
   w.dpart = (double2*)take((size_t)B * (m + 1) * std::max(maxP, 1) * 16);
   w.hbuf = (double2*)take((size_t)B * (m + 1) * 16);
+  w.hsum = (double2*)take((size_t)B * (m + 1) * 16);
+  w.nsum = (double*)take((size_t)B * 8);
   w.nrm = (double2*)take((size_t)B * 16);
   w.st = (RhsState*)take((size_t)B * sizeof(RhsState));
   w.rv = (RhsVec*)take((size_t)B * sizeof(RhsVec));
@@ -890,33 +898,45 @@ struct GmresRun {
                       W.mv_partial, lists_for(Z), G, s, live);
     const dim3 dgrid(maxP, (j + 1 + kDotVec - 1) / kDotVec, B);
     const int maxB = (int)((maxN + 63) / 64 + 1);
+    // long vectors (more than 64 chunk partials per coefficient): sum the
+    // partials once in their own launch rather than in every update block
+    const bool long_vec = maxP > 64;
     for (int pass = 0; pass < 2; ++pass) {
       hipLaunchKernelGGL(dots_partials_kernel, dgrid, dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, j + 1, maxP,
                          W.dpart, pass == 0 ? run_slot(j) : (int*)nullptr, live);
+      if (long_vec)
+        hipLaunchKernelGGL(finish_partials_kernel, dim3(j + 1, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
+                           j + 1, W.rv, W.hsum, live);
       hipLaunchKernelGGL(gs_update_kernel, dim3(ceil_div((size_t)maxN, 64), B), dim3(256),
-                         (size_t)(j + 1) * sizeof(double2), s, W.V, W.w, W.rv, W.st, W.dpart, maxP, j + 1, ut, pass,
-                         W.npart, maxB, W.H, m, j, pass, live);
+                         (size_t)(j + 1) * sizeof(double2), s, W.V, W.w, W.rv, W.st,
+                         long_vec ? (const double2*)W.hsum : (const double2*)W.dpart, long_vec ? 1 : maxP,
+                         long_vec ? 1 : 0, j + 1, ut, pass, W.npart, maxB, W.H, m, j, pass, live);
     }
+    if (long_vec)
+      hipLaunchKernelGGL(finish_norm_kernel, dim3(B), dim3(256), 0, s, (const double*)W.npart, maxB, W.rv, W.nsum,
+                         live);
+    const double* np = long_vec ? W.nsum : W.npart;
+    const int npB = long_vec ? 1 : maxB, npN = long_vec ? 1 : 0;
     // blocks of whole units (the preconditioner multiplies per unit)
     const int nthr = (256 / n_a) * n_a;
     const dim3 ngrid(ceil_div((size_t)maxN, nthr), B);
     const size_t glds = (size_t)(2 * m + 2) * 16 + (size_t)m * 8;
     const bool c64 = Z->near_dtype == R3M_C64;
     if (pre && c64)
-      hipLaunchKernelGGL((normalize_step_kernel<float, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, W.npart,
-                         maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
+      hipLaunchKernelGGL((normalize_step_kernel<float, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
+                         npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
                          W.soff, n_a, n_states, (float*)W.xs);
     else if (pre)
       hipLaunchKernelGGL((normalize_step_kernel<double, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
-                         W.npart, maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
+                         np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
                          batch->states, W.soff, n_a, n_states, (double*)W.xs);
     else if (c64)
-      hipLaunchKernelGGL((normalize_step_kernel<float, 1>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, W.npart,
-                         maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
+      hipLaunchKernelGGL((normalize_step_kernel<float, 1>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
+                         npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
                          W.soff, n_a, n_states, (float*)W.xs);
     else
       hipLaunchKernelGGL((normalize_step_kernel<double, 0>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
-                         W.npart, maxB, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
+                         np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
                          batch->states, W.soff, n_a, n_states, (double*)nullptr);
     R3M_CHECK_HIP(hipGetLastError());
   }
