@@ -197,32 +197,55 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
   if (A.live && *A.live == 0) return;
   constexpr bool rows = MODE == kPlainRows || MODE == kFwdRows || MODE == kInvRows;
   constexpr bool masked = MODE >= kFwdRows;
+  // the compacting row passes take one row of lpw consecutive channels (grids)
+  // of one right-hand side, so that the compact vector is read (kFwdRows) or
+  // written (kInvRows) in runs of adjacent rows A(s) of a unit; the other
+  // passes take lpw adjacent lines of one grid
+  constexpr bool chan = MODE == kFwdRows || MODE == kInvRows;
+  // thread -> (line, element) maps: line-fastest for columns and for the
+  // compact side of the compacting passes, element-fastest otherwise
+  constexpr bool load_lf = !rows || MODE == kFwdRows;
+  constexpr bool store_lf = !rows || MODE == kInvRows;
   constexpr int SGN = MODE == kInvCols || MODE == kInvRows ? 1 : -1;
   constexpr int KE = fft_ke<T>();
   extern __shared__ unsigned char smem_raw[];
   const int lgG = A.lgG, G = 1 << lgG;
   const int S = G + (G >> 4) + 1;
   const int lpw = 1 << A.lg_lpw;
-  const int64_t l0 = (int64_t)blockIdx.x << A.lg_lpw;
-  const int64_t g = l0 >> A.lg_lpg;
-  const int lig0 = (int)(l0 & ((1 << A.lg_lpg) - 1));
+  const int lgG2 = lgG + A.lg_lpg;
   const int lgGx = rows ? lgG : A.lg_lpg;
-  C2<T>* grid = A.data + (g << (lgG + A.lg_lpg));
-  int Lx = 0, Ly = 0, c = 0;
+  int64_t g0;  // grid of line 0; line li lies in grid g0 + li (chan) or g0
+  int lig0;    // its line within the grid; line li is lig0 (chan) or lig0 + li
+  if (chan) {
+    const int ncg = A.n >> A.lg_lpw;
+    const int64_t id = blockIdx.x;
+    const int cg = (int)(id % ncg);
+    const int64_t rest = id / ncg;
+    lig0 = (int)(rest & ((1 << A.lg_lpg) - 1));
+    g0 = (rest >> A.lg_lpg) * A.n + ((int64_t)cg << A.lg_lpw);
+  } else {
+    const int64_t l0 = (int64_t)blockIdx.x << A.lg_lpw;
+    g0 = l0 >> A.lg_lpg;
+    lig0 = (int)(l0 & ((1 << A.lg_lpg) - 1));
+  }
+  int Lx = 0, Ly = 0, c0 = 0;
   RhsDev R{};
   if (masked) {
-    const int b = (int)(g / A.n);
-    c = (int)(g - (int64_t)b * A.n);
+    const int b = (int)(g0 / A.n);
+    c0 = (int)(g0 - (int64_t)b * A.n);
     R = A.rhs[b];
     Lx = R.Lx;
     Ly = R.Ly;
-    if ((MODE == kFwdRows || MODE == kInvRows) && lig0 >= Ly) return;  // rows past the array
+    if (chan && lig0 >= Ly) return;  // a row past the array
   }
   // the active macro row of unit u in channel c, or -1
-  auto active = [&](int64_t u) -> int {
+  auto active = [&](int64_t u, int c) -> int {
     const int s = min((int)A.states[R.state_off + u], A.n_states - 1);
     const int r = c - s * A.n_a;
     return r >= 0 && r < A.n_a ? r : -1;
+  };
+  auto grid_at = [&](int li, int gx, int gy) -> C2<T>* {
+    return A.data + ((g0 + (chan ? li : 0)) << lgG2) + ((int64_t)gy << lgGx) + gx;
   };
   C2<T>* buf = reinterpret_cast<C2<T>*>(smem_raw);
   C2<T>* tw = buf + (size_t)lpw * S;
@@ -233,24 +256,24 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
   }
   const int tot = lpw << lgG;
   for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int li = rows ? t >> lgG : t & (lpw - 1);
-    const int e = rows ? t & (G - 1) : t >> A.lg_lpw;
-    const int line = lig0 + li;
+    const int li = load_lf ? t & (lpw - 1) : t >> lgG;
+    const int e = load_lf ? t >> A.lg_lpw : t & (G - 1);
+    const int line = chan ? lig0 : lig0 + li;
     const int gx = rows ? e : line, gy = rows ? line : e;
     C2<T> v = {0, 0};
     if (MODE == kFwdRows) {
-      if (gx < Lx && gy < Ly) {
+      if (gx < Lx) {
         const int64_t u = (int64_t)gy * Lx + gx;
-        const int r = active(u);
+        const int r = active(u, c0 + li);
         if (r >= 0) {
           const VT* xv = (const VT*)A.x + ((R.unit_off + u) * A.n_a + r) * 2;
           v = {(T)xv[0], (T)xv[1]};
         }
       }
-    } else if (MODE == kFwdCols || MODE == kInvRows) {
-      if (gy < Ly) v = grid[((int64_t)gy << lgGx) + gx];
+    } else if (MODE == kFwdCols) {
+      if (gy < Ly) v = *grid_at(li, gx, gy);
     } else {
-      v = grid[((int64_t)gy << lgGx) + gx];
+      v = *grid_at(li, gx, gy);
     }
     buf[lds_at(li, e, S)] = v;
   }
@@ -264,27 +287,27 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
     case 3: stockham_stage<T, 8, KE, SGN>(buf, tw, lgG, lgNs, tot >> 3, S); break;
     default: break;
   }
-  const T scale = T(1) / (T)((int64_t)1 << (lgG + A.lg_lpg));
+  const T scale = T(1) / (T)((int64_t)1 << lgG2);
   for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-    const int li = rows ? t >> lgG : t & (lpw - 1);
-    const int e = rows ? t & (G - 1) : t >> A.lg_lpw;
-    const int line = lig0 + li;
+    const int li = store_lf ? t & (lpw - 1) : t >> lgG;
+    const int e = store_lf ? t >> A.lg_lpw : t & (G - 1);
+    const int line = chan ? lig0 : lig0 + li;
     const int gx = rows ? e : line, gy = rows ? line : e;
     const C2<T> v = buf[lds_at(li, e, S)];
     if (MODE == kInvRows) {
-      if (gx < Lx && gy < Ly) {
+      if (gx < Lx) {
         const int64_t u = (int64_t)gy * Lx + gx;
-        const int r = active(u);
+        const int r = active(u, c0 + li);
         if (r >= 0) {
           VT* yv = (VT*)A.y + ((R.unit_off + u) * A.n_a + r) * 2;
           yv[0] = (VT)(v.re * scale);
           yv[1] = (VT)(v.im * scale);
         }
       }
-    } else if (MODE == kFwdRows || MODE == kInvCols) {
-      if (gy < Ly) grid[((int64_t)gy << lgGx) + gx] = v;
+    } else if (MODE == kInvCols) {
+      if (gy < Ly) *grid_at(li, gx, gy) = v;
     } else {
-      grid[((int64_t)gy << lgGx) + gx] = v;
+      *grid_at(li, gx, gy) = v;
     }
   }
 }
@@ -303,15 +326,27 @@ int fft_lpw_log(int lgG, int lg_lpg) {
   return std::max(0, std::min(8 + LKE - lgG, lg_lpg));
 }
 
-// one pass over every row or column (by MODE) of n_grids Gy x Gx grids
+// one pass over every row or column (by MODE) of n_grids Gy x Gx grids; the
+// compacting row passes group lpw channels of one RHS instead (lpw the
+// largest power of two dividing n that fits)
 template <typename T, int MODE, typename VT>
 void fft_pass(FftArgs<T> A, int lgGx, int lgGy, int64_t n_grids, hipStream_t s) {
   constexpr bool rows = MODE == kPlainRows || MODE == kFwdRows || MODE == kInvRows;
+  constexpr bool chan = MODE == kFwdRows || MODE == kInvRows;
   A.lgG = rows ? lgGx : lgGy;
   A.lg_lpg = rows ? lgGy : lgGx;
-  A.lg_lpw = fft_lpw_log<T>(A.lgG, A.lg_lpg);
+  int64_t n_wg;
+  if (chan) {
+    constexpr int LKE = fft_ke<T>() == 16 ? 4 : 3;
+    int lg = 0;
+    while (lg < 8 + LKE - A.lgG && (A.n & ((2 << lg) - 1)) == 0) ++lg;
+    A.lg_lpw = std::max(0, lg);
+    n_wg = (n_grids >> A.lg_lpw) << A.lg_lpg;
+  } else {
+    A.lg_lpw = fft_lpw_log<T>(A.lgG, A.lg_lpg);
+    n_wg = (n_grids << A.lg_lpg) >> A.lg_lpw;
+  }
   const int G = 1 << A.lgG;
-  const int64_t n_wg = (n_grids << A.lg_lpg) >> A.lg_lpw;
   const size_t lds = ((size_t)((size_t)1 << A.lg_lpw) * (G + (G >> 4) + 1) + G) * sizeof(C2<T>);
   hipLaunchKernelGGL((fft_kernel<T, MODE, VT>), dim3((unsigned)n_wg), dim3(256), lds, s, A);
   R3M_CHECK_HIP(hipGetLastError());
