@@ -439,101 +439,140 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
 // GEMM, taken as four real GEMMs (Re Y = Re Z Re X - Im Z Im X, Im Y = Re Z
 // Im X + Im Z Re X) on 16x16x4 FP32 MFMA tiles (lane l holds A[l % 16][l / 16]
 // and B[l / 16][l % 16]; result rows 4 (l / 16) + r, column l % 16).  A
-// workgroup owns 16 frequencies x 80 rows x 16 right-hand sides; wave w takes
-// frequencies 4w .. 4w + 3 for all five row tiles.  Columns are consumed in
-// chunks of 4: the chunk is staged in LDS as [c][k][m] and [c][k][b] (rows
+// workgroup owns 4 KPW frequencies x 80 rows x 16 right-hand sides; wave w
+// takes KPW adjacent frequencies for all five row tiles.  Columns are consumed
+// in chunks of PC: the chunk is staged in LDS as [c][k][m] and [c][k][b] (rows
 // contiguous per frequency, padded strides) while the next chunk is already
-// in flight from global memory (128-byte runs of 16 frequencies).  Results
+// in flight from global memory (runs of 4 KPW frequencies).  Results
 // leave through LDS one row tile at a time, again as 16-frequency runs.
-// Workgroup ids run over RHS tiles first, so the tiles that share a slice of
-// the spectra are in flight together.
-constexpr int kPK = 16, kPM = 80, kPB = 16, kPC = 4;
-constexpr int kZP = kPM + 1, kXP = kPB + 1, kYP = kPK + 1;
+// Tile order.  The two frequency tiles that share the 128-byte lines of their
+// 64-byte runs must meet in one L2 (workgroup i runs on XCD i mod 8):
+//  - with fewer than 8 RHS tiles each XCD takes a contiguous range of
+//    (frequency-tile pair, RHS tile, row group, tile of the pair), so a pair's
+//    lines of the spectra and of X stay in its L2;
+//  - with 8 or more, workgroup ids run over RHS tiles first and wrap around
+//    the XCDs, so each XCD keeps the same RHS tiles for every frequency tile
+//    and meets both halves of their X lines (the larger stream there).
+constexpr int kPM = 80, kPB = 16;
+constexpr int kZP = kPM + 1, kXP = kPB + 1;
 
+// KPW frequencies per wave, 4 KPW per workgroup; PC columns per staged chunk
+template <int KPW, int PC>
 __global__ void __launch_bounds__(256)
 spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __restrict__ Xh, C2<float>* __restrict__ Yh,
-                         int n, int64_t K, int B, int n_mg, int n_bt, const int* __restrict__ live) {
+                         int n, int64_t K, int B, int n_mg, int n_bt, int64_t n_tiles,
+                         const int* __restrict__ live) {
   if (live && *live == 0) return;
   typedef float v4 __attribute__((ext_vector_type(4)));
-  __shared__ C2<float> Zs[kPC * kPK * kZP];  // [c][k][m]; reused as the output tile [b][m][k]
-  __shared__ C2<float> Xs[kPC * kPK * kXP];  // [c][k][b]
-  const int64_t id = blockIdx.x;
-  const int bt = (int)(id % n_bt);
-  const int64_t r1 = id / n_bt;
-  const int mg = (int)(r1 % n_mg);
-  const int64_t k0 = (r1 / n_mg) * kPK;
+  constexpr int PK = 4 * KPW;                   // frequencies per workgroup
+  constexpr int LPK = PK == 8 ? 3 : PK == 16 ? 4 : 2;
+  constexpr int YP = PK + 1;
+  constexpr int LPC = PC == 8 ? 3 : 2;
+  __shared__ C2<float> Zs[PC * PK * kZP];  // [c][k][m]; reused as the output tile [b][m][k]
+  __shared__ C2<float> Xs[PC * PK * kXP];  // [c][k][b]
+  static_assert(16 * 16 * YP <= PC * PK * kZP, "output tile fits the staging buffer");
+  int bt, mg;
+  int64_t kt;
+  if (n_bt < 8) {
+    const int64_t id = (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);  // grid: a multiple of 8
+    const int kh = (int)(id & 1);
+    const int64_t r0 = id >> 1;
+    bt = (int)(r0 % n_bt);
+    const int64_t r1 = r0 / n_bt;
+    mg = (int)(r1 % n_mg);
+    kt = (r1 / n_mg) * 2 + kh;
+  } else {
+    const int64_t id = blockIdx.x;
+    bt = (int)(id % n_bt);
+    const int64_t r1 = id / n_bt;
+    mg = (int)(r1 % n_mg);
+    kt = r1 / n_mg;
+  }
+  if (kt >= n_tiles) return;  // n_tiles: frequency tiles
+  const int64_t k0 = kt * PK;
   const int m0 = mg * kPM, b0 = bt * kPB;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  v4 are[4][5], aim[4][5];
+  v4 are[KPW][5], aim[KPW][5];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < KPW; ++q)
 #pragma unroll
     for (int t = 0; t < 5; ++t) are[q][t] = aim[q][t] = v4{0, 0, 0, 0};
-  constexpr int NZ = kPC * kPK * kPM / 256, NX = kPC * kPK * kPB / 256;  // 20, 4 entries per thread
+  constexpr int NZ = PC * PK * kPM / 256, NX = PC * PK * kPB / 256;
   C2<float> zp[NZ], xp[NX];
   auto load_chunk = [&](int c0) {
 #pragma unroll
     for (int i = 0; i < NZ; ++i) {
-      const int e = tid + 256 * i, k = e & 15, c = (e >> 4) & 3, m = e >> 6;
+      const int e = tid + 256 * i, k = e & (PK - 1), c = (e >> LPK) & (PC - 1), m = e >> (LPK + LPC);
       const bool ok = m0 + m < n && c0 + c < n && k0 + k < K;
       zp[i] = ok ? Zh[((int64_t)(m0 + m) * n + c0 + c) * K + k0 + k] : C2<float>{0, 0};
     }
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
-      const int e = tid + 256 * i, k = e & 15, c = (e >> 4) & 3, b = e >> 6;
+      const int e = tid + 256 * i, k = e & (PK - 1), c = (e >> LPK) & (PC - 1), b = e >> (LPK + LPC);
       const bool ok = b0 + b < B && c0 + c < n && k0 + k < K;
       xp[i] = ok ? Xh[((int64_t)(b0 + b) * n + c0 + c) * K + k0 + k] : C2<float>{0, 0};
     }
   };
   load_chunk(0);
-  for (int c0 = 0; c0 < n; c0 += kPC) {
+  for (int c0 = 0; c0 < n; c0 += PC) {
     __syncthreads();  // the previous chunk's fragments have been read
 #pragma unroll
     for (int i = 0; i < NZ; ++i) {
-      const int e = tid + 256 * i, k = e & 15, c = (e >> 4) & 3, m = e >> 6;
-      Zs[(c * kPK + k) * kZP + m] = zp[i];
+      const int e = tid + 256 * i, k = e & (PK - 1), c = (e >> LPK) & (PC - 1), m = e >> (LPK + LPC);
+      Zs[(c * PK + k) * kZP + m] = zp[i];
     }
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
-      const int e = tid + 256 * i, k = e & 15, c = (e >> 4) & 3, b = e >> 6;
-      Xs[(c * kPK + k) * kXP + b] = xp[i];
+      const int e = tid + 256 * i, k = e & (PK - 1), c = (e >> LPK) & (PC - 1), b = e >> (LPK + LPC);
+      Xs[(c * PK + k) * kXP + b] = xp[i];
     }
     __syncthreads();
-    if (c0 + kPC < n) load_chunk(c0 + kPC);
+    if (c0 + PC < n) load_chunk(c0 + PC);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = w * 4 + q;
-      const C2<float> bv = Xs[((lane >> 4) * kPK + kk) * kXP + (lane & 15)];
+    for (int cs = 0; cs < PC / 4; ++cs) {
+      const int c = cs * 4 + (lane >> 4);  // the fragment's column of the chunk
 #pragma unroll
-      for (int t = 0; t < 5; ++t) {
-        const C2<float> av = Zs[((lane >> 4) * kPK + kk) * kZP + t * 16 + (lane & 15)];
-        are[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.re, are[q][t], 0, 0, 0);
-        are[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.im, bv.im, are[q][t], 0, 0, 0);
-        aim[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.im, aim[q][t], 0, 0, 0);
-        aim[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.im, bv.re, aim[q][t], 0, 0, 0);
+      for (int q = 0; q < KPW; ++q) {
+        const int kk = w * KPW + q;
+        const C2<float> bv = Xs[(c * PK + kk) * kXP + (lane & 15)];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) {
+          const C2<float> av = Zs[(c * PK + kk) * kZP + t * 16 + (lane & 15)];
+          are[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.re, are[q][t], 0, 0, 0);
+          are[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.im, bv.im, are[q][t], 0, 0, 0);
+          aim[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.im, aim[q][t], 0, 0, 0);
+          aim[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.im, bv.re, aim[q][t], 0, 0, 0);
+        }
       }
     }
   }
-  C2<float>* Ys = Zs;  // [b 16][m 16][k kYP]
+  C2<float>* Ys = Zs;  // [b 16][m 16][k YP]
 #pragma unroll
   for (int t = 0; t < 5; ++t) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < KPW; ++q)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = 4 * (lane >> 4) + r, b = lane & 15;
-        Ys[(b * 16 + m) * kYP + w * 4 + q] = {are[q][t][r], aim[q][t][r]};
+        Ys[(b * 16 + m) * YP + w * KPW + q] = {are[q][t][r], aim[q][t][r]};
       }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int e = tid + 256 * i, k = e & 15, m = (e >> 4) & 15, b = e >> 8;
+    for (int i = 0; i < 16 * 16 * PK / 256; ++i) {
+      const int e = tid + 256 * i, k = e & (PK - 1), m = (e >> LPK) & 15, b = e >> (LPK + 4);
       const int row = m0 + t * 16 + m;
-      if (b0 + b < B && row < n && k0 + k < K) Yh[((int64_t)(b0 + b) * n + row) * K + k0 + k] = Ys[(b * 16 + m) * kYP + k];
+      if (b0 + b < B && row < n && k0 + k < K) Yh[((int64_t)(b0 + b) * n + row) * K + k0 + k] = Ys[(b * 16 + m) * YP + k];
     }
   }
 }
+
+#ifndef R3M_SPEC_MFMA_KPW
+#define R3M_SPEC_MFMA_KPW 2
+#endif
+#ifndef R3M_SPEC_MFMA_PC
+#define R3M_SPEC_MFMA_PC 4
+#endif
 
 template <typename T, int MT, int BC>
 void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, hipStream_t s,
@@ -550,10 +589,13 @@ void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2
 template <typename T>
 void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, hipStream_t s, const int* live) {
   if (sizeof(T) == 4 && B >= 12) {  // matrix cores once a 16-wide RHS tile is mostly full
+    constexpr int PK = 4 * R3M_SPEC_MFMA_KPW;
     const int n_mg = (n + kPM - 1) / kPM, n_bt = (B + kPB - 1) / kPB;
-    const int64_t nwg = (G2 + kPK - 1) / kPK * n_mg * n_bt;
-    hipLaunchKernelGGL(spec_product_mfma_kernel, dim3((unsigned)nwg), dim3(256), 0, s, (const C2<float>*)Zh,
-                       (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg, n_bt, live);
+    const int64_t n_kt = (G2 + PK - 1) / PK;
+    const int64_t nwg = n_bt < 8 ? ((n_kt + 1) / 2 * 2 * n_mg * n_bt + 7) / 8 * 8 : n_kt * n_mg * n_bt;
+    hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC>), dim3((unsigned)nwg), dim3(256),
+                       0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg, n_bt, n_kt,
+                       live);
   } else if (B == 1)
     launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, s, live);
   else if (B == 2)
