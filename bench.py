@@ -36,7 +36,10 @@ RCS_TARGET = 1e-4
 # four launches, with the copy-kernel calibration; valid only for the launch
 # shape it was taken at (displacement groups) and the kernels as they were then.
 # Source: profiles/retrieved_matvec_2bit_32x32.md
-PROFILED_TRAFFIC = None  # the kernels changed since the last counter runs
+# HBM bytes of one matvec call (convert_flat + far_near + reduce_groups
+# launches) from FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 at 128 displacement groups
+# (profiles/retrieved_matvec_2bit_32x32.md); reported only for that launch shape
+PROFILED_TRAFFIC = {"bytes": 403.5e6, "groups": 128}
 
 
 def parse():
