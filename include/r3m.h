@@ -226,6 +226,24 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
  * r3m_status. */
 int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch);
 
+/* ------------------------------------------------------ relaxed codebook -- */
+
+/* Relaxed (blended) retrieval, the operator of codebook differentiation: unit
+ * u of RHS b carries real state weights w[unit_off[b] + u][s] (device, FP64,
+ * [total units][n_states], e.g. a softmax of logits) instead of one state.
+ * The slicing matrix P_k of eq. (3) becomes the non-square blend
+ *   P(w) = blockdiag_u [w[u][0] I; ...; w[u][S-1] I]   (n x n_a per unit),
+ * Z_k(w) = P(w)^T Z P(w), which is eq. (3) for one-hot weights.  Computes
+ * y = Z_k(w) x, or y = Z_k(w)^T x = P(w)^T Z^T P(w) x with transpose != 0
+ * (the adjoint solve's operator; Z^T is block-Toeplitz with blocks Z(-d)^T).
+ * The store must be spectral (R3M_SPEC_*; R3M_ERR_UNSUPPORTED otherwise);
+ * batch->states must be non-NULL but are not read.  Vectors C128 or C64 as in
+ * r3m_retrieved_matvec.  work: r3m_relaxed_work_bytes bytes. */
+size_t r3m_relaxed_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch);
+int r3m_relaxed_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, const double* weights_dev,
+                       int32_t transpose, r3m_dtype vec_dtype, const void* x_dev, void* y_dev, void* work_dev,
+                       size_t work_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------- GMRES -- */
 
 typedef enum {

@@ -171,6 +171,9 @@ __device__ __forceinline__ void stockham_stage(C2<T>* buf, const C2<T>* tw, int 
 //   kInvCols  columns, only rows gy < Ly written back;
 //   kInvRows  rows gy < Ly, written straight to the compact output
 //             (active rows only, times 1 / (Gx Gy)).
+// With relaxed weights w[u][s] (a blended codebook) every channel c = s n_a + r
+// is active: kFwdRows reads w[u][s] x[u][r], and kInvRows writes
+// w[u][s] y~[u][c] / (Gx Gy) to a macro buffer whose sum over s is y[u][r].
 enum FftMode { kPlainRows, kPlainCols, kFwdRows, kFwdCols, kInvCols, kInvRows };
 
 template <typename T>
@@ -184,6 +187,11 @@ struct FftArgs {
   int n_states, n, n_a;
   const void* x;  // kFwdRows
   void* y;        // kInvRows
+  // relaxed retrieval (nullable): state weights [unit][n_states] replace the
+  // one-hot state test; kInvRows then writes the weighted channels to
+  // ymacro [unit][n] (summed over states afterwards)
+  const double* wts;
+  C2<T>* ymacro;
   const int* live;
 };
 
@@ -264,10 +272,17 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
     if (MODE == kFwdRows) {
       if (gx < Lx) {
         const int64_t u = (int64_t)gy * Lx + gx;
-        const int r = active(u, c0 + li);
-        if (r >= 0) {
+        if (A.wts) {
+          const int c = c0 + li, s = c / A.n_a, r = c - s * A.n_a;
+          const double wv = A.wts[(R.unit_off + u) * A.n_states + s];
           const VT* xv = (const VT*)A.x + ((R.unit_off + u) * A.n_a + r) * 2;
-          v = {(T)xv[0], (T)xv[1]};
+          v = {(T)(wv * (double)xv[0]), (T)(wv * (double)xv[1])};
+        } else {
+          const int r = active(u, c0 + li);
+          if (r >= 0) {
+            const VT* xv = (const VT*)A.x + ((R.unit_off + u) * A.n_a + r) * 2;
+            v = {(T)xv[0], (T)xv[1]};
+          }
         }
       }
     } else if (MODE == kFwdCols) {
@@ -297,11 +312,17 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
     if (MODE == kInvRows) {
       if (gx < Lx) {
         const int64_t u = (int64_t)gy * Lx + gx;
-        const int r = active(u, c0 + li);
-        if (r >= 0) {
-          VT* yv = (VT*)A.y + ((R.unit_off + u) * A.n_a + r) * 2;
-          yv[0] = (VT)(v.re * scale);
-          yv[1] = (VT)(v.im * scale);
+        if (A.wts) {
+          const int c = c0 + li, s = c / A.n_a;
+          const T ws = (T)A.wts[(R.unit_off + u) * A.n_states + s] * scale;
+          A.ymacro[(R.unit_off + u) * A.n + c] = {v.re * ws, v.im * ws};
+        } else {
+          const int r = active(u, c0 + li);
+          if (r >= 0) {
+            VT* yv = (VT*)A.y + ((R.unit_off + u) * A.n_a + r) * 2;
+            yv[0] = (VT)(v.re * scale);
+            yv[1] = (VT)(v.im * scale);
+          }
         }
       }
     } else if (MODE == kInvCols) {
@@ -385,10 +406,19 @@ spec_embed_kernel(const double2* __restrict__ dense, int n, int Dx, int Dy, int 
 // and workgroup ids run over RHS chunks first, then row tiles, then
 // frequency blocks, so the workgroups that share a slice of X^ or Z^ are in
 // flight together.
-template <typename T, int MT, int BC>
+// Transposed operator (TR): the macro system's transpose is block-Toeplitz
+// with kernel Z(-d)^T, whose spectrum at frequency k is Z^(-k)^T, so entry
+// (m, c) is read from Z^[c][m] at the mirrored frequency (-kx mod Gx, -ky mod
+// Gy).
+__device__ __forceinline__ int64_t mirror_freq(int64_t k, int lgGx, int lgGy) {
+  const int64_t kx = k & ((1 << lgGx) - 1), ky = k >> lgGx;
+  return ((((int64_t)1 << lgGy) - ky) & ((1 << lgGy) - 1)) << lgGx | ((((int64_t)1 << lgGx) - kx) & ((1 << lgGx) - 1));
+}
+
+template <typename T, int MT, int BC, bool TR>
 __global__ void __launch_bounds__(256)
 spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, C2<T>* __restrict__ Yh, int n,
-                    int64_t K, int B, int n_mg, const int* __restrict__ live) {
+                    int64_t K, int B, int n_mg, int lgGx, int lgGy, const int* __restrict__ live) {
   if (live && *live == 0) return;
   const int nz = (B + BC - 1) / BC;
   const int64_t id = blockIdx.x;
@@ -406,7 +436,7 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
   for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int q = 0; q < BC; ++q) ar[i][q] = ai[i][q] = 0;
-  const C2<T>* zr = Zh + (size_t)m0 * n * K + k;
+  const int64_t kz = TR ? mirror_freq(k, lgGx, lgGy) : k;
   const C2<T>* xr = Xh + (size_t)b0 * n * K + k;
   const int mt = min(MT, n - m0);
   constexpr int kUnroll = MT * BC <= 4 ? 4 : 2;
@@ -414,7 +444,8 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
   for (int c = 0; c < n; ++c) {
     C2<T> zv[MT], xv[BC];
 #pragma unroll
-    for (int i = 0; i < MT; ++i) zv[i] = i < mt ? zr[((size_t)i * n + c) * K] : C2<T>{0, 0};
+    for (int i = 0; i < MT; ++i)
+      zv[i] = i < mt ? Zh[(TR ? (size_t)c * n + m0 + i : (size_t)(m0 + i) * n + c) * K + kz] : C2<T>{0, 0};
 #pragma unroll
     for (int q = 0; q < BC; ++q) xv[q] = q < nb ? xr[((size_t)q * n + c) * K] : C2<T>{0, 0};
 #pragma unroll
@@ -457,10 +488,10 @@ constexpr int kPM = 80, kPB = 16;
 constexpr int kZP = kPM + 1, kXP = kPB + 1;
 
 // KPW frequencies per wave, 4 KPW per workgroup; PC columns per staged chunk
-template <int KPW, int PC>
+template <int KPW, int PC, bool TR>
 __global__ void __launch_bounds__(256)
 spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __restrict__ Xh, C2<float>* __restrict__ Yh,
-                         int n, int64_t K, int B, int n_mg, int n_bt, int64_t n_tiles,
+                         int n, int64_t K, int B, int n_mg, int n_bt, int64_t n_tiles, int lgGx, int lgGy,
                          const int* __restrict__ live) {
   if (live && *live == 0) return;
   typedef float v4 __attribute__((ext_vector_type(4)));
@@ -504,7 +535,9 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
     for (int i = 0; i < NZ; ++i) {
       const int e = tid + 256 * i, k = e & (PK - 1), c = (e >> LPK) & (PC - 1), m = e >> (LPK + LPC);
       const bool ok = m0 + m < n && c0 + c < n && k0 + k < K;
-      zp[i] = ok ? Zh[((int64_t)(m0 + m) * n + c0 + c) * K + k0 + k] : C2<float>{0, 0};
+      const int64_t zi = TR ? ((int64_t)(c0 + c) * n + m0 + m) * K + mirror_freq(k0 + k, lgGx, lgGy)
+                            : ((int64_t)(m0 + m) * n + c0 + c) * K + k0 + k;
+      zp[i] = ok ? Zh[zi] : C2<float>{0, 0};
     }
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
@@ -575,40 +608,72 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
 #endif
 
 template <typename T, int MT, int BC>
-void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, hipStream_t s,
-                    const int* live) {
+void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, bool tr, int lgGx,
+                    int lgGy, hipStream_t s, const int* live) {
   const int n_mg = (n + 4 * MT - 1) / (4 * MT);
   const int64_t nwg = (G2 + 63) / 64 * n_mg * ((B + BC - 1) / BC);
-  hipLaunchKernelGGL((spec_product_kernel<T, MT, BC>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y, n, G2, B,
-                     n_mg, live);
+  if (tr)
+    hipLaunchKernelGGL((spec_product_kernel<T, MT, BC, true>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y, n, G2,
+                       B, n_mg, lgGx, lgGy, live);
+  else
+    hipLaunchKernelGGL((spec_product_kernel<T, MT, BC, false>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y, n,
+                       G2, B, n_mg, lgGx, lgGy, live);
 }
 
 // register tile by batch width: 2 rows for one or two right-hand sides (a
 // stream of the spectra wants many waves in flight), 4 rows x 4 or 8
 // right-hand sides otherwise (arithmetic per load)
 template <typename T>
-void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, hipStream_t s, const int* live) {
+void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, bool tr, int lgGx, int lgGy,
+             hipStream_t s, const int* live) {
   if (sizeof(T) == 4 && B >= 12) {  // matrix cores once a 16-wide RHS tile is mostly full
     constexpr int PK = 4 * R3M_SPEC_MFMA_KPW;
     const int n_mg = (n + kPM - 1) / kPM, n_bt = (B + kPB - 1) / kPB;
     const int64_t n_kt = (G2 + PK - 1) / PK;
     const int64_t nwg = n_bt < 8 ? ((n_kt + 1) / 2 * 2 * n_mg * n_bt + 7) / 8 * 8 : n_kt * n_mg * n_bt;
-    hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC>), dim3((unsigned)nwg), dim3(256),
-                       0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg, n_bt, n_kt,
-                       live);
+    if (tr)
+      hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC, true>), dim3((unsigned)nwg),
+                         dim3(256), 0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg,
+                         n_bt, n_kt, lgGx, lgGy, live);
+    else
+      hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC, false>), dim3((unsigned)nwg),
+                         dim3(256), 0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg,
+                         n_bt, n_kt, lgGx, lgGy, live);
   } else if (B == 1)
-    launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, s, live);
+    launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
   else if (B == 2)
-    launch_product<T, 2, 2>(Zh, X, Y, n, G2, B, s, live);
+    launch_product<T, 2, 2>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
   else if (B <= 4)
-    launch_product<T, 4, 4>(Zh, X, Y, n, G2, B, s, live);
+    launch_product<T, 4, 4>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
   else
-    launch_product<T, 4, 8>(Zh, X, Y, n, G2, B, s, live);
+    launch_product<T, 4, 8>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
+}
+
+// relaxed compaction: y[u][r] = sum over states s of ymacro[u][s n_a + r]
+// (fixed order), per RHS b = blockIdx.y
+template <typename T, typename YT>
+__global__ void __launch_bounds__(256)
+relaxed_sum_kernel(const RhsDev* __restrict__ rhs, const C2<T>* __restrict__ ym, int n, int n_a, int n_states,
+                   YT* __restrict__ y) {
+  const RhsDev R = rhs[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)R.Lx * R.Ly * n_a) return;
+  const int64_t u = e / n_a;
+  const int r = (int)(e - u * n_a);
+  const C2<T>* p = ym + (R.unit_off + u) * n + r;
+  T re = 0, im = 0;
+  for (int s = 0; s < n_states; ++s) {
+    re += p[s * n_a].re;
+    im += p[s * n_a].im;
+  }
+  YT* yv = y + (R.unit_off * n_a + e) * 2;
+  yv[0] = (YT)re;
+  yv[1] = (YT)im;
 }
 
 template <typename T, typename XT, typename YT>
 void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
-                    void* work, hipStream_t s, const int* live) {
+                    void* work, hipStream_t s, const int* live, const double* wts = nullptr, bool tr = false) {
   const int n = Z->n;
   const int lgGx = ilog2(next_pow2(2 * Z->Dx + 1)), lgGy = ilog2(next_pow2(2 * Z->Dy + 1));
   const int64_t G2 = (int64_t)1 << (lgGx + lgGy);
@@ -623,15 +688,22 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
   A.n_a = n / Z->n_states;
   A.x = x;
   A.y = y;
+  A.wts = wts;
+  A.ymacro = wts ? Y + (size_t)B * n * G2 : nullptr;  // relaxed: [units][n] after Y
   A.live = live;
   const int64_t ng = (int64_t)B * n;
   A.data = X;
   fft_pass<T, kFwdRows, XT>(A, lgGx, lgGy, ng, s);
   fft_pass<T, kFwdCols, XT>(A, lgGx, lgGy, ng, s);
-  product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, s, live);
+  product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
   A.data = Y;
   fft_pass<T, kInvCols, YT>(A, lgGx, lgGy, ng, s);
   fft_pass<T, kInvRows, YT>(A, lgGx, lgGy, ng, s);
+  if (wts) {
+    hipLaunchKernelGGL((relaxed_sum_kernel<T, YT>), dim3(ceil_div((size_t)bd.max_units * A.n_a, 256), B), dim3(256),
+                       0, s, bd.rhs, (const C2<T>*)A.ymacro, n, A.n_a, A.n_states, (YT*)y);
+    R3M_CHECK_HIP(hipGetLastError());
+  }
 }
 
 size_t spectra_bytes(int n, int Dx, int Dy, r3m_dtype dtype) {
@@ -661,21 +733,34 @@ size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z) {
   return 2 * (size_t)bd.B * Z->n * G2 * es + 256;
 }
 
-void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
-                     const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live) {
+void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
+                        const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
+                        const double* wts, bool tr) {
   const bool xd = x_type == R3M_C128, yd = y_type == R3M_C128;
   if (Z->far_dtype == R3M_SPEC_C128) {
     R3M_REQUIRE(xd && yd, R3M_ERR_UNSUPPORTED, "complex128 spectra need C128 vectors");
-    spectral_typed<double, double, double>(Z, bd, states, x, y, work, s, live);
+    spectral_typed<double, double, double>(Z, bd, states, x, y, work, s, live, wts, tr);
   } else if (xd && yd) {
-    spectral_typed<float, double, double>(Z, bd, states, x, y, work, s, live);
+    spectral_typed<float, double, double>(Z, bd, states, x, y, work, s, live, wts, tr);
   } else if (!xd && yd) {
-    spectral_typed<float, float, double>(Z, bd, states, x, y, work, s, live);
+    spectral_typed<float, float, double>(Z, bd, states, x, y, work, s, live, wts, tr);
   } else if (!xd && !yd) {
-    spectral_typed<float, float, float>(Z, bd, states, x, y, work, s, live);
+    spectral_typed<float, float, float>(Z, bd, states, x, y, work, s, live, wts, tr);
   } else {
     R3M_REQUIRE(false, R3M_ERR_UNSUPPORTED, "C128 input with C64 output");
   }
+}
+
+void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
+                     const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live) {
+  launch_spectral_ex(Z, bd, states, x_type, x, y_type, y, work, s, live, nullptr, false);
+}
+
+// relaxed workspace: the spectral workspace followed by [units][n] complex
+size_t relaxed_work_bytes(const BatchDesc& bd, const r3m_store* Z) {
+  const size_t es = Z->far_dtype == R3M_SPEC_C128 ? 16 : 8;
+  const size_t G2 = (size_t)next_pow2(2 * Z->Dx + 1) * next_pow2(2 * Z->Dy + 1);
+  return 2 * (size_t)bd.B * Z->n * G2 * es + (size_t)bd.total_units * Z->n * es + 256;
 }
 
 }  // namespace r3m
@@ -683,6 +768,38 @@ void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* sta
 using namespace r3m;
 
 extern "C" {
+
+size_t r3m_relaxed_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch) {
+  size_t out = 0;
+  int rc = guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_store(Z);
+    R3M_REQUIRE(store_is_spectral(Z), R3M_ERR_UNSUPPORTED, "relaxed retrieval needs a spectral store");
+    validate_batch(batch, Z->Dx, Z->Dy);
+    if (batch->B == 0) return;
+    out = relaxed_work_bytes(get_batch(ctx, batch, 8, 8, 0), Z);
+  });
+  return rc == R3M_OK ? out : 0;
+}
+
+int r3m_relaxed_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, const double* weights_dev,
+                       int32_t transpose, r3m_dtype vec_dtype, const void* x_dev, void* y_dev, void* work_dev,
+                       size_t work_bytes, hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_store(Z);
+    R3M_REQUIRE(store_is_spectral(Z), R3M_ERR_UNSUPPORTED, "relaxed retrieval needs a spectral store");
+    validate_batch(batch, Z->Dx, Z->Dy);
+    R3M_REQUIRE(vec_dtype == R3M_C128 || vec_dtype == R3M_C64, R3M_ERR_UNSUPPORTED, "vectors must be C128 or C64");
+    if (batch->B == 0) return;
+    R3M_REQUIRE(x_dev && y_dev && weights_dev && work_dev, R3M_ERR_INVALID_ARG, "NULL buffer");
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    const BatchDesc& bd = get_batch(ctx, batch, 8, 8, stream);
+    R3M_REQUIRE(work_bytes >= relaxed_work_bytes(bd, Z), R3M_ERR_BUFFER_TOO_SMALL, "relaxed workspace too small");
+    launch_spectral_ex(Z, bd, batch->states, vec_dtype, x_dev, vec_dtype, y_dev, work_dev, stream, nullptr,
+                       weights_dev, transpose != 0);
+  });
+}
 
 size_t r3m_spectral_bytes(int32_t n, int32_t Dx, int32_t Dy, r3m_dtype dtype) {
   if (n <= 0 || Dx < 0 || Dy < 0 || (dtype != R3M_SPEC_C64 && dtype != R3M_SPEC_C128)) return 0;

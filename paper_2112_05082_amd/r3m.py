@@ -31,7 +31,7 @@ EXPORTED = (
     "r3m_ctx_create", "r3m_ctx_destroy", "r3m_last_error", "r3m_version",
     "r3m_blocks_bytes", "r3m_fill_unique_blocks",
     "r3m_far_count", "r3m_far_bytes", "r3m_compress_work_bytes", "r3m_compress_far",
-    "r3m_spectral_bytes", "r3m_build_spectral",
+    "r3m_spectral_bytes", "r3m_build_spectral", "r3m_relaxed_work_bytes", "r3m_relaxed_matvec",
     "r3m_matvec_work_bytes", "r3m_retrieved_matvec", "r3m_matvec_groups",
     "r3m_gmres_work_bytes", "r3m_gmres_solve",
     "r3m_plane_wave_rhs", "r3m_rcs",
@@ -111,6 +111,9 @@ def load(path: str = LIB_PATH):
                                        C.POINTER(C.c_int32), C.POINTER(C.c_double), vp, sz, vp]),
         "r3m_spectral_bytes": (sz, [i32, i32, i32, C.c_int]),
         "r3m_build_spectral": (C.c_int, [vp, vp, i32, i32, i32, C.c_int, vp, sz, vp]),
+        "r3m_relaxed_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
+        "r3m_relaxed_matvec": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), vp, i32, C.c_int, vp, vp, vp,
+                                         sz, vp]),
         "r3m_matvec_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int]),
         "r3m_retrieved_matvec": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int, vp, vp, vp,
                                            sz, vp]),
@@ -295,6 +298,27 @@ def r3m_build_spectral(ctx: Context, dense, n: int, Dx: int, Dy: int, dtype: int
     _check(lib.r3m_build_spectral(ctx.handle, C.c_void_p(dense.data_ptr()), n, Dx, Dy, dtype,
                                   C.c_void_p(out.data_ptr()), out.numel() * out.element_size(), _stream(stream)),
            ctx.handle)
+
+
+def relaxed_work_bytes(ctx: Context, store: Store, batch: Batch) -> int:
+    sc = store.c()
+    return load().r3m_relaxed_work_bytes(ctx.handle, C.byref(sc), C.byref(batch.cs))
+
+
+def r3m_relaxed_matvec(ctx: Context, store: Store, batch: Batch, weights, vec_dtype: int, x, y, work,
+                       transpose: bool = False, stream=None):
+    """y = P(w)^T Z P(w) x (transpose: with Z^T); weights: float64 device
+    tensor [total units][n_states]."""
+    lib = load()
+    _need_vec(x, batch, store.n // store.n_states, "x")
+    _need_vec(y, batch, store.n // store.n_states, "y")
+    if batch.B and weights.numel() < batch.total_units * store.n_states:
+        raise ValueError("weights hold fewer than total_units x n_states entries")
+    sc = store.c()
+    _check(lib.r3m_relaxed_matvec(ctx.handle, C.byref(sc), C.byref(batch.cs), C.c_void_p(weights.data_ptr()),
+                                  1 if transpose else 0, vec_dtype, C.c_void_p(x.data_ptr()),
+                                  C.c_void_p(y.data_ptr()), C.c_void_p(work.data_ptr()),
+                                  work.numel() * work.element_size(), _stream(stream)), ctx.handle)
 
 
 def _need_vec(t, batch: Batch, n_a: int, what: str):

@@ -1,0 +1,126 @@
+"""Relaxed (blended) retrieval on the GPU against the oracle.
+
+The relaxed operator Z_k(w) = P(w)^T Z P(w) (state weights per unit, the
+operator of codebook differentiation) and its transpose P(w)^T Z^T P(w) (the
+adjoint solve's operator), on spectral stores:
+  * oracle blocks uploaded, 3 x 3 arrays, random and one-hot weights, 2 RHS
+    and 15 RHS (the latter takes the matrix-core product), both operators:
+    element-wise against the oracle's matrix form, 1e-12 (complex128
+    spectra) and 2e-6 (complex64), the tolerances of the plain spectral path;
+  * 2-bit 32 x 32: one-hot weights give the standard retrieved product
+    bitwise (weights 1 and 0 are exact), and the transpose satisfies
+    y^T (A x) = (A^T y)^T x for random weights to 1e-12 (complex128 spectra).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from gpu_common import FREQ, K, rel_max, unit  # noqa: E402
+from oracle import efie, relaxed, retrieval  # noqa: E402
+from workloads import codebooks as cb  # noqa: E402
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2112_05082_amd import pipeline, r3m
+    r3m.load()
+    ctx = r3m.Context(0)
+    yield r3m, pipeline, ctx
+    ctx.close()
+
+
+def to_dev(a, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV).to(dtype)
+
+
+def relaxed_mv(r3m, ctx, store, batch, w, x, vt, transpose):
+    y = torch.zeros_like(x)
+    work = torch.empty(r3m.relaxed_work_bytes(ctx, store, batch), dtype=torch.uint8, device=DEV)
+    r3m.r3m_relaxed_matvec(ctx, store, batch, w, vt, x, y, work, transpose=transpose)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype,tol,nrhs", [("c128", 1e-12, 2), ("c64", 2e-6, 2), ("c64", 2e-6, 15),
+                                            ("c128", 1e-12, 15)])
+def test_relaxed_vs_oracle(lib, dtype, tol, nrhs):
+    r3m, _, ctx = lib
+    L, D = 3, 2
+    blocks = efie.displacement_blocks(unit(1), D, D, K, extract=1)
+    st = r3m.C128 if dtype == "c128" else r3m.C64
+    tdt = torch.complex128 if st == r3m.C128 else torch.complex64
+    sd = r3m.SPEC_C64 if st == r3m.C64 else r3m.SPEC_C128
+    spec = torch.empty(r3m.spectral_bytes(80, D, D, sd), dtype=torch.uint8, device=DEV)
+    r3m.r3m_build_spectral(ctx, to_dev(blocks), 80, D, D, sd, spec)
+    store = r3m.Store(80, 2, D, D, 0, st, to_dev(blocks[retrieval.slot(0, 0, D, D)][None], tdt), sd, spec)
+    rng = np.random.default_rng(40 + nrhs)
+    W = rng.random((nrhs, L * L, 2))
+    W[0, :4] = np.eye(2)[rng.integers(0, 2, 4)]  # some one-hot units
+    batch = r3m.Batch.from_codebooks([np.zeros(L * L, np.uint8)] * nrhs, [L] * nrhs, DEV)
+    x = cb.random_complex(nrhs * L * L * 40, 41)
+    xd = to_dev(x, tdt)
+    if st == r3m.C64:
+        x = x.astype(np.complex64).astype(np.complex128)
+    wd = torch.from_numpy(W.reshape(-1, 2)).to(DEV)
+    worst = 0.0
+    for tr in (False, True):
+        y = relaxed_mv(r3m, ctx, store, batch, wd, xd, st, tr)
+        for b in range(nrhs):
+            sl = slice(b * L * L * 40, (b + 1) * L * L * 40)
+            ref = relaxed.relaxed_matvec(blocks, D, D, unit(1).state_off, W[b], L, x[sl], transpose=tr)
+            worst = max(worst, rel_max(y[sl], ref))
+    print(f"relaxed {dtype}, {nrhs} RHS, both operators: worst element error {worst:.2e}")
+    assert worst <= tol
+
+
+@pytest.fixture(scope="module")
+def full(lib):
+    r3m, pipeline, ctx = lib
+    geom = r3m.UnitGeom.from_macro(unit(2), FREQ, 1)
+    states = cb.uniform(32, 4, 1)
+    batch = r3m.Batch.from_codebooks([states], [32], DEV)
+    dense = pipeline.fill_blocks(ctx, geom, 31, r3m.C128, DEV)
+    s64 = pipeline.spectral_store(ctx, geom, 32, 2, r3m.C64, DEV, dense_c128=dense)
+    s128 = pipeline.spectral_store(ctx, geom, 32, 2, r3m.C128, DEV, dense_c128=dense)
+    yield states, batch, s64, s128
+
+
+def test_relaxed_one_hot_is_retrieval_fullsize(lib, full):
+    r3m, _, ctx = lib
+    states, batch, s64, _ = full
+    w = np.zeros((32 * 32, 4))
+    w[np.arange(32 * 32), states] = 1.0
+    x = to_dev(cb.random_complex(32 * 32 * 40, 42))
+    y_rel = relaxed_mv(r3m, ctx, s64, batch, torch.from_numpy(w).to(DEV), x, r3m.C128, False)
+    y = torch.zeros_like(x)
+    work = torch.empty(r3m.matvec_work_bytes(ctx, s64, batch, r3m.C128), dtype=torch.uint8, device=DEV)
+    r3m.r3m_retrieved_matvec(ctx, s64, batch, r3m.C128, x, y, work)
+    torch.cuda.synchronize()
+    assert np.array_equal(y_rel, y.cpu().numpy())
+
+
+def test_relaxed_transpose_identity_fullsize(lib, full):
+    r3m, _, ctx = lib
+    _, batch, _, s128 = full
+    rng = np.random.default_rng(43)
+    logits = rng.standard_normal((32 * 32, 4))
+    w = np.exp(logits) / np.exp(logits).sum(axis=1, keepdims=True)  # softmax blend
+    wd = torch.from_numpy(w).to(DEV)
+    x = to_dev(cb.random_complex(32 * 32 * 40, 44))
+    y = to_dev(cb.random_complex(32 * 32 * 40, 45))
+    ax = relaxed_mv(r3m, ctx, s128, batch, wd, x, r3m.C128, False)
+    aty = relaxed_mv(r3m, ctx, s128, batch, wd, y, r3m.C128, True)
+    ay = relaxed_mv(r3m, ctx, s128, batch, wd, y, r3m.C128, False)
+    xn, yn = x.cpu().numpy(), y.cpu().numpy()
+    lhs, rhs, plain = yn @ ax, aty @ xn, ay @ xn
+    print(f"32x32 relaxed: |y^T A x - (A^T y)^T x| / |y^T A x| = {abs(lhs - rhs) / abs(lhs):.2e}, "
+          f"without the transpose {abs(plain - lhs) / abs(lhs):.2e}")
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    assert abs(plain - lhs) > 1e-9 * abs(lhs)

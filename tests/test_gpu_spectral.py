@@ -261,3 +261,79 @@ def test_spectral_large_refined_solve(lib, large):
           f"{sorted(set(r[1] for r in rep))}, max residual {max(r[2] for r in rep):.2e}; FP64 reference "
           f"{rep1[0][0]} iters, RCS error {err:.2e}")
     assert rep1[0][3] and err <= 1e-4
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 2e-6)])
+def test_spectral_degenerate_extent(lib, dtype, tol):
+    """Dx = 0: single-column arrays, transforms of length 2 along x (one
+    radix-2 stage) and 8 along y; an array of one unit."""
+    r3m, _, ctx = lib
+    Dx, Dy = 0, 3
+    blocks = efie.displacement_blocks(unit(1), Dx, Dy, K, extract=1)
+    st = r3m.C128 if dtype == "c128" else r3m.C64
+    tdt = torch.complex128 if st == r3m.C128 else torch.complex64
+    sd, spec = spectra_of(r3m, ctx, to_dev(blocks), 80, Dx, Dy, st)
+    store = r3m.Store(80, 2, Dx, Dy, 0, st, to_dev(blocks[retrieval.slot(0, 0, Dx, Dy)][None], tdt), sd, spec)
+    L = np.array([[1, 4], [1, 1], [1, 2]], np.int32)
+    books = [cb.bernoulli(4, 90 + b)[: lx * ly] for b, (lx, ly) in enumerate(L)]
+    uo = np.concatenate([[0], np.cumsum(L[:, 0] * L[:, 1])[:-1]])
+    u = int((L[:, 0] * L[:, 1]).sum())
+    batch = r3m.Batch(L, uo, uo, torch.from_numpy(np.concatenate(books)).to(DEV))
+    x = cb.random_complex(u * 40, 33)
+    y = matvec(r3m, ctx, store, batch, to_dev(x, tdt), st)
+    if st == r3m.C64:
+        x = x.astype(np.complex64).astype(np.complex128)
+    worst = 0.0
+    for b, (lx, ly) in enumerate(L):
+        sl = slice(uo[b] * 40, (uo[b] + lx * ly) * 40)
+        ref = oracle_rect(blocks, Dx, Dy, 40, unit(1).state_off, books[b], lx, ly, x[sl])
+        worst = max(worst, rel_max(y[sl], ref))
+    print(f"spectral Dx=0 {dtype}: worst element error {worst:.2e}")
+    assert worst <= tol
+
+
+def test_spectral_empty_batch_and_errors(lib):
+    r3m, _, ctx = lib
+    Dx = Dy = 1
+    blocks = efie.displacement_blocks(unit(1), Dx, Dy, K, extract=1)
+    dense = to_dev(blocks)
+    sd, spec = spectra_of(r3m, ctx, dense, 80, Dx, Dy, r3m.C64)
+    near64 = to_dev(blocks[retrieval.slot(0, 0, Dx, Dy)][None], torch.complex64)
+    near128 = to_dev(blocks[retrieval.slot(0, 0, Dx, Dy)][None])
+    good = r3m.Store(80, 2, Dx, Dy, 0, r3m.C64, near64, sd, spec)
+    # an empty batch is a no-op
+    empty = r3m.Batch(np.zeros((0, 2), np.int32), [], [], torch.zeros(1, dtype=torch.uint8, device=DEV))
+    xe = torch.zeros(1, dtype=torch.complex64, device=DEV)
+    r3m.r3m_retrieved_matvec(ctx, good, empty, r3m.C64, xe, xe.clone(), None)
+    books = [cb.bernoulli(2, 5)]
+    batch = r3m.Batch.from_codebooks(books, [2], DEV)
+    x = torch.zeros(160, dtype=torch.complex64, device=DEV)
+    work = torch.empty(r3m.matvec_work_bytes(ctx, good, batch, r3m.C64), dtype=torch.uint8, device=DEV)
+
+    def code_of(fn):
+        with pytest.raises(r3m.R3MError) as e:
+            fn()
+        return e.value.code
+
+    # complex64 spectra with complex128 near blocks
+    bad = r3m.Store(80, 2, Dx, Dy, 0, r3m.C128, near128, sd, spec)
+    assert code_of(lambda: r3m.r3m_retrieved_matvec(ctx, bad, batch, r3m.C64, x, x.clone(), work)) == \
+        r3m.R3M_ERR_UNSUPPORTED
+    # missing spectra
+    nospec = r3m.Store(80, 2, Dx, Dy, 0, r3m.C64, near64, sd, None)
+    assert code_of(lambda: r3m.r3m_retrieved_matvec(ctx, nospec, batch, r3m.C64, x, x.clone(), work)) == \
+        r3m.R3M_ERR_INVALID_ARG
+    # complex128 spectra need complex128 vectors
+    sd2, spec2 = spectra_of(r3m, ctx, dense, 80, Dx, Dy, r3m.C128)
+    s128 = r3m.Store(80, 2, Dx, Dy, 0, r3m.C128, near128, sd2, spec2)
+    w2 = torch.empty(r3m.matvec_work_bytes(ctx, s128, batch, r3m.C64), dtype=torch.uint8, device=DEV)
+    assert code_of(lambda: r3m.r3m_retrieved_matvec(ctx, s128, batch, r3m.C64, x, x.clone(), w2)) == \
+        r3m.R3M_ERR_UNSUPPORTED
+    # a workspace one byte short, a spectra buffer one byte short
+    short = torch.empty(work.numel() - 1, dtype=torch.uint8, device=DEV)
+    assert code_of(lambda: r3m.r3m_retrieved_matvec(ctx, good, batch, r3m.C64, x, x.clone(), short)) == \
+        r3m.R3M_ERR_BUFFER_TOO_SMALL
+    small = torch.empty(r3m.spectral_bytes(80, Dx, Dy, r3m.SPEC_C64) - 1, dtype=torch.uint8, device=DEV)
+    assert code_of(lambda: r3m.r3m_build_spectral(ctx, dense, 80, Dx, Dy, r3m.SPEC_C64, small)) == \
+        r3m.R3M_ERR_BUFFER_TOO_SMALL
+    torch.cuda.synchronize()
