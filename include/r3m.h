@@ -264,6 +264,10 @@ typedef struct {
   int32_t precond;    /* r3m_precond */
   int32_t flags;      /* bit 0 (R3M_GMRES_EAGER): launch every Arnoldi step eagerly instead of
                          replaying captured HIP graphs of blocks of steps */
+  const double* relaxed_weights; /* NULL, or device [total units][n_states]: solve the relaxed
+                                    system Z_k(w) x = b of r3m_relaxed_matvec (spectral stores,
+                                    precond R3M_PRECOND_NONE; Z64 spectral too) */
+  int32_t transpose;             /* with relaxed_weights: solve Z_k(w)^T x = b (the adjoint) */
 } r3m_gmres_opts;
 
 #define R3M_GMRES_EAGER 1

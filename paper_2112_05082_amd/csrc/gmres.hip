@@ -816,6 +816,8 @@ struct GmresRun {
   int n_a, m, maxP, B;
   int n_states = 1;
   bool pre = false;
+  const double* wts = nullptr;  // relaxed retrieval weights (spectral stores)
+  bool tr = false;              // with wts: the transposed operator
   int G = 1;  // displacement groups of the matvec (autotuned)
   int64_t maxN, ut;
   Work W;
@@ -851,6 +853,10 @@ struct GmresRun {
   const void* lists_for(const r3m_store* Z) const { return Z == Zsolve ? W.lists : W.lists64; }
 
   void matvec(const r3m_store* Z, const double2* x, double2* y) {
+    if (wts) {
+      launch_spectral_ex(Z, *bd, batch->states, R3M_C128, x, R3M_C128, y, W.mv_partial, s, nullptr, wts, tr);
+      return;
+    }
     launch_matvec(ctx, Z, *bd, batch->states, R3M_C128, x, y, W.mv_partial, lists_for(Z), plan_groups(ctx, Z, *bd),
                   s);
   }
@@ -894,8 +900,13 @@ struct GmresRun {
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
     const int* live = run_slot(j - 1);  // j = 0: set by the cycle start
     const double2* vj = W.V + (int64_t)j * ut;
-    launch_matvec_pre(Z, *bd, batch->states, input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, W.w,
-                      W.mv_partial, lists_for(Z), G, s, live);
+    if (wts)
+      launch_spectral_ex(Z, *bd, batch->states, input_in_xs(Z) ? Z->near_dtype : R3M_C128,
+                         input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, R3M_C128, W.w, W.mv_partial, s, live,
+                         wts, tr);
+    else
+      launch_matvec_pre(Z, *bd, batch->states, input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, W.w,
+                        W.mv_partial, lists_for(Z), G, s, live);
     const dim3 dgrid(maxP, (j + 1 + kDotVec - 1) / kDotVec, B);
     const int maxB = (int)((maxN + 63) / 64 + 1);
     // long vectors (more than 64 chunk partials per coefficient): sum the
@@ -1155,7 +1166,10 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     run.ctx = ctx;
     run.use_graph = !(opts->flags & R3M_GMRES_EAGER);
     run.graph_key = {(int64_t)(intptr_t)&bd, (int64_t)(intptr_t)batch->states, (int64_t)(intptr_t)work_dev,
-                     (int64_t)m, (int64_t)opts->precond, (int64_t)bd.B, (int64_t)n_a};
+                     (int64_t)m, (int64_t)opts->precond, (int64_t)bd.B, (int64_t)n_a,
+                     (int64_t)(intptr_t)opts->relaxed_weights, (int64_t)opts->transpose};
+    run.wts = opts->relaxed_weights;
+    run.tr = opts->relaxed_weights && opts->transpose;
     run.bd = &bd;
     run.batch = batch;
     run.n_a = n_a;
@@ -1181,6 +1195,12 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
 
     R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE || opts->precond == R3M_PRECOND_BLOCK_JACOBI,
                 R3M_ERR_INVALID_ARG, "unknown preconditioner");
+    if (opts->relaxed_weights) {
+      R3M_REQUIRE(store_is_spectral(Z) && (!refine || store_is_spectral(Z64)), R3M_ERR_UNSUPPORTED,
+                  "relaxed retrieval needs spectral stores");
+      R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE, R3M_ERR_UNSUPPORTED,
+                  "relaxed retrieval runs without preconditioner");
+    }
     // input checks on the device: state bytes and finite right-hand sides
     const int64_t maxU = run.maxN / n_a;
     hipLaunchKernelGGL(states_check_kernel, dim3(ceil_div((size_t)maxU, 256), bd.B), dim3(256), 0, stream,

@@ -38,5 +38,9 @@ size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z);
 // x (x_type) to y (y_type); work: spectral_work_bytes; live as above
 void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                      const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live);
+// relaxed retrieval (wts [units][n_states], nullable) and the transposed operator
+void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
+                        const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
+                        const double* wts, bool tr);
 
 }  // namespace r3m

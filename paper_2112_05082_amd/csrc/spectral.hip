@@ -727,10 +727,11 @@ void validate_spectral(const r3m_store* Z) {
               "displacement extent too large for the transform");
 }
 
+// X and Y grids, then the relaxed compaction's macro buffer [units][n]
 size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z) {
   const size_t es = Z->far_dtype == R3M_SPEC_C128 ? 16 : 8;
   const size_t G2 = (size_t)next_pow2(2 * Z->Dx + 1) * next_pow2(2 * Z->Dy + 1);
-  return 2 * (size_t)bd.B * Z->n * G2 * es + 256;
+  return 2 * (size_t)bd.B * Z->n * G2 * es + (size_t)bd.total_units * Z->n * es + 256;
 }
 
 void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
@@ -756,12 +757,7 @@ void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* sta
   launch_spectral_ex(Z, bd, states, x_type, x, y_type, y, work, s, live, nullptr, false);
 }
 
-// relaxed workspace: the spectral workspace followed by [units][n] complex
-size_t relaxed_work_bytes(const BatchDesc& bd, const r3m_store* Z) {
-  const size_t es = Z->far_dtype == R3M_SPEC_C128 ? 16 : 8;
-  const size_t G2 = (size_t)next_pow2(2 * Z->Dx + 1) * next_pow2(2 * Z->Dy + 1);
-  return 2 * (size_t)bd.B * Z->n * G2 * es + (size_t)bd.total_units * Z->n * es + 256;
-}
+size_t relaxed_work_bytes(const BatchDesc& bd, const r3m_store* Z) { return spectral_work_bytes(bd, Z); }
 
 }  // namespace r3m
 

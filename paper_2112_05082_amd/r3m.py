@@ -74,7 +74,7 @@ class GmresOptsC(C.Structure):
     _fields_ = [
         ("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
         ("refine_tol", C.c_double), ("max_refine", C.c_int32), ("precond", C.c_int32),
-        ("flags", C.c_int32),
+        ("flags", C.c_int32), ("relaxed_weights", C.c_void_p), ("transpose", C.c_int32),
     ]
 
 
@@ -348,14 +348,17 @@ def r3m_retrieved_matvec(ctx: Context, store: Store, batch: Batch, vec_dtype: in
 def r3m_gmres_solve(ctx: Context, store: Store, store64: Store | None, batch: Batch, b, x, tol: float,
                     restart: int, max_iter: int, work, refine_tol: float = 0.0, max_refine: int = 0,
                     stream=None, allow_not_converged: bool = False, precond: int = PRECOND_NONE,
-                    eager: bool = False):
+                    eager: bool = False, relaxed_weights=None, transpose: bool = False):
+    """relaxed_weights: float64 device tensor [total units][n_states] to solve
+    the relaxed system P(w)^T Z P(w) x = b (transpose: with Z^T)."""
     lib = load()
     _need_vec(b, batch, store.n // store.n_states, "b")
     _need_vec(x, batch, store.n // store.n_states, "x")
     sc = store.c()
     s64 = store64.c() if store64 is not None else None
+    wp = C.c_void_p(relaxed_weights.data_ptr() if relaxed_weights is not None else 0)
     opts = GmresOptsC(float(tol), int(restart), int(max_iter), float(refine_tol), int(max_refine), int(precond),
-                      1 if eager else 0)
+                      1 if eager else 0, wp, 1 if transpose else 0)
     rep = (GmresReportC * max(batch.B, 1))()
     rc = lib.r3m_gmres_solve(ctx.handle, C.byref(sc), C.byref(s64) if s64 is not None else None,
                              C.byref(batch.cs), C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
@@ -424,6 +427,6 @@ def gmres_work_bytes(ctx, store: Store, batch: Batch, restart: int, store64: Sto
     """store64: the refinement store the solve will use (None: no refinement)."""
     sc = store.c()
     s64 = store64.c() if store64 is not None else None
-    opts = GmresOptsC(1e-6, int(restart), 1, 0.0, 0, 0, 0)
+    opts = GmresOptsC(1e-6, int(restart), 1, 0.0, 0, 0, 0, None, 0)
     return load().r3m_gmres_work_bytes(ctx.handle, C.byref(sc), C.byref(s64) if s64 is not None else None,
                                        C.byref(batch.cs), C.byref(opts))
