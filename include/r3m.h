@@ -244,6 +244,23 @@ int r3m_relaxed_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, 
                        int32_t transpose, r3m_dtype vec_dtype, const void* x_dev, void* y_dev, void* work_dev,
                        size_t work_bytes, hipStream_t stream);
 
+/* Gradient of a relaxed codebook's objective (the backward pass of
+ * differentiation), with G = dJ/dI~ the derivative of J with respect to the
+ * blended current I~ = P(w) I (Wirtinger, I~* held fixed), lam the adjoint
+ * solution of Z_k(w)^T lam = P(w)^T G (r3m_gmres_solve with relaxed weights
+ * and transpose), U the macro excitation (r3m_relaxed_rhs, macro = 1):
+ *   dJ/dw[u][s] = dJ[b] 2 Re sum_r [ (G - Z^T P(w) lam)[u][s n_a + r] I[u][r]
+ *                                   + lam[u][r] (U - Z P(w) I)[u][s n_a + r] ]
+ * (dI~ = dP I + P dI and dI = Z_k^-1 (dP^T U - dP^T Z I~ - P^T Z dP I)).
+ * I, lam: C128 [unit][n_a]; G, U: C128 macro [unit][n] (n = n_states n_a,
+ * state order); dJ_dev: device [B] upstream factors or NULL (1); grad_dev:
+ * [total units][n_states] FP64.  Complex128 spectra only. */
+size_t r3m_relaxed_gradient_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch);
+int r3m_relaxed_gradient(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, const double* weights_dev,
+                         const void* I_dev, const void* lam_dev, const void* G_dev, const void* U_dev,
+                         const double* dJ_dev, double* grad_dev, void* work_dev, size_t work_bytes,
+                         hipStream_t stream);
+
 /* ---------------------------------------------------------------- GMRES -- */
 
 typedef enum {
@@ -316,6 +333,22 @@ int r3m_plane_wave_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* 
 int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, const void* I_dev,
             int32_t n_dir, const double* dirs_host, double e0, double* sigma_dev,
             hipStream_t stream);
+
+/* Relaxed codebook excitation: macro == 0 writes U_k(w) = P(w)^T U
+ * ([unit][n_a] per RHS, C128; weights as in r3m_relaxed_matvec); macro != 0
+ * writes the excitation of every macro RWG, U [unit][n] (weights unused).
+ * inc_host as in r3m_plane_wave_rhs.  Synchronises the stream. */
+int r3m_relaxed_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, const double* weights_dev,
+                    const double* inc_host, int32_t macro, void* b_dev, hipStream_t stream);
+
+/* Objective of a relaxed codebook: the bistatic RCS sigma[b][dir] of the
+ * blended current I~ = P(w) I (as r3m_rcs, currents w[u][s] I[u][r] on the
+ * RWGs of every state), J[b] = mean over the directions, the derivative
+ * G = dJ/dI~ ([unit][n], C128) and the adjoint right-hand side P(w)^T G
+ * ([unit][n_a], C128).  Synchronises the stream. */
+int r3m_relaxed_objective(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, const double* weights_dev,
+                          const void* I_dev, int32_t n_dir, const double* dirs_host, double e0, double* J_dev,
+                          double* sigma_dev, void* G_dev, void* adj_dev, hipStream_t stream);
 
 #ifdef __cplusplus
 }

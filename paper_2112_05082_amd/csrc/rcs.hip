@@ -21,21 +21,8 @@ struct IncDev {
   double pad;
 };
 
-__global__ void plane_wave_kernel(GeomDev g, const RhsDev* __restrict__ rhs, const IncDev* __restrict__ inc,
-                                  const uint8_t* __restrict__ states, int n_a, int n_states, double k,
-                                  double px, double py, double2* __restrict__ out) {
-  const int b = blockIdx.y;
-  const RhsDev R = rhs[b];
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t units = (int64_t)R.Lx * R.Ly;
-  if (e >= units * n_a) return;
-  const int64_t u = e / n_a;
-  const int m = (int)(e % n_a);
-  int s = states[R.state_off + u];
-  s = s < n_states ? s : n_states - 1;
-  const int mm = s * n_a + m;
-  const double cx = (double)(u % R.Lx) * px, cy = (double)(u / R.Lx) * py;
-  const IncDev I = inc[b];
+// U of macro RWG mm of the unit whose origin is (cx, cy, 0), without e0
+__device__ double2 plane_wave_value(const GeomDev& g, int mm, double cx, double cy, const IncDev& I, double k) {
   double re = 0.0, im = 0.0;
   for (int a = 0; a < 2; ++a) {
     const int t = g.rwg_tri[2 * mm + a];
@@ -57,7 +44,54 @@ __global__ void plane_wave_kernel(GeomDev g, const RhsDev* __restrict__ rhs, con
       im += c * w * A * proj * sn;
     }
   }
-  out[R.unit_off * n_a + e] = make_double2(I.e0 * re, I.e0 * im);
+  return make_double2(re, im);
+}
+
+__global__ void plane_wave_kernel(GeomDev g, const RhsDev* __restrict__ rhs, const IncDev* __restrict__ inc,
+                                  const uint8_t* __restrict__ states, int n_a, int n_states, double k,
+                                  double px, double py, double2* __restrict__ out) {
+  const int b = blockIdx.y;
+  const RhsDev R = rhs[b];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t units = (int64_t)R.Lx * R.Ly;
+  if (e >= units * n_a) return;
+  const int64_t u = e / n_a;
+  const int m = (int)(e % n_a);
+  int s = states[R.state_off + u];
+  s = s < n_states ? s : n_states - 1;
+  const double cx = (double)(u % R.Lx) * px, cy = (double)(u / R.Lx) * py;
+  const IncDev I = inc[b];
+  const double2 v = plane_wave_value(g, s * n_a + m, cx, cy, I, k);
+  out[R.unit_off * n_a + e] = make_double2(I.e0 * v.x, I.e0 * v.y);
+}
+
+// Relaxed codebook (weights w [unit][n_states]): macro == 0 writes the blended
+// excitation U_k(w)[u][m] = sum_s w[u][s] U[u][s n_a + m] ([unit][n_a]);
+// macro != 0 writes every macro row U[u][mm] ([unit][n]), weights unused.
+__global__ void plane_wave_relaxed_kernel(GeomDev g, const RhsDev* __restrict__ rhs, const IncDev* __restrict__ inc,
+                                          const double* __restrict__ wts, int n_a, int n_states, int macro, double k,
+                                          double px, double py, double2* __restrict__ out) {
+  const int b = blockIdx.y;
+  const RhsDev R = rhs[b];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = macro ? n_a * n_states : n_a;
+  if (e >= (int64_t)R.Lx * R.Ly * per) return;
+  const int64_t u = e / per;
+  const int m = (int)(e - u * per);
+  const double cx = (double)(u % R.Lx) * px, cy = (double)(u / R.Lx) * py;
+  const IncDev I = inc[b];
+  double2 acc = make_double2(0.0, 0.0);
+  if (macro) {
+    acc = plane_wave_value(g, m, cx, cy, I, k);
+  } else {
+    for (int st = 0; st < n_states; ++st) {
+      const double w = wts[(R.unit_off + u) * n_states + st];
+      const double2 v = plane_wave_value(g, st * n_a + m, cx, cy, I, k);
+      acc.x += w * v.x;
+      acc.y += w * v.y;
+    }
+  }
+  out[R.unit_off * per + e] = make_double2(I.e0 * acc.x, I.e0 * acc.y);
 }
 
 // F[dir][m][3] for the macro unit at the origin
@@ -150,6 +184,126 @@ rcs_kernel(const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, c
   }
 }
 
+// Radiation vector of the blended current I~[u][s n_a + r] = w[u][s] I[u][r]
+// (relaxed codebook) for direction d and RHS b: sigma as rcs_kernel, and the
+// transverse part N_perp (3 complex) kept for the objective's gradient.
+__global__ void __launch_bounds__(kRcsThreads)
+rcs_relaxed_kernel(const RhsDev* __restrict__ rhs, const double* __restrict__ wts, const double2* __restrict__ I,
+                   const double2* __restrict__ F, const double* __restrict__ dirs, int n_dir, int n, int n_a,
+                   int n_states, double k, double px, double py, double scale, double* __restrict__ sigma,
+                   double2* __restrict__ nperp) {
+  __shared__ double sh[kRcsThreads / 64][6];
+  const int d = blockIdx.x, b = blockIdx.y;
+  const RhsDev R = rhs[b];
+  const double th = dirs[2 * d], ph = dirs[2 * d + 1];
+  const double rx = sin(th) * cos(ph), ry = sin(th) * sin(ph), rz = cos(th);
+  const int64_t units = (int64_t)R.Lx * R.Ly;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const double2* Fd = F + (size_t)d * n * 3;
+  for (int64_t u = threadIdx.x; u < units; u += blockDim.x) {
+    const double cx = (double)(u % R.Lx) * px, cy = (double)(u / R.Lx) * py;
+    double sn, cs;
+    sincos(k * (rx * cx + ry * cy), &sn, &cs);
+    double loc[6] = {0, 0, 0, 0, 0, 0};
+    const double2* Iu = I + (R.unit_off + u) * n_a;
+    for (int st = 0; st < n_states; ++st) {
+      const double w = wts[(R.unit_off + u) * n_states + st];
+      for (int m = 0; m < n_a; ++m) {
+        const double2 cur = make_double2(w * Iu[m].x, w * Iu[m].y);
+        const double2* f = Fd + (size_t)(st * n_a + m) * 3;
+        for (int q = 0; q < 3; ++q) {
+          loc[2 * q] += cur.x * f[q].x - cur.y * f[q].y;
+          loc[2 * q + 1] += cur.x * f[q].y + cur.y * f[q].x;
+        }
+      }
+    }
+    for (int q = 0; q < 3; ++q) {
+      acc[2 * q] += loc[2 * q] * cs - loc[2 * q + 1] * sn;
+      acc[2 * q + 1] += loc[2 * q] * sn + loc[2 * q + 1] * cs;
+    }
+  }
+  for (int q = 0; q < 6; ++q)
+    for (int o = 32; o >= 1; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
+  if ((threadIdx.x & 63) == 0)
+    for (int q = 0; q < 6; ++q) sh[threadIdx.x >> 6][q] = acc[q];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double N[6];
+    for (int q = 0; q < 6; ++q) {
+      N[q] = sh[0][q];
+      for (int w = 1; w < kRcsThreads / 64; ++w) N[q] += sh[w][q];
+    }
+    const double rr[3] = {rx, ry, rz};
+    const double dre = N[0] * rx + N[2] * ry + N[4] * rz;
+    const double dim = N[1] * rx + N[3] * ry + N[5] * rz;
+    double p2 = 0.0;
+    for (int q = 0; q < 3; ++q) {
+      const double pr = N[2 * q] - dre * rr[q], pi = N[2 * q + 1] - dim * rr[q];
+      p2 += pr * pr + pi * pi;
+      nperp[((size_t)b * n_dir + d) * 3 + q] = make_double2(pr, pi);
+    }
+    sigma[(size_t)b * n_dir + d] = scale * p2;
+  }
+}
+
+// J[b] = mean over directions of sigma[b][:] (fixed order)
+__global__ void mean_dirs_kernel(const double* __restrict__ sigma, int n_dir, int B, double* __restrict__ J) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double t = 0.0;
+  for (int d = 0; d < n_dir; ++d) t += sigma[(size_t)b * n_dir + d];
+  J[b] = t / n_dir;
+}
+
+// G[u][mm] = dJ/dI~[u][mm] = (scale / n_dir) sum_d conj(N_perp(d)) . F_mm(d)
+// exp(j k r_hat_d . c_u) (Wirtinger derivative of the mean RCS), macro layout
+__global__ void relaxed_dj_kernel(const RhsDev* __restrict__ rhs, const double2* __restrict__ F,
+                                  const double* __restrict__ dirs, const double2* __restrict__ nperp, int n_dir, int n,
+                                  double k, double px, double py, double scale, double2* __restrict__ G) {
+  const int b = blockIdx.y;
+  const RhsDev R = rhs[b];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)R.Lx * R.Ly * n) return;
+  const int64_t u = e / n;
+  const int mm = (int)(e - u * n);
+  const double cx = (double)(u % R.Lx) * px, cy = (double)(u / R.Lx) * py;
+  double gr = 0.0, gi = 0.0;
+  for (int d = 0; d < n_dir; ++d) {
+    const double th = dirs[2 * d], ph = dirs[2 * d + 1];
+    double sn, cs;
+    sincos(k * (sin(th) * cos(ph) * cx + sin(th) * sin(ph) * cy), &sn, &cs);
+    const double2* f = F + ((size_t)d * n + mm) * 3;
+    const double2* np_ = nperp + ((size_t)b * n_dir + d) * 3;
+    double tr = 0.0, ti = 0.0;  // conj(N_perp) . F_mm
+    for (int q = 0; q < 3; ++q) {
+      tr += np_[q].x * f[q].x + np_[q].y * f[q].y;
+      ti += np_[q].x * f[q].y - np_[q].y * f[q].x;
+    }
+    gr += tr * cs - ti * sn;
+    gi += tr * sn + ti * cs;
+  }
+  G[R.unit_off * n + e] = make_double2(scale / n_dir * gr, scale / n_dir * gi);
+}
+
+// a[u][r] = sum_s w[u][s] G[u][s n_a + r]: P(w)^T G, the adjoint right-hand side
+__global__ void blend_transpose_kernel(const RhsDev* __restrict__ rhs, const double* __restrict__ wts,
+                                       const double2* __restrict__ G, int n_a, int n_states, double2* __restrict__ a) {
+  const int b = blockIdx.y;
+  const RhsDev R = rhs[b];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)R.Lx * R.Ly * n_a) return;
+  const int64_t u = e / n_a;
+  const int r = (int)(e - u * n_a);
+  double xr = 0.0, xi = 0.0;
+  for (int st = 0; st < n_states; ++st) {
+    const double w = wts[(R.unit_off + u) * n_states + st];
+    const double2 g = G[(R.unit_off + u) * n_a * n_states + st * n_a + r];
+    xr += w * g.x;
+    xi += w * g.y;
+  }
+  a[R.unit_off * n_a + e] = make_double2(xr, xi);
+}
+
 }  // namespace
 }  // namespace r3m
 
@@ -222,6 +376,91 @@ int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, cons
     hipLaunchKernelGGL(rcs_kernel, dim3(n_dir, bd.B), dim3(kRcsThreads), 0, stream, bd.rhs, batch->states,
                        (const double2*)I_dev, F, ddev, n_dir, geom->n_rwg, n_a, geom->n_states, k,
                        geom->period_x, geom->period_y, scale, sigma_dev);
+    R3M_CHECK_HIP(hipGetLastError());
+    R3M_CHECK_HIP(hipStreamSynchronize(stream));
+    tmp.release();
+  });
+}
+
+int r3m_relaxed_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, const double* weights_dev,
+                    const double* inc_host, int32_t macro, void* b_dev, hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_geom(geom);
+    validate_batch(batch, 1 << 20, 1 << 20);
+    if (batch->B == 0) return;
+    R3M_REQUIRE(inc_host && b_dev && (macro || weights_dev), R3M_ERR_INVALID_ARG, "NULL argument");
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    const int n_a = geom->state_off[1] - geom->state_off[0];
+    GeomDev g = upload_geom(ctx, geom, stream);
+    const BatchDesc& bd = get_batch(ctx, batch, 4, 4, stream);
+    std::vector<IncDev> inc(bd.B);
+    for (int b = 0; b < bd.B; ++b) {
+      const double th = inc_host[3 * b], ph = inc_host[3 * b + 1];
+      R3M_REQUIRE(std::isfinite(th) && std::isfinite(ph) && std::isfinite(inc_host[3 * b + 2]),
+                  R3M_ERR_INVALID_ARG, "non-finite incidence");
+      inc[b] = IncDev{-std::sin(th) * std::cos(ph), -std::sin(th) * std::sin(ph), -std::cos(th),
+                      std::cos(th) * std::cos(ph), std::cos(th) * std::sin(ph), -std::sin(th),
+                      inc_host[3 * b + 2], 0.0};
+    }
+    DevBuf tmp;
+    tmp.ensure(inc.size() * sizeof(IncDev));
+    R3M_CHECK_HIP(hipMemcpyAsync(tmp.ptr, inc.data(), inc.size() * sizeof(IncDev), hipMemcpyHostToDevice, stream));
+    int64_t maxU = 0;
+    for (int b = 0; b < bd.B; ++b) maxU = std::max<int64_t>(maxU, bd.n_units[b]);
+    const double k = 2.0 * kPi * geom->freq_hz / kC0;
+    const int per = macro ? n_a * geom->n_states : n_a;
+    hipLaunchKernelGGL(plane_wave_relaxed_kernel, dim3(ceil_div((size_t)maxU * per, 256), bd.B), dim3(256), 0,
+                       stream, g, bd.rhs, (const IncDev*)tmp.ptr, weights_dev, n_a, geom->n_states, macro ? 1 : 0, k,
+                       geom->period_x, geom->period_y, (double2*)b_dev);
+    R3M_CHECK_HIP(hipGetLastError());
+    R3M_CHECK_HIP(hipStreamSynchronize(stream));
+    tmp.release();
+  });
+}
+
+int r3m_relaxed_objective(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, const double* weights_dev,
+                          const void* I_dev, int32_t n_dir, const double* dirs_host, double e0, double* J_dev,
+                          double* sigma_dev, void* G_dev, void* adj_dev, hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_geom(geom);
+    validate_batch(batch, 1 << 20, 1 << 20);
+    R3M_REQUIRE(n_dir >= 1, R3M_ERR_INVALID_ARG, "n_dir < 1");
+    R3M_REQUIRE(e0 != 0.0 && std::isfinite(e0), R3M_ERR_INVALID_ARG, "e0 must be finite and non-zero");
+    if (batch->B == 0) return;
+    R3M_REQUIRE(weights_dev && I_dev && dirs_host && J_dev && sigma_dev && G_dev && adj_dev, R3M_ERR_INVALID_ARG,
+                "NULL argument");
+    for (int d = 0; d < 2 * n_dir; ++d)
+      R3M_REQUIRE(std::isfinite(dirs_host[d]), R3M_ERR_INVALID_ARG, "non-finite direction");
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    const int n_a = geom->state_off[1] - geom->state_off[0];
+    GeomDev g = upload_geom(ctx, geom, stream);
+    const BatchDesc& bd = get_batch(ctx, batch, 4, 4, stream);
+    const double k = 2.0 * kPi * geom->freq_hz / kC0;
+    DevBuf tmp;
+    const size_t fbytes = (size_t)n_dir * geom->n_rwg * 3 * sizeof(double2);
+    const size_t npbytes = (size_t)bd.B * n_dir * 3 * sizeof(double2);
+    tmp.ensure(fbytes + npbytes + (size_t)n_dir * 16 + 512);
+    double2* F = (double2*)tmp.ptr;
+    double2* np_ = (double2*)((char*)tmp.ptr + fbytes);
+    double* ddev = (double*)((char*)tmp.ptr + fbytes + npbytes);
+    R3M_CHECK_HIP(hipMemcpyAsync(ddev, dirs_host, (size_t)n_dir * 16, hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(macro_radiation_kernel, dim3(ceil_div((size_t)n_dir * geom->n_rwg, 128)), dim3(128), 0,
+                       stream, g, ddev, n_dir, k, F);
+    const double scale = k * k * kEta0 * kEta0 / (4.0 * kPi) / (e0 * e0);
+    hipLaunchKernelGGL(rcs_relaxed_kernel, dim3(n_dir, bd.B), dim3(kRcsThreads), 0, stream, bd.rhs, weights_dev,
+                       (const double2*)I_dev, (const double2*)F, (const double*)ddev, n_dir, geom->n_rwg, n_a,
+                       geom->n_states, k, geom->period_x, geom->period_y, scale, sigma_dev, np_);
+    hipLaunchKernelGGL(mean_dirs_kernel, dim3(ceil_div((size_t)bd.B, 64)), dim3(64), 0, stream,
+                       (const double*)sigma_dev, n_dir, bd.B, J_dev);
+    int64_t maxU = 0;
+    for (int b = 0; b < bd.B; ++b) maxU = std::max<int64_t>(maxU, bd.n_units[b]);
+    hipLaunchKernelGGL(relaxed_dj_kernel, dim3(ceil_div((size_t)maxU * geom->n_rwg, 256), bd.B), dim3(256), 0,
+                       stream, bd.rhs, (const double2*)F, (const double*)ddev, (const double2*)np_, n_dir,
+                       geom->n_rwg, k, geom->period_x, geom->period_y, scale, (double2*)G_dev);
+    hipLaunchKernelGGL(blend_transpose_kernel, dim3(ceil_div((size_t)maxU * n_a, 256), bd.B), dim3(256), 0, stream,
+                       bd.rhs, weights_dev, (const double2*)G_dev, n_a, geom->n_states, (double2*)adj_dev);
     R3M_CHECK_HIP(hipGetLastError());
     R3M_CHECK_HIP(hipStreamSynchronize(stream));
     tmp.release();

@@ -192,6 +192,7 @@ struct FftArgs {
   // ymacro [unit][n] (summed over states afterwards)
   const double* wts;
   C2<T>* ymacro;
+  int macro_plain;  // kInvRows with wts: write y~ itself (the macro product Z P(w) x), no weights
   const int* live;
 };
 
@@ -314,7 +315,7 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
         const int64_t u = (int64_t)gy * Lx + gx;
         if (A.wts) {
           const int c = c0 + li, s = c / A.n_a;
-          const T ws = (T)A.wts[(R.unit_off + u) * A.n_states + s] * scale;
+          const T ws = (A.macro_plain ? T(1) : (T)A.wts[(R.unit_off + u) * A.n_states + s]) * scale;
           A.ymacro[(R.unit_off + u) * A.n + c] = {v.re * ws, v.im * ws};
         } else {
           const int r = active(u, c0 + li);
@@ -673,7 +674,8 @@ relaxed_sum_kernel(const RhsDev* __restrict__ rhs, const C2<T>* __restrict__ ym,
 
 template <typename T, typename XT, typename YT>
 void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
-                    void* work, hipStream_t s, const int* live, const double* wts = nullptr, bool tr = false) {
+                    void* work, hipStream_t s, const int* live, const double* wts = nullptr, bool tr = false,
+                    C2<T>* macro_out = nullptr) {
   const int n = Z->n;
   const int lgGx = ilog2(next_pow2(2 * Z->Dx + 1)), lgGy = ilog2(next_pow2(2 * Z->Dy + 1));
   const int64_t G2 = (int64_t)1 << (lgGx + lgGy);
@@ -689,7 +691,8 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
   A.x = x;
   A.y = y;
   A.wts = wts;
-  A.ymacro = wts ? Y + (size_t)B * n * G2 : nullptr;  // relaxed: [units][n] after Y
+  A.ymacro = macro_out ? macro_out : wts ? Y + (size_t)B * n * G2 : nullptr;  // relaxed: [units][n] after Y
+  A.macro_plain = macro_out ? 1 : 0;
   A.live = live;
   const int64_t ng = (int64_t)B * n;
   A.data = X;
@@ -699,11 +702,40 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
   A.data = Y;
   fft_pass<T, kInvCols, YT>(A, lgGx, lgGy, ng, s);
   fft_pass<T, kInvRows, YT>(A, lgGx, lgGy, ng, s);
-  if (wts) {
+  if (wts && !macro_out) {
     hipLaunchKernelGGL((relaxed_sum_kernel<T, YT>), dim3(ceil_div((size_t)bd.max_units * A.n_a, 256), B), dim3(256),
                        0, s, bd.rhs, (const C2<T>*)A.ymacro, n, A.n_a, A.n_states, (YT*)y);
     R3M_CHECK_HIP(hipGetLastError());
   }
+}
+
+// dJ/dw[u][s] = dJ[b] 2 Re sum_r [ (G - Q)[u][s n_a + r] I[u][r]
+//                                 + lam[u][r] (U - ZI)[u][s n_a + r] ]
+// with Q = Z^T P(w) lam and ZI = Z P(w) I (macro layout [unit][n]), per RHS
+// b = blockIdx.y, one thread per (unit, state)
+__global__ void __launch_bounds__(256)
+relaxed_grad_kernel(const RhsDev* __restrict__ rhs, const double2* __restrict__ I, const double2* __restrict__ lam,
+                    const double2* __restrict__ G, const double2* __restrict__ U, const double2* __restrict__ ZI,
+                    const double2* __restrict__ Q, const double* __restrict__ dJ, int n_a, int n_states,
+                    double* __restrict__ grad) {
+  const int b = blockIdx.y;
+  const RhsDev R = rhs[b];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)R.Lx * R.Ly * n_states) return;
+  const int64_t u = e / n_states;
+  const int st = (int)(e - u * n_states);
+  const int n = n_a * n_states;
+  const double2* Iu = I + (R.unit_off + u) * n_a;
+  const double2* lu = lam + (R.unit_off + u) * n_a;
+  const size_t mb = (size_t)(R.unit_off + u) * n + (size_t)st * n_a;
+  double acc = 0.0;
+  for (int r = 0; r < n_a; ++r) {
+    const double2 gq = make_double2(G[mb + r].x - Q[mb + r].x, G[mb + r].y - Q[mb + r].y);
+    const double2 rr = make_double2(U[mb + r].x - ZI[mb + r].x, U[mb + r].y - ZI[mb + r].y);
+    acc += gq.x * Iu[r].x - gq.y * Iu[r].y;
+    acc += lu[r].x * rr.x - lu[r].y * rr.y;
+  }
+  grad[(R.unit_off + u) * n_states + st] = (dJ ? dJ[b] : 1.0) * 2.0 * acc;
 }
 
 size_t spectra_bytes(int n, int Dx, int Dy, r3m_dtype dtype) {
@@ -764,6 +796,52 @@ size_t relaxed_work_bytes(const BatchDesc& bd, const r3m_store* Z) { return spec
 using namespace r3m;
 
 extern "C" {
+
+size_t r3m_relaxed_gradient_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch) {
+  size_t out = 0;
+  int rc = guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_store(Z);
+    R3M_REQUIRE(Z->far_dtype == R3M_SPEC_C128, R3M_ERR_UNSUPPORTED, "the gradient needs complex128 spectra");
+    validate_batch(batch, Z->Dx, Z->Dy);
+    if (batch->B == 0) return;
+    const BatchDesc& bd = get_batch(ctx, batch, 8, 8, 0);
+    out = (spectral_work_bytes(bd, Z) + 255) / 256 * 256 + 2 * (size_t)bd.total_units * Z->n * 16;
+  });
+  return rc == R3M_OK ? out : 0;
+}
+
+int r3m_relaxed_gradient(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, const double* weights_dev,
+                         const void* I_dev, const void* lam_dev, const void* G_dev, const void* U_dev,
+                         const double* dJ_dev, double* grad_dev, void* work_dev, size_t work_bytes,
+                         hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_store(Z);
+    R3M_REQUIRE(Z->far_dtype == R3M_SPEC_C128, R3M_ERR_UNSUPPORTED, "the gradient needs complex128 spectra");
+    validate_batch(batch, Z->Dx, Z->Dy);
+    if (batch->B == 0) return;
+    R3M_REQUIRE(weights_dev && I_dev && lam_dev && G_dev && U_dev && grad_dev && work_dev, R3M_ERR_INVALID_ARG,
+                "NULL buffer");
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    const BatchDesc& bd = get_batch(ctx, batch, 8, 8, stream);
+    const size_t sw = (spectral_work_bytes(bd, Z) + 255) / 256 * 256;
+    const size_t mac = (size_t)bd.total_units * Z->n;
+    R3M_REQUIRE(work_bytes >= sw + 2 * mac * 16, R3M_ERR_BUFFER_TOO_SMALL, "gradient workspace too small");
+    C2<double>* ZI = (C2<double>*)((char*)work_dev + sw);
+    C2<double>* Q = ZI + mac;
+    spectral_typed<double, double, double>(Z, bd, batch->states, I_dev, nullptr, work_dev, stream, nullptr,
+                                           weights_dev, false, ZI);
+    spectral_typed<double, double, double>(Z, bd, batch->states, lam_dev, nullptr, work_dev, stream, nullptr,
+                                           weights_dev, true, Q);
+    const int n_a = Z->n / Z->n_states;
+    hipLaunchKernelGGL(relaxed_grad_kernel, dim3(ceil_div((size_t)bd.max_units * Z->n_states, 256), bd.B), dim3(256),
+                       0, stream, bd.rhs, (const double2*)I_dev, (const double2*)lam_dev, (const double2*)G_dev,
+                       (const double2*)U_dev, (const double2*)ZI, (const double2*)Q, dJ_dev, n_a, Z->n_states,
+                       grad_dev);
+    R3M_CHECK_HIP(hipGetLastError());
+  });
+}
 
 size_t r3m_relaxed_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch) {
   size_t out = 0;

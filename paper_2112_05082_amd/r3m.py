@@ -32,6 +32,7 @@ EXPORTED = (
     "r3m_blocks_bytes", "r3m_fill_unique_blocks",
     "r3m_far_count", "r3m_far_bytes", "r3m_compress_work_bytes", "r3m_compress_far",
     "r3m_spectral_bytes", "r3m_build_spectral", "r3m_relaxed_work_bytes", "r3m_relaxed_matvec",
+    "r3m_relaxed_gradient_work_bytes", "r3m_relaxed_gradient", "r3m_relaxed_rhs", "r3m_relaxed_objective",
     "r3m_matvec_work_bytes", "r3m_retrieved_matvec", "r3m_matvec_groups",
     "r3m_gmres_work_bytes", "r3m_gmres_solve",
     "r3m_plane_wave_rhs", "r3m_rcs",
@@ -112,6 +113,13 @@ def load(path: str = LIB_PATH):
         "r3m_spectral_bytes": (sz, [i32, i32, i32, C.c_int]),
         "r3m_build_spectral": (C.c_int, [vp, vp, i32, i32, i32, C.c_int, vp, sz, vp]),
         "r3m_relaxed_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
+        "r3m_relaxed_gradient_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
+        "r3m_relaxed_gradient": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), vp, vp, vp, vp, vp, vp, vp, vp,
+                                           sz, vp]),
+        "r3m_relaxed_rhs": (C.c_int, [vp, C.POINTER(UnitGeomC), C.POINTER(BatchC), vp, C.POINTER(C.c_double), i32,
+                                      vp, vp]),
+        "r3m_relaxed_objective": (C.c_int, [vp, C.POINTER(UnitGeomC), C.POINTER(BatchC), vp, vp, i32,
+                                            C.POINTER(C.c_double), dbl, vp, vp, vp, vp, vp]),
         "r3m_relaxed_matvec": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), vp, i32, C.c_int, vp, vp, vp,
                                          sz, vp]),
         "r3m_matvec_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int]),
@@ -319,6 +327,40 @@ def r3m_relaxed_matvec(ctx: Context, store: Store, batch: Batch, weights, vec_dt
                                   1 if transpose else 0, vec_dtype, C.c_void_p(x.data_ptr()),
                                   C.c_void_p(y.data_ptr()), C.c_void_p(work.data_ptr()),
                                   work.numel() * work.element_size(), _stream(stream)), ctx.handle)
+
+
+def relaxed_gradient_work_bytes(ctx: Context, store: Store, batch: Batch) -> int:
+    sc = store.c()
+    return load().r3m_relaxed_gradient_work_bytes(ctx.handle, C.byref(sc), C.byref(batch.cs))
+
+
+def _p(t):
+    return C.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def r3m_relaxed_rhs(ctx: Context, geom: "UnitGeom", batch: Batch, weights, inc, b, macro: bool = False,
+                    stream=None):
+    inc = np.ascontiguousarray(np.asarray(inc, dtype=np.float64).reshape(-1, 3))
+    if len(inc) != batch.B:
+        raise ValueError("one incidence per RHS")
+    _check(load().r3m_relaxed_rhs(ctx.handle, C.byref(geom.c), C.byref(batch.cs), _p(weights), _ptr(inc, C.c_double),
+                                  1 if macro else 0, _p(b), _stream(stream)), ctx.handle)
+
+
+def r3m_relaxed_objective(ctx: Context, geom: "UnitGeom", batch: Batch, weights, I, dirs, e0, J, sigma, G, adj,
+                          stream=None):
+    dirs = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 2))
+    _check(load().r3m_relaxed_objective(ctx.handle, C.byref(geom.c), C.byref(batch.cs), _p(weights), _p(I),
+                                        len(dirs), _ptr(dirs, C.c_double), float(e0), _p(J), _p(sigma), _p(G),
+                                        _p(adj), _stream(stream)), ctx.handle)
+
+
+def r3m_relaxed_gradient(ctx: Context, store: Store, batch: Batch, weights, I, lam, G, U, dJ, grad, work,
+                         stream=None):
+    sc = store.c()
+    _check(load().r3m_relaxed_gradient(ctx.handle, C.byref(sc), C.byref(batch.cs), _p(weights), _p(I), _p(lam),
+                                       _p(G), _p(U), _p(dJ), _p(grad), _p(work), work.numel() * work.element_size(),
+                                       _stream(stream)), ctx.handle)
 
 
 def _need_vec(t, batch: Batch, n_a: int, what: str):

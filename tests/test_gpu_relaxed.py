@@ -161,3 +161,73 @@ def test_relaxed_solve_vs_oracle_lu(lib, transpose):
     print(f"relaxed solve (transpose={transpose}): iters {[r[0] for r in rep]}, errors vs LU "
           f"{['%.2e' % e for e in errs]}")
     assert all(r[3] for r in rep) and max(errs) <= 1e-8
+
+
+def test_relaxed_objective_and_gradient_vs_oracle(lib):
+    """Objective J = mean RCS over a 30-degree cone of the blended current and
+    its adjoint gradient dJ/dw, 2-bit 2 x 2 arrays x 2 RHS, complex128
+    spectra, GMRES to 1e-12: J and sigma within 1e-9, gradient within 1e-7 of
+    its largest entry, against the oracle (dense LU; gradient pinned by
+    finite differences of the oracle's J)."""
+    from paper_2112_05082_amd.relaxed import RelaxedRcs
+    r3m, _, ctx = lib
+    L, D = 2, 1
+    u2 = unit(2)
+    blocks = efie.displacement_blocks(u2, D, D, K, extract=1)
+    spec = torch.empty(r3m.spectral_bytes(160, D, D, r3m.SPEC_C128), dtype=torch.uint8, device=DEV)
+    r3m.r3m_build_spectral(ctx, to_dev(blocks), 160, D, D, r3m.SPEC_C128, spec)
+    store = r3m.Store(160, 4, D, D, 0, r3m.C128, to_dev(blocks[retrieval.slot(0, 0, D, D)][None]), r3m.SPEC_C128,
+                      spec)
+    geom = r3m.UnitGeom.from_macro(u2, FREQ, 1)
+    rng = np.random.default_rng(60)
+    logits = rng.standard_normal((2, L * L, 4))
+    W = np.exp(logits) / np.exp(logits).sum(axis=2, keepdims=True)
+    batch = r3m.Batch.from_codebooks([np.zeros(L * L, np.uint8)] * 2, [L] * 2, DEV)
+    dirs = cb.cone16(30.0)
+    obj = RelaxedRcs(ctx, geom, store, batch, [[0.0, 0.0, 1.0]] * 2, dirs, tol=1e-12)
+    wd = torch.from_numpy(W.reshape(-1, 4)).to(DEV)
+    J, sigma, I, G, adj = obj.forward_parts(wd)
+    grad = obj.gradient(wd, I, G, adj).cpu().numpy().reshape(2, L * L, 4)
+    J, sigma = J.cpu().numpy(), sigma.cpu().numpy()
+    for b in range(2):
+        Jr, sr, _, gr = relaxed.relaxed_objective(u2, blocks, D, W[b], L, K, dirs, with_grad=True)
+        eJ, es = abs(J[b] - Jr) / abs(Jr), rel_max(sigma[b], sr)
+        eg = np.abs(grad[b] - gr).max() / np.abs(gr).max()
+        print(f"relaxed objective RHS {b}: J {J[b]:.6e} (err {eJ:.1e}), sigma err {es:.1e}, gradient err {eg:.1e}")
+        assert eJ <= 1e-9 and es <= 1e-9 and eg <= 1e-7
+
+
+def test_relaxed_autograd_matches_finite_differences_8x8(lib):
+    """The differentiation workload at 8 x 8: 2-bit units, softmax logits
+    ~N(0,1) (seed 3), J = mean RCS over 16 directions in a 30-degree cone;
+    torch autograd through the relaxed objective against central differences
+    (h = 1e-4 on the logits) along three random directions, within 1e-5."""
+    from paper_2112_05082_amd import pipeline
+    from paper_2112_05082_amd.relaxed import RelaxedRcs
+    r3m, _, ctx = lib
+    L = 8
+    geom = r3m.UnitGeom.from_macro(unit(2), FREQ, 1)
+    store = pipeline.spectral_store(ctx, geom, L, 0, r3m.C128, DEV)
+    batch = r3m.Batch.from_codebooks([np.zeros(L * L, np.uint8)], [L], DEV)
+    obj = RelaxedRcs(ctx, geom, store, batch, [[0.0, 0.0, 1.0]], cb.cone16(30.0), tol=1e-12)
+    logits = torch.from_numpy(np.random.default_rng(3).standard_normal((L * L, 4))).to(DEV).requires_grad_(True)
+    J = obj(torch.softmax(logits, dim=1))
+    J.sum().backward()
+    g = logits.grad.detach().cpu().numpy()
+    iters = obj.last_reports[0][0]
+    rng = np.random.default_rng(4)
+    h = 1e-4
+    errs = []
+    with torch.no_grad():
+        for _ in range(3):
+            v = rng.standard_normal(g.shape)
+            v /= np.linalg.norm(v)
+            vd = torch.from_numpy(v).to(DEV)
+            Jp = obj(torch.softmax(logits + h * vd, dim=1)).item()
+            Jm = obj(torch.softmax(logits - h * vd, dim=1)).item()
+            fd = (Jp - Jm) / (2 * h)
+            ad = float(np.sum(g * v))
+            errs.append(abs(fd - ad) / max(abs(fd), 1e-300))
+    print(f"8x8 relaxed autograd: J {J.item():.6e}, adjoint solve iters {iters}, directional FD vs autograd "
+          f"errors {['%.1e' % e for e in errs]}")
+    assert max(errs) <= 1e-5

@@ -84,3 +84,30 @@ def test_blend_scales_per_unit():
     Au[:, :40] *= 2.0
     assert np.abs(y2 - Au @ x).max() <= 1e-12 * np.abs(y2).max()
     assert np.abs(y2 - y0).max() > 1e-3 * np.abs(y0).max()
+
+
+def test_adjoint_gradient_matches_finite_differences():
+    """The adjoint gradient of J(w) = mean RCS over a 30-degree cone (2-bit,
+    2 x 2 array) against central differences of J itself (forward solves
+    only): every component within 1e-6 of the largest."""
+    from workloads.mesh import macro_unit as mu
+    unit = mu((0.005, 0.007, 0.009, 0.011))
+    L = 2
+    blocks = efie.displacement_blocks(unit, L - 1, L - 1, K, extract=1)
+    rng = np.random.default_rng(13)
+    logits = rng.standard_normal((L * L, 4))
+    w = np.exp(logits) / np.exp(logits).sum(axis=1, keepdims=True)
+    thph = cb.cone16(30.0)
+    J, _, _, grad = relaxed.relaxed_objective(unit, blocks, L - 1, w, L, K, thph, with_grad=True)
+    h = 1e-6
+    fd = np.zeros_like(grad)
+    for u in range(L * L):
+        for s in range(4):
+            wp, wm = w.copy(), w.copy()
+            wp[u, s] += h
+            wm[u, s] -= h
+            Jp = relaxed.relaxed_objective(unit, blocks, L - 1, wp, L, K, thph)[0]
+            Jm = relaxed.relaxed_objective(unit, blocks, L - 1, wm, L, K, thph)[0]
+            fd[u, s] = (Jp - Jm) / (2 * h)
+    assert np.abs(grad - fd).max() <= 1e-6 * np.abs(fd).max()
+    assert np.abs(fd).max() > 0
