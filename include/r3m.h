@@ -282,8 +282,11 @@ typedef struct {
   int32_t flags;      /* bit 0 (R3M_GMRES_EAGER): launch every Arnoldi step eagerly instead of
                          replaying captured HIP graphs of blocks of steps */
   const double* relaxed_weights; /* NULL, or device [total units][n_states]: solve the relaxed
-                                    system Z_k(w) x = b of r3m_relaxed_matvec (spectral stores,
-                                    precond R3M_PRECOND_NONE; Z64 spectral too) */
+                                    system Z_k(w) x = b of r3m_relaxed_matvec (spectral stores;
+                                    Z64 spectral too).  R3M_PRECOND_BLOCK_JACOBI then inverts the
+                                    blended self block sum_{s,s'} w_s w_s' Z(0)[A(s), A(s')] of
+                                    every unit (its transpose for the adjoint).  The work query
+                                    only tests this pointer for NULL. */
   int32_t transpose;             /* with relaxed_weights: solve Z_k(w)^T x = b (the adjoint) */
 } r3m_gmres_opts;
 

@@ -416,7 +416,7 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
                       double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
                       double* __restrict__ wn, int64_t ut, const int* __restrict__ live,
                       const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
-                      const int64_t* __restrict__ soff, int n_a, int n_states, OT* __restrict__ xs) {
+                      const int64_t* __restrict__ soff, int n_a, int n_states, OT* __restrict__ xs, int per_unit) {
   if (live && *live == 0) return;
   __shared__ double nv_s;
   __shared__ double2 v_s[256];
@@ -452,7 +452,7 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
     if (in) {
       const int64_t u = k / n_a;
       const int mr = (int)(k % n_a);
-      const int sidx = min((int)states[soff[b] + u], n_states - 1);
+      const int64_t sidx = per_unit ? r.off / n_a + u : min((int)states[soff[b] + u], n_states - 1);
       const double2* M = Minv + ((size_t)sidx * n_a + mr) * n_a;
       const double2* vu = v_s + (threadIdx.x / n_a) * n_a;
       double2 acc = make_double2(0.0, 0.0);
@@ -592,28 +592,12 @@ __global__ void nonfinite_kernel(const double2* __restrict__ v, const RhsVec* __
 
 // Inverse of the self block Z(0)[A(s), A(s)] of each state s by Gauss-Jordan
 // elimination with partial pivoting in FP64 (one workgroup per state).
-template <typename S>
-__global__ void __launch_bounds__(256)
-selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a, double2* __restrict__ Minv,
-                         int* __restrict__ flag) {
-  extern __shared__ double2 aug[];  // [n_a][2 n_a], then column k [n_a]
-  __shared__ int piv_row;
-  double2* colk = aug + 2 * n_a * n_a;
-  const int st = blockIdx.x;
+// Gauss-Jordan inversion with partial pivoting of the n_a x n_a block held in
+// the left half of aug [n_a][2 n_a] (right half: identity), by one workgroup;
+// the inverse is left in the right half.  Returns false (and sets bit 8 of
+// flag) for a singular block; uniform over the workgroup.
+__device__ bool gj_invert(double2* aug, double2* colk, int n_a, int* piv_row, int* __restrict__ flag) {
   const int w = 2 * n_a;
-  const S* Z0 = nearb + (size_t)slot0 * n * n * 2;
-  for (int e = threadIdx.x; e < n_a * w; e += blockDim.x) {
-    const int i = e / w, j = e % w;
-    double2 v;
-    if (j < n_a) {
-      const size_t idx = (size_t)(st * n_a + i) * n + st * n_a + j;
-      v = make_double2((double)Z0[2 * idx], (double)Z0[2 * idx + 1]);
-    } else {
-      v = make_double2(j - n_a == i ? 1.0 : 0.0, 0.0);
-    }
-    aug[e] = v;
-  }
-  __syncthreads();
   for (int k = 0; k < n_a; ++k) {
     if (threadIdx.x == 0) {
       int p = k;
@@ -626,12 +610,12 @@ selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a,
           p = i;
         }
       }
-      piv_row = best > 0.0 ? p : -1;
+      *piv_row = best > 0.0 ? p : -1;
       if (best <= 0.0) atomicOr(flag, 8);
     }
     __syncthreads();
-    const int p = piv_row;
-    if (p < 0) return;
+    const int p = *piv_row;
+    if (p < 0) return false;
     if (p != k)
       for (int j = threadIdx.x; j < w; j += blockDim.x) {
         const double2 t = aug[k * w + j];
@@ -655,18 +639,90 @@ selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a,
     }
     __syncthreads();
   }
+  return true;
+}
+
+// Block-Jacobi inverses Z(0)[A(s), A(s)]^-1, one workgroup per state.
+// Dynamic LDS: (2 n_a^2 + n_a) double2.
+template <typename S>
+__global__ void __launch_bounds__(256)
+selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a, double2* __restrict__ Minv,
+                         int* __restrict__ flag) {
+  extern __shared__ double2 aug[];  // [n_a][2 n_a], then column k [n_a]
+  __shared__ int piv_row;
+  double2* colk = aug + 2 * n_a * n_a;
+  const int st = blockIdx.x;
+  const int w = 2 * n_a;
+  const S* Z0 = nearb + (size_t)slot0 * n * n * 2;
+  for (int e = threadIdx.x; e < n_a * w; e += blockDim.x) {
+    const int i = e / w, j = e % w;
+    double2 v;
+    if (j < n_a) {
+      const size_t idx = (size_t)(st * n_a + i) * n + st * n_a + j;
+      v = make_double2((double)Z0[2 * idx], (double)Z0[2 * idx + 1]);
+    } else {
+      v = make_double2(j - n_a == i ? 1.0 : 0.0, 0.0);
+    }
+    aug[e] = v;
+  }
+  __syncthreads();
+  if (!gj_invert(aug, colk, n_a, &piv_row, flag)) return;
   for (int e = threadIdx.x; e < n_a * n_a; e += blockDim.x) {
     const int i = e / n_a, j = e % n_a;
     Minv[(size_t)st * n_a * n_a + e] = aug[i * w + n_a + j];
   }
 }
 
-// out_u = Minv[s_u] in_u for every unit (user layout); OT is the output real type
+// Relaxed codebook: per unit u (of RHS b = blockIdx.y) the self block of the
+// blended operator, M_u = sum_{s,s'} w[u][s] w[u][s'] Z(0)[A(s), A(s')]
+// (transposed for the adjoint operator), inverted into Minv[global unit].
+template <typename S>
+__global__ void __launch_bounds__(256)
+relaxed_selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a, int n_states,
+                                 const RhsVec* __restrict__ rv, const double* __restrict__ wts, int transpose,
+                                 double2* __restrict__ Minv, int* __restrict__ flag) {
+  extern __shared__ double2 aug[];
+  __shared__ int piv_row;
+  double2* colk = aug + 2 * n_a * n_a;
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t u = blockIdx.x;
+  if (u * n_a >= r.N) return;  // uniform over the workgroup
+  const int64_t gu = r.off / n_a + u;  // global unit
+  const double* wu = wts + gu * n_states;
+  const int w = 2 * n_a;
+  const S* Z0 = nearb + (size_t)slot0 * n * n * 2;
+  for (int e = threadIdx.x; e < n_a * w; e += blockDim.x) {
+    const int i = e / w, j = e % w;
+    double2 v = make_double2(j - n_a == i ? 1.0 : 0.0, 0.0);
+    if (j < n_a) {
+      const int ri = transpose ? j : i, rj = transpose ? i : j;
+      v = make_double2(0.0, 0.0);
+      for (int s1 = 0; s1 < n_states; ++s1)
+        for (int s2 = 0; s2 < n_states; ++s2) {
+          const size_t idx = (size_t)(s1 * n_a + ri) * n + s2 * n_a + rj;
+          const double ww = wu[s1] * wu[s2];
+          v.x += ww * (double)Z0[2 * idx];
+          v.y += ww * (double)Z0[2 * idx + 1];
+        }
+    }
+    aug[e] = v;
+  }
+  __syncthreads();
+  if (!gj_invert(aug, colk, n_a, &piv_row, flag)) return;
+  for (int e = threadIdx.x; e < n_a * n_a; e += blockDim.x) {
+    const int i = e / n_a, j = e % n_a;
+    Minv[(size_t)gu * n_a * n_a + e] = aug[i * w + n_a + j];
+  }
+}
+
+// out_u = Minv[s_u] in_u for every unit (user layout); OT is the output real
+// type.  per_unit: Minv holds one block per global unit (relaxed codebooks)
 template <typename OT>
 __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
                                      const int64_t* __restrict__ soff, const RhsVec* __restrict__ rv, int n_a,
                                      int n_states, const double2* __restrict__ in, OT* __restrict__ out,
-                                     const int* __restrict__ live) {
+                                     const int* __restrict__ live, int per_unit) {
   if (live && *live == 0) return;
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
@@ -674,7 +730,7 @@ __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uin
   if (k >= r.N) return;
   const int64_t u = k / n_a;
   const int m = (int)(k % n_a);
-  const int s = min((int)states[soff[b] + u], n_states - 1);
+  const int64_t s = per_unit ? r.off / n_a + u : min((int)states[soff[b] + u], n_states - 1);
   const double2* M = Minv + ((size_t)s * n_a + m) * n_a;
   const double2* v = in + r.off + u * n_a;
   double2 acc = make_double2(0.0, 0.0);
@@ -759,7 +815,9 @@ struct Work {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, size_t mv_bytes,
+// n_blocks: block-Jacobi inverses held (one per state, or one per unit for
+// relaxed codebooks)
+Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_blocks, int m, size_t mv_bytes,
                  size_t lists_bytes, size_t lists64_bytes) {
   Work w{};
   const int B = bd.B;
@@ -783,7 +841,7 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_states, int m, 
   w.xs = (double2*)take(ut * 16);
   w.wn = (double*)take((size_t)B * 8);
   w.npart = (double*)take((size_t)B * ((maxN + 63) / 64 + 1) * 8);
-  w.Minv = (double2*)take((size_t)n_states * n_a * n_a * 16);
+  w.Minv = (double2*)take((size_t)n_blocks * n_a * n_a * 16);
   w.mv_partial = take(mv_bytes);
   w.lists = take(lists_bytes);
   w.lists64 = take(lists64_bytes);
@@ -818,6 +876,7 @@ struct GmresRun {
   bool pre = false;
   const double* wts = nullptr;  // relaxed retrieval weights (spectral stores)
   bool tr = false;              // with wts: the transposed operator
+  int pu = 0;                   // block-Jacobi inverses per global unit (relaxed) instead of per state
   int G = 1;  // displacement groups of the matvec (autotuned)
   int64_t maxN, ut;
   Work W;
@@ -868,7 +927,7 @@ struct GmresRun {
 
   void precond(const double2* in, double2* out) {
     hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff, W.rv,
-                       n_a, n_states, in, (double*)out, (const int*)nullptr);
+                       n_a, n_states, in, (double*)out, (const int*)nullptr, pu);
   }
 
   // Running-RHS counts of Arnoldi step j live in two slots used in turn: step
@@ -887,10 +946,10 @@ struct GmresRun {
     if (pre) {
       if (c64)
         hipLaunchKernelGGL(apply_precond_kernel<float>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr);
+                           W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr, pu);
       else
         hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (double*)W.xs, (const int*)nullptr);
+                           W.rv, n_a, n_states, v, (double*)W.xs, (const int*)nullptr, pu);
     } else if (c64) {
       hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs,
                          (const int*)nullptr);
@@ -936,19 +995,19 @@ struct GmresRun {
     if (pre && c64)
       hipLaunchKernelGGL((normalize_step_kernel<float, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
                          npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
-                         W.soff, n_a, n_states, (float*)W.xs);
+                         W.soff, n_a, n_states, (float*)W.xs, pu);
     else if (pre)
       hipLaunchKernelGGL((normalize_step_kernel<double, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
                          np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
-                         batch->states, W.soff, n_a, n_states, (double*)W.xs);
+                         batch->states, W.soff, n_a, n_states, (double*)W.xs, pu);
     else if (c64)
       hipLaunchKernelGGL((normalize_step_kernel<float, 1>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
                          npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
-                         W.soff, n_a, n_states, (float*)W.xs);
+                         W.soff, n_a, n_states, (float*)W.xs, pu);
     else
       hipLaunchKernelGGL((normalize_step_kernel<double, 0>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
                          np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
-                         batch->states, W.soff, n_a, n_states, (double*)nullptr);
+                         batch->states, W.soff, n_a, n_states, (double*)nullptr, pu);
     R3M_CHECK_HIP(hipGetLastError());
   }
 
@@ -1081,11 +1140,12 @@ struct GmresRun {
   }
 };
 
-size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m) {
+size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m,
+                   bool per_unit) {
   const int n_a = Z->n / Z->n_states;
   size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
   if (Z64) mv = std::max(mv, partials_and_x_bytes(bd, Z64, max_groups(bd)));
-  return layout_work(nullptr, bd, n_a, Z->n_states, m, mv, near_lists_bytes(Z, bd),
+  return layout_work(nullptr, bd, n_a, per_unit ? (int)bd.total_units : Z->n_states, m, mv, near_lists_bytes(Z, bd),
                      Z64 ? near_lists_bytes(Z64, bd) : 0).bytes;
 }
 
@@ -1106,7 +1166,8 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z6
     R3M_REQUIRE(opts->restart >= 1 && opts->restart <= 1024, R3M_ERR_INVALID_ARG, "restart out of range");
     if (batch->B == 0) return;
     const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, 0);
-    out = gmres_bytes(ctx, Z, Z64, bd, opts->restart);
+    out = gmres_bytes(ctx, Z, Z64, bd, opts->restart,
+                      opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI);
   });
   return rc == R3M_OK ? out : 0;
 }
@@ -1135,7 +1196,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, stream);
     const int m = opts->restart;
     const int n_a = Z->n / Z->n_states;
-    const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m);
+    const bool per_unit = opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI;
+    const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m, per_unit);
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "GMRES workspace too small");
 
     size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
@@ -1176,7 +1238,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     run.m = m;
     run.B = bd.B;
     run.s = stream;
-    run.W = layout_work((char*)work_dev, bd, n_a, Z->n_states, m, mv, near_lists_bytes(Z, bd),
+    run.W = layout_work((char*)work_dev, bd, n_a, per_unit ? (int)bd.total_units : Z->n_states, m, mv,
+                        near_lists_bytes(Z, bd),
                         refine ? near_lists_bytes(Z64, bd) : 0);
     run.Zsolve = Z;
     run.ut = (int64_t)bd.total_units * n_a;
@@ -1198,8 +1261,6 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     if (opts->relaxed_weights) {
       R3M_REQUIRE(store_is_spectral(Z) && (!refine || store_is_spectral(Z64)), R3M_ERR_UNSUPPORTED,
                   "relaxed retrieval needs spectral stores");
-      R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE, R3M_ERR_UNSUPPORTED,
-                  "relaxed retrieval runs without preconditioner");
     }
     // input checks on the device: state bytes and finite right-hand sides
     const int64_t maxU = run.maxN / n_a;
@@ -1213,7 +1274,18 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
       const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
       const int slot0 = Ny * (2 * Nx + 1) + Nx;
       const size_t lds = ((size_t)n_a * 2 * n_a + n_a) * sizeof(double2);
-      if (Z->near_dtype == R3M_C128)
+      if (per_unit) {  // relaxed codebook: the blended self block of every unit
+        run.pu = 1;
+        const dim3 ig((unsigned)maxU, bd.B);
+        if (Z->near_dtype == R3M_C128)
+          hipLaunchKernelGGL(relaxed_selfblock_inverse_kernel<double>, ig, dim3(256), lds, stream,
+                             (const double*)Z->near, slot0, Z->n, n_a, Z->n_states, (const RhsVec*)run.W.rv,
+                             opts->relaxed_weights, run.tr ? 1 : 0, run.W.Minv, run.W.counters + 1);
+        else
+          hipLaunchKernelGGL(relaxed_selfblock_inverse_kernel<float>, ig, dim3(256), lds, stream,
+                             (const float*)Z->near, slot0, Z->n, n_a, Z->n_states, (const RhsVec*)run.W.rv,
+                             opts->relaxed_weights, run.tr ? 1 : 0, run.W.Minv, run.W.counters + 1);
+      } else if (Z->near_dtype == R3M_C128)
         hipLaunchKernelGGL(selfblock_inverse_kernel<double>, dim3(Z->n_states), dim3(256), lds, stream,
                            (const double*)Z->near, slot0, Z->n, n_a, run.W.Minv, run.W.counters + 1);
       else

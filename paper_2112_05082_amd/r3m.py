@@ -465,10 +465,12 @@ def matvec_groups(ctx, store: Store, batch: Batch) -> int:
     return g
 
 
-def gmres_work_bytes(ctx, store: Store, batch: Batch, restart: int, store64: Store | None = None):
-    """store64: the refinement store the solve will use (None: no refinement)."""
+def gmres_work_bytes(ctx, store: Store, batch: Batch, restart: int, store64: Store | None = None,
+                     relaxed: bool = False, precond: int = PRECOND_NONE):
+    """store64: the refinement store the solve will use (None: no refinement);
+    relaxed + precond: a relaxed solve with block-Jacobi keeps one inverse per unit."""
     sc = store.c()
     s64 = store64.c() if store64 is not None else None
-    opts = GmresOptsC(1e-6, int(restart), 1, 0.0, 0, 0, 0, None, 0)
+    opts = GmresOptsC(1e-6, int(restart), 1, 0.0, 0, int(precond), 0, C.c_void_p(1 if relaxed else 0), 0)
     return load().r3m_gmres_work_bytes(ctx.handle, C.byref(sc), C.byref(s64) if s64 is not None else None,
                                        C.byref(batch.cs), C.byref(opts))

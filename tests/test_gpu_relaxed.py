@@ -126,11 +126,12 @@ def test_relaxed_transpose_identity_fullsize(lib, full):
     assert abs(plain - lhs) > 1e-9 * abs(lhs)
 
 
-@pytest.mark.parametrize("transpose", [False, True])
-def test_relaxed_solve_vs_oracle_lu(lib, transpose):
+@pytest.mark.parametrize("transpose,precond", [(False, 0), (True, 0), (False, 1), (True, 1)])
+def test_relaxed_solve_vs_oracle_lu(lib, transpose, precond):
     """GMRES on the relaxed operator (and on its transpose, the adjoint solve)
     against dense LU on the oracle's relaxed matrix, 3 x 3 x 2 RHS, complex128
-    spectra, GMRES to 1e-12: solutions within 1e-8 (cond x 1e-12)."""
+    spectra, GMRES to 1e-12, without and with the block-Jacobi preconditioner
+    of the blended self blocks: solutions within 1e-8 (cond x 1e-12)."""
     r3m, _, ctx = lib
     L, D = 3, 2
     blocks = efie.displacement_blocks(unit(1), D, D, K, extract=1)
@@ -145,9 +146,11 @@ def test_relaxed_solve_vs_oracle_lu(lib, transpose):
     bvec = cb.random_complex(2 * L * L * 40, 51)
     bd = to_dev(bvec)
     x = torch.zeros_like(bd)
-    work = torch.empty(r3m.gmres_work_bytes(ctx, store, batch, 60), dtype=torch.uint8, device=DEV)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, store, batch, 60, relaxed=True, precond=precond),
+                       dtype=torch.uint8, device=DEV)
     _, rep = r3m.r3m_gmres_solve(ctx, store, None, batch, bd, x, 1e-12, 60, 4000, work,
-                                 relaxed_weights=torch.from_numpy(W.reshape(-1, 2)).to(DEV), transpose=transpose)
+                                 relaxed_weights=torch.from_numpy(W.reshape(-1, 2)).to(DEV), transpose=transpose,
+                                 precond=precond)
     torch.cuda.synchronize()
     x = x.cpu().numpy()
     Zm = retrieval.macro_matrix(blocks, D, D, L)
@@ -158,7 +161,7 @@ def test_relaxed_solve_vs_oracle_lu(lib, transpose):
         sl = slice(b * L * L * 40, (b + 1) * L * L * 40)
         ref = np.linalg.solve(A, bvec[sl])
         errs.append(np.linalg.norm(x[sl] - ref) / np.linalg.norm(ref))
-    print(f"relaxed solve (transpose={transpose}): iters {[r[0] for r in rep]}, errors vs LU "
+    print(f"relaxed solve (transpose={transpose}, precond={precond}): iters {[r[0] for r in rep]}, errors vs LU "
           f"{['%.2e' % e for e in errs]}")
     assert all(r[3] for r in rep) and max(errs) <= 1e-8
 
