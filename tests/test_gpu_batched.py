@@ -175,3 +175,62 @@ def test_large_matvec(lib):
     print(f"large 128x128 x16: errors vs plain {['%.2e' % e for e in errs]}, max ACA error "
           f"{store.rel_err.max():.2e}, ranks at cap {(store.ranks == 12).sum()} of {len(store.ranks)}")
     assert max(errs) <= aca_bound(store)
+
+
+def test_batched_fullsize_solve_spectral(lib):
+    """The batched workload solved at full size on block spectra: 384 1-bit
+    codebooks (128 each at 32x32, 48x48, 64x64) x 4 angles = 1,536 RHS in one
+    solver call, complex64 spectra for the inner block-Jacobi GMRES(30) to
+    1e-3, FP64 refinement residual on complex128 spectra to 1e-6.  Every RHS
+    must converge; three RHS (one per array size) are re-solved on their own
+    in FP64 to 1e-10, and their RCS must agree to 1e-4."""
+    r3m, pipeline, ctx, geom = lib
+    w = batched_1bit(128)
+    rep_ = len(w.angles_deg)
+    batch = r3m.Batch.from_codebooks(w.codebooks, w.sizes, DEV, repeat=rep_)
+    assert batch.B == 1536
+    dense = pipeline.fill_blocks(ctx, geom, 63, r3m.C128, DEV)
+    s64 = pipeline.spectral_store(ctx, geom, 64, 2, r3m.C64, DEV, dense_c128=dense)
+    s128 = pipeline.spectral_store(ctx, geom, 64, 2, r3m.C128, DEV, dense_c128=dense)
+    del dense
+    torch.cuda.empty_cache()
+    N = batch.total_units * 40
+    inc = incidences(len(w.codebooks))
+    b = torch.zeros(N, dtype=torch.complex128, device=DEV)
+    r3m.r3m_plane_wave_rhs(ctx, geom, batch, inc, b)
+    x = torch.zeros_like(b)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, s64, batch, 30, s128), dtype=torch.uint8, device=DEV)
+    import time
+    torch.cuda.synchronize()
+    t0 = time.time()
+    _, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, 1e-3, 30, 3000, work, refine_tol=1e-6,
+                                 max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI)
+    torch.cuda.synchronize()
+    t_solve = time.time() - t0
+    del work
+    torch.cuda.empty_cache()
+    assert all(r[3] and r[2] <= 1e-6 for r in rep)
+    dirs = cb.phi0_cut(5.0)
+    sig = torch.zeros(batch.B * len(dirs), dtype=torch.float64, device=DEV)
+    r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
+    sig = sig.cpu().numpy().reshape(batch.B, -1)
+    errs = []
+    for r in (5, 512 + 6, 1024 + 7):
+        sub = sub_batch(r3m, w.codebooks, w.sizes, [r], rep_)
+        n1 = w.sizes[r // rep_] ** 2 * 40
+        o = int(batch.unit_off[r]) * 40
+        b1 = b[o:o + n1].clone()
+        x1 = torch.zeros_like(b1)
+        wk = torch.empty(r3m.gmres_work_bytes(ctx, s128, sub, 60), dtype=torch.uint8, device=DEV)
+        _, rep1 = r3m.r3m_gmres_solve(ctx, s128, None, sub, b1, x1, 1e-10, 60, 6000, wk,
+                                      precond=r3m.PRECOND_BLOCK_JACOBI)
+        s1 = torch.zeros(len(dirs), dtype=torch.float64, device=DEV)
+        r3m.r3m_rcs(ctx, geom, sub, x1, dirs, 1.0, s1)
+        torch.cuda.synchronize()
+        assert rep1[0][3]
+        errs.append(rel_l2(sig[r], s1.cpu().numpy()))
+    print(f"batched full-size spectral solve: {batch.B} RHS in {t_solve:.1f} s "
+          f"({batch.B / t_solve:.0f} solves/s), inner iters max {max(r[0] for r in rep)}, refine steps "
+          f"{sorted(set(r[1] for r in rep))}, max residual {max(r[2] for r in rep):.1e}; RCS errors vs FP64 "
+          f"{['%.1e' % e for e in errs]}")
+    assert max(errs) <= 1e-4
