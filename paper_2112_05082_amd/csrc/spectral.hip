@@ -18,7 +18,8 @@
 //
 // Layouts (complex, interleaved; grids row-major, k = gy * Gx + gx):
 //   spectra  Z^[m][n][Gy][Gx]     (m, n macro rows and columns)
-//   work     X[b][n][Gy][Gx], then Y[b][n][Gy][Gx]
+//   work     X[b][n][Gy][Gx], then Y[b][n][Gy][Gx], then the relaxed
+//            compaction's macro buffer [units][n]
 #include "matvec_internal.h"
 
 #include <algorithm>
