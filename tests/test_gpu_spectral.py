@@ -337,3 +337,43 @@ def test_spectral_empty_batch_and_errors(lib):
     assert code_of(lambda: r3m.r3m_build_spectral(ctx, dense, 80, Dx, Dy, r3m.SPEC_C64, small)) == \
         r3m.R3M_ERR_BUFFER_TOO_SMALL
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("relaxed_solve", [False, True])
+def test_spectral_graph_replays_match_eager(lib, relaxed_solve):
+    """Arnoldi blocks replayed from captured HIP graphs on a spectral store
+    (transform kernels with dynamic LDS, per-frequency products) give bitwise
+    the eager result on the first capture and on later replays, with eager
+    work and synchronisations in between; also for a relaxed transposed solve
+    with per-unit block-Jacobi."""
+    r3m, pipeline, ctx = lib
+    geom = r3m.UnitGeom.from_macro(unit(2), FREQ, 1)
+    L = 8
+    store = pipeline.spectral_store(ctx, geom, L, 0, r3m.C64 if not relaxed_solve else r3m.C128, DEV)
+    batch = r3m.Batch.from_codebooks([cb.uniform(L, 4, 21), cb.uniform(L, 4, 22)], [L, L], DEV)
+    b = torch.zeros(2 * L * L * 40, dtype=torch.complex128, device=DEV)
+    r3m.r3m_plane_wave_rhs(ctx, geom, batch, [[0.2, 0.1, 1.0], [0.0, 0.0, 1.0]], b)
+    w = None
+    if relaxed_solve:
+        lg = np.random.default_rng(23).standard_normal((2 * L * L, 4))
+        w = torch.from_numpy(np.exp(lg) / np.exp(lg).sum(axis=1, keepdims=True)).to(DEV)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, store, batch, 20, relaxed=relaxed_solve,
+                                            precond=r3m.PRECOND_BLOCK_JACOBI), dtype=torch.uint8, device=DEV)
+
+    def run(eager):
+        x = torch.zeros_like(b)
+        _, rep = r3m.r3m_gmres_solve(ctx, store, None, batch, b, x, 1e-8 if relaxed_solve else 1e-5, 20, 2000,
+                                     work, precond=r3m.PRECOND_BLOCK_JACOBI, eager=eager, relaxed_weights=w,
+                                     transpose=relaxed_solve)
+        torch.cuda.synchronize()
+        return x.cpu().numpy(), rep
+
+    x_e, rep_e = run(True)
+    assert all(r[3] for r in rep_e)
+    for _ in range(3):
+        x_g, rep_g = run(False)
+        assert np.array_equal(x_g, x_e) and [r[0] for r in rep_g] == [r[0] for r in rep_e]
+        matvec(r3m, ctx, store, batch, b.to(torch.complex64 if not relaxed_solve else torch.complex128),
+               r3m.C64 if not relaxed_solve else r3m.C128)
+    x_e2, _ = run(True)
+    assert np.array_equal(x_e2, x_e)
