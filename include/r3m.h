@@ -261,6 +261,39 @@ int r3m_relaxed_gradient(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
                          const double* dJ_dev, double* grad_dev, void* work_dev, size_t work_bytes,
                          hipStream_t stream);
 
+/* ------------------------------------------------- near-field block ILU -- */
+
+/* Incomplete LU of the retrieved near field (Sec. III-D: the preconditioner
+ * is built per codebook after retrieval; a factor of a retrieved matrix is
+ * not the retrieval of a factor).  Blocks are whole units (n_a x n_a); the
+ * pattern of unit i holds the units j at Chebyshev lattice distance
+ * max(|jx - ix|, |jy - iy|) <= radius, with A_ij = Z(p_i - p_j)[A(s_i), A(s_j)]
+ * read from the store's near blocks (so radius <= near_radius; 1 <= radius
+ * <= 3; n_a <= 64).  No fill is kept outside the pattern (ILU(0)); pivot
+ * blocks are inverted by Gauss-Jordan with partial pivoting in FP64.  Units
+ * are eliminated in multicolour order: unit (ix, iy) has colour
+ * (iy mod (r+1)) (r+1) + (ix mod (r+1)), colours in increasing order (units
+ * of one colour never share a pattern, so the order inside a colour does not
+ * matter).  Arithmetic in FP64, factors stored in the store's near precision.
+ *
+ * Factor buffer (r3m_ilu_bytes): per global unit g (unit_off[b] + iy Lx + ix)
+ * S = (2 radius + 1)^2 blocks; slot (ey + radius)(2 radius + 1) + ex + radius
+ * holds the block of the neighbour at offset (ex, ey): the multiplier L_gj
+ * (lower colour), the upper factor U_gj (higher colour), or the inverted
+ * pivot U_gg^-1 at offset 0; zero for neighbours outside the array.  Blocks
+ * are column-major: element (row, col) at col * n_a + row, complex double
+ * (C128 near store) or float (C64).  State bytes >= n_states are read as
+ * n_states - 1. */
+size_t r3m_ilu_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t radius);
+/* Factors every RHS's codebook.  R3M_ERR_NONFINITE for a singular pivot
+ * block; this call synchronises the stream. */
+int r3m_ilu_factor(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t radius, void* factors_dev,
+                   size_t factors_bytes, hipStream_t stream);
+/* y = U^-1 L^-1 x for every RHS (C128 [unit][n_a] vectors, x and y distinct;
+ * y is also the scratch of the forward solve).  Asynchronous. */
+int r3m_ilu_apply(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t radius, const void* factors_dev,
+                  size_t factors_bytes, const void* x_dev, void* y_dev, hipStream_t stream);
+
 /* ---------------------------------------------------------------- GMRES -- */
 
 typedef enum {
@@ -269,7 +302,12 @@ typedef enum {
    * inverse of each unit's self block Z(0)[A(s_u), A(s_u)] (one inverse per
    * coding state, FP64).  It is the diagonal-block special case of the
    * near-field block-ILU preconditioner built after retrieval (Sec. III-D). */
-  R3M_PRECOND_BLOCK_JACOBI = 1
+  R3M_PRECOND_BLOCK_JACOBI = 1,
+  /* right near-field block ILU(0) preconditioner (Sec. III-D), factored for
+   * every RHS's codebook from its retrieved near blocks (r3m_ilu_factor with
+   * opts->ilu_radius) and applied by colour-parallel triangular solves
+   * (r3m_ilu_apply).  Not available with relaxed_weights. */
+  R3M_PRECOND_BLOCK_ILU = 2
 } r3m_precond;
 
 typedef struct {
@@ -288,6 +326,8 @@ typedef struct {
                                     every unit (its transpose for the adjoint).  The work query
                                     only tests this pointer for NULL. */
   int32_t transpose;             /* with relaxed_weights: solve Z_k(w)^T x = b (the adjoint) */
+  int32_t ilu_radius;            /* R3M_PRECOND_BLOCK_ILU pattern radius (1..3, <= near_radius);
+                                    0 selects 1 */
 } r3m_gmres_opts;
 
 #define R3M_GMRES_EAGER 1

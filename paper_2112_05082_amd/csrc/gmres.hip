@@ -9,6 +9,7 @@
 // with fixed order (bitwise reproducible).  Convergence flags live on the
 // device and are read by the host once every few iterations.
 #include "matvec_internal.h"
+#include "small_dense.h"
 
 #include <algorithm>
 
@@ -590,58 +591,6 @@ __global__ void nonfinite_kernel(const double2* __restrict__ v, const RhsVec* __
   if (!(isfinite(t.x) && isfinite(t.y))) atomicOr(flag, 4);
 }
 
-// Inverse of the self block Z(0)[A(s), A(s)] of each state s by Gauss-Jordan
-// elimination with partial pivoting in FP64 (one workgroup per state).
-// Gauss-Jordan inversion with partial pivoting of the n_a x n_a block held in
-// the left half of aug [n_a][2 n_a] (right half: identity), by one workgroup;
-// the inverse is left in the right half.  Returns false (and sets bit 8 of
-// flag) for a singular block; uniform over the workgroup.
-__device__ bool gj_invert(double2* aug, double2* colk, int n_a, int* piv_row, int* __restrict__ flag) {
-  const int w = 2 * n_a;
-  for (int k = 0; k < n_a; ++k) {
-    if (threadIdx.x == 0) {
-      int p = k;
-      double best = -1.0;
-      for (int i = k; i < n_a; ++i) {
-        const double2 a = aug[i * w + k];
-        const double m = a.x * a.x + a.y * a.y;
-        if (m > best) {
-          best = m;
-          p = i;
-        }
-      }
-      *piv_row = best > 0.0 ? p : -1;
-      if (best <= 0.0) atomicOr(flag, 8);
-    }
-    __syncthreads();
-    const int p = *piv_row;
-    if (p < 0) return false;
-    if (p != k)
-      for (int j = threadIdx.x; j < w; j += blockDim.x) {
-        const double2 t = aug[k * w + j];
-        aug[k * w + j] = aug[p * w + j];
-        aug[p * w + j] = t;
-      }
-    __syncthreads();
-    const double2 d = aug[k * w + k];
-    const double dd = d.x * d.x + d.y * d.y;
-    const double2 inv = make_double2(d.x / dd, -d.y / dd);
-    __syncthreads();
-    for (int j = threadIdx.x; j < w; j += blockDim.x) aug[k * w + j] = cmul(aug[k * w + j], inv);
-    // multipliers of column k, read before any row update touches that column
-    for (int i = threadIdx.x; i < n_a; i += blockDim.x) colk[i] = aug[i * w + k];
-    __syncthreads();
-    for (int e = threadIdx.x; e < n_a * w; e += blockDim.x) {
-      const int i = e / w, j = e % w;
-      if (i == k) continue;
-      const double2 t = cmul(colk[i], aug[k * w + j]);
-      aug[e] = make_double2(aug[e].x - t.x, aug[e].y - t.y);
-    }
-    __syncthreads();
-  }
-  return true;
-}
-
 // Block-Jacobi inverses Z(0)[A(s), A(s)]^-1, one workgroup per state.
 // Dynamic LDS: (2 n_a^2 + n_a) double2.
 template <typename S>
@@ -792,6 +741,7 @@ struct Work {
   double2* pz;
   double2* xs;   // matvec input in the store precision
   double2* Minv;
+  void* ilu;  // near-field block ILU factors
   double* wn;
   double* npart;
   void* mv_partial;
@@ -818,7 +768,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // n_blocks: block-Jacobi inverses held (one per state, or one per unit for
 // relaxed codebooks)
 Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_blocks, int m, size_t mv_bytes,
-                 size_t lists_bytes, size_t lists64_bytes) {
+                 size_t lists_bytes, size_t lists64_bytes, size_t ilu_bytes) {
   Work w{};
   const int B = bd.B;
   int64_t maxN = 0;
@@ -842,6 +792,7 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_blocks, int m, 
   w.wn = (double*)take((size_t)B * 8);
   w.npart = (double*)take((size_t)B * ((maxN + 63) / 64 + 1) * 8);
   w.Minv = (double2*)take((size_t)n_blocks * n_a * n_a * 16);
+  w.ilu = take(ilu_bytes);
   w.mv_partial = take(mv_bytes);
   w.lists = take(lists_bytes);
   w.lists64 = take(lists64_bytes);
@@ -877,6 +828,7 @@ struct GmresRun {
   const double* wts = nullptr;  // relaxed retrieval weights (spectral stores)
   bool tr = false;              // with wts: the transposed operator
   int pu = 0;                   // block-Jacobi inverses per global unit (relaxed) instead of per state
+  int ilu_r = 0;                // > 0: the near-field block ILU(0) of this radius preconditions
   int G = 1;  // displacement groups of the matvec (autotuned)
   int64_t maxN, ut;
   Work W;
@@ -926,6 +878,10 @@ struct GmresRun {
   }
 
   void precond(const double2* in, double2* out) {
+    if (ilu_r) {
+      launch_ilu_apply(Zsolve, *bd, ilu_r, W.ilu, in, out, R3M_C128, nullptr, s, nullptr);
+      return;
+    }
     hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff, W.rv,
                        n_a, n_states, in, (double*)out, (const int*)nullptr, pu);
   }
@@ -943,7 +899,9 @@ struct GmresRun {
   bool input_in_xs(const r3m_store* Z) const { return pre || Z->near_dtype == R3M_C64; }
   void prepare_input(const r3m_store* Z, const double2* v) {
     const bool c64 = Z->near_dtype == R3M_C64;
-    if (pre) {
+    if (ilu_r) {  // W.w is free here: the forward solve's scratch
+      launch_ilu_apply(Z, *bd, ilu_r, W.ilu, v, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s, nullptr);
+    } else if (pre) {
       if (c64)
         hipLaunchKernelGGL(apply_precond_kernel<float>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
                            W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr, pu);
@@ -992,7 +950,15 @@ struct GmresRun {
     const dim3 ngrid(ceil_div((size_t)maxN, nthr), B);
     const size_t glds = (size_t)(2 * m + 2) * 16 + (size_t)m * 8;
     const bool c64 = Z->near_dtype == R3M_C64;
-    if (pre && c64)
+    if (ilu_r) {
+      // V_{j+1}, then the next step's input M^-1 V_{j+1} by the colour solves
+      // (W.w, the matvec output, is free once normalised)
+      hipLaunchKernelGGL((normalize_step_kernel<double, 0>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
+                         np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
+                         batch->states, W.soff, n_a, n_states, (double*)nullptr, pu);
+      launch_ilu_apply(Z, *bd, ilu_r, W.ilu, W.V + (int64_t)(j + 1) * ut, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s,
+                       run_slot(j));
+    } else if (pre && c64)
       hipLaunchKernelGGL((normalize_step_kernel<float, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
                          npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
                          W.soff, n_a, n_states, (float*)W.xs, pu);
@@ -1141,12 +1107,21 @@ struct GmresRun {
 };
 
 size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m,
-                   bool per_unit) {
+                   bool per_unit, int ilu_r) {
   const int n_a = Z->n / Z->n_states;
   size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
   if (Z64) mv = std::max(mv, partials_and_x_bytes(bd, Z64, max_groups(bd)));
   return layout_work(nullptr, bd, n_a, per_unit ? (int)bd.total_units : Z->n_states, m, mv, near_lists_bytes(Z, bd),
-                     Z64 ? near_lists_bytes(Z64, bd) : 0).bytes;
+                     Z64 ? near_lists_bytes(Z64, bd) : 0, ilu_r ? ilu_factor_bytes(Z, bd, ilu_r) : 0)
+      .bytes;
+}
+
+// the ILU radius a solve uses (0: no ILU), validated against the store
+int ilu_radius_of(const r3m_store* Z, const r3m_gmres_opts* opts) {
+  if (opts->precond != R3M_PRECOND_BLOCK_ILU) return 0;
+  const int r = opts->ilu_radius == 0 ? 1 : opts->ilu_radius;
+  validate_ilu(Z, r);
+  return r;
 }
 
 }  // namespace r3m
@@ -1167,7 +1142,7 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z6
     if (batch->B == 0) return;
     const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, 0);
     out = gmres_bytes(ctx, Z, Z64, bd, opts->restart,
-                      opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI);
+                      opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI, ilu_radius_of(Z, opts));
   });
   return rc == R3M_OK ? out : 0;
 }
@@ -1197,7 +1172,13 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     const int m = opts->restart;
     const int n_a = Z->n / Z->n_states;
     const bool per_unit = opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI;
-    const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m, per_unit);
+    R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE || opts->precond == R3M_PRECOND_BLOCK_JACOBI ||
+                    opts->precond == R3M_PRECOND_BLOCK_ILU,
+                R3M_ERR_INVALID_ARG, "unknown preconditioner");
+    R3M_REQUIRE(!(opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_ILU), R3M_ERR_UNSUPPORTED,
+                "the block ILU preconditioner does not take relaxed weights");
+    const int ilu_r = ilu_radius_of(Z, opts);
+    const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m, per_unit, ilu_r);
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "GMRES workspace too small");
 
     size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
@@ -1229,7 +1210,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     run.use_graph = !(opts->flags & R3M_GMRES_EAGER);
     run.graph_key = {(int64_t)(intptr_t)&bd, (int64_t)(intptr_t)batch->states, (int64_t)(intptr_t)work_dev,
                      (int64_t)m, (int64_t)opts->precond, (int64_t)bd.B, (int64_t)n_a,
-                     (int64_t)(intptr_t)opts->relaxed_weights, (int64_t)opts->transpose};
+                     (int64_t)(intptr_t)opts->relaxed_weights, (int64_t)opts->transpose, (int64_t)ilu_r};
     run.wts = opts->relaxed_weights;
     run.tr = opts->relaxed_weights && opts->transpose;
     run.bd = &bd;
@@ -1239,8 +1220,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     run.B = bd.B;
     run.s = stream;
     run.W = layout_work((char*)work_dev, bd, n_a, per_unit ? (int)bd.total_units : Z->n_states, m, mv,
-                        near_lists_bytes(Z, bd),
-                        refine ? near_lists_bytes(Z64, bd) : 0);
+                        near_lists_bytes(Z, bd), refine ? near_lists_bytes(Z64, bd) : 0,
+                        ilu_r ? ilu_factor_bytes(Z, bd, ilu_r) : 0);
     run.Zsolve = Z;
     run.ut = (int64_t)bd.total_units * n_a;
     run.maxN = 0;
@@ -1256,8 +1237,6 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     R3M_CHECK_HIP(hipMemcpyAsync(run.W.soff, soff.data(), soff.size() * 8, hipMemcpyHostToDevice, stream));
     R3M_CHECK_HIP(hipMemsetAsync(run.W.counters, 0, 256, stream));
 
-    R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE || opts->precond == R3M_PRECOND_BLOCK_JACOBI,
-                R3M_ERR_INVALID_ARG, "unknown preconditioner");
     if (opts->relaxed_weights) {
       R3M_REQUIRE(store_is_spectral(Z) && (!refine || store_is_spectral(Z64)), R3M_ERR_UNSUPPORTED,
                   "relaxed retrieval needs spectral stores");
@@ -1292,6 +1271,10 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
         hipLaunchKernelGGL(selfblock_inverse_kernel<float>, dim3(Z->n_states), dim3(256), lds, stream,
                            (const float*)Z->near, slot0, Z->n, n_a, run.W.Minv, run.W.counters + 1);
       R3M_CHECK_HIP(hipGetLastError());
+    } else if (ilu_r) {
+      run.pre = true;
+      run.ilu_r = ilu_r;
+      launch_ilu_factor(Z, bd, batch->states, ilu_r, run.W.ilu, run.W.counters + 1, stream);
     }
     // one read-back for the input checks and the preconditioner's pivots
     const int f = run.flag_check(14);

@@ -25,7 +25,7 @@ R3M_ERR_UNSUPPORTED = -6
 
 C128, C64, BF16X2, F16X2, SPEC_C64, SPEC_C128 = 0, 1, 2, 3, 4, 5
 BATCH_INDEX_READY = 1
-PRECOND_NONE, PRECOND_BLOCK_JACOBI = 0, 1
+PRECOND_NONE, PRECOND_BLOCK_JACOBI, PRECOND_BLOCK_ILU = 0, 1, 2
 
 EXPORTED = (
     "r3m_ctx_create", "r3m_ctx_destroy", "r3m_last_error", "r3m_version",
@@ -34,7 +34,7 @@ EXPORTED = (
     "r3m_spectral_bytes", "r3m_build_spectral", "r3m_relaxed_work_bytes", "r3m_relaxed_matvec",
     "r3m_relaxed_gradient_work_bytes", "r3m_relaxed_gradient", "r3m_relaxed_rhs", "r3m_relaxed_objective",
     "r3m_matvec_work_bytes", "r3m_retrieved_matvec", "r3m_matvec_groups",
-    "r3m_gmres_work_bytes", "r3m_gmres_solve",
+    "r3m_gmres_work_bytes", "r3m_gmres_solve", "r3m_ilu_bytes", "r3m_ilu_factor", "r3m_ilu_apply",
     "r3m_plane_wave_rhs", "r3m_rcs",
 )
 
@@ -76,6 +76,7 @@ class GmresOptsC(C.Structure):
         ("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
         ("refine_tol", C.c_double), ("max_refine", C.c_int32), ("precond", C.c_int32),
         ("flags", C.c_int32), ("relaxed_weights", C.c_void_p), ("transpose", C.c_int32),
+        ("ilu_radius", C.c_int32),
     ]
 
 
@@ -130,6 +131,9 @@ def load(path: str = LIB_PATH):
                                       C.POINTER(GmresOptsC)]),
         "r3m_gmres_solve": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(StoreC), C.POINTER(BatchC), vp, vp,
                                       C.POINTER(GmresOptsC), C.POINTER(GmresReportC), vp, sz, vp]),
+        "r3m_ilu_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(BatchC), i32]),
+        "r3m_ilu_factor": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), i32, vp, sz, vp]),
+        "r3m_ilu_apply": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), i32, vp, sz, vp, vp, vp]),
         "r3m_plane_wave_rhs": (C.c_int, [vp, C.POINTER(UnitGeomC), C.POINTER(BatchC), C.POINTER(C.c_double),
                                          vp, vp]),
         "r3m_rcs": (C.c_int, [vp, C.POINTER(UnitGeomC), C.POINTER(BatchC), vp, i32, C.POINTER(C.c_double),
@@ -390,9 +394,10 @@ def r3m_retrieved_matvec(ctx: Context, store: Store, batch: Batch, vec_dtype: in
 def r3m_gmres_solve(ctx: Context, store: Store, store64: Store | None, batch: Batch, b, x, tol: float,
                     restart: int, max_iter: int, work, refine_tol: float = 0.0, max_refine: int = 0,
                     stream=None, allow_not_converged: bool = False, precond: int = PRECOND_NONE,
-                    eager: bool = False, relaxed_weights=None, transpose: bool = False):
+                    eager: bool = False, relaxed_weights=None, transpose: bool = False, ilu_radius: int = 1):
     """relaxed_weights: float64 device tensor [total units][n_states] to solve
-    the relaxed system P(w)^T Z P(w) x = b (transpose: with Z^T)."""
+    the relaxed system P(w)^T Z P(w) x = b (transpose: with Z^T).
+    ilu_radius: pattern radius of PRECOND_BLOCK_ILU."""
     lib = load()
     _need_vec(b, batch, store.n // store.n_states, "b")
     _need_vec(x, batch, store.n // store.n_states, "x")
@@ -400,7 +405,7 @@ def r3m_gmres_solve(ctx: Context, store: Store, store64: Store | None, batch: Ba
     s64 = store64.c() if store64 is not None else None
     wp = C.c_void_p(relaxed_weights.data_ptr() if relaxed_weights is not None else 0)
     opts = GmresOptsC(float(tol), int(restart), int(max_iter), float(refine_tol), int(max_refine), int(precond),
-                      1 if eager else 0, wp, 1 if transpose else 0)
+                      1 if eager else 0, wp, 1 if transpose else 0, int(ilu_radius))
     rep = (GmresReportC * max(batch.B, 1))()
     rc = lib.r3m_gmres_solve(ctx.handle, C.byref(sc), C.byref(s64) if s64 is not None else None,
                              C.byref(batch.cs), C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()),
@@ -408,6 +413,31 @@ def r3m_gmres_solve(ctx: Context, store: Store, store64: Store | None, batch: Ba
                              _stream(stream))
     _check(rc, ctx.handle, allow=(R3M_ERR_NOT_CONVERGED,) if allow_not_converged else ())
     return rc, [(r.iters, r.refine_steps, r.rel_residual, bool(r.converged)) for r in rep[: batch.B]]
+
+
+def ilu_bytes(ctx: Context, store: Store, batch: Batch, radius: int) -> int:
+    sc = store.c()
+    return load().r3m_ilu_bytes(ctx.handle, C.byref(sc), C.byref(batch.cs), int(radius))
+
+
+def r3m_ilu_factor(ctx: Context, store: Store, batch: Batch, radius: int, factors, stream=None):
+    """Near-field block ILU(0) factors of every RHS's codebook into `factors`
+    (a device byte tensor of ilu_bytes(...))."""
+    sc = store.c()
+    _check(load().r3m_ilu_factor(ctx.handle, C.byref(sc), C.byref(batch.cs), int(radius),
+                                 C.c_void_p(factors.data_ptr()), factors.numel() * factors.element_size(),
+                                 _stream(stream)), ctx.handle)
+
+
+def r3m_ilu_apply(ctx: Context, store: Store, batch: Batch, radius: int, factors, x, y, stream=None):
+    """y = M^-1 x with the factors of r3m_ilu_factor (complex128 vectors)."""
+    n_a = store.n // store.n_states
+    _need_vec(x, batch, n_a, "x")
+    _need_vec(y, batch, n_a, "y")
+    sc = store.c()
+    _check(load().r3m_ilu_apply(ctx.handle, C.byref(sc), C.byref(batch.cs), int(radius),
+                                C.c_void_p(factors.data_ptr()), factors.numel() * factors.element_size(),
+                                C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), _stream(stream)), ctx.handle)
 
 
 def r3m_plane_wave_rhs(ctx: Context, geom: UnitGeom, batch: Batch, inc, b, stream=None):
@@ -466,11 +496,13 @@ def matvec_groups(ctx, store: Store, batch: Batch) -> int:
 
 
 def gmres_work_bytes(ctx, store: Store, batch: Batch, restart: int, store64: Store | None = None,
-                     relaxed: bool = False, precond: int = PRECOND_NONE):
+                     relaxed: bool = False, precond: int = PRECOND_NONE, ilu_radius: int = 1):
     """store64: the refinement store the solve will use (None: no refinement);
-    relaxed + precond: a relaxed solve with block-Jacobi keeps one inverse per unit."""
+    relaxed + precond: a relaxed solve with block-Jacobi keeps one inverse per unit;
+    PRECOND_BLOCK_ILU adds the factors of radius ilu_radius."""
     sc = store.c()
     s64 = store64.c() if store64 is not None else None
-    opts = GmresOptsC(1e-6, int(restart), 1, 0.0, 0, int(precond), 0, C.c_void_p(1 if relaxed else 0), 0)
+    opts = GmresOptsC(1e-6, int(restart), 1, 0.0, 0, int(precond), 0, C.c_void_p(1 if relaxed else 0), 0,
+                      int(ilu_radius))
     return load().r3m_gmres_work_bytes(ctx.handle, C.byref(sc), C.byref(s64) if s64 is not None else None,
                                        C.byref(batch.cs), C.byref(opts))
