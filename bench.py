@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_VALU_TFLOPS = 157.3
 RCS_TARGET = 1e-4
+PRECOND_NAMES = {0: "unpreconditioned", 1: "block-Jacobi", 2: "block-ILU(0) r={r}"}
 
 # HBM bytes of one r3m_retrieved_matvec call on this workload (complex128
 # vectors), from rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 summed over its
@@ -54,7 +55,9 @@ def parse():
     p.add_argument("--L", type=int, default=32)
     p.add_argument("--max-iter", type=int, default=6000)
     p.add_argument("--ref-tol", type=float, default=1e-10)
-    p.add_argument("--precond", type=int, default=1, help="0 none, 1 block-Jacobi (self blocks)")
+    p.add_argument("--precond", type=int, default=1,
+                   help="0 none, 1 block-Jacobi (self blocks), 2 near-field block ILU(0)")
+    p.add_argument("--ilu-radius", type=int, default=1, help="pattern radius of --precond 2")
     p.add_argument("--no-batched", action="store_true", help="skip the 1,536-RHS batched solve leg (about 40 s)")
     p.add_argument("--no-spectral", action="store_true",
                    help="skip the FFT-path legs (2-bit 32x32 spectral solve, 1-bit 128x128 x 16 refined solve)")
@@ -361,16 +364,18 @@ def main():
     # device buffers of a solve, allocated once per store (a serving loop reuses them)
     bufs = {}
 
-    def solve(st, tol, restart):
-        key = id(st)
+    def solve(st, tol, restart, pc=args.precond):
+        key = (id(st), pc)
         if key not in bufs:
             bufs[key] = (torch.zeros(N, dtype=torch.complex128, device=dev),
-                         torch.empty(r3m.gmres_work_bytes(ctx, st, batch, restart), dtype=torch.uint8, device=dev))
+                         torch.empty(r3m.gmres_work_bytes(ctx, st, batch, restart, precond=pc,
+                                                          ilu_radius=args.ilu_radius),
+                                     dtype=torch.uint8, device=dev))
         b, work = bufs[key]
         r3m.r3m_plane_wave_rhs(ctx, geom, batch, inc, b)
         x = torch.empty_like(b)
         _, rep = r3m.r3m_gmres_solve(ctx, st, None, batch, b, x, tol, restart, args.max_iter, work,
-                                     allow_not_converged=True, precond=args.precond)
+                                     allow_not_converged=True, precond=pc, ilu_radius=args.ilu_radius)
         sig = torch.empty(len(dirs), dtype=torch.float64, device=dev)
         r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
         return x, sig, rep
@@ -378,7 +383,7 @@ def main():
     # ---- reference: plain FP64 GPU path (dense complex128 store)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x_ref, sig_ref, rep_ref = solve(plain, args.ref_tol, args.restart)
+    x_ref, sig_ref, rep_ref = solve(plain, args.ref_tol, args.restart, pc=1)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     sig_ref = sig_ref.cpu().numpy()
@@ -459,7 +464,8 @@ def main():
         "dtype": "c64 store / f32 accumulate / f64 krylov",
         "data": "synthetic (seeded uniform 2-bit codebook, PEC patch units)",
         "config": {"workload": f"2-bit DCM {L}x{L}, near c64 |d|<=2 dense, far ACA tol 1e-4 c64, "
-                               f"block-Jacobi GMRES({args.restart}) tol {args.gmres_tol:g}, 360-direction RCS",
+                               f"{PRECOND_NAMES.get(args.precond, '?').format(r=args.ilu_radius)} "
+                               f"GMRES({args.restart}) tol {args.gmres_tol:g}, 360-direction RCS",
                    "macro_unknowns": L * L * n, "retrieved_unknowns": N},
         "matvec_gbps": byt / mv_s / 1e9,
         "matvec_hbm_frac": byt / mv_s / 1e9 / PEAK_HBM_GBS,

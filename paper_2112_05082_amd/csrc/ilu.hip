@@ -31,7 +31,6 @@ namespace r3m {
 
 namespace {
 
-constexpr int kIluMaxNa = 64;
 constexpr int kIluMaxRadius = 3;
 
 template <typename T>
@@ -85,7 +84,7 @@ ilu_fill_kernel(const T* __restrict__ near, int n, int Nx, int Ny, int n_a, int 
                 const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, int r,
                 typename Cx<T>::t2* __restrict__ F) {
   using T2 = typename Cx<T>::t2;
-  extern __shared__ unsigned char ilu_lds[];
+  extern __shared__ double2 ilu_lds[];  // typed: 16-byte aligned after any static LDS
   T2* tile = reinterpret_cast<T2*>(ilu_lds);  // [n_a][n_a + 1]
   const RhsDev R = rhs[blockIdx.y];
   const int S = (2 * r + 1) * (2 * r + 1);
@@ -122,28 +121,49 @@ ilu_fill_kernel(const T* __restrict__ near, int n, int Nx, int Ny, int n_a, int 
 }
 
 // One colour step of the factorisation: every unit i of colour `colour`
-// (one workgroup each) eliminates its lower-colour neighbours k in colour
-// order: L_ik = A_ik U_kk^-1, then A_ij -= L_ik U_kj for every neighbour j of
-// i of a colour above k's whose offset from k is in the pattern; finally the
-// pivot A_ii is inverted (Gauss-Jordan, FP64).  Rows of lower colours are
-// final when this launch runs.  Dynamic LDS (2 n_a^2 + n_a) double2.
-template <typename T>
-__global__ void __launch_bounds__(256)
-ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, int n_a,
-                  typename Cx<T>::t2* __restrict__ F, int* __restrict__ flag) {
+// (one workgroup of kFactorThreads threads each) eliminates its lower-colour neighbours
+// k in colour order: L_ik = A_ik U_kk^-1, then A_ij -= L_ik U_kj for every
+// neighbour j of i of a colour above k's whose offset from k is in the
+// pattern; finally the pivot A_ii is inverted (Gauss-Jordan, FP64).  Rows of
+// lower colours are final when this launch runs.  Each thread owns the same
+// kPer entries of every n_a x n_a product (column-major index q = tid + NT t),
+// so all of its global loads of a block are issued together.  Dynamic LDS
+// (2 n_a^2 + n_a) double2.
+constexpr int kFactorThreads = 512;
+
+template <typename T, int NA>
+__global__ void __launch_bounds__(kFactorThreads)
+ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, typename Cx<T>::t2* __restrict__ F,
+                  int* __restrict__ flag) {
   using T2 = typename Cx<T>::t2;
-  extern __shared__ unsigned char ilu_lds[];
+  constexpr int NT = kFactorThreads;
+  constexpr int n_a = NA, nn = NA * NA, kPer = (NA * NA + NT - 1) / NT;
+  extern __shared__ double2 ilu_lds[];  // typed: 16-byte aligned after any static LDS
   __shared__ int piv_row;
   const RhsDev R = rhs[blockIdx.y];
   int ix, iy;
   if (!colour_unit(R, r, colour, ncx, ix, iy)) return;
-  const int W = 2 * r + 1, S = W * W, nn = n_a * n_a;
+  const int W = 2 * r + 1, S = W * W;
+  const int tid = threadIdx.x;
   const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;
   T2* Fi = F + (size_t)g * S * nn;
   T2* Ls = reinterpret_cast<T2*>(ilu_lds);  // current multiplier, column-major
   T2* Bs = Ls + nn;                          // pivot inverse or U_kj, column-major
-  constexpr int kPer = (kIluMaxNa * kIluMaxNa + 255) / 256;
-  double2 acc[kPer];
+
+  // c[t] = sum_m Ls[row][m] Bs[m][col] for this thread's entries
+  auto product = [&](double2 (&c)[kPer]) {
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const int q = tid + t * NT;
+      double2 a = make_double2(0.0, 0.0);
+      if (q < nn) {
+        const int col = q / n_a, row = q % n_a;
+#pragma unroll 8
+        for (int m = 0; m < n_a; ++m) cmac(a, to_d2(Ls[m * n_a + row]), to_d2(Bs[col * n_a + m]));
+      }
+      c[t] = a;
+    }
+  };
 
   for (int ck = 0; ck < colour; ++ck) {
     for (int ek = 0; ek < S; ++ek) {
@@ -151,25 +171,21 @@ ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, in
       if (kx < 0 || kx >= R.Lx || ky < 0 || ky >= R.Ly || colour_of(kx, ky, r) != ck) continue;
       const T2* Fk = F + (size_t)(R.unit_off + (int64_t)ky * R.Lx + kx) * S * nn;
       // multiplier L_ik = A_ik D_k (D_k: k's inverted pivot, centre slot)
-      for (int q = threadIdx.x; q < nn; q += blockDim.x) {
-        Ls[q] = Fi[(size_t)ek * nn + q];
-        Bs[q] = Fk[(size_t)(S / 2) * nn + q];
-      }
-      __syncthreads();
 #pragma unroll
       for (int t = 0; t < kPer; ++t) {
-        const int q = threadIdx.x + t * 256;
-        double2 a = make_double2(0.0, 0.0);
+        const int q = tid + t * NT;
         if (q < nn) {
-          const int col = q / n_a, row = q % n_a;
-          for (int m = 0; m < n_a; ++m) cmac(a, to_d2(Ls[m * n_a + row]), to_d2(Bs[col * n_a + m]));
+          Ls[q] = Fi[(size_t)ek * nn + q];
+          Bs[q] = Fk[(size_t)(S / 2) * nn + q];
         }
-        acc[t] = a;
       }
+      __syncthreads();
+      double2 acc[kPer];
+      product(acc);
       __syncthreads();
 #pragma unroll
       for (int t = 0; t < kPer; ++t) {
-        const int q = threadIdx.x + t * 256;
+        const int q = tid + t * NT;
         if (q < nn) {
           const T2 v = from_d2<T2>(acc[t]);
           Ls[q] = v;
@@ -186,49 +202,71 @@ ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, in
         if (ox < -r || ox > r || oy < -r || oy > r) continue;
         __syncthreads();  // Bs free (and Ls complete)
         const int okj = (oy + r) * W + (ox + r);
-        for (int q = threadIdx.x; q < nn; q += blockDim.x) Bs[q] = Fk[(size_t)okj * nn + q];
+        T2 old[kPer];
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+          const int q = tid + t * NT;
+          if (q < nn) {
+            Bs[q] = Fk[(size_t)okj * nn + q];
+            old[t] = Fi[(size_t)ej * nn + q];
+          }
+        }
         __syncthreads();
-        for (int q = threadIdx.x; q < nn; q += blockDim.x) {
-          const int col = q / n_a, row = q % n_a;
-          double2 a = make_double2(0.0, 0.0);
-          for (int m = 0; m < n_a; ++m) cmac(a, to_d2(Ls[m * n_a + row]), to_d2(Bs[col * n_a + m]));
-          const double2 o = to_d2(Fi[(size_t)ej * nn + q]);
-          Fi[(size_t)ej * nn + q] = from_d2<T2>(make_double2(o.x - a.x, o.y - a.y));
+        product(acc);
+#pragma unroll
+        for (int t = 0; t < kPer; ++t) {
+          const int q = tid + t * NT;
+          if (q < nn) {
+            const double2 o = to_d2(old[t]);
+            Fi[(size_t)ej * nn + q] = from_d2<T2>(make_double2(o.x - acc[t].x, o.y - acc[t].y));
+          }
         }
       }
       __syncthreads();
     }
   }
-  // invert the pivot A_ii in FP64
-  __threadfence_block();
+  // invert the pivot A_ii in FP64 (its last update is this workgroup's own)
   __syncthreads();
   double2* aug = reinterpret_cast<double2*>(ilu_lds);  // [n_a][2 n_a], then a column
   double2* colk = aug + 2 * nn;
-  const int w2 = 2 * n_a;
+  constexpr int w2 = 2 * NA;
   const T2* Aii = Fi + (size_t)(S / 2) * nn;
-  for (int q = threadIdx.x; q < n_a * w2; q += blockDim.x) {
+  for (int q = tid; q < n_a * w2; q += NT) {
     const int row = q / w2, c = q % w2;
     aug[q] = c < n_a ? to_d2(Aii[(size_t)c * n_a + row]) : make_double2(c - n_a == row ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
-  if (!gj_invert(aug, colk, n_a, &piv_row, flag)) return;
+  if (!gj_invert<NA, NT>(aug, colk, &piv_row, flag)) return;
   T2* Dst = Fi + (size_t)(S / 2) * nn;
-  for (int q = threadIdx.x; q < nn; q += blockDim.x) {
+  for (int q = tid; q < nn; q += NT) {
     const int col = q / n_a, row = q % n_a;
     Dst[q] = from_d2<T2>(aug[row * w2 + n_a + col]);
   }
 }
 
+// launch shape of the triangular solves: waves per unit, and the parts each
+// neighbour block's columns are split into (work items dealt to the waves)
+#ifndef R3M_ILU_APPLY_WAVES
+#define R3M_ILU_APPLY_WAVES 8
+#endif
+#ifndef R3M_ILU_APPLY_PARTS
+#define R3M_ILU_APPLY_PARTS 2
+#endif
+constexpr int kApplyWaves = R3M_ILU_APPLY_WAVES;
+
 // Sum over the neighbour blocks of unit (ix, iy) whose colour is below
-// (lower != 0) or above `colour` of  B_ij v_j  (v: [unit][n_a] complex
-// double); the blocks are split over the workgroup's waves, lane = row.
-// Leaves the row sums in red[0][row] (LDS [4][64] double2).
-template <typename T2>
-__device__ inline void neighbour_sum(const RhsDev& R, int r, int colour, bool lower, int ix, int iy, int n_a,
-                                     const T2* __restrict__ Fi, const double2* __restrict__ v, double2* red) {
+// (lower) or above `colour` of  B_ij v_j  (v: [unit][n_a] complex double;
+// units of colour 0 are read from v0 instead).
+// Work items are (block, part of its columns), dealt to the workgroup's
+// waves in turn, lane = row.  Leaves the row sums in red[0..n_a) (LDS
+// [kApplyWaves][64] double2).
+template <int NA, typename T2>
+__device__ inline void neighbour_sum(const RhsDev& R, int r, int colour, bool lower, int ix, int iy,
+                                     const T2* __restrict__ Fi, const double2* __restrict__ v0,
+                                     const double2* __restrict__ v, double2* red) {
+  constexpr int n_a = NA, kParts = R3M_ILU_APPLY_PARTS, kCols = NA / kParts;
   const int W = 2 * r + 1, S = W * W, nn = n_a * n_a;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int nw = blockDim.x / 64;
   double2 acc = make_double2(0.0, 0.0);
   int item = 0;
   for (int e = 0; e < S; ++e) {
@@ -236,18 +274,22 @@ __device__ inline void neighbour_sum(const RhsDev& R, int r, int colour, bool lo
     if (jx < 0 || jx >= R.Lx || jy < 0 || jy >= R.Ly) continue;
     const int cj = colour_of(jx, jy, r);
     if (lower ? cj >= colour : cj <= colour) continue;
-    if (item++ % nw != wave) continue;
-    if (lane < n_a) {
-      const T2* Bk = Fi + (size_t)e * nn;
-      const double2* vj = v + (size_t)(R.unit_off + (int64_t)jy * R.Lx + jx) * n_a;
-      for (int c = 0; c < n_a; ++c) cmac(acc, to_d2(Bk[(size_t)c * n_a + lane]), vj[c]);
+    for (int part = 0; part < kParts; ++part) {
+      if (item++ % kApplyWaves != wave) continue;
+      if (lane < n_a) {
+        const T2* Bk = Fi + (size_t)e * nn + (size_t)part * kCols * n_a;
+        const double2* vj = (cj == 0 ? v0 : v) + (size_t)(R.unit_off + (int64_t)jy * R.Lx + jx) * n_a + part * kCols;
+#pragma unroll
+        for (int c = 0; c < kCols; ++c) cmac(acc, to_d2(Bk[(size_t)c * n_a + lane]), vj[c]);
+      }
     }
   }
   red[wave * 64 + lane] = acc;
   __syncthreads();
   if (wave == 0) {
     double2 s = red[lane];
-    for (int q = 1; q < nw; ++q) {
+#pragma unroll
+    for (int q = 1; q < kApplyWaves; ++q) {
       s.x += red[q * 64 + lane].x;
       s.y += red[q * 64 + lane].y;
     }
@@ -256,62 +298,23 @@ __device__ inline void neighbour_sum(const RhsDev& R, int r, int colour, bool lo
   __syncthreads();
 }
 
-// Forward step of colour `colour`: z_i = in_i - sum over lower neighbours k
-// of L_ik z_k.  One workgroup (4 waves) per unit of the colour.
-template <typename T>
-__global__ void __launch_bounds__(256)
-ilu_forward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, int n_a,
-                   const typename Cx<T>::t2* __restrict__ F, const double2* __restrict__ in, double2* __restrict__ z,
-                   const int* __restrict__ live) {
-  __shared__ double2 red[4 * 64];
-  if (live && *live == 0) return;
-  const RhsDev R = rhs[blockIdx.y];
-  int ix, iy;
-  if (!colour_unit(R, r, colour, ncx, ix, iy)) return;
-  const int S = (2 * r + 1) * (2 * r + 1);
-  const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;
-  neighbour_sum(R, r, colour, true, ix, iy, n_a, F + (size_t)g * S * n_a * n_a, z, red);
-  if (threadIdx.x < n_a) {
-    const double2 a = in[g * n_a + threadIdx.x], s = red[threadIdx.x];
-    z[g * n_a + threadIdx.x] = make_double2(a.x - s.x, a.y - s.y);
-  }
-}
-
-// Backward step of colour `colour`: x_i = U_ii^-1 (z_i - sum over upper
-// neighbours j of U_ij x_j), written over z_i (x_j of higher colours are
-// already there) and, when out is given, into out (OT: float or double).
-template <typename T, typename OT>
-__global__ void __launch_bounds__(256)
-ilu_backward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, int n_a,
-                    const typename Cx<T>::t2* __restrict__ F, double2* __restrict__ z, OT* __restrict__ out,
-                    const int* __restrict__ live) {
-  using T2 = typename Cx<T>::t2;
-  __shared__ double2 red[4 * 64];
-  __shared__ double2 t[64];
-  if (live && *live == 0) return;
-  const RhsDev R = rhs[blockIdx.y];
-  int ix, iy;
-  if (!colour_unit(R, r, colour, ncx, ix, iy)) return;
-  const int S = (2 * r + 1) * (2 * r + 1), nn = n_a * n_a;
-  const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;
-  const T2* Fi = F + (size_t)g * S * nn;
-  neighbour_sum(R, r, colour, false, ix, iy, n_a, Fi, z, red);
-  if (threadIdx.x < n_a) {
-    const double2 a = z[g * n_a + threadIdx.x], s = red[threadIdx.x];
-    t[threadIdx.x] = make_double2(a.x - s.x, a.y - s.y);
-  }
-  __syncthreads();
-  // x_i = D_i t, the columns of D_i split over the waves
-  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, nw = blockDim.x / 64;
-  const T2* D = Fi + (size_t)(S / 2) * nn;
+// x_i = D_i t (t: LDS [64]) into z_i and, when given, out_i (OT: float or
+// double); the columns of D_i are dealt to the waves.
+template <int NA, typename T2, typename OT>
+__device__ inline void pivot_solve(const T2* __restrict__ D, const double2* t, double2* red, int64_t g,
+                                   double2* __restrict__ z, OT* __restrict__ out) {
+  constexpr int n_a = NA;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   double2 acc = make_double2(0.0, 0.0);
   if (lane < n_a)
-    for (int c = wave; c < n_a; c += nw) cmac(acc, to_d2(D[(size_t)c * n_a + lane]), t[c]);
+#pragma unroll
+    for (int c = wave; c < n_a; c += kApplyWaves) cmac(acc, to_d2(D[(size_t)c * n_a + lane]), t[c]);
   red[wave * 64 + lane] = acc;
   __syncthreads();
   if (wave == 0 && lane < n_a) {
     double2 s = red[lane];
-    for (int q = 1; q < nw; ++q) {
+#pragma unroll
+    for (int q = 1; q < kApplyWaves; ++q) {
       s.x += red[q * 64 + lane].x;
       s.y += red[q * 64 + lane].y;
     }
@@ -321,6 +324,68 @@ ilu_backward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, 
       out[2 * (g * n_a + lane) + 1] = (OT)s.y;
     }
   }
+}
+
+// Forward step of colour `colour` (>= 1; colour 0 has z = in and is never
+// stored): z_i = in_i - sum over lower neighbours k of L_ik z_k.  For the last
+// colour (no upper neighbours) the backward step follows in the same launch:
+// x_i = U_ii^-1 z_i.  One workgroup per unit of the colour.
+template <typename T, int NA, typename OT>
+__global__ void __launch_bounds__(64 * kApplyWaves)
+ilu_forward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, int last,
+                   const typename Cx<T>::t2* __restrict__ F, const double2* __restrict__ in, double2* __restrict__ z,
+                   OT* __restrict__ out, const int* __restrict__ live) {
+  constexpr int n_a = NA;
+  __shared__ double2 red[kApplyWaves * 64];
+  __shared__ double2 t[64];
+  if (live && *live == 0) return;
+  const RhsDev R = rhs[blockIdx.y];
+  int ix, iy;
+  if (!colour_unit(R, r, colour, ncx, ix, iy)) return;
+  const int S = (2 * r + 1) * (2 * r + 1), nn = n_a * n_a;
+  const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;
+  const typename Cx<T>::t2* Fi = F + (size_t)g * S * nn;
+  neighbour_sum<NA>(R, r, colour, true, ix, iy, Fi, in, z, red);
+  if (threadIdx.x < n_a) {
+    const double2 a = in[g * n_a + threadIdx.x], s = red[threadIdx.x];
+    const double2 zi = make_double2(a.x - s.x, a.y - s.y);
+    if (last)
+      t[threadIdx.x] = zi;
+    else
+      z[g * n_a + threadIdx.x] = zi;
+  }
+  if (last) {
+    __syncthreads();
+    pivot_solve<NA>(Fi + (size_t)(S / 2) * nn, t, red, g, z, out);
+  }
+}
+
+// Backward step of colour `colour`: x_i = U_ii^-1 (z_i - sum over upper
+// neighbours j of U_ij x_j), written over z_i (x_j of higher colours are
+// already there; z_i of colour 0 is in_i) and, when out is given, into out.
+template <typename T, int NA, typename OT>
+__global__ void __launch_bounds__(64 * kApplyWaves)
+ilu_backward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx,
+                    const typename Cx<T>::t2* __restrict__ F, const double2* __restrict__ in, double2* __restrict__ z,
+                    OT* __restrict__ out, const int* __restrict__ live) {
+  using T2 = typename Cx<T>::t2;
+  constexpr int n_a = NA;
+  __shared__ double2 red[kApplyWaves * 64];
+  __shared__ double2 t[64];
+  if (live && *live == 0) return;
+  const RhsDev R = rhs[blockIdx.y];
+  int ix, iy;
+  if (!colour_unit(R, r, colour, ncx, ix, iy)) return;
+  const int S = (2 * r + 1) * (2 * r + 1), nn = n_a * n_a;
+  const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;
+  const T2* Fi = F + (size_t)g * S * nn;
+  neighbour_sum<NA>(R, r, colour, false, ix, iy, Fi, z, z, red);
+  if (threadIdx.x < n_a) {
+    const double2 a = (colour == 0 ? in : z)[g * n_a + threadIdx.x], s = red[threadIdx.x];
+    t[threadIdx.x] = make_double2(a.x - s.x, a.y - s.y);
+  }
+  __syncthreads();
+  pivot_solve<NA>(Fi + (size_t)(S / 2) * nn, t, red, g, z, out);
 }
 
 int colour_cols(const BatchDesc& bd, int r) {
@@ -334,21 +399,31 @@ int colour_rows(const BatchDesc& bd, int r) {
   return (my + r) / (r + 1);
 }
 
-template <typename T, typename OT>
-void apply_typed(const r3m_store* Z, const BatchDesc& bd, int r, const void* F, const double2* in, double2* z,
-                 OT* out, hipStream_t s, const int* live) {
+template <typename T, int NA, typename OT>
+void apply_typed(const BatchDesc& bd, int r, const void* F, const double2* in, double2* z, OT* out, hipStream_t s,
+                 const int* live) {
   using T2 = typename Cx<T>::t2;
-  const int n_a = Z->n / Z->n_states;
   const int ncx = colour_cols(bd, r), ncy = colour_rows(bd, r);
   const dim3 grid((unsigned)(ncx * ncy), (unsigned)bd.B);
   const int nc = (r + 1) * (r + 1);
-  for (int c = 0; c < nc; ++c)
-    hipLaunchKernelGGL(ilu_forward_kernel<T>, grid, dim3(256), 0, s, bd.rhs, r, c, ncx, n_a, (const T2*)F, in, z,
-                       live);
-  for (int c = nc - 1; c >= 0; --c)
-    hipLaunchKernelGGL((ilu_backward_kernel<T, OT>), grid, dim3(256), 0, s, bd.rhs, r, c, ncx, n_a, (const T2*)F,
-                       z, out, live);
+  // colours 1 .. nc-1 forward (the last one also solves its pivots), then
+  // nc-2 .. 0 backward
+  for (int c = 1; c < nc; ++c)
+    hipLaunchKernelGGL((ilu_forward_kernel<T, NA, OT>), grid, dim3(64 * kApplyWaves), 0, s, bd.rhs, r, c, ncx,
+                       c == nc - 1 ? 1 : 0, (const T2*)F, in, z, out, live);
+  for (int c = nc - 2; c >= 0; --c)
+    hipLaunchKernelGGL((ilu_backward_kernel<T, NA, OT>), grid, dim3(64 * kApplyWaves), 0, s, bd.rhs, r, c, ncx,
+                       (const T2*)F, in, z, out, live);
   R3M_CHECK_HIP(hipGetLastError());
+}
+
+template <typename T, typename OT>
+void apply_na(const r3m_store* Z, const BatchDesc& bd, int r, const void* F, const double2* in, double2* z, OT* out,
+              hipStream_t s, const int* live) {
+  if (Z->n / Z->n_states == 40)
+    apply_typed<T, 40, OT>(bd, r, F, in, z, out, s, live);
+  else
+    apply_typed<T, 64, OT>(bd, r, F, in, z, out, s, live);
 }
 
 template <typename T>
@@ -364,8 +439,12 @@ void factor_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states
   const int ncx = colour_cols(bd, r), ncy = colour_rows(bd, r);
   const dim3 grid((unsigned)(ncx * ncy), (unsigned)bd.B);
   const size_t lds = ((size_t)2 * n_a * n_a + n_a) * sizeof(double2);
-  for (int c = 0; c < (r + 1) * (r + 1); ++c)
-    hipLaunchKernelGGL(ilu_factor_kernel<T>, grid, dim3(256), lds, s, bd.rhs, r, c, ncx, n_a, (T2*)F, flag);
+  for (int c = 0; c < (r + 1) * (r + 1); ++c) {
+    if (n_a == 40)
+      hipLaunchKernelGGL((ilu_factor_kernel<T, 40>), grid, dim3(kFactorThreads), lds, s, bd.rhs, r, c, ncx, (T2*)F, flag);
+    else
+      hipLaunchKernelGGL((ilu_factor_kernel<T, 64>), grid, dim3(kFactorThreads), lds, s, bd.rhs, r, c, ncx, (T2*)F, flag);
+  }
   R3M_CHECK_HIP(hipGetLastError());
 }
 
@@ -375,7 +454,7 @@ void validate_ilu(const r3m_store* Z, int radius) {
   const int n_a = Z->n / Z->n_states;
   R3M_REQUIRE(radius >= 1 && radius <= kIluMaxRadius, R3M_ERR_INVALID_ARG, "ILU radius must be in 1..3");
   R3M_REQUIRE(radius <= Z->near_radius, R3M_ERR_INVALID_ARG, "ILU radius exceeds the store's near radius");
-  R3M_REQUIRE(n_a <= kIluMaxNa, R3M_ERR_UNSUPPORTED, "ILU supports at most 64 active RWG per unit");
+  R3M_REQUIRE(n_a == 40 || n_a == 64, R3M_ERR_UNSUPPORTED, "ILU kernels are built for 40 or 64 active RWG per unit");
 }
 
 size_t ilu_factor_bytes(const r3m_store* Z, const BatchDesc& bd, int radius) {
@@ -397,14 +476,14 @@ void launch_ilu_apply(const r3m_store* Z, const BatchDesc& bd, int radius, const
   const bool d = Z->near_dtype == R3M_C128;
   if (out_type == R3M_C64) {
     if (d)
-      apply_typed<double, float>(Z, bd, radius, F, in, z, (float*)out, s, live);
+      apply_na<double, float>(Z, bd, radius, F, in, z, (float*)out, s, live);
     else
-      apply_typed<float, float>(Z, bd, radius, F, in, z, (float*)out, s, live);
+      apply_na<float, float>(Z, bd, radius, F, in, z, (float*)out, s, live);
   } else {
     if (d)
-      apply_typed<double, double>(Z, bd, radius, F, in, z, (double*)out, s, live);
+      apply_na<double, double>(Z, bd, radius, F, in, z, (double*)out, s, live);
     else
-      apply_typed<float, double>(Z, bd, radius, F, in, z, (double*)out, s, live);
+      apply_na<float, double>(Z, bd, radius, F, in, z, (double*)out, s, live);
   }
 }
 

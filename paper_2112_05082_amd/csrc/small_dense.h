@@ -8,17 +8,25 @@ __device__ inline double2 dense_cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Gauss-Jordan inversion with partial pivoting of the n_a x n_a block held in
-// the left half of aug [n_a][2 n_a] (right half: identity), by one workgroup;
-// the inverse is left in the right half.  Returns false (and sets bit 8 of
-// flag) for a singular block; uniform over the workgroup.
-__device__ inline bool gj_invert(double2* aug, double2* colk, int n_a, int* piv_row, int* __restrict__ flag) {
-  const int w = 2 * n_a;
-  for (int k = 0; k < n_a; ++k) {
-    if (threadIdx.x == 0) {
-      int p = k;
+// Gauss-Jordan inversion with partial pivoting of the NA x NA block held in
+// the left half of aug [NA][2 NA] (right half: identity), by one workgroup of
+// NT threads; the inverse is left in the right half.  The pivot of column k
+// is the row of largest modulus at or below k (the lowest such row on ties),
+// found by wave 0 with a butterfly reduction.  colk: NA double2 of LDS.
+// Returns false (and sets bit 8 of flag) for a singular block; uniform over
+// the workgroup.
+template <int NA, int NT>
+__device__ inline bool gj_invert(double2* aug, double2* colk, int* piv_row, int* __restrict__ flag) {
+  constexpr int w = 2 * NA;
+  constexpr int G = NT / w;                   // row groups (one column per thread)
+  constexpr int kRows = (NA + G - 1) / G;     // rows per thread
+  constexpr int kChunk = kRows < 7 ? kRows : 7;
+  const int tid = threadIdx.x;
+  for (int k = 0; k < NA; ++k) {
+    if (tid < 64) {
       double best = -1.0;
-      for (int i = k; i < n_a; ++i) {
+      int p = NA;
+      for (int i = k + tid; i < NA; i += 64) {
         const double2 a = aug[i * w + k];
         const double m = a.x * a.x + a.y * a.y;
         if (m > best) {
@@ -26,36 +34,69 @@ __device__ inline bool gj_invert(double2* aug, double2* colk, int n_a, int* piv_
           p = i;
         }
       }
-      *piv_row = best > 0.0 ? p : -1;
-      if (best <= 0.0) atomicOr(flag, 8);
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ob = __shfl_xor(best, off);
+        const int op = __shfl_xor(p, off);
+        if (ob > best || (ob == best && op < p)) {
+          best = ob;
+          p = op;
+        }
+      }
+      if (tid == 0) {
+        *piv_row = best > 0.0 ? p : -1;
+        if (!(best > 0.0)) atomicOr(flag, 8);
+      }
     }
     __syncthreads();
     const int p = *piv_row;
     if (p < 0) return false;
-    if (p != k)
-      for (int j = threadIdx.x; j < w; j += blockDim.x) {
-        const double2 t = aug[k * w + j];
-        aug[k * w + j] = aug[p * w + j];
-        aug[p * w + j] = t;
-      }
-    __syncthreads();
-    const double2 d = aug[k * w + k];
+    const double2 d = aug[p * w + k];
     const double dd = d.x * d.x + d.y * d.y;
     const double2 inv = make_double2(d.x / dd, -d.y / dd);
+    __syncthreads();  // every thread holds the pivot before rows move
+    // rows k and p exchange; the new row k is scaled by the inverse pivot
+    for (int j = tid; j < w; j += NT) {
+      const double2 a = aug[k * w + j], b = aug[p * w + j];
+      aug[k * w + j] = dense_cmul(b, inv);
+      if (p != k) aug[p * w + j] = a;
+    }
     __syncthreads();
-    for (int j = threadIdx.x; j < w; j += blockDim.x) aug[k * w + j] = dense_cmul(aug[k * w + j], inv);
     // multipliers of column k, read before any row update touches that column
-    for (int i = threadIdx.x; i < n_a; i += blockDim.x) colk[i] = aug[i * w + k];
+    for (int i = tid; i < NA; i += NT) colk[i] = aug[i * w + k];
     __syncthreads();
-    for (int e = threadIdx.x; e < n_a * w; e += blockDim.x) {
-      const int i = e / w, j = e % w;
-      if (i == k) continue;
-      const double2 t = dense_cmul(colk[i], aug[k * w + j]);
-      aug[e] = make_double2(aug[e].x - t.x, aug[e].y - t.y);
+    // elimination: thread (g, j) updates column j of rows g, g + G, ...; all of
+    // its operands are read before any of its writes
+    if (tid < G * w) {
+      const int j = tid % w, g = tid / w;
+      const double2 pj = aug[k * w + j];
+      for (int q0 = 0; q0 < kRows; q0 += kChunk) {
+        double2 v[kChunk], c[kChunk];
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+          const int i = g + (q0 + q) * G;
+          if (i < NA) {
+            v[q] = aug[i * w + j];
+            c[q] = colk[i];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kChunk; ++q) {
+          const int i = g + (q0 + q) * G;
+          if (i < NA && i != k) {
+            const double2 u = dense_cmul(c[q], pj);
+            aug[i * w + j] = make_double2(v[q].x - u.x, v[q].y - u.y);
+          }
+        }
+      }
     }
     __syncthreads();
   }
   return true;
+}
+
+// gj_invert for the unit sizes the kernels are built for (40 or 64), 256 threads
+__device__ inline bool gj_invert_na(double2* aug, double2* colk, int n_a, int* piv_row, int* __restrict__ flag) {
+  return n_a == 40 ? gj_invert<40, 256>(aug, colk, piv_row, flag) : gj_invert<64, 256>(aug, colk, piv_row, flag);
 }
 
 }  // namespace r3m
