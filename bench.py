@@ -6,8 +6,9 @@ The global matrix is stored as 25 dense complex-FP32 near blocks
 (Chebyshev |d| <= 2) plus 3,944 ACA far blocks (tol 1e-4, complex FP32).  One
 seeded uniform-random codebook at normal incidence.
 
-A step is one whole retrieved solve: plane-wave excitation, right
-block-Jacobi preconditioned GMRES (FP64 Krylov vectors and rotations,
+A step is one whole retrieved solve: plane-wave excitation, the codebook's
+near-field block ILU(0) (radius 1, factored per codebook after retrieval),
+right-preconditioned GMRES (FP64 Krylov vectors and rotations,
 complex-FP32 store and accumulation in the matvec), bistatic RCS on a
 1-degree phi = 0 cut.  Its RCS is checked against
 the plain FP64 GPU path (all 3,969 blocks dense complex128); a step counts
@@ -55,10 +56,12 @@ def parse():
     p.add_argument("--L", type=int, default=32)
     p.add_argument("--max-iter", type=int, default=6000)
     p.add_argument("--ref-tol", type=float, default=1e-10)
-    p.add_argument("--precond", type=int, default=1,
+    p.add_argument("--precond", type=int, default=2,
                    help="0 none, 1 block-Jacobi (self blocks), 2 near-field block ILU(0)")
     p.add_argument("--ilu-radius", type=int, default=1, help="pattern radius of --precond 2")
     p.add_argument("--no-batched", action="store_true", help="skip the 1,536-RHS batched solve leg (about 40 s)")
+    p.add_argument("--no-sweep", action="store_true",
+                   help="skip the preconditioner study (iterations over Bernoulli p at 16x16)")
     p.add_argument("--no-spectral", action="store_true",
                    help="skip the FFT-path legs (2-bit 32x32 spectral solve, 1-bit 128x128 x 16 refined solve)")
     return p.parse_args()
@@ -162,13 +165,15 @@ def spectral_leg(ctx, geom, batch, dense, sig_ref, dirs, inc, N, args):
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     b = torch.zeros(N, dtype=torch.complex128, device=dev)
-    work = torch.empty(r3m.gmres_work_bytes(ctx, spec, batch, args.restart), dtype=torch.uint8, device=dev)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, spec, batch, args.restart, precond=args.precond,
+                                            ilu_radius=args.ilu_radius), dtype=torch.uint8, device=dev)
 
     def solve():
         r3m.r3m_plane_wave_rhs(ctx, geom, batch, inc, b)
         x = torch.empty_like(b)
         _, rep = r3m.r3m_gmres_solve(ctx, spec, None, batch, b, x, args.gmres_tol, args.restart, args.max_iter,
-                                     work, allow_not_converged=True, precond=args.precond)
+                                     work, allow_not_converged=True, precond=args.precond,
+                                     ilu_radius=args.ilu_radius)
         sig = torch.empty(len(dirs), dtype=torch.float64, device=dev)
         r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
         return x, sig, rep
@@ -226,8 +231,9 @@ def large_leg(ctx, args):
     work = torch.empty(r3m.gmres_work_bytes(ctx, s64, batch, restart, s128), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # block-Jacobi: per-RHS ILU factors of 16 x 128 x 128 units would hold 30 GB
     _, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, 1e-3, restart, 3000, work, refine_tol=w.refine_tol,
-                                 max_refine=20, precond=args.precond, allow_not_converged=True)
+                                 max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI, allow_not_converged=True)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t0
     byt, flops, G = spectral_cost(80, 127, batch.B)
@@ -312,8 +318,9 @@ def batched_leg(ctx, args):
     mv = timed_matvec(r3m, ctx, s64, batch, b.to(torch.complex64), r3m.C64, 3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    # block-Jacobi: per-RHS ILU factors of the 1,536 RHS would not fit in HBM
     _, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, 1e-3, 30, 3000, work, refine_tol=1e-6,
-                                 max_refine=20, precond=args.precond, allow_not_converged=True)
+                                 max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI, allow_not_converged=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     del work, x, b
@@ -323,6 +330,48 @@ def batched_leg(ctx, args):
             "rhs": batch.B, "matvec_ms_c64": mv * 1e3, "solve_s": t, "solves_per_s": batch.B / t,
             "converged": all(r[3] for r in rep), "max_rel_residual": max(r[2] for r in rep),
             "inner_iters_max": max(r[0] for r in rep), "refine_steps_max": max(r[1] for r in rep)}
+
+
+def sweep_leg(ctx, args):
+    """Preconditioner study in the manner of the paper's iteration histogram
+    over random codebooks: GMRES(60) iterations to 1e-5 for 1-bit 16x16
+    Bernoulli(p) codebooks, p = 0.1 .. 0.9 (seed 0), normal incidence, on the
+    complex128 dense store, without preconditioner, with block-Jacobi and with
+    the near-field block ILU(0) of radius 1 and 2."""
+    import torch
+    from paper_2112_05082_amd import pipeline, r3m
+    from workloads import codebooks as cb
+    from workloads.configs import FREQ_HZ, SIDES_1BIT
+    from workloads.mesh import macro_unit
+    dev = "cuda:0"
+    L = 16
+    unit = macro_unit(SIDES_1BIT)
+    geom = r3m.UnitGeom.from_macro(unit, FREQ_HZ, 1)
+    store = pipeline.dense_store(ctx, geom, L, r3m.C128, dev)
+    cases = [("none", r3m.PRECOND_NONE, 1), ("block_jacobi", r3m.PRECOND_BLOCK_JACOBI, 1),
+             ("block_ilu_r1", r3m.PRECOND_BLOCK_ILU, 1), ("block_ilu_r2", r3m.PRECOND_BLOCK_ILU, 2)]
+    ps = [round(0.1 * k, 1) for k in range(1, 10)]
+    out = {name: [] for name, _, _ in cases}
+    secs = {name: 0.0 for name, _, _ in cases}
+    b = torch.zeros(L * L * unit.n_a, dtype=torch.complex128, device=dev)
+    for p in ps:
+        batch = r3m.Batch.from_codebooks([cb.bernoulli(L, 0, p)], [L], dev)
+        r3m.r3m_plane_wave_rhs(ctx, geom, batch, [[0.0, 0.0, 1.0]], b)
+        for name, pc, rad in cases:
+            work = torch.empty(r3m.gmres_work_bytes(ctx, store, batch, 60, precond=pc, ilu_radius=rad),
+                               dtype=torch.uint8, device=dev)
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rep = r3m.r3m_gmres_solve(ctx, store, None, batch, b, x, 1e-5, 60, 4000, work, precond=pc,
+                                         ilu_radius=rad, allow_not_converged=True)
+            torch.cuda.synchronize()
+            secs[name] += time.perf_counter() - t0
+            out[name].append(rep[0][0] if rep[0][3] else -rep[0][0])
+            del work
+    return {"workload": "1-bit 16x16 Bernoulli(p) codebooks, seed 0, p = 0.1..0.9, complex128 dense store, "
+                        "GMRES(60) to 1e-5 (negative: not converged within 4000)",
+            "p": ps, "iters": out, "total_solve_s": secs}
 
 
 def main():
@@ -383,7 +432,7 @@ def main():
     # ---- reference: plain FP64 GPU path (dense complex128 store)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    x_ref, sig_ref, rep_ref = solve(plain, args.ref_tol, args.restart, pc=1)
+    x_ref, sig_ref, rep_ref = solve(plain, args.ref_tol, args.restart)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     sig_ref = sig_ref.cpu().numpy()
@@ -500,6 +549,9 @@ def main():
         if not args.no_batched:
             torch.cuda.empty_cache()
             out["batched_1536"] = batched_leg(ctx, args)
+    if not args.no_sweep:
+        torch.cuda.empty_cache()
+        out["precond_sweep_16x16"] = sweep_leg(ctx, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(L, n, n_a, iters + 2)
     ctx.close()
