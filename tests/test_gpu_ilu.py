@@ -97,8 +97,9 @@ def test_factors_and_apply_match_oracle(r3m, ctx, dense_1bit_5, r, prec):
     y = torch.zeros_like(xd)
     r3m.r3m_ilu_apply(ctx, store, batch, r, F, xd, y)
     y = y.cpu().numpy()
-    tol_f, tol_a = (1e-9, 1e-9) if prec == "c128" else (2e-4, 2e-4)
+    tol_f, tol_a = (1e-11, 1e-11) if prec == "c128" else (2e-5, 2e-5)
     u0 = 0
+    worst_f = worst_a = 0.0
     for (Lx, Ly), book in zip(shapes, books):
         A, n_a = oracle_near(blocks, 4, unit(1).state_off, book, Lx, Ly, r)
         f = ilu.block_ilu0(A, Lx, Ly, n_a, r)
@@ -109,10 +110,15 @@ def test_factors_and_apply_match_oracle(r3m, ctx, dense_1bit_5, r, prec):
             if scale == 0:
                 assert np.abs(mine[:, s]).max() == 0
                 continue
-            assert np.abs(mine[:, s] - ref[:, s]).max() <= tol_f * scale, (Lx, Ly, s)
+            err = np.abs(mine[:, s] - ref[:, s]).max() / scale
+            worst_f = max(worst_f, err)
+            assert err <= tol_f, (Lx, Ly, s)
         ya = ilu.ilu_apply(f, x[u0 * n_a:(u0 + Lx * Ly) * n_a])
-        assert rel_l2(y[u0 * n_a:(u0 + Lx * Ly) * n_a], ya) <= tol_a
+        err = rel_l2(y[u0 * n_a:(u0 + Lx * Ly) * n_a], ya)
+        worst_a = max(worst_a, err)
+        assert err <= tol_a
         u0 += Lx * Ly
+    print(f"ILU {prec} r={r}: factor blocks max rel {worst_f:.1e}, apply rel L2 {worst_a:.1e}")
 
 
 def test_gmres_block_ilu_6x6(r3m, ctx):
@@ -141,6 +147,7 @@ def test_gmres_block_ilu_6x6(r3m, ctx):
     f = ilu.block_ilu0(Zk, 6, 6, 40, 1)
     ref = solve.gmres(lambda v: Zk @ v, U, tol=1e-10, restart=100, max_iter=1000,
                       precond=lambda v: ilu.ilu_apply(f, v))
+    print(f"ILU GMRES 6x6: {rep[0][0]} iterations (oracle {ref.iters}, block-Jacobi {it_bj})")
     assert abs(rep[0][0] - ref.iters) <= max(3, 0.05 * ref.iters)
     assert rep[0][0] < it_bj
 
@@ -167,7 +174,9 @@ def test_refined_c64_solve_with_ilu(r3m, ctx):
     x64 = torch.zeros_like(b)
     work2 = torch.empty(r3m.gmres_work_bytes(ctx, s128, batch, 60), dtype=torch.uint8, device=DEV)
     r3m.r3m_gmres_solve(ctx, s128, None, batch, b, x64, 1e-11, 60, 3000, work2, precond=r3m.PRECOND_BLOCK_JACOBI)
-    assert rel_l2(x.cpu().numpy(), x64.cpu().numpy()) <= 1e-8
+    err = rel_l2(x.cpu().numpy(), x64.cpu().numpy())
+    print(f"ILU refined c64 solve: {[r[0] for r in rep]} inner iterations, {err:.1e} vs the FP64 solution")
+    assert err <= 1e-8
 
 
 def test_ilu_graph_replays_match_eager(r3m, ctx):
