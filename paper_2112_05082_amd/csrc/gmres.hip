@@ -592,7 +592,7 @@ __global__ void nonfinite_kernel(const double2* __restrict__ v, const RhsVec* __
 }
 
 // Block-Jacobi inverses Z(0)[A(s), A(s)]^-1, one workgroup per state.
-// Dynamic LDS: (2 n_a^2 + n_a) double2.
+// Dynamic LDS: (2 n_a^2 + n_a + 1) double2.
 template <typename S>
 __global__ void __launch_bounds__(256)
 selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a, double2* __restrict__ Minv,
@@ -615,7 +615,7 @@ selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a,
     aug[e] = v;
   }
   __syncthreads();
-  if (!gj_invert(aug, colk, n_a, &piv_row, flag)) return;
+  if (!gj_invert_na(aug, colk, n_a, &piv_row, flag)) return;
   for (int e = threadIdx.x; e < n_a * n_a; e += blockDim.x) {
     const int i = e / n_a, j = e % n_a;
     Minv[(size_t)st * n_a * n_a + e] = aug[i * w + n_a + j];
@@ -658,7 +658,7 @@ relaxed_selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, 
     aug[e] = v;
   }
   __syncthreads();
-  if (!gj_invert(aug, colk, n_a, &piv_row, flag)) return;
+  if (!gj_invert_na(aug, colk, n_a, &piv_row, flag)) return;
   for (int e = threadIdx.x; e < n_a * n_a; e += blockDim.x) {
     const int i = e / n_a, j = e % n_a;
     Minv[(size_t)gu * n_a * n_a + e] = aug[i * w + n_a + j];
@@ -1252,7 +1252,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
       run.pre = true;
       const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
       const int slot0 = Ny * (2 * Nx + 1) + Nx;
-      const size_t lds = ((size_t)n_a * 2 * n_a + n_a) * sizeof(double2);
+      const size_t lds = ((size_t)n_a * 2 * n_a + n_a + 1) * sizeof(double2);
       if (per_unit) {  // relaxed codebook: the blended self block of every unit
         run.pu = 1;
         const dim3 ig((unsigned)maxU, bd.B);

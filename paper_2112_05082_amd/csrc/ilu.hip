@@ -128,7 +128,7 @@ ilu_fill_kernel(const T* __restrict__ near, int n, int Nx, int Ny, int n_a, int 
 // lower colours are final when this launch runs.  Each thread owns the same
 // kPer entries of every n_a x n_a product (column-major index q = tid + NT t),
 // so all of its global loads of a block are issued together.  Dynamic LDS
-// (2 n_a^2 + n_a) double2.
+// (2 n_a^2 + n_a + 1) double2.
 constexpr int kFactorThreads = 512;
 
 template <typename T, int NA>
@@ -138,6 +138,8 @@ ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, ty
   using T2 = typename Cx<T>::t2;
   constexpr int NT = kFactorThreads;
   constexpr int n_a = NA, nn = NA * NA, kPer = (NA * NA + NT - 1) / NT;
+  // products in 2 x 2 register blocks: rows {rb, rb + H}, columns {cb, cb + H}
+  constexpr int H = NA / 2, kBlk = (H * H + NT - 1) / NT;
   extern __shared__ double2 ilu_lds[];  // typed: 16-byte aligned after any static LDS
   __shared__ int piv_row;
   const RhsDev R = rhs[blockIdx.y];
@@ -147,24 +149,41 @@ ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, ty
   const int tid = threadIdx.x;
   const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;
   T2* Fi = F + (size_t)g * S * nn;
-  T2* Ls = reinterpret_cast<T2*>(ilu_lds);  // current multiplier, column-major
-  T2* Bs = Ls + nn;                          // pivot inverse or U_kj, column-major
+  double2* Ls = ilu_lds;   // current multiplier, column-major, FP64
+  double2* Bs = Ls + nn;   // pivot inverse or U_kj, column-major, FP64
 
-  // c[t] = sum_m Ls[row][m] Bs[m][col] for this thread's entries
-  auto product = [&](double2 (&c)[kPer]) {
+  // c[b][e] = sum_m Ls[row][m] Bs[m][col] for entry e of this thread's block b
+  // (e: bit 0 selects row rb + H, bit 1 column cb + H)
+  auto product = [&](double2 (&c)[kBlk][4]) {
 #pragma unroll
-    for (int t = 0; t < kPer; ++t) {
-      const int q = tid + t * NT;
-      double2 a = make_double2(0.0, 0.0);
-      if (q < nn) {
-        const int col = q / n_a, row = q % n_a;
-#pragma unroll 8
-        for (int m = 0; m < n_a; ++m) cmac(a, to_d2(Ls[m * n_a + row]), to_d2(Bs[col * n_a + m]));
+    for (int b = 0; b < kBlk; ++b) {
+      const int blk = tid + b * NT;
+      double2 a00 = make_double2(0.0, 0.0), a10 = a00, a01 = a00, a11 = a00;
+      if (blk < H * H) {
+        const int rb = blk % H, cb = blk / H;
+#pragma unroll 4
+        for (int m = 0; m < n_a; ++m) {
+          const double2 l0 = Ls[m * n_a + rb], l1 = Ls[m * n_a + rb + H];
+          const double2 b0 = Bs[cb * n_a + m], b1 = Bs[(cb + H) * n_a + m];
+          cmac(a00, l0, b0);
+          cmac(a10, l1, b0);
+          cmac(a01, l0, b1);
+          cmac(a11, l1, b1);
+        }
       }
-      c[t] = a;
+      c[b][0] = a00;
+      c[b][1] = a10;
+      c[b][2] = a01;
+      c[b][3] = a11;
     }
   };
+  auto entry = [&](int b, int e) {  // column-major index of entry e of block b
+    const int blk = tid + b * NT;
+    const int rb = blk % H, cb = blk / H;
+    return (cb + (e >> 1) * H) * n_a + rb + (e & 1) * H;
+  };
 
+  double2 acc[kBlk][4];
   for (int ck = 0; ck < colour; ++ck) {
     for (int ek = 0; ek < S; ++ek) {
       const int kx = ix + ek % W - r, ky = iy + ek / W - r;
@@ -175,21 +194,22 @@ ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, ty
       for (int t = 0; t < kPer; ++t) {
         const int q = tid + t * NT;
         if (q < nn) {
-          Ls[q] = Fi[(size_t)ek * nn + q];
-          Bs[q] = Fk[(size_t)(S / 2) * nn + q];
+          Ls[q] = to_d2(Fi[(size_t)ek * nn + q]);
+          Bs[q] = to_d2(Fk[(size_t)(S / 2) * nn + q]);
         }
       }
       __syncthreads();
-      double2 acc[kPer];
       product(acc);
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < kPer; ++t) {
-        const int q = tid + t * NT;
-        if (q < nn) {
-          const T2 v = from_d2<T2>(acc[t]);
-          Ls[q] = v;
-          Fi[(size_t)ek * nn + q] = v;
+      for (int b = 0; b < kBlk; ++b) {
+        if (tid + b * NT < H * H) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int q = entry(b, e);
+            Ls[q] = acc[b][e];
+            Fi[(size_t)ek * nn + q] = from_d2<T2>(acc[b][e]);
+          }
         }
       }
       // A_ij -= L_ik U_kj for the later part of row k inside i's pattern
@@ -202,23 +222,27 @@ ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, ty
         if (ox < -r || ox > r || oy < -r || oy > r) continue;
         __syncthreads();  // Bs free (and Ls complete)
         const int okj = (oy + r) * W + (ox + r);
-        T2 old[kPer];
 #pragma unroll
         for (int t = 0; t < kPer; ++t) {
           const int q = tid + t * NT;
-          if (q < nn) {
-            Bs[q] = Fk[(size_t)okj * nn + q];
-            old[t] = Fi[(size_t)ej * nn + q];
-          }
+          if (q < nn) Bs[q] = to_d2(Fk[(size_t)okj * nn + q]);
         }
+        T2 old[kBlk][4];
+#pragma unroll
+        for (int b = 0; b < kBlk; ++b)
+          if (tid + b * NT < H * H)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) old[b][e] = Fi[(size_t)ej * nn + entry(b, e)];
         __syncthreads();
         product(acc);
 #pragma unroll
-        for (int t = 0; t < kPer; ++t) {
-          const int q = tid + t * NT;
-          if (q < nn) {
-            const double2 o = to_d2(old[t]);
-            Fi[(size_t)ej * nn + q] = from_d2<T2>(make_double2(o.x - acc[t].x, o.y - acc[t].y));
+        for (int b = 0; b < kBlk; ++b) {
+          if (tid + b * NT < H * H) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const double2 o = to_d2(old[b][e]);
+              Fi[(size_t)ej * nn + entry(b, e)] = from_d2<T2>(make_double2(o.x - acc[b][e].x, o.y - acc[b][e].y));
+            }
           }
         }
       }
@@ -438,7 +462,7 @@ void factor_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states
                      Z->n, Nx, Ny, n_a, Z->n_states, bd.rhs, states, r, (T2*)F);
   const int ncx = colour_cols(bd, r), ncy = colour_rows(bd, r);
   const dim3 grid((unsigned)(ncx * ncy), (unsigned)bd.B);
-  const size_t lds = ((size_t)2 * n_a * n_a + n_a) * sizeof(double2);
+  const size_t lds = ((size_t)2 * n_a * n_a + n_a + 1) * sizeof(double2);
   for (int c = 0; c < (r + 1) * (r + 1); ++c) {
     if (n_a == 40)
       hipLaunchKernelGGL((ilu_factor_kernel<T, 40>), grid, dim3(kFactorThreads), lds, s, bd.rhs, r, c, ncx, (T2*)F, flag);

@@ -12,7 +12,8 @@ __device__ inline double2 dense_cmul(double2 a, double2 b) {
 // the left half of aug [NA][2 NA] (right half: identity), by one workgroup of
 // NT threads; the inverse is left in the right half.  The pivot of column k
 // is the row of largest modulus at or below k (the lowest such row on ties),
-// found by wave 0 with a butterfly reduction.  colk: NA double2 of LDS.
+// found by wave 0 with a butterfly reduction.  colk: NA + 1 double2 of LDS
+// (the multipliers of the current column, then the inverse pivot).
 // Returns false (and sets bit 8 of flag) for a singular block; uniform over
 // the workgroup.
 template <int NA, int NT>
@@ -22,7 +23,9 @@ __device__ inline bool gj_invert(double2* aug, double2* colk, int* piv_row, int*
   constexpr int kRows = (NA + G - 1) / G;     // rows per thread
   constexpr int kChunk = kRows < 7 ? kRows : 7;
   const int tid = threadIdx.x;
+  double2* piv_inv = colk + NA;
   for (int k = 0; k < NA; ++k) {
+    // pivot row and its inverse pivot (wave 0)
     if (tid < 64) {
       double best = -1.0;
       int p = NA;
@@ -43,26 +46,33 @@ __device__ inline bool gj_invert(double2* aug, double2* colk, int* piv_row, int*
         }
       }
       if (tid == 0) {
-        *piv_row = best > 0.0 ? p : -1;
-        if (!(best > 0.0)) atomicOr(flag, 8);
+        if (best > 0.0) {
+          const double2 d = aug[p * w + k];
+          const double dd = d.x * d.x + d.y * d.y;
+          *piv_inv = make_double2(d.x / dd, -d.y / dd);
+          *piv_row = p;
+        } else {
+          *piv_row = -1;
+          atomicOr(flag, 8);
+        }
       }
     }
     __syncthreads();
     const int p = *piv_row;
     if (p < 0) return false;
-    const double2 d = aug[p * w + k];
-    const double dd = d.x * d.x + d.y * d.y;
-    const double2 inv = make_double2(d.x / dd, -d.y / dd);
-    __syncthreads();  // every thread holds the pivot before rows move
-    // rows k and p exchange; the new row k is scaled by the inverse pivot
+    const double2 inv = *piv_inv;
+    // rows k and p exchange and the new row k is scaled by the inverse pivot;
+    // the multipliers of column k are taken as they stand after the exchange
     for (int j = tid; j < w; j += NT) {
       const double2 a = aug[k * w + j], b = aug[p * w + j];
       aug[k * w + j] = dense_cmul(b, inv);
-      if (p != k) aug[p * w + j] = a;
+      if (p != k) {
+        aug[p * w + j] = a;
+        if (j == k) colk[p] = a;
+      }
     }
-    __syncthreads();
-    // multipliers of column k, read before any row update touches that column
-    for (int i = tid; i < NA; i += NT) colk[i] = aug[i * w + k];
+    for (int i = tid; i < NA; i += NT)
+      if (i != k && i != p) colk[i] = aug[i * w + k];  // rows that did not move
     __syncthreads();
     // elimination: thread (g, j) updates column j of rows g, g + G, ...; all of
     // its operands are read before any of its writes
