@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--precond", type=int, default=2,
                    help="0 none, 1 block-Jacobi (self blocks), 2 near-field block ILU(0)")
     p.add_argument("--ilu-radius", type=int, default=1, help="pattern radius of --precond 2")
+    p.add_argument("--relaxed-precond", type=int, default=2,
+                   help="preconditioner of the differentiation leg (1 block-Jacobi, 2 block ILU(0) r = 1)")
     p.add_argument("--no-batched", action="store_true", help="skip the 1,536-RHS batched solve leg (about 40 s)")
     p.add_argument("--no-sweep", action="store_true",
                    help="skip the preconditioner study (iterations over Bernoulli p at 16x16)")
@@ -253,7 +255,8 @@ def relaxed_leg(ctx, args):
     N(0,1) logits, seed 3), J = mean RCS over 16 directions in a 30-degree
     cone; one forward (relaxed solve + objective) and one backward (adjoint
     solve with the transposed operator + gradient) on complex128 spectra,
-    block-Jacobi of the blended self blocks, GMRES(60) to 1e-8."""
+    block ILU(0) of the blended near field (radius 1; --relaxed-precond 1:
+    block-Jacobi of the blended self blocks), GMRES(60) to 1e-8."""
     import numpy as np
     import torch
     from paper_2112_05082_amd import pipeline, r3m
@@ -265,9 +268,10 @@ def relaxed_leg(ctx, args):
     L = 32
     unit = macro_unit(SIDES_2BIT)
     geom = r3m.UnitGeom.from_macro(unit, FREQ_HZ, 1)
-    store = pipeline.spectral_store(ctx, geom, L, 0, r3m.C128, dev)
+    pc = args.relaxed_precond
+    store = pipeline.spectral_store(ctx, geom, L, 1 if pc == r3m.PRECOND_BLOCK_ILU else 0, r3m.C128, dev)
     batch = r3m.Batch.from_codebooks([np.zeros(L * L, np.uint8)], [L], dev)
-    obj = RelaxedRcs(ctx, geom, store, batch, [[0.0, 0.0, 1.0]], cb.cone16(30.0), tol=1e-8)
+    obj = RelaxedRcs(ctx, geom, store, batch, [[0.0, 0.0, 1.0]], cb.cone16(30.0), tol=1e-8, precond=pc)
     logits = torch.from_numpy(np.random.default_rng(3).standard_normal((L * L, 4))).to(dev)
     for _ in range(2):
         lg = logits.clone().requires_grad_(True)
@@ -281,8 +285,9 @@ def relaxed_leg(ctx, args):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         it_b = obj.last_reports[0][0]
+    pname = PRECOND_NAMES.get(pc, "?").format(r=1)
     return {"workload": "2-bit 32x32 relaxed codebook (softmax of N(0,1) logits, seed 3), J = mean RCS over "
-                        "16 directions in a 30-degree cone, complex128 spectra, block-Jacobi GMRES(60) to 1e-8",
+                        f"16 directions in a 30-degree cone, complex128 spectra, {pname} GMRES(60) to 1e-8",
             "J": J.item(), "forward_s": t1 - t0, "backward_s": t2 - t1, "forward_iters": it_f,
             "adjoint_iters": it_b, "grad_norm": float(lg.grad.norm().item()),
             "gradients_per_s": 1.0 / (t2 - t0)}

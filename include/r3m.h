@@ -306,7 +306,8 @@ typedef enum {
   /* right near-field block ILU(0) preconditioner (Sec. III-D), factored for
    * every RHS's codebook from its retrieved near blocks (r3m_ilu_factor with
    * opts->ilu_radius) and applied by colour-parallel triangular solves
-   * (r3m_ilu_apply).  Not available with relaxed_weights. */
+   * (r3m_ilu_apply).  With relaxed_weights the pattern blocks are those of
+   * the blended operator Z_k(w) (of Z_k(w)^T with transpose). */
   R3M_PRECOND_BLOCK_ILU = 2
 } r3m_precond;
 
@@ -323,8 +324,9 @@ typedef struct {
                                     system Z_k(w) x = b of r3m_relaxed_matvec (spectral stores;
                                     Z64 spectral too).  R3M_PRECOND_BLOCK_JACOBI then inverts the
                                     blended self block sum_{s,s'} w_s w_s' Z(0)[A(s), A(s')] of
-                                    every unit (its transpose for the adjoint).  The work query
-                                    only tests this pointer for NULL. */
+                                    every unit (its transpose for the adjoint);
+                                    R3M_PRECOND_BLOCK_ILU factors the blended near field.  The
+                                    work query only tests this pointer for NULL. */
   int32_t transpose;             /* with relaxed_weights: solve Z_k(w)^T x = b (the adjoint) */
   int32_t ilu_radius;            /* R3M_PRECOND_BLOCK_ILU pattern radius (1..3, <= near_radius);
                                     0 selects 1 */

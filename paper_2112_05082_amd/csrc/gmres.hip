@@ -1175,8 +1175,6 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE || opts->precond == R3M_PRECOND_BLOCK_JACOBI ||
                     opts->precond == R3M_PRECOND_BLOCK_ILU,
                 R3M_ERR_INVALID_ARG, "unknown preconditioner");
-    R3M_REQUIRE(!(opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_ILU), R3M_ERR_UNSUPPORTED,
-                "the block ILU preconditioner does not take relaxed weights");
     const int ilu_r = ilu_radius_of(Z, opts);
     const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m, per_unit, ilu_r);
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "GMRES workspace too small");
@@ -1274,7 +1272,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     } else if (ilu_r) {
       run.pre = true;
       run.ilu_r = ilu_r;
-      launch_ilu_factor(Z, bd, batch->states, ilu_r, run.W.ilu, run.W.counters + 1, stream);
+      launch_ilu_factor(Z, bd, batch->states, ilu_r, run.W.ilu, run.W.counters + 1, stream, opts->relaxed_weights,
+                        run.tr);
     }
     // one read-back for the input checks and the preconditioner's pivots
     const int f = run.flag_check(14);

@@ -76,13 +76,16 @@ __device__ inline bool colour_unit(const RhsDev& R, int r, int colour, int ncx, 
 
 // Retrieval of the near-field pattern blocks: F[g][e] = Z(p_g - p_j)[A(s_g),
 // A(s_j)] for the neighbour j = g + e, transposed to column-major through
-// LDS (rows read along the store's rows, columns written along F's).
+// LDS (rows read along the store's rows, columns written along F's).  With
+// relaxed weights wts ([global unit][n_states]) the block is the blend
+// sum_{s,s'} w[g][s] w[j][s'] Z(p_g - p_j)[A(s), A(s')], or with transpose
+// that of the transposed operator, sum w[g][s] w[j][s'] Z(p_j - p_g)[A(s'), A(s)]^T.
 // Grid (max units * S, B); dynamic LDS n_a (n_a + 1) T2.
 template <typename T>
 __global__ void __launch_bounds__(256)
 ilu_fill_kernel(const T* __restrict__ near, int n, int Nx, int Ny, int n_a, int n_states,
                 const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, int r,
-                typename Cx<T>::t2* __restrict__ F) {
+                typename Cx<T>::t2* __restrict__ F, const double* __restrict__ wts, int transpose) {
   using T2 = typename Cx<T>::t2;
   extern __shared__ double2 ilu_lds[];  // typed: 16-byte aligned after any static LDS
   T2* tile = reinterpret_cast<T2*>(ilu_lds);  // [n_a][n_a + 1]
@@ -98,6 +101,27 @@ ilu_fill_kernel(const T* __restrict__ near, int n, int Nx, int Ny, int n_a, int 
   const int nn = n_a * n_a;
   if (jx < 0 || jx >= R.Lx || jy < 0 || jy >= R.Ly) {
     for (int q = threadIdx.x; q < nn; q += blockDim.x) dst[q] = from_d2<T2>(make_double2(0.0, 0.0));
+    return;
+  }
+  if (wts) {
+    const double* wg = wts + (R.unit_off + u) * n_states;
+    const double* wj = wts + (R.unit_off + (int64_t)jy * R.Lx + jx) * n_states;
+    // observer g, source j: displacement p_g - p_j = -e; the transpose reads +e
+    const int sx = transpose ? ex : -ex, sy = transpose ? ey : -ey;
+    const T* blk = near + ((size_t)(sy + Ny) * (2 * Nx + 1) + (sx + Nx)) * n * n * 2;
+    for (int q = threadIdx.x; q < nn; q += blockDim.x) {
+      const int col = q / n_a, row = q % n_a;
+      double re = 0.0, im = 0.0;
+      for (int s1 = 0; s1 < n_states; ++s1)
+        for (int s2 = 0; s2 < n_states; ++s2) {
+          const size_t idx = transpose ? (size_t)(s2 * n_a + col) * n + s1 * n_a + row
+                                       : (size_t)(s1 * n_a + row) * n + s2 * n_a + col;
+          const double ww = wg[s1] * wj[s2];
+          re += ww * (double)blk[2 * idx];
+          im += ww * (double)blk[2 * idx + 1];
+        }
+      dst[q] = from_d2<T2>(make_double2(re, im));
+    }
     return;
   }
   const int si = min((int)states[R.state_off + u], n_states - 1);
@@ -452,14 +476,14 @@ void apply_na(const r3m_store* Z, const BatchDesc& bd, int r, const void* F, con
 
 template <typename T>
 void factor_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, int r, void* F, int* flag,
-                  hipStream_t s) {
+                  hipStream_t s, const double* wts, bool tr) {
   using T2 = typename Cx<T>::t2;
   const int n_a = Z->n / Z->n_states;
   const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
   const int S = (2 * r + 1) * (2 * r + 1);
   const dim3 fg((unsigned)(bd.max_units * S), (unsigned)bd.B);
   hipLaunchKernelGGL(ilu_fill_kernel<T>, fg, dim3(256), (size_t)n_a * (n_a + 1) * sizeof(T2), s, (const T*)Z->near,
-                     Z->n, Nx, Ny, n_a, Z->n_states, bd.rhs, states, r, (T2*)F);
+                     Z->n, Nx, Ny, n_a, Z->n_states, bd.rhs, states, r, (T2*)F, wts, tr ? 1 : 0);
   const int ncx = colour_cols(bd, r), ncy = colour_rows(bd, r);
   const dim3 grid((unsigned)(ncx * ncy), (unsigned)bd.B);
   const size_t lds = ((size_t)2 * n_a * n_a + n_a + 1) * sizeof(double2);
@@ -488,11 +512,11 @@ size_t ilu_factor_bytes(const r3m_store* Z, const BatchDesc& bd, int radius) {
 }
 
 void launch_ilu_factor(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, int radius, void* F,
-                       int* flag, hipStream_t s) {
+                       int* flag, hipStream_t s, const double* wts, bool tr) {
   if (Z->near_dtype == R3M_C128)
-    factor_typed<double>(Z, bd, states, radius, F, flag, s);
+    factor_typed<double>(Z, bd, states, radius, F, flag, s, wts, tr);
   else
-    factor_typed<float>(Z, bd, states, radius, F, flag, s);
+    factor_typed<float>(Z, bd, states, radius, F, flag, s, wts, tr);
 }
 
 void launch_ilu_apply(const r3m_store* Z, const BatchDesc& bd, int radius, const void* F, const double2* in,

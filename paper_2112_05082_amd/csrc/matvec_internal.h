@@ -47,9 +47,10 @@ void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
 void validate_ilu(const r3m_store* Z, int radius);
 size_t ilu_factor_bytes(const r3m_store* Z, const BatchDesc& bd, int radius);
 // retrieval of the pattern blocks, then one launch per colour; singular
-// pivots set bit 8 of *flag
+// pivots set bit 8 of *flag.  wts (nullable): relaxed weights [unit][n_states]
+// (blended blocks; tr: of the transposed operator)
 void launch_ilu_factor(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, int radius, void* F,
-                       int* flag, hipStream_t s);
+                       int* flag, hipStream_t s, const double* wts = nullptr, bool tr = false);
 // z = M^-1 in (C128; z must not alias in); out (nullable, C128 or C64 per
 // out_type) receives a copy.  live as for the matvec
 void launch_ilu_apply(const r3m_store* Z, const BatchDesc& bd, int radius, const void* F, const double2* in,

@@ -23,21 +23,25 @@ class RelaxedRcs:
     logits taken in torch); inc: [B][3] incidences (theta, phi, e0); dirs:
     [n_dir][2] observation directions.  The solves run GMRES on complex128
     spectra to `tol`, right-preconditioned by the inverses of the blended self
-    blocks (precond=r3m.PRECOND_BLOCK_JACOBI; their transposes for the adjoint).
+    blocks (precond=r3m.PRECOND_BLOCK_JACOBI; their transposes for the adjoint)
+    or by the block ILU(0) of the blended near field (precond=
+    r3m.PRECOND_BLOCK_ILU with ilu_radius <= the store's near radius; that of
+    the transposed operator for the adjoint).
     """
 
     def __init__(self, ctx, geom, store, batch, inc, dirs, tol=1e-10, restart=60, max_iter=20000, e0=1.0,
-                 precond=r3m.PRECOND_BLOCK_JACOBI):
+                 precond=r3m.PRECOND_BLOCK_JACOBI, ilu_radius=1):
         self.ctx, self.geom, self.store, self.batch = ctx, geom, store, batch
         self.inc = np.asarray(inc, dtype=np.float64).reshape(-1, 3)
         self.dirs = np.asarray(dirs, dtype=np.float64).reshape(-1, 2)
         self.tol, self.restart, self.max_iter, self.e0, self.precond = tol, restart, max_iter, e0, precond
+        self.ilu_radius = ilu_radius
         dev = batch.states.device
         n_a = store.n // store.n_states
         self.N = batch.total_units * n_a
         self.M = batch.total_units * store.n
-        self.work = torch.empty(r3m.gmres_work_bytes(ctx, store, batch, restart, relaxed=True, precond=precond),
-                                dtype=torch.uint8, device=dev)
+        self.work = torch.empty(r3m.gmres_work_bytes(ctx, store, batch, restart, relaxed=True, precond=precond,
+                                                     ilu_radius=ilu_radius), dtype=torch.uint8, device=dev)
         self.gwork = torch.empty(r3m.relaxed_gradient_work_bytes(ctx, store, batch), dtype=torch.uint8, device=dev)
         self.last_reports = None
 
@@ -45,7 +49,7 @@ class RelaxedRcs:
         x = torch.zeros_like(b)
         _, rep = r3m.r3m_gmres_solve(self.ctx, self.store, None, self.batch, b, x, self.tol, self.restart,
                                      self.max_iter, self.work, relaxed_weights=w, transpose=transpose,
-                                     precond=self.precond)
+                                     precond=self.precond, ilu_radius=self.ilu_radius)
         self.last_reports = rep
         return x
 

@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 from gpu_common import FREQ, K, rel_max, unit  # noqa: E402
-from oracle import efie, relaxed, retrieval  # noqa: E402
+from oracle import efie, ilu, relaxed, retrieval, solve  # noqa: E402
 from workloads import codebooks as cb  # noqa: E402
 
 DEV = "cuda:0"
@@ -126,19 +126,24 @@ def test_relaxed_transpose_identity_fullsize(lib, full):
     assert abs(plain - lhs) > 1e-9 * abs(lhs)
 
 
-@pytest.mark.parametrize("transpose,precond", [(False, 0), (True, 0), (False, 1), (True, 1)])
+@pytest.mark.parametrize("transpose,precond", [(False, 0), (True, 0), (False, 1), (True, 1), (False, 2), (True, 2)])
 def test_relaxed_solve_vs_oracle_lu(lib, transpose, precond):
     """GMRES on the relaxed operator (and on its transpose, the adjoint solve)
     against dense LU on the oracle's relaxed matrix, 3 x 3 x 2 RHS, complex128
-    spectra, GMRES to 1e-12, without and with the block-Jacobi preconditioner
-    of the blended self blocks: solutions within 1e-8 (cond x 1e-12)."""
+    spectra, GMRES to 1e-12, without preconditioner, with the block-Jacobi of
+    the blended self blocks and with the block ILU(0) (radius 1) of the
+    blended near field: solutions within 1e-8 (cond x 1e-12); with the ILU,
+    iterations within 10% of the oracle's ILU GMRES on the same matrix."""
     r3m, _, ctx = lib
     L, D = 3, 2
     blocks = efie.displacement_blocks(unit(1), D, D, K, extract=1)
     spec = torch.empty(r3m.spectral_bytes(80, D, D, r3m.SPEC_C128), dtype=torch.uint8, device=DEV)
     r3m.r3m_build_spectral(ctx, to_dev(blocks), 80, D, D, r3m.SPEC_C128, spec)
-    store = r3m.Store(80, 2, D, D, 0, r3m.C128, to_dev(blocks[retrieval.slot(0, 0, D, D)][None]), r3m.SPEC_C128,
-                      spec)
+    if precond == r3m.PRECOND_BLOCK_ILU:  # near blocks of every |d| <= 2
+        store = r3m.Store(80, 2, D, D, D, r3m.C128, to_dev(blocks), r3m.SPEC_C128, spec)
+    else:
+        store = r3m.Store(80, 2, D, D, 0, r3m.C128, to_dev(blocks[retrieval.slot(0, 0, D, D)][None]),
+                          r3m.SPEC_C128, spec)
     rng = np.random.default_rng(50)
     logits = rng.standard_normal((2, L * L, 2))
     W = np.exp(logits) / np.exp(logits).sum(axis=2, keepdims=True)
@@ -154,16 +159,22 @@ def test_relaxed_solve_vs_oracle_lu(lib, transpose, precond):
     torch.cuda.synchronize()
     x = x.cpu().numpy()
     Zm = retrieval.macro_matrix(blocks, D, D, L)
-    errs = []
+    errs, oracle_iters = [], []
     for b in range(2):
         P = relaxed.blend_matrix(W[b], unit(1).state_off, L)
         A = P.T @ (Zm.T if transpose else Zm) @ P
         sl = slice(b * L * L * 40, (b + 1) * L * L * 40)
         ref = np.linalg.solve(A, bvec[sl])
         errs.append(np.linalg.norm(x[sl] - ref) / np.linalg.norm(ref))
+        if precond == r3m.PRECOND_BLOCK_ILU:
+            f = ilu.block_ilu0(A, L, L, 40, 1)
+            oracle_iters.append(solve.gmres(lambda v: A @ v, bvec[sl], 1e-12, 60, 4000,
+                                            precond=lambda v: ilu.ilu_apply(f, v)).iters)
     print(f"relaxed solve (transpose={transpose}, precond={precond}): iters {[r[0] for r in rep]}, errors vs LU "
-          f"{['%.2e' % e for e in errs]}")
+          f"{['%.2e' % e for e in errs]}, oracle ILU iters {oracle_iters}")
     assert all(r[3] for r in rep) and max(errs) <= 1e-8
+    for r, o in zip(rep, oracle_iters):
+        assert abs(r[0] - o) <= max(3, 0.1 * o)
 
 
 def test_relaxed_objective_and_gradient_vs_oracle(lib):
