@@ -339,44 +339,54 @@ def batched_leg(ctx, args):
 
 def sweep_leg(ctx, args):
     """Preconditioner study in the manner of the paper's iteration histogram
-    over random codebooks: GMRES(60) iterations to 1e-5 for 1-bit 16x16
-    Bernoulli(p) codebooks, p = 0.1 .. 0.9 (seed 0), normal incidence, on the
-    complex128 dense store, without preconditioner, with block-Jacobi and with
-    the near-field block ILU(0) of radius 1 and 2."""
+    over 90 random codebooks: GMRES(60) iterations to 1e-5 for 1-bit 16x16
+    Bernoulli(p) codebooks, p = 0.1 .. 0.9, 10 seeds each, normal incidence, on
+    the complex128 dense store, without preconditioner, with block-Jacobi and
+    with the near-field block ILU(0) of radius 1 and 2."""
+    import numpy as np
     import torch
     from paper_2112_05082_amd import pipeline, r3m
     from workloads import codebooks as cb
     from workloads.configs import FREQ_HZ, SIDES_1BIT
     from workloads.mesh import macro_unit
     dev = "cuda:0"
-    L = 16
+    L, seeds = 16, 10
     unit = macro_unit(SIDES_1BIT)
     geom = r3m.UnitGeom.from_macro(unit, FREQ_HZ, 1)
     store = pipeline.dense_store(ctx, geom, L, r3m.C128, dev)
     cases = [("none", r3m.PRECOND_NONE, 1), ("block_jacobi", r3m.PRECOND_BLOCK_JACOBI, 1),
              ("block_ilu_r1", r3m.PRECOND_BLOCK_ILU, 1), ("block_ilu_r2", r3m.PRECOND_BLOCK_ILU, 2)]
     ps = [round(0.1 * k, 1) for k in range(1, 10)]
-    out = {name: [] for name, _, _ in cases}
+    iters = {name: np.zeros((len(ps), seeds), dtype=np.int64) for name, _, _ in cases}
     secs = {name: 0.0 for name, _, _ in cases}
     b = torch.zeros(L * L * unit.n_a, dtype=torch.complex128, device=dev)
-    for p in ps:
-        batch = r3m.Batch.from_codebooks([cb.bernoulli(L, 0, p)], [L], dev)
-        r3m.r3m_plane_wave_rhs(ctx, geom, batch, [[0.0, 0.0, 1.0]], b)
-        for name, pc, rad in cases:
-            work = torch.empty(r3m.gmres_work_bytes(ctx, store, batch, 60, precond=pc, ilu_radius=rad),
-                               dtype=torch.uint8, device=dev)
-            x = torch.zeros_like(b)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            _, rep = r3m.r3m_gmres_solve(ctx, store, None, batch, b, x, 1e-5, 60, 4000, work, precond=pc,
-                                         ilu_radius=rad, allow_not_converged=True)
-            torch.cuda.synchronize()
-            secs[name] += time.perf_counter() - t0
-            out[name].append(rep[0][0] if rep[0][3] else -rep[0][0])
-            del work
-    return {"workload": "1-bit 16x16 Bernoulli(p) codebooks, seed 0, p = 0.1..0.9, complex128 dense store, "
-                        "GMRES(60) to 1e-5 (negative: not converged within 4000)",
-            "p": ps, "iters": out, "total_solve_s": secs}
+    works = {name: torch.empty(r3m.gmres_work_bytes(ctx, store, r3m.Batch.from_codebooks(
+        [cb.bernoulli(L, 0)], [L], dev), 60, precond=pc, ilu_radius=rad), dtype=torch.uint8, device=dev)
+        for name, pc, rad in cases}
+    for ip, p in enumerate(ps):
+        for sd in range(seeds):
+            batch = r3m.Batch.from_codebooks([cb.bernoulli(L, 100 * ip + sd, p)], [L], dev)
+            r3m.r3m_plane_wave_rhs(ctx, geom, batch, [[0.0, 0.0, 1.0]], b)
+            for name, pc, rad in cases:
+                x = torch.zeros_like(b)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, rep = r3m.r3m_gmres_solve(ctx, store, None, batch, b, x, 1e-5, 60, 4000, works[name],
+                                             precond=pc, ilu_radius=rad, allow_not_converged=True)
+                torch.cuda.synchronize()
+                secs[name] += time.perf_counter() - t0
+                iters[name][ip, sd] = rep[0][0] if rep[0][3] else -rep[0][0]
+    del works
+    return {"workload": "1-bit 16x16 Bernoulli(p) codebooks, p = 0.1..0.9 x 10 seeds (seed 100 i + s), "
+                        "complex128 dense store, GMRES(60) to 1e-5 (negative: not converged within 4000)",
+            "p": ps, "mean_iters": {k: v.mean(axis=1).round(1).tolist() for k, v in iters.items()},
+            "max_iters": {k: v.max(axis=1).tolist() for k, v in iters.items()},
+            "all_converged": bool(all((v > 0).all() for v in iters.values())),
+            "histogram_all_90": {k: np.bincount(np.clip(v.ravel(), 0, None) // 5).tolist() if k != "none"
+                                 else np.bincount(np.clip(v.ravel(), 0, None) // 50).tolist()
+                                 for k, v in iters.items()},
+            "histogram_bin": {"none": 50, "others": 5},
+            "total_solve_s": secs}
 
 
 def main():
