@@ -183,7 +183,8 @@ typedef struct {
 } r3m_store;
 
 /* A batch of right-hand sides sharing one store (Sec. III-A: the global
- * matrix is computed once and shared across codebooks).  RHS b is an
+ * matrix is computed once and shared across codebooks), B <= 65,535
+ * (R3M_ERR_UNSUPPORTED above).  RHS b is an
  * L[2b] x L[2b+1] array (Lx, Ly <= Dx+1, Dy+1) whose codebook is
  * states[state_off[b] ...] (uint8, device, one byte per unit, < n_states),
  * and whose reduced vectors start at unit unit_off[b] of x/y.  Several RHS

@@ -134,6 +134,8 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
 void validate_batch(const r3m_batch* batch, int Dx, int Dy) {
   R3M_REQUIRE(batch, R3M_ERR_INVALID_ARG, "batch is NULL");
   R3M_REQUIRE(batch->B >= 0, R3M_ERR_INVALID_ARG, "batch size < 0");
+  // the right-hand side is a grid dimension of the per-RHS launches
+  R3M_REQUIRE(batch->B <= 65535, R3M_ERR_UNSUPPORTED, "at most 65,535 right-hand sides per batch");
   if (batch->B == 0) return;
   R3M_REQUIRE(batch->L && batch->unit_off && batch->state_off && batch->states, R3M_ERR_INVALID_ARG,
               "NULL batch array");
