@@ -431,6 +431,9 @@ def r3m_ilu_factor(ctx: Context, store: Store, batch: Batch, radius: int, factor
 
 def r3m_ilu_apply(ctx: Context, store: Store, batch: Batch, radius: int, factors, x, y, stream=None):
     """y = M^-1 x with the factors of r3m_ilu_factor (complex128 vectors)."""
+    for t, name in ((x, "x"), (y, "y")):
+        if not (t.is_complex() and t.element_size() == 16):
+            raise ValueError(f"{name} must be complex128")
     n_a = store.n // store.n_states
     _need_vec(x, batch, n_a, "x")
     _need_vec(y, batch, n_a, "y")
