@@ -335,6 +335,7 @@ def batched_leg(ctx, args):
     return {"workload": "1-bit 384 codebooks (128 each at 32x32/48x48/64x64) x 4 angles = 1,536 RHS, block "
                         f"spectra (complex64 inner GMRES({m}) to 1e-3, complex128 refinement residual to 1e-6)",
             "rhs": batch.B, "matvec_ms_c64": mv * 1e3, "solve_s": t, "solves_per_s": batch.B / t,
+            "codebooks": len(w.codebooks), "codebooks_per_s": len(w.codebooks) / t,
             "converged": all(r[3] for r in rep), "max_rel_residual": max(r[2] for r in rep),
             "inner_iters_max": max(r[0] for r in rep), "refine_steps_max": max(r[1] for r in rep)}
 
