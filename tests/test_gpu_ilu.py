@@ -121,6 +121,47 @@ def test_factors_and_apply_match_oracle(r3m, ctx, dense_1bit_5, r, prec):
     print(f"ILU {prec} r={r}: factor blocks max rel {worst_f:.1e}, apply rel L2 {worst_a:.1e}")
 
 
+@pytest.mark.parametrize("prec", ["c128", "c64"])
+def test_factors_64_rwg_units_radius_3(r3m, ctx, prec):
+    """The 64-RWG build of the kernels and the largest radius: synthetic near
+    blocks (two states of 64, diagonally weighted so that the pivots are well
+    conditioned) for |d| <= 3, a 4x4 and a 4x3 array, radius 3 (16 colours,
+    49 blocks per unit); every factor block and M^-1 x against the oracle."""
+    n, S, D, r = 128, 2, 3, 3
+    rng = np.random.default_rng(77)
+    nd = (2 * D + 1) ** 2
+    blocks = (rng.standard_normal((nd, n, n)) + 1j * rng.standard_normal((nd, n, n))) / n
+    blocks[retrieval.slot(0, 0, D, D)] += 4.0 * np.eye(n)
+    cd = torch.complex128 if prec == "c128" else torch.complex64
+    near = torch.from_numpy(blocks).to(DEV).to(cd)
+    store = r3m.Store(n, S, D, D, D, r3m.C128 if prec == "c128" else r3m.C64, near)
+    shapes = [(4, 4), (4, 3)]
+    batch, books = rect_batch(r3m, shapes, 9, S)
+    F, got = gpu_factors(r3m, ctx, store, batch, r)
+    x = cb.random_complex(batch.total_units * 64, 3)
+    xd = torch.from_numpy(x).to(DEV)
+    y = torch.zeros_like(xd)
+    r3m.r3m_ilu_apply(ctx, store, batch, r, F, xd, y)
+    y = y.cpu().numpy()
+    tol = 1e-11 if prec == "c128" else 2e-5
+    ref_blocks = blocks if prec == "c128" else blocks.astype(np.complex64).astype(np.complex128)
+    u0 = 0
+    for (Lx, Ly), book in zip(shapes, books):
+        A, n_a = oracle_near(ref_blocks, D, [0, 64, 128], book, Lx, Ly, r)
+        f = ilu.block_ilu0(A, Lx, Ly, n_a, r)
+        ref = ilu.slot_blocks(f)
+        mine = got[u0:u0 + Lx * Ly]
+        for sl in range(ref.shape[1]):
+            scale = np.abs(ref[:, sl]).max()
+            if scale == 0:
+                assert np.abs(mine[:, sl]).max() == 0
+                continue
+            assert np.abs(mine[:, sl] - ref[:, sl]).max() <= tol * scale, (Lx, Ly, sl)
+        ya = ilu.ilu_apply(f, x[u0 * 64:(u0 + Lx * Ly) * 64])
+        assert rel_l2(y[u0 * 64:(u0 + Lx * Ly) * 64], ya) <= tol
+        u0 += Lx * Ly
+
+
 def test_gmres_block_ilu_6x6(r3m, ctx):
     """Right block-ILU GMRES on the 1-bit 6x6 direct system: iteration count of
     the oracle's preconditioned GMRES(100), the LU solution, and fewer
