@@ -161,7 +161,10 @@ def test_spectral_fullsize_rows(lib, fullsize):
     assert e64 <= 2e-6 and e64_l2 <= 1e-6
 
 
-def test_spectral_solves(lib, fullsize):
+@pytest.mark.parametrize("pc", [1, 2])
+def test_spectral_solves(lib, fullsize, pc):
+    """Block-Jacobi (1) or near-field block ILU (2) solves of the 2-bit 32x32
+    workload on complex64 spectra, and refined on complex128 spectra."""
     r3m, _, ctx = lib
     geom, _, batch, s128, s64, plain = fullsize
     N = 32 * 32 * 40
@@ -171,9 +174,10 @@ def test_spectral_solves(lib, fullsize):
 
     def solve(st, st64, tol, refine_tol):
         x = torch.zeros_like(b)
-        work = torch.empty(r3m.gmres_work_bytes(ctx, st, batch, 60, st64), dtype=torch.uint8, device=DEV)
+        work = torch.empty(r3m.gmres_work_bytes(ctx, st, batch, 60, st64, precond=pc), dtype=torch.uint8,
+                           device=DEV)
         _, rep = r3m.r3m_gmres_solve(ctx, st, st64, batch, b, x, tol, 60, 6000, work, refine_tol=refine_tol,
-                                     max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI)
+                                     max_refine=20, precond=pc)
         sig = torch.zeros(len(dirs), dtype=torch.float64, device=DEV)
         r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
         torch.cuda.synchronize()
@@ -185,7 +189,7 @@ def test_spectral_solves(lib, fullsize):
     s_ref_spec, rep2 = solve(s64, s128, 1e-4, 1e-9)
     e_mix = rel_l2(s_mix, s_ref)
     e_ref = rel_l2(s_ref_spec, s_ref)
-    print(f"spectral solves: c64 iters {rep[0][0]} RCS error {e_mix:.2e}; refined to 1e-9 on c128 spectra "
+    print(f"spectral solves (precond {pc}): c64 iters {rep[0][0]} RCS error {e_mix:.2e}; refined to 1e-9 on c128 spectra "
           f"(steps {rep2[0][1]}) RCS error {e_ref:.2e}")
     assert rep[0][3] and e_mix <= 1e-4
     assert rep2[0][3] and rep2[0][2] <= 1e-9 and e_ref <= 1e-7
