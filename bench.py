@@ -127,9 +127,10 @@ def cpu_baseline(L, n, n_a, n_matvec):
 
 def spectral_cost(n, D, B):
     """Algorithmic bytes and flops of one spectral matvec (complex64 spectra):
-    the spectra read once, the compact x read and y written once; flops of
-    the per-frequency products (8 n^2 per frequency per RHS) and of the four
-    transform passes (5 G log2 G per line, real flops of a radix-2 count)."""
+    bytes = the spectra read once (the compact vectors are small beside them);
+    flops of the per-frequency products (8 n^2 per frequency per RHS) and of
+    the four transform passes (5 G log2 G per line, real flops of a radix-2
+    count)."""
     import math
     G = 1
     while G < 2 * D + 1:
