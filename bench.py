@@ -61,6 +61,8 @@ def parse():
                    help="0 none, 1 block-Jacobi (self blocks), 2 near-field block ILU(0)")
     p.add_argument("--ilu-radius", type=int, default=1, help="pattern radius of --precond 2")
     p.add_argument("--batched-restart", type=int, default=20, help="GMRES restart of the 1,536-RHS leg")
+    p.add_argument("--inner-tol", type=float, default=1e-3,
+                   help="inner GMRES tolerance of the refined legs (128x128 x 16 and 1,536 RHS)")
     p.add_argument("--relaxed-precond", type=int, default=2,
                    help="preconditioner of the differentiation leg (1 block-Jacobi, 2 block ILU(0) r = 1)")
     p.add_argument("--no-batched", action="store_true", help="skip the 1,536-RHS batched solve leg (about 40 s)")
@@ -237,7 +239,8 @@ def large_leg(ctx, args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     # block-Jacobi: per-RHS ILU factors of 16 x 128 x 128 units would hold 30 GB
-    _, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, 1e-3, restart, 3000, work, refine_tol=w.refine_tol,
+    _, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, args.inner_tol, restart, 3000, work,
+                                 refine_tol=w.refine_tol,
                                  max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI, allow_not_converged=True)
     torch.cuda.synchronize()
     t_solve = time.perf_counter() - t0
@@ -328,7 +331,7 @@ def batched_leg(ctx, args):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     # block-Jacobi: per-RHS ILU factors of the 1,536 RHS would not fit in HBM
-    _, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, 1e-3, m, 3000, work, refine_tol=1e-6,
+    _, rep = r3m.r3m_gmres_solve(ctx, s64, s128, batch, b, x, args.inner_tol, m, 3000, work, refine_tol=1e-6,
                                  max_refine=20, precond=r3m.PRECOND_BLOCK_JACOBI, allow_not_converged=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
