@@ -277,8 +277,11 @@ int r3m_relaxed_gradient(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
  * of one colour never share a pattern, so the order inside a colour does not
  * matter).  Arithmetic in FP64, factors stored in the store's near precision.
  *
- * Factor buffer (r3m_ilu_bytes): per global unit g (unit_off[b] + iy Lx + ix)
- * S = (2 radius + 1)^2 blocks; slot (ey + radius)(2 radius + 1) + ex + radius
+ * Factor buffer (r3m_ilu_bytes): one factorisation per distinct codebook
+ * (right-hand sides with equal state_off and array shape share it, e.g. the
+ * incidence angles of one codebook), the codebooks one after another in the
+ * order of their first right-hand side; per unit (u = iy Lx + ix within its
+ * codebook) S = (2 radius + 1)^2 blocks; slot (ey + radius)(2 radius + 1) + ex + radius
  * holds the block of the neighbour at offset (ex, ey): the multiplier L_gj
  * (lower colour), the upper factor U_gj (higher colour), or the inverted
  * pivot U_gg^-1 at offset 0; zero for neighbours outside the array.  Blocks
@@ -286,8 +289,8 @@ int r3m_relaxed_gradient(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
  * (C128 near store) or float (C64).  State bytes >= n_states are read as
  * n_states - 1. */
 size_t r3m_ilu_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t radius);
-/* Factors every RHS's codebook.  R3M_ERR_NONFINITE for a singular pivot
- * block; this call synchronises the stream. */
+/* Factors every distinct codebook of the batch.  R3M_ERR_NONFINITE for a
+ * singular pivot block; this call synchronises the stream. */
 int r3m_ilu_factor(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t radius, void* factors_dev,
                    size_t factors_bytes, hipStream_t stream);
 /* y = U^-1 L^-1 x for every RHS (C128 [unit][n_a] vectors, x and y distinct;
@@ -304,8 +307,8 @@ typedef enum {
    * coding state, FP64).  It is the diagonal-block special case of the
    * near-field block-ILU preconditioner built after retrieval (Sec. III-D). */
   R3M_PRECOND_BLOCK_JACOBI = 1,
-  /* right near-field block ILU(0) preconditioner (Sec. III-D), factored for
-   * every RHS's codebook from its retrieved near blocks (r3m_ilu_factor with
+  /* right near-field block ILU(0) preconditioner (Sec. III-D), factored once
+   * per distinct codebook from its retrieved near blocks (r3m_ilu_factor with
    * opts->ilu_radius) and applied by colour-parallel triangular solves
    * (r3m_ilu_apply).  With relaxed_weights the pattern blocks are those of
    * the blended operator Z_k(w) (of Z_k(w)^T with transpose). */

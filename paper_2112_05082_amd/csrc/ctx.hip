@@ -169,9 +169,17 @@ const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int 
   std::vector<RhsDev> rhs(batch->B);
   std::vector<TileDev> tiles;
   int64_t total = 0;
+  std::map<std::vector<int64_t>, int64_t> codebook_at;  // (state_off, Lx, Ly) -> fac_off
   for (int b = 0; b < batch->B; ++b) {
     int Lx = batch->L[2 * b], Ly = batch->L[2 * b + 1];
-    rhs[b] = RhsDev{batch->unit_off[b], batch->state_off[b], Lx, Ly};
+    const std::vector<int64_t> ck{batch->state_off[b], Lx, Ly};
+    auto f = codebook_at.find(ck);
+    const bool lead = f == codebook_at.end();
+    if (lead) {
+      f = codebook_at.emplace(ck, d->codebook_units).first;
+      d->codebook_units += (int64_t)Lx * Ly;
+    }
+    rhs[b] = RhsDev{batch->unit_off[b], batch->state_off[b], Lx, Ly, f->second, lead ? 1 : 0, 0};
     d->Lx.push_back(Lx);
     d->Ly.push_back(Ly);
     d->unit_off.push_back(batch->unit_off[b]);

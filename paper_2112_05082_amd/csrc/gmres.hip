@@ -879,7 +879,7 @@ struct GmresRun {
 
   void precond(const double2* in, double2* out) {
     if (ilu_r) {
-      launch_ilu_apply(Zsolve, *bd, ilu_r, W.ilu, in, out, R3M_C128, nullptr, s, nullptr);
+      launch_ilu_apply(Zsolve, *bd, ilu_r, W.ilu, in, out, R3M_C128, nullptr, s, nullptr, wts == nullptr);
       return;
     }
     hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff, W.rv,
@@ -900,7 +900,7 @@ struct GmresRun {
   void prepare_input(const r3m_store* Z, const double2* v) {
     const bool c64 = Z->near_dtype == R3M_C64;
     if (ilu_r) {  // W.w is free here: the forward solve's scratch
-      launch_ilu_apply(Z, *bd, ilu_r, W.ilu, v, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s, nullptr);
+      launch_ilu_apply(Z, *bd, ilu_r, W.ilu, v, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s, nullptr, wts == nullptr);
     } else if (pre) {
       if (c64)
         hipLaunchKernelGGL(apply_precond_kernel<float>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
@@ -957,7 +957,7 @@ struct GmresRun {
                          np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
                          batch->states, W.soff, n_a, n_states, (double*)nullptr, pu);
       launch_ilu_apply(Z, *bd, ilu_r, W.ilu, W.V + (int64_t)(j + 1) * ut, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s,
-                       run_slot(j));
+                       run_slot(j), wts == nullptr);
     } else if (pre && c64)
       hipLaunchKernelGGL((normalize_step_kernel<float, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
                          npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
@@ -1107,12 +1107,12 @@ struct GmresRun {
 };
 
 size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m,
-                   bool per_unit, int ilu_r) {
+                   bool per_unit, int ilu_r, bool relaxed) {
   const int n_a = Z->n / Z->n_states;
   size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
   if (Z64) mv = std::max(mv, partials_and_x_bytes(bd, Z64, max_groups(bd)));
   return layout_work(nullptr, bd, n_a, per_unit ? (int)bd.total_units : Z->n_states, m, mv, near_lists_bytes(Z, bd),
-                     Z64 ? near_lists_bytes(Z64, bd) : 0, ilu_r ? ilu_factor_bytes(Z, bd, ilu_r) : 0)
+                     Z64 ? near_lists_bytes(Z64, bd) : 0, ilu_r ? ilu_factor_bytes(Z, bd, ilu_r, !relaxed) : 0)
       .bytes;
 }
 
@@ -1142,7 +1142,8 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z6
     if (batch->B == 0) return;
     const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, 0);
     out = gmres_bytes(ctx, Z, Z64, bd, opts->restart,
-                      opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI, ilu_radius_of(Z, opts));
+                      opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI, ilu_radius_of(Z, opts),
+                      opts->relaxed_weights != nullptr);
   });
   return rc == R3M_OK ? out : 0;
 }
@@ -1176,7 +1177,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
                     opts->precond == R3M_PRECOND_BLOCK_ILU,
                 R3M_ERR_INVALID_ARG, "unknown preconditioner");
     const int ilu_r = ilu_radius_of(Z, opts);
-    const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m, per_unit, ilu_r);
+    const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m, per_unit, ilu_r,
+                                    opts->relaxed_weights != nullptr);
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "GMRES workspace too small");
 
     size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
@@ -1219,7 +1221,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     run.s = stream;
     run.W = layout_work((char*)work_dev, bd, n_a, per_unit ? (int)bd.total_units : Z->n_states, m, mv,
                         near_lists_bytes(Z, bd), refine ? near_lists_bytes(Z64, bd) : 0,
-                        ilu_r ? ilu_factor_bytes(Z, bd, ilu_r) : 0);
+                        ilu_r ? ilu_factor_bytes(Z, bd, ilu_r, opts->relaxed_weights == nullptr) : 0);
     run.Zsolve = Z;
     run.ut = (int64_t)bd.total_units * n_a;
     run.maxN = 0;

@@ -85,7 +85,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 ilu_fill_kernel(const T* __restrict__ near, int n, int Nx, int Ny, int n_a, int n_states,
                 const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, int r,
-                typename Cx<T>::t2* __restrict__ F, const double* __restrict__ wts, int transpose) {
+                typename Cx<T>::t2* __restrict__ F, const double* __restrict__ wts, int transpose, int shared) {
   using T2 = typename Cx<T>::t2;
   extern __shared__ double2 ilu_lds[];  // typed: 16-byte aligned after any static LDS
   T2* tile = reinterpret_cast<T2*>(ilu_lds);  // [n_a][n_a + 1]
@@ -93,11 +93,11 @@ ilu_fill_kernel(const T* __restrict__ near, int n, int Nx, int Ny, int n_a, int 
   const int S = (2 * r + 1) * (2 * r + 1);
   const int64_t u = blockIdx.x / S;
   const int e = blockIdx.x % S;
-  if (u >= (int64_t)R.Lx * R.Ly) return;
+  if (u >= (int64_t)R.Lx * R.Ly || (shared && !R.fac_lead)) return;
   const int ix = (int)(u % R.Lx), iy = (int)(u / R.Lx);
   const int ex = e % (2 * r + 1) - r, ey = e / (2 * r + 1) - r;
   const int jx = ix + ex, jy = iy + ey;
-  T2* dst = F + ((size_t)(R.unit_off + u) * S + e) * n_a * n_a;
+  T2* dst = F + ((size_t)((shared ? R.fac_off : R.unit_off) + u) * S + e) * n_a * n_a;
   const int nn = n_a * n_a;
   if (jx < 0 || jx >= R.Lx || jy < 0 || jy >= R.Ly) {
     for (int q = threadIdx.x; q < nn; q += blockDim.x) dst[q] = from_d2<T2>(make_double2(0.0, 0.0));
@@ -158,7 +158,7 @@ constexpr int kFactorThreads = 512;
 template <typename T, int NA>
 __global__ void __launch_bounds__(kFactorThreads)
 ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, typename Cx<T>::t2* __restrict__ F,
-                  int* __restrict__ flag) {
+                  int* __restrict__ flag, int shared) {
   using T2 = typename Cx<T>::t2;
   constexpr int NT = kFactorThreads;
   constexpr int n_a = NA, nn = NA * NA, kPer = (NA * NA + NT - 1) / NT;
@@ -168,10 +168,11 @@ ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, ty
   __shared__ int piv_row;
   const RhsDev R = rhs[blockIdx.y];
   int ix, iy;
-  if (!colour_unit(R, r, colour, ncx, ix, iy)) return;
+  if (!colour_unit(R, r, colour, ncx, ix, iy) || (shared && !R.fac_lead)) return;
   const int W = 2 * r + 1, S = W * W;
   const int tid = threadIdx.x;
-  const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;
+  const int64_t fb = shared ? R.fac_off : R.unit_off;  // first factor unit of this codebook
+  const int64_t g = fb + (int64_t)iy * R.Lx + ix;
   T2* Fi = F + (size_t)g * S * nn;
   double2* Ls = ilu_lds;   // current multiplier, column-major, FP64
   double2* Bs = Ls + nn;   // pivot inverse or U_kj, column-major, FP64
@@ -212,7 +213,7 @@ ilu_factor_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, ty
     for (int ek = 0; ek < S; ++ek) {
       const int kx = ix + ek % W - r, ky = iy + ek / W - r;
       if (kx < 0 || kx >= R.Lx || ky < 0 || ky >= R.Ly || colour_of(kx, ky, r) != ck) continue;
-      const T2* Fk = F + (size_t)(R.unit_off + (int64_t)ky * R.Lx + kx) * S * nn;
+      const T2* Fk = F + (size_t)(fb + (int64_t)ky * R.Lx + kx) * S * nn;
       // multiplier L_ik = A_ik D_k (D_k: k's inverted pivot, centre slot)
 #pragma unroll
       for (int t = 0; t < kPer; ++t) {
@@ -380,7 +381,7 @@ __device__ inline void pivot_solve(const T2* __restrict__ D, const double2* t, d
 // x_i = U_ii^-1 z_i.  One workgroup per unit of the colour.
 template <typename T, int NA, typename OT>
 __global__ void __launch_bounds__(64 * kApplyWaves)
-ilu_forward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, int last,
+ilu_forward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, int last, int shared,
                    const typename Cx<T>::t2* __restrict__ F, const double2* __restrict__ in, double2* __restrict__ z,
                    OT* __restrict__ out, const int* __restrict__ live) {
   constexpr int n_a = NA;
@@ -391,8 +392,9 @@ ilu_forward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, i
   int ix, iy;
   if (!colour_unit(R, r, colour, ncx, ix, iy)) return;
   const int S = (2 * r + 1) * (2 * r + 1), nn = n_a * n_a;
-  const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;
-  const typename Cx<T>::t2* Fi = F + (size_t)g * S * nn;
+  const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;  // vectors
+  const typename Cx<T>::t2* Fi =
+      F + (size_t)((shared ? R.fac_off : R.unit_off) + (int64_t)iy * R.Lx + ix) * S * nn;
   neighbour_sum<NA>(R, r, colour, true, ix, iy, Fi, in, z, red);
   if (threadIdx.x < n_a) {
     const double2 a = in[g * n_a + threadIdx.x], s = red[threadIdx.x];
@@ -413,7 +415,7 @@ ilu_forward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, i
 // already there; z_i of colour 0 is in_i) and, when out is given, into out.
 template <typename T, int NA, typename OT>
 __global__ void __launch_bounds__(64 * kApplyWaves)
-ilu_backward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx,
+ilu_backward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx, int shared,
                     const typename Cx<T>::t2* __restrict__ F, const double2* __restrict__ in, double2* __restrict__ z,
                     OT* __restrict__ out, const int* __restrict__ live) {
   using T2 = typename Cx<T>::t2;
@@ -425,8 +427,8 @@ ilu_backward_kernel(const RhsDev* __restrict__ rhs, int r, int colour, int ncx,
   int ix, iy;
   if (!colour_unit(R, r, colour, ncx, ix, iy)) return;
   const int S = (2 * r + 1) * (2 * r + 1), nn = n_a * n_a;
-  const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;
-  const T2* Fi = F + (size_t)g * S * nn;
+  const int64_t g = R.unit_off + (int64_t)iy * R.Lx + ix;  // vectors
+  const T2* Fi = F + (size_t)((shared ? R.fac_off : R.unit_off) + (int64_t)iy * R.Lx + ix) * S * nn;
   neighbour_sum<NA>(R, r, colour, false, ix, iy, Fi, z, z, red);
   if (threadIdx.x < n_a) {
     const double2 a = (colour == 0 ? in : z)[g * n_a + threadIdx.x], s = red[threadIdx.x];
@@ -448,8 +450,8 @@ int colour_rows(const BatchDesc& bd, int r) {
 }
 
 template <typename T, int NA, typename OT>
-void apply_typed(const BatchDesc& bd, int r, const void* F, const double2* in, double2* z, OT* out, hipStream_t s,
-                 const int* live) {
+void apply_typed(const BatchDesc& bd, int r, int shared, const void* F, const double2* in, double2* z, OT* out,
+                 hipStream_t s, const int* live) {
   using T2 = typename Cx<T>::t2;
   const int ncx = colour_cols(bd, r), ncy = colour_rows(bd, r);
   const dim3 grid((unsigned)(ncx * ncy), (unsigned)bd.B);
@@ -458,40 +460,43 @@ void apply_typed(const BatchDesc& bd, int r, const void* F, const double2* in, d
   // nc-2 .. 0 backward
   for (int c = 1; c < nc; ++c)
     hipLaunchKernelGGL((ilu_forward_kernel<T, NA, OT>), grid, dim3(64 * kApplyWaves), 0, s, bd.rhs, r, c, ncx,
-                       c == nc - 1 ? 1 : 0, (const T2*)F, in, z, out, live);
+                       c == nc - 1 ? 1 : 0, shared, (const T2*)F, in, z, out, live);
   for (int c = nc - 2; c >= 0; --c)
     hipLaunchKernelGGL((ilu_backward_kernel<T, NA, OT>), grid, dim3(64 * kApplyWaves), 0, s, bd.rhs, r, c, ncx,
-                       (const T2*)F, in, z, out, live);
+                       shared, (const T2*)F, in, z, out, live);
   R3M_CHECK_HIP(hipGetLastError());
 }
 
 template <typename T, typename OT>
-void apply_na(const r3m_store* Z, const BatchDesc& bd, int r, const void* F, const double2* in, double2* z, OT* out,
-              hipStream_t s, const int* live) {
+void apply_na(const r3m_store* Z, const BatchDesc& bd, int r, int shared, const void* F, const double2* in,
+              double2* z, OT* out, hipStream_t s, const int* live) {
   if (Z->n / Z->n_states == 40)
-    apply_typed<T, 40, OT>(bd, r, F, in, z, out, s, live);
+    apply_typed<T, 40, OT>(bd, r, shared, F, in, z, out, s, live);
   else
-    apply_typed<T, 64, OT>(bd, r, F, in, z, out, s, live);
+    apply_typed<T, 64, OT>(bd, r, shared, F, in, z, out, s, live);
 }
 
 template <typename T>
 void factor_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, int r, void* F, int* flag,
                   hipStream_t s, const double* wts, bool tr) {
+  const int shared = wts ? 0 : 1;  // relaxed weights are per right-hand side
   using T2 = typename Cx<T>::t2;
   const int n_a = Z->n / Z->n_states;
   const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
   const int S = (2 * r + 1) * (2 * r + 1);
   const dim3 fg((unsigned)(bd.max_units * S), (unsigned)bd.B);
   hipLaunchKernelGGL(ilu_fill_kernel<T>, fg, dim3(256), (size_t)n_a * (n_a + 1) * sizeof(T2), s, (const T*)Z->near,
-                     Z->n, Nx, Ny, n_a, Z->n_states, bd.rhs, states, r, (T2*)F, wts, tr ? 1 : 0);
+                     Z->n, Nx, Ny, n_a, Z->n_states, bd.rhs, states, r, (T2*)F, wts, tr ? 1 : 0, shared);
   const int ncx = colour_cols(bd, r), ncy = colour_rows(bd, r);
   const dim3 grid((unsigned)(ncx * ncy), (unsigned)bd.B);
   const size_t lds = ((size_t)2 * n_a * n_a + n_a + 1) * sizeof(double2);
   for (int c = 0; c < (r + 1) * (r + 1); ++c) {
     if (n_a == 40)
-      hipLaunchKernelGGL((ilu_factor_kernel<T, 40>), grid, dim3(kFactorThreads), lds, s, bd.rhs, r, c, ncx, (T2*)F, flag);
+      hipLaunchKernelGGL((ilu_factor_kernel<T, 40>), grid, dim3(kFactorThreads), lds, s, bd.rhs, r, c, ncx, (T2*)F, flag,
+                         shared);
     else
-      hipLaunchKernelGGL((ilu_factor_kernel<T, 64>), grid, dim3(kFactorThreads), lds, s, bd.rhs, r, c, ncx, (T2*)F, flag);
+      hipLaunchKernelGGL((ilu_factor_kernel<T, 64>), grid, dim3(kFactorThreads), lds, s, bd.rhs, r, c, ncx, (T2*)F, flag,
+                         shared);
   }
   R3M_CHECK_HIP(hipGetLastError());
 }
@@ -505,10 +510,11 @@ void validate_ilu(const r3m_store* Z, int radius) {
   R3M_REQUIRE(n_a == 40 || n_a == 64, R3M_ERR_UNSUPPORTED, "ILU kernels are built for 40 or 64 active RWG per unit");
 }
 
-size_t ilu_factor_bytes(const r3m_store* Z, const BatchDesc& bd, int radius) {
+size_t ilu_factor_bytes(const r3m_store* Z, const BatchDesc& bd, int radius, bool shared) {
   const int n_a = Z->n / Z->n_states;
   const size_t S = (size_t)(2 * radius + 1) * (2 * radius + 1);
-  return (size_t)bd.total_units * S * n_a * n_a * (Z->near_dtype == R3M_C128 ? 16 : 8);
+  const int64_t units = shared ? bd.codebook_units : bd.total_units;
+  return (size_t)units * S * n_a * n_a * (Z->near_dtype == R3M_C128 ? 16 : 8);
 }
 
 void launch_ilu_factor(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, int radius, void* F,
@@ -520,18 +526,19 @@ void launch_ilu_factor(const r3m_store* Z, const BatchDesc& bd, const uint8_t* s
 }
 
 void launch_ilu_apply(const r3m_store* Z, const BatchDesc& bd, int radius, const void* F, const double2* in,
-                      double2* z, r3m_dtype out_type, void* out, hipStream_t s, const int* live) {
+                      double2* z, r3m_dtype out_type, void* out, hipStream_t s, const int* live, bool shared) {
   const bool d = Z->near_dtype == R3M_C128;
+  const int sh = shared ? 1 : 0;
   if (out_type == R3M_C64) {
     if (d)
-      apply_na<double, float>(Z, bd, radius, F, in, z, (float*)out, s, live);
+      apply_na<double, float>(Z, bd, radius, sh, F, in, z, (float*)out, s, live);
     else
-      apply_na<float, float>(Z, bd, radius, F, in, z, (float*)out, s, live);
+      apply_na<float, float>(Z, bd, radius, sh, F, in, z, (float*)out, s, live);
   } else {
     if (d)
-      apply_na<double, double>(Z, bd, radius, F, in, z, (double*)out, s, live);
+      apply_na<double, double>(Z, bd, radius, sh, F, in, z, (double*)out, s, live);
     else
-      apply_na<float, double>(Z, bd, radius, F, in, z, (double*)out, s, live);
+      apply_na<float, double>(Z, bd, radius, sh, F, in, z, (double*)out, s, live);
   }
 }
 

@@ -43,9 +43,11 @@ void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
                         const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
                         const double* wts, bool tr);
 
-// near-field block ILU(0) (r3m_ilu_*): factors of every RHS's codebook
+// near-field block ILU(0) (r3m_ilu_*): factors of every distinct codebook
+// (shared: right-hand sides with the same codebook share them; relaxed
+// weights are per right-hand side, so those factors are not shared)
 void validate_ilu(const r3m_store* Z, int radius);
-size_t ilu_factor_bytes(const r3m_store* Z, const BatchDesc& bd, int radius);
+size_t ilu_factor_bytes(const r3m_store* Z, const BatchDesc& bd, int radius, bool shared = true);
 // retrieval of the pattern blocks, then one launch per colour; singular
 // pivots set bit 8 of *flag.  wts (nullable): relaxed weights [unit][n_states]
 // (blended blocks; tr: of the transposed operator)
@@ -54,6 +56,7 @@ void launch_ilu_factor(const r3m_store* Z, const BatchDesc& bd, const uint8_t* s
 // z = M^-1 in (C128; z must not alias in); out (nullable, C128 or C64 per
 // out_type) receives a copy.  live as for the matvec
 void launch_ilu_apply(const r3m_store* Z, const BatchDesc& bd, int radius, const void* F, const double2* in,
-                      double2* z, r3m_dtype out_type, void* out, hipStream_t s, const int* live);
+                      double2* z, r3m_dtype out_type, void* out, hipStream_t s, const int* live,
+                      bool shared = true);
 
 }  // namespace r3m

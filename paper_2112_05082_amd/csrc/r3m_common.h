@@ -74,12 +74,18 @@ struct BatchDesc {
   const struct TileDev* tiles = nullptr;
   std::vector<int64_t> unit_off, n_units;
   std::vector<int32_t> Lx, Ly;
+  int64_t codebook_units = 0;  // units of the distinct codebooks (RhsDev::fac_off)
 };
 
 struct RhsDev {
   int64_t unit_off;
   int64_t state_off;
   int32_t Lx, Ly;
+  // per-codebook data (the near-field factors): right-hand sides with equal
+  // state_off and array shape share one codebook; fac_off is its unit offset
+  // among the distinct codebooks, fac_lead is 1 for its first right-hand side
+  int64_t fac_off;
+  int32_t fac_lead, pad;
 };
 
 struct TileDev {

@@ -121,6 +121,41 @@ def test_factors_and_apply_match_oracle(r3m, ctx, dense_1bit_5, r, prec):
     print(f"ILU {prec} r={r}: factor blocks max rel {worst_f:.1e}, apply rel L2 {worst_a:.1e}")
 
 
+def test_rhs_sharing_a_codebook_share_factors(r3m, ctx, dense_1bit_5):
+    """Right-hand sides with the same codebook (state offset and array shape)
+    share one factorisation: a batch of 4x4 codebook A, 3x3 codebook B, A
+    again, and A's first 10 bytes read as a 2x5 array holds three
+    factorisations (16 + 9 + 10 units), in the order of first appearance;
+    every right-hand side's M^-1 x matches the oracle for its codebook."""
+    store = dense_1bit_5[r3m.C128]
+    rng = np.random.default_rng(21)
+    A = rng.integers(0, 2, 16).astype(np.uint8)
+    B = rng.integers(0, 2, 9).astype(np.uint8)
+    states = torch.from_numpy(np.concatenate([A, B])).to(DEV)
+    shapes = [(4, 4), (3, 3), (4, 4), (2, 5)]
+    books = [A, B, A, A[:10]]
+    batch = r3m.Batch(shapes, [0, 16, 25, 41], [0, 16, 0, 0], states)
+    r = 1
+    assert r3m.ilu_bytes(ctx, store, batch, r) == (16 + 9 + 10) * 9 * 40 * 40 * 16
+    F, got = gpu_factors(r3m, ctx, store, batch, r)
+    blocks = oracle_blocks(1, 4)
+    x = cb.random_complex(batch.total_units * 40, 23)
+    xd = torch.from_numpy(x).to(DEV)
+    y = torch.zeros_like(xd)
+    r3m.r3m_ilu_apply(ctx, store, batch, r, F, xd, y)
+    y = y.cpu().numpy()
+    fac_off = {0: 0, 1: 16, 2: 0, 3: 25}
+    u0s = [0, 16, 25, 41]
+    for b, ((Lx, Ly), book) in enumerate(zip(shapes, books)):
+        Am, n_a = oracle_near(blocks, 4, unit(1).state_off, book, Lx, Ly, r)
+        f = ilu.block_ilu0(Am, Lx, Ly, n_a, r)
+        ref = ilu.slot_blocks(f)
+        mine = got[fac_off[b]:fac_off[b] + Lx * Ly]
+        assert np.abs(mine - ref).max() <= 1e-11 * np.abs(ref).max(), b
+        sl = slice(u0s[b] * 40, (u0s[b] + Lx * Ly) * 40)
+        assert rel_l2(y[sl], ilu.ilu_apply(f, x[sl])) <= 1e-11, b
+
+
 @pytest.mark.parametrize("prec", ["c128", "c64"])
 def test_factors_64_rwg_units_radius_3(r3m, ctx, prec):
     """The 64-RWG build of the kernels and the largest radius: synthetic near
@@ -191,6 +226,36 @@ def test_gmres_block_ilu_6x6(r3m, ctx):
     print(f"ILU GMRES 6x6: {rep[0][0]} iterations (oracle {ref.iters}, block-Jacobi {it_bj})")
     assert abs(rep[0][0] - ref.iters) <= max(3, 0.05 * ref.iters)
     assert rep[0][0] < it_bj
+
+
+def test_angles_of_one_codebook_share_the_factorisation(r3m, ctx):
+    """Two incidence angles of one 6x6 codebook in one ILU solve (one
+    factorisation for both) equal the two angles solved one at a time."""
+    from paper_2112_05082_amd import pipeline
+    states, _ = oracle_direct(1, 6, 0)
+    g = geom(r3m, 1)
+    store = pipeline.dense_store(ctx, g, 6, r3m.C128, DEV)
+    inc = [[0.0, 0.0, 1.0], [0.5, 0.3, 1.0]]
+    both = r3m.Batch.from_codebooks([states], [6], DEV, repeat=2)
+    assert r3m.ilu_bytes(ctx, store, both, 1) == 36 * 9 * 40 * 40 * 16
+    b = torch.zeros(2 * 1440, dtype=torch.complex128, device=DEV)
+    r3m.r3m_plane_wave_rhs(ctx, g, both, inc, b)
+    x = torch.zeros_like(b)
+    work = torch.empty(r3m.gmres_work_bytes(ctx, store, both, 100, precond=r3m.PRECOND_BLOCK_ILU), dtype=torch.uint8,
+                       device=DEV)
+    _, rep = r3m.r3m_gmres_solve(ctx, store, None, both, b, x, 1e-10, 100, 1000, work,
+                                 precond=r3m.PRECOND_BLOCK_ILU)
+    one = r3m.Batch.from_codebooks([states], [6], DEV)
+    for a in range(2):
+        b1 = torch.zeros(1440, dtype=torch.complex128, device=DEV)
+        r3m.r3m_plane_wave_rhs(ctx, g, one, [inc[a]], b1)
+        x1 = torch.zeros_like(b1)
+        w1 = torch.empty(r3m.gmres_work_bytes(ctx, store, one, 100, precond=r3m.PRECOND_BLOCK_ILU),
+                         dtype=torch.uint8, device=DEV)
+        _, r1 = r3m.r3m_gmres_solve(ctx, store, None, one, b1, x1, 1e-10, 100, 1000, w1,
+                                    precond=r3m.PRECOND_BLOCK_ILU)
+        assert abs(r1[0][0] - rep[a][0]) <= 1
+        assert rel_l2(x[a * 1440:(a + 1) * 1440].cpu().numpy(), x1.cpu().numpy()) <= 1e-9
 
 
 def test_refined_c64_solve_with_ilu(r3m, ctx):
