@@ -105,7 +105,7 @@ __global__ void dots_finish_kernel(const double2* __restrict__ partial, const Rh
 // lds: (m + 2) + m double2 and m double.  Every thread must call it.
 __device__ void givens_step_block(int b, double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
                                   double2* __restrict__ sn, RhsState* __restrict__ st, int m, int j, double tol,
-                                  int* __restrict__ n_running, double hn, double2* lds) {
+                                  int* __restrict__ n_running, double hn, double2* lds, int* __restrict__ idle) {
   RhsState s = st[b];
   if (!s.active || s.jdone >= 0) return;  // uniform over the block
   double2* h = H + (size_t)b * (m + 1) * m;
@@ -164,6 +164,7 @@ __device__ void givens_step_block(int b, double2* __restrict__ H, double2* __res
     s.res = res;
     if (!(res > tol) || nb == 0.0 || j == m - 1) {
       s.jdone = j + 1;
+      if (idle) idle[b] = 1;  // the rest of the cycle skips this right-hand side
     } else {
       atomicAdd(n_running, 1);
     }
@@ -218,7 +219,7 @@ __device__ double2 block_sum2(double2 v, double2* sh) {
 __global__ void __launch_bounds__(kDotThreads)
 dots_partials_kernel(const double2* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
                      const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
-                     int* __restrict__ reset, const int* __restrict__ live) {
+                     int* __restrict__ reset, const int* __restrict__ live, const int* __restrict__ idle) {
   __shared__ double2 sh[kDotThreads / 64][kDotVec];
   const int p = blockIdx.x, grp = blockIdx.y, b = blockIdx.z;
   const int tid = threadIdx.x, wave = tid >> 6;
@@ -226,6 +227,7 @@ dots_partials_kernel(const double2* __restrict__ A, int64_t a_stride, const doub
   // skipped step still leaves it zero for the next one)
   if (reset && p == 0 && grp == 0 && b == 0 && tid == 0) *reset = 0;
   if (live && *live == 0) return;
+  if (idle && idle[b]) return;
   const RhsVec r = rv[b];
   const int64_t P = (r.N + kDotChunk - 1) / kDotChunk;
   if (p >= P) return;
@@ -285,8 +287,9 @@ dots_partials_kernel(const double2* __restrict__ A, int64_t a_stride, const doub
 // blocks read one value per vector instead of every partial.
 __global__ void __launch_bounds__(256)
 finish_partials_kernel(const double2* __restrict__ partial, int maxP, int nvec, const RhsVec* __restrict__ rv,
-                       double2* __restrict__ out, const int* __restrict__ run_prev) {
+                       double2* __restrict__ out, const int* __restrict__ run_prev, const int* __restrict__ idle) {
   if (run_prev && *run_prev == 0) return;
+  if (idle && idle[blockIdx.y]) return;
   __shared__ double2 sh[4];
   const int i = blockIdx.x, b = blockIdx.y;
   const int64_t P = (rv[b].N + kDotChunk - 1) / kDotChunk;
@@ -303,8 +306,9 @@ finish_partials_kernel(const double2* __restrict__ partial, int maxP, int nvec, 
 // the per-block parts of ||w||^2 summed once into out[b] (grid B)
 __global__ void __launch_bounds__(256)
 finish_norm_kernel(const double* __restrict__ npart, int maxB, const RhsVec* __restrict__ rv,
-                   double* __restrict__ out, const int* __restrict__ run_prev) {
+                   double* __restrict__ out, const int* __restrict__ run_prev, const int* __restrict__ idle) {
   if (run_prev && *run_prev == 0) return;
+  if (idle && idle[blockIdx.x]) return;
   __shared__ double2 sh[4];
   const int b = blockIdx.x;
   const int64_t nb = (rv[b].N + 63) / 64;
@@ -325,8 +329,9 @@ __global__ void __launch_bounds__(256)
 gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
                  const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int n_part,
                  int nvec, int64_t ut, int do_norm, double* __restrict__ npart, int maxB, double2* __restrict__ H,
-                 int m, int j, int mode, const int* __restrict__ run_prev) {
+                 int m, int j, int mode, const int* __restrict__ run_prev, const int* __restrict__ idle) {
   if (run_prev && *run_prev == 0) return;
+  if (idle && idle[blockIdx.y]) return;
   extern __shared__ double2 hb[];
   __shared__ double2 sh[4];
   __shared__ double2 part[3][64];
@@ -417,11 +422,20 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
                       double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
                       double* __restrict__ wn, int64_t ut, const int* __restrict__ live,
                       const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
-                      const int64_t* __restrict__ soff, int n_a, int n_states, OT* __restrict__ xs, int per_unit) {
+                      const int64_t* __restrict__ soff, int n_a, int n_states, OT* __restrict__ xs, int per_unit,
+                      int* __restrict__ idle) {
   if (live && *live == 0) return;
   __shared__ double nv_s;
   __shared__ double2 v_s[256];
   const int b = blockIdx.y;
+  if (idle) {
+    // a right-hand side not being solved, or converged at an earlier step of
+    // this cycle, has no step left to finish (its V_{j+1} is never read).
+    // Tested on the state, not on idle[b], which block 0 of this launch may
+    // set (the state's jdone changes here only from -1 to j + 1)
+    const RhsState si = st[b];
+    if (!si.active || (si.jdone >= 0 && si.jdone <= j)) return;
+  }
   const RhsVec r = rv[b];
   const int64_t nb = (r.N + 63) / 64;
   if ((int64_t)blockIdx.x * blockDim.x >= r.N) return;  // uniform over the block
@@ -469,7 +483,7 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
   if (blockIdx.x == 0) {  // uniform over the block
     if (threadIdx.x == 0) wn[b] = nv;
     extern __shared__ double2 glds[];
-    givens_step_block(b, H, g, cs, sn, st, m, j, tol, n_running, nv, glds);
+    givens_step_block(b, H, g, cs, sn, st, m, j, tol, n_running, nv, glds, idle);
   }
 }
 
@@ -558,9 +572,10 @@ __global__ void zero_kernel(double2* __restrict__ x, const RhsVec* __restrict__ 
 __global__ void cycle_start_kernel(const double2* __restrict__ r, double2* __restrict__ V,
                                    const RhsVec* __restrict__ rv, RhsState* __restrict__ st,
                                    const double2* __restrict__ nrm2, double2* __restrict__ g, int m,
-                                   int* __restrict__ live0) {
+                                   int* __restrict__ live0, int* __restrict__ idle) {
   const int b = blockIdx.y;
   if (blockIdx.x == 0 && b == 0 && threadIdx.x == 0) *live0 = 1;  // step 0 runs
+  if (blockIdx.x == 0 && threadIdx.x == 0) idle[b] = st[b].active ? 0 : 1;
   const RhsVec rr = rv[b];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double beta = sqrt(fmax(nrm2[b].x, 0.0));
@@ -726,6 +741,13 @@ __global__ void combine_basis_kernel(const double2* __restrict__ V, const double
   z[r.off + k] = acc;
 }
 
+// idle[b] = 1 for a right-hand side that the last cycle did not solve: the
+// restart's residual skips it
+__global__ void idle_from_state_kernel(const RhsState* __restrict__ st, int B, int* __restrict__ idle) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) idle[b] = st[b].active ? 0 : 1;
+}
+
 __global__ void finalize_kernel(RhsState* __restrict__ st, int B, int J) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
@@ -757,6 +779,7 @@ struct Work {
   double* nsum;   // ||w||^2 summed from npart (long vectors)
   double2* nrm;
   RhsState* st;
+  int* idle;  // per RHS: 1 while it has no work in the current cycle (the matvec and Krylov kernels skip it)
   RhsVec* rv;
   int64_t* soff;
   int* counters;
@@ -806,6 +829,7 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_blocks, int m, 
   w.nsum = (double*)take((size_t)B * 8);
   w.nrm = (double2*)take((size_t)B * 16);
   w.st = (RhsState*)take((size_t)B * sizeof(RhsState));
+  w.idle = (int*)take((size_t)B * sizeof(int));
   w.rv = (RhsVec*)take((size_t)B * sizeof(RhsVec));
   w.soff = (int64_t*)take((size_t)B * 8);
   w.counters = (int*)take(256);
@@ -863,17 +887,20 @@ struct GmresRun {
   const r3m_store* Zsolve = nullptr;
   const void* lists_for(const r3m_store* Z) const { return Z == Zsolve ? W.lists : W.lists64; }
 
-  void matvec(const r3m_store* Z, const double2* x, double2* y) {
+  // idle (device, nullable): right-hand sides whose output is not needed
+  void matvec(const r3m_store* Z, const double2* x, double2* y, const int* idle = nullptr) {
     if (wts) {
-      launch_spectral_ex(Z, *bd, batch->states, R3M_C128, x, R3M_C128, y, W.mv_partial, s, nullptr, wts, tr);
+      launch_spectral_ex(Z, *bd, batch->states, R3M_C128, x, R3M_C128, y, W.mv_partial, s, nullptr, wts, tr, idle);
       return;
     }
     launch_matvec(ctx, Z, *bd, batch->states, R3M_C128, x, y, W.mv_partial, lists_for(Z), plan_groups(ctx, Z, *bd),
-                  s);
+                  s, idle);
   }
 
-  void residual(const r3m_store* Z, const double2* rhs, const double2* sol, double2* out) {
-    matvec(Z, sol, W.w);
+  // out = rhs - Z sol (for a right-hand side with idle[b] set, out[b] is meaningless)
+  void residual(const r3m_store* Z, const double2* rhs, const double2* sol, double2* out,
+                const int* idle = nullptr) {
+    matvec(Z, sol, W.w, idle);
     hipLaunchKernelGGL(sub_kernel, vgrid(), dim3(256), 0, s, rhs, W.w, out, W.rv);
   }
 
@@ -920,10 +947,10 @@ struct GmresRun {
     if (wts)
       launch_spectral_ex(Z, *bd, batch->states, input_in_xs(Z) ? Z->near_dtype : R3M_C128,
                          input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, R3M_C128, W.w, W.mv_partial, s, live,
-                         wts, tr);
+                         wts, tr, W.idle);
     else
       launch_matvec_pre(Z, *bd, batch->states, input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, W.w,
-                        W.mv_partial, lists_for(Z), G, s, live);
+                        W.mv_partial, lists_for(Z), G, s, live, W.idle);
     const dim3 dgrid(maxP, (j + 1 + kDotVec - 1) / kDotVec, B);
     const int maxB = (int)((maxN + 63) / 64 + 1);
     // long vectors (more than 64 chunk partials per coefficient): sum the
@@ -931,18 +958,18 @@ struct GmresRun {
     const bool long_vec = maxP > 64;
     for (int pass = 0; pass < 2; ++pass) {
       hipLaunchKernelGGL(dots_partials_kernel, dgrid, dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, j + 1, maxP,
-                         W.dpart, pass == 0 ? run_slot(j) : (int*)nullptr, live);
+                         W.dpart, pass == 0 ? run_slot(j) : (int*)nullptr, live, W.idle);
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(j + 1, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
-                           j + 1, W.rv, W.hsum, live);
+                           j + 1, W.rv, W.hsum, live, W.idle);
       hipLaunchKernelGGL(gs_update_kernel, dim3(ceil_div((size_t)maxN, 64), B), dim3(256),
                          (size_t)(j + 1) * sizeof(double2), s, W.V, W.w, W.rv, W.st,
                          long_vec ? (const double2*)W.hsum : (const double2*)W.dpart, long_vec ? 1 : maxP,
-                         long_vec ? 1 : 0, j + 1, ut, pass, W.npart, maxB, W.H, m, j, pass, live);
+                         long_vec ? 1 : 0, j + 1, ut, pass, W.npart, maxB, W.H, m, j, pass, live, W.idle);
     }
     if (long_vec)
       hipLaunchKernelGGL(finish_norm_kernel, dim3(B), dim3(256), 0, s, (const double*)W.npart, maxB, W.rv, W.nsum,
-                         live);
+                         live, W.idle);
     const double* np = long_vec ? W.nsum : W.npart;
     const int npB = long_vec ? 1 : maxB, npN = long_vec ? 1 : 0;
     // blocks of whole units (the preconditioner multiplies per unit)
@@ -955,25 +982,25 @@ struct GmresRun {
       // (W.w, the matvec output, is free once normalised)
       hipLaunchKernelGGL((normalize_step_kernel<double, 0>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
                          np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
-                         batch->states, W.soff, n_a, n_states, (double*)nullptr, pu);
+                         batch->states, W.soff, n_a, n_states, (double*)nullptr, pu, W.idle);
       launch_ilu_apply(Z, *bd, ilu_r, W.ilu, W.V + (int64_t)(j + 1) * ut, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s,
                        run_slot(j), wts == nullptr);
     } else if (pre && c64)
       hipLaunchKernelGGL((normalize_step_kernel<float, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
                          npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
-                         W.soff, n_a, n_states, (float*)W.xs, pu);
+                         W.soff, n_a, n_states, (float*)W.xs, pu, W.idle);
     else if (pre)
       hipLaunchKernelGGL((normalize_step_kernel<double, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
                          np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
-                         batch->states, W.soff, n_a, n_states, (double*)W.xs, pu);
+                         batch->states, W.soff, n_a, n_states, (double*)W.xs, pu, W.idle);
     else if (c64)
       hipLaunchKernelGGL((normalize_step_kernel<float, 1>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
                          npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
-                         W.soff, n_a, n_states, (float*)W.xs, pu);
+                         W.soff, n_a, n_states, (float*)W.xs, pu, W.idle);
     else
       hipLaunchKernelGGL((normalize_step_kernel<double, 0>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
                          np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
-                         batch->states, W.soff, n_a, n_states, (double*)nullptr, pu);
+                         batch->states, W.soff, n_a, n_states, (double*)nullptr, pu, W.idle);
     R3M_CHECK_HIP(hipGetLastError());
   }
 
@@ -1036,12 +1063,18 @@ struct GmresRun {
         norms(W.r);
         rnorm = rhs_norm;
       } else {
-        residual(Z, rhs, sol, W.r);
+        // a restart: right-hand sides the last cycle did not solve keep their
+        // residual norm and are skipped by the matvec
+        if (!first)
+          hipLaunchKernelGGL(idle_from_state_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, (const RhsState*)W.st, B,
+                             W.idle);
+        residual(Z, rhs, sol, W.r, first ? nullptr : (const int*)W.idle);
         norms(W.r);
         std::vector<double2> nr(B);
         R3M_CHECK_HIP(hipMemcpyAsync(nr.data(), W.nrm, (size_t)B * 16, hipMemcpyDeviceToHost, s));
         R3M_CHECK_HIP(hipStreamSynchronize(s));
-        for (int b = 0; b < B; ++b) rnorm[b] = std::sqrt(std::max(nr[b].x, 0.0));
+        for (int b = 0; b < B; ++b)
+          if (first || running[b]) rnorm[b] = std::sqrt(std::max(nr[b].x, 0.0));
       }
       first = false;
       bool any = false;
@@ -1058,7 +1091,8 @@ struct GmresRun {
       if (!any) break;
       R3M_CHECK_HIP(hipMemcpyAsync(W.st, hst.data(), (size_t)B * sizeof(RhsState), hipMemcpyHostToDevice, s));
       dim3 g0(std::max(ceil_div((size_t)maxN, 256), ceil_div((size_t)m + 1, 256)), B);
-      hipLaunchKernelGGL(cycle_start_kernel, g0, dim3(256), 0, s, W.r, W.V, W.rv, W.st, W.nrm, W.g, m, run_slot(-1));
+      hipLaunchKernelGGL(cycle_start_kernel, g0, dim3(256), 0, s, W.r, W.V, W.rv, W.st, W.nrm, W.g, m, run_slot(-1),
+                         W.idle);
       prepare_input(Z, W.V);
       const int steps = std::max(1, std::min(m, max_iter - min_used));
       // Blocks of kCheckEvery steps.  The running count after a block is read

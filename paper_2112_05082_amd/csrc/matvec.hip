@@ -389,6 +389,7 @@ struct FarArgs {
   S* out;
   int64_t total_units;
   int lds_state_cap, n_blocks;
+  const int* idle;  // per right-hand side (nullable): tiles of b with idle[b] != 0 return at once
 };
 
 // far field of workgroup wg (see far_kernel)
@@ -413,6 +414,7 @@ __device__ __forceinline__ void far_body(const FarArgs<S>& A, int wg) {
   int bi, g;
   if (!decode_wg(wg, n_blocks, groups, bi, g)) return;
   const TileDev blk = tiles[bi];
+  if (A.idle && A.idle[blk.b]) return;  // uniform over the workgroup
   const RhsDev R = rhs[blk.b];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -620,8 +622,10 @@ far_kernel(FarArgs<S> A, const int* __restrict__ live) {
 template <typename S, typename XT>
 __global__ void __launch_bounds__(256)
 reduce_groups_kernel(const RhsDev* __restrict__ rhs, const S* __restrict__ partial, int slots,
-                     int64_t total_units, int n_a, XT* __restrict__ y, const int* __restrict__ live) {
+                     int64_t total_units, int n_a, XT* __restrict__ y, const int* __restrict__ live,
+                     const int* __restrict__ idle) {
   if (live && *live == 0) return;  // every right-hand side has converged
+  if (idle && idle[blockIdx.y]) return;
   const RhsDev R = rhs[blockIdx.y];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= (int64_t)R.Lx * R.Ly * n_a) return;
@@ -1069,7 +1073,7 @@ void validate_store(const r3m_store* Z) {
 template <typename S, typename XT>
 static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const S* xs, XT* y,
                         char* part, const void* lists, int chunks, hipStream_t stream,
-                        const int* live = nullptr) {
+                        const int* live = nullptr, const int* idle = nullptr) {
   const int n_a = Z->n / Z->n_states;
   const int Nx = std::min(Z->near_radius, Z->Dx), Ny = std::min(Z->near_radius, Z->Dy);
   const bool far = store_has_far(Z);
@@ -1100,7 +1104,7 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
         Z->far_dtype == R3M_F16X2 ? (const float*)((const char*)Z->far + head + body) : nullptr;
     const FarArgs<S> FA{bd.rhs, bd.tiles, groups, states, (const S*)((const char*)Z->far + head),
                         (const int*)Z->far, fscale, Z->max_rank, Z->Dx, Z->Dy, Z->near_radius, Z->n, n_a,
-                        Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles};
+                        Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles, idle};
     const int nwg = (bd.n_tiles * groups + kXcd - 1) / kXcd * kXcd;
     const int ft = sizeof(S) == 4 ? (int)Z->far_dtype : 0;
     if (fuse) {
@@ -1147,13 +1151,13 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
   }
   R3M_CHECK_HIP(hipGetLastError());
   hipLaunchKernelGGL((reduce_groups_kernel<S, XT>), dim3(ceil_div((size_t)bd.max_units * n_a, 64), bd.B),
-                     dim3(64), 0, stream, bd.rhs, (const S*)part, groups + hg, tu, n_a, y, live);
+                     dim3(64), 0, stream, bd.rhs, (const S*)part, groups + hg, tu, n_a, y, live, idle);
   R3M_CHECK_HIP(hipGetLastError());
 }
 
 template <typename S, typename XT>
 static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
-                         void* partial, const void* lists, int chunks, hipStream_t stream) {
+                         void* partial, const void* lists, int chunks, hipStream_t stream, const int* idle) {
   const int n_a = Z->n / Z->n_states;
   const bool far = store_has_far(Z);
   const int groups = far ? std::max(chunks, 1) : 0;
@@ -1167,24 +1171,25 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
                        dim3(256), 0, stream, bd.rhs, n_a, (const XT*)x, xc);
     xs = xc;
   }
-  launch_core<S, XT>(Z, bd, states, xs, (XT*)y, part, lists, chunks, stream);
+  launch_core<S, XT>(Z, bd, states, xs, (XT*)y, part, lists, chunks, stream, nullptr, idle);
 }
 
 // matvec with x already in the store precision (float for C64, double for
 // C128); y is C128
 // the near retrieval lists (build_near_lists) must be current at lists
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
-                       void* partial, const void* lists, int chunks, hipStream_t stream, const int* live) {
+                       void* partial, const void* lists, int chunks, hipStream_t stream, const int* live,
+                       const int* idle) {
   if (store_is_spectral(Z)) {
-    launch_spectral(Z, bd, states, Z->near_dtype, xs, R3M_C128, y, partial, stream, live);
+    launch_spectral(Z, bd, states, Z->near_dtype, xs, R3M_C128, y, partial, stream, live, idle);
     return;
   }
   if (Z->near_dtype == R3M_C128)
     launch_core<double, double>(Z, bd, states, (const double*)xs, (double*)y, (char*)partial, lists, chunks, stream,
-                                live);
+                                live, idle);
   else
     launch_core<float, double>(Z, bd, states, (const float*)xs, (double*)y, (char*)partial, lists, chunks, stream,
-                               live);
+                               live, idle);
 }
 
 static std::vector<int64_t> tune_key(const r3m_store* Z, const BatchDesc& bd) {
@@ -1249,20 +1254,20 @@ int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd) {
 // current near lists (build_near_lists), or NULL for the ones inside partial
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
                    r3m_dtype vec_dtype, const void* x, void* y, void* partial, const void* lists, int chunks,
-                   hipStream_t stream) {
+                   hipStream_t stream, const int* idle) {
   (void)ctx;
   if (store_is_spectral(Z)) {
-    launch_spectral(Z, bd, states, vec_dtype, x, vec_dtype, y, partial, stream, nullptr);
+    launch_spectral(Z, bd, states, vec_dtype, x, vec_dtype, y, partial, stream, nullptr, idle);
     return;
   }
   if (!lists) lists = workspace_lists(partial, bd, Z);
   if (Z->near_dtype == R3M_C128) {
     R3M_REQUIRE(vec_dtype == R3M_C128, R3M_ERR_UNSUPPORTED, "a C128 store needs C128 vectors");
-    launch_typed<double, double>(Z, bd, states, x, y, partial, lists, chunks, stream);
+    launch_typed<double, double>(Z, bd, states, x, y, partial, lists, chunks, stream, idle);
   } else if (vec_dtype == R3M_C64) {
-    launch_typed<float, float>(Z, bd, states, x, y, partial, lists, chunks, stream);
+    launch_typed<float, float>(Z, bd, states, x, y, partial, lists, chunks, stream, idle);
   } else {
-    launch_typed<float, double>(Z, bd, states, x, y, partial, lists, chunks, stream);
+    launch_typed<float, double>(Z, bd, states, x, y, partial, lists, chunks, stream, idle);
   }
 }
 

@@ -21,27 +21,33 @@ size_t near_lists_bytes(const r3m_store* Z, const BatchDesc& bd);
 size_t near_lists_bytes_bound(int n_states, const BatchDesc& bd);
 void build_near_lists(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, void* lists_dev,
                       hipStream_t stream);
-// y (C128 or C64 vectors); lists NULL: the ones inside partial
+// y (C128 or C64 vectors); lists NULL: the ones inside partial.  idle
+// (device, nullable, one int per right-hand side): the output of a right-hand
+// side b with idle[b] != 0 is not computed and keeps whatever it held (the
+// vector-unit far tiles, the reduction and every spectral pass skip it; the
+// matrix-core near items, which mix right-hand sides, still run)
 void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states,
                    r3m_dtype vec_dtype, const void* x, void* y, void* partial, const void* lists, int chunks,
-                   hipStream_t stream);
+                   hipStream_t stream, const int* idle = nullptr);
 // xs already in the store precision; y C128.  live (device, nullable): the
 // kernels return at once when *live == 0 (used to skip Arnoldi steps after
-// every right-hand side has converged)
+// every right-hand side has converged); idle as above
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
-                       void* partial, const void* lists, int chunks, hipStream_t stream, const int* live);
+                       void* partial, const void* lists, int chunks, hipStream_t stream, const int* live,
+                       const int* idle = nullptr);
 
 // spectral stores (far_dtype R3M_SPEC_*): the whole product by FFT
 bool store_is_spectral(const r3m_store* Z);
 void validate_spectral(const r3m_store* Z);
 size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z);
-// x (x_type) to y (y_type); work: spectral_work_bytes; live as above
+// x (x_type) to y (y_type); work: spectral_work_bytes; live and idle as above
 void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
-                     const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live);
+                     const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
+                     const int* idle = nullptr);
 // relaxed retrieval (wts [units][n_states], nullable) and the transposed operator
 void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                         const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
-                        const double* wts, bool tr);
+                        const double* wts, bool tr, const int* idle = nullptr);
 
 // near-field block ILU(0) (r3m_ilu_*): factors of every distinct codebook
 // (shared: right-hand sides with the same codebook share them; relaxed

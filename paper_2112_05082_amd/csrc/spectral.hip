@@ -195,6 +195,7 @@ struct FftArgs {
   C2<T>* ymacro;
   int macro_plain;  // kInvRows with wts: write y~ itself (the macro product Z P(w) x), no weights
   const int* live;
+  const int* idle;  // per right-hand side (nullable): lines of b with idle[b] != 0 are left alone
 };
 
 template <typename T>
@@ -248,6 +249,8 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
     Ly = R.Ly;
     if (chan && lig0 >= Ly) return;  // a row past the array
   }
+  // a workgroup's lines belong to one right-hand side (grids are [B][n])
+  if (A.idle && A.idle[g0 / A.n]) return;
   // the active macro row of unit u in channel c, or -1
   auto active = [&](int64_t u, int c) -> int {
     const int s = min((int)A.states[R.state_off + u], A.n_states - 1);
@@ -420,7 +423,8 @@ __device__ __forceinline__ int64_t mirror_freq(int64_t k, int lgGx, int lgGy) {
 template <typename T, int MT, int BC, bool TR>
 __global__ void __launch_bounds__(256)
 spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, C2<T>* __restrict__ Yh, int n,
-                    int64_t K, int B, int n_mg, int lgGx, int lgGy, const int* __restrict__ live) {
+                    int64_t K, int B, int n_mg, int lgGx, int lgGy, const int* __restrict__ live,
+                    const int* __restrict__ idle) {
   if (live && *live == 0) return;
   const int nz = (B + BC - 1) / BC;
   const int64_t id = blockIdx.x;
@@ -433,6 +437,11 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
   if (k >= K || m0 >= n) return;
   const int b0 = z * BC;
   const int nb = min(BC, B - b0);
+  if (idle) {  // nothing to do when every right-hand side of the chunk is idle
+    bool any = false;
+    for (int q = 0; q < nb; ++q) any |= idle[b0 + q] == 0;
+    if (!any) return;
+  }
   T ar[MT][BC], ai[MT][BC];
 #pragma unroll
   for (int i = 0; i < MT; ++i)
@@ -494,7 +503,7 @@ template <int KPW, int PC, bool TR>
 __global__ void __launch_bounds__(256)
 spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __restrict__ Xh, C2<float>* __restrict__ Yh,
                          int n, int64_t K, int B, int n_mg, int n_bt, int64_t n_tiles, int lgGx, int lgGy,
-                         const int* __restrict__ live) {
+                         const int* __restrict__ live, const int* __restrict__ idle) {
   if (live && *live == 0) return;
   typedef float v4 __attribute__((ext_vector_type(4)));
   constexpr int PK = 4 * KPW;                   // frequencies per workgroup
@@ -524,6 +533,11 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
   if (kt >= n_tiles) return;  // n_tiles: frequency tiles
   const int64_t k0 = kt * PK;
   const int m0 = mg * kPM, b0 = bt * kPB;
+  if (idle) {  // uniform over the workgroup: skip a tile of idle right-hand sides
+    bool any = false;
+    for (int q = b0; q < min(b0 + kPB, B); ++q) any |= idle[q] == 0;
+    if (!any) return;
+  }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   v4 are[KPW][5], aim[KPW][5];
 #pragma unroll
@@ -611,15 +625,15 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
 
 template <typename T, int MT, int BC>
 void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, bool tr, int lgGx,
-                    int lgGy, hipStream_t s, const int* live) {
+                    int lgGy, hipStream_t s, const int* live, const int* idle) {
   const int n_mg = (n + 4 * MT - 1) / (4 * MT);
   const int64_t nwg = (G2 + 63) / 64 * n_mg * ((B + BC - 1) / BC);
   if (tr)
     hipLaunchKernelGGL((spec_product_kernel<T, MT, BC, true>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y, n, G2,
-                       B, n_mg, lgGx, lgGy, live);
+                       B, n_mg, lgGx, lgGy, live, idle);
   else
     hipLaunchKernelGGL((spec_product_kernel<T, MT, BC, false>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y, n,
-                       G2, B, n_mg, lgGx, lgGy, live);
+                       G2, B, n_mg, lgGx, lgGy, live, idle);
 }
 
 // register tile by batch width: 2 rows for one or two right-hand sides (a
@@ -627,7 +641,7 @@ void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2
 // right-hand sides otherwise (arithmetic per load)
 template <typename T>
 void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, bool tr, int lgGx, int lgGy,
-             hipStream_t s, const int* live) {
+             hipStream_t s, const int* live, const int* idle) {
   if (sizeof(T) == 4 && B >= 12) {  // matrix cores once a 16-wide RHS tile is mostly full
     constexpr int PK = 4 * R3M_SPEC_MFMA_KPW;
     const int n_mg = (n + kPM - 1) / kPM, n_bt = (B + kPB - 1) / kPB;
@@ -636,19 +650,19 @@ void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B
     if (tr)
       hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC, true>), dim3((unsigned)nwg),
                          dim3(256), 0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg,
-                         n_bt, n_kt, lgGx, lgGy, live);
+                         n_bt, n_kt, lgGx, lgGy, live, idle);
     else
       hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC, false>), dim3((unsigned)nwg),
                          dim3(256), 0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg,
-                         n_bt, n_kt, lgGx, lgGy, live);
+                         n_bt, n_kt, lgGx, lgGy, live, idle);
   } else if (B == 1)
-    launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
+    launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
   else if (B == 2)
-    launch_product<T, 2, 2>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
+    launch_product<T, 2, 2>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
   else if (B <= 4)
-    launch_product<T, 4, 4>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
+    launch_product<T, 4, 4>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
   else
-    launch_product<T, 4, 8>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
+    launch_product<T, 4, 8>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
 }
 
 // relaxed compaction: y[u][r] = sum over states s of ymacro[u][s n_a + r]
@@ -656,7 +670,8 @@ void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B
 template <typename T, typename YT>
 __global__ void __launch_bounds__(256)
 relaxed_sum_kernel(const RhsDev* __restrict__ rhs, const C2<T>* __restrict__ ym, int n, int n_a, int n_states,
-                   YT* __restrict__ y) {
+                   YT* __restrict__ y, const int* __restrict__ idle) {
+  if (idle && idle[blockIdx.y]) return;
   const RhsDev R = rhs[blockIdx.y];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)R.Lx * R.Ly * n_a) return;
@@ -676,7 +691,7 @@ relaxed_sum_kernel(const RhsDev* __restrict__ rhs, const C2<T>* __restrict__ ym,
 template <typename T, typename XT, typename YT>
 void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
                     void* work, hipStream_t s, const int* live, const double* wts = nullptr, bool tr = false,
-                    C2<T>* macro_out = nullptr) {
+                    C2<T>* macro_out = nullptr, const int* idle = nullptr) {
   const int n = Z->n;
   const int lgGx = ilog2(next_pow2(2 * Z->Dx + 1)), lgGy = ilog2(next_pow2(2 * Z->Dy + 1));
   const int64_t G2 = (int64_t)1 << (lgGx + lgGy);
@@ -695,17 +710,18 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
   A.ymacro = macro_out ? macro_out : wts ? Y + (size_t)B * n * G2 : nullptr;  // relaxed: [units][n] after Y
   A.macro_plain = macro_out ? 1 : 0;
   A.live = live;
+  A.idle = idle;
   const int64_t ng = (int64_t)B * n;
   A.data = X;
   fft_pass<T, kFwdRows, XT>(A, lgGx, lgGy, ng, s);
   fft_pass<T, kFwdCols, XT>(A, lgGx, lgGy, ng, s);
-  product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, tr, lgGx, lgGy, s, live);
+  product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
   A.data = Y;
   fft_pass<T, kInvCols, YT>(A, lgGx, lgGy, ng, s);
   fft_pass<T, kInvRows, YT>(A, lgGx, lgGy, ng, s);
   if (wts && !macro_out) {
     hipLaunchKernelGGL((relaxed_sum_kernel<T, YT>), dim3(ceil_div((size_t)bd.max_units * A.n_a, 256), B), dim3(256),
-                       0, s, bd.rhs, (const C2<T>*)A.ymacro, n, A.n_a, A.n_states, (YT*)y);
+                       0, s, bd.rhs, (const C2<T>*)A.ymacro, n, A.n_a, A.n_states, (YT*)y, idle);
     R3M_CHECK_HIP(hipGetLastError());
   }
 }
@@ -769,25 +785,26 @@ size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z) {
 
 void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                         const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
-                        const double* wts, bool tr) {
+                        const double* wts, bool tr, const int* idle) {
   const bool xd = x_type == R3M_C128, yd = y_type == R3M_C128;
   if (Z->far_dtype == R3M_SPEC_C128) {
     R3M_REQUIRE(xd && yd, R3M_ERR_UNSUPPORTED, "complex128 spectra need C128 vectors");
-    spectral_typed<double, double, double>(Z, bd, states, x, y, work, s, live, wts, tr);
+    spectral_typed<double, double, double>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle);
   } else if (xd && yd) {
-    spectral_typed<float, double, double>(Z, bd, states, x, y, work, s, live, wts, tr);
+    spectral_typed<float, double, double>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle);
   } else if (!xd && yd) {
-    spectral_typed<float, float, double>(Z, bd, states, x, y, work, s, live, wts, tr);
+    spectral_typed<float, float, double>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle);
   } else if (!xd && !yd) {
-    spectral_typed<float, float, float>(Z, bd, states, x, y, work, s, live, wts, tr);
+    spectral_typed<float, float, float>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle);
   } else {
     R3M_REQUIRE(false, R3M_ERR_UNSUPPORTED, "C128 input with C64 output");
   }
 }
 
 void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
-                     const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live) {
-  launch_spectral_ex(Z, bd, states, x_type, x, y_type, y, work, s, live, nullptr, false);
+                     const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
+                     const int* idle) {
+  launch_spectral_ex(Z, bd, states, x_type, x, y_type, y, work, s, live, nullptr, false, idle);
 }
 
 size_t relaxed_work_bytes(const BatchDesc& bd, const r3m_store* Z) { return spectral_work_bytes(bd, Z); }
