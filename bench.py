@@ -65,7 +65,7 @@ def parse():
                    help="inner GMRES tolerance of the refined legs (128x128 x 16 and 1,536 RHS)")
     p.add_argument("--relaxed-precond", type=int, default=2,
                    help="preconditioner of the differentiation leg (1 block-Jacobi, 2 block ILU(0) r = 1)")
-    p.add_argument("--no-batched", action="store_true", help="skip the 1,536-RHS batched solve leg (about 15 s)")
+    p.add_argument("--no-batched", action="store_true", help="skip the 1,536-RHS batched solve leg (about 12 s)")
     p.add_argument("--no-sweep", action="store_true",
                    help="skip the preconditioner study (iterations over Bernoulli p at 16x16)")
     p.add_argument("--no-spectral", action="store_true",

@@ -550,9 +550,11 @@ __global__ void sub_kernel(const double2* __restrict__ a, const double2* __restr
   out[r.off + k] = make_double2(u.x - v.x, u.y - v.y);
 }
 
+// x += d; st (nullable): only right-hand sides being solved
 __global__ void add_kernel(double2* __restrict__ x, const double2* __restrict__ d,
-                           const RhsVec* __restrict__ rv) {
+                           const RhsVec* __restrict__ rv, const RhsState* __restrict__ st) {
   const int b = blockIdx.y;
+  if (st && !st[b].active) return;
   const RhsVec r = rv[b];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= r.N) return;
@@ -686,9 +688,10 @@ template <typename OT>
 __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
                                      const int64_t* __restrict__ soff, const RhsVec* __restrict__ rv, int n_a,
                                      int n_states, const double2* __restrict__ in, OT* __restrict__ out,
-                                     const int* __restrict__ live, int per_unit) {
+                                     const int* __restrict__ live, int per_unit, const RhsState* __restrict__ st) {
   if (live && *live == 0) return;
   const int b = blockIdx.y;
+  if (st && !st[b].active) return;  // a right-hand side this cycle does not solve
   const RhsVec r = rv[b];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= r.N) return;
@@ -910,7 +913,7 @@ struct GmresRun {
       return;
     }
     hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff, W.rv,
-                       n_a, n_states, in, (double*)out, (const int*)nullptr, pu);
+                       n_a, n_states, in, (double*)out, (const int*)nullptr, pu, (const RhsState*)W.st);
   }
 
   // Running-RHS counts of Arnoldi step j live in two slots used in turn: step
@@ -931,10 +934,12 @@ struct GmresRun {
     } else if (pre) {
       if (c64)
         hipLaunchKernelGGL(apply_precond_kernel<float>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr, pu);
+                           W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr, pu,
+                           (const RhsState*)W.st);
       else
         hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (double*)W.xs, (const int*)nullptr, pu);
+                           W.rv, n_a, n_states, v, (double*)W.xs, (const int*)nullptr, pu,
+                           (const RhsState*)W.st);
     } else if (c64) {
       hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs,
                          (const int*)nullptr);
@@ -1120,7 +1125,7 @@ struct GmresRun {
         // x += M^{-1} (V y)
         hipLaunchKernelGGL(combine_basis_kernel, vgrid(), dim3(256), 0, s, W.V, W.g, W.pz, W.rv, W.st, m, ut);
         precond(W.pz, W.w);
-        hipLaunchKernelGGL(add_kernel, vgrid(), dim3(256), 0, s, sol, W.w, W.rv);
+        hipLaunchKernelGGL(add_kernel, vgrid(), dim3(256), 0, s, sol, W.w, W.rv, (const RhsState*)W.st);
       } else {
         hipLaunchKernelGGL(update_x_kernel, vgrid(), dim3(256), 0, s, W.V, W.g, sol, W.rv, W.st, m, ut);
       }
@@ -1352,7 +1357,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
         if (!any || step == max_refine) break;
         hipLaunchKernelGGL(zero_kernel, run.vgrid(), dim3(256), 0, stream, run.W.d, run.W.rv);
         run.solve(Z, run.W.ro, run.W.d, act, rn, opts->tol, opts->max_iter, iters, true);
-        hipLaunchKernelGGL(add_kernel, run.vgrid(), dim3(256), 0, stream, x, run.W.d, run.W.rv);
+        hipLaunchKernelGGL(add_kernel, run.vgrid(), dim3(256), 0, stream, x, run.W.d, run.W.rv,
+                           (const RhsState*)nullptr);
         for (int i = 0; i < bd.B; ++i) refine_steps[i] += act[i];
       }
     } else {

@@ -495,6 +495,9 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
 //  - with 8 or more, workgroup ids run over RHS tiles first and wrap around
 //    the XCDs, so each XCD keeps the same RHS tiles for every frequency tile
 //    and meets both halves of their X lines (the larger stream there).
+#ifndef R3M_SPEC_RHS_FIRST
+#define R3M_SPEC_RHS_FIRST 8  // RHS tiles from which ids run over RHS tiles first
+#endif
 constexpr int kPM = 80, kPB = 16;
 constexpr int kZP = kPM + 1, kXP = kPB + 1;
 
@@ -503,7 +506,8 @@ template <int KPW, int PC, bool TR>
 __global__ void __launch_bounds__(256)
 spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __restrict__ Xh, C2<float>* __restrict__ Yh,
                          int n, int64_t K, int B, int n_mg, int n_bt, int64_t n_tiles, int lgGx, int lgGy,
-                         const int* __restrict__ live, const int* __restrict__ idle) {
+                         const int* __restrict__ live, const int* __restrict__ idle,
+                         const int* __restrict__ tile_list, const int* __restrict__ n_live) {
   if (live && *live == 0) return;
   typedef float v4 __attribute__((ext_vector_type(4)));
   constexpr int PK = 4 * KPW;                   // frequencies per workgroup
@@ -513,27 +517,37 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
   __shared__ C2<float> Zs[PC * PK * kZP];  // [c][k][m]; reused as the output tile [b][m][k]
   __shared__ C2<float> Xs[PC * PK * kXP];  // [c][k][b]
   static_assert(16 * 16 * YP <= PC * PK * kZP, "output tile fits the staging buffer");
+  // RHS tiles to cover: all n_bt, or the nl live ones of tile_list (the
+  // launch is sized for both orders below)
+  const int nl = tile_list ? *n_live : n_bt;
   int bt, mg;
   int64_t kt;
-  if (n_bt < 8) {
-    const int64_t id = (int64_t)(blockIdx.x & 7) * (gridDim.x >> 3) + (blockIdx.x >> 3);  // grid: a multiple of 8
+  if (nl < R3M_SPEC_RHS_FIRST) {
+    const int64_t items = (n_tiles + 1) / 2 * 2 * n_mg * nl;
+    const int64_t per = (items + 7) / 8, loc = blockIdx.x >> 3;  // grid: a multiple of 8
+    if (loc >= per) return;
+    const int64_t id = (int64_t)(blockIdx.x & 7) * per + loc;
+    if (id >= items) return;
     const int kh = (int)(id & 1);
     const int64_t r0 = id >> 1;
-    bt = (int)(r0 % n_bt);
-    const int64_t r1 = r0 / n_bt;
+    const int bi = (int)(r0 % nl);
+    const int64_t r1 = r0 / nl;
     mg = (int)(r1 % n_mg);
     kt = (r1 / n_mg) * 2 + kh;
+    bt = tile_list ? tile_list[bi] : bi;
   } else {
     const int64_t id = blockIdx.x;
-    bt = (int)(id % n_bt);
-    const int64_t r1 = id / n_bt;
+    if (id >= n_tiles * n_mg * nl) return;
+    const int bi = (int)(id % nl);
+    const int64_t r1 = id / nl;
     mg = (int)(r1 % n_mg);
     kt = r1 / n_mg;
+    bt = tile_list ? tile_list[bi] : bi;
   }
   if (kt >= n_tiles) return;  // n_tiles: frequency tiles
   const int64_t k0 = kt * PK;
   const int m0 = mg * kPM, b0 = bt * kPB;
-  if (idle) {  // uniform over the workgroup: skip a tile of idle right-hand sides
+  if (idle && !tile_list) {  // uniform over the workgroup: skip a tile of idle right-hand sides
     bool any = false;
     for (int q = b0; q < min(b0 + kPB, B); ++q) any |= idle[q] == 0;
     if (!any) return;
@@ -616,6 +630,36 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
   }
 }
 
+// The live tiles of the matrix-core product (tiles of kPB right-hand sides
+// with any idle[b] == 0) in increasing order, and their count: one workgroup,
+// thread t takes a contiguous run of tiles, a scan of the counts places them.
+__global__ void __launch_bounds__(1024)
+live_tiles_kernel(const int* __restrict__ idle, int B, int n_bt, int* __restrict__ list, int* __restrict__ n_live) {
+  __shared__ int cnt[1024];
+  const int t = threadIdx.x;
+  const int per = (n_bt + 1023) / 1024;
+  const int t0 = min(n_bt, t * per), t1 = min(n_bt, t0 + per);
+  auto is_live = [&](int bt) {
+    for (int q = bt * kPB; q < min(bt * kPB + kPB, B); ++q)
+      if (idle[q] == 0) return true;
+    return false;
+  };
+  int c = 0;
+  for (int bt = t0; bt < t1; ++bt) c += is_live(bt) ? 1 : 0;
+  cnt[t] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = t >= o ? cnt[t - o] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  int at = cnt[t] - c;
+  for (int bt = t0; bt < t1; ++bt)
+    if (is_live(bt)) list[at++] = bt;
+  if (t == 1023) *n_live = cnt[1023];
+}
+
 #ifndef R3M_SPEC_MFMA_KPW
 #define R3M_SPEC_MFMA_KPW 2
 #endif
@@ -638,23 +682,38 @@ void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2
 
 // register tile by batch width: 2 rows for one or two right-hand sides (a
 // stream of the spectra wants many waves in flight), 4 rows x 4 or 8
-// right-hand sides otherwise (arithmetic per load)
+// right-hand sides otherwise (arithmetic per load).  tl: room for the
+// live-tile list of the matrix-core product (ceil(B / 16) + 1 ints), used
+// with idle flags on wide batches
 template <typename T>
 void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, bool tr, int lgGx, int lgGy,
-             hipStream_t s, const int* live, const int* idle) {
+             hipStream_t s, const int* live, const int* idle, int* tl) {
   if (sizeof(T) == 4 && B >= 12) {  // matrix cores once a 16-wide RHS tile is mostly full
     constexpr int PK = 4 * R3M_SPEC_MFMA_KPW;
     const int n_mg = (n + kPM - 1) / kPM, n_bt = (B + kPB - 1) / kPB;
     const int64_t n_kt = (G2 + PK - 1) / PK;
-    const int64_t nwg = n_bt < 8 ? ((n_kt + 1) / 2 * 2 * n_mg * n_bt + 7) / 8 * 8 : n_kt * n_mg * n_bt;
+    // contiguous per-XCD order for fewer than R3M_SPEC_RHS_FIRST tiles, RHS
+    // tiles first otherwise; with a live-tile list the kernel picks the order
+    // from the live count, so the launch covers both
+    const bool use_list = idle && tl && n_bt >= R3M_SPEC_RHS_FIRST;
+    const int64_t nwg_c =
+        ((n_kt + 1) / 2 * 2 * n_mg * (use_list ? R3M_SPEC_RHS_FIRST - 1 : n_bt) + 7) / 8 * 8;
+    const int64_t nwg_r = (n_kt * n_mg * n_bt + 7) / 8 * 8;
+    const int64_t nwg = use_list ? std::max(nwg_c, nwg_r) : n_bt < R3M_SPEC_RHS_FIRST ? nwg_c : nwg_r;
+    const int* list = use_list ? tl : nullptr;
+    const int* cnt = use_list ? tl + n_bt : nullptr;
+    if (use_list) {
+      hipLaunchKernelGGL(live_tiles_kernel, dim3(1), dim3(1024), 0, s, idle, B, n_bt, tl, tl + n_bt);
+      R3M_CHECK_HIP(hipGetLastError());
+    }
     if (tr)
       hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC, true>), dim3((unsigned)nwg),
                          dim3(256), 0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg,
-                         n_bt, n_kt, lgGx, lgGy, live, idle);
+                         n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt);
     else
       hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC, false>), dim3((unsigned)nwg),
                          dim3(256), 0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg,
-                         n_bt, n_kt, lgGx, lgGy, live, idle);
+                         n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt);
   } else if (B == 1)
     launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
   else if (B == 2)
@@ -688,6 +747,12 @@ relaxed_sum_kernel(const RhsDev* __restrict__ rhs, const C2<T>* __restrict__ ym,
   yv[1] = (YT)im;
 }
 
+size_t spectral_list_offset(const BatchDesc& bd, const r3m_store* Z) {
+  const size_t es = Z->far_dtype == R3M_SPEC_C128 ? 16 : 8;
+  const size_t G2 = (size_t)next_pow2(2 * Z->Dx + 1) * next_pow2(2 * Z->Dy + 1);
+  return (2 * (size_t)bd.B * Z->n * G2 * es + (size_t)bd.total_units * Z->n * es + 255) / 256 * 256;
+}
+
 template <typename T, typename XT, typename YT>
 void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
                     void* work, hipStream_t s, const int* live, const double* wts = nullptr, bool tr = false,
@@ -715,7 +780,8 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
   A.data = X;
   fft_pass<T, kFwdRows, XT>(A, lgGx, lgGy, ng, s);
   fft_pass<T, kFwdCols, XT>(A, lgGx, lgGy, ng, s);
-  product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
+  int* tl = (int*)((char*)work + spectral_list_offset(bd, Z));
+  product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl);
   A.data = Y;
   fft_pass<T, kInvCols, YT>(A, lgGx, lgGy, ng, s);
   fft_pass<T, kInvRows, YT>(A, lgGx, lgGy, ng, s);
@@ -776,11 +842,10 @@ void validate_spectral(const r3m_store* Z) {
               "displacement extent too large for the transform");
 }
 
-// X and Y grids, then the relaxed compaction's macro buffer [units][n]
+// X and Y grids, then the relaxed compaction's macro buffer [units][n], then
+// the live-tile list of the matrix-core product
 size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z) {
-  const size_t es = Z->far_dtype == R3M_SPEC_C128 ? 16 : 8;
-  const size_t G2 = (size_t)next_pow2(2 * Z->Dx + 1) * next_pow2(2 * Z->Dy + 1);
-  return 2 * (size_t)bd.B * Z->n * G2 * es + (size_t)bd.total_units * Z->n * es + 256;
+  return spectral_list_offset(bd, Z) + ((size_t)(bd.B + kPB - 1) / kPB + 1) * sizeof(int) + 256;
 }
 
 void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
