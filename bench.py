@@ -328,6 +328,7 @@ def batched_leg(ctx, args):
     m = args.batched_restart
     work = torch.empty(r3m.gmres_work_bytes(ctx, s64, batch, m, s128), dtype=torch.uint8, device=dev)
     mv = timed_matvec(r3m, ctx, s64, batch, b.to(torch.complex64), r3m.C64, 3)
+    _, flops, _ = spectral_cost(s64.n, 63, batch.B)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     # block-Jacobi: per-RHS ILU factors of the 1,536 RHS would not fit in HBM
@@ -339,7 +340,8 @@ def batched_leg(ctx, args):
     torch.cuda.empty_cache()
     return {"workload": "1-bit 384 codebooks (128 each at 32x32/48x48/64x64) x 4 angles = 1,536 RHS, block "
                         f"spectra (complex64 inner GMRES({m}) to 1e-3, complex128 refinement residual to 1e-6)",
-            "rhs": batch.B, "matvec_ms_c64": mv * 1e3, "solve_s": t, "solves_per_s": batch.B / t,
+            "rhs": batch.B, "matvec_ms_c64": mv * 1e3, "matvec_tflops_c64": flops / mv / 1e12,
+            "matvec_frac_fp32_peak": flops / mv / 1e12 / PEAK_FP32_VALU_TFLOPS, "solve_s": t, "solves_per_s": batch.B / t,
             "codebooks": len(w.codebooks), "codebooks_per_s": len(w.codebooks) / t,
             "converged": all(r[3] for r in rep), "max_rel_residual": max(r[2] for r in rep),
             "inner_iters_max": max(r[0] for r in rep), "refine_steps_max": max(r[1] for r in rep)}
