@@ -468,11 +468,11 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
       const int64_t u = k / n_a;
       const int mr = (int)(k % n_a);
       const int64_t sidx = per_unit ? r.off / n_a + u : min((int)states[soff[b] + u], n_states - 1);
-      const double2* M = Minv + ((size_t)sidx * n_a + mr) * n_a;
+      const double2* M = Minv + (size_t)sidx * n_a * n_a + mr;  // column-major
       const double2* vu = v_s + (threadIdx.x / n_a) * n_a;
       double2 acc = make_double2(0.0, 0.0);
       for (int c = 0; c < n_a; ++c) {
-        const double2 t = cmul(M[c], vu[c]);
+        const double2 t = cmul(M[(size_t)c * n_a], vu[c]);
         acc.x += t.x;
         acc.y += t.y;
       }
@@ -608,7 +608,7 @@ __global__ void nonfinite_kernel(const double2* __restrict__ v, const RhsVec* __
   if (!(isfinite(t.x) && isfinite(t.y))) atomicOr(flag, 4);
 }
 
-// Block-Jacobi inverses Z(0)[A(s), A(s)]^-1, one workgroup per state.
+// Block-Jacobi inverses Z(0)[A(s), A(s)]^-1 (column-major), one workgroup per state.
 // Dynamic LDS: (2 n_a^2 + n_a + 1) double2.
 template <typename S>
 __global__ void __launch_bounds__(256)
@@ -635,7 +635,7 @@ selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, int n_a,
   if (!gj_invert_na(aug, colk, n_a, &piv_row, flag)) return;
   for (int e = threadIdx.x; e < n_a * n_a; e += blockDim.x) {
     const int i = e / n_a, j = e % n_a;
-    Minv[(size_t)st * n_a * n_a + e] = aug[i * w + n_a + j];
+    Minv[(size_t)st * n_a * n_a + (size_t)j * n_a + i] = aug[i * w + n_a + j];  // column-major
   }
 }
 
@@ -678,7 +678,7 @@ relaxed_selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, 
   if (!gj_invert_na(aug, colk, n_a, &piv_row, flag)) return;
   for (int e = threadIdx.x; e < n_a * n_a; e += blockDim.x) {
     const int i = e / n_a, j = e % n_a;
-    Minv[(size_t)gu * n_a * n_a + e] = aug[i * w + n_a + j];
+    Minv[(size_t)gu * n_a * n_a + (size_t)j * n_a + i] = aug[i * w + n_a + j];  // column-major
   }
 }
 
@@ -698,11 +698,13 @@ __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uin
   const int64_t u = k / n_a;
   const int m = (int)(k % n_a);
   const int64_t s = per_unit ? r.off / n_a + u : min((int)states[soff[b] + u], n_states - 1);
-  const double2* M = Minv + ((size_t)s * n_a + m) * n_a;
+  // column-major blocks: the lanes of a unit (consecutive rows m) read
+  // consecutive entries for each column c
+  const double2* M = Minv + (size_t)s * n_a * n_a + m;
   const double2* v = in + r.off + u * n_a;
   double2 acc = make_double2(0.0, 0.0);
   for (int c = 0; c < n_a; ++c) {
-    const double2 t = cmul(M[c], v[c]);
+    const double2 t = cmul(M[(size_t)c * n_a], v[c]);
     acc.x += t.x;
     acc.y += t.y;
   }
