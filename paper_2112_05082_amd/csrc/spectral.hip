@@ -495,6 +495,10 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
 //  - with 8 or more, workgroup ids run over RHS tiles first and wrap around
 //    the XCDs, so each XCD keeps the same RHS tiles for every frequency tile
 //    and meets both halves of their X lines (the larger stream there).
+// Inside a solve the tiles are those with a live right-hand side (a list
+// built on the device each step), and the order follows their count: when
+// few are left, the contiguous order spreads them over all eight XCDs,
+// where the RHS-first order would put each tile on one XCD.
 #ifndef R3M_SPEC_RHS_FIRST
 #define R3M_SPEC_RHS_FIRST 8  // RHS tiles from which ids run over RHS tiles first
 #endif
