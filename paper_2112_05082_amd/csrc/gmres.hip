@@ -306,12 +306,13 @@ finish_partials_kernel(const double2* __restrict__ partial, int maxP, int nvec, 
 // the per-block parts of ||w||^2 summed once into out[b] (grid B)
 __global__ void __launch_bounds__(256)
 finish_norm_kernel(const double* __restrict__ npart, int maxB, const RhsVec* __restrict__ rv,
-                   double* __restrict__ out, const int* __restrict__ run_prev, const int* __restrict__ idle) {
+                   double* __restrict__ out, const int* __restrict__ run_prev, const int* __restrict__ idle,
+                   int nsub) {
   if (run_prev && *run_prev == 0) return;
   if (idle && idle[blockIdx.x]) return;
   __shared__ double2 sh[4];
   const int b = blockIdx.x;
-  const int64_t nb = (rv[b].N + 63) / 64;
+  const int64_t nb = (rv[b].N + 64 * nsub - 1) / (64 * nsub);  // gs_update_kernel's blocks
   double t = 0.0;
   for (int64_t q = threadIdx.x; q < nb; q += blockDim.x) t += npart[(size_t)b * maxB + q];
   const double2 s2 = block_sum2(make_double2(t, 0.0), sh);
@@ -321,15 +322,17 @@ finish_norm_kernel(const double* __restrict__ npart, int maxB, const RhsVec* __r
 // w -= sum_{i<nvec} h_i V_i with h_i the sum of the chunk partials of the
 // preceding dots_partials_kernel launch (n_part of them per vector; 0: one
 // per 1024 elements), taken by every block in the same fixed order (block 0 also records them in H: mode 0 H[i][j] = h_i, mode 1
-// H[i][j] += h_i).  A block takes 64 elements; its four waves take the vectors
-// i = q mod 4 (q = wave) and their sums are added in wave order.  With
-// do_norm, each block also writes its part of ||w||^2 to npart[b][block].
+// H[i][j] += h_i).  A block takes nsub runs of 64 elements in turn; its four
+// waves take the vectors i = q mod 4 (q = wave) and their sums are added in
+// wave order.  With do_norm, each block also writes its part of ||w||^2 to
+// npart[b][block].
 // Dynamic LDS: nvec double2.
 __global__ void __launch_bounds__(256)
 gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
                  const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int n_part,
                  int nvec, int64_t ut, int do_norm, double* __restrict__ npart, int maxB, double2* __restrict__ H,
-                 int m, int j, int mode, const int* __restrict__ run_prev, const int* __restrict__ idle) {
+                 int m, int j, int mode, const int* __restrict__ run_prev, const int* __restrict__ idle,
+                 int nsub) {
   if (run_prev && *run_prev == 0) return;
   if (idle && idle[blockIdx.y]) return;
   extern __shared__ double2 hb[];
@@ -337,7 +340,7 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
   __shared__ double2 part[3][64];
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
-  const int64_t nb = (r.N + 63) / 64;
+  const int64_t nb = (r.N + 64 * nsub - 1) / (64 * nsub);
   if ((int64_t)blockIdx.x >= nb) return;
   const int P = n_part > 0 ? n_part : (int)((r.N + kDotChunk - 1) / kDotChunk);
   for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
@@ -361,46 +364,50 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
   }
   __syncthreads();
   const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const int64_t k = (int64_t)blockIdx.x * 64 + e;
-  const bool live = k < r.N && st[b].active;
-  double2 acc = make_double2(0.0, 0.0);
-  if (live) {
-    const double2* vk = V + r.off + k;
-    int i = q;
-    for (; i + 12 < nvec; i += 16) {
-      const double2 v0 = vk[(int64_t)i * ut], v1 = vk[(int64_t)(i + 4) * ut];
-      const double2 v2 = vk[(int64_t)(i + 8) * ut], v3 = vk[(int64_t)(i + 12) * ut];
-      const double2 t0 = cmul(hb[i], v0), t1 = cmul(hb[i + 4], v1);
-      const double2 t2 = cmul(hb[i + 8], v2), t3 = cmul(hb[i + 12], v3);
-      acc.x += t0.x;
-      acc.y += t0.y;
-      acc.x += t1.x;
-      acc.y += t1.y;
-      acc.x += t2.x;
-      acc.y += t2.y;
-      acc.x += t3.x;
-      acc.y += t3.y;
-    }
-    for (; i < nvec; i += 4) {
-      const double2 t = cmul(hb[i], vk[(int64_t)i * ut]);
-      acc.x += t.x;
-      acc.y += t.y;
-    }
-  }
-  if (q > 0) part[q - 1][e] = acc;
-  __syncthreads();
+  const bool act = st[b].active;
   double nrm2 = 0.0;
-  if (q == 0 && live) {
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      acc.x += part[t][e].x;
-      acc.y += part[t][e].y;
+  for (int sb = 0; sb < nsub; ++sb) {  // uniform trip count: the barriers below are reached by all
+    const int64_t k = ((int64_t)blockIdx.x * nsub + sb) * 64 + e;
+    const bool live = k < r.N && act;
+    double2 acc = make_double2(0.0, 0.0);
+    if (live) {
+      const double2* vk = V + r.off + k;
+      int i = q;
+      for (; i + 12 < nvec; i += 16) {
+        const double2 v0 = vk[(int64_t)i * ut], v1 = vk[(int64_t)(i + 4) * ut];
+        const double2 v2 = vk[(int64_t)(i + 8) * ut], v3 = vk[(int64_t)(i + 12) * ut];
+        const double2 t0 = cmul(hb[i], v0), t1 = cmul(hb[i + 4], v1);
+        const double2 t2 = cmul(hb[i + 8], v2), t3 = cmul(hb[i + 12], v3);
+        acc.x += t0.x;
+        acc.y += t0.y;
+        acc.x += t1.x;
+        acc.y += t1.y;
+        acc.x += t2.x;
+        acc.y += t2.y;
+        acc.x += t3.x;
+        acc.y += t3.y;
+      }
+      for (; i < nvec; i += 4) {
+        const double2 t = cmul(hb[i], vk[(int64_t)i * ut]);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
     }
-    double2 wk = w[r.off + k];
-    wk.x -= acc.x;
-    wk.y -= acc.y;
-    w[r.off + k] = wk;
-    nrm2 = wk.x * wk.x + wk.y * wk.y;
+    if (q > 0) part[q - 1][e] = acc;
+    __syncthreads();
+    if (q == 0 && live) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        acc.x += part[t][e].x;
+        acc.y += part[t][e].y;
+      }
+      double2 wk = w[r.off + k];
+      wk.x -= acc.x;
+      wk.y -= acc.y;
+      w[r.off + k] = wk;
+      nrm2 += wk.x * wk.x + wk.y * wk.y;
+    }
+    __syncthreads();  // part is reused by the next run
   }
   if (!do_norm) return;
   const double2 t = block_sum2(make_double2(nrm2, 0.0), sh);
@@ -963,20 +970,26 @@ struct GmresRun {
     // long vectors (more than 64 chunk partials per coefficient): sum the
     // partials once in their own launch rather than in every update block
     const bool long_vec = maxP > 64;
+    // long vectors: each update block takes four runs of 64 elements (a
+    // quarter of the workgroups, which matters once most right-hand sides of
+    // a wide batch are idle and their workgroups only return); short ones
+    // keep one run so that the single-RHS solve has enough workgroups, and
+    // normalize_step_kernel sums their per-64 parts itself
+    const int nsub = long_vec ? 4 : 1;
     for (int pass = 0; pass < 2; ++pass) {
       hipLaunchKernelGGL(dots_partials_kernel, dgrid, dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, j + 1, maxP,
                          W.dpart, pass == 0 ? run_slot(j) : (int*)nullptr, live, W.idle);
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(j + 1, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
                            j + 1, W.rv, W.hsum, live, W.idle);
-      hipLaunchKernelGGL(gs_update_kernel, dim3(ceil_div((size_t)maxN, 64), B), dim3(256),
+      hipLaunchKernelGGL(gs_update_kernel, dim3(ceil_div((size_t)maxN, 64 * nsub), B), dim3(256),
                          (size_t)(j + 1) * sizeof(double2), s, W.V, W.w, W.rv, W.st,
                          long_vec ? (const double2*)W.hsum : (const double2*)W.dpart, long_vec ? 1 : maxP,
-                         long_vec ? 1 : 0, j + 1, ut, pass, W.npart, maxB, W.H, m, j, pass, live, W.idle);
+                         long_vec ? 1 : 0, j + 1, ut, pass, W.npart, maxB, W.H, m, j, pass, live, W.idle, nsub);
     }
     if (long_vec)
       hipLaunchKernelGGL(finish_norm_kernel, dim3(B), dim3(256), 0, s, (const double*)W.npart, maxB, W.rv, W.nsum,
-                         live, W.idle);
+                         live, W.idle, nsub);
     const double* np = long_vec ? W.nsum : W.npart;
     const int npB = long_vec ? 1 : maxB, npN = long_vec ? 1 : 0;
     // blocks of whole units (the preconditioner multiplies per unit)
