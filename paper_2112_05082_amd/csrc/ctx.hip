@@ -149,22 +149,9 @@ void validate_batch(const r3m_batch* batch, int Dx, int Dy) {
   }
 }
 
-const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int tile_h,
-                           hipStream_t stream) {
-  BatchKey key;
-  key.states = nullptr;  // the descriptor holds offsets only
-  key.v.push_back(tile_w);
-  key.v.push_back(tile_h);
-  for (int b = 0; b < batch->B; ++b) {
-    key.v.push_back(batch->L[2 * b]);
-    key.v.push_back(batch->L[2 * b + 1]);
-    key.v.push_back(batch->unit_off[b]);
-    key.v.push_back(batch->state_off[b]);
-  }
-  auto it = ctx->batches.find(key);
-  if (it != ctx->batches.end()) return *it->second;
-
-  auto* d = new BatchDesc();
+// Host side of a batch descriptor: the per-RHS table and the unit tiles,
+// packed as they are laid out on the device (rhs table, then tile table).
+void describe_batch(const r3m_batch* batch, int tile_w, int tile_h, BatchDesc* d, std::vector<char>& host) {
   d->B = batch->B;
   std::vector<RhsDev> rhs(batch->B);
   std::vector<TileDev> tiles;
@@ -192,15 +179,68 @@ const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int 
   }
   d->total_units = total;
   d->n_tiles = (int32_t)tiles.size();
-  size_t bytes = rhs.size() * sizeof(RhsDev) + tiles.size() * sizeof(TileDev);
-  std::vector<char> host(std::max<size_t>(bytes, 16));
+  const size_t bytes = rhs.size() * sizeof(RhsDev) + tiles.size() * sizeof(TileDev);
+  host.assign(std::max<size_t>(bytes, 16), 0);
   std::memcpy(host.data(), rhs.data(), rhs.size() * sizeof(RhsDev));
   std::memcpy(host.data() + rhs.size() * sizeof(RhsDev), tiles.data(), tiles.size() * sizeof(TileDev));
+}
+
+void point_batch(BatchDesc* d, void* dev) {
+  d->rhs = (const RhsDev*)dev;
+  d->tiles = (const TileDev*)((char*)dev + (size_t)d->B * sizeof(RhsDev));
+}
+
+std::vector<int64_t> batch_key(const r3m_batch* batch, int tile_w, int tile_h) {
+  std::vector<int64_t> v{tile_w, tile_h};
+  v.reserve(2 + 4 * (size_t)batch->B);
+  for (int b = 0; b < batch->B; ++b) {
+    v.push_back(batch->L[2 * b]);
+    v.push_back(batch->L[2 * b + 1]);
+    v.push_back(batch->unit_off[b]);
+    v.push_back(batch->state_off[b]);
+  }
+  return v;
+}
+
+// Bounded cache: when full, the descriptors no call of the current entry has
+// used are released, together with every captured graph and autotuned launch
+// shape (their keys hold descriptor addresses).
+static void evict_batches(r3m_ctx ctx) {
+  R3M_CHECK_HIP(hipDeviceSynchronize());  // queued work may still read the tables
+  for (auto it = ctx->batches.begin(); it != ctx->batches.end();) {
+    if (it->second->epoch != ctx->epoch) {
+      it->second->dev.release();
+      delete it->second;
+      it = ctx->batches.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  for (auto& kv : ctx->graphs) R3M_CHECK_HIP(hipGraphExecDestroy(kv.second));
+  ctx->graphs.clear();
+  ctx->tuned_groups.clear();
+}
+
+const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int tile_h,
+                           hipStream_t stream) {
+  BatchKey key;
+  key.states = nullptr;  // the descriptor holds offsets only
+  key.v = batch_key(batch, tile_w, tile_h);
+  auto it = ctx->batches.find(key);
+  if (it != ctx->batches.end()) {
+    it->second->epoch = ctx->epoch;
+    return *it->second;
+  }
+  if (ctx->batches.size() >= kMaxBatches) evict_batches(ctx);
+
+  auto* d = new BatchDesc();
+  std::vector<char> host;
+  describe_batch(batch, tile_w, tile_h, d, host);
   d->dev.ensure(host.size());
   R3M_CHECK_HIP(hipMemcpyAsync(d->dev.ptr, host.data(), host.size(), hipMemcpyHostToDevice, stream));
   R3M_CHECK_HIP(hipStreamSynchronize(stream));
-  d->rhs = (const RhsDev*)d->dev.ptr;
-  d->tiles = (const TileDev*)((char*)d->dev.ptr + rhs.size() * sizeof(RhsDev));
+  point_batch(d, d->dev.ptr);
+  d->epoch = ctx->epoch;
   ctx->batches[key] = d;
   return *d;
 }

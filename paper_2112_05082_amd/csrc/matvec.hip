@@ -14,6 +14,8 @@
 #include <cstdlib>
 #include "matvec_internal.h"
 
+#include <mutex>
+
 #include <algorithm>
 #include <hip/hip_fp16.h>
 #include <type_traits>
@@ -1345,3 +1347,4 @@ extern "C" int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_
   });
   return rc == R3M_OK ? out : rc;
 }
+

@@ -75,6 +75,7 @@ struct BatchDesc {
   std::vector<int64_t> unit_off, n_units;
   std::vector<int32_t> Lx, Ly;
   int64_t codebook_units = 0;  // units of the distinct codebooks (RhsDev::fac_off)
+  uint64_t epoch = 0;          // entry call that last used it (cache eviction)
 };
 
 struct RhsDev {
@@ -110,6 +111,7 @@ struct r3m_ctx_s {
   hipEvent_t ev_run[2] = {nullptr, nullptr};  // completion of those read-backs
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
   std::map<std::vector<int64_t>, int> tuned_groups;  // autotuned displacement groups per (store, batch)
+  uint64_t epoch = 0;  // counts entry calls (see get_batch)
 };
 
 namespace r3m {
@@ -127,8 +129,16 @@ struct GeomDev {
 void validate_geom(const r3m_unit_geom* g);
 GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream);
 
+// At most kMaxBatches descriptors are cached per context; a new one beyond
+// that releases those the current entry call has not used (and every captured
+// graph and autotuned launch shape, whose keys hold descriptor addresses).
+constexpr size_t kMaxBatches = 64;
 const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int tile_h,
                            hipStream_t stream);
+// host tables of a batch (rhs table, then tiles) and the device pointers into them
+void describe_batch(const r3m_batch* batch, int tile_w, int tile_h, BatchDesc* d, std::vector<char>& host);
+void point_batch(BatchDesc* d, void* dev);
+std::vector<int64_t> batch_key(const r3m_batch* batch, int tile_w, int tile_h);
 void validate_batch(const r3m_batch* batch, int Dx, int Dy);
 
 inline int32_t slot_of(int dx, int dy, int Dx, int Dy) { return (dy + Dy) * (2 * Dx + 1) + (dx + Dx); }
@@ -174,6 +184,7 @@ __host__ __device__ inline void quad7_point(int i, double& b0, double& b1, doubl
 // guarded entry: converts exceptions into status codes
 template <class F>
 int guarded(r3m_ctx ctx, F&& f) {
+  if (ctx) ++ctx->epoch;
   try {
     f();
     return R3M_OK;
