@@ -227,6 +227,26 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
  * r3m_status. */
 int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as r3m_retrieved_matvec, with the workspace taken from a static
+ * device scratch of R3M_STATIC_SCRATCH_BYTES that the library holds on each
+ * GPU until the process ends (the batch's device tables sit at its head).
+ * No device or pinned memory is allocated and no workspace is passed; the
+ * caller owns x and y as before.  The displacement-group count is the
+ * default one (no autotuning), so results agree with r3m_retrieved_matvec to
+ * rounding order, not bitwise.  R3M_ERR_BUFFER_TOO_SMALL when the batch needs
+ * more scratch than that (r3m_matvec_work_bytes plus the tables); use
+ * r3m_retrieved_matvec then.  Every call on a GPU shares that GPU's scratch
+ * and leaves its contents behind, so calls that overlap on one GPU (other
+ * streams or threads) race; R3M_BATCH_INDEX_READY refers to the index that
+ * the previous static call on this GPU left there.  A new batch layout
+ * uploads its tables and synchronises `stream`; otherwise asynchronous. */
+#define R3M_STATIC_SCRATCH_BYTES (64u << 20)
+size_t r3m_static_scratch_bytes(void);
+int r3m_retrieved_matvec_static(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, r3m_dtype vec_dtype,
+                                const void* x_dev, void* y_dev, hipStream_t stream);
+
 /* ------------------------------------------------------ relaxed codebook -- */
 
 /* Relaxed (blended) retrieval, the operator of codebook differentiation: unit

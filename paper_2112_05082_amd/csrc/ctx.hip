@@ -266,6 +266,7 @@ int r3m_ctx_create(r3m_ctx* out, int device) {
     ctx->device = device;
     ctx->flag.ensure(256);
     R3M_CHECK_HIP(hipMemset(ctx->flag.ptr, 0, 256));
+    init_static_scratch(device);
   });
   if (rc != R3M_OK) {
     delete ctx;

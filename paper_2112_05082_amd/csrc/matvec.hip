@@ -1348,3 +1348,75 @@ extern "C" int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_
   return rc == R3M_OK ? out : rc;
 }
 
+// ------------------------------------------------- allocation-free variant
+//
+// The library's own device scratch for r3m_retrieved_matvec_static: one copy
+// per GPU, held until the process ends.  In host code `scratch` names a
+// host-side stand-in, never the device memory: the device address is looked
+// up once per device (init_static_scratch, at context creation) and only that
+// address is used.
+static __device__ __align__(256) unsigned char scratch[R3M_STATIC_SCRATCH_BYTES];
+
+namespace r3m {
+namespace {
+struct StaticScratch {
+  void* ptr = nullptr;           // device address of `scratch` on this GPU
+  std::vector<int64_t> key;      // batch layout whose tables sit at its head
+};
+std::mutex g_scratch_mu;
+std::map<int, StaticScratch> g_scratch;  // device -> state
+}  // namespace
+
+void init_static_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  StaticScratch& s = g_scratch[device];
+  if (s.ptr) return;
+  void* p = nullptr;
+  R3M_CHECK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  R3M_REQUIRE(p, R3M_ERR_HIP, "static scratch has no device address");
+  s.ptr = p;
+}
+}  // namespace r3m
+
+extern "C" size_t r3m_static_scratch_bytes(void) { return (size_t)R3M_STATIC_SCRATCH_BYTES; }
+
+extern "C" int r3m_retrieved_matvec_static(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch,
+                                           r3m_dtype vec_dtype, const void* x_dev, void* y_dev,
+                                           hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_store(Z);
+    validate_batch(batch, Z->Dx, Z->Dy);
+    R3M_REQUIRE(vec_dtype == R3M_C128 || vec_dtype == R3M_C64, R3M_ERR_UNSUPPORTED,
+                "vectors must be C128 or C64");
+    if (batch->B == 0) return;
+    R3M_REQUIRE(x_dev && y_dev, R3M_ERR_INVALID_ARG, "x or y is NULL");
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch.find(ctx->device);
+    R3M_REQUIRE(it != g_scratch.end() && it->second.ptr, R3M_ERR_HIP, "static scratch not set up on this device");
+    StaticScratch& sc = it->second;
+    // the batch tables at the head of the scratch, then the matvec workspace
+    BatchDesc bd;
+    std::vector<char> host;
+    describe_batch(batch, kBW, kBH, &bd, host);
+    const size_t head = (host.size() + 255) / 256 * 256;
+    const int groups = choose_chunks(bd, 64);
+    const size_t need = head + matvec_partial_bytes(bd, Z, max_groups(bd));
+    R3M_REQUIRE(need <= (size_t)R3M_STATIC_SCRATCH_BYTES, R3M_ERR_BUFFER_TOO_SMALL,
+                "batch needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                    std::to_string((size_t)R3M_STATIC_SCRATCH_BYTES) + " (use r3m_retrieved_matvec)");
+    std::vector<int64_t> key = batch_key(batch, kBW, kBH);
+    if (key != sc.key) {
+      R3M_CHECK_HIP(hipMemcpyAsync(sc.ptr, host.data(), host.size(), hipMemcpyHostToDevice, stream));
+      // the host copy of the tables is released when this call returns
+      R3M_CHECK_HIP(hipStreamSynchronize(stream));
+      sc.key.swap(key);
+    }
+    point_batch(&bd, sc.ptr);
+    char* work = (char*)sc.ptr + head;
+    if (!(batch->flags & R3M_BATCH_INDEX_READY))
+      build_near_lists(Z, bd, batch->states, workspace_lists(work, bd, Z), stream);
+    launch_matvec(ctx, Z, bd, batch->states, vec_dtype, x_dev, y_dev, work, nullptr, groups, stream);
+  });
+}

@@ -139,6 +139,9 @@ const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int 
 void describe_batch(const r3m_batch* batch, int tile_w, int tile_h, BatchDesc* d, std::vector<char>& host);
 void point_batch(BatchDesc* d, void* dev);
 std::vector<int64_t> batch_key(const r3m_batch* batch, int tile_w, int tile_h);
+// looks up the device address of the library's static scratch on `device`
+// (current), once per device; called by r3m_ctx_create
+void init_static_scratch(int device);
 void validate_batch(const r3m_batch* batch, int Dx, int Dy);
 
 inline int32_t slot_of(int dx, int dy, int Dx, int Dy) { return (dy + Dy) * (2 * Dx + 1) + (dx + Dx); }

@@ -34,6 +34,7 @@ EXPORTED = (
     "r3m_spectral_bytes", "r3m_build_spectral", "r3m_relaxed_work_bytes", "r3m_relaxed_matvec",
     "r3m_relaxed_gradient_work_bytes", "r3m_relaxed_gradient", "r3m_relaxed_rhs", "r3m_relaxed_objective",
     "r3m_matvec_work_bytes", "r3m_retrieved_matvec", "r3m_matvec_groups",
+    "r3m_static_scratch_bytes", "r3m_retrieved_matvec_static",
     "r3m_gmres_work_bytes", "r3m_gmres_solve", "r3m_ilu_bytes", "r3m_ilu_factor", "r3m_ilu_apply",
     "r3m_plane_wave_rhs", "r3m_rcs",
 )
@@ -127,6 +128,8 @@ def load(path: str = LIB_PATH):
         "r3m_retrieved_matvec": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int, vp, vp, vp,
                                            sz, vp]),
         "r3m_matvec_groups": (i32, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
+        "r3m_static_scratch_bytes": (sz, []),
+        "r3m_retrieved_matvec_static": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int, vp, vp, vp]),
         "r3m_gmres_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(StoreC), C.POINTER(BatchC),
                                       C.POINTER(GmresOptsC)]),
         "r3m_gmres_solve": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(StoreC), C.POINTER(BatchC), vp, vp,
@@ -389,6 +392,26 @@ def r3m_retrieved_matvec(ctx: Context, store: Store, batch: Batch, vec_dtype: in
                                         _stream(stream)), ctx.handle)
     finally:
         batch.cs.flags = 0
+
+
+def r3m_retrieved_matvec_static(ctx: Context, store: Store, batch: Batch, vec_dtype: int, x, y, stream=None,
+                                index_ready: bool = False):
+    """r3m_retrieved_matvec with the library's static device scratch (no workspace)."""
+    lib = load()
+    _need_vec(x, batch, store.n // store.n_states, "x")
+    _need_vec(y, batch, store.n // store.n_states, "y")
+    sc = store.c()
+    batch.cs.flags = BATCH_INDEX_READY if index_ready else 0
+    try:
+        _check(lib.r3m_retrieved_matvec_static(ctx.handle, C.byref(sc), C.byref(batch.cs), vec_dtype,
+                                               C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                                               _stream(stream)), ctx.handle)
+    finally:
+        batch.cs.flags = 0
+
+
+def static_scratch_bytes() -> int:
+    return int(load().r3m_static_scratch_bytes())
 
 
 def r3m_gmres_solve(ctx: Context, store: Store, store64: Store | None, batch: Batch, b, x, tol: float,

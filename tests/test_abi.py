@@ -51,6 +51,7 @@ def test_version_and_size_queries():
     assert r3m.spectral_bytes(80, 3, 2, r3m.SPEC_C128) == 80 * 80 * 8 * 8 * 16
     assert r3m.spectral_bytes(80, 0, 4, r3m.SPEC_C64) == 80 * 80 * 2 * 16 * 8
     assert r3m.spectral_bytes(80, 3, 3, r3m.C64) == 0
+    assert r3m.static_scratch_bytes() == 64 << 20
 
 
 def test_ctx_create_without_gpu_reports_hip_error():
