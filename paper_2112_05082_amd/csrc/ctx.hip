@@ -2,6 +2,7 @@
 #include "r3m_common.h"
 
 #include <algorithm>
+#include <array>
 
 namespace r3m {
 
@@ -154,9 +155,12 @@ void validate_batch(const r3m_batch* batch, int Dx, int Dy) {
 void describe_batch(const r3m_batch* batch, int tile_w, int tile_h, BatchDesc* d, std::vector<char>& host) {
   d->B = batch->B;
   std::vector<RhsDev> rhs(batch->B);
-  std::vector<TileDev> tiles;
+  std::vector<TileDev> tiles, gtiles;
+  std::vector<GroupDev> groups;
   int64_t total = 0;
   std::map<std::vector<int64_t>, int64_t> codebook_at;  // (state_off, Lx, Ly) -> fac_off
+  std::map<std::vector<int64_t>, int32_t> open_group;   // (state_off, Lx, Ly) -> group being filled
+  std::vector<std::array<int32_t, 3>> gshape;           // group -> (Lx, Ly, first tile) for its tiles
   for (int b = 0; b < batch->B; ++b) {
     int Lx = batch->L[2 * b], Ly = batch->L[2 * b + 1];
     const std::vector<int64_t> ck{batch->state_off[b], Lx, Ly};
@@ -176,18 +180,50 @@ void describe_batch(const r3m_batch* batch, int tile_w, int tile_h, BatchDesc* d
     d->max_units = std::max<int64_t>(d->max_units, (int64_t)Lx * Ly);
     for (int ty = 0; ty < Ly; ty += tile_h)
       for (int tx = 0; tx < Lx; tx += tile_w) tiles.push_back(TileDev{b, tx, ty, 0});
+    auto g = open_group.find(ck);
+    if (g == open_group.end() || groups[g->second].n == kGroupRhs) {
+      GroupDev nw{};
+      nw.n = 0;
+      groups.push_back(nw);
+      gshape.push_back({Lx, Ly, 0});
+      open_group[ck] = (int32_t)groups.size() - 1;
+      g = open_group.find(ck);
+    }
+    GroupDev& gd = groups[g->second];
+    gd.rhs[gd.n++] = b;
+    d->max_group_rhs = std::max(d->max_group_rhs, gd.n);
+  }
+  // group tiles: tile_w wide, and tile_h divided by the group's right-hand
+  // sides (rounded up to a power of two) tall
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    GroupDev& gd = groups[gi];
+    gd.th = group_tile_h(tile_h, gd.n);
+    for (int ty = 0; ty < gshape[gi][1]; ty += gd.th)
+      for (int tx = 0; tx < gshape[gi][0]; tx += tile_w) gtiles.push_back(TileDev{(int32_t)gi, tx, ty, 0});
   }
   d->total_units = total;
   d->n_tiles = (int32_t)tiles.size();
-  const size_t bytes = rhs.size() * sizeof(RhsDev) + tiles.size() * sizeof(TileDev);
-  host.assign(std::max<size_t>(bytes, 16), 0);
-  std::memcpy(host.data(), rhs.data(), rhs.size() * sizeof(RhsDev));
-  std::memcpy(host.data() + rhs.size() * sizeof(RhsDev), tiles.data(), tiles.size() * sizeof(TileDev));
+  d->n_groups = (int32_t)groups.size();
+  d->n_gtiles = (int32_t)gtiles.size();
+  const size_t b_rhs = rhs.size() * sizeof(RhsDev), b_t = tiles.size() * sizeof(TileDev);
+  const size_t b_g = groups.size() * sizeof(GroupDev), b_gt = gtiles.size() * sizeof(TileDev);
+  host.assign(std::max<size_t>(b_rhs + b_t + b_g + b_gt, 16), 0);
+  char* h = host.data();
+  std::memcpy(h, rhs.data(), b_rhs);
+  std::memcpy(h + b_rhs, tiles.data(), b_t);
+  std::memcpy(h + b_rhs + b_t, groups.data(), b_g);
+  std::memcpy(h + b_rhs + b_t + b_g, gtiles.data(), b_gt);
 }
 
 void point_batch(BatchDesc* d, void* dev) {
-  d->rhs = (const RhsDev*)dev;
-  d->tiles = (const TileDev*)((char*)dev + (size_t)d->B * sizeof(RhsDev));
+  char* p = (char*)dev;
+  d->rhs = (const RhsDev*)p;
+  p += (size_t)d->B * sizeof(RhsDev);
+  d->tiles = (const TileDev*)p;
+  p += (size_t)d->n_tiles * sizeof(TileDev);
+  d->groups = (const GroupDev*)p;
+  p += (size_t)d->n_groups * sizeof(GroupDev);
+  d->gtiles = (const TileDev*)p;
 }
 
 std::vector<int64_t> batch_key(const r3m_batch* batch, int tile_w, int tile_h) {

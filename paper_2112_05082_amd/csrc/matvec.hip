@@ -917,6 +917,521 @@ far_near_kernel(FarArgs<S> F, NearArgs<S> N, int near_wgs, const int* __restrict
     far_body<S, QS, kRch, FT>(F, blockIdx.x - near_wgs);
 }
 
+// ----------------------------------------------------------------- far field
+// on the matrix cores.
+//
+// Work item: a tile of observer units (8 wide, th tall) of one codebook with
+// the right-hand sides that share the codebook (a group of up to kGroupRhs;
+// th shrinks as the group grows), and the rows dy = g, g + G, ... of the
+// tile's displacement rectangle.  Per displacement d the low-rank block
+// (Sec. II-B) acts on column (observer slot i, right-hand side) in two steps,
+//     t = V(d)[A(s_j), :]^H x_j   (j = i - d),     y_i += U(d)[A(s_i), :] t,
+// both evaluated as real-form GEMMs on 16x16x4 FP32 MFMA tiles.  A row of
+// displacements is swept in runs of kRun consecutive dx.  The sources of a
+// run form a window of kRing columns of units that slides by kRun columns
+// from run to run; it is held in an LDS ring, so each source's x is read
+// once per displacement row rather than once per displacement.
+//  - First product: rows are the run's (displacement, rank, re/im) stacked,
+//    K is (basis function, re/im), columns are the window's (source,
+//    right-hand side) pairs grouped by source state (one row block A(b) of V
+//    per column tile).
+//  - Second product: rows are (basis function, re/im) of the observer state,
+//    K is the run's (displacement, rank, re/im), columns are the tile's
+//    (observer, right-hand side) pairs grouped by observer state (fixed for
+//    the tile); the accumulators stay in registers for the whole work item.
+// The run's ranks are taken KC / 2 at a time (a sub-chunk); t passes between
+// the two products through LDS.  A work item writes its own partial slot, one
+// write per (unit, right-hand side), so the sum over the G slots
+// (reduce_groups_kernel) has a fixed order.
+constexpr int kRun = 4;                    // displacements per run (consecutive dx)
+constexpr int kRing = 8 + kRun - 1;        // source columns of a run's window
+constexpr int kFNA = 40;                   // active RWG per unit on this path
+constexpr int kXS = kFNA + 2;              // complex per window row in LDS (padded: rows 8 banks apart)
+constexpr int kWinRows = 8;                // window rows per source column: th rows x (8 / th) rhs slots
+constexpr int kWinCols = kRing * kWinRows;
+constexpr int kP1Tiles = (kWinCols + 15 * 4 + 15) / 16;  // column tiles of the first product
+constexpr int kP2Tiles = (64 + 15 * 4 + 15) / 16;        // ... of the second product
+constexpr int kStLds = 4096;               // codebooks up to this many units keep their states in LDS
+
+struct FarMArgs {
+  const RhsDev* rhs;
+  const GroupDev* groups;
+  const TileDev* gtiles;  // TileDev.b: group
+  int n_gtiles, n_dgroups;
+  const uint8_t* states;
+  const float* farf;      // factors (store format)
+  const int* ranks;
+  const float* fscale;    // F16X2 column scales, else NULL
+  int max_rank, Dx, Dy, nr;
+  const float* x;         // vectors in FP32
+  float* out;             // partial slot 0
+  int64_t total_units;
+  const int* idle;        // per right-hand side (nullable)
+};
+
+// dynamic LDS of far_mfma_body: the x ring, the factor columns of a
+// sub-chunk (rows padded by two), the t buffer and the codebook states
+template <int KC, int NS>
+__host__ __device__ constexpr size_t far_mfma_lds_bytes() {
+  return (size_t)kWinCols * kXS * 8 + 2 * (size_t)(KC / 2) * (NS * kFNA + 2) * 8 +
+         (size_t)kP1Tiles * 16 * (KC + 4) * 4 + kStLds;
+}
+
+template <int FT, int CTW, int KC, int NS>
+__device__ __forceinline__ void far_mfma_body(const FarMArgs& A, int wg) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  constexpr int KR = KC / 2, TS = KC + 4, n = NS * kFNA, NP = n + 2, MT1 = KC / 16;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ int16_t p2tab[kP2Tiles * 16];   // second product: column -> slot | q << 8, or -1
+  __shared__ uint8_t ct2_state[kP2Tiles];
+  __shared__ int16_t p1tab[kP1Tiles * 16];   // first product: column -> window row, or -1
+  __shared__ int16_t p1col[kWinCols];        // window position (slot th + wy) -> first column, or -1
+  __shared__ uint8_t ct1_state[kP1Tiles];
+  __shared__ int nct1_s, nct2_s;
+  __shared__ int64_t g_uoff[kGroupRhs];
+
+  int ti, g;
+  if (!decode_wg(wg, A.n_gtiles, A.n_dgroups, ti, g)) return;
+  const TileDev tl = A.gtiles[ti];
+  const GroupDev* __restrict__ G = A.groups + tl.b;  // read in place (indexed at run time)
+  const int nrhs = G->n, th = G->th;
+  const int lth = th == 8 ? 3 : th == 4 ? 2 : 1;      // th = 8 / (rhs slots per row)
+  const int lq = 3 - lth;                              // log2 of the rhs slots per window row
+  if (A.idle) {
+    bool live = false;
+    for (int q = 0; q < nrhs; ++q) live |= A.idle[G->rhs[q]] == 0;
+    if (!live) return;  // uniform over the workgroup
+  }
+  const RhsDev R = A.rhs[G->rhs[0]];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int nl = lane & 15, kk = lane >> 4;
+  Cx<float>* Xr = reinterpret_cast<Cx<float>*>(smem_raw);  // [ring slot][kWinRows][kXS]: the window
+  Cx<float>* Uc = Xr + kWinCols * kXS;                      // [KR][NP]
+  Cx<float>* Vc = Uc + KR * NP;                             // [KR][NP]
+  float* Tb = reinterpret_cast<float*>(Vc + KR * NP);       // [first-product column][TS]
+  uint8_t* sts = reinterpret_cast<uint8_t*>(Tb + kP1Tiles * 16 * TS);
+  const int64_t units = (int64_t)R.Lx * R.Ly;
+  const bool st_lds = units <= kStLds;
+  if (st_lds)
+    for (int64_t u = tid; u < units; u += blockDim.x) sts[u] = A.states[R.state_off + u];
+  __syncthreads();
+  // state of unit (jx, jy), or NS outside the array
+  auto state_at = [&](int jx, int jy) -> int {
+    if (jx < 0 || jx >= R.Lx || jy < 0 || jy >= R.Ly) return NS;
+    const int64_t u = (int64_t)jy * R.Lx + jx;
+    return min((int)(st_lds ? sts[u] : A.states[R.state_off + u]), NS - 1);
+  };
+  // ring slot of source column jx (jx > -kRing * 64)
+  auto ring = [](int jx) { return (int)((unsigned)(jx + kRing * 64) % (unsigned)kRing); };
+
+  // wave 0: the tile's (observer, rhs) columns grouped by observer state
+  if (wave == 0) {
+    const int sx = lane & 7, sy = lane >> 3;
+    const int st = lane < 8 * th ? state_at(tl.tx + sx, tl.ty + sy) : NS;
+    int base = 0, nt = 0;
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+      const uint64_t m = __ballot(st == a);
+      const int cnt = __popcll(m);
+      const int rank =
+          __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+      if (st == a)
+        for (int q = 0; q < nrhs; ++q) p2tab[base + rank * nrhs + q] = (int16_t)(lane | q << 8);
+      const int used = cnt * nrhs, tiles = (used + 15) >> 4;
+      for (int c = used + lane; c < tiles * 16; c += 64) p2tab[base + c] = -1;
+      if (lane < tiles) ct2_state[nt + lane] = (uint8_t)a;
+      base += tiles * 16;
+      nt += tiles;
+    }
+    if (lane == 0) nct2_s = nt;
+    if (lane < nrhs) g_uoff[lane] = A.rhs[G->rhs[lane]].unit_off;
+  }
+
+  // displacements keeping a source of the tile in the array: a rectangle
+  const int bx_hi = min(tl.tx + 8, R.Lx) - 1, by_hi = min(tl.ty + th, R.Ly) - 1;
+  const int dx_lo = tl.tx - (R.Lx - 1), dy_lo = tl.ty - (R.Ly - 1);
+  const int wdy = by_hi - dy_lo + 1;
+  const int fstride = 2 * A.max_rank * n * 2;  // floats per far block
+  auto col_scale = [&](int f, int col) -> float {
+    return FT == R3M_F16X2 ? A.fscale[(size_t)f * 2 * A.max_rank + col] : 1.0f;
+  };
+
+  v4 acc[CTW][5];
+#pragma unroll
+  for (int q = 0; q < CTW; ++q)
+#pragma unroll
+    for (int mt = 0; mt < 5; ++mt) acc[q][mt] = v4{0, 0, 0, 0};
+  __syncthreads();
+  const int nct2 = nct2_s;
+  // this lane's second-product columns: observer slot and rhs of each tile it serves
+  int o_sx[CTW], o_sy[CTW], o_q[CTW];
+  bool o_ok[CTW];
+#pragma unroll
+  for (int qi = 0; qi < CTW; ++qi) {
+    const int ct2 = wave + 4 * qi;
+    const int ent = ct2 < nct2 ? p2tab[ct2 * 16 + nl] : -1;
+    o_ok[qi] = ent >= 0;
+    o_sx[qi] = ent & 7;
+    o_sy[qi] = (ent & 0xff) >> 3;
+    o_q[qi] = ent >> 8;
+  }
+
+  // A step is one sub-chunk (KR ranks) of one run (kRun consecutive dx of a
+  // displacement row).  Steps are software-pipelined: while a step computes,
+  // the next step's window columns and factor columns are fetched into
+  // registers, then stored to LDS where the current step no longer reads
+  // them, so each step needs two barriers.
+  struct Run {
+    int dy, dxa, nrun, jlo, jhi, new_hi, jy0, f0, f1, f2, f3, p1, p2, p3, nrk;
+  };
+  auto make_run = [&](int row, int dxa) {
+    Run r;
+    r.dy = dy_lo + row;
+    r.dxa = dxa;
+    r.nrun = min(kRun, bx_hi - dxa + 1);
+    r.jhi = tl.tx - dxa + 7;
+    r.jlo = tl.tx - dxa - r.nrun + 1;
+    r.new_hi = dxa == dx_lo ? r.jhi : tl.tx - dxa;  // columns the previous run of the row did not hold
+    r.jy0 = tl.ty - r.dy;
+    r.f0 = r.f1 = r.f2 = r.f3 = 0;
+    auto blk = [&](int dl, int& f) {
+      const int dx = dxa + dl;
+      if (dl < r.nrun && ((dx < 0 ? -dx : dx) > A.nr || (r.dy < 0 ? -r.dy : r.dy) > A.nr)) {
+        f = far_index(dx, r.dy, A.Dx, A.Dy, A.nr);
+        return min(A.ranks[f], A.max_rank);
+      }
+      return 0;
+    };
+    r.p1 = blk(0, r.f0);
+    r.p2 = r.p1 + blk(1, r.f1);
+    r.p3 = r.p2 + blk(2, r.f2);
+    r.nrk = r.p3 + blk(3, r.f3);
+    return r;
+  };
+  static_assert(kRun == 4, "the run's blocks are unrolled for four displacements");
+  // run rank rho -> displacement dl of the run
+  auto rank_dl = [](const Run& r, int rho) {
+    return (rho >= r.p1 ? 1 : 0) + (rho >= r.p2 ? 1 : 0) + (rho >= r.p3 ? 1 : 0);
+  };
+  // factor columns of run ranks [k0, k0 + KR): fetch (to registers), then store
+  constexpr int kPairIt = (KR * n / 2 + 255) / 256;
+  Cx<float> fu[2 * kPairIt], fv[2 * kPairIt];
+  auto fetch_f = [&](const Run& r, int k0) {
+    const int nk = min(KR, r.nrk - k0);
+#pragma unroll
+    for (int it = 0; it < kPairIt; ++it) {
+      const int e2 = 2 * (tid + it * 256);
+      if (e2 < nk * n) {
+        const int rl = e2 / n, rw = e2 - rl * n;
+        const int rho = k0 + rl, dl = rank_dl(r, rho);
+        const int f = dl == 0 ? r.f0 : dl == 1 ? r.f1 : dl == 2 ? r.f2 : r.f3;
+        const int rr = rho - (dl == 0 ? 0 : dl == 1 ? r.p1 : dl == 2 ? r.p2 : r.p3);
+        const float* Uf = A.farf + (size_t)f * fstride;
+        load_factor2<float, FT>(Uf + (size_t)rr * n * 2, rw, col_scale(f, rr), fu[2 * it], fu[2 * it + 1]);
+        load_factor2<float, FT>(Uf + (size_t)(A.max_rank + rr) * n * 2, rw, col_scale(f, A.max_rank + rr),
+                                fv[2 * it], fv[2 * it + 1]);
+      }
+    }
+  };
+  auto store_f = [&](const Run& r, int k0, bool u, bool v) {
+    const int nk = min(KR, r.nrk - k0);
+#pragma unroll
+    for (int it = 0; it < kPairIt; ++it) {
+      const int e2 = 2 * (tid + it * 256);
+      if (e2 < nk * n) {
+        const int rl = e2 / n, rw = e2 - rl * n;
+        if (u) {
+          Uc[rl * NP + rw] = fu[2 * it];
+          Uc[rl * NP + rw + 1] = fu[2 * it + 1];
+        }
+        if (v) {
+          Vc[rl * NP + rw] = fv[2 * it];
+          Vc[rl * NP + rw + 1] = fv[2 * it + 1];
+        }
+      }
+    }
+  };
+  // new window columns of a run (x of every right-hand side), window row
+  // wr = wy << lq | q: fetch (to registers), then store into the ring
+  constexpr int kPer = kWinRows * (kFNA / 2);            // float4 per window column
+  constexpr int kColIt = (kRun * kPer + 255) / 256;       // float4 per thread, kRun columns
+  v4 fx[kColIt];
+  // columns [r.jlo + c0, r.jlo + c0 + kRun) of the new ones (c0 = 0 for a run
+  // inside a row, 0, 4, 8 for the first run of a row)
+  auto fetch_x = [&](const Run& r, int c0) {
+    const int total = min(kRun, r.new_hi - r.jlo + 1 - c0) * kPer;
+#pragma unroll
+    for (int it = 0; it < kColIt; ++it) {
+      const int e4 = tid + it * 256;
+      fx[it] = v4{0, 0, 0, 0};
+      if (e4 < total) {
+        const int c = e4 / kPer, rem = e4 - c * kPer;
+        const int wr = rem / (kFNA / 2), part = rem - wr * (kFNA / 2);
+        const int wy = wr >> lq, q = wr & ((1 << lq) - 1);
+        const int jx = r.jlo + c0 + c, jy = r.jy0 + wy;
+        if (q < nrhs && jx >= 0 && jx < R.Lx && jy >= 0 && jy < R.Ly)
+          fx[it] = *reinterpret_cast<const v4*>(A.x + ((size_t)(g_uoff[q] + (int64_t)jy * R.Lx + jx) * kFNA) * 2 +
+                                                4 * part);
+      }
+    }
+  };
+  auto store_x = [&](const Run& r, int c0) {
+    const int total = min(kRun, r.new_hi - r.jlo + 1 - c0) * kPer;
+#pragma unroll
+    for (int it = 0; it < kColIt; ++it) {
+      const int e4 = tid + it * 256;
+      if (e4 < total) {
+        const int c = e4 / kPer, rem = e4 - c * kPer;
+        const int wr = rem / (kFNA / 2), part = rem - wr * (kFNA / 2);
+        *reinterpret_cast<v4*>(Xr + (ring(r.jlo + c0 + c) * kWinRows + wr) * kXS + 2 * part) = fx[it];
+      }
+    }
+  };
+  // a whole window (first run of a row): the columns past the first kRun
+  // synchronously, the first kRun through the pipelined path
+  auto load_rest = [&](const Run& r) {
+    for (int c0 = kRun; c0 < r.new_hi - r.jlo + 1; c0 += kRun) {
+      fetch_x(r, c0);
+      store_x(r, c0);
+    }
+  };
+  // wave 0: the window's (source, rhs) columns grouped by source state
+  auto sort_window = [&](const Run& r) {
+    int base = 0, nt = 0;
+    int st[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int pos = lane + 64 * h;  // ring slot pos >> lth, row pos & (th - 1)
+      st[h] = NS;
+      if (pos < kRing * th) {
+        const int sl = pos >> lth, wy = pos & (th - 1);
+        const int jx = r.jlo + ring(sl - r.jlo);
+        if (jx <= r.jhi) st[h] = state_at(jx, r.jy0 + wy);
+        p1col[pos] = -1;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+      const uint64_t m0 = __ballot(st[0] == a), m1 = __ballot(st[1] == a);
+      const int c0 = __popcll(m0), cnt = c0 + __popcll(m1);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint64_t m = h ? m1 : m0;
+        const int rank = (h ? c0 : 0) + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+        if (st[h] == a) {
+          const int pos = lane + 64 * h;
+          const int wrow = (pos >> lth) * kWinRows + ((pos & (th - 1)) << lq);  // window row of rhs 0
+          p1col[pos] = (int16_t)(base + rank * nrhs);
+          for (int q = 0; q < nrhs; ++q) p1tab[base + rank * nrhs + q] = (int16_t)(wrow + q);
+        }
+      }
+      const int used = cnt * nrhs, tiles = (used + 15) >> 4;
+      for (int c = used + lane; c < tiles * 16; c += 64) p1tab[base + c] = -1;
+      if (lane < tiles) ct1_state[nt + lane] = (uint8_t)a;
+      base += tiles * 16;
+      nt += tiles;
+    }
+    if (lane == 0) nct1_s = nt;
+  };
+  // first-product column of this lane's observers' sources for each dl of
+  // a run, as four 16-bit fields (dl 0, 1 in pk_lo; 2, 3 in pk_hi)
+  uint32_t pk_lo[CTW], pk_hi[CTW];
+  auto make_pk = [&](const Run& r) {
+#pragma unroll
+    for (int qi = 0; qi < CTW; ++qi) {
+      uint32_t f4[kRun];
+#pragma unroll
+      for (int dl = 0; dl < kRun; ++dl) {
+        int c1 = -1;
+        if (o_ok[qi] && dl < r.nrun) c1 = p1col[(ring(tl.tx + o_sx[qi] - (r.dxa + dl)) << lth) + o_sy[qi]];
+        f4[dl] = (uint32_t)(c1 < 0 ? 0xffff : c1 + o_q[qi]) & 0xffffu;
+      }
+      pk_lo[qi] = f4[0] | f4[1] << 16;
+      pk_hi[qi] = f4[2] | f4[3] << 16;
+    }
+  };
+
+  if (g < wdy) {
+    Run ru = make_run(g, dx_lo);
+    int row = g, k0 = 0;
+    fetch_x(ru, 0);
+    if (ru.nrk > 0) fetch_f(ru, 0);
+    store_x(ru, 0);
+    load_rest(ru);
+    if (ru.nrk > 0) store_f(ru, 0, true, true);
+    if (wave == 0) sort_window(ru);
+    __syncthreads();
+    make_pk(ru);
+    for (;;) {
+      const int Kc = ru.nrk > k0 ? 2 * min(KR, ru.nrk - k0) : 0;
+      // the next step
+      Run nx = ru;
+      int nrow = row, nk0 = k0 + KR;
+      bool newrun = false, done = false;
+      if (nk0 >= ru.nrk) {
+        newrun = true;
+        nk0 = 0;
+        int ndxa = ru.dxa + kRun;
+        if (ndxa > bx_hi) {
+          nrow += A.n_dgroups;
+          ndxa = dx_lo;
+        }
+        if (nrow >= wdy)
+          done = true;
+        else
+          nx = make_run(nrow, ndxa);
+      }
+      const int nct1 = nct1_s;
+      // (b) first product: t = V^H x over (row tile, source-state column tile)
+      for (int w = wave; w < MT1 * nct1 && Kc > 0; w += 4) {
+        const int ct = w / MT1, mt = w - ct * MT1;
+        const int b = ct1_state[ct];
+        const int m = 16 * mt + nl, rl = m >> 1, c = m & 1;
+        float a0[10], a1[10];
+        if (m < Kc) {
+          const float* vr = reinterpret_cast<const float*>(Vc + rl * NP + b * kFNA + 10 * kk);
+#pragma unroll
+          for (int k2 = 0; k2 < 10; k2 += 2) {
+            Cx<float> p, q2;
+            load2<float>(vr, k2, p, q2);
+            a0[k2] = c ? -p.im : p.re;
+            a1[k2] = c ? p.re : p.im;
+            a0[k2 + 1] = c ? -q2.im : q2.re;
+            a1[k2 + 1] = c ? q2.re : q2.im;
+          }
+        } else {
+#pragma unroll
+          for (int k2 = 0; k2 < 10; ++k2) a0[k2] = a1[k2] = 0.f;
+        }
+        const int ent = p1tab[ct * 16 + nl];
+        float xr[10], xi[10];
+        if (ent >= 0) {
+          const float* xp = reinterpret_cast<const float*>(Xr + ent * kXS + 10 * kk);
+#pragma unroll
+          for (int k2 = 0; k2 < 10; k2 += 2) {
+            Cx<float> p, q2;
+            load2<float>(xp, k2, p, q2);
+            xr[k2] = p.re;
+            xi[k2] = p.im;
+            xr[k2 + 1] = q2.re;
+            xi[k2 + 1] = q2.im;
+          }
+        } else {
+#pragma unroll
+          for (int k2 = 0; k2 < 10; ++k2) xr[k2] = xi[k2] = 0.f;
+        }
+        v4 cc = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 20; ++s)
+          cc = __builtin_amdgcn_mfma_f32_16x16x4f32((s & 1) ? a1[s >> 1] : a0[s >> 1],
+                                                    (s & 1) ? xi[s >> 1] : xr[s >> 1], cc, 0, 0, 0);
+        if (ent >= 0) {
+          float* tc = Tb + (ct * 16 + nl) * TS;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int mr = 16 * mt + 4 * kk + i;
+            if (mr < Kc) tc[mr] = cc[i];
+          }
+        }
+      }
+      // the next step's data into registers
+      if (!done) {
+        if (newrun) fetch_x(nx, 0);
+        if (nx.nrk > nk0) fetch_f(nx, nk0);
+      }
+      __syncthreads();
+      // (c) second product: y += U t over the step's stacked ranks
+      if (Kc > 0) {
+        const int S2 = (Kc + 3) >> 2;
+        float bt[CTW][8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int k = kk * S2 + s;
+          const int dl = rank_dl(ru, k0 + (k >> 1));  // displacement of the run of K entry k
+          const int sh = (dl & 1) * 16;
+#pragma unroll
+          for (int qi = 0; qi < CTW; ++qi) {
+            const int c1 = (int)(((dl < 2 ? pk_lo[qi] : pk_hi[qi]) >> sh) & 0xffffu);
+            bt[qi][s] = (s < S2 && k < Kc && c1 != 0xffff) ? Tb[c1 * TS + k] : 0.f;
+          }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 5; ++mt) {
+          const int e = 8 * mt + (nl >> 1), c = nl & 1;
+          int cur = -1;
+          float au[8];
+#pragma unroll
+          for (int qi = 0; qi < CTW; ++qi) {
+            const int ct2 = wave + 4 * qi;
+            if (ct2 >= nct2) break;
+            const int a = ct2_state[ct2];
+            if (a != cur) {
+              cur = a;
+#pragma unroll
+              for (int s = 0; s < 8; ++s) {
+                const int k = kk * S2 + s;
+                float v = 0.f;
+                if (s < S2 && k < Kc) {
+                  const Cx<float> u = Uc[(k >> 1) * NP + a * kFNA + e];
+                  v = (k & 1) ? (c ? u.re : -u.im) : (c ? u.im : u.re);
+                }
+                au[s] = v;
+              }
+            }
+#pragma unroll
+            for (int s = 0; s < 8; ++s)
+              if (s < S2) acc[qi][mt] = __builtin_amdgcn_mfma_f32_16x16x4f32(au[s], bt[qi][s], acc[qi][mt], 0, 0, 0);
+          }
+        }
+      }
+      // the next step's window and V columns where this step no longer reads
+      if (!done) {
+        if (newrun) {
+          store_x(nx, 0);
+          if (nx.dxa == dx_lo) load_rest(nx);  // a new row: the rest of its first window
+          if (wave == 0) sort_window(nx);
+        }
+        if (nx.nrk > nk0) store_f(nx, nk0, false, true);
+      }
+      __syncthreads();
+      if (done) break;
+      if (nx.nrk > nk0) store_f(nx, nk0, true, false);  // read by the next step's second product only
+      if (newrun) make_pk(nx);
+      ru = nx;
+      row = nrow;
+      k0 = nk0;
+    }
+  }
+  // the work item's partial slot
+#pragma unroll
+  for (int qi = 0; qi < CTW; ++qi) {
+    if (!o_ok[qi]) continue;
+    const int64_t unit = (int64_t)(tl.ty + o_sy[qi]) * R.Lx + tl.tx + o_sx[qi];
+    float* o = A.out + ((size_t)g * A.total_units + g_uoff[o_q[qi]] + unit) * kFNA * 2;
+#pragma unroll
+    for (int mt = 0; mt < 5; ++mt) *reinterpret_cast<v4*>(o + 2 * (8 * mt + 2 * kk)) = acc[qi][mt];
+  }
+}
+
+template <int FT, int CTW, int KC, int NS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+far_mfma_kernel(FarMArgs A, const int* __restrict__ live) {
+  if (live && *live == 0) return;  // every right-hand side has converged
+  far_mfma_body<FT, CTW, KC, NS>(A, blockIdx.x);
+}
+
+// near items (matrix cores, first near_wgs workgroups) beside the far items
+template <int FT, int CTW, int KC, int NS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+far_mfma_near_kernel(FarMArgs F, NearArgs<float> N, int near_wgs, const int* __restrict__ live) {
+  if (live && *live == 0) return;  // every right-hand side has converged
+  if ((int)blockIdx.x < near_wgs)
+    near_body<float, 40>(N, blockIdx.x);
+  else
+    far_mfma_body<FT, CTW, KC, NS>(F, blockIdx.x - near_wgs);
+}
+
 template <typename S, typename XT>
 __global__ void __launch_bounds__(256)
 convert_flat_kernel(const RhsDev* __restrict__ rhs, int n_a, const XT* __restrict__ x, S* __restrict__ xs) {
@@ -1072,6 +1587,58 @@ void validate_store(const r3m_store* Z) {
   }
 }
 
+// far field on the matrix cores: complex64 near store (FP32 arithmetic), 40
+// active RWG per unit, two or four states
+static bool far_on_mfma(const r3m_store* Z) {
+  return store_has_far(Z) && !store_is_spectral(Z) && Z->near_dtype == R3M_C64 && Z->n / Z->n_states == kFNA &&
+         (Z->n_states == 2 || Z->n_states == 4) && Z->max_rank <= 255;
+}
+static size_t far_mfma_lds(const r3m_store* Z) {
+  return Z->n_states == 2 ? far_mfma_lds_bytes<32, 2>() : far_mfma_lds_bytes<16, 4>();
+}
+
+// the far field (and, with fuse, the near items) on the matrix cores
+static void launch_far_mfma(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const float* xs,
+                        float* part, int groups, const float* fscale, size_t head, int64_t tu, bool fuse,
+                        const NearArgs<float>& NA_, int near_wgs, size_t lds_nearm, const int* idle,
+                        const int* live, hipStream_t stream) {
+  const int ft = (int)Z->far_dtype;
+  // matrix-core far field over (codebook tile, displacement group) items
+  const FarMArgs FM{bd.rhs, bd.groups, bd.gtiles, bd.n_gtiles, groups, states,
+                    (const float*)((const char*)Z->far + head), (const int*)Z->far, fscale, Z->max_rank,
+                    Z->Dx, Z->Dy, Z->near_radius, xs, part, tu, idle};
+  const size_t lds_m = far_mfma_lds(Z);
+  const int nwg_m = (bd.n_gtiles * groups + kXcd - 1) / kXcd * kXcd;
+  typedef void (*KF)(FarMArgs, NearArgs<float>, int, const int*);
+  typedef void (*KO)(FarMArgs, const int*);
+  KF kf = nullptr;
+  KO ko = nullptr;
+  constexpr int ctw = (kP2Tiles + 3) / 4;
+  // two states (n = 80): 16 ranks per sub-chunk; four states (n = 160): 8
+#define R3M_FARM_PICK(FTV)                                                                   \
+  if (Z->n_states == 2) {                                                                    \
+    kf = far_mfma_near_kernel<FTV, ctw, 32, 2>;                                              \
+    ko = far_mfma_kernel<FTV, ctw, 32, 2>;                                                   \
+  } else {                                                                                   \
+    kf = far_mfma_near_kernel<FTV, ctw, 16, 4>;                                              \
+    ko = far_mfma_kernel<FTV, ctw, 16, 4>;                                                   \
+  }
+  if (ft == R3M_BF16X2) {
+    R3M_FARM_PICK(R3M_BF16X2)
+  } else if (ft == R3M_F16X2) {
+    R3M_FARM_PICK(R3M_F16X2)
+  } else {
+    R3M_FARM_PICK(0)
+  }
+#undef R3M_FARM_PICK
+  if (fuse) {
+    hipLaunchKernelGGL(kf, dim3(near_wgs + nwg_m), dim3(256), std::max(lds_m, lds_nearm), stream, FM,
+                       NA_, near_wgs, live);
+  } else {
+    hipLaunchKernelGGL(ko, dim3(nwg_m), dim3(256), lds_m, stream, FM, live);
+  }
+}
+
 template <typename S, typename XT>
 static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const S* xs, XT* y,
                         char* part, const void* lists, int chunks, hipStream_t stream,
@@ -1081,11 +1648,15 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
   const bool far = store_has_far(Z);
   const int n_far = far ? r3m_far_count(Z->Dx, Z->Dy, Z->near_radius) : 0;
   const size_t head = ((size_t)n_far * 4 + 255) / 256 * 256;
-  const int groups = far ? std::max(chunks, 1) : 0;
+  const int groups = far ? std::max(chunks & kPlanGroups, 1) : 0;
+  const bool mfma_far = far && (chunks & kPlanMfmaFar) && far_on_mfma(Z);
   const int hg = near_groups(Z, bd);
   const int64_t tu = (int64_t)bd.total_units;
   const bool mfma_near = near_on_mfma(Z);
-  const bool fuse = mfma_near && far && sizeof(S) == 4;
+  // the vector-unit far kernel shares its launch with the near items; the
+  // matrix-core one runs alone (the shared kernel would take the larger
+  // register budget of the two bodies)
+  const bool fuse = mfma_near && far && sizeof(S) == 4 && !mfma_far;
   NearArgs<S> NA_{};
   size_t lds_nearm = 0;
   int near_wgs = 0;
@@ -1109,7 +1680,15 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
                         Z->n_states, xs, (S*)part, tu, lds_state_cap, bd.n_tiles, idle};
     const int nwg = (bd.n_tiles * groups + kXcd - 1) / kXcd * kXcd;
     const int ft = sizeof(S) == 4 ? (int)Z->far_dtype : 0;
-    if (fuse) {
+    bool done = false;
+    if constexpr (sizeof(S) == 4) {
+      if (mfma_far) {
+        launch_far_mfma(Z, bd, states, xs, (float*)part, groups, fscale, head, tu, fuse, NA_, near_wgs, lds_nearm, idle,
+                        live, stream);
+        done = true;
+      }
+    }
+    if (!done && fuse) {
       // one launch for both fields (complex64: the matrix-core near items run
       // beside the vector-unit far tiles; complex128 is faster as two launches)
       decltype(&far_near_kernel<S, 10, rch, 0, 40>) kern;
@@ -1123,7 +1702,7 @@ static void launch_core(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
                                 : far_near_kernel<S, 16, rch, 0, 64>;
       hipLaunchKernelGGL(kern, dim3(near_wgs + nwg), dim3(256), std::max(lds, lds_nearm), stream, FA, NA_,
                          near_wgs, live);
-    } else {
+    } else if (!done) {
       decltype(&far_kernel<S, 10, rch, 0>) kern;
       if (n_a == 40)
         kern = ft == R3M_BF16X2 ? far_kernel<S, 10, rch, sizeof(S) == 4 ? R3M_BF16X2 : 0>
@@ -1162,7 +1741,6 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
                          void* partial, const void* lists, int chunks, hipStream_t stream, const int* idle) {
   const int n_a = Z->n / Z->n_states;
   const bool far = store_has_far(Z);
-  const int groups = far ? std::max(chunks, 1) : 0;
   const int hg = near_groups(Z, bd);
   const size_t vec = (size_t)bd.total_units * n_a * 2 * sizeof(S);
   char* part = (char*)partial;
@@ -1200,7 +1778,8 @@ static std::vector<int64_t> tune_key(const r3m_store* Z, const BatchDesc& bd) {
 }
 
 // Autotuner: the first time a (store, batch) pair is seen, time the matvec for
-// a few displacement-group counts around the default and keep the fastest.
+// a few displacement-group counts around the default, with the vector-unit and
+// (where it applies) the matrix-core far kernel, and keep the fastest plan.
 // xs is the input in the store precision, y a C128 output (overwritten).
 int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
                  void* y, void* partial, const void* lists, hipStream_t stream) {
@@ -1209,37 +1788,49 @@ int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uin
   auto it = ctx->tuned_groups.find(key);
   if (it != ctx->tuned_groups.end()) return it->second;
   const int g0 = choose_chunks(bd, 64), gcap = max_groups(bd);
-  // R3M_MATVEC_GROUPS fixes the count instead (clamped to [1, gcap]); used to
-  // hold the launch shape constant across profiler runs
-  if (const char* env = std::getenv("R3M_MATVEC_GROUPS")) {
-    const int forced = std::max(1, std::min(gcap, std::atoi(env)));
-    ctx->tuned_groups[key] = forced;
-    return forced;
+  // R3M_FAR_KERNEL ("valu" or "mfma") restricts the far kernel and
+  // R3M_MATVEC_GROUPS fixes the count (clamped to [1, gcap]); used by tests and
+  // to hold the launch shape constant across profiler runs
+  std::vector<int> kinds{0};
+  if (far_on_mfma(Z)) kinds.push_back(kPlanMfmaFar);
+  if (const char* env = std::getenv("R3M_FAR_KERNEL")) {
+    if (std::string(env) == "valu") kinds = {0};
+    if (std::string(env) == "mfma" && far_on_mfma(Z)) kinds = {kPlanMfmaFar};
   }
   std::vector<int> cand;
-  for (int g = std::max(1, g0 / 4); g <= gcap; g *= 2) cand.push_back(g);
-  hipEvent_t e0, e1;
-  R3M_CHECK_HIP(hipEventCreate(&e0));
-  R3M_CHECK_HIP(hipEventCreate(&e1));
-  int best = g0;
-  float best_ms = 1e30f;
-  for (int g : cand) {
-    launch_matvec_pre(Z, bd, states, xs, y, partial, lists, g, stream, nullptr);  // warm
-    R3M_CHECK_HIP(hipEventRecord(e0, stream));
-    for (int rep = 0; rep < 2; ++rep) launch_matvec_pre(Z, bd, states, xs, y, partial, lists, g, stream, nullptr);
-    R3M_CHECK_HIP(hipEventRecord(e1, stream));
-    R3M_CHECK_HIP(hipEventSynchronize(e1));
-    float ms = 0.f;
-    R3M_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
-    // candidates come in increasing order; a larger count must win by 3% (keeps
-    // the choice stable between runs when two counts are within noise)
-    if (ms < 0.97f * best_ms) {
-      best_ms = ms;
-      best = g;
-    }
+  if (const char* env = std::getenv("R3M_MATVEC_GROUPS")) {
+    cand.push_back(std::max(1, std::min(gcap, std::atoi(env))));
+  } else {
+    for (int g = std::max(1, g0 / 4); g <= gcap; g *= 2) cand.push_back(g);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  int best = g0 | kinds[0];
+  if (cand.size() * kinds.size() > 1) {
+    hipEvent_t e0, e1;
+    R3M_CHECK_HIP(hipEventCreate(&e0));
+    R3M_CHECK_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    for (int kind : kinds)
+      for (int g : cand) {
+        const int plan = g | kind;
+        launch_matvec_pre(Z, bd, states, xs, y, partial, lists, plan, stream, nullptr);  // warm
+        R3M_CHECK_HIP(hipEventRecord(e0, stream));
+        for (int rep = 0; rep < 2; ++rep) launch_matvec_pre(Z, bd, states, xs, y, partial, lists, plan, stream, nullptr);
+        R3M_CHECK_HIP(hipEventRecord(e1, stream));
+        R3M_CHECK_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        R3M_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+        // candidates come in a fixed order; a later one must win by 3% (keeps
+        // the choice stable between runs when two plans are within noise)
+        if (ms < 0.97f * best_ms) {
+          best_ms = ms;
+          best = plan;
+        }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  } else {
+    best = cand[0] | kinds[0];
+  }
   ctx->tuned_groups[key] = best;
   return best;
 }
@@ -1343,7 +1934,7 @@ extern "C" int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_
     validate_store(Z);
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;
-    out = plan_groups(ctx, Z, get_batch(ctx, batch, kBW, kBH, 0));
+    out = plan_groups(ctx, Z, get_batch(ctx, batch, kBW, kBH, 0)) & kPlanGroups;
   });
   return rc == R3M_OK ? out : rc;
 }

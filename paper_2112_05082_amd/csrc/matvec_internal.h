@@ -5,12 +5,17 @@
 namespace r3m {
 
 void validate_store(const r3m_store* Z);
+// A matvec plan (the value the autotuner keeps per store and batch): the
+// displacement-group count in the low bits, kPlanMfmaFar for the matrix-core
+// far kernel
+constexpr int kPlanGroups = 0xffff;
+constexpr int kPlanMfmaFar = 1 << 16;
 int choose_chunks(const BatchDesc& bd, int max_chunks);
 // largest displacement-group count the autotuner may pick (workspaces are sized for it)
 int max_groups(const BatchDesc& bd);
-// the autotuned group count of (store, batch) if known, else the default
+// the autotuned plan of (store, batch) if known, else the default
 int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd);
-// times candidate group counts once per (store, batch); xs in the store precision, y C128
+// times candidate plans once per (store, batch); xs in the store precision, y C128
 int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
                  void* y, void* partial, const void* lists, hipStream_t stream);
 // matvec workspace: partial slots, converted x, near retrieval lists

@@ -69,9 +69,15 @@ struct BatchDesc {
   int32_t n_tiles = 0;
   int32_t max_L = 0;
   int64_t max_units = 0;  // largest Lx * Ly of the batch
-  DevBuf dev;  // rhs table [B] then tile table [n_tiles]
+  DevBuf dev;  // rhs table [B], tile table [n_tiles], group table [n_groups], group tiles [n_gtiles]
   const struct RhsDev* rhs = nullptr;
   const struct TileDev* tiles = nullptr;
+  // right-hand sides sharing a codebook (same state bytes and array shape),
+  // up to kGroupRhs per group, and the unit tiles of each group (TileDev.b =
+  // group index)
+  int32_t n_groups = 0, n_gtiles = 0, max_group_rhs = 0;
+  const struct GroupDev* groups = nullptr;
+  const struct TileDev* gtiles = nullptr;
   std::vector<int64_t> unit_off, n_units;
   std::vector<int32_t> Lx, Ly;
   int64_t codebook_units = 0;  // units of the distinct codebooks (RhsDev::fac_off)
@@ -95,6 +101,19 @@ struct TileDev {
   int32_t ty;  // first unit row
   int32_t pad;
 };
+
+constexpr int kGroupRhs = 4;
+struct GroupDev {
+  int32_t n;               // right-hand sides in the group (1..kGroupRhs)
+  int32_t rhs[kGroupRhs];  // their indices; rhs[0] carries the codebook
+  int32_t th;              // height of the group's unit tiles (width: the call's tile width)
+  int32_t pad[2];
+};
+// tile height of a group of n right-hand sides: tile_h / (n rounded up to a power of two), at least 1
+inline int group_tile_h(int tile_h, int n) {
+  const int p = n <= 1 ? 1 : n <= 2 ? 2 : 4;
+  return tile_h / p > 0 ? tile_h / p : 1;
+}
 
 }  // namespace r3m
 
