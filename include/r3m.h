@@ -24,6 +24,11 @@
  *  - Every call takes a caller-owned hipStream_t and is asynchronous on it,
  *    except calls that return host data (noted), which synchronise it.
  *  - Shapes, ranges and pointers are validated on the host before any launch.
+ *    Data that lives on the device (the codebooks' state bytes) is checked
+ *    on the device: a call that synchronises reports its own inputs; an
+ *    asynchronous call (r3m_retrieved_matvec) leaves the error in the context
+ *    and the next r3m_ctx_check, r3m_gmres_solve, r3m_plane_wave_rhs or
+ *    r3m_rcs on that context returns it (and clears it).
  *  - Complex values are interleaved (re, im): R3M_C128 = 2 x double,
  *    R3M_C64 = 2 x float.
  *  - Units: metres, hertz.  Time convention exp(+j w t).
@@ -75,6 +80,11 @@ int r3m_ctx_destroy(r3m_ctx ctx);
 const char* r3m_last_error(r3m_ctx ctx);
 /* Library version string. */
 const char* r3m_version(void);
+/* Synchronises `stream` and returns (then clears) the error an earlier
+ * asynchronous call on ctx found on the device: R3M_ERR_INVALID_ARG for a
+ * codebook state byte >= n_states (the product of that call is undefined
+ * for the units concerned), else R3M_OK. */
+int r3m_ctx_check(r3m_ctx ctx, hipStream_t stream);
 
 /* Geometry of the macro unit (host memory, read during the call).
  * The macro unit is the union of its coding states (Sec. III-A): state s owns
@@ -213,7 +223,9 @@ size_t r3m_matvec_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* b
  * basis range of state s.  Far blocks use U (V^H x).  Vectors are C128 or C64
  * (vec_dtype), accumulation is in the store's precision (FP64 for a C128
  * store, FP32 otherwise).  The sum over displacements is reduced in a fixed
- * order (bitwise reproducible run to run).  work: r3m_matvec_work_bytes. */
+ * order (bitwise reproducible run to run).  work: r3m_matvec_work_bytes.
+ * Every state byte must be < n_states: the call checks them on the device
+ * (unless R3M_BATCH_INDEX_READY) and r3m_ctx_check reports a violation. */
 int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch,
                          r3m_dtype vec_dtype, const void* x_dev, void* y_dev, void* work_dev,
                          size_t work_bytes, hipStream_t stream);
@@ -306,11 +318,11 @@ int r3m_relaxed_gradient(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
  * (lower colour), the upper factor U_gj (higher colour), or the inverted
  * pivot U_gg^-1 at offset 0; zero for neighbours outside the array.  Blocks
  * are column-major: element (row, col) at col * n_a + row, complex double
- * (C128 near store) or float (C64).  State bytes >= n_states are read as
- * n_states - 1. */
+ * (C128 near store) or float (C64). */
 size_t r3m_ilu_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t radius);
-/* Factors every distinct codebook of the batch.  R3M_ERR_NONFINITE for a
- * singular pivot block; this call synchronises the stream. */
+/* Factors every distinct codebook of the batch.  R3M_ERR_INVALID_ARG for a
+ * state byte >= n_states, R3M_ERR_NONFINITE for a singular pivot block; this
+ * call synchronises the stream. */
 int r3m_ilu_factor(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t radius, void* factors_dev,
                    size_t factors_bytes, hipStream_t stream);
 /* y = U^-1 L^-1 x for every RHS (C128 [unit][n_a] vectors, x and y distinct;

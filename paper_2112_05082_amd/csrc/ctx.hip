@@ -281,6 +281,38 @@ const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int 
   return *d;
 }
 
+// One thread per unit of every codebook (the first right-hand side of each):
+// a state byte >= n_states sets `bit` in *word.
+__global__ void __launch_bounds__(256)
+bad_states_kernel(const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, int n_states, int* word,
+                  int bit) {
+  const RhsDev R = rhs[blockIdx.y];
+  if (!R.fac_lead) return;
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= (int64_t)R.Lx * R.Ly) return;
+  if (states[R.state_off + u] >= n_states) atomicOr(word, bit);
+}
+
+void check_states(const BatchDesc& bd, const uint8_t* states, int n_states, int* word, int bit, hipStream_t s) {
+  if (bd.B == 0) return;
+  hipLaunchKernelGGL(bad_states_kernel, dim3(ceil_div((size_t)bd.max_units, 256), bd.B), dim3(256), 0, s, bd.rhs,
+                     states, n_states, word, bit);
+  R3M_CHECK_HIP(hipGetLastError());
+}
+
+int* deferred_word(r3m_ctx ctx) { return (int*)ctx->flag.ptr + kDeferredWord; }
+
+void take_deferred(r3m_ctx ctx, hipStream_t s) {
+  int w = 0;
+  R3M_CHECK_HIP(hipMemcpyAsync(&w, deferred_word(ctx), sizeof(int), hipMemcpyDeviceToHost, s));
+  R3M_CHECK_HIP(hipStreamSynchronize(s));
+  if (w == 0) return;
+  R3M_CHECK_HIP(hipMemsetAsync(deferred_word(ctx), 0, sizeof(int), s));
+  R3M_CHECK_HIP(hipStreamSynchronize(s));
+  R3M_REQUIRE(!(w & kDeferredBadState), R3M_ERR_INVALID_ARG,
+              "a codebook given to an earlier asynchronous call has a state byte >= n_states");
+}
+
 }  // namespace r3m
 
 using namespace r3m;
@@ -338,6 +370,14 @@ const char* r3m_last_error(r3m_ctx ctx) {
   return g_thread_error.c_str();
 }
 
-const char* r3m_version(void) { return "r3m 0.1 gfx950"; }
+const char* r3m_version(void) { return "r3m 0.2 gfx950"; }
+
+int r3m_ctx_check(r3m_ctx ctx, hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    take_deferred(ctx, stream);
+  });
+}
 
 }  // extern "C"

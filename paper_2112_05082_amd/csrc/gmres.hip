@@ -1393,6 +1393,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
       rep_host[i].converged = rel[i] <= target ? 1 : 0;
       all = all && rep_host[i].converged;
     }
+    take_deferred(ctx, stream);  // errors left by earlier asynchronous calls on this context
     R3M_REQUIRE(all, R3M_ERR_NOT_CONVERGED, "some right-hand sides did not converge");
   });
 }

@@ -575,10 +575,12 @@ int r3m_ilu_factor(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int3
     R3M_REQUIRE(factors_bytes >= ilu_factor_bytes(Z, bd, radius), R3M_ERR_BUFFER_TOO_SMALL,
                 "ILU factor buffer too small");
     R3M_CHECK_HIP(hipMemsetAsync(ctx->flag.ptr, 0, sizeof(int), stream));
+    check_states(bd, batch->states, Z->n_states, (int*)ctx->flag.ptr, 2, stream);
     launch_ilu_factor(Z, bd, batch->states, radius, factors_dev, (int*)ctx->flag.ptr, stream);
     int flag = 0;
     R3M_CHECK_HIP(hipMemcpyAsync(&flag, ctx->flag.ptr, sizeof(int), hipMemcpyDeviceToHost, stream));
     R3M_CHECK_HIP(hipStreamSynchronize(stream));
+    R3M_REQUIRE(!(flag & 2), R3M_ERR_INVALID_ARG, "codebook state out of range");
     R3M_REQUIRE(!(flag & 8), R3M_ERR_NONFINITE, "singular pivot block in the ILU factorisation");
   });
 }

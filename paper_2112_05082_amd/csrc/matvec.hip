@@ -1902,8 +1902,10 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
     R3M_REQUIRE(work_dev, R3M_ERR_INVALID_ARG, "work is NULL");
     // the retrieval index of this codebook (near lists), unless the caller
     // declares the one in the workspace current
-    if (!(batch->flags & R3M_BATCH_INDEX_READY))
+    if (!(batch->flags & R3M_BATCH_INDEX_READY)) {
+      check_states(bd, batch->states, Z->n_states, deferred_word(ctx), kDeferredBadState, stream);
       build_near_lists(Z, bd, batch->states, workspace_lists(work_dev, bd, Z), stream);
+    }
     // first C128 call on this (store, batch): tune the group count on this x
     // (the tuner writes y as C128, so C64 vectors take the tuned or default value)
     if (vec_dtype == R3M_C128 && store_has_far(Z) && !store_is_spectral(Z)) {
@@ -2006,8 +2008,10 @@ extern "C" int r3m_retrieved_matvec_static(r3m_ctx ctx, const r3m_store* Z, cons
     }
     point_batch(&bd, sc.ptr);
     char* work = (char*)sc.ptr + head;
-    if (!(batch->flags & R3M_BATCH_INDEX_READY))
+    if (!(batch->flags & R3M_BATCH_INDEX_READY)) {
+      check_states(bd, batch->states, Z->n_states, deferred_word(ctx), kDeferredBadState, stream);
       build_near_lists(Z, bd, batch->states, workspace_lists(work, bd, Z), stream);
+    }
     launch_matvec(ctx, Z, bd, batch->states, vec_dtype, x_dev, y_dev, work, nullptr, groups, stream);
   });
 }

@@ -158,6 +158,16 @@ const BatchDesc& get_batch(r3m_ctx ctx, const r3m_batch* batch, int tile_w, int 
 void describe_batch(const r3m_batch* batch, int tile_w, int tile_h, BatchDesc* d, std::vector<char>& host);
 void point_batch(BatchDesc* d, void* dev);
 std::vector<int64_t> batch_key(const r3m_batch* batch, int tile_w, int tile_h);
+// Errors found on the device by asynchronous calls are kept in a word of the
+// context's flag buffer and reported by the next call that synchronises and
+// reads it (r3m_ctx_check, r3m_gmres_solve).
+constexpr int kDeferredWord = 16;      // int index in ctx->flag
+constexpr int kDeferredBadState = 1;   // a state byte >= n_states
+int* deferred_word(r3m_ctx ctx);
+// reads (and clears) the deferred word; throws the error it records
+void take_deferred(r3m_ctx ctx, hipStream_t s);
+// sets `bit` in *word if any codebook of the batch has a state byte >= n_states
+void check_states(const BatchDesc& bd, const uint8_t* states, int n_states, int* word, int bit, hipStream_t s);
 // looks up the device address of the library's static scratch on `device`
 // (current), once per device; called by r3m_ctx_create
 void init_static_scratch(int device);

@@ -339,11 +339,13 @@ int r3m_plane_wave_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* 
     for (int b = 0; b < bd.B; ++b) maxU = std::max<int64_t>(maxU, bd.n_units[b]);
     const double k = 2.0 * kPi * geom->freq_hz / kC0;
     dim3 grid(ceil_div((size_t)maxU * n_a, 256), bd.B);
+    check_states(bd, batch->states, geom->n_states, deferred_word(ctx), kDeferredBadState, stream);
     hipLaunchKernelGGL(plane_wave_kernel, grid, dim3(256), 0, stream, g, bd.rhs, (const IncDev*)tmp.ptr,
                        batch->states, n_a, geom->n_states, k, geom->period_x, geom->period_y, (double2*)b_dev);
     R3M_CHECK_HIP(hipGetLastError());
     R3M_CHECK_HIP(hipStreamSynchronize(stream));
     tmp.release();
+    take_deferred(ctx, stream);
   });
 }
 
@@ -373,12 +375,14 @@ int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, cons
     hipLaunchKernelGGL(macro_radiation_kernel, dim3(ceil_div((size_t)n_dir * geom->n_rwg, 128)), dim3(128), 0,
                        stream, g, ddev, n_dir, k, F);
     const double scale = k * k * kEta0 * kEta0 / (4.0 * kPi) / (e0 * e0);
+    check_states(bd, batch->states, geom->n_states, deferred_word(ctx), kDeferredBadState, stream);
     hipLaunchKernelGGL(rcs_kernel, dim3(n_dir, bd.B), dim3(kRcsThreads), 0, stream, bd.rhs, batch->states,
                        (const double2*)I_dev, F, ddev, n_dir, geom->n_rwg, n_a, geom->n_states, k,
                        geom->period_x, geom->period_y, scale, sigma_dev);
     R3M_CHECK_HIP(hipGetLastError());
     R3M_CHECK_HIP(hipStreamSynchronize(stream));
     tmp.release();
+    take_deferred(ctx, stream);
   });
 }
 

@@ -28,7 +28,7 @@ BATCH_INDEX_READY = 1
 PRECOND_NONE, PRECOND_BLOCK_JACOBI, PRECOND_BLOCK_ILU = 0, 1, 2
 
 EXPORTED = (
-    "r3m_ctx_create", "r3m_ctx_destroy", "r3m_last_error", "r3m_version",
+    "r3m_ctx_create", "r3m_ctx_destroy", "r3m_last_error", "r3m_version", "r3m_ctx_check",
     "r3m_blocks_bytes", "r3m_fill_unique_blocks",
     "r3m_far_count", "r3m_far_bytes", "r3m_compress_work_bytes", "r3m_compress_far",
     "r3m_spectral_bytes", "r3m_build_spectral", "r3m_relaxed_work_bytes", "r3m_relaxed_matvec",
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
         "r3m_ctx_destroy": (C.c_int, [vp]),
         "r3m_last_error": (C.c_char_p, [vp]),
         "r3m_version": (C.c_char_p, []),
+        "r3m_ctx_check": (C.c_int, [vp, vp]),
         "r3m_blocks_bytes": (sz, [i32, i32, i32, C.c_int]),
         "r3m_fill_unique_blocks": (C.c_int, [vp, C.POINTER(UnitGeomC), i32, i32, C.c_int, vp, sz, vp]),
         "r3m_far_count": (i32, [i32, i32, i32]),
@@ -392,6 +393,11 @@ def r3m_retrieved_matvec(ctx: Context, store: Store, batch: Batch, vec_dtype: in
                                         _stream(stream)), ctx.handle)
     finally:
         batch.cs.flags = 0
+
+
+def r3m_ctx_check(ctx: Context, stream=None):
+    """Synchronise and raise the error an earlier asynchronous call left on the device."""
+    _check(load().r3m_ctx_check(ctx.handle, _stream(stream)), ctx.handle)
 
 
 def r3m_retrieved_matvec_static(ctx: Context, store: Store, batch: Batch, vec_dtype: int, x, y, stream=None,

@@ -438,3 +438,42 @@ def test_index_ready_reuses_retrieval_index(r3m, ctx, stores_2bit_8):
     yd = run_matvec(r3m, ctx, sden, batch, xd, r3m.C128)
     torch.cuda.synchronize()
     assert rel_l2(y3.cpu().numpy(), yd.cpu().numpy()) <= 1e-4
+
+
+def test_invalid_codebook_reported(r3m, ctx):
+    """A state byte >= n_states is an error at the boundary, not a clamp: the
+    asynchronous matvec (dense, compressed and spectral stores) leaves it for
+    r3m_ctx_check; excitation, RCS and the ILU factorisation, which
+    synchronise, return it themselves; the check clears it."""
+    from paper_2112_05082_amd import pipeline
+    g = geom(r3m, 1)
+    stores = [pipeline.dense_store(ctx, g, 3, r3m.C128, DEV),
+              pipeline.compressed_store(ctx, g, 3, 1, r3m.C64, r3m.C64, 1e-4, 40, DEV),
+              pipeline.spectral_store(ctx, g, 3, 1, r3m.C128, DEV)]
+    bad = r3m.Batch([[3, 3]], [0], [0], torch.tensor([0, 1, 0, 1, 2, 1, 0, 0, 1], dtype=torch.uint8, device=DEV))
+    good = r3m.Batch([[3, 3]], [0], [0], torch.tensor([0, 1, 0, 1, 1, 1, 0, 0, 1], dtype=torch.uint8, device=DEV))
+    x = torch.ones(360, dtype=torch.complex128, device=DEV)
+    for st in stores:
+        y = torch.zeros_like(x)
+        work = torch.empty(max(r3m.matvec_work_bytes(ctx, st, bad, r3m.C128), 16), dtype=torch.uint8, device=DEV)
+        r3m.r3m_retrieved_matvec(ctx, st, good, r3m.C128, x, y, work)
+        r3m.r3m_ctx_check(ctx)  # a valid codebook leaves nothing
+        r3m.r3m_retrieved_matvec(ctx, st, bad, r3m.C128, x, y, work)  # asynchronous: returns OK
+        with pytest.raises(r3m.R3MError) as e:
+            r3m.r3m_ctx_check(ctx)
+        assert e.value.code == r3m.R3M_ERR_INVALID_ARG
+        r3m.r3m_ctx_check(ctx)  # cleared
+    with pytest.raises(r3m.R3MError) as e:
+        r3m.r3m_plane_wave_rhs(ctx, g, bad, [[0.0, 0.0, 1.0]], x)
+    assert e.value.code == r3m.R3M_ERR_INVALID_ARG
+    sig = torch.zeros(4, dtype=torch.float64, device=DEV)
+    with pytest.raises(r3m.R3MError) as e:
+        r3m.r3m_rcs(ctx, g, bad, x, [[0.1, 0.0], [0.2, 0.0], [0.3, 0.0], [0.4, 0.0]], 1.0, sig)
+    assert e.value.code == r3m.R3M_ERR_INVALID_ARG
+    st = stores[1]
+    fac = torch.empty(r3m.ilu_bytes(ctx, st, bad, 1), dtype=torch.uint8, device=DEV)
+    with pytest.raises(r3m.R3MError) as e:
+        r3m.r3m_ilu_factor(ctx, st, bad, 1, fac)
+    assert e.value.code == r3m.R3M_ERR_INVALID_ARG
+    r3m.r3m_ilu_factor(ctx, st, good, 1, fac)
+    r3m.r3m_ctx_check(ctx)

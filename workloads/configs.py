@@ -95,3 +95,14 @@ def far_pair_count(L: int, near_radius: int) -> int:
 
 def near_pair_count(L: int, near_radius: int) -> int:
     return L ** 4 - far_pair_count(L, near_radius)
+
+
+# Solver settings of the batched workload (1,536 right-hand sides), shared by
+# the benchmark and its full-size test: complex64 inner GMRES(20) to 1e-3 with
+# block-Jacobi, complex128 refinement residual to 1e-6; the reference solution
+# that the RCS error is measured against is the same system refined to 1e-10.
+BATCHED_SOLVE = {"restart": 20, "inner_tol": 1e-3, "refine_tol": 1e-6, "max_refine": 20, "max_iter": 3000,
+                 "ref_refine_tol": 1e-10}
+# Headline solve of the 2-bit 32x32 workload: block ILU(0) radius 1, GMRES(60)
+# to 5e-5 on the compressed complex64 store.
+TWOBIT_SOLVE = {"restart": 60, "tol": 5e-5, "ilu_radius": 1, "max_iter": 6000}
