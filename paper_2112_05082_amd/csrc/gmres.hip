@@ -35,6 +35,8 @@ struct RhsState {
   double res;    // latest relative residual estimate
   int jdone;     // iteration at which this cycle converged, -1 while running
   int active;    // 1 while the RHS is being solved
+  int budget;    // steps this cycle may take (what is left of max_iter)
+  int pad;
 };
 
 __device__ inline double2 cmul(double2 a, double2 b) {
@@ -162,7 +164,7 @@ __device__ void givens_step_block(int b, double2* __restrict__ H, double2* __res
     gg[j] = make_double2(cj * gj.x, cj * gj.y);
     const double res = s.bnorm > 0.0 ? hypot(gj1.x, gj1.y) / s.bnorm : 0.0;
     s.res = res;
-    if (!(res > tol) || nb == 0.0 || j == m - 1) {
+    if (!(res > tol) || nb == 0.0 || j == m - 1 || j + 1 >= s.budget) {
       s.jdone = j + 1;
       if (idle) idle[b] = 1;  // the rest of the cycle skips this right-hand side
     } else {
@@ -1102,7 +1104,7 @@ struct GmresRun {
       for (int b = 0; b < B; ++b) {
         const double rel = rhs_norm[b] > 0 ? rnorm[b] / rhs_norm[b] : 0.0;
         if (running[b] && (!(rel > tol) || iters[b] >= max_iter)) running[b] = 0;
-        hst[b] = RhsState{rhs_norm[b], 0.0, rel, -1, running[b]};
+        hst[b] = RhsState{rhs_norm[b], 0.0, rel, -1, running[b], std::max(1, max_iter - iters[b]), 0};
         if (running[b]) {
           any = true;
           min_used = std::min(min_used, iters[b]);
