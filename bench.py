@@ -73,6 +73,9 @@ def parse():
     p.add_argument("--n-per-size", type=int, default=128, help="codebooks per array size of the batched workload")
     p.add_argument("--c2-compressed", action="store_true",
                    help="run the batched workload on its compressed split-BF16 store (long; progress lines)")
+    p.add_argument("--matvec-only", action="store_true",
+                   help="time only the batched spectral matvec (W warmup calls, the first tunes; K timed): the "
+                        "command profiler summaries are taken on")
     p.add_argument("--c1-precond", type=int, default=2,
                    help="2-bit 32x32 leg: 0 none, 1 block-Jacobi, 2 near-field block ILU(0)")
     return p.parse_args()
@@ -231,6 +234,27 @@ def headline_c2(ctx, args):
         "_rep": rep,
     }
     return out
+
+
+def matvec_only(ctx, args):
+    """The batched workload's spectral matvec alone: a seeded complex64 vector,
+    W untimed calls (the first one runs the autotuner), K timed calls."""
+    import torch
+    from paper_2112_05082_amd import r3m
+    from workloads import codebooks as cb
+    S = c2_setup(ctx, args)
+    batch = S["batch"]
+    x = torch.from_numpy(cb.random_complex(S["N"], 5)).to("cuda:0").to(torch.complex64)
+    y = torch.zeros_like(x)
+    work = torch.empty(r3m.matvec_work_bytes(ctx, S["s64"], batch, r3m.C64), dtype=torch.uint8, device="cuda:0")
+    for _ in range(max(1, args.warmup)):
+        r3m.r3m_retrieved_matvec(ctx, S["s64"], batch, r3m.C64, x, y, work)
+    torch.cuda.synchronize()
+    mv = timed_matvec(r3m, ctx, S["s64"], batch, x, r3m.C64, args.steps)
+    byt, flops, G = spectral_cost(S["s64"].n, 63, batch.B)
+    return {"matvec_ms": mv * 1e3, "rhs": batch.B, "grid": [G, G], "steps": args.steps,
+            "plan": r3m.decode_plan(r3m.matvec_plan(ctx, S["s64"], batch)),
+            "algorithmic_flops_per_call": flops}
 
 
 def c2_compressed(ctx, args):
@@ -769,6 +793,11 @@ def main():
 
     from paper_2112_05082_amd import r3m
     ctx = r3m.Context(0)
+    if args.matvec_only:
+        out = matvec_only(ctx, args)
+        ctx.close()
+        print(json.dumps({"matvec_only": out}), flush=True)
+        return
     if args.c2_compressed:
         out = c2_compressed(ctx, args)
         ctx.close()

@@ -239,6 +239,32 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
  * r3m_status. */
 int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch);
 
+/* The whole launch plan of the matvec for this (store, batch), as the
+ * autotuner chose it (or r3m_matvec_set_plan pinned it), else the default.
+ * Compressed stores: bits 0-15 the displacement-group count,
+ * R3M_PLAN_MFMA_FAR when the far blocks run on the matrix cores.  Spectral
+ * stores (R3M_SPEC_*): R3M_PLAN_SPECTRAL, in bits 0-3 the frequency-product
+ * shape (0: vector units; 1..5: matrix cores with {frequencies per wave,
+ * columns per staged chunk} = {1,4}, {2,4}, {2,8}, {4,4}, {1,8}; complex64
+ * spectra only) and in bits 4-11 the count of live 16-RHS tiles from which
+ * the matrix-core product orders its workgroups RHS tile first.  The
+ * spectral autotuner runs on the first r3m_retrieved_matvec or
+ * r3m_gmres_solve of the pair.  Every matrix-core shape and order gives the
+ * same bits; the vector-unit shape differs from them by FP32 rounding order
+ * only.  Returns the plan (> 0), 0 for an empty batch, or a negative
+ * r3m_status. */
+#define R3M_PLAN_MFMA_FAR (1 << 16)
+#define R3M_PLAN_SPECTRAL (1 << 17)
+int32_t r3m_matvec_plan(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch);
+
+/* Pins the plan of (store, batch) (the encoding of r3m_matvec_plan) in the
+ * context; later matvecs and solves on the pair use it and the autotuner does
+ * not run for it.  R3M_ERR_INVALID_ARG when the plan does not fit the store
+ * (a matrix-core shape on complex128 spectra, R3M_PLAN_MFMA_FAR on a store
+ * the matrix-core far kernel does not take, a group count outside [1, the
+ * workspace's maximum], unknown bits).  An empty batch is a no-op. */
+int r3m_matvec_set_plan(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t plan);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * product as r3m_retrieved_matvec, with the workspace taken from a static

@@ -1761,7 +1761,7 @@ void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* s
                        void* partial, const void* lists, int chunks, hipStream_t stream, const int* live,
                        const int* idle) {
   if (store_is_spectral(Z)) {
-    launch_spectral(Z, bd, states, Z->near_dtype, xs, R3M_C128, y, partial, stream, live, idle);
+    launch_spectral(Z, bd, states, Z->near_dtype, xs, R3M_C128, y, partial, stream, live, idle, chunks);
     return;
   }
   if (Z->near_dtype == R3M_C128)
@@ -1783,7 +1783,8 @@ static std::vector<int64_t> tune_key(const r3m_store* Z, const BatchDesc& bd) {
 // xs is the input in the store precision, y a C128 output (overwritten).
 int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs,
                  void* y, void* partial, const void* lists, hipStream_t stream) {
-  if (!store_has_far(Z) || store_is_spectral(Z)) return 1;
+  if (store_is_spectral(Z)) return tuned_spectral(ctx, Z, bd, states, Z->near_dtype, xs, R3M_C128, y, partial, stream);
+  if (!store_has_far(Z)) return 1;
   const std::vector<int64_t> key = tune_key(Z, bd);
   auto it = ctx->tuned_groups.find(key);
   if (it != ctx->tuned_groups.end()) return it->second;
@@ -1835,12 +1836,91 @@ int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uin
   return best;
 }
 
-// displacement groups for (store, batch): the autotuned value when known
-int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd) {
-  if (store_is_spectral(Z)) return 1;
+// Spectral autotuner: the first time a (store, batch) pair is seen, time the
+// frequency product's shapes (the vector-unit kernel and, for complex64
+// spectra from 4 right-hand sides, each matrix-core shape) on the whole
+// matvec with the default workgroup order, then the other order of the full
+// batch on the two fastest matrix-core shapes; keep the fastest plan.
+// R3M_SPEC_SHAPE (an index of kSpecShapes) fixes the shape.
+int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
+                   const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t stream) {
   const std::vector<int64_t> key = tune_key(Z, bd);
   auto it = ctx->tuned_groups.find(key);
-  return it != ctx->tuned_groups.end() ? it->second : choose_chunks(bd, 64);
+  if (it != ctx->tuned_groups.end()) return it->second;
+  std::vector<int> shapes{0};
+  if (Z->far_dtype == R3M_SPEC_C64 && bd.B >= 4)
+    for (int k = 1; k < kSpecShapeCount; ++k) shapes.push_back(k);
+  if (const char* env = std::getenv("R3M_SPEC_SHAPE")) {
+    const int k = std::atoi(env);
+    if (spectral_plan_valid(Z, spec_plan(k, kSpecRhsFirst))) shapes = {k};
+  }
+  int best = spectral_default_plan(Z, bd.B);
+  if (shapes.size() == 1) {
+    best = spec_plan(shapes[0], kSpecRhsFirst);
+  } else {
+    hipEvent_t e0, e1;
+    R3M_CHECK_HIP(hipEventCreate(&e0));
+    R3M_CHECK_HIP(hipEventCreate(&e1));
+    auto time_plan = [&](int plan) {
+      launch_spectral(Z, bd, states, x_type, x, y_type, y, work, stream, nullptr, nullptr, plan);  // warm
+      R3M_CHECK_HIP(hipEventRecord(e0, stream));
+      for (int rep = 0; rep < 2; ++rep)
+        launch_spectral(Z, bd, states, x_type, x, y_type, y, work, stream, nullptr, nullptr, plan);
+      R3M_CHECK_HIP(hipEventRecord(e1, stream));
+      R3M_CHECK_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      R3M_CHECK_HIP(hipEventElapsedTime(&ms, e0, e1));
+      return ms;
+    };
+    // candidates in a fixed order; a later one must win by 3% (stable choices
+    // between runs when two plans are within noise)
+    float best_ms = 1e30f;
+    std::vector<std::pair<float, int>> mfma;
+    for (int k : shapes) {
+      const int plan = spec_plan(k, kSpecRhsFirst);
+      const float ms = time_plan(plan);
+      if (k != 0) mfma.push_back({ms, k});
+      if (ms < 0.97f * best_ms) {
+        best_ms = ms;
+        best = plan;
+      }
+    }
+    // the other workgroup order of the full batch: the default threshold
+    // orders RHS tile first from kSpecRhsFirst tiles on, so from there the
+    // alternative is the contiguous order at every count, below it RHS tile
+    // first from the batch's own tile count
+    const int n_bt = (bd.B + 15) / 16;
+    std::sort(mfma.begin(), mfma.end());
+    for (size_t i = 0; i < mfma.size() && i < 2 && n_bt > 1; ++i) {
+      const int k = mfma[i].second;
+      const int other = spec_plan(k, n_bt >= kSpecRhsFirst ? 255 : n_bt);
+      const float ms = time_plan(other);
+      if (ms < 0.97f * best_ms) {
+        best_ms = ms;
+        best = other;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  ctx->tuned_groups[key] = best;
+  return best;
+}
+
+// the plan of (store, batch): the autotuned (or pinned) value when known,
+// else the default
+int plan_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd) {
+  const std::vector<int64_t> key = tune_key(Z, bd);
+  auto it = ctx->tuned_groups.find(key);
+  if (it != ctx->tuned_groups.end()) return it->second;
+  return store_is_spectral(Z) ? spectral_default_plan(Z, bd.B) : choose_chunks(bd, 64);
+}
+
+bool plan_valid(const r3m_store* Z, const BatchDesc& bd, int plan) {
+  if (store_is_spectral(Z)) return spectral_plan_valid(Z, plan);
+  const int g = plan & kPlanGroups;
+  return (plan & ~(kPlanGroups | kPlanMfmaFar)) == 0 && g >= 1 && g <= max_groups(bd) &&
+         (!(plan & kPlanMfmaFar) || far_on_mfma(Z));
 }
 
 // partial: a workspace of matvec_partial_bytes(bd, Z, max_groups(bd)); lists:
@@ -1850,7 +1930,7 @@ void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
                    hipStream_t stream, const int* idle) {
   (void)ctx;
   if (store_is_spectral(Z)) {
-    launch_spectral(Z, bd, states, vec_dtype, x, vec_dtype, y, partial, stream, nullptr, idle);
+    launch_spectral(Z, bd, states, vec_dtype, x, vec_dtype, y, partial, stream, nullptr, idle, chunks);
     return;
   }
   if (!lists) lists = workspace_lists(partial, bd, Z);
@@ -1908,6 +1988,8 @@ int r3m_retrieved_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
     }
     // first C128 call on this (store, batch): tune the group count on this x
     // (the tuner writes y as C128, so C64 vectors take the tuned or default value)
+    if (store_is_spectral(Z))  // first call on this (store, batch): tune the frequency product on this x
+      tuned_spectral(ctx, Z, bd, batch->states, vec_dtype, x_dev, vec_dtype, y_dev, work_dev, stream);
     if (vec_dtype == R3M_C128 && store_has_far(Z) && !store_is_spectral(Z)) {
       const void* xs = x_dev;
       if (Z->near_dtype == R3M_C64) {
@@ -1936,9 +2018,33 @@ extern "C" int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_
     validate_store(Z);
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;
-    out = plan_groups(ctx, Z, get_batch(ctx, batch, kBW, kBH, 0)) & kPlanGroups;
+    out = store_is_spectral(Z) ? 1 : plan_groups(ctx, Z, get_batch(ctx, batch, kBW, kBH, 0)) & kPlanGroups;
   });
   return rc == R3M_OK ? out : rc;
+}
+
+extern "C" int32_t r3m_matvec_plan(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch) {
+  int32_t out = 0;
+  int rc = guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_store(Z);
+    validate_batch(batch, Z->Dx, Z->Dy);
+    if (batch->B == 0) return;
+    out = plan_groups(ctx, Z, get_batch(ctx, batch, kBW, kBH, 0));
+  });
+  return rc == R3M_OK ? out : rc;
+}
+
+extern "C" int r3m_matvec_set_plan(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t plan) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_store(Z);
+    validate_batch(batch, Z->Dx, Z->Dy);
+    if (batch->B == 0) return;
+    const BatchDesc& bd = get_batch(ctx, batch, kBW, kBH, 0);
+    R3M_REQUIRE(plan_valid(Z, bd, plan), R3M_ERR_INVALID_ARG, "plan does not fit this store and batch");
+    ctx->tuned_groups[tune_key(Z, bd)] = plan;
+  });
 }
 
 // ------------------------------------------------- allocation-free variant

@@ -5,11 +5,33 @@
 namespace r3m {
 
 void validate_store(const r3m_store* Z);
-// A matvec plan (the value the autotuner keeps per store and batch): the
-// displacement-group count in the low bits, kPlanMfmaFar for the matrix-core
-// far kernel
+// A matvec plan (the value the autotuner keeps per store and batch).
+// Compressed stores: the displacement-group count in the low bits,
+// kPlanMfmaFar for the matrix-core far kernel.  Spectral stores: kPlanSpectral,
+// the frequency-product shape in bits 0-3 (kSpecShapes) and in bits 4-11 the
+// count of live 16-RHS tiles from which the matrix-core product orders its
+// workgroups RHS tile first
 constexpr int kPlanGroups = 0xffff;
 constexpr int kPlanMfmaFar = 1 << 16;
+constexpr int kPlanSpectral = 1 << 17;
+static_assert(kPlanMfmaFar == R3M_PLAN_MFMA_FAR && kPlanSpectral == R3M_PLAN_SPECTRAL, "plan bits as published");
+// frequency-product shapes: {frequencies per wave, columns per staged chunk}
+// of the matrix-core kernel; {0, 0} is the vector-unit kernel (register tile
+// by batch width)
+struct SpecShape {
+  int kpw, pc;
+};
+constexpr SpecShape kSpecShapes[] = {{0, 0}, {1, 4}, {2, 4}, {2, 8}, {4, 4}, {1, 8}};
+constexpr int kSpecShapeCount = (int)(sizeof(kSpecShapes) / sizeof(kSpecShapes[0]));
+constexpr int kSpecRhsFirst = 8;  // default ordering threshold
+inline int spec_plan(int shape, int rhs_first) { return kPlanSpectral | shape | rhs_first << 4; }
+inline int spec_shape(int plan) { return plan & 15; }
+inline int spec_rhs_first(int plan) { return (plan >> 4) & 255; }
+// the untuned plan: matrix cores for complex64 spectra once a 16-wide RHS
+// tile is mostly full, the vector units otherwise
+int spectral_default_plan(const r3m_store* Z, int B);
+// the plan is valid for this store (shape and threshold in range)
+bool spectral_plan_valid(const r3m_store* Z, int plan);
 int choose_chunks(const BatchDesc& bd, int max_chunks);
 // largest displacement-group count the autotuner may pick (workspaces are sized for it)
 int max_groups(const BatchDesc& bd);
@@ -46,13 +68,18 @@ bool store_is_spectral(const r3m_store* Z);
 void validate_spectral(const r3m_store* Z);
 size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z);
 // x (x_type) to y (y_type); work: spectral_work_bytes; live and idle as above
+// plan: a spectral plan (kPlanSpectral set), anything else takes the default
 void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                      const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
-                     const int* idle = nullptr);
+                     const int* idle = nullptr, int plan = 0);
 // relaxed retrieval (wts [units][n_states], nullable) and the transposed operator
 void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                         const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
-                        const double* wts, bool tr, const int* idle = nullptr);
+                        const double* wts, bool tr, const int* idle = nullptr, int plan = 0);
+// times the frequency-product shapes once per (store, batch) on x (x_type) into
+// y (y_type) and keeps the fastest plan (the same map as tuned_groups)
+int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
+                   const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t stream);
 
 // near-field block ILU(0) (r3m_ilu_*): factors of every distinct codebook
 // (shared: right-hand sides with the same codebook share them; relaxed

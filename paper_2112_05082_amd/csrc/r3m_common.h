@@ -129,7 +129,7 @@ struct r3m_ctx_s {
   int* run_host = nullptr;                   // pinned [2]: running counts read back without a stall
   hipEvent_t ev_run[2] = {nullptr, nullptr};  // completion of those read-backs
   std::map<std::vector<int64_t>, hipGraphExec_t> graphs;
-  std::map<std::vector<int64_t>, int> tuned_groups;  // autotuned displacement groups per (store, batch)
+  std::map<std::vector<int64_t>, int> tuned_groups;  // autotuned (or pinned) matvec plans per (store, batch)
   uint64_t epoch = 0;  // counts entry calls (see get_batch)
 };
 

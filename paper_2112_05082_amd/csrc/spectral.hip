@@ -498,10 +498,8 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
 // Inside a solve the tiles are those with a live right-hand side (a list
 // built on the device each step), and the order follows their count: when
 // few are left, the contiguous order spreads them over all eight XCDs,
-// where the RHS-first order would put each tile on one XCD.
-#ifndef R3M_SPEC_RHS_FIRST
-#define R3M_SPEC_RHS_FIRST 8  // RHS tiles from which ids run over RHS tiles first
-#endif
+// where the RHS-first order would put each tile on one XCD.  The count from
+// which the RHS-first order is taken (rhs_first) is part of the plan.
 constexpr int kPM = 80, kPB = 16;
 constexpr int kZP = kPM + 1, kXP = kPB + 1;
 
@@ -511,7 +509,7 @@ __global__ void __launch_bounds__(256)
 spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __restrict__ Xh, C2<float>* __restrict__ Yh,
                          int n, int64_t K, int B, int n_mg, int n_bt, int64_t n_tiles, int lgGx, int lgGy,
                          const int* __restrict__ live, const int* __restrict__ idle,
-                         const int* __restrict__ tile_list, const int* __restrict__ n_live) {
+                         const int* __restrict__ tile_list, const int* __restrict__ n_live, int rhs_first) {
   if (live && *live == 0) return;
   typedef float v4 __attribute__((ext_vector_type(4)));
   constexpr int PK = 4 * KPW;                   // frequencies per workgroup
@@ -526,7 +524,7 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
   const int nl = tile_list ? *n_live : n_bt;
   int bt, mg;
   int64_t kt;
-  if (nl < R3M_SPEC_RHS_FIRST) {
+  if (nl < rhs_first) {
     const int64_t items = (n_tiles + 1) / 2 * 2 * n_mg * nl;
     const int64_t per = (items + 7) / 8, loc = blockIdx.x >> 3;  // grid: a multiple of 8
     if (loc >= per) return;
@@ -664,13 +662,6 @@ live_tiles_kernel(const int* __restrict__ idle, int B, int n_bt, int* __restrict
   if (t == 1023) *n_live = cnt[1023];
 }
 
-#ifndef R3M_SPEC_MFMA_KPW
-#define R3M_SPEC_MFMA_KPW 2
-#endif
-#ifndef R3M_SPEC_MFMA_PC
-#define R3M_SPEC_MFMA_PC 4
-#endif
-
 template <typename T, int MT, int BC>
 void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, bool tr, int lgGx,
                     int lgGy, hipStream_t s, const int* live, const int* idle) {
@@ -684,41 +675,60 @@ void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2
                        G2, B, n_mg, lgGx, lgGy, live, idle);
 }
 
-// register tile by batch width: 2 rows for one or two right-hand sides (a
-// stream of the spectra wants many waves in flight), 4 rows x 4 or 8
-// right-hand sides otherwise (arithmetic per load).  tl: room for the
-// live-tile list of the matrix-core product (ceil(B / 16) + 1 ints), used
-// with idle flags on wide batches
+// The matrix-core product with KPW frequencies per wave and PC columns per
+// staged chunk.  tl: room for the live-tile list (ceil(B / 16) + 1 ints),
+// used with idle flags on batches of at least rhs_first RHS tiles; with the
+// list the kernel picks the order from the live count, so the grid covers
+// both orders.
+template <int KPW, int PC>
+void launch_product_mfma(const C2<float>* Zh, const C2<float>* X, C2<float>* Y, int n, int64_t G2, int B, bool tr,
+                         int lgGx, int lgGy, hipStream_t s, const int* live, const int* idle, int* tl, int rf) {
+  constexpr int PK = 4 * KPW;
+  const int n_mg = (n + kPM - 1) / kPM, n_bt = (B + kPB - 1) / kPB;
+  const int64_t n_kt = (G2 + PK - 1) / PK;
+  const bool use_list = idle && tl && n_bt >= rf;
+  const int64_t nwg_c = ((n_kt + 1) / 2 * 2 * n_mg * (use_list ? std::min(rf - 1, n_bt) : n_bt) + 7) / 8 * 8;
+  const int64_t nwg_r = (n_kt * n_mg * n_bt + 7) / 8 * 8;
+  const int64_t nwg = use_list ? std::max(nwg_c, nwg_r) : n_bt < rf ? nwg_c : nwg_r;
+  const int* list = use_list ? tl : nullptr;
+  const int* cnt = use_list ? tl + n_bt : nullptr;
+  if (use_list) {
+    hipLaunchKernelGGL(live_tiles_kernel, dim3(1), dim3(1024), 0, s, idle, B, n_bt, tl, tl + n_bt);
+    R3M_CHECK_HIP(hipGetLastError());
+  }
+  if (tr)
+    hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, true>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y, n,
+                       G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf);
+  else
+    hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, false>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y,
+                       n, G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf);
+  R3M_CHECK_HIP(hipGetLastError());
+}
+
+// Per-frequency product by plan (a valid spectral plan).  The vector-unit
+// kernel takes its register tile by batch width: 2 rows for one or two
+// right-hand sides (a stream of the spectra wants many waves in flight), 4
+// rows x 4 or 8 right-hand sides otherwise (arithmetic per load).  Every
+// matrix-core shape sums each output over the columns in the same order (16x16x4
+// tiles of four consecutive columns, in increasing column order), so all of
+// them give the same bits.
 template <typename T>
 void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, bool tr, int lgGx, int lgGy,
-             hipStream_t s, const int* live, const int* idle, int* tl) {
-  if (sizeof(T) == 4 && B >= 12) {  // matrix cores once a 16-wide RHS tile is mostly full
-    constexpr int PK = 4 * R3M_SPEC_MFMA_KPW;
-    const int n_mg = (n + kPM - 1) / kPM, n_bt = (B + kPB - 1) / kPB;
-    const int64_t n_kt = (G2 + PK - 1) / PK;
-    // contiguous per-XCD order for fewer than R3M_SPEC_RHS_FIRST tiles, RHS
-    // tiles first otherwise; with a live-tile list the kernel picks the order
-    // from the live count, so the launch covers both
-    const bool use_list = idle && tl && n_bt >= R3M_SPEC_RHS_FIRST;
-    const int64_t nwg_c =
-        ((n_kt + 1) / 2 * 2 * n_mg * (use_list ? R3M_SPEC_RHS_FIRST - 1 : n_bt) + 7) / 8 * 8;
-    const int64_t nwg_r = (n_kt * n_mg * n_bt + 7) / 8 * 8;
-    const int64_t nwg = use_list ? std::max(nwg_c, nwg_r) : n_bt < R3M_SPEC_RHS_FIRST ? nwg_c : nwg_r;
-    const int* list = use_list ? tl : nullptr;
-    const int* cnt = use_list ? tl + n_bt : nullptr;
-    if (use_list) {
-      hipLaunchKernelGGL(live_tiles_kernel, dim3(1), dim3(1024), 0, s, idle, B, n_bt, tl, tl + n_bt);
-      R3M_CHECK_HIP(hipGetLastError());
+             hipStream_t s, const int* live, const int* idle, int* tl, int plan) {
+  if constexpr (sizeof(T) == 4) {
+    const C2<float>*zf = Zh, *xf = X;
+    C2<float>* yf = Y;
+    const int rf = spec_rhs_first(plan);
+    switch (spec_shape(plan)) {
+      case 1: return launch_product_mfma<1, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
+      case 2: return launch_product_mfma<2, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
+      case 3: return launch_product_mfma<2, 8>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
+      case 4: return launch_product_mfma<4, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
+      case 5: return launch_product_mfma<1, 8>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
+      default: break;
     }
-    if (tr)
-      hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC, true>), dim3((unsigned)nwg),
-                         dim3(256), 0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg,
-                         n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt);
-    else
-      hipLaunchKernelGGL((spec_product_mfma_kernel<R3M_SPEC_MFMA_KPW, R3M_SPEC_MFMA_PC, false>), dim3((unsigned)nwg),
-                         dim3(256), 0, s, (const C2<float>*)Zh, (const C2<float>*)X, (C2<float>*)Y, n, G2, B, n_mg,
-                         n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt);
-  } else if (B == 1)
+  }
+  if (B == 1)
     launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
   else if (B == 2)
     launch_product<T, 2, 2>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
@@ -760,7 +770,7 @@ size_t spectral_list_offset(const BatchDesc& bd, const r3m_store* Z) {
 template <typename T, typename XT, typename YT>
 void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
                     void* work, hipStream_t s, const int* live, const double* wts = nullptr, bool tr = false,
-                    C2<T>* macro_out = nullptr, const int* idle = nullptr) {
+                    C2<T>* macro_out = nullptr, const int* idle = nullptr, int plan = 0) {
   const int n = Z->n;
   const int lgGx = ilog2(next_pow2(2 * Z->Dx + 1)), lgGy = ilog2(next_pow2(2 * Z->Dy + 1));
   const int64_t G2 = (int64_t)1 << (lgGx + lgGy);
@@ -785,7 +795,8 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
   fft_pass<T, kFwdRows, XT>(A, lgGx, lgGy, ng, s);
   fft_pass<T, kFwdCols, XT>(A, lgGx, lgGy, ng, s);
   int* tl = (int*)((char*)work + spectral_list_offset(bd, Z));
-  product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl);
+  if (!(plan & kPlanSpectral)) plan = spectral_default_plan(Z, B);
+  product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, plan);
   A.data = Y;
   fft_pass<T, kInvCols, YT>(A, lgGx, lgGy, ng, s);
   fft_pass<T, kInvRows, YT>(A, lgGx, lgGy, ng, s);
@@ -854,17 +865,17 @@ size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z) {
 
 void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                         const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
-                        const double* wts, bool tr, const int* idle) {
+                        const double* wts, bool tr, const int* idle, int plan) {
   const bool xd = x_type == R3M_C128, yd = y_type == R3M_C128;
   if (Z->far_dtype == R3M_SPEC_C128) {
     R3M_REQUIRE(xd && yd, R3M_ERR_UNSUPPORTED, "complex128 spectra need C128 vectors");
-    spectral_typed<double, double, double>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle);
+    spectral_typed<double, double, double>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle, plan);
   } else if (xd && yd) {
-    spectral_typed<float, double, double>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle);
+    spectral_typed<float, double, double>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle, plan);
   } else if (!xd && yd) {
-    spectral_typed<float, float, double>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle);
+    spectral_typed<float, float, double>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle, plan);
   } else if (!xd && !yd) {
-    spectral_typed<float, float, float>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle);
+    spectral_typed<float, float, float>(Z, bd, states, x, y, work, s, live, wts, tr, nullptr, idle, plan);
   } else {
     R3M_REQUIRE(false, R3M_ERR_UNSUPPORTED, "C128 input with C64 output");
   }
@@ -872,8 +883,18 @@ void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
 
 void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                      const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
-                     const int* idle) {
-  launch_spectral_ex(Z, bd, states, x_type, x, y_type, y, work, s, live, nullptr, false, idle);
+                     const int* idle, int plan) {
+  launch_spectral_ex(Z, bd, states, x_type, x, y_type, y, work, s, live, nullptr, false, idle, plan);
+}
+
+int spectral_default_plan(const r3m_store* Z, int B) {
+  return spec_plan(Z->far_dtype == R3M_SPEC_C64 && B >= 12 ? 2 : 0, kSpecRhsFirst);
+}
+
+bool spectral_plan_valid(const r3m_store* Z, int plan) {
+  const int shape = spec_shape(plan), rf = spec_rhs_first(plan);
+  return (plan & ~(kPlanSpectral | 0xfff)) == 0 && (plan & kPlanSpectral) && shape < kSpecShapeCount && rf >= 1 &&
+         (shape == 0 || Z->far_dtype == R3M_SPEC_C64);
 }
 
 size_t relaxed_work_bytes(const BatchDesc& bd, const r3m_store* Z) { return spectral_work_bytes(bd, Z); }

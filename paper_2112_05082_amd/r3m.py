@@ -33,7 +33,8 @@ EXPORTED = (
     "r3m_far_count", "r3m_far_bytes", "r3m_compress_work_bytes", "r3m_compress_far",
     "r3m_spectral_bytes", "r3m_build_spectral", "r3m_relaxed_work_bytes", "r3m_relaxed_matvec",
     "r3m_relaxed_gradient_work_bytes", "r3m_relaxed_gradient", "r3m_relaxed_rhs", "r3m_relaxed_objective",
-    "r3m_matvec_work_bytes", "r3m_retrieved_matvec", "r3m_matvec_groups",
+    "r3m_matvec_work_bytes", "r3m_retrieved_matvec", "r3m_matvec_groups", "r3m_matvec_plan",
+    "r3m_matvec_set_plan",
     "r3m_static_scratch_bytes", "r3m_retrieved_matvec_static",
     "r3m_gmres_work_bytes", "r3m_gmres_solve", "r3m_ilu_bytes", "r3m_ilu_factor", "r3m_ilu_apply",
     "r3m_plane_wave_rhs", "r3m_rcs",
@@ -129,6 +130,8 @@ def load(path: str = LIB_PATH):
         "r3m_retrieved_matvec": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int, vp, vp, vp,
                                            sz, vp]),
         "r3m_matvec_groups": (i32, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
+        "r3m_matvec_plan": (i32, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
+        "r3m_matvec_set_plan": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), i32]),
         "r3m_static_scratch_bytes": (sz, []),
         "r3m_retrieved_matvec_static": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int, vp, vp, vp]),
         "r3m_gmres_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(StoreC), C.POINTER(BatchC),
@@ -525,6 +528,38 @@ def matvec_groups(ctx, store: Store, batch: Batch) -> int:
     if g < 0:
         _check(g, ctx.handle)
     return g
+
+
+PLAN_MFMA_FAR, PLAN_SPECTRAL = 1 << 16, 1 << 17
+# frequency-product shapes of spectral stores: {frequencies per wave, columns
+# per staged chunk} of the matrix-core kernel; (0, 0) is the vector-unit kernel
+SPEC_SHAPES = ((0, 0), (1, 4), (2, 4), (2, 8), (4, 4), (1, 8))
+
+
+def spec_plan(shape: int, rhs_first: int = 8) -> int:
+    return PLAN_SPECTRAL | shape | rhs_first << 4
+
+
+def matvec_plan(ctx, store: Store, batch: Batch) -> int:
+    """The launch plan of (store, batch): tuned, pinned or default (see r3m_matvec_plan)."""
+    sc = store.c()
+    p = load().r3m_matvec_plan(ctx.handle, C.byref(sc), C.byref(batch.cs))
+    if p < 0:
+        _check(p, ctx.handle)
+    return p
+
+
+def decode_plan(plan: int) -> dict:
+    if plan & PLAN_SPECTRAL:
+        k = plan & 15
+        return {"kind": "spectral", "shape": k, "mfma": k != 0, "kpw": SPEC_SHAPES[k][0] if k < len(SPEC_SHAPES) else None,
+                "pc": SPEC_SHAPES[k][1] if k < len(SPEC_SHAPES) else None, "rhs_first": (plan >> 4) & 255}
+    return {"kind": "compressed", "groups": plan & 0xFFFF, "mfma_far": bool(plan & PLAN_MFMA_FAR)}
+
+
+def matvec_set_plan(ctx, store: Store, batch: Batch, plan: int) -> None:
+    sc = store.c()
+    _check(load().r3m_matvec_set_plan(ctx.handle, C.byref(sc), C.byref(batch.cs), int(plan)), ctx.handle)
 
 
 def gmres_work_bytes(ctx, store: Store, batch: Batch, restart: int, store64: Store | None = None,
