@@ -246,13 +246,17 @@ int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batc
  * stores (R3M_SPEC_*): R3M_PLAN_SPECTRAL, in bits 0-3 the frequency-product
  * shape (0: vector units; 1..5: matrix cores with {frequencies per wave,
  * columns per staged chunk} = {1,4}, {2,4}, {2,8}, {4,4}, {1,8}; complex64
- * spectra only) and in bits 4-11 the count of live 16-RHS tiles from which
- * the matrix-core product orders its workgroups RHS tile first.  The
- * spectral autotuner runs on the first r3m_retrieved_matvec or
+ * spectra only), in bits 4-11 the count of live 16-RHS tiles from which
+ * the matrix-core product orders its workgroups RHS tile first, and
+ * R3M_PLAN_SPEC_TWO_PASS when the retrieval transforms run as separate row
+ * and column passes through HBM although the fused 2-D transform (complex64
+ * grids of at most 16,384 points, one grid per workgroup in LDS) applies.
+ * The spectral autotuner runs on the first r3m_retrieved_matvec or
  * r3m_gmres_solve of the pair.  Every matrix-core shape and order gives the
- * same bits; the vector-unit shape differs from them by FP32 rounding order
- * only.  Returns the plan (> 0), 0 for an empty batch, or a negative
- * r3m_status. */
+ * same bits; the vector-unit shape and the transform form differ by FP32
+ * rounding order only.  Returns the plan (> 0), 0 for an empty batch, or a
+ * negative r3m_status. */
+#define R3M_PLAN_SPEC_TWO_PASS (1 << 12)
 #define R3M_PLAN_MFMA_FAR (1 << 16)
 #define R3M_PLAN_SPECTRAL (1 << 17)
 int32_t r3m_matvec_plan(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch);

@@ -1840,7 +1840,8 @@ int tuned_groups(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uin
 // frequency product's shapes (the vector-unit kernel and, for complex64
 // spectra from 4 right-hand sides, each matrix-core shape) on the whole
 // matvec with the default workgroup order, then the other order of the full
-// batch on the two fastest matrix-core shapes; keep the fastest plan.
+// batch on the two fastest matrix-core shapes, then the two-pass transforms
+// against the fused ones; keep the fastest plan.
 // R3M_SPEC_SHAPE (an index of kSpecShapes) fixes the shape.
 int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                    const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t stream) {
@@ -1861,11 +1862,12 @@ int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
     hipEvent_t e0, e1;
     R3M_CHECK_HIP(hipEventCreate(&e0));
     R3M_CHECK_HIP(hipEventCreate(&e1));
+    // one warm and one timed call per candidate (a wide batch's matvec runs
+    // tens of milliseconds, well above the timer's noise)
     auto time_plan = [&](int plan) {
       launch_spectral(Z, bd, states, x_type, x, y_type, y, work, stream, nullptr, nullptr, plan);  // warm
       R3M_CHECK_HIP(hipEventRecord(e0, stream));
-      for (int rep = 0; rep < 2; ++rep)
-        launch_spectral(Z, bd, states, x_type, x, y_type, y, work, stream, nullptr, nullptr, plan);
+      launch_spectral(Z, bd, states, x_type, x, y_type, y, work, stream, nullptr, nullptr, plan);
       R3M_CHECK_HIP(hipEventRecord(e1, stream));
       R3M_CHECK_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -1900,6 +1902,9 @@ int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
         best = other;
       }
     }
+    // the transform form: two passes through HBM against the fused 2-D transform
+    if (spectral_fused_transforms(Z) && time_plan(best | kPlanSpecTwoPass) < 0.97f * best_ms)
+      best |= kPlanSpecTwoPass;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }

@@ -10,11 +10,15 @@ void validate_store(const r3m_store* Z);
 // kPlanMfmaFar for the matrix-core far kernel.  Spectral stores: kPlanSpectral,
 // the frequency-product shape in bits 0-3 (kSpecShapes) and in bits 4-11 the
 // count of live 16-RHS tiles from which the matrix-core product orders its
-// workgroups RHS tile first
+// workgroups RHS tile first, and kPlanSpecTwoPass for the row and column
+// transform passes through HBM where the fused 2-D transform would apply
 constexpr int kPlanGroups = 0xffff;
 constexpr int kPlanMfmaFar = 1 << 16;
 constexpr int kPlanSpectral = 1 << 17;
-static_assert(kPlanMfmaFar == R3M_PLAN_MFMA_FAR && kPlanSpectral == R3M_PLAN_SPECTRAL, "plan bits as published");
+constexpr int kPlanSpecTwoPass = 1 << 12;
+static_assert(kPlanMfmaFar == R3M_PLAN_MFMA_FAR && kPlanSpectral == R3M_PLAN_SPECTRAL &&
+                  kPlanSpecTwoPass == R3M_PLAN_SPEC_TWO_PASS,
+              "plan bits as published");
 // frequency-product shapes: {frequencies per wave, columns per staged chunk}
 // of the matrix-core kernel; {0, 0} is the vector-unit kernel (register tile
 // by batch width)
@@ -32,6 +36,8 @@ inline int spec_rhs_first(int plan) { return (plan >> 4) & 255; }
 int spectral_default_plan(const r3m_store* Z, int B);
 // the plan is valid for this store (shape and threshold in range)
 bool spectral_plan_valid(const r3m_store* Z, int plan);
+// the store's retrieval transforms can run fused (complex64 grids that fit LDS)
+bool spectral_fused_transforms(const r3m_store* Z);
 int choose_chunks(const BatchDesc& bd, int max_chunks);
 // largest displacement-group count the autotuner may pick (workspaces are sized for it)
 int max_groups(const BatchDesc& bd);

@@ -23,6 +23,7 @@
 #include "matvec_internal.h"
 
 #include <algorithm>
+#include <atomic>
 
 namespace r3m {
 namespace {
@@ -376,6 +377,271 @@ void fft_pass(FftArgs<T> A, int lgGx, int lgGy, int64_t n_grids, hipStream_t s) 
   const size_t lds = ((size_t)((size_t)1 << A.lg_lpw) * (G + (G >> 4) + 1) + G) * sizeof(C2<T>);
   hipLaunchKernelGGL((fft_kernel<T, MODE, VT>), dim3((unsigned)n_wg), dim3(256), lds, s, A);
   R3M_CHECK_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------------- fused 2-D transforms
+//
+// Complex64 grids of up to 16,384 points: one workgroup holds a whole Gy x Gx
+// grid in LDS (element (gx, gy) at gy Sx + gx + gx / 16 with Sx = Gx + Gx / 16
+// + 1, the padding of lds_at) and runs the row and the column stages there, so
+// that a grid crosses HBM once per direction; the two-pass form above writes
+// it out between its passes and reads it back.
+//   forward: the first row stage gathers the masked compact input straight
+//            into registers (rows gy < Ly only: the others are zero), the
+//            first column stage reads rows gy >= Ly as zero, and the last
+//            column stage writes X^ to HBM;
+//   inverse: the first column stage reads Y^ from HBM, the last column stage
+//            keeps rows gy < Ly only, the row stages run on those rows and
+//            the last one writes the active rows of the compact output
+//            (times 1 / (Gx Gy)).
+// Workgroups are persistent over the grids g = b n + c: the workgroups with
+// id = x mod 8 (one XCD) take the contiguous eighth x of the grids,
+// interleaved over it, so the consecutive channels of a right-hand side,
+// which gather from (or scatter to) the same lines of its compact vector, are
+// in flight together in one L2.
+struct Fft2Args {
+  C2<float>* grid;  // [B][n][Gy][Gx]
+  const RhsDev* rhs;
+  const uint8_t* states;
+  int n_states, n, n_a;
+  int lgGx, lgGy;
+  int64_t n_grids;
+  const void* x;  // forward: compact input
+  void* y;        // inverse: compact output
+  const int* live;
+  const int* idle;
+};
+
+
+__device__ __forceinline__ int at2(int gx, int gy, int Sx) { return gy * Sx + gx + (gx >> 4); }
+
+// One Stockham stage of radix R (the map of stockham_stage) over n_lines
+// lines of length 2^lgG of the LDS grid: rows (line = gy, element = gx; a
+// thread's items are adjacent elements of one line) or columns (line = gx,
+// element = gy; adjacent threads take adjacent lines, so that a wave touches
+// 64 adjacent columns, in LDS and in HBM alike).  GSRC: the inputs come from
+// the HBM grid gm (row-major, Gx = 2^lg_lines columns) instead of LDS; GDST:
+// the outputs go there.  Elements e >= nz read as zero and outputs at e >=
+// keep are dropped (first forward and last inverse column stages).  A stage
+// that writes LDS does so in place, after a barrier that follows every read,
+// and ends with a barrier.  Up to 16 elements per thread.
+template <int R, bool COLS, int SGN, bool GSRC, bool GDST>
+__device__ __forceinline__ void stage2d(float2* __restrict__ buf, int Sx, const float2* __restrict__ tw,
+                                        float2* __restrict__ gm, int lgG, int lgNs, int n_lines, int lg_lines,
+                                        int nz, int keep) {
+  constexpr int LR = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+  constexpr int IT = 16 / R;
+  const int lgQ = lgG - LR;
+  const int Ns = 1 << lgNs;
+  const int n_items = n_lines << lgQ;
+  const int tws = lgG - lgNs - LR;
+  C2<float> a[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int item = threadIdx.x + it * blockDim.x;
+    if (item < n_items) {
+      const int li = COLS ? item & ((1 << lg_lines) - 1) : item >> lgQ;
+      const int j = COLS ? item >> lg_lines : item & ((1 << lgQ) - 1);
+      const int k = j & (Ns - 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int e = j + (r << lgQ);
+        const int gx = COLS ? li : e, gy = COLS ? e : li;
+        float2 v = make_float2(0.f, 0.f);
+        if (e < nz) v = GSRC ? gm[((int64_t)gy << lg_lines) + gx] : buf[at2(gx, gy, Sx)];
+        if (r > 0 && lgNs > 0) {
+          const float2 w = tw[(r * k) << tws];
+          v = make_float2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+        }
+        a[it][r] = {v.x, v.y};
+      }
+      dft_regs<float, R, SGN>(a[it]);
+    }
+  }
+  if (!GDST) __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int item = threadIdx.x + it * blockDim.x;
+    if (item < n_items) {
+      const int li = COLS ? item & ((1 << lg_lines) - 1) : item >> lgQ;
+      const int j = COLS ? item >> lg_lines : item & ((1 << lgQ) - 1);
+      const int k = j & (Ns - 1);
+      const int o = ((j >> lgNs) << (lgNs + LR)) + k;
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        const int e = o + (q << lgNs);
+        const int gx = COLS ? li : e, gy = COLS ? e : li;
+        const float2 v = make_float2(a[it][q].re, a[it][q].im);
+        if (GDST)
+          gm[((int64_t)gy << lg_lines) + gx] = v;
+        else if (e < keep)
+          buf[at2(gx, gy, Sx)] = v;
+      }
+    }
+  }
+  if (!GDST) __syncthreads();
+}
+
+// Every stage of one direction of a G = 2^LG grid: radix-16 stages, then one
+// of radix 2, 4 or 8 for the rest of LG.  GSRC: the first stage reads the HBM
+// grid; GDST: the last one writes it; nz applies to the first stage, keep to
+// the last.
+template <bool COLS, int SGN, int LG, bool GSRC, bool GDST, int LGNS = 0>
+__device__ __forceinline__ void line_stages(float2* buf, const float2* tw, float2* gm, int n_lines, int nz,
+                                            int keep) {
+  if constexpr (LGNS < LG) {
+    constexpr int LR = LG - LGNS >= 4 ? 4 : LG - LGNS;
+    constexpr bool first = LGNS == 0, last = LGNS + LR == LG;
+    constexpr int G = 1 << LG, Sx = G + G / 16 + 1;
+    stage2d<1 << LR, COLS, SGN, GSRC && first, GDST && last>(buf, Sx, tw, gm, LG, LGNS, n_lines, LG,
+                                                             first ? nz : G, last ? keep : G);
+    line_stages<COLS, SGN, LG, GSRC, GDST, LGNS + LR>(buf, tw, gm, n_lines, nz, keep);
+  }
+}
+
+// Square grids G x G, G = 2^LG (the stores' transform grids for square arrays)
+// one complex value of a compact vector (float or double pairs, aligned to
+// the pair) as a single load or store
+template <typename VT>
+__device__ __forceinline__ float2 load_c2(const VT* p) {
+  if constexpr (sizeof(VT) == 8) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    return make_float2((float)v.x, (float)v.y);
+  } else {
+    return *reinterpret_cast<const float2*>(p);
+  }
+}
+template <typename VT>
+__device__ __forceinline__ void store_c2(VT* p, float re, float im) {
+  if constexpr (sizeof(VT) == 8)
+    *reinterpret_cast<double2*>(p) = make_double2((double)re, (double)im);
+  else
+    *reinterpret_cast<float2*>(p) = make_float2(re, im);
+}
+
+template <int LG>
+constexpr int fft2_threads() {
+  return (1 << (2 * LG)) / 16 > 64 ? (1 << (2 * LG)) / 16 : 64;
+}
+
+template <bool INV, typename VT, int LG>
+__global__ void __launch_bounds__(fft2_threads<LG>()) fft2_kernel(Fft2Args A) {
+  if (A.live && *A.live == 0) return;
+  constexpr int SGN = INV ? 1 : -1;
+  constexpr int G = 1 << LG, Sx = G + G / 16 + 1;
+  // threads; points of the rows gy < Ly <= G / 2 per thread (an array of
+  // Ly rows has Ly - 1 <= Dy displacements and G >= 2 Dy + 1)
+  constexpr int kNT = fft2_threads<LG>(), kPer = (G * G / 2 + kNT - 1) / kNT;
+  extern __shared__ unsigned char smem_raw[];
+  float2* buf = reinterpret_cast<float2*>(smem_raw);
+  float2* tw = buf + G * Sx;
+  for (int m = threadIdx.x; m < G; m += blockDim.x) {
+    float sn, cs;
+    sincospif((float)(2 * m) / (float)G, &sn, &cs);
+    tw[m] = make_float2(cs, (float)SGN * sn);
+  }
+  const float scale = 1.0f / (float)(G * G);
+  const int64_t per_x = gridDim.x >> 3, span = (A.n_grids + 7) >> 3;
+  const int64_t g_end = min(A.n_grids, ((int64_t)blockIdx.x & 7) * span + span);
+  for (int64_t g = ((int64_t)blockIdx.x & 7) * span + (blockIdx.x >> 3); g < g_end; g += per_x) {
+    const int b = (int)(g / A.n), c = (int)(g - (int64_t)b * A.n);
+    if (A.idle && A.idle[b]) continue;  // uniform over the workgroup
+    const RhsDev R = A.rhs[b];
+    const int Lx = R.Lx, Ly = R.Ly;
+    // channel c is row rc of state sc: a unit contributes (or receives) it
+    // when its state byte is sc
+    const int sc = c / A.n_a, rc = c - sc * A.n_a;
+    float2* grid = reinterpret_cast<float2*>(A.grid) + (g << (2 * LG));
+    __syncthreads();  // the previous grid's last LDS reads (and the twiddle table) are done
+    if (!INV) {
+      // masked compact input -> rows gy < Ly of the LDS grid: every state
+      // byte first, then every input, so that the loads overlap
+      int sv[kPer];
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
+        sv[i] = t < (Ly << LG) && gx < Lx ? (int)A.states[R.state_off + (int64_t)gy * Lx + gx] : -1;
+      }
+      float2 vv[kPer];
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
+        vv[i] = make_float2(0.f, 0.f);
+        if (sv[i] == sc) {
+          vv[i] = load_c2<VT>((const VT*)A.x + ((R.unit_off + (int64_t)gy * Lx + gx) * A.n_a + rc) * 2);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int t = threadIdx.x + i * kNT;
+        if (t < (Ly << LG)) buf[at2(t & (G - 1), t >> LG, Sx)] = vv[i];
+      }
+      __syncthreads();
+      line_stages<false, SGN, LG, false, false>(buf, tw, grid, Ly, G, G);
+      line_stages<true, SGN, LG, false, true>(buf, tw, grid, G, Ly, G);
+    } else {
+      line_stages<true, SGN, LG, true, false>(buf, tw, grid, G, G, Ly);
+      line_stages<false, SGN, LG, false, false>(buf, tw, grid, Ly, G, G);
+      // active rows of units gx < Lx, gy < Ly -> compact output (state
+      // bytes first, as for the input)
+      int sv[kPer];
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
+        sv[i] = t < (Ly << LG) && gx < Lx ? (int)A.states[R.state_off + (int64_t)gy * Lx + gx] : -1;
+      }
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
+        if (sv[i] == sc) {
+          const float2 v = buf[at2(gx, gy, Sx)];
+          store_c2<VT>((VT*)A.y + ((R.unit_off + (int64_t)gy * Lx + gx) * A.n_a + rc) * 2, v.x * scale,
+                       v.y * scale);
+        }
+      }
+    }
+  }
+}
+
+// square grids from 4 x 4 to 128 x 128
+bool fft2_fits(int lgGx, int lgGy) { return lgGx == lgGy && lgGx >= 2 && lgGx <= 7; }
+
+size_t fft2_lds_bytes(int lgGx, int lgGy) {
+  const size_t Gx = (size_t)1 << lgGx, Gy = (size_t)1 << lgGy;
+  return (Gy * (Gx + (Gx >> 4) + 1) + Gx + Gy) * sizeof(C2<float>);
+}
+
+template <bool INV, typename VT, int LG>
+void fft2_launch(const Fft2Args& A, hipStream_t s) {
+  const int threads = fft2_threads<LG>();
+  const size_t lds = fft2_lds_bytes(LG, LG);
+  const int64_t nwg = std::min<int64_t>((A.n_grids + 7) / 8 * 8, 2048);
+  // the LDS limit of the kernel, raised once per device (outside any capture
+  // in practice: the first call on a device comes before a solve captures)
+  static std::atomic<uint64_t> raised{0};
+  int dev = 0;
+  R3M_CHECK_HIP(hipGetDevice(&dev));
+  const uint64_t bit = (uint64_t)1 << (dev & 63);
+  if (!(raised.load() & bit)) {
+    R3M_CHECK_HIP(hipFuncSetAttribute((const void*)fft2_kernel<INV, VT, LG>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    raised.fetch_or(bit);
+  }
+  hipLaunchKernelGGL((fft2_kernel<INV, VT, LG>), dim3((unsigned)nwg), dim3(threads), lds, s, A);
+  R3M_CHECK_HIP(hipGetLastError());
+}
+
+template <bool INV, typename VT>
+void fft2_pass(const Fft2Args& A, hipStream_t s) {
+  switch (A.lgGx) {
+    case 2: return fft2_launch<INV, VT, 2>(A, s);
+    case 3: return fft2_launch<INV, VT, 3>(A, s);
+    case 4: return fft2_launch<INV, VT, 4>(A, s);
+    case 5: return fft2_launch<INV, VT, 5>(A, s);
+    case 6: return fft2_launch<INV, VT, 6>(A, s);
+    case 7: return fft2_launch<INV, VT, 7>(A, s);
+    default: R3M_REQUIRE(false, R3M_ERR_UNSUPPORTED, "fused transform grid out of range");
+  }
 }
 
 // Circulant embedding of the displacement blocks dense[slot][m][n]
@@ -791,15 +1057,44 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
   A.live = live;
   A.idle = idle;
   const int64_t ng = (int64_t)B * n;
-  A.data = X;
-  fft_pass<T, kFwdRows, XT>(A, lgGx, lgGy, ng, s);
-  fft_pass<T, kFwdCols, XT>(A, lgGx, lgGy, ng, s);
-  int* tl = (int*)((char*)work + spectral_list_offset(bd, Z));
   if (!(plan & kPlanSpectral)) plan = spectral_default_plan(Z, B);
+  // the fused 2-D transforms where the grid fits LDS (complex64, retrieval)
+  const bool fused = sizeof(T) == 4 && !wts && !macro_out && !(plan & kPlanSpecTwoPass) && fft2_fits(lgGx, lgGy);
+  if (fused)
+    for (int b = 0; b < B; ++b)
+      R3M_REQUIRE(2 * bd.Ly[b] <= (1 << lgGy) && bd.Lx[b] <= (1 << lgGx), R3M_ERR_INVALID_ARG,
+                  "array larger than the store's displacement range");
+  Fft2Args F{};
+  if (fused) {
+    F.rhs = bd.rhs;
+    F.states = states;
+    F.n_states = Z->n_states;
+    F.n = n;
+    F.n_a = A.n_a;
+    F.lgGx = lgGx;
+    F.lgGy = lgGy;
+    F.n_grids = ng;
+    F.x = x;
+    F.y = y;
+    F.live = live;
+    F.idle = idle;
+    F.grid = (C2<float>*)X;
+    fft2_pass<false, XT>(F, s);
+  } else {
+    A.data = X;
+    fft_pass<T, kFwdRows, XT>(A, lgGx, lgGy, ng, s);
+    fft_pass<T, kFwdCols, XT>(A, lgGx, lgGy, ng, s);
+  }
+  int* tl = (int*)((char*)work + spectral_list_offset(bd, Z));
   product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, plan);
-  A.data = Y;
-  fft_pass<T, kInvCols, YT>(A, lgGx, lgGy, ng, s);
-  fft_pass<T, kInvRows, YT>(A, lgGx, lgGy, ng, s);
+  if (fused) {
+    F.grid = (C2<float>*)Y;
+    fft2_pass<true, YT>(F, s);
+  } else {
+    A.data = Y;
+    fft_pass<T, kInvCols, YT>(A, lgGx, lgGy, ng, s);
+    fft_pass<T, kInvRows, YT>(A, lgGx, lgGy, ng, s);
+  }
   if (wts && !macro_out) {
     hipLaunchKernelGGL((relaxed_sum_kernel<T, YT>), dim3(ceil_div((size_t)bd.max_units * A.n_a, 256), B), dim3(256),
                        0, s, bd.rhs, (const C2<T>*)A.ymacro, n, A.n_a, A.n_states, (YT*)y, idle);
@@ -893,8 +1188,13 @@ int spectral_default_plan(const r3m_store* Z, int B) {
 
 bool spectral_plan_valid(const r3m_store* Z, int plan) {
   const int shape = spec_shape(plan), rf = spec_rhs_first(plan);
-  return (plan & ~(kPlanSpectral | 0xfff)) == 0 && (plan & kPlanSpectral) && shape < kSpecShapeCount && rf >= 1 &&
-         (shape == 0 || Z->far_dtype == R3M_SPEC_C64);
+  return (plan & ~(kPlanSpectral | kPlanSpecTwoPass | 0xfff)) == 0 && (plan & kPlanSpectral) &&
+         shape < kSpecShapeCount && rf >= 1 && (shape == 0 || Z->far_dtype == R3M_SPEC_C64);
+}
+
+bool spectral_fused_transforms(const r3m_store* Z) {
+  return Z->far_dtype == R3M_SPEC_C64 &&
+         fft2_fits(ilog2(next_pow2(2 * Z->Dx + 1)), ilog2(next_pow2(2 * Z->Dy + 1)));
 }
 
 size_t relaxed_work_bytes(const BatchDesc& bd, const r3m_store* Z) { return spectral_work_bytes(bd, Z); }

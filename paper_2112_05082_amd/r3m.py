@@ -530,14 +530,14 @@ def matvec_groups(ctx, store: Store, batch: Batch) -> int:
     return g
 
 
-PLAN_MFMA_FAR, PLAN_SPECTRAL = 1 << 16, 1 << 17
+PLAN_SPEC_TWO_PASS, PLAN_MFMA_FAR, PLAN_SPECTRAL = 1 << 12, 1 << 16, 1 << 17
 # frequency-product shapes of spectral stores: {frequencies per wave, columns
 # per staged chunk} of the matrix-core kernel; (0, 0) is the vector-unit kernel
 SPEC_SHAPES = ((0, 0), (1, 4), (2, 4), (2, 8), (4, 4), (1, 8))
 
 
-def spec_plan(shape: int, rhs_first: int = 8) -> int:
-    return PLAN_SPECTRAL | shape | rhs_first << 4
+def spec_plan(shape: int, rhs_first: int = 8, two_pass: bool = False) -> int:
+    return PLAN_SPECTRAL | shape | rhs_first << 4 | (PLAN_SPEC_TWO_PASS if two_pass else 0)
 
 
 def matvec_plan(ctx, store: Store, batch: Batch) -> int:
@@ -553,7 +553,8 @@ def decode_plan(plan: int) -> dict:
     if plan & PLAN_SPECTRAL:
         k = plan & 15
         return {"kind": "spectral", "shape": k, "mfma": k != 0, "kpw": SPEC_SHAPES[k][0] if k < len(SPEC_SHAPES) else None,
-                "pc": SPEC_SHAPES[k][1] if k < len(SPEC_SHAPES) else None, "rhs_first": (plan >> 4) & 255}
+                "pc": SPEC_SHAPES[k][1] if k < len(SPEC_SHAPES) else None, "rhs_first": (plan >> 4) & 255,
+                "two_pass": bool(plan & PLAN_SPEC_TWO_PASS)}
     return {"kind": "compressed", "groups": plan & 0xFFFF, "mfma_far": bool(plan & PLAN_MFMA_FAR)}
 
 

@@ -144,4 +144,37 @@ def test_plan_validation(lib):
     # the default of an untuned pair: vector units for one right-hand side
     batch2 = r3m.Batch.from_codebooks([cb.uniform(L, 2, 2)], [L], DEV)
     assert r3m.decode_plan(r3m.matvec_plan(ctx, s64, batch2)) == {
-        "kind": "spectral", "shape": 0, "mfma": False, "kpw": 0, "pc": 0, "rhs_first": 8}
+        "kind": "spectral", "shape": 0, "mfma": False, "kpw": 0, "pc": 0, "rhs_first": 8,
+        "two_pass": False}
+
+
+@pytest.mark.parametrize("L", [2, 4, 8, 12, 24, 40])
+def test_fused_transforms_match_two_pass(lib, L):
+    """The fused 2-D transforms (one grid per workgroup in LDS) against the
+    two-pass ones on the same store: transform grids from 4 x 4 to 128 x 128
+    (one to three stages per direction, every radix), arrays smaller than the
+    store's extent and rectangular ones (rows gy >= Ly and columns gx >= Lx of
+    a grid are zero), complex128 and complex64 vectors."""
+    r3m, pipeline, ctx, geom = lib
+    spec = pipeline.spectral_store(ctx, geom, L, 2, r3m.C64, DEV)
+    shapes = [(L, L), (max(1, L // 2), L), (L, max(1, L - 3)), (1, 1), (L, L)]
+    rng = np.random.default_rng(900 + L)
+    books = [rng.integers(0, 2, lx * ly).astype(np.uint8) for lx, ly in shapes]
+    uoff = np.cumsum([0] + [lx * ly for lx, ly in shapes])[:-1].tolist()
+    batch = r3m.Batch(shapes, uoff, uoff, torch.from_numpy(np.concatenate(books)).to(DEV))
+    n1 = sum(lx * ly for lx, ly in shapes) * 40
+    x = torch.from_numpy(cb.random_complex(n1, 77 + L)).to(DEV)
+    worst = 0.0
+    for vt, xv in ((r3m.C128, x), (r3m.C64, x.to(torch.complex64))):
+        work = torch.empty(r3m.matvec_work_bytes(ctx, spec, batch, vt), dtype=torch.uint8, device=DEV)
+        ys = []
+        for two_pass in (False, True):
+            r3m.matvec_set_plan(ctx, spec, batch, r3m.spec_plan(0, 8, two_pass))
+            y = torch.zeros_like(xv)
+            r3m.r3m_retrieved_matvec(ctx, spec, batch, vt, xv, y, work)
+            torch.cuda.synchronize()
+            ys.append(y.to(torch.complex128).cpu().numpy())
+        assert np.abs(ys[0]).max() > 0
+        worst = max(worst, rel_max(ys[0], ys[1]))
+    print(f"{L}x{L} store: fused vs two-pass transforms, max relative difference {worst:.1e}")
+    assert worst <= 1e-6
