@@ -54,8 +54,11 @@ class RwgMesh:
         return len(self.rwg_len)
 
 
-def rwg_mesh(vert, tri, rwg, offset=(0.0, 0.0, 0.0), unit=(0, 0)) -> RwgMesh:
-    """Build an RwgMesh from a connectivity table, translated by `offset`."""
+def rwg_mesh(vert, tri, rwg, offset=(0.0, 0.0, 0.0), unit=(0, 0), tri_cell=None) -> RwgMesh:
+    """Build an RwgMesh from a connectivity table, translated by `offset`.
+
+    Every triangle is in cell `unit`, shifted by tri_cell[t] when given (the
+    neighbour-cell halves of bridging bases, Sec. III-B)."""
     vert = np.asarray(vert, dtype=np.float64) + np.asarray(offset, dtype=np.float64)
     tri = np.asarray(tri)
     rwg = np.asarray(rwg)
@@ -69,6 +72,8 @@ def rwg_mesh(vert, tri, rwg, offset=(0.0, 0.0, 0.0), unit=(0, 0)) -> RwgMesh:
             free[m, s] = loc[0]
     elen = np.linalg.norm(vert[rwg[:, 2]] - vert[rwg[:, 3]], axis=1)
     tri_unit = np.tile(np.asarray(unit, dtype=np.int64), (len(tri), 1))
+    if tri_cell is not None:
+        tri_unit = tri_unit + np.asarray(tri_cell, dtype=np.int64)
     return RwgMesh(tri_xyz, tri_unit, rwg[:, 0:2].astype(np.int64), free, elen)
 
 
