@@ -91,8 +91,16 @@ int r3m_ctx_check(r3m_ctx ctx, hipStream_t stream);
  * RWG [state_off[s], state_off[s+1]).  rwg[m] = {T+, T-, edge vertex 0, edge
  * vertex 1} with T+ carrying +(l/2A)(r - free vertex) (RWG basis, Sec. II-A).
  * All vertices lie in the unit's local frame; unit centres are on the lattice.
- * Triangle pairs whose units are within Chebyshev distance extract_radius
- * use closed-form 1/R singularity extraction. */
+ * Triangle pairs whose cells are within Chebyshev distance extract_radius
+ * use closed-form 1/R singularity extraction.
+ * Connected geometries (Sec. III-B, basis extension of periodic boundaries):
+ * the last n_common RWG (after state_off[n_states]) belong to every state,
+ * e.g. a ground plane; a basis bridging two cells is ascribed to one unit and
+ * its triangle in the neighbouring cell carries that cell's lattice offset in
+ * tri_cell ([n_tri][2], NULL: every triangle in the unit's own cell), which
+ * the extraction rule uses.  n_common = 0 and tri_cell = NULL for isolated
+ * units.  The fill takes connected geometries; excitation and RCS do not yet
+ * (R3M_ERR_UNSUPPORTED). */
 typedef struct {
   double freq_hz;
   double period_x, period_y;
@@ -105,6 +113,8 @@ typedef struct {
   int32_t n_rwg;
   const int32_t* rwg; /* [n_rwg][4] */
   int32_t extract_radius;
+  int32_t n_common;        /* RWG shared by every state, after the states' ranges */
+  const int32_t* tri_cell; /* [n_tri][2] or NULL */
 } r3m_unit_geom;
 
 /* ---------------------------------------------------------------- fill -- */
@@ -182,7 +192,7 @@ int r3m_build_spectral(r3m_ctx ctx, const void* dense_dev, int32_t n, int32_t Dx
  *       and max_rank is ignored. */
 typedef struct {
   int32_t n;        /* macro RWG per unit */
-  int32_t n_states; /* coding states; n_a = n / n_states */
+  int32_t n_states; /* coding states; n_a = (n - n_common) / n_states */
   int32_t Dx, Dy;   /* half-extent of the displacement set */
   int32_t near_radius;
   r3m_dtype near_dtype;
@@ -190,6 +200,16 @@ typedef struct {
   r3m_dtype far_dtype;
   const void* far;
   int32_t max_rank;
+  /* Connected geometries (Sec. III-B): the last n_common macro RWG are
+   * shared by every state and common_ext (device, [n_common]) classes them:
+   * 0 active in every unit, 1 extended toward -x (masked by D_k in the units
+   * of the array's first column), 2 toward -y (first row).  A unit's reduced
+   * vector is then its state's n_a entries followed by the n_common shared
+   * ones, masked entries included (products write zero there and ignore
+   * the input there).  Spectral stores only (R3M_ERR_UNSUPPORTED
+   * otherwise); 0 / NULL for isolated units. */
+  int32_t n_common;
+  const int32_t* common_ext;
 } r3m_store;
 
 /* A batch of right-hand sides sharing one store (Sec. III-A: the global

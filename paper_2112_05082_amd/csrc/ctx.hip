@@ -45,8 +45,9 @@ void validate_geom(const r3m_unit_geom* g) {
   R3M_REQUIRE(g->n_states >= 1 && g->n_states <= 256, R3M_ERR_INVALID_ARG, "n_states out of range");
   R3M_REQUIRE(g->state_off && g->vert && g->tri && g->rwg, R3M_ERR_INVALID_ARG, "NULL geometry array");
   R3M_REQUIRE(g->n_vert > 0 && g->n_tri > 0 && g->n_rwg > 0, R3M_ERR_INVALID_ARG, "empty mesh");
-  R3M_REQUIRE(g->state_off[0] == 0 && g->state_off[g->n_states] == g->n_rwg, R3M_ERR_INVALID_ARG,
-              "state_off must run from 0 to n_rwg");
+  R3M_REQUIRE(g->n_common >= 0 && g->n_common < g->n_rwg, R3M_ERR_INVALID_ARG, "n_common out of range");
+  R3M_REQUIRE(g->state_off[0] == 0 && g->state_off[g->n_states] == g->n_rwg - g->n_common, R3M_ERR_INVALID_ARG,
+              "state_off must run from 0 to n_rwg - n_common");
   int na = g->state_off[1] - g->state_off[0];
   for (int s = 0; s < g->n_states; ++s)
     R3M_REQUIRE(g->state_off[s + 1] - g->state_off[s] == na && na > 0, R3M_ERR_UNSUPPORTED,
@@ -63,6 +64,18 @@ void validate_geom(const r3m_unit_geom* g) {
   }
   for (int v = 0; v < 3 * g->n_vert; ++v)
     R3M_REQUIRE(std::isfinite(g->vert[v]), R3M_ERR_INVALID_ARG, "non-finite vertex");
+  if (g->tri_cell)
+    for (int t = 0; t < 2 * g->n_tri; ++t)
+      R3M_REQUIRE(std::abs(g->tri_cell[t]) <= 1, R3M_ERR_INVALID_ARG, "tri_cell offsets must be -1, 0 or 1");
+}
+
+void require_isolated(const r3m_store* Z) {
+  R3M_REQUIRE(Z->n_common == 0, R3M_ERR_UNSUPPORTED,
+              "this call does not take shared (connected-geometry) bases yet");
+}
+void require_isolated(const r3m_unit_geom* g) {
+  R3M_REQUIRE(g->n_common == 0 && !g->tri_cell, R3M_ERR_UNSUPPORTED,
+              "this call does not take connected geometries yet");
 }
 
 GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
@@ -108,13 +121,15 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
   size_t off_len = off_ar + area.size() * 8;
   size_t off_rt = off_len + len.size() * 8;
   size_t off_rf = off_rt + rtri.size() * 4;
-  size_t total = off_rf + rfree.size() * 4;
+  size_t off_tc = off_rf + rfree.size() * 4;
+  size_t total = off_tc + (g->tri_cell ? 8 * (size_t)nt : 0);
   std::vector<char> host(total);
   std::memcpy(host.data() + off_tv, tri_v.data(), tri_v.size() * 8);
   std::memcpy(host.data() + off_ar, area.data(), area.size() * 8);
   std::memcpy(host.data() + off_len, len.data(), len.size() * 8);
   std::memcpy(host.data() + off_rt, rtri.data(), rtri.size() * 4);
   std::memcpy(host.data() + off_rf, rfree.data(), rfree.size() * 4);
+  if (g->tri_cell) std::memcpy(host.data() + off_tc, g->tri_cell, 8 * (size_t)nt);
   // previous users of the table may still be queued on this stream
   R3M_CHECK_HIP(hipStreamSynchronize(stream));
   ctx->geom.ensure(total);
@@ -127,6 +142,7 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
   d.rwg_len = (const double*)(base + off_len);
   d.rwg_tri = (const int32_t*)(base + off_rt);
   d.rwg_free = (const int32_t*)(base + off_rf);
+  d.tri_cell = g->tri_cell ? (const int32_t*)(base + off_tc) : nullptr;
   d.n_tri = nt;
   d.n_rwg = nr;
   return d;

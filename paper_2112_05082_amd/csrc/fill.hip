@@ -4,8 +4,10 @@
 // source macro RWG n of the unit at the origin (eq. (1), Sec. II-A):
 //   Z_mn = j k eta sum_{a,b in +-} s_a s_b l_m l_n / (A_p A_q)
 //          int_p int_q [ (r - v_a).(r' - v_b)/4 - 1/k^2 ] G(|r - r'|) dS' dS
-// with the 7-point degree-5 rule on both triangles.  For blocks with
-// max(|dx|,|dy|) <= extract_radius, G = 1/(4 pi R) + (exp(-jkR) - 1)/(4 pi R):
+// with the 7-point degree-5 rule on both triangles.  For triangle pairs whose
+// cells are within Chebyshev distance extract_radius (the cells of the two
+// units, shifted by the triangles' own cell offsets for bases that bridge two
+// cells, Sec. III-B), G = 1/(4 pi R) + (exp(-jkR) - 1)/(4 pi R):
 // the first term is integrated in closed form over the source triangle
 // (edge-sum formulas of Wilton et al. / Graglia), the second by quadrature.
 // One thread per (block, m, n); everything in FP64.
@@ -108,7 +110,6 @@ __global__ void __launch_bounds__(256) fill_blocks_kernel(GeomDev g, double k, d
   const int dx = slot % (2 * Dx + 1) - Dx;
   const int dy = slot / (2 * Dx + 1) - Dy;
   const V3 off = {dx * px, dy * py, 0.0};
-  const bool extract = (abs(dx) <= extract_radius) && (abs(dy) <= extract_radius);
   const double inv4pi = 1.0 / (4.0 * kPi);
   const double invk2 = 1.0 / (k * k);
 
@@ -133,6 +134,14 @@ __global__ void __launch_bounds__(256) fill_blocks_kernel(GeomDev g, double k, d
       V3 vb = be == 0 ? Q0 : (be == 1 ? Q1 : Q2);
       const double Aq = g.tri_area[q];
       const double cn = (b == 0 ? 1.0 : -1.0) * g.rwg_len[nn] / Aq;
+      // cells of the two triangles (a bridging basis has a triangle in the
+      // neighbouring cell)
+      int cx = dx, cy = dy;
+      if (g.tri_cell) {
+        cx += g.tri_cell[2 * p] - g.tri_cell[2 * q];
+        cy += g.tri_cell[2 * p + 1] - g.tri_cell[2 * q + 1];
+      }
+      const bool extract = abs(cx) <= extract_radius && abs(cy) <= extract_radius;
       double t_re = 0.0, t_im = 0.0;
       for (int i = 0; i < 7; ++i) {
         V3 r = c_quad.b[i][0] * P0 + c_quad.b[i][1] * P1 + c_quad.b[i][2] * P2;

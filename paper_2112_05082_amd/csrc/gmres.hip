@@ -46,6 +46,41 @@ __device__ inline double2 cmulc(double2 a, double2 b) {  // conj(a) * b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
+// Lists of right-hand sides with work in an Arnoldi step: rl[0..n) the
+// indices in increasing order, rl[B] = n; a NULL list stands for all B (the
+// kernels then test idle flags themselves).  The Krylov kernels take a fixed
+// grid that strides over (listed RHS x block) items, so that the right-hand
+// sides that have converged cost nothing, not even a returning workgroup.
+__device__ __forceinline__ int rhs_count(const int* rl, int B) { return rl ? rl[B] : B; }
+__device__ __forceinline__ int rhs_at(const int* rl, int li) { return rl ? rl[li] : li; }
+
+// rl from idle (one workgroup of 1024 threads: each thread takes a
+// contiguous run of right-hand sides, a scan of the counts places them)
+__global__ void __launch_bounds__(1024) live_rhs_kernel(const int* __restrict__ idle, int B, int* __restrict__ rl) {
+  __shared__ int cnt[1024];
+  const int t = threadIdx.x;
+  const int per = (B + 1023) / 1024;
+  const int t0 = min(B, t * per), t1 = min(B, t0 + per);
+  int c = 0;
+  for (int b = t0; b < t1; ++b) c += idle[b] == 0 ? 1 : 0;
+  cnt[t] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = t >= o ? cnt[t - o] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  int at = cnt[t] - c;
+  for (int b = t0; b < t1; ++b)
+    if (idle[b] == 0) rl[at++] = b;
+  if (t == 1023) rl[B] = cnt[1023];
+}
+
+// grid of a strided Krylov kernel: every item when there are few, else enough
+// workgroups to fill the chip several times over
+inline unsigned stride_grid(int64_t items) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, 8192)); }
+
 // partial[b][i][p] = sum over chunk p of conj(A_i) B
 __global__ void __launch_bounds__(kDotThreads)
 dots_kernel(const double2* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
@@ -214,87 +249,100 @@ __device__ double2 block_sum2(double2 v, double2* sh) {
   return t;
 }
 
-// Chunk partials of <A_i, B> for i < nvec: partial[b][i][p].  Block
-// (p, grp, b) takes chunk p of RHS b against the kDotVec vectors of group
+// Chunk partials of <A_i, B> for i < nvec: partial[b][i][p].  Work item
+// (b, grp, p) takes chunk p of RHS b against the kDotVec vectors of group
 // grp; B's chunk is loaded once and all loads are issued before the products.
-// The consumer kernel sums the partials itself (no grid-wide fence here).
+// The blocks stride over the items of the right-hand sides of rl (a live
+// list, see rhs_count), or of all B.  The consumer kernel sums the partials
+// itself (no grid-wide fence here).
 __global__ void __launch_bounds__(kDotThreads)
 dots_partials_kernel(const double2* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
                      const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
-                     int* __restrict__ reset, const int* __restrict__ live, const int* __restrict__ idle) {
+                     int* __restrict__ reset, const int* __restrict__ live, const int* __restrict__ idle,
+                     const int* __restrict__ rl, int B) {
   __shared__ double2 sh[kDotThreads / 64][kDotVec];
-  const int p = blockIdx.x, grp = blockIdx.y, b = blockIdx.z;
   const int tid = threadIdx.x, wave = tid >> 6;
   // this step's running count starts at zero (done before the exit test, so a
   // skipped step still leaves it zero for the next one)
-  if (reset && p == 0 && grp == 0 && b == 0 && tid == 0) *reset = 0;
+  if (reset && blockIdx.x == 0 && tid == 0) *reset = 0;
   if (live && *live == 0) return;
-  if (idle && idle[b]) return;
-  const RhsVec r = rv[b];
-  const int64_t P = (r.N + kDotChunk - 1) / kDotChunk;
-  if (p >= P) return;
-  const int i0 = grp * kDotVec;
-  const int nv = min(kDotVec, nvec - i0);
-  const double2* bb = Bv + r.off;
-  const int64_t lo = (int64_t)p * kDotChunk + tid;
-  double2 wv[kDotPer];
-#pragma unroll
-  for (int e = 0; e < kDotPer; ++e) {
-    const int64_t k = lo + (int64_t)e * kDotThreads;
-    wv[e] = k < r.N ? bb[k] : make_double2(0.0, 0.0);
-  }
-  double2 av[kDotVec][kDotPer];
-#pragma unroll
-  for (int q = 0; q < kDotVec; ++q) {
-    const double2* a = A + (int64_t)(i0 + min(q, nv - 1)) * a_stride + r.off;
+  const int ngrp = (nvec + kDotVec - 1) / kDotVec;
+  const int64_t per = (int64_t)maxP * ngrp, items = per * rhs_count(rl, B);
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {  // uniform over the block
+    const int li = (int)(item / per);
+    const int64_t rem = item - li * per;
+    const int grp = (int)(rem / maxP), p = (int)(rem - (int64_t)grp * maxP);
+    const int b = rhs_at(rl, li);
+    if (!rl && idle && idle[b]) continue;
+    const RhsVec r = rv[b];
+    const int64_t P = (r.N + kDotChunk - 1) / kDotChunk;
+    if (p >= P) continue;
+    const int i0 = grp * kDotVec;
+    const int nv = min(kDotVec, nvec - i0);
+    const double2* bb = Bv + r.off;
+    const int64_t lo = (int64_t)p * kDotChunk + tid;
+    double2 wv[kDotPer];
 #pragma unroll
     for (int e = 0; e < kDotPer; ++e) {
       const int64_t k = lo + (int64_t)e * kDotThreads;
-      av[q][e] = k < r.N ? a[k] : make_double2(0.0, 0.0);
+      wv[e] = k < r.N ? bb[k] : make_double2(0.0, 0.0);
     }
-  }
-  double2 acc[kDotVec];
+    double2 av[kDotVec][kDotPer];
 #pragma unroll
-  for (int q = 0; q < kDotVec; ++q) {
-    acc[q] = make_double2(0.0, 0.0);
+    for (int q = 0; q < kDotVec; ++q) {
+      const double2* a = A + (int64_t)(i0 + min(q, nv - 1)) * a_stride + r.off;
 #pragma unroll
-    for (int e = 0; e < kDotPer; ++e) {
-      const double2 t = cmulc(av[q][e], wv[e]);
-      acc[q].x += t.x;
-      acc[q].y += t.y;
+      for (int e = 0; e < kDotPer; ++e) {
+        const int64_t k = lo + (int64_t)e * kDotThreads;
+        av[q][e] = k < r.N ? a[k] : make_double2(0.0, 0.0);
+      }
     }
+    double2 acc[kDotVec];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      acc[q].x += __shfl_xor(acc[q].x, o);
-      acc[q].y += __shfl_xor(acc[q].y, o);
-    }
-  }
-  if ((tid & 63) == 0) {
+    for (int q = 0; q < kDotVec; ++q) {
+      acc[q] = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int q = 0; q < kDotVec; ++q) sh[wave][q] = acc[q];
-  }
-  __syncthreads();
-  if (tid < nv) {
-    double2 t = sh[0][tid];
-    for (int w = 1; w < kDotThreads / 64; ++w) {
-      t.x += sh[w][tid].x;
-      t.y += sh[w][tid].y;
+      for (int e = 0; e < kDotPer; ++e) {
+        const double2 t = cmulc(av[q][e], wv[e]);
+        acc[q].x += t.x;
+        acc[q].y += t.y;
+      }
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        acc[q].x += __shfl_xor(acc[q].x, o);
+        acc[q].y += __shfl_xor(acc[q].y, o);
+      }
     }
-    partial[((size_t)b * nvec + i0 + tid) * maxP + p] = t;
+    if ((tid & 63) == 0) {
+#pragma unroll
+      for (int q = 0; q < kDotVec; ++q) sh[wave][q] = acc[q];
+    }
+    __syncthreads();
+    if (tid < nv) {
+      double2 t = sh[0][tid];
+      for (int w = 1; w < kDotThreads / 64; ++w) {
+        t.x += sh[w][tid].x;
+        t.y += sh[w][tid].y;
+      }
+      partial[((size_t)b * nvec + i0 + tid) * maxP + p] = t;
+    }
+    __syncthreads();  // sh is reused by the next item
   }
 }
 
-// Long vectors: the chunk partials of dots_partials_kernel summed once, in a
+// Long vectors: the partials of dots_partials_kernel (one per part_chunk
+// elements) or of the folded update (one per update block) summed once, in a
 // fixed order, into out[b][i] (grid (nvec, B)), so that the update kernel's
 // blocks read one value per vector instead of every partial.
 __global__ void __launch_bounds__(256)
 finish_partials_kernel(const double2* __restrict__ partial, int maxP, int nvec, const RhsVec* __restrict__ rv,
-                       double2* __restrict__ out, const int* __restrict__ run_prev, const int* __restrict__ idle) {
+                       double2* __restrict__ out, const int* __restrict__ run_prev, const int* __restrict__ idle,
+                       int part_chunk) {
   if (run_prev && *run_prev == 0) return;
   if (idle && idle[blockIdx.y]) return;
   __shared__ double2 sh[4];
   const int i = blockIdx.x, b = blockIdx.y;
-  const int64_t P = (rv[b].N + kDotChunk - 1) / kDotChunk;
+  const int64_t P = (rv[b].N + part_chunk - 1) / part_chunk;
   const double2* pp = partial + ((size_t)b * nvec + i) * maxP;
   double2 t = make_double2(0.0, 0.0);
   for (int64_t p = threadIdx.x; p < P; p += blockDim.x) {
@@ -321,99 +369,162 @@ finish_norm_kernel(const double* __restrict__ npart, int maxB, const RhsVec* __r
   if (threadIdx.x == 0) out[b] = s2.x;
 }
 
-// w -= sum_{i<nvec} h_i V_i with h_i the sum of the chunk partials of the
-// preceding dots_partials_kernel launch (n_part of them per vector; 0: one
-// per 1024 elements), taken by every block in the same fixed order (block 0 also records them in H: mode 0 H[i][j] = h_i, mode 1
-// H[i][j] += h_i).  A block takes nsub runs of 64 elements in turn; its four
-// waves take the vectors i = q mod 4 (q = wave) and their sums are added in
-// wave order.  With do_norm, each block also writes its part of ||w||^2 to
-// npart[b][block].
+// w -= sum_{i<nvec} h_i V_i with h_i the sum of the partials of the preceding
+// dots launch (n_part of them per vector; 0: one per part_chunk elements),
+// taken by every block in the same fixed order (block 0 also records them in
+// H: mode 0 H[i][j] = h_i, mode 1 H[i][j] += h_i).  A block takes nsub runs of
+// 64 elements in turn; its four waves take the vectors i = q mod 4 (q = wave)
+// and their sums are added in wave order.  With do_norm, each block also
+// writes its part of ||w||^2 to npart[b][block].
+// KV > 0 folds the second Gram-Schmidt pass's inner products into the first
+// pass's update (nvec <= 4 KV): each wave keeps its KV basis entries of the
+// element in registers, and once the updated w is known forms conj(V_i) w for
+// them, so that the basis is streamed once for both; partial2[b][i][block]
+// receives the block's sums (fixed lane and run order).
+// Blocks (of nsub runs, nb_max per RHS) are work items strided over by the
+// grid, for the right-hand sides of rl (see rhs_count).
 // Dynamic LDS: nvec double2.
+template <int KV>
 __global__ void __launch_bounds__(256)
 gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
                  const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int n_part,
                  int nvec, int64_t ut, int do_norm, double* __restrict__ npart, int maxB, double2* __restrict__ H,
                  int m, int j, int mode, const int* __restrict__ run_prev, const int* __restrict__ idle,
-                 int nsub) {
+                 int nsub, int part_chunk, double2* __restrict__ partial2, int maxP2, const int* __restrict__ rl,
+                 int B, int64_t nb_max) {
   if (run_prev && *run_prev == 0) return;
-  if (idle && idle[blockIdx.y]) return;
   extern __shared__ double2 hb[];
   __shared__ double2 sh[4];
   __shared__ double2 part[3][64];
-  const int b = blockIdx.y;
-  const RhsVec r = rv[b];
-  const int64_t nb = (r.N + 64 * nsub - 1) / (64 * nsub);
-  if ((int64_t)blockIdx.x >= nb) return;
-  const int P = n_part > 0 ? n_part : (int)((r.N + kDotChunk - 1) / kDotChunk);
-  for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
-    const double2* pp = partial + ((size_t)b * nvec + i) * maxP;
-    double2 t = make_double2(0.0, 0.0);
-    for (int p = 0; p < P; ++p) {
-      const double2 v = pp[p];
-      t.x += v.x;
-      t.y += v.y;
-    }
-    hb[i] = t;
-    if (blockIdx.x == 0) {
-      double2* h = H + (size_t)b * (m + 1) * m + (size_t)i * m + j;
-      if (mode == 0) {
-        *h = t;
-      } else {
-        h->x += t.x;
-        h->y += t.y;
-      }
-    }
-  }
-  __syncthreads();
+  __shared__ double2 wnew[64];
   const int e = threadIdx.x & 63, q = threadIdx.x >> 6;
-  const bool act = st[b].active;
-  double nrm2 = 0.0;
-  for (int sb = 0; sb < nsub; ++sb) {  // uniform trip count: the barriers below are reached by all
-    const int64_t k = ((int64_t)blockIdx.x * nsub + sb) * 64 + e;
-    const bool live = k < r.N && act;
-    double2 acc = make_double2(0.0, 0.0);
-    if (live) {
-      const double2* vk = V + r.off + k;
-      int i = q;
-      for (; i + 12 < nvec; i += 16) {
-        const double2 v0 = vk[(int64_t)i * ut], v1 = vk[(int64_t)(i + 4) * ut];
-        const double2 v2 = vk[(int64_t)(i + 8) * ut], v3 = vk[(int64_t)(i + 12) * ut];
-        const double2 t0 = cmul(hb[i], v0), t1 = cmul(hb[i + 4], v1);
-        const double2 t2 = cmul(hb[i + 8], v2), t3 = cmul(hb[i + 12], v3);
-        acc.x += t0.x;
-        acc.y += t0.y;
-        acc.x += t1.x;
-        acc.y += t1.y;
-        acc.x += t2.x;
-        acc.y += t2.y;
-        acc.x += t3.x;
-        acc.y += t3.y;
+  const int64_t items = nb_max * rhs_count(rl, B);
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {  // uniform over the block
+    const int li = (int)(item / nb_max);
+    const int64_t blk = item - li * nb_max;
+    const int b = rhs_at(rl, li);
+    if (!rl && idle && idle[b]) continue;
+    const RhsVec r = rv[b];
+    const int64_t nb = (r.N + 64 * nsub - 1) / (64 * nsub);
+    if (blk >= nb) continue;
+    const int P = n_part > 0 ? n_part : (int)((r.N + part_chunk - 1) / part_chunk);
+    __syncthreads();  // the previous item's reads of hb are done
+    for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
+      const double2* pp = partial + ((size_t)b * nvec + i) * maxP;
+      double2 t = make_double2(0.0, 0.0);
+      for (int p = 0; p < P; ++p) {
+        const double2 v = pp[p];
+        t.x += v.x;
+        t.y += v.y;
       }
-      for (; i < nvec; i += 4) {
-        const double2 t = cmul(hb[i], vk[(int64_t)i * ut]);
-        acc.x += t.x;
-        acc.y += t.y;
+      hb[i] = t;
+      if (blk == 0) {
+        double2* h = H + (size_t)b * (m + 1) * m + (size_t)i * m + j;
+        if (mode == 0) {
+          *h = t;
+        } else {
+          h->x += t.x;
+          h->y += t.y;
+        }
       }
     }
-    if (q > 0) part[q - 1][e] = acc;
     __syncthreads();
-    if (q == 0 && live) {
+    const bool act = st[b].active;
+    double nrm2 = 0.0;
+    double2 d2[KV > 0 ? KV : 1];
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        acc.x += part[t][e].x;
-        acc.y += part[t][e].y;
+    for (int t = 0; t < (KV > 0 ? KV : 1); ++t) d2[t] = make_double2(0.0, 0.0);
+    for (int sb = 0; sb < nsub; ++sb) {  // uniform trip count: the barriers below are reached by all
+      const int64_t k = (blk * nsub + sb) * 64 + e;
+      const bool live = k < r.N && act;
+      double2 acc = make_double2(0.0, 0.0);
+      double2 vv[KV > 0 ? KV : 1];
+      if (KV > 0) {
+        if (live) {
+          const double2* vk = V + r.off + k;
+#pragma unroll
+          for (int t = 0; t < KV; ++t) {
+            const int i = q + 4 * t;
+            vv[t] = i < nvec ? vk[(int64_t)i * ut] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int t = 0; t < KV; ++t) {
+            const int i = q + 4 * t;
+            if (i < nvec) {
+              const double2 c = cmul(hb[i], vv[t]);
+              acc.x += c.x;
+              acc.y += c.y;
+            }
+          }
+        }
+      } else if (live) {
+        const double2* vk = V + r.off + k;
+        int i = q;
+        for (; i + 12 < nvec; i += 16) {
+          const double2 v0 = vk[(int64_t)i * ut], v1 = vk[(int64_t)(i + 4) * ut];
+          const double2 v2 = vk[(int64_t)(i + 8) * ut], v3 = vk[(int64_t)(i + 12) * ut];
+          const double2 t0 = cmul(hb[i], v0), t1 = cmul(hb[i + 4], v1);
+          const double2 t2 = cmul(hb[i + 8], v2), t3 = cmul(hb[i + 12], v3);
+          acc.x += t0.x;
+          acc.y += t0.y;
+          acc.x += t1.x;
+          acc.y += t1.y;
+          acc.x += t2.x;
+          acc.y += t2.y;
+          acc.x += t3.x;
+          acc.y += t3.y;
+        }
+        for (; i < nvec; i += 4) {
+          const double2 t = cmul(hb[i], vk[(int64_t)i * ut]);
+          acc.x += t.x;
+          acc.y += t.y;
+        }
       }
-      double2 wk = w[r.off + k];
-      wk.x -= acc.x;
-      wk.y -= acc.y;
-      w[r.off + k] = wk;
-      nrm2 += wk.x * wk.x + wk.y * wk.y;
+      if (q > 0) part[q - 1][e] = acc;
+      __syncthreads();
+      if (q == 0 && live) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          acc.x += part[t][e].x;
+          acc.y += part[t][e].y;
+        }
+        double2 wk = w[r.off + k];
+        wk.x -= acc.x;
+        wk.y -= acc.y;
+        w[r.off + k] = wk;
+        nrm2 += wk.x * wk.x + wk.y * wk.y;
+        if (KV > 0) wnew[e] = wk;
+      }
+      __syncthreads();  // part (and wnew) are reused by the next run
+      if (KV > 0 && live) {
+        // (the next run writes wnew only after its first barrier, which every
+        // wave reaches after these reads)
+        const double2 wk = wnew[e];
+#pragma unroll
+        for (int t = 0; t < KV; ++t) {
+          const double2 c = cmulc(vv[t], wk);
+          d2[t].x += c.x;
+          d2[t].y += c.y;
+        }
+      }
     }
-    __syncthreads();  // part is reused by the next run
+    if (KV > 0) {
+#pragma unroll
+      for (int t = 0; t < KV; ++t) {
+        double2 v = d2[t];
+        for (int o = 32; o >= 1; o >>= 1) {
+          v.x += __shfl_xor(v.x, o);
+          v.y += __shfl_xor(v.y, o);
+        }
+        const int i = q + 4 * t;
+        if (e == 0 && i < nvec) partial2[((size_t)b * nvec + i) * maxP2 + blk] = v;
+      }
+    }
+    if (do_norm) {
+      const double2 t = block_sum2(make_double2(nrm2, 0.0), sh);
+      if (threadIdx.x == 0) npart[(size_t)b * maxB + blk] = t.x;
+    }
   }
-  if (!do_norm) return;
-  const double2 t = block_sum2(make_double2(nrm2, 0.0), sh);
-  if (threadIdx.x == 0) npart[(size_t)b * maxB + blockIdx.x] = t.x;
 }
 
 // ||w|| from the per-block parts of the preceding gs_update_kernel (n_npart
@@ -423,6 +534,8 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
 // a finished RHS or a breakdown) and, for the next step's matvec, its input
 // in the store precision OT: V_{j+1} itself (MODE 1) or M^{-1} V_{j+1}
 // (MODE 2, block-Jacobi; a block holds whole units).  MODE 0 writes V only.
+// Blocks (nb_max per RHS) are work items strided over by the grid, for the
+// right-hand sides of rl (see rhs_count).
 template <typename OT, int MODE>
 __global__ void __launch_bounds__(256)
 normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, const RhsVec* __restrict__ rv,
@@ -432,67 +545,73 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
                       double* __restrict__ wn, int64_t ut, const int* __restrict__ live,
                       const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
                       const int64_t* __restrict__ soff, int n_a, int n_states, OT* __restrict__ xs, int per_unit,
-                      int* __restrict__ idle) {
+                      int* __restrict__ idle, const int* __restrict__ rl, int B, int64_t nb_max) {
   if (live && *live == 0) return;
   __shared__ double nv_s;
   __shared__ double2 v_s[256];
-  const int b = blockIdx.y;
-  if (idle) {
-    // a right-hand side not being solved, or converged at an earlier step of
-    // this cycle, has no step left to finish (its V_{j+1} is never read).
-    // Tested on the state, not on idle[b], which block 0 of this launch may
-    // set (the state's jdone changes here only from -1 to j + 1)
-    const RhsState si = st[b];
-    if (!si.active || (si.jdone >= 0 && si.jdone <= j)) return;
-  }
-  const RhsVec r = rv[b];
-  const int64_t nb = (r.N + 63) / 64;
-  if ((int64_t)blockIdx.x * blockDim.x >= r.N) return;  // uniform over the block
-  if (threadIdx.x < 64) {
-    const double sum = wave_sum_partials(npart + (size_t)b * maxB, n_npart > 0 ? n_npart : (int)nb);
-    if (threadIdx.x == 0) nv_s = sqrt(fmax(sum, 0.0));
-  }
-  __syncthreads();
-  const double nv = nv_s;
-  // the running test reads only fields the Givens step below leaves alone or
-  // changes to a value with the same outcome (jdone: -1 -> j + 1)
-  const RhsState s0 = st[b];
-  const bool ok = s0.active && (s0.jdone < 0 || s0.jdone == j + 1) && nv > 0.0;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = k < r.N;
-  double2 v = make_double2(0.0, 0.0);
-  if (in) {
-    const double2 wk = w[r.off + k];
-    if (ok) v = make_double2(wk.x / nv, wk.y / nv);
-    V[(int64_t)(j + 1) * ut + r.off + k] = v;
-  }
-  if (MODE == 1 && in) {
-    xs[2 * (r.off + k)] = (OT)v.x;
-    xs[2 * (r.off + k) + 1] = (OT)v.y;
-  }
-  if (MODE == 2) {
-    v_s[threadIdx.x] = v;
-    __syncthreads();
-    if (in) {
-      const int64_t u = k / n_a;
-      const int mr = (int)(k % n_a);
-      const int64_t sidx = per_unit ? r.off / n_a + u : min((int)states[soff[b] + u], n_states - 1);
-      const double2* M = Minv + (size_t)sidx * n_a * n_a + mr;  // column-major
-      const double2* vu = v_s + (threadIdx.x / n_a) * n_a;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int c = 0; c < n_a; ++c) {
-        const double2 t = cmul(M[(size_t)c * n_a], vu[c]);
-        acc.x += t.x;
-        acc.y += t.y;
-      }
-      xs[2 * (r.off + k)] = (OT)acc.x;
-      xs[2 * (r.off + k) + 1] = (OT)acc.y;
+  extern __shared__ double2 glds[];
+  const int64_t items = nb_max * rhs_count(rl, B);
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {  // uniform over the block
+    const int li = (int)(item / nb_max);
+    const int64_t blk = item - li * nb_max;
+    const int b = rhs_at(rl, li);
+    if (idle) {
+      // a right-hand side not being solved, or converged at an earlier step of
+      // this cycle, has no step left to finish (its V_{j+1} is never read).
+      // Tested on the state, not on idle[b], which the Givens step of this
+      // launch may set (the state's jdone changes here only from -1 to j + 1)
+      const RhsState si = st[b];
+      if (!si.active || (si.jdone >= 0 && si.jdone <= j)) continue;
     }
-  }
-  if (blockIdx.x == 0) {  // uniform over the block
-    if (threadIdx.x == 0) wn[b] = nv;
-    extern __shared__ double2 glds[];
-    givens_step_block(b, H, g, cs, sn, st, m, j, tol, n_running, nv, glds, idle);
+    const RhsVec r = rv[b];
+    const int64_t nb = (r.N + 63) / 64;
+    if (blk * blockDim.x >= r.N) continue;  // uniform over the block
+    __syncthreads();  // the previous item's reads of nv_s and v_s are done
+    if (threadIdx.x < 64) {
+      const double sum = wave_sum_partials(npart + (size_t)b * maxB, n_npart > 0 ? n_npart : (int)nb);
+      if (threadIdx.x == 0) nv_s = sqrt(fmax(sum, 0.0));
+    }
+    __syncthreads();
+    const double nv = nv_s;
+    // the running test reads only fields the Givens step below leaves alone or
+    // changes to a value with the same outcome (jdone: -1 -> j + 1)
+    const RhsState s0 = st[b];
+    const bool ok = s0.active && (s0.jdone < 0 || s0.jdone == j + 1) && nv > 0.0;
+    const int64_t k = blk * blockDim.x + threadIdx.x;
+    const bool in = k < r.N;
+    double2 v = make_double2(0.0, 0.0);
+    if (in) {
+      const double2 wk = w[r.off + k];
+      if (ok) v = make_double2(wk.x / nv, wk.y / nv);
+      V[(int64_t)(j + 1) * ut + r.off + k] = v;
+    }
+    if (MODE == 1 && in) {
+      xs[2 * (r.off + k)] = (OT)v.x;
+      xs[2 * (r.off + k) + 1] = (OT)v.y;
+    }
+    if (MODE == 2) {
+      v_s[threadIdx.x] = v;
+      __syncthreads();
+      if (in) {
+        const int64_t u = k / n_a;
+        const int mr = (int)(k % n_a);
+        const int64_t sidx = per_unit ? r.off / n_a + u : min((int)states[soff[b] + u], n_states - 1);
+        const double2* M = Minv + (size_t)sidx * n_a * n_a + mr;  // column-major
+        const double2* vu = v_s + (threadIdx.x / n_a) * n_a;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int c = 0; c < n_a; ++c) {
+          const double2 t = cmul(M[(size_t)c * n_a], vu[c]);
+          acc.x += t.x;
+          acc.y += t.y;
+        }
+        xs[2 * (r.off + k)] = (OT)acc.x;
+        xs[2 * (r.off + k) + 1] = (OT)acc.y;
+      }
+    }
+    if (blk == 0) {  // uniform over the block
+      if (threadIdx.x == 0) wn[b] = nv;
+      givens_step_block(b, H, g, cs, sn, st, m, j, tol, n_running, nv, glds, idle);
+    }
   }
 }
 
@@ -788,12 +907,14 @@ struct Work {
   double* cs;
   double2* sn;
   double2* dpart;
+  double2* dpart2;  // second-pass inner products of the folded update, per update block
   double2* hbuf;
   double2* hsum;  // Gram-Schmidt coefficients summed from dpart (long vectors)
   double* nsum;   // ||w||^2 summed from npart (long vectors)
   double2* nrm;
   RhsState* st;
   int* idle;  // per RHS: 1 while it has no work in the current cycle (the matvec and Krylov kernels skip it)
+  int* rl;    // the RHS with work in the current Arnoldi step (list, then count; see rhs_count)
   RhsVec* rv;
   int64_t* soff;
   int* counters;
@@ -801,6 +922,20 @@ struct Work {
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// The folded Gram-Schmidt update keeps up to 8 basis entries per wave in
+// registers, so it takes steps with at most 32 basis vectors.
+constexpr int kFoldMaxVec = 32;
+// 64-element runs per update block: four for long vectors (more than 64
+// chunks of kDotChunk: a quarter of the workgroups, which matters once most
+// right-hand sides of a wide batch are idle and their workgroups only
+// return), else one (the single-RHS solve keeps enough workgroups, and
+// normalize_step_kernel sums their per-64 parts itself)
+int update_runs(int64_t maxN) { return (maxN + kDotChunk - 1) / kDotChunk > 64 ? 4 : 1; }
+int64_t fold_blocks(int64_t maxN) {
+  const int nsub = update_runs(maxN);
+  return std::max<int64_t>(1, (maxN + 64 * nsub - 1) / (64 * nsub));
+}
 
 // n_blocks: block-Jacobi inverses held (one per state, or one per unit for
 // relaxed codebooks)
@@ -838,12 +973,14 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_blocks, int m, 
   w.cs = (double*)take((size_t)B * m * 8);
   w.sn = (double2*)take((size_t)B * m * 16);
   w.dpart = (double2*)take((size_t)B * (m + 1) * std::max(maxP, 1) * 16);
+  if (m + 1 <= kFoldMaxVec) w.dpart2 = (double2*)take((size_t)B * (m + 1) * fold_blocks(maxN) * 16);
   w.hbuf = (double2*)take((size_t)B * (m + 1) * 16);
   w.hsum = (double2*)take((size_t)B * (m + 1) * 16);
   w.nsum = (double*)take((size_t)B * 8);
   w.nrm = (double2*)take((size_t)B * 16);
   w.st = (RhsState*)take((size_t)B * sizeof(RhsState));
   w.idle = (int*)take((size_t)B * sizeof(int));
+  w.rl = (int*)take((size_t)(B + 1) * sizeof(int));
   w.rv = (RhsVec*)take((size_t)B * sizeof(RhsVec));
   w.soff = (int64_t*)take((size_t)B * 8);
   w.counters = (int*)take(256);
@@ -960,34 +1097,67 @@ struct GmresRun {
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
     const int* live = run_slot(j - 1);  // j = 0: set by the cycle start
     const double2* vj = W.V + (int64_t)j * ut;
+    // the right-hand sides with work in this step (not idle at its start)
+    hipLaunchKernelGGL(live_rhs_kernel, dim3(1), dim3(1024), 0, s, (const int*)W.idle, B, W.rl);
+    const int* rl = W.rl;
     if (wts)
       launch_spectral_ex(Z, *bd, batch->states, input_in_xs(Z) ? Z->near_dtype : R3M_C128,
                          input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, R3M_C128, W.w, W.mv_partial, s, live,
                          wts, tr, W.idle);
     else
       launch_matvec_pre(Z, *bd, batch->states, input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, W.w,
-                        W.mv_partial, lists_for(Z), G, s, live, W.idle);
-    const dim3 dgrid(maxP, (j + 1 + kDotVec - 1) / kDotVec, B);
+                        W.mv_partial, lists_for(Z), G, s, live, W.idle, rl);
     const int maxB = (int)((maxN + 63) / 64 + 1);
     // long vectors (more than 64 chunk partials per coefficient): sum the
     // partials once in their own launch rather than in every update block
     const bool long_vec = maxP > 64;
-    // long vectors: each update block takes four runs of 64 elements (a
-    // quarter of the workgroups, which matters once most right-hand sides of
-    // a wide batch are idle and their workgroups only return); short ones
-    // keep one run so that the single-RHS solve has enough workgroups, and
-    // normalize_step_kernel sums their per-64 parts itself
-    const int nsub = long_vec ? 4 : 1;
-    for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(dots_partials_kernel, dgrid, dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, j + 1, maxP,
-                         W.dpart, pass == 0 ? run_slot(j) : (int*)nullptr, live, W.idle);
+    const int nsub = update_runs(maxN);
+    const int nvec = j + 1;
+    const int ngrp = (nvec + kDotVec - 1) / kDotVec;
+    const int64_t nb_u = (maxN + 64 * nsub - 1) / (64 * nsub);
+    const unsigned dgrid = stride_grid((int64_t)maxP * ngrp * B), ugrid = stride_grid(nb_u * B);
+    const size_t ulds = (size_t)nvec * sizeof(double2);
+    // CGS2, first pass: inner products with the basis, then the update
+    hipLaunchKernelGGL(dots_partials_kernel, dim3(dgrid), dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, nvec, maxP,
+                       W.dpart, run_slot(j), live, W.idle, rl, B);
+    if (long_vec)
+      hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP, nvec,
+                         W.rv, W.hsum, live, W.idle, kDotChunk);
+    const double2* h0 = long_vec ? (const double2*)W.hsum : (const double2*)W.dpart;
+    const int h0P = long_vec ? 1 : maxP, h0n = long_vec ? 1 : 0;
+    if (nvec <= kFoldMaxVec && W.dpart2) {
+      // the first update also forms the second pass's inner products
+      const int maxP2 = (int)fold_blocks(maxN);
+#define R3M_FOLDED(KV)                                                                                             \
+  hipLaunchKernelGGL(gs_update_kernel<KV>, dim3(ugrid), dim3(256), ulds, s, W.V, W.w, W.rv, W.st, h0, h0P, h0n, nvec, \
+                     ut, 0, W.npart, maxB, W.H, m, j, 0, live, W.idle, nsub, kDotChunk, W.dpart2, maxP2, rl, B, nb_u)
+      if (nvec <= 8)
+        R3M_FOLDED(2);
+      else if (nvec <= 16)
+        R3M_FOLDED(4);
+      else
+        R3M_FOLDED(8);
+#undef R3M_FOLDED
       if (long_vec)
-        hipLaunchKernelGGL(finish_partials_kernel, dim3(j + 1, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
-                           j + 1, W.rv, W.hsum, live, W.idle);
-      hipLaunchKernelGGL(gs_update_kernel, dim3(ceil_div((size_t)maxN, 64 * nsub), B), dim3(256),
-                         (size_t)(j + 1) * sizeof(double2), s, W.V, W.w, W.rv, W.st,
-                         long_vec ? (const double2*)W.hsum : (const double2*)W.dpart, long_vec ? 1 : maxP,
-                         long_vec ? 1 : 0, j + 1, ut, pass, W.npart, maxB, W.H, m, j, pass, live, W.idle, nsub);
+        hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart2, maxP2,
+                           nvec, W.rv, W.hsum, live, W.idle, 64 * nsub);
+      hipLaunchKernelGGL(gs_update_kernel<0>, dim3(ugrid), dim3(256), ulds, s, W.V, W.w, W.rv, W.st,
+                         long_vec ? (const double2*)W.hsum : (const double2*)W.dpart2, long_vec ? 1 : maxP2,
+                         long_vec ? 1 : 0, nvec, ut, 1, W.npart, maxB, W.H, m, j, 1, live, W.idle, nsub, 64 * nsub,
+                         (double2*)nullptr, 0, rl, B, nb_u);
+    } else {
+      hipLaunchKernelGGL(gs_update_kernel<0>, dim3(ugrid), dim3(256), ulds, s, W.V, W.w, W.rv, W.st, h0, h0P, h0n,
+                         nvec, ut, 0, W.npart, maxB, W.H, m, j, 0, live, W.idle, nsub, kDotChunk, (double2*)nullptr, 0,
+                         rl, B, nb_u);
+      // CGS2, second pass
+      hipLaunchKernelGGL(dots_partials_kernel, dim3(dgrid), dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, nvec, maxP,
+                         W.dpart, (int*)nullptr, live, W.idle, rl, B);
+      if (long_vec)
+        hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
+                           nvec, W.rv, W.hsum, live, W.idle, kDotChunk);
+      hipLaunchKernelGGL(gs_update_kernel<0>, dim3(ugrid), dim3(256), ulds, s, W.V, W.w, W.rv, W.st, h0, h0P, h0n,
+                         nvec, ut, 1, W.npart, maxB, W.H, m, j, 1, live, W.idle, nsub, kDotChunk, (double2*)nullptr, 0,
+                         rl, B, nb_u);
     }
     if (long_vec)
       hipLaunchKernelGGL(finish_norm_kernel, dim3(B), dim3(256), 0, s, (const double*)W.npart, maxB, W.rv, W.nsum,
@@ -996,33 +1166,30 @@ struct GmresRun {
     const int npB = long_vec ? 1 : maxB, npN = long_vec ? 1 : 0;
     // blocks of whole units (the preconditioner multiplies per unit)
     const int nthr = (256 / n_a) * n_a;
-    const dim3 ngrid(ceil_div((size_t)maxN, nthr), B);
+    const int64_t nb_n = ceil_div((size_t)maxN, nthr);
+    const dim3 ngrid(stride_grid(nb_n * B));
     const size_t glds = (size_t)(2 * m + 2) * 16 + (size_t)m * 8;
     const bool c64 = Z->near_dtype == R3M_C64;
+#define R3M_NORMALIZE(OT, MODE, XS)                                                                                  \
+  hipLaunchKernelGGL((normalize_step_kernel<OT, MODE>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np, npB,  \
+                     npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states, W.soff, \
+                     n_a, n_states, XS, pu, W.idle, rl, B, nb_n)
     if (ilu_r) {
       // V_{j+1}, then the next step's input M^-1 V_{j+1} by the colour solves
       // (W.w, the matvec output, is free once normalised)
-      hipLaunchKernelGGL((normalize_step_kernel<double, 0>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
-                         np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
-                         batch->states, W.soff, n_a, n_states, (double*)nullptr, pu, W.idle);
+      R3M_NORMALIZE(double, 0, (double*)nullptr);
       launch_ilu_apply(Z, *bd, ilu_r, W.ilu, W.V + (int64_t)(j + 1) * ut, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s,
                        run_slot(j), wts == nullptr);
-    } else if (pre && c64)
-      hipLaunchKernelGGL((normalize_step_kernel<float, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
-                         npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
-                         W.soff, n_a, n_states, (float*)W.xs, pu, W.idle);
-    else if (pre)
-      hipLaunchKernelGGL((normalize_step_kernel<double, 2>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
-                         np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
-                         batch->states, W.soff, n_a, n_states, (double*)W.xs, pu, W.idle);
-    else if (c64)
-      hipLaunchKernelGGL((normalize_step_kernel<float, 1>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np,
-                         npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
-                         W.soff, n_a, n_states, (float*)W.xs, pu, W.idle);
-    else
-      hipLaunchKernelGGL((normalize_step_kernel<double, 0>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st,
-                         np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv,
-                         batch->states, W.soff, n_a, n_states, (double*)nullptr, pu, W.idle);
+    } else if (pre && c64) {
+      R3M_NORMALIZE(float, 2, (float*)W.xs);
+    } else if (pre) {
+      R3M_NORMALIZE(double, 2, (double*)W.xs);
+    } else if (c64) {
+      R3M_NORMALIZE(float, 1, (float*)W.xs);
+    } else {
+      R3M_NORMALIZE(double, 0, (double*)nullptr);
+    }
+#undef R3M_NORMALIZE
     R3M_CHECK_HIP(hipGetLastError());
   }
 
@@ -1192,7 +1359,11 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z6
   int rc = guarded(ctx, [&] {
     R3M_REQUIRE(ctx && opts, R3M_ERR_INVALID_ARG, "NULL argument");
     validate_store(Z);
-    if (Z64) validate_store(Z64);
+    require_isolated(Z);
+    if (Z64) {
+      validate_store(Z64);
+      require_isolated(Z64);
+    }
     validate_batch(batch, Z->Dx, Z->Dy);
     R3M_REQUIRE(opts->restart >= 1 && opts->restart <= 1024, R3M_ERR_INVALID_ARG, "restart out of range");
     if (batch->B == 0) return;
@@ -1211,10 +1382,12 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx && opts, R3M_ERR_INVALID_ARG, "NULL argument");
     validate_store(Z);
+    require_isolated(Z);
     validate_batch(batch, Z->Dx, Z->Dy);
     const bool refine = Z64 != nullptr && opts->refine_tol > 0.0;
     if (refine) {
       validate_store(Z64);
+      require_isolated(Z64);
       R3M_REQUIRE(Z64->near_dtype == R3M_C128, R3M_ERR_INVALID_ARG, "refinement store must be C128");
       R3M_REQUIRE(Z64->n == Z->n && Z64->n_states == Z->n_states && Z64->Dx >= Z->Dx && Z64->Dy >= Z->Dy,
                   R3M_ERR_INVALID_ARG, "refinement store does not match");

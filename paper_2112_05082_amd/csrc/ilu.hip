@@ -553,6 +553,7 @@ size_t r3m_ilu_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, in
   int rc = guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_store(Z);
+    require_isolated(Z);
     validate_ilu(Z, radius);
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;
@@ -566,6 +567,7 @@ int r3m_ilu_factor(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int3
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_store(Z);
+    require_isolated(Z);
     validate_ilu(Z, radius);
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;
@@ -590,6 +592,7 @@ int r3m_ilu_apply(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_store(Z);
+    require_isolated(Z);
     validate_ilu(Z, radius);
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;

@@ -1566,9 +1566,15 @@ void* workspace_lists(void* work, const BatchDesc& bd, const r3m_store* Z) {
 
 void validate_store(const r3m_store* Z) {
   R3M_REQUIRE(Z, R3M_ERR_INVALID_ARG, "store is NULL");
-  R3M_REQUIRE(Z->n > 0 && Z->n_states >= 1 && Z->n % Z->n_states == 0, R3M_ERR_INVALID_ARG,
-              "store n must be a multiple of n_states");
-  const int n_a = Z->n / Z->n_states;
+  R3M_REQUIRE(Z->n_common >= 0 && Z->n_common < Z->n, R3M_ERR_INVALID_ARG, "n_common out of range");
+  R3M_REQUIRE(Z->n > 0 && Z->n_states >= 1 && (Z->n - Z->n_common) % Z->n_states == 0, R3M_ERR_INVALID_ARG,
+              "store n minus n_common must be a multiple of n_states");
+  if (Z->n_common > 0) {
+    R3M_REQUIRE(store_is_spectral(Z), R3M_ERR_UNSUPPORTED,
+                "shared (connected-geometry) bases need a spectral store");
+    R3M_REQUIRE(Z->common_ext, R3M_ERR_INVALID_ARG, "common_ext is NULL");
+  }
+  const int n_a = (Z->n - Z->n_common) / Z->n_states;
   R3M_REQUIRE(n_a == 40 || n_a == 64, R3M_ERR_UNSUPPORTED,
               "the matvec kernels are instantiated for 40 or 64 active RWG per unit");
   R3M_REQUIRE(Z->n <= 256, R3M_ERR_UNSUPPORTED, "at most 256 macro RWG per unit");
@@ -1759,9 +1765,9 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
 // the near retrieval lists (build_near_lists) must be current at lists
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
                        void* partial, const void* lists, int chunks, hipStream_t stream, const int* live,
-                       const int* idle) {
+                       const int* idle, const int* rl) {
   if (store_is_spectral(Z)) {
-    launch_spectral(Z, bd, states, Z->near_dtype, xs, R3M_C128, y, partial, stream, live, idle, chunks);
+    launch_spectral(Z, bd, states, Z->near_dtype, xs, R3M_C128, y, partial, stream, live, idle, chunks, rl);
     return;
   }
   if (Z->near_dtype == R3M_C128)

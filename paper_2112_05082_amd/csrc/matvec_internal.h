@@ -65,9 +65,12 @@ void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
 // xs already in the store precision; y C128.  live (device, nullable): the
 // kernels return at once when *live == 0 (used to skip Arnoldi steps after
 // every right-hand side has converged); idle as above
+// rl (device, nullable): the right-hand sides with work, as a list (rl[0..n)
+// indices, rl[B] = n, every other one idle); the spectral transforms then
+// visit only their grids
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
                        void* partial, const void* lists, int chunks, hipStream_t stream, const int* live,
-                       const int* idle = nullptr);
+                       const int* idle = nullptr, const int* rl = nullptr);
 
 // spectral stores (far_dtype R3M_SPEC_*): the whole product by FFT
 bool store_is_spectral(const r3m_store* Z);
@@ -77,7 +80,7 @@ size_t spectral_work_bytes(const BatchDesc& bd, const r3m_store* Z);
 // plan: a spectral plan (kPlanSpectral set), anything else takes the default
 void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                      const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
-                     const int* idle = nullptr, int plan = 0);
+                     const int* idle = nullptr, int plan = 0, const int* rl = nullptr);
 // relaxed retrieval (wts [units][n_states], nullable) and the transposed operator
 void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                         const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,

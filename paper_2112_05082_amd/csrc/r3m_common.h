@@ -142,10 +142,14 @@ struct GeomDev {
   const int32_t* rwg_tri; // [n_rwg][2]
   const int32_t* rwg_free;// [n_rwg][2] local index of the free vertex
   const double* rwg_len;  // [n_rwg]
+  const int32_t* tri_cell;// [n_tri][2] lattice offset of each triangle's cell, or NULL
   int32_t n_tri, n_rwg;
 };
 
 void validate_geom(const r3m_unit_geom* g);
+// calls that do not take connected geometries yet (shared bases)
+void require_isolated(const r3m_store* Z);
+void require_isolated(const r3m_unit_geom* g);
 GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream);
 
 // At most kMaxBatches descriptors are cached per context; a new one beyond

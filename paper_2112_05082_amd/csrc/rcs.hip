@@ -316,6 +316,7 @@ int r3m_plane_wave_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* 
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_geom(geom);
+    require_isolated(geom);
     validate_batch(batch, 1 << 20, 1 << 20);
     if (batch->B == 0) return;
     R3M_REQUIRE(inc_host && b_dev, R3M_ERR_INVALID_ARG, "NULL argument");
@@ -354,6 +355,7 @@ int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, cons
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_geom(geom);
+    require_isolated(geom);
     validate_batch(batch, 1 << 20, 1 << 20);
     R3M_REQUIRE(n_dir >= 0, R3M_ERR_INVALID_ARG, "n_dir < 0");
     R3M_REQUIRE(e0 != 0.0 && std::isfinite(e0), R3M_ERR_INVALID_ARG, "e0 must be finite and non-zero");
@@ -391,6 +393,7 @@ int r3m_relaxed_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* bat
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_geom(geom);
+    require_isolated(geom);
     validate_batch(batch, 1 << 20, 1 << 20);
     if (batch->B == 0) return;
     R3M_REQUIRE(inc_host && b_dev && (macro || weights_dev), R3M_ERR_INVALID_ARG, "NULL argument");
@@ -429,6 +432,7 @@ int r3m_relaxed_objective(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batc
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_geom(geom);
+    require_isolated(geom);
     validate_batch(batch, 1 << 20, 1 << 20);
     R3M_REQUIRE(n_dir >= 1, R3M_ERR_INVALID_ARG, "n_dir < 1");
     R3M_REQUIRE(e0 != 0.0 && std::isfinite(e0), R3M_ERR_INVALID_ARG, "e0 must be finite and non-zero");

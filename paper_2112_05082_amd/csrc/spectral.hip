@@ -187,6 +187,11 @@ struct FftArgs {
   const RhsDev* rhs;  // retrieval passes only
   const uint8_t* states;
   int n_states, n, n_a;
+  // shared bases (connected geometries): macro rows [n_st, n) are in every
+  // unit (ext: 0, or 1 / 2 masked in the array's first column / row); a
+  // unit's compact vector has n_red = n_a + n - n_st entries
+  int n_st, n_red;
+  const int* ext;
   const void* x;  // kFwdRows
   void* y;        // kInvRows
   // relaxed retrieval (nullable): state weights [unit][n_states] replace the
@@ -252,8 +257,14 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
   }
   // a workgroup's lines belong to one right-hand side (grids are [B][n])
   if (A.idle && A.idle[g0 / A.n]) return;
-  // the active macro row of unit u in channel c, or -1
-  auto active = [&](int64_t u, int c) -> int {
+  // the compact row of channel c in unit u = gy Lx + gx: -1 when c is not a
+  // row of the unit's state, -2 for an extended basis masked by D_k (its
+  // output is zero)
+  auto active = [&](int64_t u, int gx, int gy, int c) -> int {
+    if (c >= A.n_st) {
+      const int e = A.ext[c - A.n_st];
+      return e == 0 || (e == 1 && gx > 0) || (e == 2 && gy > 0) ? A.n_a + c - A.n_st : -2;
+    }
     const int s = min((int)A.states[R.state_off + u], A.n_states - 1);
     const int r = c - s * A.n_a;
     return r >= 0 && r < A.n_a ? r : -1;
@@ -284,9 +295,9 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
           const VT* xv = (const VT*)A.x + ((R.unit_off + u) * A.n_a + r) * 2;
           v = {(T)(wv * (double)xv[0]), (T)(wv * (double)xv[1])};
         } else {
-          const int r = active(u, c0 + li);
+          const int r = active(u, gx, gy, c0 + li);
           if (r >= 0) {
-            const VT* xv = (const VT*)A.x + ((R.unit_off + u) * A.n_a + r) * 2;
+            const VT* xv = (const VT*)A.x + ((R.unit_off + u) * A.n_red + r) * 2;
             v = {(T)xv[0], (T)xv[1]};
           }
         }
@@ -323,11 +334,14 @@ __global__ void __launch_bounds__(256) fft_kernel(FftArgs<T> A) {
           const T ws = (A.macro_plain ? T(1) : (T)A.wts[(R.unit_off + u) * A.n_states + s]) * scale;
           A.ymacro[(R.unit_off + u) * A.n + c] = {v.re * ws, v.im * ws};
         } else {
-          const int r = active(u, c0 + li);
+          const int r = active(u, gx, gy, c0 + li);
           if (r >= 0) {
-            VT* yv = (VT*)A.y + ((R.unit_off + u) * A.n_a + r) * 2;
+            VT* yv = (VT*)A.y + ((R.unit_off + u) * A.n_red + r) * 2;
             yv[0] = (VT)(v.re * scale);
             yv[1] = (VT)(v.im * scale);
+          } else if (r == -2) {
+            VT* yv = (VT*)A.y + ((R.unit_off + u) * A.n_red + A.n_a + c0 + li - A.n_st) * 2;
+            yv[0] = yv[1] = (VT)0;
           }
         }
       }
@@ -406,12 +420,17 @@ struct Fft2Args {
   int n_states, n, n_a;
   int lgGx, lgGy;
   int64_t n_grids;
+  int n_st, n_red;  // shared bases, as in FftArgs
+  const int* ext;
   const void* x;  // forward: compact input
   void* y;        // inverse: compact output
   const int* live;
   const int* idle;
+  // the right-hand sides with work (nullable): rl[0..rl[B]) their indices;
+  // the workgroups then visit only their grids (the list replaces idle)
+  const int* rl;
+  int B;
 };
-
 
 __device__ __forceinline__ int at2(int gx, int gy, int Sx) { return gy * Sx + gx + (gx >> 4); }
 
@@ -541,16 +560,23 @@ __global__ void __launch_bounds__(fft2_threads<LG>()) fft2_kernel(Fft2Args A) {
     tw[m] = make_float2(cs, (float)SGN * sn);
   }
   const float scale = 1.0f / (float)(G * G);
-  const int64_t per_x = gridDim.x >> 3, span = (A.n_grids + 7) >> 3;
-  const int64_t g_end = min(A.n_grids, ((int64_t)blockIdx.x & 7) * span + span);
-  for (int64_t g = ((int64_t)blockIdx.x & 7) * span + (blockIdx.x >> 3); g < g_end; g += per_x) {
-    const int b = (int)(g / A.n), c = (int)(g - (int64_t)b * A.n);
-    if (A.idle && A.idle[b]) continue;  // uniform over the workgroup
+  const int64_t n_grids = A.rl ? (int64_t)A.rl[A.B] * A.n : A.n_grids;
+  const int64_t per_x = gridDim.x >> 3, span = (n_grids + 7) >> 3;
+  const int64_t g_end = min(n_grids, ((int64_t)blockIdx.x & 7) * span + span);
+  for (int64_t gi = ((int64_t)blockIdx.x & 7) * span + (blockIdx.x >> 3); gi < g_end; gi += per_x) {
+    const int li = (int)(gi / A.n), c = (int)(gi - (int64_t)li * A.n);
+    const int b = A.rl ? A.rl[li] : li;
+    const int64_t g = (int64_t)b * A.n + c;
+    if (!A.rl && A.idle && A.idle[b]) continue;  // uniform over the workgroup
     const RhsDev R = A.rhs[b];
     const int Lx = R.Lx, Ly = R.Ly;
     // channel c is row rc of state sc: a unit contributes (or receives) it
-    // when its state byte is sc
-    const int sc = c / A.n_a, rc = c - sc * A.n_a;
+    // when its state byte is sc; a shared channel (c >= n_st) is compact row
+    // rc of every unit, except where D_k masks an extended basis
+    const bool shared = c >= A.n_st;
+    const int sc = shared ? -1 : c / A.n_a;
+    const int rc = shared ? A.n_a + c - A.n_st : c - sc * A.n_a;
+    const int ec = shared ? A.ext[c - A.n_st] : 0;
     float2* grid = reinterpret_cast<float2*>(A.grid) + (g << (2 * LG));
     __syncthreads();  // the previous grid's last LDS reads (and the twiddle table) are done
     if (!INV) {
@@ -560,16 +586,19 @@ __global__ void __launch_bounds__(fft2_threads<LG>()) fft2_kernel(Fft2Args A) {
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
         const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
-        sv[i] = t < (Ly << LG) && gx < Lx ? (int)A.states[R.state_off + (int64_t)gy * Lx + gx] : -1;
+        const bool in = t < (Ly << LG) && gx < Lx;
+        if (shared)
+          sv[i] = in && (ec == 0 || (ec == 1 && gx > 0) || (ec == 2 && gy > 0)) ? sc : -2;
+        else
+          sv[i] = in ? (int)A.states[R.state_off + (int64_t)gy * Lx + gx] : -2;
       }
       float2 vv[kPer];
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
         const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
         vv[i] = make_float2(0.f, 0.f);
-        if (sv[i] == sc) {
-          vv[i] = load_c2<VT>((const VT*)A.x + ((R.unit_off + (int64_t)gy * Lx + gx) * A.n_a + rc) * 2);
-        }
+        if (sv[i] == sc)
+          vv[i] = load_c2<VT>((const VT*)A.x + ((R.unit_off + (int64_t)gy * Lx + gx) * A.n_red + rc) * 2);
       }
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
@@ -583,19 +612,23 @@ __global__ void __launch_bounds__(fft2_threads<LG>()) fft2_kernel(Fft2Args A) {
       line_stages<true, SGN, LG, true, false>(buf, tw, grid, G, G, Ly);
       line_stages<false, SGN, LG, false, false>(buf, tw, grid, Ly, G, G);
       // active rows of units gx < Lx, gy < Ly -> compact output (state
-      // bytes first, as for the input)
+      // bytes first, as for the input); masked shared rows receive zero
       int sv[kPer];
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
         const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
-        sv[i] = t < (Ly << LG) && gx < Lx ? (int)A.states[R.state_off + (int64_t)gy * Lx + gx] : -1;
+        const bool in = t < (Ly << LG) && gx < Lx;
+        if (shared)
+          sv[i] = !in ? -2 : ec == 0 || (ec == 1 && gx > 0) || (ec == 2 && gy > 0) ? sc : -3;
+        else
+          sv[i] = in ? (int)A.states[R.state_off + (int64_t)gy * Lx + gx] : -2;
       }
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
         const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
-        if (sv[i] == sc) {
-          const float2 v = buf[at2(gx, gy, Sx)];
-          store_c2<VT>((VT*)A.y + ((R.unit_off + (int64_t)gy * Lx + gx) * A.n_a + rc) * 2, v.x * scale,
+        if (sv[i] == sc || sv[i] == -3) {
+          const float2 v = sv[i] == sc ? buf[at2(gx, gy, Sx)] : make_float2(0.f, 0.f);
+          store_c2<VT>((VT*)A.y + ((R.unit_off + (int64_t)gy * Lx + gx) * A.n_red + rc) * 2, v.x * scale,
                        v.y * scale);
         }
       }
@@ -1036,7 +1069,8 @@ size_t spectral_list_offset(const BatchDesc& bd, const r3m_store* Z) {
 template <typename T, typename XT, typename YT>
 void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* x, void* y,
                     void* work, hipStream_t s, const int* live, const double* wts = nullptr, bool tr = false,
-                    C2<T>* macro_out = nullptr, const int* idle = nullptr, int plan = 0) {
+                    C2<T>* macro_out = nullptr, const int* idle = nullptr, int plan = 0,
+                    const int* rl = nullptr) {
   const int n = Z->n;
   const int lgGx = ilog2(next_pow2(2 * Z->Dx + 1)), lgGy = ilog2(next_pow2(2 * Z->Dy + 1));
   const int64_t G2 = (int64_t)1 << (lgGx + lgGy);
@@ -1048,7 +1082,10 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
   A.states = states;
   A.n_states = Z->n_states;
   A.n = n;
-  A.n_a = n / Z->n_states;
+  A.n_st = n - Z->n_common;
+  A.n_a = A.n_st / Z->n_states;
+  A.n_red = A.n_a + Z->n_common;
+  A.ext = Z->common_ext;
   A.x = x;
   A.y = y;
   A.wts = wts;
@@ -1071,6 +1108,9 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
     F.n_states = Z->n_states;
     F.n = n;
     F.n_a = A.n_a;
+    F.n_st = A.n_st;
+    F.n_red = A.n_red;
+    F.ext = A.ext;
     F.lgGx = lgGx;
     F.lgGy = lgGy;
     F.n_grids = ng;
@@ -1078,6 +1118,8 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
     F.y = y;
     F.live = live;
     F.idle = idle;
+    F.rl = rl;
+    F.B = B;
     F.grid = (C2<float>*)X;
     fft2_pass<false, XT>(F, s);
   } else {
@@ -1178,7 +1220,12 @@ void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* 
 
 void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                      const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
-                     const int* idle, int plan) {
+                     const int* idle, int plan, const int* rl) {
+  const bool xd = x_type == R3M_C128, yd = y_type == R3M_C128;
+  if (Z->far_dtype == R3M_SPEC_C64 && !xd && yd) {  // the solver's form: the list reaches the transforms
+    spectral_typed<float, float, double>(Z, bd, states, x, y, work, s, live, nullptr, false, nullptr, idle, plan, rl);
+    return;
+  }
   launch_spectral_ex(Z, bd, states, x_type, x, y_type, y, work, s, live, nullptr, false, idle, plan);
 }
 
@@ -1210,6 +1257,7 @@ size_t r3m_relaxed_gradient_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3
   int rc = guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_store(Z);
+    require_isolated(Z);
     R3M_REQUIRE(Z->far_dtype == R3M_SPEC_C128, R3M_ERR_UNSUPPORTED, "the gradient needs complex128 spectra");
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;
@@ -1226,6 +1274,7 @@ int r3m_relaxed_gradient(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_store(Z);
+    require_isolated(Z);
     R3M_REQUIRE(Z->far_dtype == R3M_SPEC_C128, R3M_ERR_UNSUPPORTED, "the gradient needs complex128 spectra");
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;
@@ -1256,6 +1305,7 @@ size_t r3m_relaxed_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* 
   int rc = guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_store(Z);
+    require_isolated(Z);
     R3M_REQUIRE(store_is_spectral(Z), R3M_ERR_UNSUPPORTED, "relaxed retrieval needs a spectral store");
     validate_batch(batch, Z->Dx, Z->Dy);
     if (batch->B == 0) return;
@@ -1270,6 +1320,7 @@ int r3m_relaxed_matvec(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, 
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_store(Z);
+    require_isolated(Z);
     R3M_REQUIRE(store_is_spectral(Z), R3M_ERR_UNSUPPORTED, "relaxed retrieval needs a spectral store");
     validate_batch(batch, Z->Dx, Z->Dy);
     R3M_REQUIRE(vec_dtype == R3M_C128 || vec_dtype == R3M_C64, R3M_ERR_UNSUPPORTED, "vectors must be C128 or C64");

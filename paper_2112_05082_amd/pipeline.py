@@ -73,4 +73,7 @@ def spectral_store(ctx, geom, L: int, near_radius: int, dtype: int, device,
     r3m.r3m_build_spectral(ctx, dense_c128, n, D, D, sd, spec)
     if own_dense:
         del dense_c128
-    return r3m.Store(n, geom.n_states, D, D, nr, dtype, near, sd, spec)
+    ext = None
+    if getattr(geom, "common_ext", None) is not None:  # shared bases of a connected geometry
+        ext = torch.from_numpy(geom.common_ext).to(device)
+    return r3m.Store(n, geom.n_states, D, D, nr, dtype, near, sd, spec, common_ext=ext)

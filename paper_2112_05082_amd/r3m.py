@@ -54,7 +54,7 @@ class UnitGeomC(C.Structure):
         ("n_vert", C.c_int32), ("vert", C.POINTER(C.c_double)),
         ("n_tri", C.c_int32), ("tri", C.POINTER(C.c_int32)),
         ("n_rwg", C.c_int32), ("rwg", C.POINTER(C.c_int32)),
-        ("extract_radius", C.c_int32),
+        ("extract_radius", C.c_int32), ("n_common", C.c_int32), ("tri_cell", C.POINTER(C.c_int32)),
     ]
 
 
@@ -63,6 +63,7 @@ class StoreC(C.Structure):
         ("n", C.c_int32), ("n_states", C.c_int32), ("Dx", C.c_int32), ("Dy", C.c_int32),
         ("near_radius", C.c_int32), ("near_dtype", C.c_int), ("near", C.c_void_p),
         ("far_dtype", C.c_int), ("far", C.c_void_p), ("max_rank", C.c_int32),
+        ("n_common", C.c_int32), ("common_ext", C.c_void_p),
     ]
 
 
@@ -198,20 +199,29 @@ class Context:
 class UnitGeom:
     """Host geometry of a macro unit (keeps the numpy arrays alive)."""
 
-    def __init__(self, vert, tri, rwg, state_off, freq_hz, period, extract_radius=1):
+    def __init__(self, vert, tri, rwg, state_off, freq_hz, period, extract_radius=1, tri_cell=None,
+                 common_ext=None):
         self.vert = np.ascontiguousarray(vert, dtype=np.float64)
         self.tri = np.ascontiguousarray(tri, dtype=np.int32)
         self.rwg = np.ascontiguousarray(rwg, dtype=np.int32)
         self.state_off = np.ascontiguousarray(state_off, dtype=np.int32)
+        self.tri_cell = None if tri_cell is None else np.ascontiguousarray(tri_cell, dtype=np.int32)
+        # connected geometries: the classes of the shared bases (host copy)
+        self.common_ext = None if common_ext is None else np.ascontiguousarray(common_ext, dtype=np.int32)
         self.c = UnitGeomC(
             float(freq_hz), float(period[0]), float(period[1]), len(self.state_off) - 1,
             _ptr(self.state_off, C.c_int32), len(self.vert), _ptr(self.vert, C.c_double),
             len(self.tri), _ptr(self.tri, C.c_int32), len(self.rwg), _ptr(self.rwg, C.c_int32),
-            int(extract_radius))
+            int(extract_radius), self.n_common,
+            _ptr(self.tri_cell, C.c_int32) if self.tri_cell is not None else None)
 
     @property
     def n(self):
-        return int(self.state_off[-1])
+        return len(self.rwg)
+
+    @property
+    def n_common(self):
+        return len(self.rwg) - int(self.state_off[-1])
 
     @property
     def n_states(self):
@@ -220,6 +230,12 @@ class UnitGeom:
     @classmethod
     def from_macro(cls, unit, freq_hz, extract_radius=1):
         return cls(unit.vert, unit.tri, unit.rwg, unit.state_off, freq_hz, unit.period, extract_radius)
+
+    @classmethod
+    def from_connected(cls, cu, freq_hz, extract_radius=1):
+        """An extended macro unit over a connected ground plane (see
+        workloads.mesh.connected_unit)."""
+        return cls(cu.vert, cu.tri, cu.rwg, cu.state_off, freq_hz, cu.period, extract_radius, cu.tri_cell, cu.ext)
 
 
 @dataclass
@@ -237,11 +253,18 @@ class Store:
     max_rank: int = 0
     ranks: np.ndarray | None = None
     rel_err: np.ndarray | None = None
+    common_ext: object = None  # torch int32 device tensor of the shared bases' classes, or None
+
+    @property
+    def n_common(self) -> int:
+        return 0 if self.common_ext is None else int(self.common_ext.numel())
 
     def c(self) -> StoreC:
         return StoreC(self.n, self.n_states, self.Dx, self.Dy, self.near_radius, self.near_dtype,
                       C.c_void_p(self.near.data_ptr()), self.far_dtype,
-                      C.c_void_p(self.far.data_ptr() if self.far is not None else 0), self.max_rank)
+                      C.c_void_p(self.far.data_ptr() if self.far is not None else 0), self.max_rank,
+                      self.n_common,
+                      C.c_void_p(self.common_ext.data_ptr() if self.common_ext is not None else 0))
 
 
 class Batch:
