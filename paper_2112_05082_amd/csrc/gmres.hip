@@ -12,6 +12,7 @@
 #include "small_dense.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace r3m {
 
@@ -45,6 +46,17 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 __device__ inline double2 cmulc(double2 a, double2 b) {  // conj(a) * b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
+
+// Krylov basis storage: complex128, or complex64 for inner solves on
+// complex64 stores under FP64 refinement (their products carry FP32 error
+// already; the basis then takes half the bytes).  Arithmetic stays FP64.
+__device__ __forceinline__ double2 ld_b(const double2* p) { return *p; }
+__device__ __forceinline__ double2 ld_b(const float2* p) {
+  const float2 v = *p;
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_b(double2* p, double2 v) { *p = v; }
+__device__ __forceinline__ void st_b(float2* p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
 
 // Lists of right-hand sides with work in an Arnoldi step: rl[0..n) the
 // indices in increasing order, rl[B] = n; a NULL list stands for all B (the
@@ -255,8 +267,9 @@ __device__ double2 block_sum2(double2 v, double2* sh) {
 // The blocks stride over the items of the right-hand sides of rl (a live
 // list, see rhs_count), or of all B.  The consumer kernel sums the partials
 // itself (no grid-wide fence here).
+template <typename VB>
 __global__ void __launch_bounds__(kDotThreads)
-dots_partials_kernel(const double2* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
+dots_partials_kernel(const VB* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
                      const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
                      int* __restrict__ reset, const int* __restrict__ live, const int* __restrict__ idle,
                      const int* __restrict__ rl, int B) {
@@ -290,11 +303,11 @@ dots_partials_kernel(const double2* __restrict__ A, int64_t a_stride, const doub
     double2 av[kDotVec][kDotPer];
 #pragma unroll
     for (int q = 0; q < kDotVec; ++q) {
-      const double2* a = A + (int64_t)(i0 + min(q, nv - 1)) * a_stride + r.off;
+      const VB* a = A + (int64_t)(i0 + min(q, nv - 1)) * a_stride + r.off;
 #pragma unroll
       for (int e = 0; e < kDotPer; ++e) {
         const int64_t k = lo + (int64_t)e * kDotThreads;
-        av[q][e] = k < r.N ? a[k] : make_double2(0.0, 0.0);
+        av[q][e] = k < r.N ? ld_b(a + k) : make_double2(0.0, 0.0);
       }
     }
     double2 acc[kDotVec];
@@ -384,9 +397,9 @@ finish_norm_kernel(const double* __restrict__ npart, int maxB, const RhsVec* __r
 // Blocks (of nsub runs, nb_max per RHS) are work items strided over by the
 // grid, for the right-hand sides of rl (see rhs_count).
 // Dynamic LDS: nvec double2.
-template <int KV>
+template <int KV, typename VB>
 __global__ void __launch_bounds__(256)
-gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
+gs_update_kernel(const VB* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
                  const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int n_part,
                  int nvec, int64_t ut, int do_norm, double* __restrict__ npart, int maxB, double2* __restrict__ H,
                  int m, int j, int mode, const int* __restrict__ run_prev, const int* __restrict__ idle,
@@ -438,14 +451,17 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
       const int64_t k = (blk * nsub + sb) * 64 + e;
       const bool live = k < r.N && act;
       double2 acc = make_double2(0.0, 0.0);
+      // wave 0 reads w with the basis entries, so that the update after the
+      // barrier does not wait for memory
+      const double2 wpre = q == 0 && live ? w[r.off + k] : make_double2(0.0, 0.0);
       double2 vv[KV > 0 ? KV : 1];
       if (KV > 0) {
         if (live) {
-          const double2* vk = V + r.off + k;
+          const VB* vk = V + r.off + k;
 #pragma unroll
           for (int t = 0; t < KV; ++t) {
             const int i = q + 4 * t;
-            vv[t] = i < nvec ? vk[(int64_t)i * ut] : make_double2(0.0, 0.0);
+            vv[t] = i < nvec ? ld_b(vk + (int64_t)i * ut) : make_double2(0.0, 0.0);
           }
 #pragma unroll
           for (int t = 0; t < KV; ++t) {
@@ -458,11 +474,11 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
           }
         }
       } else if (live) {
-        const double2* vk = V + r.off + k;
+        const VB* vk = V + r.off + k;
         int i = q;
         for (; i + 12 < nvec; i += 16) {
-          const double2 v0 = vk[(int64_t)i * ut], v1 = vk[(int64_t)(i + 4) * ut];
-          const double2 v2 = vk[(int64_t)(i + 8) * ut], v3 = vk[(int64_t)(i + 12) * ut];
+          const double2 v0 = ld_b(vk + (int64_t)i * ut), v1 = ld_b(vk + (int64_t)(i + 4) * ut);
+          const double2 v2 = ld_b(vk + (int64_t)(i + 8) * ut), v3 = ld_b(vk + (int64_t)(i + 12) * ut);
           const double2 t0 = cmul(hb[i], v0), t1 = cmul(hb[i + 4], v1);
           const double2 t2 = cmul(hb[i + 8], v2), t3 = cmul(hb[i + 12], v3);
           acc.x += t0.x;
@@ -475,7 +491,7 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
           acc.y += t3.y;
         }
         for (; i < nvec; i += 4) {
-          const double2 t = cmul(hb[i], vk[(int64_t)i * ut]);
+          const double2 t = cmul(hb[i], ld_b(vk + (int64_t)i * ut));
           acc.x += t.x;
           acc.y += t.y;
         }
@@ -488,7 +504,7 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
           acc.x += part[t][e].x;
           acc.y += part[t][e].y;
         }
-        double2 wk = w[r.off + k];
+        double2 wk = wpre;
         wk.x -= acc.x;
         wk.y -= acc.y;
         w[r.off + k] = wk;
@@ -536,21 +552,30 @@ gs_update_kernel(const double2* __restrict__ V, double2* __restrict__ w, const R
 // (MODE 2, block-Jacobi; a block holds whole units).  MODE 0 writes V only.
 // Blocks (nb_max per RHS) are work items strided over by the grid, for the
 // right-hand sides of rl (see rhs_count).
-template <typename OT, int MODE>
+template <typename OT, int MODE, typename VB>
 __global__ void __launch_bounds__(256)
-normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, const RhsVec* __restrict__ rv,
+normalize_step_kernel(const double2* __restrict__ w, VB* __restrict__ V, const RhsVec* __restrict__ rv,
                       RhsState* __restrict__ st, const double* __restrict__ npart, int maxB, int n_npart,
                       double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
                       double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
                       double* __restrict__ wn, int64_t ut, const int* __restrict__ live,
                       const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
                       const int64_t* __restrict__ soff, int n_a, int n_states, OT* __restrict__ xs, int per_unit,
-                      int* __restrict__ idle, const int* __restrict__ rl, int B, int64_t nb_max) {
+                      int* __restrict__ idle, const int* __restrict__ rl, int B, int64_t nb_max, int stage) {
   if (live && *live == 0) return;
   __shared__ double nv_s;
   __shared__ double2 v_s[256];
   extern __shared__ double2 glds[];
   const int64_t items = nb_max * rhs_count(rl, B);
+  // stage: the block-Jacobi inverses of every state, rounded to complex64, in
+  // LDS after the Givens scratch (one read per workgroup instead of one per
+  // element; a complex64 product needs no more)
+  float2* Ms = reinterpret_cast<float2*>(glds + (2 * m + 2) + (m + 1) / 2);
+  if (MODE == 2 && stage && (int64_t)blockIdx.x < items) {
+    for (int t = threadIdx.x; t < n_states * n_a * n_a; t += blockDim.x)
+      Ms[t] = make_float2((float)Minv[t].x, (float)Minv[t].y);
+    __syncthreads();
+  }
   for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {  // uniform over the block
     const int li = (int)(item / nb_max);
     const int64_t blk = item - li * nb_max;
@@ -583,7 +608,7 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
     if (in) {
       const double2 wk = w[r.off + k];
       if (ok) v = make_double2(wk.x / nv, wk.y / nv);
-      V[(int64_t)(j + 1) * ut + r.off + k] = v;
+      st_b(V + (int64_t)(j + 1) * ut + r.off + k, v);
     }
     if (MODE == 1 && in) {
       xs[2 * (r.off + k)] = (OT)v.x;
@@ -596,16 +621,29 @@ normalize_step_kernel(const double2* __restrict__ w, double2* __restrict__ V, co
         const int64_t u = k / n_a;
         const int mr = (int)(k % n_a);
         const int64_t sidx = per_unit ? r.off / n_a + u : min((int)states[soff[b] + u], n_states - 1);
-        const double2* M = Minv + (size_t)sidx * n_a * n_a + mr;  // column-major
         const double2* vu = v_s + (threadIdx.x / n_a) * n_a;
-        double2 acc = make_double2(0.0, 0.0);
-        for (int c = 0; c < n_a; ++c) {
-          const double2 t = cmul(M[(size_t)c * n_a], vu[c]);
-          acc.x += t.x;
-          acc.y += t.y;
+        if (stage) {
+          const float2* M = Ms + (size_t)sidx * n_a * n_a + mr;  // column-major
+          float2 acc = make_float2(0.f, 0.f);
+          for (int c = 0; c < n_a; ++c) {
+            const float2 mm = M[(size_t)c * n_a];
+            const float vx = (float)vu[c].x, vy = (float)vu[c].y;
+            acc.x += mm.x * vx - mm.y * vy;
+            acc.y += mm.x * vy + mm.y * vx;
+          }
+          xs[2 * (r.off + k)] = (OT)acc.x;
+          xs[2 * (r.off + k) + 1] = (OT)acc.y;
+        } else {
+          const double2* M = Minv + (size_t)sidx * n_a * n_a + mr;  // column-major
+          double2 acc = make_double2(0.0, 0.0);
+          for (int c = 0; c < n_a; ++c) {
+            const double2 t = cmul(M[(size_t)c * n_a], vu[c]);
+            acc.x += t.x;
+            acc.y += t.y;
+          }
+          xs[2 * (r.off + k)] = (OT)acc.x;
+          xs[2 * (r.off + k) + 1] = (OT)acc.y;
         }
-        xs[2 * (r.off + k)] = (OT)acc.x;
-        xs[2 * (r.off + k) + 1] = (OT)acc.y;
       }
     }
     if (blk == 0) {  // uniform over the block
@@ -649,7 +687,8 @@ backsolve_kernel(const double2* __restrict__ H, double2* __restrict__ g, const R
 }
 
 // x += V y (first jdone columns)
-__global__ void update_x_kernel(const double2* __restrict__ V, const double2* __restrict__ g,
+template <typename VB>
+__global__ void update_x_kernel(const VB* __restrict__ V, const double2* __restrict__ g,
                                 double2* __restrict__ x, const RhsVec* __restrict__ rv,
                                 const RhsState* __restrict__ st, int m, int64_t ut) {
   const int b = blockIdx.y;
@@ -660,7 +699,7 @@ __global__ void update_x_kernel(const double2* __restrict__ V, const double2* __
   double2 acc = x[r.off + k];
   const double2* y = g + (size_t)b * (m + 1);
   for (int i = 0; i < s.jdone; ++i) {
-    double2 t = cmul(y[i], V[(int64_t)i * ut + r.off + k]);
+    double2 t = cmul(y[i], ld_b(V + (int64_t)i * ut + r.off + k));
     acc.x += t.x;
     acc.y += t.y;
   }
@@ -699,7 +738,8 @@ __global__ void zero_kernel(double2* __restrict__ x, const RhsVec* __restrict__ 
 }
 
 // start of a cycle: beta = ||r||, V_0 = r / beta, g = (beta, 0, ...), jdone = -1
-__global__ void cycle_start_kernel(const double2* __restrict__ r, double2* __restrict__ V,
+template <typename VB>
+__global__ void cycle_start_kernel(const double2* __restrict__ r, VB* __restrict__ V,
                                    const RhsVec* __restrict__ rv, RhsState* __restrict__ st,
                                    const double2* __restrict__ nrm2, double2* __restrict__ g, int m,
                                    int* __restrict__ live0, int* __restrict__ idle) {
@@ -711,8 +751,7 @@ __global__ void cycle_start_kernel(const double2* __restrict__ r, double2* __res
   const double beta = sqrt(fmax(nrm2[b].x, 0.0));
   const bool act = st[b].active && beta > 0.0;
   if (k < rr.N)
-    V[rr.off + k] = act ? make_double2(r[rr.off + k].x / beta, r[rr.off + k].y / beta)
-                        : make_double2(0.0, 0.0);
+    st_b(V + rr.off + k, act ? make_double2(r[rr.off + k].x / beta, r[rr.off + k].y / beta) : make_double2(0.0, 0.0));
   if (k <= m) g[(size_t)b * (m + 1) + k] = (k == 0 && act) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
 }
 
@@ -812,10 +851,10 @@ relaxed_selfblock_inverse_kernel(const S* __restrict__ nearb, int slot0, int n, 
 
 // out_u = Minv[s_u] in_u for every unit (user layout); OT is the output real
 // type.  per_unit: Minv holds one block per global unit (relaxed codebooks)
-template <typename OT>
+template <typename OT, typename IT = double2>
 __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
                                      const int64_t* __restrict__ soff, const RhsVec* __restrict__ rv, int n_a,
-                                     int n_states, const double2* __restrict__ in, OT* __restrict__ out,
+                                     int n_states, const IT* __restrict__ in, OT* __restrict__ out,
                                      const int* __restrict__ live, int per_unit, const RhsState* __restrict__ st) {
   if (live && *live == 0) return;
   const int b = blockIdx.y;
@@ -829,10 +868,10 @@ __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uin
   // column-major blocks: the lanes of a unit (consecutive rows m) read
   // consecutive entries for each column c
   const double2* M = Minv + (size_t)s * n_a * n_a + m;
-  const double2* v = in + r.off + u * n_a;
+  const IT* v = in + r.off + u * n_a;
   double2 acc = make_double2(0.0, 0.0);
   for (int c = 0; c < n_a; ++c) {
-    const double2 t = cmul(M[(size_t)c * n_a], v[c]);
+    const double2 t = cmul(M[(size_t)c * n_a], ld_b(v + c));
     acc.x += t.x;
     acc.y += t.y;
   }
@@ -840,21 +879,22 @@ __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uin
   out[2 * (r.off + k) + 1] = (OT)acc.y;
 }
 
-template <typename OT>
-__global__ void convert_vec_kernel(const RhsVec* __restrict__ rv, const double2* __restrict__ in,
+template <typename OT, typename IT = double2>
+__global__ void convert_vec_kernel(const RhsVec* __restrict__ rv, const IT* __restrict__ in,
                                    OT* __restrict__ out, const int* __restrict__ live) {
   if (live && *live == 0) return;
   const int b = blockIdx.y;
   const RhsVec r = rv[b];
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= r.N) return;
-  const double2 v = in[r.off + k];
+  const double2 v = ld_b(in + r.off + k);
   out[2 * (r.off + k)] = (OT)v.x;
   out[2 * (r.off + k) + 1] = (OT)v.y;
 }
 
 // z = V y (first jdone columns)
-__global__ void combine_basis_kernel(const double2* __restrict__ V, const double2* __restrict__ g,
+template <typename VB>
+__global__ void combine_basis_kernel(const VB* __restrict__ V, const double2* __restrict__ g,
                                      double2* __restrict__ z, const RhsVec* __restrict__ rv,
                                      const RhsState* __restrict__ st, int m, int64_t ut) {
   const int b = blockIdx.y;
@@ -866,7 +906,7 @@ __global__ void combine_basis_kernel(const double2* __restrict__ V, const double
   if (s.active) {
     const double2* y = g + (size_t)b * (m + 1);
     for (int i = 0; i < s.jdone; ++i) {
-      double2 t = cmul(y[i], V[(int64_t)i * ut + r.off + k]);
+      double2 t = cmul(y[i], ld_b(V + (int64_t)i * ut + r.off + k));
       acc.x += t.x;
       acc.y += t.y;
     }
@@ -923,9 +963,11 @@ struct Work {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// The folded Gram-Schmidt update keeps up to 8 basis entries per wave in
-// registers, so it takes steps with at most 32 basis vectors.
-constexpr int kFoldMaxVec = 32;
+// The folded Gram-Schmidt update keeps up to 4 basis entries per wave in
+// registers, so it takes steps with at most 16 basis vectors (with 8 per
+// wave its register count leaves three waves per SIMD, and it measured no
+// faster than the two separate passes).
+constexpr int kFoldMaxVec = 16;
 // 64-element runs per update block: four for long vectors (more than 64
 // chunks of kDotChunk: a quarter of the workgroups, which matters once most
 // right-hand sides of a wide batch are idle and their workgroups only
@@ -940,7 +982,7 @@ int64_t fold_blocks(int64_t maxN) {
 // n_blocks: block-Jacobi inverses held (one per state, or one per unit for
 // relaxed codebooks)
 Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_blocks, int m, size_t mv_bytes,
-                 size_t lists_bytes, size_t lists64_bytes, size_t ilu_bytes) {
+                 size_t lists_bytes, size_t lists64_bytes, size_t ilu_bytes, bool vb32) {
   Work w{};
   const int B = bd.B;
   int64_t maxN = 0;
@@ -954,7 +996,7 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_blocks, int m, 
     o = align256(o + bytes);
     return base ? (void*)(base + at) : nullptr;
   };
-  w.V = (double2*)take((size_t)vtot * 16);
+  w.V = (double2*)take((size_t)vtot * (vb32 ? 8 : 16));  // complex64 entries when vb32
   w.w = (double2*)take(ut * 16);
   w.r = (double2*)take(ut * 16);
   w.d = (double2*)take(ut * 16);
@@ -973,7 +1015,7 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_blocks, int m, 
   w.cs = (double*)take((size_t)B * m * 8);
   w.sn = (double2*)take((size_t)B * m * 16);
   w.dpart = (double2*)take((size_t)B * (m + 1) * std::max(maxP, 1) * 16);
-  if (m + 1 <= kFoldMaxVec) w.dpart2 = (double2*)take((size_t)B * (m + 1) * fold_blocks(maxN) * 16);
+  w.dpart2 = (double2*)take((size_t)B * std::min(m + 1, kFoldMaxVec) * fold_blocks(maxN) * 16);
   w.hbuf = (double2*)take((size_t)B * (m + 1) * 16);
   w.hsum = (double2*)take((size_t)B * (m + 1) * 16);
   w.nsum = (double*)take((size_t)B * 8);
@@ -1004,6 +1046,7 @@ struct GmresRun {
   bool tr = false;              // with wts: the transposed operator
   int pu = 0;                   // block-Jacobi inverses per global unit (relaxed) instead of per state
   int ilu_r = 0;                // > 0: the near-field block ILU(0) of this radius preconditions
+  bool vb32 = false;            // the Krylov basis W.V holds complex64 (see basis32)
   int G = 1;  // displacement groups of the matvec (autotuned)
   int64_t maxN, ut;
   Work W;
@@ -1075,28 +1118,40 @@ struct GmresRun {
   // normalisation, or by prepare_input for V_0.  A complex128 store without
   // preconditioner reads V_j itself.
   bool input_in_xs(const r3m_store* Z) const { return pre || Z->near_dtype == R3M_C64; }
-  void prepare_input(const r3m_store* Z, const double2* v) {
+  template <typename VB>
+  void prepare_input(const r3m_store* Z, const VB* v) {
     const bool c64 = Z->near_dtype == R3M_C64;
     if (ilu_r) {  // W.w is free here: the forward solve's scratch
-      launch_ilu_apply(Z, *bd, ilu_r, W.ilu, v, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s, nullptr, wts == nullptr);
+      if constexpr (std::is_same<VB, double2>::value)
+        launch_ilu_apply(Z, *bd, ilu_r, W.ilu, v, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s, nullptr, wts == nullptr);
+      else
+        R3M_REQUIRE(false, R3M_ERR_UNSUPPORTED, "a complex64 basis with the ILU preconditioner");
     } else if (pre) {
       if (c64)
-        hipLaunchKernelGGL(apply_precond_kernel<float>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr, pu,
-                           (const RhsState*)W.st);
+        hipLaunchKernelGGL((apply_precond_kernel<float, VB>), vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
+                           W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr, pu, (const RhsState*)W.st);
       else
-        hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (double*)W.xs, (const int*)nullptr, pu,
+        hipLaunchKernelGGL((apply_precond_kernel<double, VB>), vgrid(), dim3(256), 0, s, W.Minv, batch->states,
+                           W.soff, W.rv, n_a, n_states, v, (double*)W.xs, (const int*)nullptr, pu,
                            (const RhsState*)W.st);
     } else if (c64) {
-      hipLaunchKernelGGL(convert_vec_kernel<float>, vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs,
+      hipLaunchKernelGGL((convert_vec_kernel<float, VB>), vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs,
                          (const int*)nullptr);
     }
   }
 
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
+    if (vb32)
+      arnoldi_step_t<float2>(Z, j, tol);
+    else
+      arnoldi_step_t<double2>(Z, j, tol);
+  }
+
+  template <typename VB>
+  void arnoldi_step_t(const r3m_store* Z, int j, double tol) {
+    VB* V = reinterpret_cast<VB*>(W.V);
     const int* live = run_slot(j - 1);  // j = 0: set by the cycle start
-    const double2* vj = W.V + (int64_t)j * ut;
+    const VB* vj = V + (int64_t)j * ut;
     // the right-hand sides with work in this step (not idle at its start)
     hipLaunchKernelGGL(live_rhs_kernel, dim3(1), dim3(1024), 0, s, (const int*)W.idle, B, W.rl);
     const int* rl = W.rl;
@@ -1118,7 +1173,7 @@ struct GmresRun {
     const unsigned dgrid = stride_grid((int64_t)maxP * ngrp * B), ugrid = stride_grid(nb_u * B);
     const size_t ulds = (size_t)nvec * sizeof(double2);
     // CGS2, first pass: inner products with the basis, then the update
-    hipLaunchKernelGGL(dots_partials_kernel, dim3(dgrid), dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, nvec, maxP,
+    hipLaunchKernelGGL(dots_partials_kernel<VB>, dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, W.w, W.rv, nvec, maxP,
                        W.dpart, run_slot(j), live, W.idle, rl, B);
     if (long_vec)
       hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP, nvec,
@@ -1129,33 +1184,31 @@ struct GmresRun {
       // the first update also forms the second pass's inner products
       const int maxP2 = (int)fold_blocks(maxN);
 #define R3M_FOLDED(KV)                                                                                             \
-  hipLaunchKernelGGL(gs_update_kernel<KV>, dim3(ugrid), dim3(256), ulds, s, W.V, W.w, W.rv, W.st, h0, h0P, h0n, nvec, \
+  hipLaunchKernelGGL((gs_update_kernel<KV, VB>), dim3(ugrid), dim3(256), ulds, s, V, W.w, W.rv, W.st, h0, h0P, h0n, nvec, \
                      ut, 0, W.npart, maxB, W.H, m, j, 0, live, W.idle, nsub, kDotChunk, W.dpart2, maxP2, rl, B, nb_u)
       if (nvec <= 8)
         R3M_FOLDED(2);
-      else if (nvec <= 16)
-        R3M_FOLDED(4);
       else
-        R3M_FOLDED(8);
+        R3M_FOLDED(4);
 #undef R3M_FOLDED
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart2, maxP2,
                            nvec, W.rv, W.hsum, live, W.idle, 64 * nsub);
-      hipLaunchKernelGGL(gs_update_kernel<0>, dim3(ugrid), dim3(256), ulds, s, W.V, W.w, W.rv, W.st,
+      hipLaunchKernelGGL((gs_update_kernel<0, VB>), dim3(ugrid), dim3(256), ulds, s, V, W.w, W.rv, W.st,
                          long_vec ? (const double2*)W.hsum : (const double2*)W.dpart2, long_vec ? 1 : maxP2,
                          long_vec ? 1 : 0, nvec, ut, 1, W.npart, maxB, W.H, m, j, 1, live, W.idle, nsub, 64 * nsub,
                          (double2*)nullptr, 0, rl, B, nb_u);
     } else {
-      hipLaunchKernelGGL(gs_update_kernel<0>, dim3(ugrid), dim3(256), ulds, s, W.V, W.w, W.rv, W.st, h0, h0P, h0n,
+      hipLaunchKernelGGL((gs_update_kernel<0, VB>), dim3(ugrid), dim3(256), ulds, s, V, W.w, W.rv, W.st, h0, h0P, h0n,
                          nvec, ut, 0, W.npart, maxB, W.H, m, j, 0, live, W.idle, nsub, kDotChunk, (double2*)nullptr, 0,
                          rl, B, nb_u);
       // CGS2, second pass
-      hipLaunchKernelGGL(dots_partials_kernel, dim3(dgrid), dim3(kDotThreads), 0, s, W.V, ut, W.w, W.rv, nvec, maxP,
+      hipLaunchKernelGGL(dots_partials_kernel<VB>, dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, W.w, W.rv, nvec, maxP,
                          W.dpart, (int*)nullptr, live, W.idle, rl, B);
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
                            nvec, W.rv, W.hsum, live, W.idle, kDotChunk);
-      hipLaunchKernelGGL(gs_update_kernel<0>, dim3(ugrid), dim3(256), ulds, s, W.V, W.w, W.rv, W.st, h0, h0P, h0n,
+      hipLaunchKernelGGL((gs_update_kernel<0, VB>), dim3(ugrid), dim3(256), ulds, s, V, W.w, W.rv, W.st, h0, h0P, h0n,
                          nvec, ut, 1, W.npart, maxB, W.H, m, j, 1, live, W.idle, nsub, kDotChunk, (double2*)nullptr, 0,
                          rl, B, nb_u);
     }
@@ -1168,18 +1221,22 @@ struct GmresRun {
     const int nthr = (256 / n_a) * n_a;
     const int64_t nb_n = ceil_div((size_t)maxN, nthr);
     const dim3 ngrid(stride_grid(nb_n * B));
-    const size_t glds = (size_t)(2 * m + 2) * 16 + (size_t)m * 8;
+    const size_t glds0 = (size_t)(2 * m + 2) * 16 + (size_t)((m + 1) / 2) * 16;
+    // complex64 inner solves stage the (per-state) inverses in LDS
+    const int stage = pre && !pu && Z->near_dtype == R3M_C64 && glds0 + (size_t)n_states * n_a * n_a * 8 <= 60 * 1024;
+    const size_t glds = glds0 + (stage ? (size_t)n_states * n_a * n_a * 8 : 0);
     const bool c64 = Z->near_dtype == R3M_C64;
 #define R3M_NORMALIZE(OT, MODE, XS)                                                                                  \
-  hipLaunchKernelGGL((normalize_step_kernel<OT, MODE>), ngrid, dim3(nthr), glds, s, W.w, W.V, W.rv, W.st, np, npB,  \
+  hipLaunchKernelGGL((normalize_step_kernel<OT, MODE, VB>), ngrid, dim3(nthr), glds, s, W.w, V, W.rv, W.st, np, npB,  \
                      npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states, W.soff, \
-                     n_a, n_states, XS, pu, W.idle, rl, B, nb_n)
+                     n_a, n_states, XS, pu, W.idle, rl, B, nb_n, stage)
     if (ilu_r) {
       // V_{j+1}, then the next step's input M^-1 V_{j+1} by the colour solves
       // (W.w, the matvec output, is free once normalised)
       R3M_NORMALIZE(double, 0, (double*)nullptr);
-      launch_ilu_apply(Z, *bd, ilu_r, W.ilu, W.V + (int64_t)(j + 1) * ut, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s,
-                       run_slot(j), wts == nullptr);
+      if constexpr (std::is_same<VB, double2>::value)
+        launch_ilu_apply(Z, *bd, ilu_r, W.ilu, V + (int64_t)(j + 1) * ut, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s,
+                         run_slot(j), wts == nullptr);
     } else if (pre && c64) {
       R3M_NORMALIZE(float, 2, (float*)W.xs);
     } else if (pre) {
@@ -1280,9 +1337,15 @@ struct GmresRun {
       if (!any) break;
       R3M_CHECK_HIP(hipMemcpyAsync(W.st, hst.data(), (size_t)B * sizeof(RhsState), hipMemcpyHostToDevice, s));
       dim3 g0(std::max(ceil_div((size_t)maxN, 256), ceil_div((size_t)m + 1, 256)), B);
-      hipLaunchKernelGGL(cycle_start_kernel, g0, dim3(256), 0, s, W.r, W.V, W.rv, W.st, W.nrm, W.g, m, run_slot(-1),
-                         W.idle);
-      prepare_input(Z, W.V);
+      if (vb32) {
+        hipLaunchKernelGGL(cycle_start_kernel<float2>, g0, dim3(256), 0, s, W.r, (float2*)W.V, W.rv, W.st, W.nrm, W.g,
+                           m, run_slot(-1), W.idle);
+        prepare_input(Z, (const float2*)W.V);
+      } else {
+        hipLaunchKernelGGL(cycle_start_kernel<double2>, g0, dim3(256), 0, s, W.r, W.V, W.rv, W.st, W.nrm, W.g, m,
+                           run_slot(-1), W.idle);
+        prepare_input(Z, (const double2*)W.V);
+      }
       const int steps = std::max(1, std::min(m, max_iter - min_used));
       // Blocks of kCheckEvery steps.  The running count after a block is read
       // back asynchronously while the next block is already queued: the host
@@ -1307,11 +1370,21 @@ struct GmresRun {
       hipLaunchKernelGGL(backsolve_kernel, dim3(B), dim3(256), 0, s, W.H, W.g, W.st, m);
       if (pre) {
         // x += M^{-1} (V y)
-        hipLaunchKernelGGL(combine_basis_kernel, vgrid(), dim3(256), 0, s, W.V, W.g, W.pz, W.rv, W.st, m, ut);
+        if (vb32)
+          hipLaunchKernelGGL(combine_basis_kernel<float2>, vgrid(), dim3(256), 0, s, (const float2*)W.V, W.g, W.pz,
+                             W.rv, W.st, m, ut);
+        else
+          hipLaunchKernelGGL(combine_basis_kernel<double2>, vgrid(), dim3(256), 0, s, (const double2*)W.V, W.g,
+                             W.pz, W.rv, W.st, m, ut);
         precond(W.pz, W.w);
         hipLaunchKernelGGL(add_kernel, vgrid(), dim3(256), 0, s, sol, W.w, W.rv, (const RhsState*)W.st);
       } else {
-        hipLaunchKernelGGL(update_x_kernel, vgrid(), dim3(256), 0, s, W.V, W.g, sol, W.rv, W.st, m, ut);
+        if (vb32)
+          hipLaunchKernelGGL(update_x_kernel<float2>, vgrid(), dim3(256), 0, s, (const float2*)W.V, W.g, sol, W.rv,
+                             W.st, m, ut);
+        else
+          hipLaunchKernelGGL(update_x_kernel<double2>, vgrid(), dim3(256), 0, s, (const double2*)W.V, W.g, sol, W.rv,
+                             W.st, m, ut);
       }
       R3M_CHECK_HIP(hipMemcpyAsync(hst.data(), W.st, (size_t)B * sizeof(RhsState), hipMemcpyDeviceToHost, s));
       R3M_CHECK_HIP(hipStreamSynchronize(s));
@@ -1329,13 +1402,20 @@ struct GmresRun {
   }
 };
 
+// The Krylov basis is stored in complex64 for inner solves on a complex64
+// store with a refinement store (the FP64 residual of the outer loop corrects
+// what FP32 storage loses), without ILU or relaxed weights
+bool basis32(const r3m_store* Z, const r3m_store* Z64, int ilu_r, bool relaxed) {
+  return Z64 && Z->near_dtype == R3M_C64 && ilu_r == 0 && !relaxed;
+}
+
 size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m,
-                   bool per_unit, int ilu_r, bool relaxed) {
+                   bool per_unit, int ilu_r, bool relaxed, bool vb32) {
   const int n_a = Z->n / Z->n_states;
   size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
   if (Z64) mv = std::max(mv, partials_and_x_bytes(bd, Z64, max_groups(bd)));
   return layout_work(nullptr, bd, n_a, per_unit ? (int)bd.total_units : Z->n_states, m, mv, near_lists_bytes(Z, bd),
-                     Z64 ? near_lists_bytes(Z64, bd) : 0, ilu_r ? ilu_factor_bytes(Z, bd, ilu_r, !relaxed) : 0)
+                     Z64 ? near_lists_bytes(Z64, bd) : 0, ilu_r ? ilu_factor_bytes(Z, bd, ilu_r, !relaxed) : 0, vb32)
       .bytes;
 }
 
@@ -1368,9 +1448,10 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z6
     R3M_REQUIRE(opts->restart >= 1 && opts->restart <= 1024, R3M_ERR_INVALID_ARG, "restart out of range");
     if (batch->B == 0) return;
     const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, 0);
+    const int ilu_r = ilu_radius_of(Z, opts);
     out = gmres_bytes(ctx, Z, Z64, bd, opts->restart,
-                      opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI, ilu_radius_of(Z, opts),
-                      opts->relaxed_weights != nullptr);
+                      opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI, ilu_r,
+                      opts->relaxed_weights != nullptr, basis32(Z, Z64, ilu_r, opts->relaxed_weights != nullptr));
   });
   return rc == R3M_OK ? out : 0;
 }
@@ -1406,8 +1487,9 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
                     opts->precond == R3M_PRECOND_BLOCK_ILU,
                 R3M_ERR_INVALID_ARG, "unknown preconditioner");
     const int ilu_r = ilu_radius_of(Z, opts);
+    const bool vb32 = basis32(Z, Z64, ilu_r, opts->relaxed_weights != nullptr);
     const size_t need = gmres_bytes(ctx, Z, refine ? Z64 : nullptr, bd, m, per_unit, ilu_r,
-                                    opts->relaxed_weights != nullptr);
+                                    opts->relaxed_weights != nullptr, vb32);
     R3M_REQUIRE(work_bytes >= need, R3M_ERR_BUFFER_TOO_SMALL, "GMRES workspace too small");
 
     size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
@@ -1450,7 +1532,8 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     run.s = stream;
     run.W = layout_work((char*)work_dev, bd, n_a, per_unit ? (int)bd.total_units : Z->n_states, m, mv,
                         near_lists_bytes(Z, bd), refine ? near_lists_bytes(Z64, bd) : 0,
-                        ilu_r ? ilu_factor_bytes(Z, bd, ilu_r, opts->relaxed_weights == nullptr) : 0);
+                        ilu_r ? ilu_factor_bytes(Z, bd, ilu_r, opts->relaxed_weights == nullptr) : 0, vb32);
+    run.vb32 = vb32;
     run.Zsolve = Z;
     run.ut = (int64_t)bd.total_units * n_a;
     run.maxN = 0;
