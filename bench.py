@@ -57,8 +57,8 @@ PRECOND_NAMES = {0: "unpreconditioned", 1: "block-Jacobi", 2: "block-ILU(0) r={r
 PROFILED_TRAFFIC = {
     # 2-bit 32x32 compressed matvec (convert + far_near + reduce) at 128 groups
     "c1_matvec": {"bytes": 403.5e6, "groups": 128},
-    # 1,536-RHS spectral matvec (four transform passes + matrix-core product)
-    "c2_matvec": None,
+    # frequency product of the 1,536-RHS spectral matvec (spec_product_mfma_kernel)
+    "c2_product": {"bytes": 78.93e9},
 }
 
 
@@ -101,6 +101,37 @@ def spectral_cost(n, D, B):
     byt = n * n * G2 * 8
     flops = 8.0 * n * n * G2 * B + 4 * 5.0 * G2 * math.log2(G) * n * B
     return byt, flops, G
+
+
+def product_cost(n, D, B):
+    """Algorithmic flops and HBM bytes of one frequency product over the batch
+    (complex64 spectra): 8 n^2 flops per frequency per RHS; the transformed
+    input grids read once, the output grids written once, the spectra read
+    once."""
+    G = 1
+    while G < 2 * D + 1:
+        G *= 2
+    G2 = G * G
+    return 8.0 * n * n * G2 * B, (2 * B * n * G2 + n * n * G2) * 8
+
+
+def timed_product(r3m, ctx, store, batch, x, reps):
+    """Seconds per r3m_spectral_product call (the frequency product alone, one
+    kernel launch) on the grids of a matvec of x, HIP events on the stream the
+    call launches on (torch's current stream)."""
+    import torch
+    y = torch.zeros_like(x)
+    work = torch.empty(r3m.matvec_work_bytes(ctx, store, batch, r3m.C64), dtype=torch.uint8, device=x.device)
+    r3m.r3m_retrieved_matvec(ctx, store, batch, r3m.C64, x, y, work)
+    r3m.r3m_spectral_product(ctx, store, batch, work)  # warm
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        r3m.r3m_spectral_product(ctx, store, batch, work)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / reps
 
 
 def timed_matvec(r3m, ctx, store, batch, x, vt, reps):
@@ -196,11 +227,16 @@ def headline_c2(ctx, args):
     ok = sum(int((e <= RCS_TARGET).sum()) for e in errs)
     err_all = np.concatenate(errs)
     rep = reps[-1]
-    # the dominant operation of a step: the spectral matvec over the whole batch
+    # the dominant kernel of a step: the frequency product over the whole batch
+    # (one launch; timed alone), and the whole spectral matvec around it
     xm = b.to(torch.complex64)
+    del work
+    torch.cuda.empty_cache()
     mv = timed_matvec(r3m, ctx, S["s64"], batch, xm, r3m.C64, 5)
+    pr = timed_product(r3m, ctx, S["s64"], batch, xm, 10)
     byt, flops, G = spectral_cost(S["s64"].n, 63, B)
-    del work, xm
+    pflops, pbytes = product_cost(S["s64"].n, 63, B)
+    del xm
     torch.cuda.empty_cache()
     iters = np.array([r[0] for r in rep])
     by_size = {int(L): {"rhs": int((S["sizes"] == L).sum()),
@@ -208,7 +244,7 @@ def headline_c2(ctx, args):
                         "inner_iters_mean": float(iters[S["sizes"] == L].mean()),
                         "inner_iters_max": int(iters[S["sizes"] == L].max())}
                for L in (32, 48, 64)}
-    traffic = PROFILED_TRAFFIC["c2_matvec"]
+    traffic = PROFILED_TRAFFIC["c2_product"]
     out = {
         "value": ok / dt,
         "ms_per_step": dt / args.steps * 1e3,
@@ -222,13 +258,17 @@ def headline_c2(ctx, args):
         "by_size": by_size,
         "reference": {"refine_tol": P["ref_refine_tol"], "solve_s": t_ref, "converged": ref_ok,
                       "max_rel_residual": max(r[2] for r in rep_ref)},
-        "roofline": {"bound": "mfma", "achieved": flops / mv / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": flops / mv / 1e12 / PEAK_FP32_TFLOPS,
+        "roofline": {"bound": "mfma", "achieved": pflops / pr / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": pflops / pr / 1e12 / PEAK_FP32_TFLOPS,
                      "traffic": traffic["bytes"] if traffic else None,
-                     "kernel": "spectral retrieved matvec over the 1,536-RHS batch (four fft_kernel passes + "
-                               "spec_product_mfma_kernel, FP32 matrix cores), timed together",
-                     "matvec_ms": mv * 1e3, "algorithmic_flops_per_launch": flops,
-                     "algorithmic_bytes_per_launch": byt, "grid": [G, G]},
+                     "kernel": "spec_product_mfma_kernel: the per-frequency product of the spectral matvec over "
+                               "the 1,536-RHS batch (FP32 matrix cores), one launch timed alone",
+                     "kernel_ms": pr * 1e3, "algorithmic_flops_per_launch": pflops,
+                     "algorithmic_bytes_per_launch": pbytes, "hbm_gbs_algorithmic": pbytes / pr / 1e9,
+                     "grid": [G, G],
+                     "matvec": {"ms": mv * 1e3, "tflops_algorithmic": flops / mv / 1e12,
+                                "kernels": "fused forward transform + frequency product + fused inverse transform",
+                                "algorithmic_flops": flops, "spectra_bytes": byt}},
         "setup_s": S["setup_s"],
         "_S": S,
         "_rep": rep,
@@ -251,10 +291,20 @@ def matvec_only(ctx, args):
         r3m.r3m_retrieved_matvec(ctx, S["s64"], batch, r3m.C64, x, y, work)
     torch.cuda.synchronize()
     mv = timed_matvec(r3m, ctx, S["s64"], batch, x, r3m.C64, args.steps)
+    del work
+    pr = timed_product(r3m, ctx, S["s64"], batch, x, args.steps)
     byt, flops, G = spectral_cost(S["s64"].n, 63, batch.B)
-    return {"matvec_ms": mv * 1e3, "rhs": batch.B, "grid": [G, G], "steps": args.steps,
+    pflops, pbytes = product_cost(S["s64"].n, 63, batch.B)
+    # a plain device copy of known size: the reference for the HBM counters
+    src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return {"matvec_ms": mv * 1e3, "product_ms": pr * 1e3, "product_tflops": pflops / pr / 1e12,
+            "rhs": batch.B, "grid": [G, G], "steps": args.steps,
             "plan": r3m.decode_plan(r3m.matvec_plan(ctx, S["s64"], batch)),
-            "algorithmic_flops_per_call": flops}
+            "algorithmic_flops_per_call": flops, "product_flops": pflops, "product_bytes": pbytes,
+            "calibration_copy_bytes": 256 << 20}
 
 
 def c2_compressed(ctx, args):

@@ -267,7 +267,9 @@ int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batc
  * shape (0: vector units; 1..5: matrix cores with {frequencies per wave,
  * columns per staged chunk} = {1,4}, {2,4}, {2,8}, {4,4}, {1,8}; complex64
  * spectra only), in bits 4-11 the count of live 16-RHS tiles from which
- * the matrix-core product orders its workgroups RHS tile first, and
+ * the matrix-core product orders its workgroups RHS tile first, in bits
+ * 13-14 log2 of the groups of frequency tiles the eight XCDs split into in
+ * that order (0: each XCD sees every frequency tile), and
  * R3M_PLAN_SPEC_TWO_PASS when the retrieval transforms run as separate row
  * and column passes through HBM although the fused 2-D transform (complex64
  * grids of at most 16,384 points, one grid per workgroup in LDS) applies.
@@ -276,6 +278,16 @@ int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batc
  * same bits; the vector-unit shape and the transform form differ by FP32
  * rounding order only.  Returns the plan (> 0), 0 for an empty batch, or a
  * negative r3m_status. */
+/* The per-frequency product step of the spectral matvec alone (the
+ * block-Toeplitz FFT form of eq. (6): Y^(k) = Z^(k) X^(k) for every spatial
+ * frequency k of the transform grid), with the (store, batch) plan: it reads
+ * the transformed input grids that the last r3m_retrieved_matvec with the
+ * same store, batch and workspace left in work_dev and overwrites the
+ * workspace's output grids (the result vector is not touched).  Spectral
+ * stores only.  For measuring the dominant step of the product on its own. */
+int r3m_spectral_product(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, void* work_dev,
+                         size_t work_bytes, hipStream_t stream);
+
 #define R3M_PLAN_SPEC_TWO_PASS (1 << 12)
 #define R3M_PLAN_MFMA_FAR (1 << 16)
 #define R3M_PLAN_SPECTRAL (1 << 17)

@@ -1908,6 +1908,8 @@ int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
         best = other;
       }
     }
+    // (the XCD groupings of the frequency tiles, bits 13-14, are left at 0:
+    // measured no faster on the 1,536-RHS batch, slower with more groups)
     // the transform form: two passes through HBM against the fused 2-D transform
     if (spectral_fused_transforms(Z) && time_plan(best | kPlanSpecTwoPass) < 0.97f * best_ms)
       best |= kPlanSpecTwoPass;
@@ -2032,6 +2034,23 @@ extern "C" int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_
     out = store_is_spectral(Z) ? 1 : plan_groups(ctx, Z, get_batch(ctx, batch, kBW, kBH, 0)) & kPlanGroups;
   });
   return rc == R3M_OK ? out : rc;
+}
+
+extern "C" int r3m_spectral_product(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, void* work_dev,
+                                    size_t work_bytes, hipStream_t stream) {
+  return guarded(ctx, [&] {
+    R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
+    validate_store(Z);
+    R3M_REQUIRE(store_is_spectral(Z), R3M_ERR_UNSUPPORTED, "the frequency product needs a spectral store");
+    validate_batch(batch, Z->Dx, Z->Dy);
+    if (batch->B == 0) return;
+    R3M_CHECK_HIP(hipSetDevice(ctx->device));
+    const BatchDesc& bd = get_batch(ctx, batch, kBW, kBH, stream);
+    R3M_REQUIRE(work_dev, R3M_ERR_INVALID_ARG, "work is NULL");
+    R3M_REQUIRE(work_bytes >= matvec_partial_bytes(bd, Z, max_groups(bd)), R3M_ERR_BUFFER_TOO_SMALL,
+                "matvec workspace too small");
+    launch_spectral_product(Z, bd, work_dev, plan_groups(ctx, Z, bd), stream);
+  });
 }
 
 extern "C" int32_t r3m_matvec_plan(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch) {

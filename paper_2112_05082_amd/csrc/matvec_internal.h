@@ -10,7 +10,8 @@ void validate_store(const r3m_store* Z);
 // kPlanMfmaFar for the matrix-core far kernel.  Spectral stores: kPlanSpectral,
 // the frequency-product shape in bits 0-3 (kSpecShapes) and in bits 4-11 the
 // count of live 16-RHS tiles from which the matrix-core product orders its
-// workgroups RHS tile first, and kPlanSpecTwoPass for the row and column
+// workgroups RHS tile first, in bits 13-14 how the XCDs share the frequency
+// tiles in that order, and kPlanSpecTwoPass for the row and column
 // transform passes through HBM where the fused 2-D transform would apply
 constexpr int kPlanGroups = 0xffff;
 constexpr int kPlanMfmaFar = 1 << 16;
@@ -31,6 +32,9 @@ constexpr int kSpecRhsFirst = 8;  // default ordering threshold
 inline int spec_plan(int shape, int rhs_first) { return kPlanSpectral | shape | rhs_first << 4; }
 inline int spec_shape(int plan) { return plan & 15; }
 inline int spec_rhs_first(int plan) { return (plan >> 4) & 255; }
+// bits 13-14: log2 of the frequency-tile-pair groups the XCDs form in the
+// RHS-first order (0: every XCD sees every frequency tile)
+inline int spec_kt_groups(int plan) { return (plan >> 13) & 3; }
 // the untuned plan: matrix cores for complex64 spectra once a 16-wide RHS
 // tile is mostly full, the vector units otherwise
 int spectral_default_plan(const r3m_store* Z, int B);
@@ -85,6 +89,9 @@ void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* sta
 void launch_spectral_ex(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,
                         const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
                         const double* wts, bool tr, const int* idle = nullptr, int plan = 0);
+// the per-frequency product alone, on the transformed input grids in work
+// (spectral_work_bytes layout) into the output grids there
+void launch_spectral_product(const r3m_store* Z, const BatchDesc& bd, void* work, int plan, hipStream_t s);
 // times the frequency-product shapes once per (store, batch) on x (x_type) into
 // y (y_type) and keeps the fastest plan (the same map as tuned_groups)
 int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, r3m_dtype x_type,

@@ -808,7 +808,8 @@ __global__ void __launch_bounds__(256)
 spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __restrict__ Xh, C2<float>* __restrict__ Yh,
                          int n, int64_t K, int B, int n_mg, int n_bt, int64_t n_tiles, int lgGx, int lgGy,
                          const int* __restrict__ live, const int* __restrict__ idle,
-                         const int* __restrict__ tile_list, const int* __restrict__ n_live, int rhs_first) {
+                         const int* __restrict__ tile_list, const int* __restrict__ n_live, int rhs_first,
+                         int lkg) {
   if (live && *live == 0) return;
   typedef float v4 __attribute__((ext_vector_type(4)));
   constexpr int PK = 4 * KPW;                   // frequencies per workgroup
@@ -837,12 +838,27 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
     kt = (r1 / n_mg) * 2 + kh;
     bt = tile_list ? tile_list[bi] : bi;
   } else {
-    const int64_t id = blockIdx.x;
-    if (id >= n_tiles * n_mg * nl) return;
-    const int bi = (int)(id % nl);
-    const int64_t r1 = id / nl;
+    // RHS tile first: the eight XCDs (workgroup id mod 8) form KG = 2^lkg
+    // groups of frequency-tile pairs times 8 / KG groups of RHS tiles; an
+    // XCD runs its pairs in turn and, within a pair, its RHS tiles with the
+    // pair's two halves adjacent, so that the spectra of a few frequency
+    // tiles stay in its L2 while the RHS tiles pass (KG = 1: every XCD sees
+    // every frequency tile, one RHS tile in eight)
+    const int KG = 1 << lkg, BG = 8 >> lkg;
+    const int x = (int)(blockIdx.x & 7), kg = x & (KG - 1), bg = x >> lkg;
+    const int nb_x = (nl - bg + BG - 1) / BG;  // RHS tiles of this XCD
+    const int64_t n_pairs = (n_tiles + 1) / 2, np_x = (n_pairs - kg + KG - 1) / KG;
+    if (nb_x <= 0 || np_x <= 0) return;
+    const int64_t l = blockIdx.x >> 3;
+    const int kh = (int)(l & 1);
+    const int64_t r0 = l >> 1;
+    const int bj = (int)(r0 % nb_x);
+    const int64_t r1 = r0 / nb_x;
     mg = (int)(r1 % n_mg);
-    kt = r1 / n_mg;
+    const int64_t pj = r1 / n_mg;
+    if (pj >= np_x) return;
+    kt = (pj * KG + kg) * 2 + kh;
+    const int bi = bg + bj * BG;
     bt = tile_list ? tile_list[bi] : bi;
   }
   if (kt >= n_tiles) return;  // n_tiles: frequency tiles
@@ -981,13 +997,15 @@ void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2
 // both orders.
 template <int KPW, int PC>
 void launch_product_mfma(const C2<float>* Zh, const C2<float>* X, C2<float>* Y, int n, int64_t G2, int B, bool tr,
-                         int lgGx, int lgGy, hipStream_t s, const int* live, const int* idle, int* tl, int rf) {
+                         int lgGx, int lgGy, hipStream_t s, const int* live, const int* idle, int* tl, int rf,
+                         int lkg) {
   constexpr int PK = 4 * KPW;
   const int n_mg = (n + kPM - 1) / kPM, n_bt = (B + kPB - 1) / kPB;
   const int64_t n_kt = (G2 + PK - 1) / PK;
   const bool use_list = idle && tl && n_bt >= rf;
   const int64_t nwg_c = ((n_kt + 1) / 2 * 2 * n_mg * (use_list ? std::min(rf - 1, n_bt) : n_bt) + 7) / 8 * 8;
-  const int64_t nwg_r = (n_kt * n_mg * n_bt + 7) / 8 * 8;
+  const int KG = 1 << lkg, BG = 8 >> lkg;
+  const int64_t nwg_r = 8 * (((n_kt + 1) / 2 + KG - 1) / KG) * n_mg * ((n_bt + BG - 1) / BG) * 2;
   const int64_t nwg = use_list ? std::max(nwg_c, nwg_r) : n_bt < rf ? nwg_c : nwg_r;
   const int* list = use_list ? tl : nullptr;
   const int* cnt = use_list ? tl + n_bt : nullptr;
@@ -997,10 +1015,10 @@ void launch_product_mfma(const C2<float>* Zh, const C2<float>* X, C2<float>* Y, 
   }
   if (tr)
     hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, true>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y, n,
-                       G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf);
+                       G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf, lkg);
   else
     hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, false>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y,
-                       n, G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf);
+                       n, G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf, lkg);
   R3M_CHECK_HIP(hipGetLastError());
 }
 
@@ -1017,13 +1035,13 @@ void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B
   if constexpr (sizeof(T) == 4) {
     const C2<float>*zf = Zh, *xf = X;
     C2<float>* yf = Y;
-    const int rf = spec_rhs_first(plan);
+    const int rf = spec_rhs_first(plan), lkg = spec_kt_groups(plan);
     switch (spec_shape(plan)) {
-      case 1: return launch_product_mfma<1, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
-      case 2: return launch_product_mfma<2, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
-      case 3: return launch_product_mfma<2, 8>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
-      case 4: return launch_product_mfma<4, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
-      case 5: return launch_product_mfma<1, 8>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf);
+      case 1: return launch_product_mfma<1, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 2: return launch_product_mfma<2, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 3: return launch_product_mfma<2, 8>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 4: return launch_product_mfma<4, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 5: return launch_product_mfma<1, 8>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
       default: break;
     }
   }
@@ -1235,7 +1253,7 @@ int spectral_default_plan(const r3m_store* Z, int B) {
 
 bool spectral_plan_valid(const r3m_store* Z, int plan) {
   const int shape = spec_shape(plan), rf = spec_rhs_first(plan);
-  return (plan & ~(kPlanSpectral | kPlanSpecTwoPass | 0xfff)) == 0 && (plan & kPlanSpectral) &&
+  return (plan & ~(kPlanSpectral | kPlanSpecTwoPass | (3 << 13) | 0xfff)) == 0 && (plan & kPlanSpectral) &&
          shape < kSpecShapeCount && rf >= 1 && (shape == 0 || Z->far_dtype == R3M_SPEC_C64);
 }
 
@@ -1245,6 +1263,23 @@ bool spectral_fused_transforms(const r3m_store* Z) {
 }
 
 size_t relaxed_work_bytes(const BatchDesc& bd, const r3m_store* Z) { return spectral_work_bytes(bd, Z); }
+
+void launch_spectral_product(const r3m_store* Z, const BatchDesc& bd, void* work, int plan, hipStream_t s) {
+  const int lgGx = ilog2(next_pow2(2 * Z->Dx + 1)), lgGy = ilog2(next_pow2(2 * Z->Dy + 1));
+  const int64_t G2 = (int64_t)1 << (lgGx + lgGy);
+  if (!(plan & kPlanSpectral)) plan = spectral_default_plan(Z, bd.B);
+  int* tl = (int*)((char*)work + spectral_list_offset(bd, Z));
+  const size_t grid = (size_t)bd.B * Z->n * G2;
+  if (Z->far_dtype == R3M_SPEC_C128) {
+    C2<double>* X = (C2<double>*)work;
+    product<double>((const C2<double>*)Z->far, X, X + grid, Z->n, G2, bd.B, false, lgGx, lgGy, s, nullptr, nullptr,
+                    tl, plan);
+  } else {
+    C2<float>* X = (C2<float>*)work;
+    product<float>((const C2<float>*)Z->far, X, X + grid, Z->n, G2, bd.B, false, lgGx, lgGy, s, nullptr, nullptr, tl,
+                   plan);
+  }
+}
 
 }  // namespace r3m
 

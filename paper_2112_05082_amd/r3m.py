@@ -34,7 +34,7 @@ EXPORTED = (
     "r3m_spectral_bytes", "r3m_build_spectral", "r3m_relaxed_work_bytes", "r3m_relaxed_matvec",
     "r3m_relaxed_gradient_work_bytes", "r3m_relaxed_gradient", "r3m_relaxed_rhs", "r3m_relaxed_objective",
     "r3m_matvec_work_bytes", "r3m_retrieved_matvec", "r3m_matvec_groups", "r3m_matvec_plan",
-    "r3m_matvec_set_plan",
+    "r3m_matvec_set_plan", "r3m_spectral_product",
     "r3m_static_scratch_bytes", "r3m_retrieved_matvec_static",
     "r3m_gmres_work_bytes", "r3m_gmres_solve", "r3m_ilu_bytes", "r3m_ilu_factor", "r3m_ilu_apply",
     "r3m_plane_wave_rhs", "r3m_rcs",
@@ -133,6 +133,7 @@ def load(path: str = LIB_PATH):
         "r3m_matvec_groups": (i32, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
         "r3m_matvec_plan": (i32, [vp, C.POINTER(StoreC), C.POINTER(BatchC)]),
         "r3m_matvec_set_plan": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), i32]),
+        "r3m_spectral_product": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), vp, sz, vp]),
         "r3m_static_scratch_bytes": (sz, []),
         "r3m_retrieved_matvec_static": (C.c_int, [vp, C.POINTER(StoreC), C.POINTER(BatchC), C.c_int, vp, vp, vp]),
         "r3m_gmres_work_bytes": (sz, [vp, C.POINTER(StoreC), C.POINTER(StoreC), C.POINTER(BatchC),
@@ -559,8 +560,9 @@ PLAN_SPEC_TWO_PASS, PLAN_MFMA_FAR, PLAN_SPECTRAL = 1 << 12, 1 << 16, 1 << 17
 SPEC_SHAPES = ((0, 0), (1, 4), (2, 4), (2, 8), (4, 4), (1, 8))
 
 
-def spec_plan(shape: int, rhs_first: int = 8, two_pass: bool = False) -> int:
-    return PLAN_SPECTRAL | shape | rhs_first << 4 | (PLAN_SPEC_TWO_PASS if two_pass else 0)
+def spec_plan(shape: int, rhs_first: int = 8, two_pass: bool = False, kt_groups: int = 0) -> int:
+    """kt_groups: log2 of the frequency-tile groups the XCDs form in the RHS-first order."""
+    return PLAN_SPECTRAL | shape | rhs_first << 4 | (PLAN_SPEC_TWO_PASS if two_pass else 0) | kt_groups << 13
 
 
 def matvec_plan(ctx, store: Store, batch: Batch) -> int:
@@ -577,8 +579,15 @@ def decode_plan(plan: int) -> dict:
         k = plan & 15
         return {"kind": "spectral", "shape": k, "mfma": k != 0, "kpw": SPEC_SHAPES[k][0] if k < len(SPEC_SHAPES) else None,
                 "pc": SPEC_SHAPES[k][1] if k < len(SPEC_SHAPES) else None, "rhs_first": (plan >> 4) & 255,
-                "two_pass": bool(plan & PLAN_SPEC_TWO_PASS)}
+                "two_pass": bool(plan & PLAN_SPEC_TWO_PASS), "kt_groups": (plan >> 13) & 3}
     return {"kind": "compressed", "groups": plan & 0xFFFF, "mfma_far": bool(plan & PLAN_MFMA_FAR)}
+
+
+def r3m_spectral_product(ctx, store: Store, batch: Batch, work, stream=None) -> None:
+    """The frequency product alone on the grids a preceding matvec left in `work`."""
+    sc = store.c()
+    _check(load().r3m_spectral_product(ctx.handle, C.byref(sc), C.byref(batch.cs), C.c_void_p(work.data_ptr()),
+                                       work.numel() * work.element_size(), _stream(stream)), ctx.handle)
 
 
 def matvec_set_plan(ctx, store: Store, batch: Batch, plan: int) -> None:

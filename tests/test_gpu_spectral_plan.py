@@ -61,9 +61,9 @@ def test_matvec_identical_across_shapes(lib):
     assert info["kind"] == "spectral" and 0 <= info["shape"] < len(r3m.SPEC_SHAPES) and info["rhs_first"] >= 1
     ref = None
     for shape in MFMA_SHAPES:
-        for rf in (1, 2, 8, 255):
-            r3m.matvec_set_plan(ctx, spec, batch, r3m.spec_plan(shape, rf))
-            assert r3m.matvec_plan(ctx, spec, batch) == r3m.spec_plan(shape, rf)
+        for rf, lkg in ((1, 0), (2, 0), (8, 0), (255, 0), (1, 1), (1, 2), (1, 3)):
+            r3m.matvec_set_plan(ctx, spec, batch, r3m.spec_plan(shape, rf, kt_groups=lkg))
+            assert r3m.matvec_plan(ctx, spec, batch) == r3m.spec_plan(shape, rf, kt_groups=lkg)
             y = mv()
             if ref is None:
                 ref = y
@@ -109,10 +109,10 @@ def test_solve_identical_across_shapes(lib):
     x0, it0 = solve(r3m.spec_plan(2, 8))
     assert all(it0[r] == 0 for r in range(16, 32)) and len(set(it0)) >= 4, it0
     for shape in MFMA_SHAPES:
-        for rf in (1, 2, 255):
-            x, its = solve(r3m.spec_plan(shape, rf))
-            assert its == it0, (shape, rf)
-            assert torch.equal(x, x0), (shape, rf)
+        for rf, lkg in ((1, 0), (2, 0), (255, 0), (1, 2), (2, 3)):
+            x, its = solve(r3m.spec_plan(shape, rf, kt_groups=lkg))
+            assert its == it0, (shape, rf, lkg)
+            assert torch.equal(x, x0), (shape, rf, lkg)
     xv, itv = solve(r3m.spec_plan(0, 8))
     d = float((xv - x0).abs().max()) / float(x0.abs().max())
     print(f"solve, 48 RHS: iterations {min(it0)}..{max(it0)}; vector-unit product: iteration difference "
@@ -145,7 +145,7 @@ def test_plan_validation(lib):
     batch2 = r3m.Batch.from_codebooks([cb.uniform(L, 2, 2)], [L], DEV)
     assert r3m.decode_plan(r3m.matvec_plan(ctx, s64, batch2)) == {
         "kind": "spectral", "shape": 0, "mfma": False, "kpw": 0, "pc": 0, "rhs_first": 8,
-        "two_pass": False}
+        "two_pass": False, "kt_groups": 0}
 
 
 @pytest.mark.parametrize("L", [2, 4, 8, 12, 24, 40])
