@@ -56,9 +56,9 @@ PRECOND_NAMES = {0: "unpreconditioned", 1: "block-Jacobi", 2: "block-ILU(0) r={r
 # for the kernels as they were when taken.
 PROFILED_TRAFFIC = {
     # 2-bit 32x32 compressed matvec (convert + far_near + reduce) at 128 groups
-    "c1_matvec": {"bytes": 403.5e6, "groups": 128},
+    "c1_matvec": {"bytes": 403.7e6, "groups": 128},
     # frequency product of the 1,536-RHS spectral matvec (spec_product_mfma_kernel)
-    "c2_product": {"bytes": 78.93e9},
+    "c2_product": {"bytes": 59.95e9},
 }
 
 
@@ -76,6 +76,9 @@ def parse():
     p.add_argument("--matvec-only", action="store_true",
                    help="time only the batched spectral matvec (W warmup calls, the first tunes; K timed): the "
                         "command profiler summaries are taken on")
+    p.add_argument("--only", default="",
+                   help="comma-separated secondary legs to run alone (no headline, no CPU baseline), e.g. "
+                        "c1_2bit_32x32,large_128x128: the commands profiler summaries of those legs are taken on")
     p.add_argument("--c1-precond", type=int, default=2,
                    help="2-bit 32x32 leg: 0 none, 1 block-Jacobi, 2 near-field block ILU(0)")
     return p.parse_args()
@@ -843,6 +846,22 @@ def main():
 
     from paper_2112_05082_amd import r3m
     ctx = r3m.Context(0)
+    legs = {"c1_2bit_32x32": c1_leg, "c0_plain_6x6": c0_leg, "spectral_32x32": spectral_32x32_leg,
+            "large_128x128": large_leg, "relaxed_32x32": relaxed_leg, "precond_sweep_16x16": sweep_leg}
+    if args.only:
+        out = {}
+        for name in args.only.split(","):
+            t0 = time.perf_counter()
+            out[name] = legs[name](ctx, args)
+            out[name]["leg_s"] = time.perf_counter() - t0
+            print(f"[bench] {name} done in {out[name]['leg_s']:.1f} s", file=sys.stderr, flush=True)
+        # a plain device copy of known size: the reference for the HBM counters
+        src = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        ctx.close()
+        print(json.dumps(out), flush=True)
+        return
     if args.matvec_only:
         out = matvec_only(ctx, args)
         ctx.close()
