@@ -94,8 +94,9 @@ def spectral_cost(n, D, B):
     """Algorithmic bytes and flops of one spectral matvec (complex64 spectra):
     bytes = the spectra read once (the compact vectors are small beside them);
     flops of the per-frequency products (8 n^2 per frequency per RHS) and of
-    the four transform passes (5 G log2 G per line, real flops of a radix-2
-    count)."""
+    the forward and inverse 2-D transforms (2 G lines of 5 G log2 G each per
+    grid, real flops of a radix-2 count, whether the transform runs fused or
+    as row and column passes)."""
     import math
     G = 1
     while G < 2 * D + 1:
@@ -884,7 +885,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 spectra / f32 accumulate / f64 krylov + refinement",
+        "dtype": "f32 (c64 spectra and inner Krylov basis, f32 products) / f64 Krylov arithmetic and refinement residual",
         "data": "synthetic (seeded 1-bit codebooks: Bernoulli, checkerboard, stripes; PEC patch units)",
         "config": {"workload": f"batched 1-bit {3 * args.n_per_size} codebooks (32x32/48x48/64x64) x 4 angles = "
                                f"{12 * args.n_per_size} RHS, one global matrix for 64x64 as complex64 block spectra, "

@@ -278,16 +278,6 @@ int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batc
  * same bits; the vector-unit shape and the transform form differ by FP32
  * rounding order only.  Returns the plan (> 0), 0 for an empty batch, or a
  * negative r3m_status. */
-/* The per-frequency product step of the spectral matvec alone (the
- * block-Toeplitz FFT form of eq. (6): Y^(k) = Z^(k) X^(k) for every spatial
- * frequency k of the transform grid), with the (store, batch) plan: it reads
- * the transformed input grids that the last r3m_retrieved_matvec with the
- * same store, batch and workspace left in work_dev and overwrites the
- * workspace's output grids (the result vector is not touched).  Spectral
- * stores only.  For measuring the dominant step of the product on its own. */
-int r3m_spectral_product(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, void* work_dev,
-                         size_t work_bytes, hipStream_t stream);
-
 #define R3M_PLAN_SPEC_TWO_PASS (1 << 12)
 #define R3M_PLAN_MFMA_FAR (1 << 16)
 #define R3M_PLAN_SPECTRAL (1 << 17)
@@ -300,6 +290,16 @@ int32_t r3m_matvec_plan(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch)
  * the matrix-core far kernel does not take, a group count outside [1, the
  * workspace's maximum], unknown bits).  An empty batch is a no-op. */
 int r3m_matvec_set_plan(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, int32_t plan);
+
+/* The per-frequency product step of the spectral matvec alone (the
+ * block-Toeplitz FFT form of eq. (6): Y^(k) = Z^(k) X^(k) for every spatial
+ * frequency k of the transform grid), with the (store, batch) plan: it reads
+ * the transformed input grids that the last r3m_retrieved_matvec with the
+ * same store, batch and workspace left in work_dev and overwrites the
+ * workspace's output grids (the result vector is not touched).  Spectral
+ * stores only.  For measuring the dominant step of the product on its own. */
+int r3m_spectral_product(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batch, void* work_dev,
+                         size_t work_bytes, hipStream_t stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -89,6 +89,9 @@ __global__ void __launch_bounds__(1024) live_rhs_kernel(const int* __restrict__ 
   if (t == 1023) rl[B] = cnt[1023];
 }
 
+// batches from which the Arnoldi steps build the list of live right-hand sides
+constexpr int kListMinRhs = 64;
+
 // grid of a strided Krylov kernel: every item when there are few, else enough
 // workgroups to fill the chip several times over
 inline unsigned stride_grid(int64_t items) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(items, 8192)); }
@@ -1152,9 +1155,13 @@ struct GmresRun {
     VB* V = reinterpret_cast<VB*>(W.V);
     const int* live = run_slot(j - 1);  // j = 0: set by the cycle start
     const VB* vj = V + (int64_t)j * ut;
-    // the right-hand sides with work in this step (not idle at its start)
-    hipLaunchKernelGGL(live_rhs_kernel, dim3(1), dim3(1024), 0, s, (const int*)W.idle, B, W.rl);
-    const int* rl = W.rl;
+    // the right-hand sides with work in this step (not idle at its start);
+    // narrow batches skip the list (their grids are small either way)
+    const int* rl = nullptr;
+    if (B >= kListMinRhs) {
+      hipLaunchKernelGGL(live_rhs_kernel, dim3(1), dim3(1024), 0, s, (const int*)W.idle, B, W.rl);
+      rl = W.rl;
+    }
     if (wts)
       launch_spectral_ex(Z, *bd, batch->states, input_in_xs(Z) ? Z->near_dtype : R3M_C128,
                          input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, R3M_C128, W.w, W.mv_partial, s, live,
