@@ -34,7 +34,7 @@ def macro_mesh(cu, cell=(0, 0)) -> RwgMesh:
     """The extended macro unit placed at lattice cell (ix, iy)."""
     p = cu.period[0]
     ix, iy = cell
-    return rwg_mesh(cu.vert, cu.tri, cu.rwg, (ix * p, iy * p, 0.0), (ix, iy), cu.tri_cell)
+    return rwg_mesh(cu.vert, cu.tri, cu.rwg, (ix * p, iy * p, 0.0), (ix, iy), cu.tri_cell, cu.state_off)
 
 
 def displacement_blocks(cu, Dx: int, Dy: int, k: float, extract: int = 1) -> np.ndarray:

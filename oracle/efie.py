@@ -16,6 +16,18 @@ are within a Chebyshev radius `extract` of each other, G is split into
 ``singular``) plus the smooth remainder (exp(-j k R) - 1)/(4 pi R), whose
 limit at R = 0 is -j k/(4 pi).
 
+Overlapping coexistent meshes (Sec. III-A: the patches of different coding
+states of one macro unit lie in one plane and overlap) make the closed-form
+inner integral, seen as a function of the observation point, lose its
+smoothness along the source triangle's edges, which then cross the interior
+of the observer triangle.  For pairs of triangles of different coding states
+in the same cell the outer integral therefore uses the composite rule: the
+observer triangle split by three levels of midpoint subdivision into 64
+congruent triangles, the 7-point rule on each (448 points).  Triangles of
+the same state share whole edges (the usual case of the plain rule), and
+one-hot retrieval never reads the cross-state entries; the relaxed codebook
+of the differentiation path does.
+
 The functions here take explicit geometry (triangles with unit coordinates),
 so the same code builds both the direct active-only system Z_k of a codebook
 (explicit retrieval, Sec. III-A) and the macro-unit displacement blocks Z(d).
@@ -41,6 +53,9 @@ class RwgMesh:
     rwg_tri : [N,2]   (T+, T-) triangle ids
     rwg_free: [N,2]   local index (0..2) of the free vertex in T+ and in T-
     rwg_len : [N]     edge length
+    tri_state: [T] or None  coding state whose patch holds the triangle, -1
+              for triangles of bases shared by every state (None: no
+              coexistent states, e.g. a physical array)
     """
 
     tri_xyz: np.ndarray
@@ -48,17 +63,20 @@ class RwgMesh:
     rwg_tri: np.ndarray
     rwg_free: np.ndarray
     rwg_len: np.ndarray
+    tri_state: np.ndarray | None = None
 
     @property
     def n(self) -> int:
         return len(self.rwg_len)
 
 
-def rwg_mesh(vert, tri, rwg, offset=(0.0, 0.0, 0.0), unit=(0, 0), tri_cell=None) -> RwgMesh:
+def rwg_mesh(vert, tri, rwg, offset=(0.0, 0.0, 0.0), unit=(0, 0), tri_cell=None, state_off=None) -> RwgMesh:
     """Build an RwgMesh from a connectivity table, translated by `offset`.
 
     Every triangle is in cell `unit`, shifted by tri_cell[t] when given (the
-    neighbour-cell halves of bridging bases, Sec. III-B)."""
+    neighbour-cell halves of bridging bases, Sec. III-B).  state_off (RWG
+    ranges of the coding states of a macro unit, bases after the last range
+    shared) gives each triangle the state of the bases it carries."""
     vert = np.asarray(vert, dtype=np.float64) + np.asarray(offset, dtype=np.float64)
     tri = np.asarray(tri)
     rwg = np.asarray(rwg)
@@ -74,7 +92,16 @@ def rwg_mesh(vert, tri, rwg, offset=(0.0, 0.0, 0.0), unit=(0, 0), tri_cell=None)
     tri_unit = np.tile(np.asarray(unit, dtype=np.int64), (len(tri), 1))
     if tri_cell is not None:
         tri_unit = tri_unit + np.asarray(tri_cell, dtype=np.int64)
-    return RwgMesh(tri_xyz, tri_unit, rwg[:, 0:2].astype(np.int64), free, elen)
+    tri_state = None
+    if state_off is not None:
+        tri_state = np.full(len(tri), -1, dtype=np.int64)
+        for s in range(len(state_off) - 1):
+            for m in range(int(state_off[s]), int(state_off[s + 1])):
+                for t in rwg[m, 0:2]:
+                    if tri_state[t] not in (-1, s):
+                        raise ValueError("triangle carries bases of two coding states")
+                    tri_state[t] = s
+    return RwgMesh(tri_xyz, tri_unit, rwg[:, 0:2].astype(np.int64), free, elen, tri_state)
 
 
 def concat(meshes) -> RwgMesh:
@@ -85,6 +112,7 @@ def concat(meshes) -> RwgMesh:
         np.concatenate([m.rwg_tri + tri_off[i] for i, m in enumerate(meshes)]),
         np.concatenate([m.rwg_free for m in meshes]),
         np.concatenate([m.rwg_len for m in meshes]),
+        None if any(m.tri_state is None for m in meshes) else np.concatenate([m.tri_state for m in meshes]),
     )
 
 
@@ -153,7 +181,65 @@ def triangle_pair_integrals(obs: RwgMesh, src: RwgMesh, k: float, extract: int,
         A[pp, qq] += np.einsum("ei,eiak,eibk->eab", w, rho_o[pp], inner, optimize=True)
         B[pp, qq] += np.einsum("ei,ei->e", w, S)
 
-    return A / 4.0 - B[:, :, None, None] / (k * k)
+    T = A / 4.0 - B[:, :, None, None] / (k * k)
+    # overlapping triangles of different coding states: the composite outer rule
+    if obs.tri_state is not None and src.tri_state is not None:
+        so = obs.tri_state[P_idx][:, None]
+        ss = src.tri_state[Q_idx][None, :]
+        pp, qq = np.nonzero(ext & (cheb == 0) & (so >= 0) & (ss >= 0) & (so != ss))
+        for c in range(0, len(pp), 128):
+            T[pp[c:c + 128], qq[c:c + 128]] = _overlap_pair_integrals(to[pp[c:c + 128]], ts[qq[c:c + 128]], k)
+    return T
+
+
+def _composite_rule(level: int):
+    """Barycentric points [7 * 4^level, 3] and weights (summing to one) of the
+    7-point rule on the 4^level triangles of `level` midpoint subdivisions."""
+    bary, w = quadrature.seven_point()
+    tris = [np.eye(3)]  # corners of each sub-triangle, in barycentric coordinates
+    for _ in range(level):
+        nxt = []
+        for c in tris:
+            m01, m12, m20 = (c[0] + c[1]) / 2, (c[1] + c[2]) / 2, (c[2] + c[0]) / 2
+            nxt += [np.array([c[0], m01, m20]), np.array([m01, c[1], m12]),
+                    np.array([m20, m12, c[2]]), np.array([m12, m20, m01])]
+        tris = nxt
+    pts = np.concatenate([bary @ c for c in tris])
+    return pts, np.tile(w, len(tris)) / len(tris)
+
+
+OVERLAP_LEVEL = 3
+
+
+def _overlap_pair_integrals(tp: np.ndarray, tq: np.ndarray, k: float) -> np.ndarray:
+    """T[e,a,b] (as triangle_pair_integrals) for paired triangles tp[e], tq[e]
+    with the composite outer rule on tp; the inner integral over tq is the
+    closed-form 1/(4 pi R) part plus the 7-point smooth remainder."""
+    bary, wb = _composite_rule(OVERLAP_LEVEL)
+    area = 0.5 * np.linalg.norm(np.cross(tp[:, 1] - tp[:, 0], tp[:, 2] - tp[:, 0]), axis=1)
+    po = np.einsum("ia,ead->eid", bary, tp)  # [E,M,3]
+    wo = area[:, None] * wb[None, :]  # [E,M]
+    rho_o = po[:, :, None, :] - tp[:, None, :, :]  # [E,M,3(a),3]
+    ps, ws, _ = quadrature.points(tq)  # [E,7,3], [E,7]
+    rho_s = ps[:, :, None, :] - tq[:, None, :, :]  # [E,7,3(b),3]
+    E, M = po.shape[0], po.shape[1]
+    d = po[:, :, None, :] - ps[:, None, :, :]
+    R = np.sqrt(np.sum(d * d, axis=-1))  # [E,M,7]
+    Wg = _smooth_remainder(k * R, k) * wo[:, :, None] * ws[:, None, :]
+    # inner[e,i,b,:] = int_q (r' - v_b) g dS' at outer point i: the 7-point sum
+    # of the smooth remainder plus the closed-form 1/(4 pi R) part
+    inner = np.matmul(Wg, rho_s.reshape(E, 7, 9).astype(np.complex128)).reshape(E, M, 3, 3)
+    B = Wg.sum(axis=(1, 2))
+    S, V = potential_integrals_paired(po.reshape(-1, 3), np.repeat(tq, M, axis=0))
+    S = S.reshape(E, M)
+    V = V.reshape(E, M, 3)
+    w = wo / (4.0 * math.pi)
+    inner = inner + w[:, :, None, None] * (V[:, :, None, :] + (po[:, :, None, :] - tq[:, None, :, :]) * S[..., None, None])
+    B = B + np.sum(w * S, axis=1)
+    # A[e,a,b] = sum_i rho_o[e,i,a,:] . inner[e,i,b,:]
+    A = np.matmul(rho_o.transpose(0, 2, 1, 3).reshape(E, 3, M * 3),
+                  inner.transpose(0, 1, 3, 2).reshape(E, M * 3, 3))
+    return A / 4.0 - B[:, None, None] / (k * k)
 
 
 def efie_matrix(obs: RwgMesh, src: RwgMesh, k: float, extract: int = 1,
@@ -209,7 +295,7 @@ def macro_mesh(unit, cell=(0, 0)) -> RwgMesh:
     """The macro unit (union of all states) placed at lattice cell (ix, iy)."""
     px, py = unit.period
     ix, iy = cell
-    return rwg_mesh(unit.vert, unit.tri, unit.rwg, (ix * px, iy * py, 0.0), (ix, iy))
+    return rwg_mesh(unit.vert, unit.tri, unit.rwg, (ix * px, iy * py, 0.0), (ix, iy), state_off=unit.state_off)
 
 
 def direct_system(unit, states, L, k, extract=1, obs_units=None):

@@ -2,8 +2,9 @@
 
 Points are barycentric; weights sum to one and are multiplied by the triangle
 area by the caller.  Used for every surface integral of the Galerkin EFIE of
-eq. (1) (testing and source integrals), the excitation and the radiation
-integrals.
+eq. (1) (testing and source integrals; on 64 sub-triangles of the observer
+triangle for overlapping triangles of different coding states, see efie),
+the excitation and the radiation integrals.
 """
 import math
 

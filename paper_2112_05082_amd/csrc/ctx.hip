@@ -116,13 +116,24 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
     double dz = g->vert[3 * r[2] + 2] - g->vert[3 * r[3] + 2];
     len[m] = std::sqrt(dx * dx + dy * dy + dz * dz);
   }
+  // the coding state whose patch holds each triangle (coexistent meshes of
+  // the macro unit); triangles of shared bases keep -1
+  std::vector<int32_t> tstate(nt, -1);
+  for (int s = 0; s < g->n_states; ++s)
+    for (int m = g->state_off[s]; m < g->state_off[s + 1]; ++m)
+      for (int a = 0; a < 2; ++a) {
+        int32_t& ts = tstate[rtri[2 * m + a]];
+        R3M_REQUIRE(ts == -1 || ts == s, R3M_ERR_INVALID_ARG, "a triangle carries bases of two coding states");
+        ts = s;
+      }
   size_t off_tv = 0;
   size_t off_ar = off_tv + tri_v.size() * 8;
   size_t off_len = off_ar + area.size() * 8;
   size_t off_rt = off_len + len.size() * 8;
   size_t off_rf = off_rt + rtri.size() * 4;
   size_t off_tc = off_rf + rfree.size() * 4;
-  size_t total = off_tc + (g->tri_cell ? 8 * (size_t)nt : 0);
+  size_t off_ts = off_tc + (g->tri_cell ? 8 * (size_t)nt : 0);
+  size_t total = off_ts + 4 * (size_t)nt;
   std::vector<char> host(total);
   std::memcpy(host.data() + off_tv, tri_v.data(), tri_v.size() * 8);
   std::memcpy(host.data() + off_ar, area.data(), area.size() * 8);
@@ -130,6 +141,7 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
   std::memcpy(host.data() + off_rt, rtri.data(), rtri.size() * 4);
   std::memcpy(host.data() + off_rf, rfree.data(), rfree.size() * 4);
   if (g->tri_cell) std::memcpy(host.data() + off_tc, g->tri_cell, 8 * (size_t)nt);
+  std::memcpy(host.data() + off_ts, tstate.data(), 4 * (size_t)nt);
   // previous users of the table may still be queued on this stream
   R3M_CHECK_HIP(hipStreamSynchronize(stream));
   ctx->geom.ensure(total);
@@ -143,6 +155,7 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
   d.rwg_tri = (const int32_t*)(base + off_rt);
   d.rwg_free = (const int32_t*)(base + off_rf);
   d.tri_cell = g->tri_cell ? (const int32_t*)(base + off_tc) : nullptr;
+  d.tri_state = (const int32_t*)(base + off_ts);
   d.n_tri = nt;
   d.n_rwg = nr;
   return d;

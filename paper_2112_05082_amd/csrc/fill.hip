@@ -10,7 +10,14 @@
 // cells, Sec. III-B), G = 1/(4 pi R) + (exp(-jkR) - 1)/(4 pi R):
 // the first term is integrated in closed form over the source triangle
 // (edge-sum formulas of Wilton et al. / Graglia), the second by quadrature.
-// One thread per (block, m, n); everything in FP64.
+// Triangles of different coding states in the same cell overlap (coexistent
+// meshes of the macro unit, Sec. III-A): the closed-form inner integral then
+// has kinks along the source triangle's edges inside the observer triangle,
+// so for those pairs the outer integral takes the composite rule, the 7-point
+// rule on each of the 64 triangles of three midpoint subdivisions of the
+// observer triangle.  One thread per (block, m, n); everything in FP64.
+#include <array>
+
 #include "r3m_common.h"
 
 namespace r3m {
@@ -22,6 +29,16 @@ struct Quad7 {
 };
 
 __constant__ Quad7 c_quad;
+
+// the composite outer rule for overlapping cross-state pairs
+constexpr int kSubLevels = 3;
+constexpr int kSubTris = 1 << (2 * kSubLevels);  // 64
+constexpr int kCompPts = 7 * kSubTris;           // 448
+struct QuadComp {
+  double b[kCompPts][3];
+  double w[kCompPts];
+};
+__constant__ QuadComp c_comp;
 
 Quad7 make_quad7() {
   Quad7 q;
@@ -36,6 +53,40 @@ Quad7 make_quad7() {
     for (int c = 0; c < 3; ++c) q.b[i][c] = pts[i][c];
     q.w[i] = ws[i];
   }
+  return q;
+}
+
+// 7-point rule on each triangle of kSubLevels midpoint subdivisions, in
+// barycentric coordinates of the parent triangle (weights sum to one)
+QuadComp make_composite(const Quad7& q7) {
+  // corners of the sub-triangles, in barycentric coordinates
+  std::vector<std::array<std::array<double, 3>, 3>> tris(1);
+  for (int c = 0; c < 3; ++c)
+    for (int d = 0; d < 3; ++d) tris[0][c][d] = c == d ? 1.0 : 0.0;
+  for (int lev = 0; lev < kSubLevels; ++lev) {
+    std::vector<std::array<std::array<double, 3>, 3>> next;
+    for (const auto& t : tris) {
+      std::array<double, 3> m[3];  // midpoints of the edges opposite corners 2, 0, 1
+      for (int d = 0; d < 3; ++d) {
+        m[0][d] = 0.5 * (t[0][d] + t[1][d]);
+        m[1][d] = 0.5 * (t[1][d] + t[2][d]);
+        m[2][d] = 0.5 * (t[2][d] + t[0][d]);
+      }
+      next.push_back({t[0], m[0], m[2]});
+      next.push_back({m[0], t[1], m[1]});
+      next.push_back({m[2], m[1], t[2]});
+      next.push_back({m[1], m[2], m[0]});
+    }
+    tris.swap(next);
+  }
+  QuadComp q;
+  int i = 0;
+  for (const auto& t : tris)
+    for (int j = 0; j < 7; ++j, ++i) {
+      for (int d = 0; d < 3; ++d)
+        q.b[i][d] = q7.b[j][0] * t[0][d] + q7.b[j][1] * t[1][d] + q7.b[j][2] * t[2][d];
+      q.w[i] = q7.w[j] / kSubTris;
+    }
   return q;
 }
 
@@ -98,7 +149,7 @@ __device__ inline V3 load_vertex(const double* tv, int t, int a) {
 }
 
 template <typename OutT>
-__global__ void __launch_bounds__(256) fill_blocks_kernel(GeomDev g, double k, double px, double py,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) fill_blocks_kernel(GeomDev g, double k, double px, double py,
                                                           int Dx, int Dy, int slot_begin,
                                                           int extract_radius, OutT* out,
                                                           int* flag) {
@@ -142,10 +193,15 @@ __global__ void __launch_bounds__(256) fill_blocks_kernel(GeomDev g, double k, d
         cy += g.tri_cell[2 * p + 1] - g.tri_cell[2 * q + 1];
       }
       const bool extract = abs(cx) <= extract_radius && abs(cy) <= extract_radius;
+      const int sp = g.tri_state[p], sq = g.tri_state[q];
+      const bool overlap = extract && cx == 0 && cy == 0 && sp >= 0 && sq >= 0 && sp != sq;
+      const int n_outer = overlap ? kCompPts : 7;
       double t_re = 0.0, t_im = 0.0;
-      for (int i = 0; i < 7; ++i) {
-        V3 r = c_quad.b[i][0] * P0 + c_quad.b[i][1] * P1 + c_quad.b[i][2] * P2;
-        const double wi = c_quad.w[i] * Ap;
+#pragma unroll 1
+      for (int i = 0; i < n_outer; ++i) {
+        const double* bi = overlap ? c_comp.b[i] : c_quad.b[i];
+        V3 r = bi[0] * P0 + bi[1] * P1 + bi[2] * P2;
+        const double wi = (overlap ? c_comp.w[i] : c_quad.w[i]) * Ap;
         V3 ra = r - va;
         double s_re = 0.0, s_im = 0.0;
         for (int j = 0; j < 7; ++j) {
@@ -230,6 +286,8 @@ int r3m_fill_unique_blocks(r3m_ctx ctx, const r3m_unit_geom* geom, int32_t Dx, i
       if (!quad_ready) {
         Quad7 q = make_quad7();
         R3M_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_quad), &q, sizeof(q)));
+        QuadComp qc = make_composite(q);
+        R3M_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_comp), &qc, sizeof(qc)));
         quad_ready = true;
       }
     }

@@ -143,6 +143,7 @@ struct GeomDev {
   const int32_t* rwg_free;// [n_rwg][2] local index of the free vertex
   const double* rwg_len;  // [n_rwg]
   const int32_t* tri_cell;// [n_tri][2] lattice offset of each triangle's cell, or NULL
+  const int32_t* tri_state;// [n_tri] coding state of the bases a triangle carries, -1 for shared bases
   int32_t n_tri, n_rwg;
 };
 
