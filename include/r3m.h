@@ -99,8 +99,11 @@ int r3m_ctx_check(r3m_ctx ctx, hipStream_t stream);
  * its triangle in the neighbouring cell carries that cell's lattice offset in
  * tri_cell ([n_tri][2], NULL: every triangle in the unit's own cell), which
  * the extraction rule uses.  n_common = 0 and tri_cell = NULL for isolated
- * units.  The fill takes connected geometries; excitation and RCS do not yet
- * (R3M_ERR_UNSUPPORTED). */
+ * units.  The fill, excitation and RCS take connected geometries; the
+ * excitation and RCS class each shared basis by the cells of its triangles
+ * (both in the unit's cell: 0; one in the -x neighbour: 1; in the -y
+ * neighbour: 2) and return R3M_ERR_UNSUPPORTED for any other reach or for a
+ * coding-state basis outside its cell. */
 typedef struct {
   double freq_hz;
   double period_x, period_y;
@@ -454,7 +457,10 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z6
  * same matrix) is given and opts->refine_tol > 0, an outer FP64 iterative
  * refinement computes r = b - Z64 x and solves Z d = r with the inner GMRES.
  * rep_host[B] is written; returns R3M_ERR_NOT_CONVERGED if any RHS missed the
- * tolerance (x still holds the last iterate).  Synchronises the stream. */
+ * tolerance (x still holds the last iterate).  Synchronises the stream.
+ * Stores with shared (connected-geometry) bases: vectors in the store's
+ * reduced layout, R3M_PRECOND_NONE and no relaxed weights
+ * (R3M_ERR_UNSUPPORTED otherwise), Z64 with the same shared bases. */
 int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
                     const r3m_batch* batch, const void* b_dev, void* x_dev,
                     const r3m_gmres_opts* opts, r3m_gmres_report* rep_host, void* work_dev,
@@ -465,14 +471,17 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
 /* Plane-wave right-hand sides U_k (eq. (1)), C128 [unit][n_a] per RHS:
  * U_m = int f_m . E_inc dS, E_inc = e0 e_hat exp(-j k k_hat . r),
  * k_hat = -(sin t cos p, sin t sin p, cos t), e_hat = theta_hat(t, p).
- * inc_host: [B][3] = (theta, phi, e0). */
+ * inc_host: [B][3] = (theta, phi, e0).  Connected geometries: [unit][n_a +
+ * n_common], each basis integrated over its own triangles where they lie,
+ * zero on the extended bases D_k masks (Sec. III-B). */
 int r3m_plane_wave_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch,
                        const double* inc_host, void* b_dev, hipStream_t stream);
 
 /* Bistatic RCS sigma[b][dir] (m^2, FP64) of currents I (C128 reduced vectors):
  * N(r_hat) = sum_n I_n int f_n exp(j k r_hat . r') dS',
  * sigma = (k^2 eta^2 / 4 pi) |N - (N.r_hat) r_hat|^2 / |e0|^2.
- * dirs_host: [n_dir][2] = (theta, phi) in radians. */
+ * dirs_host: [n_dir][2] = (theta, phi) in radians.  Connected geometries as
+ * for r3m_plane_wave_rhs (masked entries of I are ignored). */
 int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, const void* I_dev,
             int32_t n_dir, const double* dirs_host, double e0, double* sigma_dev,
             hipStream_t stream);

@@ -21,12 +21,18 @@ The reduced vector is ordered by unit, then by macro index.
 Singularity extraction follows the physical cell of each triangle (a
 bridge's neighbour half is in the neighbour's cell), the same rule as for
 the direct system on the physical structure.
+
+Excitation and RCS integrate every active basis over its own triangles where
+they lie, so a bridge belongs to the unit that owns it and its outer half
+needs no special case; the masked bases carry no current.
 """
 from __future__ import annotations
 
 import numpy as np
 
-from .efie import RwgMesh, efie_matrix, rwg_mesh
+from .efie import RwgMesh, concat, efie_matrix, rwg_mesh
+from .excitation import plane_wave
+from .farfield import rcs as farfield_rcs
 from .retrieval import slot
 
 
@@ -87,3 +93,47 @@ def direct_system(cu, states, Lx: int, Ly: int, k: float, extract: int = 1):
     vert, tri, rwg, cell = connected_array_structure(cu, states, Lx, Ly)
     mesh = rwg_mesh(vert, tri, rwg, (0.0, 0.0, 0.0), (0, 0), cell)
     return efie_matrix(mesh, mesh, k, extract), mesh, (vert, tri, rwg, cell)
+
+
+def array_mesh(cu, Lx: int, Ly: int) -> RwgMesh:
+    """The extended macro units of every cell, concatenated in unit order
+    (macro index u n + m)."""
+    return concat([macro_mesh(cu, (u % Lx, u // Lx)) for u in range(Lx * Ly)])
+
+
+def retrieved_system(blocks: np.ndarray, Dx: int, Dy: int, active: list, Lx: int, Ly: int) -> np.ndarray:
+    """P_k^T Z P_k as a dense matrix in reduced coordinates (eq. (6) with the
+    masks of the extended bases)."""
+    offs = np.cumsum([0] + [len(a) for a in active])
+    Z = np.zeros((offs[-1], offs[-1]), dtype=np.complex128)
+    for i in range(Lx * Ly):
+        iy, ix = divmod(i, Lx)
+        for j in range(Lx * Ly):
+            jy, jx = divmod(j, Lx)
+            Zd = blocks[slot(ix - jx, iy - jy, Dx, Dy)]
+            Z[offs[i]:offs[i + 1], offs[j]:offs[j + 1]] = Zd[np.ix_(active[i], active[j])]
+    return Z
+
+
+def excitation(cu, active: list, Lx: int, Ly: int, k: float, theta: float = 0.0, phi: float = 0.0,
+               e0: float = 1.0) -> np.ndarray:
+    """P_k^T U: the plane-wave excitation of every unit's active bases, each
+    integrated over its own triangles where they lie (a bridge's outer half in
+    the neighbouring cell), in reduced order."""
+    out = []
+    for u, idx in enumerate(active):
+        U = plane_wave(macro_mesh(cu, (u % Lx, u // Lx)), k, theta, phi, e0)
+        out.append(U[idx])
+    return np.concatenate(out)
+
+
+def rcs(cu, active: list, Lx: int, Ly: int, I: np.ndarray, k: float, thph: np.ndarray,
+        e0: float = 1.0) -> np.ndarray:
+    """Bistatic RCS of the reduced current I: P_k I placed on the macro bases
+    of the array (masked and inactive bases carry no current)."""
+    n = cu.n
+    Imac = np.zeros(Lx * Ly * n, dtype=np.complex128)
+    offs = np.cumsum([0] + [len(a) for a in active])
+    for u, idx in enumerate(active):
+        Imac[u * n + idx] = I[offs[u]:offs[u + 1]]
+    return farfield_rcs(array_mesh(cu, Lx, Ly), Imac, k, thph, e0)

@@ -78,6 +78,34 @@ void require_isolated(const r3m_unit_geom* g) {
               "this call does not take connected geometries yet");
 }
 
+std::vector<int32_t> shared_classes(const r3m_unit_geom* g) {
+  // from the cells of each shared basis's two triangles: one of them may lie
+  // in the -x or the -y neighbour (the bridges a unit owns)
+  const int n_st = g->n_rwg - g->n_common;
+  std::vector<int32_t> cls(g->n_common, 0);
+  for (int c = 0; c < g->n_common; ++c)
+    for (int a = 0; a < 2 && g->tri_cell; ++a) {
+      const int t = g->rwg[4 * (n_st + c) + a];
+      const int ox = g->tri_cell[2 * t], oy = g->tri_cell[2 * t + 1];
+      const int here = ox == 0 && oy == 0 ? 0 : ox == -1 && oy == 0 ? 1 : ox == 0 && oy == -1 ? 2 : -1;
+      if (here != 0) cls[c] = cls[c] == 0 ? here : -1;
+    }
+  return cls;
+}
+
+void require_extension_classes(const r3m_unit_geom* g) {
+  for (int32_t c : shared_classes(g))
+    R3M_REQUIRE(c >= 0, R3M_ERR_UNSUPPORTED,
+                "a shared basis reaches outside its cell other than into the -x or the -y neighbour");
+  const int n_st = g->n_rwg - g->n_common;
+  for (int m = 0; m < n_st && g->tri_cell; ++m)
+    for (int a = 0; a < 2; ++a) {
+      const int t = g->rwg[4 * m + a];
+      R3M_REQUIRE(g->tri_cell[2 * t] == 0 && g->tri_cell[2 * t + 1] == 0, R3M_ERR_UNSUPPORTED,
+                  "a coding-state basis reaches outside its cell");
+    }
+}
+
 GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
   validate_geom(g);
   const int nt = g->n_tri, nr = g->n_rwg;
@@ -126,6 +154,9 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
         R3M_REQUIRE(ts == -1 || ts == s, R3M_ERR_INVALID_ARG, "a triangle carries bases of two coding states");
         ts = s;
       }
+  const int n_st = g->n_rwg - g->n_common;
+  std::vector<int32_t> cext = shared_classes(g);
+  if (cext.empty()) cext.push_back(0);
   size_t off_tv = 0;
   size_t off_ar = off_tv + tri_v.size() * 8;
   size_t off_len = off_ar + area.size() * 8;
@@ -133,7 +164,8 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
   size_t off_rf = off_rt + rtri.size() * 4;
   size_t off_tc = off_rf + rfree.size() * 4;
   size_t off_ts = off_tc + (g->tri_cell ? 8 * (size_t)nt : 0);
-  size_t total = off_ts + 4 * (size_t)nt;
+  size_t off_ce = off_ts + 4 * (size_t)nt;
+  size_t total = off_ce + 4 * cext.size();
   std::vector<char> host(total);
   std::memcpy(host.data() + off_tv, tri_v.data(), tri_v.size() * 8);
   std::memcpy(host.data() + off_ar, area.data(), area.size() * 8);
@@ -142,6 +174,7 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
   std::memcpy(host.data() + off_rf, rfree.data(), rfree.size() * 4);
   if (g->tri_cell) std::memcpy(host.data() + off_tc, g->tri_cell, 8 * (size_t)nt);
   std::memcpy(host.data() + off_ts, tstate.data(), 4 * (size_t)nt);
+  std::memcpy(host.data() + off_ce, cext.data(), 4 * cext.size());
   // previous users of the table may still be queued on this stream
   R3M_CHECK_HIP(hipStreamSynchronize(stream));
   ctx->geom.ensure(total);
@@ -156,6 +189,9 @@ GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream) {
   d.rwg_free = (const int32_t*)(base + off_rf);
   d.tri_cell = g->tri_cell ? (const int32_t*)(base + off_tc) : nullptr;
   d.tri_state = (const int32_t*)(base + off_ts);
+  d.common_ext = (const int32_t*)(base + off_ce);
+  d.n_st = n_st;
+  d.n_common = g->n_common;
   d.n_tri = nt;
   d.n_rwg = nr;
   return d;

@@ -1225,7 +1225,7 @@ struct GmresRun {
     const double* np = long_vec ? W.nsum : W.npart;
     const int npB = long_vec ? 1 : maxB, npN = long_vec ? 1 : 0;
     // blocks of whole units (the preconditioner multiplies per unit)
-    const int nthr = (256 / n_a) * n_a;
+    const int nthr = pre ? (256 / n_a) * n_a : 256;
     const int64_t nb_n = ceil_div((size_t)maxN, nthr);
     const dim3 ngrid(stride_grid(nb_n * B));
     const size_t glds0 = (size_t)(2 * m + 2) * 16 + (size_t)((m + 1) / 2) * 16;
@@ -1418,12 +1418,22 @@ bool basis32(const r3m_store* Z, const r3m_store* Z64, int ilu_r, bool relaxed) 
 
 size_t gmres_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64, const BatchDesc& bd, int m,
                    bool per_unit, int ilu_r, bool relaxed, bool vb32) {
-  const int n_a = Z->n / Z->n_states;
+  const int n_a = vec_per_unit(Z);
   size_t mv = partials_and_x_bytes(bd, Z, max_groups(bd));
   if (Z64) mv = std::max(mv, partials_and_x_bytes(bd, Z64, max_groups(bd)));
   return layout_work(nullptr, bd, n_a, per_unit ? (int)bd.total_units : Z->n_states, m, mv, near_lists_bytes(Z, bd),
                      Z64 ? near_lists_bytes(Z64, bd) : 0, ilu_r ? ilu_factor_bytes(Z, bd, ilu_r, !relaxed) : 0, vb32)
       .bytes;
+}
+
+// Shared (connected-geometry) bases: solves without preconditioner on
+// spectral stores, the refinement store with the same shared bases
+void require_solvable(const r3m_store* Z, const r3m_store* Z64, const r3m_gmres_opts* opts) {
+  if (Z->n_common == 0 && (!Z64 || Z64->n_common == 0)) return;
+  R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE && !opts->relaxed_weights, R3M_ERR_UNSUPPORTED,
+              "solves with shared (connected-geometry) bases take no preconditioner and no relaxed weights yet");
+  R3M_REQUIRE(!Z64 || Z64->n_common == Z->n_common, R3M_ERR_INVALID_ARG,
+              "the refinement store's shared bases do not match");
 }
 
 // the ILU radius a solve uses (0: no ILU), validated against the store
@@ -1446,11 +1456,8 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z6
   int rc = guarded(ctx, [&] {
     R3M_REQUIRE(ctx && opts, R3M_ERR_INVALID_ARG, "NULL argument");
     validate_store(Z);
-    require_isolated(Z);
-    if (Z64) {
-      validate_store(Z64);
-      require_isolated(Z64);
-    }
+    if (Z64) validate_store(Z64);
+    require_solvable(Z, Z64, opts);
     validate_batch(batch, Z->Dx, Z->Dy);
     R3M_REQUIRE(opts->restart >= 1 && opts->restart <= 1024, R3M_ERR_INVALID_ARG, "restart out of range");
     if (batch->B == 0) return;
@@ -1470,12 +1477,11 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx && opts, R3M_ERR_INVALID_ARG, "NULL argument");
     validate_store(Z);
-    require_isolated(Z);
     validate_batch(batch, Z->Dx, Z->Dy);
     const bool refine = Z64 != nullptr && opts->refine_tol > 0.0;
+    require_solvable(Z, refine ? Z64 : nullptr, opts);
     if (refine) {
       validate_store(Z64);
-      require_isolated(Z64);
       R3M_REQUIRE(Z64->near_dtype == R3M_C128, R3M_ERR_INVALID_ARG, "refinement store must be C128");
       R3M_REQUIRE(Z64->n == Z->n && Z64->n_states == Z->n_states && Z64->Dx >= Z->Dx && Z64->Dy >= Z->Dy,
                   R3M_ERR_INVALID_ARG, "refinement store does not match");
@@ -1488,7 +1494,7 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
     R3M_CHECK_HIP(hipSetDevice(ctx->device));
     const BatchDesc& bd = get_batch(ctx, batch, kTW, kTH, stream);
     const int m = opts->restart;
-    const int n_a = Z->n / Z->n_states;
+    const int n_a = vec_per_unit(Z);  // vector entries per unit
     const bool per_unit = opts->relaxed_weights && opts->precond == R3M_PRECOND_BLOCK_JACOBI;
     R3M_REQUIRE(opts->precond == R3M_PRECOND_NONE || opts->precond == R3M_PRECOND_BLOCK_JACOBI ||
                     opts->precond == R3M_PRECOND_BLOCK_ILU,

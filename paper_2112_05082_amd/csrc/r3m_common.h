@@ -144,13 +144,42 @@ struct GeomDev {
   const double* rwg_len;  // [n_rwg]
   const int32_t* tri_cell;// [n_tri][2] lattice offset of each triangle's cell, or NULL
   const int32_t* tri_state;// [n_tri] coding state of the bases a triangle carries, -1 for shared bases
+  // shared bases (connected geometries): the first is macro RWG n_st; class of
+  // each from its triangles' cells: 0 inside the cell, 1 reaching into the
+  // -x neighbour, 2 into the -y neighbour, -1 any other reach
+  const int32_t* common_ext;
+  int32_t n_st, n_common;
   int32_t n_tri, n_rwg;
 };
+
+// entries per unit of a solution vector: the state's n_a bases, then the
+// shared ones
+inline int vec_per_unit(const r3m_store* Z) {
+  return (Z->n - Z->n_common) / Z->n_states + Z->n_common;
+}
+inline int vec_per_unit(const r3m_unit_geom* g) {
+  return (g->n_rwg - g->n_common) / g->n_states + g->n_common;
+}
+
+// Macro RWG of compact entry r of a unit in state s at lattice position (ix,
+// iy), or -1 where D_k masks an extended basis (one that reaches into a
+// neighbour the array does not have, Sec. III-B).
+__device__ inline int compact_to_macro(const GeomDev& g, int n_a, int s, int r, int64_t ix, int64_t iy) {
+  if (r < n_a) return s * n_a + r;
+  const int c = r - n_a;
+  const int e = g.common_ext[c];
+  if ((e == 1 && ix == 0) || (e == 2 && iy == 0)) return -1;
+  return g.n_st + c;
+}
 
 void validate_geom(const r3m_unit_geom* g);
 // calls that do not take connected geometries yet (shared bases)
 void require_isolated(const r3m_store* Z);
 void require_isolated(const r3m_unit_geom* g);
+// class of each shared basis of a geometry (see GeomDev::common_ext)
+std::vector<int32_t> shared_classes(const r3m_unit_geom* g);
+// calls that need every shared basis to have a class (0, 1 or 2)
+void require_extension_classes(const r3m_unit_geom* g);
 GeomDev upload_geom(r3m_ctx ctx, const r3m_unit_geom* g, hipStream_t stream);
 
 // At most kMaxBatches descriptors are cached per context; a new one beyond

@@ -2,7 +2,10 @@
 // currents (post-processing of Sec. IV-A), FP64.
 //
 // Excitation: U_m = int f_m . E_inc dS, E_inc = e0 e_hat exp(-j k k_hat . r),
-// 7-point rule, one thread per (RHS, unit, active RWG).
+// 7-point rule, one thread per (RHS, unit, active RWG).  Connected geometries
+// (Sec. III-B): a unit's entries are its state's bases, then the shared ones;
+// a bridging basis integrates over both of its triangles at their own
+// positions, and D_k's masked extended bases get zero.
 // RCS: radiation vectors of the macro RWGs of the unit at the origin,
 // F_m(r_hat) = int f_m exp(j k r_hat . r) dS, are formed once per direction;
 // then N(r_hat) = sum_u exp(j k r_hat . c_u) sum_{m in A(s_u)} I_{u,m} F_m and
@@ -48,21 +51,23 @@ __device__ double2 plane_wave_value(const GeomDev& g, int mm, double cx, double 
 }
 
 __global__ void plane_wave_kernel(GeomDev g, const RhsDev* __restrict__ rhs, const IncDev* __restrict__ inc,
-                                  const uint8_t* __restrict__ states, int n_a, int n_states, double k,
+                                  const uint8_t* __restrict__ states, int n_a, int n_v, int n_states, double k,
                                   double px, double py, double2* __restrict__ out) {
   const int b = blockIdx.y;
   const RhsDev R = rhs[b];
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t units = (int64_t)R.Lx * R.Ly;
-  if (e >= units * n_a) return;
-  const int64_t u = e / n_a;
-  const int m = (int)(e % n_a);
+  if (e >= units * n_v) return;
+  const int64_t u = e / n_v;
+  const int r = (int)(e % n_v);
   int s = states[R.state_off + u];
   s = s < n_states ? s : n_states - 1;
-  const double cx = (double)(u % R.Lx) * px, cy = (double)(u / R.Lx) * py;
+  const int64_t ix = u % R.Lx, iy = u / R.Lx;
+  const double cx = (double)ix * px, cy = (double)iy * py;
   const IncDev I = inc[b];
-  const double2 v = plane_wave_value(g, s * n_a + m, cx, cy, I, k);
-  out[R.unit_off * n_a + e] = make_double2(I.e0 * v.x, I.e0 * v.y);
+  const int mm = compact_to_macro(g, n_a, s, r, ix, iy);
+  const double2 v = mm >= 0 ? plane_wave_value(g, mm, cx, cy, I, k) : make_double2(0.0, 0.0);
+  out[R.unit_off * n_v + e] = make_double2(I.e0 * v.x, I.e0 * v.y);
 }
 
 // Relaxed codebook (weights w [unit][n_states]): macro == 0 writes the blended
@@ -129,9 +134,10 @@ __global__ void macro_radiation_kernel(GeomDev g, const double* __restrict__ dir
 constexpr int kRcsThreads = 256;
 
 __global__ void __launch_bounds__(kRcsThreads)
-rcs_kernel(const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, const double2* __restrict__ I,
-           const double2* __restrict__ F, const double* __restrict__ dirs, int n_dir, int n, int n_a,
-           int n_states, double k, double px, double py, double scale, double* __restrict__ sigma) {
+rcs_kernel(GeomDev g, const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states,
+           const double2* __restrict__ I, const double2* __restrict__ F, const double* __restrict__ dirs, int n_dir,
+           int n, int n_a, int n_v, int n_states, double k, double px, double py, double scale,
+           double* __restrict__ sigma) {
   __shared__ double sh[kRcsThreads / 64][6];
   const int d = blockIdx.x, b = blockIdx.y;
   const RhsDev R = rhs[b];
@@ -143,14 +149,17 @@ rcs_kernel(const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states, c
   for (int64_t u = threadIdx.x; u < units; u += blockDim.x) {
     int s = states[R.state_off + u];
     s = s < n_states ? s : n_states - 1;
-    const double cx = (double)(u % R.Lx) * px, cy = (double)(u / R.Lx) * py;
+    const int64_t ix = u % R.Lx, iy = u / R.Lx;
+    const double cx = (double)ix * px, cy = (double)iy * py;
     double sn, cs;
     sincos(k * (rx * cx + ry * cy), &sn, &cs);
     double loc[6] = {0, 0, 0, 0, 0, 0};
-    const double2* Iu = I + (R.unit_off + u) * n_a;
-    for (int m = 0; m < n_a; ++m) {
+    const double2* Iu = I + (R.unit_off + u) * n_v;
+    for (int m = 0; m < n_v; ++m) {
+      const int mm = compact_to_macro(g, n_a, s, m, ix, iy);
+      if (mm < 0) continue;  // a masked extended basis carries no current
       const double2 cur = Iu[m];
-      const double2* f = Fd + (size_t)(s * n_a + m) * 3;
+      const double2* f = Fd + (size_t)mm * 3;
       for (int q = 0; q < 3; ++q) {
         loc[2 * q] += cur.x * f[q].x - cur.y * f[q].y;
         loc[2 * q + 1] += cur.x * f[q].y + cur.y * f[q].x;
@@ -316,7 +325,7 @@ int r3m_plane_wave_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* 
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_geom(geom);
-    require_isolated(geom);
+    require_extension_classes(geom);
     validate_batch(batch, 1 << 20, 1 << 20);
     if (batch->B == 0) return;
     R3M_REQUIRE(inc_host && b_dev, R3M_ERR_INVALID_ARG, "NULL argument");
@@ -339,10 +348,11 @@ int r3m_plane_wave_rhs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* 
     int64_t maxU = 0;
     for (int b = 0; b < bd.B; ++b) maxU = std::max<int64_t>(maxU, bd.n_units[b]);
     const double k = 2.0 * kPi * geom->freq_hz / kC0;
-    dim3 grid(ceil_div((size_t)maxU * n_a, 256), bd.B);
+    const int n_v = vec_per_unit(geom);
+    dim3 grid(ceil_div((size_t)maxU * n_v, 256), bd.B);
     check_states(bd, batch->states, geom->n_states, deferred_word(ctx), kDeferredBadState, stream);
     hipLaunchKernelGGL(plane_wave_kernel, grid, dim3(256), 0, stream, g, bd.rhs, (const IncDev*)tmp.ptr,
-                       batch->states, n_a, geom->n_states, k, geom->period_x, geom->period_y, (double2*)b_dev);
+                       batch->states, n_a, n_v, geom->n_states, k, geom->period_x, geom->period_y, (double2*)b_dev);
     R3M_CHECK_HIP(hipGetLastError());
     R3M_CHECK_HIP(hipStreamSynchronize(stream));
     tmp.release();
@@ -355,7 +365,7 @@ int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, cons
   return guarded(ctx, [&] {
     R3M_REQUIRE(ctx, R3M_ERR_INVALID_ARG, "ctx is NULL");
     validate_geom(geom);
-    require_isolated(geom);
+    require_extension_classes(geom);
     validate_batch(batch, 1 << 20, 1 << 20);
     R3M_REQUIRE(n_dir >= 0, R3M_ERR_INVALID_ARG, "n_dir < 0");
     R3M_REQUIRE(e0 != 0.0 && std::isfinite(e0), R3M_ERR_INVALID_ARG, "e0 must be finite and non-zero");
@@ -378,9 +388,9 @@ int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, cons
                        stream, g, ddev, n_dir, k, F);
     const double scale = k * k * kEta0 * kEta0 / (4.0 * kPi) / (e0 * e0);
     check_states(bd, batch->states, geom->n_states, deferred_word(ctx), kDeferredBadState, stream);
-    hipLaunchKernelGGL(rcs_kernel, dim3(n_dir, bd.B), dim3(kRcsThreads), 0, stream, bd.rhs, batch->states,
-                       (const double2*)I_dev, F, ddev, n_dir, geom->n_rwg, n_a, geom->n_states, k,
-                       geom->period_x, geom->period_y, scale, sigma_dev);
+    hipLaunchKernelGGL(rcs_kernel, dim3(n_dir, bd.B), dim3(kRcsThreads), 0, stream, g, bd.rhs, batch->states,
+                       (const double2*)I_dev, F, ddev, n_dir, geom->n_rwg, n_a, vec_per_unit(geom), geom->n_states,
+                       k, geom->period_x, geom->period_y, scale, sigma_dev);
     R3M_CHECK_HIP(hipGetLastError());
     R3M_CHECK_HIP(hipStreamSynchronize(stream));
     tmp.release();

@@ -353,8 +353,8 @@ def r3m_relaxed_matvec(ctx: Context, store: Store, batch: Batch, weights, vec_dt
     """y = P(w)^T Z P(w) x (transpose: with Z^T); weights: float64 device
     tensor [total units][n_states]."""
     lib = load()
-    _need_vec(x, batch, store.n // store.n_states, "x")
-    _need_vec(y, batch, store.n // store.n_states, "y")
+    _need_vec(x, batch, per_unit(store), "x")
+    _need_vec(y, batch, per_unit(store), "y")
     if batch.B and weights.numel() < batch.total_units * store.n_states:
         raise ValueError("weights hold fewer than total_units x n_states entries")
     sc = store.c()
@@ -398,6 +398,12 @@ def r3m_relaxed_gradient(ctx: Context, store: Store, batch: Batch, weights, I, l
                                        _stream(stream)), ctx.handle)
 
 
+def per_unit(obj) -> int:
+    """Vector entries per unit for a Store or UnitGeom: the state's n_a
+    bases, then the n_common shared ones (connected geometries)."""
+    return (obj.n - obj.n_common) // obj.n_states + obj.n_common
+
+
 def _need_vec(t, batch: Batch, n_a: int, what: str):
     if batch.B and t.numel() < batch.total_units * n_a:
         raise ValueError(f"{what} holds {t.numel()} complex entries, the batch needs {batch.total_units * n_a}")
@@ -408,8 +414,8 @@ def r3m_retrieved_matvec(ctx: Context, store: Store, batch: Batch, vec_dtype: in
     """index_ready: the retrieval index in `work` is current (an earlier call
     with this store, batch and codebook built it there): skip rebuilding it."""
     lib = load()
-    _need_vec(x, batch, store.n // store.n_states, "x")
-    _need_vec(y, batch, store.n // store.n_states, "y")
+    _need_vec(x, batch, per_unit(store), "x")
+    _need_vec(y, batch, per_unit(store), "y")
     sc = store.c()
     wb = 0 if work is None else work.numel() * work.element_size()
     wp = C.c_void_p(0 if work is None else work.data_ptr())
@@ -431,8 +437,8 @@ def r3m_retrieved_matvec_static(ctx: Context, store: Store, batch: Batch, vec_dt
                                 index_ready: bool = False):
     """r3m_retrieved_matvec with the library's static device scratch (no workspace)."""
     lib = load()
-    _need_vec(x, batch, store.n // store.n_states, "x")
-    _need_vec(y, batch, store.n // store.n_states, "y")
+    _need_vec(x, batch, per_unit(store), "x")
+    _need_vec(y, batch, per_unit(store), "y")
     sc = store.c()
     batch.cs.flags = BATCH_INDEX_READY if index_ready else 0
     try:
@@ -455,8 +461,8 @@ def r3m_gmres_solve(ctx: Context, store: Store, store64: Store | None, batch: Ba
     the relaxed system P(w)^T Z P(w) x = b (transpose: with Z^T).
     ilu_radius: pattern radius of PRECOND_BLOCK_ILU."""
     lib = load()
-    _need_vec(b, batch, store.n // store.n_states, "b")
-    _need_vec(x, batch, store.n // store.n_states, "x")
+    _need_vec(b, batch, per_unit(store), "b")
+    _need_vec(x, batch, per_unit(store), "x")
     sc = store.c()
     s64 = store64.c() if store64 is not None else None
     wp = C.c_void_p(relaxed_weights.data_ptr() if relaxed_weights is not None else 0)
@@ -501,7 +507,7 @@ def r3m_ilu_apply(ctx: Context, store: Store, batch: Batch, radius: int, factors
 
 def r3m_plane_wave_rhs(ctx: Context, geom: UnitGeom, batch: Batch, inc, b, stream=None):
     inc = np.ascontiguousarray(inc, dtype=np.float64).reshape(-1, 3)
-    _need_vec(b, batch, geom.n // geom.n_states, "b")
+    _need_vec(b, batch, per_unit(geom), "b")
     if len(inc) != batch.B:
         raise ValueError("one incidence row per RHS")
     _check(load().r3m_plane_wave_rhs(ctx.handle, C.byref(geom.c), C.byref(batch.cs), _ptr(inc, C.c_double),
@@ -510,7 +516,7 @@ def r3m_plane_wave_rhs(ctx: Context, geom: UnitGeom, batch: Batch, inc, b, strea
 
 def r3m_rcs(ctx: Context, geom: UnitGeom, batch: Batch, I, dirs, e0, sigma, stream=None):
     dirs = np.ascontiguousarray(dirs, dtype=np.float64).reshape(-1, 2)
-    _need_vec(I, batch, geom.n // geom.n_states, "I")
+    _need_vec(I, batch, per_unit(geom), "I")
     if sigma.numel() < batch.B * len(dirs):
         raise ValueError("sigma too small")
     _check(load().r3m_rcs(ctx.handle, C.byref(geom.c), C.byref(batch.cs), C.c_void_p(I.data_ptr()), len(dirs),
