@@ -57,8 +57,9 @@ PRECOND_NAMES = {0: "unpreconditioned", 1: "block-Jacobi", 2: "block-ILU(0) r={r
 PROFILED_TRAFFIC = {
     # 2-bit 32x32 compressed matvec (convert + far_near + reduce) at 128 groups
     "c1_matvec": {"bytes": 403.7e6, "groups": 128},
-    # frequency product of the 1,536-RHS spectral matvec (spec_product_mfma_kernel)
-    "c2_product": {"bytes": 59.95e9},
+    # frequency product of the 1,536-RHS spectral matvec (spec_product_mfma_kernel,
+    # shape 6: 2 frequencies per wave, 4 columns per chunk, two 16-RHS tiles)
+    "c2_product": {"bytes": 57.03e9, "shape": 6},
 }
 
 
@@ -248,7 +249,9 @@ def headline_c2(ctx, args):
                         "inner_iters_mean": float(iters[S["sizes"] == L].mean()),
                         "inner_iters_max": int(iters[S["sizes"] == L].max())}
                for L in (32, 48, 64)}
-    traffic = PROFILED_TRAFFIC["c2_product"]
+    plan = r3m.decode_plan(r3m.matvec_plan(ctx, S["s64"], batch))
+    tr = PROFILED_TRAFFIC["c2_product"]
+    traffic = tr["bytes"] if tr and plan.get("shape") == tr["shape"] else None
     out = {
         "value": ok / dt,
         "ms_per_step": dt / args.steps * 1e3,
@@ -264,7 +267,7 @@ def headline_c2(ctx, args):
                       "max_rel_residual": max(r[2] for r in rep_ref)},
         "roofline": {"bound": "mfma", "achieved": pflops / pr / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": pflops / pr / 1e12 / PEAK_FP32_TFLOPS,
-                     "traffic": traffic["bytes"] if traffic else None,
+                     "traffic": traffic, "plan": plan,
                      "kernel": "spec_product_mfma_kernel: the per-frequency product of the spectral matvec over "
                                "the 1,536-RHS batch (FP32 matrix cores), one launch timed alone",
                      "kernel_ms": pr * 1e3, "algorithmic_flops_per_launch": pflops,

@@ -267,9 +267,10 @@ int32_t r3m_matvec_groups(r3m_ctx ctx, const r3m_store* Z, const r3m_batch* batc
  * Compressed stores: bits 0-15 the displacement-group count,
  * R3M_PLAN_MFMA_FAR when the far blocks run on the matrix cores.  Spectral
  * stores (R3M_SPEC_*): R3M_PLAN_SPECTRAL, in bits 0-3 the frequency-product
- * shape (0: vector units; 1..5: matrix cores with {frequencies per wave,
- * columns per staged chunk} = {1,4}, {2,4}, {2,8}, {4,4}, {1,8}; complex64
- * spectra only), in bits 4-11 the count of live 16-RHS tiles from which
+ * shape (0: vector units; 1..7: matrix cores with {frequencies per wave,
+ * columns per staged chunk, 16-RHS tiles per workgroup} = {1,4,1}, {2,4,1},
+ * {2,8,1}, {4,4,1}, {1,8,1}, {2,4,2}, {1,8,2}; complex64 spectra only), in
+ * bits 4-11 the count of live 16-RHS tiles from which
  * the matrix-core product orders its workgroups RHS tile first, in bits
  * 13-14 log2 of the groups of frequency tiles the eight XCDs split into in
  * that order (0: each XCD sees every frequency tile), and

@@ -1859,11 +1859,11 @@ int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
     for (int k = 1; k < kSpecShapeCount; ++k) shapes.push_back(k);
   if (const char* env = std::getenv("R3M_SPEC_SHAPE")) {
     const int k = std::atoi(env);
-    if (spectral_plan_valid(Z, spec_plan(k, kSpecRhsFirst))) shapes = {k};
+    if (k >= 0 && k < kSpecShapeCount && spectral_plan_valid(Z, spec_plan(k, spec_default_rf(k)))) shapes = {k};
   }
   int best = spectral_default_plan(Z, bd.B);
   if (shapes.size() == 1) {
-    best = spec_plan(shapes[0], kSpecRhsFirst);
+    best = spec_plan(shapes[0], spec_default_rf(shapes[0]));
   } else {
     hipEvent_t e0, e1;
     R3M_CHECK_HIP(hipEventCreate(&e0));
@@ -1885,7 +1885,7 @@ int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
     float best_ms = 1e30f;
     std::vector<std::pair<float, int>> mfma;
     for (int k : shapes) {
-      const int plan = spec_plan(k, kSpecRhsFirst);
+      const int plan = spec_plan(k, spec_default_rf(k));
       const float ms = time_plan(plan);
       if (k != 0) mfma.push_back({ms, k});
       if (ms < 0.97f * best_ms) {
@@ -1893,15 +1893,15 @@ int tuned_spectral(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
         best = plan;
       }
     }
-    // the other workgroup order of the full batch: the default threshold
-    // orders RHS tile first from kSpecRhsFirst tiles on, so from there the
-    // alternative is the contiguous order at every count, below it RHS tile
-    // first from the batch's own tile count
+    // the other workgroup order of the full batch: the shape's default
+    // threshold orders RHS tile first from spec_default_rf tiles on, so from
+    // there the alternative is the contiguous order at every count, below it
+    // RHS tile first from the batch's own tile count
     const int n_bt = (bd.B + 15) / 16;
     std::sort(mfma.begin(), mfma.end());
     for (size_t i = 0; i < mfma.size() && i < 2 && n_bt > 1; ++i) {
       const int k = mfma[i].second;
-      const int other = spec_plan(k, n_bt >= kSpecRhsFirst ? 255 : n_bt);
+      const int other = spec_plan(k, n_bt >= spec_default_rf(k) ? 255 : n_bt);
       const float ms = time_plan(other);
       if (ms < 0.97f * best_ms) {
         best_ms = ms;

@@ -24,11 +24,16 @@ static_assert(kPlanMfmaFar == R3M_PLAN_MFMA_FAR && kPlanSpectral == R3M_PLAN_SPE
 // of the matrix-core kernel; {0, 0} is the vector-unit kernel (register tile
 // by batch width)
 struct SpecShape {
-  int kpw, pc;
+  int kpw, pc, rb;  // frequencies per wave, columns per staged chunk, 16-RHS tiles per workgroup
 };
-constexpr SpecShape kSpecShapes[] = {{0, 0}, {1, 4}, {2, 4}, {2, 8}, {4, 4}, {1, 8}};
+constexpr SpecShape kSpecShapes[] = {{0, 0, 0}, {1, 4, 1}, {2, 4, 1}, {2, 8, 1}, {4, 4, 1},
+                                     {1, 8, 1}, {2, 4, 2}, {1, 8, 2}};
 constexpr int kSpecShapeCount = (int)(sizeof(kSpecShapes) / sizeof(kSpecShapes[0]));
 constexpr int kSpecRhsFirst = 8;  // default ordering threshold
+// the default threshold of a shape: workgroups of two 16-RHS tiles keep the
+// contiguous order up to 64 live tiles (measured on the 1,536-RHS solve:
+// 7.29, 7.17, 7.13, 7.10 s at 8, 24, 40, 64; 7.81 s never RHS tile first)
+inline int spec_default_rf(int shape) { return kSpecShapes[shape].rb == 2 ? 64 : kSpecRhsFirst; }
 inline int spec_plan(int shape, int rhs_first) { return kPlanSpectral | shape | rhs_first << 4; }
 inline int spec_shape(int plan) { return plan & 15; }
 inline int spec_rhs_first(int plan) { return (plan >> 4) & 255; }

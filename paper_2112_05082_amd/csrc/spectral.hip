@@ -780,8 +780,10 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
 // GEMM, taken as four real GEMMs (Re Y = Re Z Re X - Im Z Im X, Im Y = Re Z
 // Im X + Im Z Re X) on 16x16x4 FP32 MFMA tiles (lane l holds A[l % 16][l / 16]
 // and B[l / 16][l % 16]; result rows 4 (l / 16) + r, column l % 16).  A
-// workgroup owns 4 KPW frequencies x 80 rows x 16 right-hand sides; wave w
-// takes KPW adjacent frequencies for all five row tiles.  Columns are consumed
+// workgroup owns 4 KPW frequencies x 80 rows x 16 RB right-hand sides; wave
+// w takes KPW adjacent frequencies for all five row tiles and RB tiles of 16
+// right-hand sides (RB = 2 halves the spectra staged per product: the loads
+// of a chunk, not the matrix cores, bound the kernel).  Columns are consumed
 // in chunks of PC: the chunk is staged in LDS as [c][k][m] and [c][k][b] (rows
 // contiguous per frequency, padded strides) while the next chunk is already
 // in flight from global memory (runs of 4 KPW frequencies).  Results
@@ -802,9 +804,13 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
 constexpr int kPM = 80, kPB = 16;
 constexpr int kZP = kPM + 1, kXP = kPB + 1;
 
-// KPW frequencies per wave, 4 KPW per workgroup; PC columns per staged chunk
-template <int KPW, int PC, bool TR>
+// KPW frequencies per wave, 4 KPW per workgroup; PC columns per staged
+// chunk; RB tiles of 16 right-hand sides per workgroup (each staged chunk of
+// the spectra then feeds RB times the products)
+template <int KPW, int PC, int RB, bool TR>
 __global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(KPW == 2 && PC == 4 && RB == 1 ? 3 : KPW == 2 && RB == 2 ? 2
+                                       : KPW == 1 && PC == 8 && RB == 2 ? 3 : 1)))
 spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __restrict__ Xh, C2<float>* __restrict__ Yh,
                          int n, int64_t K, int B, int n_mg, int n_bt, int64_t n_tiles, int lgGx, int lgGy,
                          const int* __restrict__ live, const int* __restrict__ idle,
@@ -815,38 +821,44 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
   constexpr int PK = 4 * KPW;                   // frequencies per workgroup
   constexpr int LPK = PK == 8 ? 3 : PK == 16 ? 4 : 2;
   constexpr int YP = PK + 1;
+  // output tile rows of one right-hand side, padded by one entry so that the
+  // 16 lanes of a quarter-wave (16 right-hand sides, one row) write 16
+  // different bank pairs (an unpadded stride of 16 YP entries is a multiple
+  // of 128 bytes: every lane in one bank)
+  constexpr int YB = 16 * YP + 1;
   constexpr int LPC = PC == 8 ? 3 : 2;
+  constexpr int NB = kPB * RB, LNB = RB == 2 ? 5 : 4, XP = NB + 1;  // right-hand sides per workgroup
   __shared__ C2<float> Zs[PC * PK * kZP];  // [c][k][m]; reused as the output tile [b][m][k]
-  __shared__ C2<float> Xs[PC * PK * kXP];  // [c][k][b]
-  static_assert(16 * 16 * YP <= PC * PK * kZP, "output tile fits the staging buffer");
+  __shared__ C2<float> Xs[PC * PK * XP];   // [c][k][b]
+  static_assert(16 * YB <= PC * PK * kZP, "output tile fits the staging buffer");
   // RHS tiles to cover: all n_bt, or the nl live ones of tile_list (the
-  // launch is sized for both orders below)
+  // launch is sized for both orders below), taken RB at a time
   const int nl = tile_list ? *n_live : n_bt;
-  int bt, mg;
+  const int ng = (nl + RB - 1) / RB;  // groups of RB tiles
+  int bi, mg;
   int64_t kt;
   if (nl < rhs_first) {
-    const int64_t items = (n_tiles + 1) / 2 * 2 * n_mg * nl;
+    const int64_t items = (n_tiles + 1) / 2 * 2 * n_mg * ng;
     const int64_t per = (items + 7) / 8, loc = blockIdx.x >> 3;  // grid: a multiple of 8
     if (loc >= per) return;
     const int64_t id = (int64_t)(blockIdx.x & 7) * per + loc;
     if (id >= items) return;
     const int kh = (int)(id & 1);
     const int64_t r0 = id >> 1;
-    const int bi = (int)(r0 % nl);
-    const int64_t r1 = r0 / nl;
+    bi = (int)(r0 % ng);
+    const int64_t r1 = r0 / ng;
     mg = (int)(r1 % n_mg);
     kt = (r1 / n_mg) * 2 + kh;
-    bt = tile_list ? tile_list[bi] : bi;
   } else {
     // RHS tile first: the eight XCDs (workgroup id mod 8) form KG = 2^lkg
     // groups of frequency-tile pairs times 8 / KG groups of RHS tiles; an
     // XCD runs its pairs in turn and, within a pair, its RHS tiles with the
     // pair's two halves adjacent, so that the spectra of a few frequency
     // tiles stay in its L2 while the RHS tiles pass (KG = 1: every XCD sees
-    // every frequency tile, one RHS tile in eight)
+    // every frequency tile, one RHS tile group in eight)
     const int KG = 1 << lkg, BG = 8 >> lkg;
     const int x = (int)(blockIdx.x & 7), kg = x & (KG - 1), bg = x >> lkg;
-    const int nb_x = (nl - bg + BG - 1) / BG;  // RHS tiles of this XCD
+    const int nb_x = (ng - bg + BG - 1) / BG;  // RHS tile groups of this XCD
     const int64_t n_pairs = (n_tiles + 1) / 2, np_x = (n_pairs - kg + KG - 1) / KG;
     if (nb_x <= 0 || np_x <= 0) return;
     const int64_t l = blockIdx.x >> 3;
@@ -858,24 +870,35 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
     const int64_t pj = r1 / n_mg;
     if (pj >= np_x) return;
     kt = (pj * KG + kg) * 2 + kh;
-    const int bi = bg + bj * BG;
-    bt = tile_list ? tile_list[bi] : bi;
+    bi = bg + bj * BG;
   }
   if (kt >= n_tiles) return;  // n_tiles: frequency tiles
   const int64_t k0 = kt * PK;
-  const int m0 = mg * kPM, b0 = bt * kPB;
-  if (idle && !tile_list) {  // uniform over the workgroup: skip a tile of idle right-hand sides
+  const int m0 = mg * kPM;
+  // first right-hand side of each of the group's tiles (-1: past the last tile)
+  int b0[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int ti = bi * RB + r;
+    b0[r] = ti < nl ? (tile_list ? tile_list[ti] : ti) * kPB : -1;
+  }
+  if (idle && !tile_list) {  // uniform over the workgroup: skip a group of idle right-hand sides
     bool any = false;
-    for (int q = b0; q < min(b0 + kPB, B); ++q) any |= idle[q] == 0;
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (b0[r] >= 0)
+        for (int q = b0[r]; q < min(b0[r] + kPB, B); ++q) any |= idle[q] == 0;
     if (!any) return;
   }
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  v4 are[KPW][5], aim[KPW][5];
+  v4 are[KPW][5][RB], aim[KPW][5][RB];
 #pragma unroll
   for (int q = 0; q < KPW; ++q)
 #pragma unroll
-    for (int t = 0; t < 5; ++t) are[q][t] = aim[q][t] = v4{0, 0, 0, 0};
-  constexpr int NZ = PC * PK * kPM / 256, NX = PC * PK * kPB / 256;
+    for (int t = 0; t < 5; ++t)
+#pragma unroll
+      for (int r = 0; r < RB; ++r) are[q][t][r] = aim[q][t][r] = v4{0, 0, 0, 0};
+  constexpr int NZ = PC * PK * kPM / 256, NX = PC * PK * NB / 256;
   C2<float> zp[NZ], xp[NX];
   auto load_chunk = [&](int c0) {
 #pragma unroll
@@ -889,8 +912,9 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
       const int e = tid + 256 * i, k = e & (PK - 1), c = (e >> LPK) & (PC - 1), b = e >> (LPK + LPC);
-      const bool ok = b0 + b < B && c0 + c < n && k0 + k < K;
-      xp[i] = ok ? Xh[((int64_t)(b0 + b) * n + c0 + c) * K + k0 + k] : C2<float>{0, 0};
+      const int bb = (RB == 1 ? b0[0] : b0[b >> 4]) + (b & 15);
+      const bool ok = (RB == 1 ? b0[0] : b0[b >> 4]) >= 0 && bb < B && c0 + c < n && k0 + k < K;
+      xp[i] = ok ? Xh[((int64_t)bb * n + c0 + c) * K + k0 + k] : C2<float>{0, 0};
     }
   };
   load_chunk(0);
@@ -904,7 +928,7 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
 #pragma unroll
     for (int i = 0; i < NX; ++i) {
       const int e = tid + 256 * i, k = e & (PK - 1), c = (e >> LPK) & (PC - 1), b = e >> (LPK + LPC);
-      Xs[(c * PK + k) * kXP + b] = xp[i];
+      Xs[(c * PK + k) * XP + b] = xp[i];
     }
     __syncthreads();
     if (c0 + PC < n) load_chunk(c0 + PC);
@@ -914,37 +938,48 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
 #pragma unroll
       for (int q = 0; q < KPW; ++q) {
         const int kk = w * KPW + q;
-        const C2<float> bv = Xs[(c * PK + kk) * kXP + (lane & 15)];
+        C2<float> bv[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) bv[r] = Xs[(c * PK + kk) * XP + r * 16 + (lane & 15)];
 #pragma unroll
         for (int t = 0; t < 5; ++t) {
           const C2<float> av = Zs[(c * PK + kk) * kZP + t * 16 + (lane & 15)];
-          are[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.re, are[q][t], 0, 0, 0);
-          are[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.im, bv.im, are[q][t], 0, 0, 0);
-          aim[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv.im, aim[q][t], 0, 0, 0);
-          aim[q][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.im, bv.re, aim[q][t], 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+            are[q][t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv[r].re, are[q][t][r], 0, 0, 0);
+            are[q][t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.im, bv[r].im, are[q][t][r], 0, 0, 0);
+            aim[q][t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv[r].im, aim[q][t][r], 0, 0, 0);
+            aim[q][t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.im, bv[r].re, aim[q][t][r], 0, 0, 0);
+          }
         }
       }
     }
   }
-  C2<float>* Ys = Zs;  // [b 16][m 16][k YP]
+  C2<float>* Ys = Zs;  // [b 16 (stride YB)][m 16][k YP]
 #pragma unroll
-  for (int t = 0; t < 5; ++t) {
-    __syncthreads();
+  for (int r = 0; r < RB; ++r) {
+    if (b0[r] < 0) break;  // uniform over the workgroup
 #pragma unroll
-    for (int q = 0; q < KPW; ++q)
+    for (int t = 0; t < 5; ++t) {
+      __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = 4 * (lane >> 4) + r, b = lane & 15;
-        Ys[(b * 16 + m) * YP + w * KPW + q] = {are[q][t][r], aim[q][t][r]};
+      for (int q = 0; q < KPW; ++q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = 4 * (lane >> 4) + i, b = lane & 15;
+          Ys[b * YB + m * YP + w * KPW + q] = {are[q][t][r][i], aim[q][t][r][i]};
+        }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16 * 16 * PK / 256; ++i) {
+        const int e = tid + 256 * i, k = e & (PK - 1), m = (e >> LPK) & 15, b = e >> (LPK + 4);
+        const int row = m0 + t * 16 + m;
+        if (b0[r] + b < B && row < n && k0 + k < K)
+          Yh[((int64_t)(b0[r] + b) * n + row) * K + k0 + k] = Ys[b * YB + m * YP + k];
       }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < 16 * 16 * PK / 256; ++i) {
-      const int e = tid + 256 * i, k = e & (PK - 1), m = (e >> LPK) & 15, b = e >> (LPK + 4);
-      const int row = m0 + t * 16 + m;
-      if (b0 + b < B && row < n && k0 + k < K) Yh[((int64_t)(b0 + b) * n + row) * K + k0 + k] = Ys[(b * 16 + m) * YP + k];
     }
   }
+  (void)LNB;
 }
 
 // The live tiles of the matrix-core product (tiles of kPB right-hand sides
@@ -995,7 +1030,7 @@ void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2
 // used with idle flags on batches of at least rhs_first RHS tiles; with the
 // list the kernel picks the order from the live count, so the grid covers
 // both orders.
-template <int KPW, int PC>
+template <int KPW, int PC, int RB>
 void launch_product_mfma(const C2<float>* Zh, const C2<float>* X, C2<float>* Y, int n, int64_t G2, int B, bool tr,
                          int lgGx, int lgGy, hipStream_t s, const int* live, const int* idle, int* tl, int rf,
                          int lkg) {
@@ -1003,9 +1038,11 @@ void launch_product_mfma(const C2<float>* Zh, const C2<float>* X, C2<float>* Y, 
   const int n_mg = (n + kPM - 1) / kPM, n_bt = (B + kPB - 1) / kPB;
   const int64_t n_kt = (G2 + PK - 1) / PK;
   const bool use_list = idle && tl && n_bt >= rf;
-  const int64_t nwg_c = ((n_kt + 1) / 2 * 2 * n_mg * (use_list ? std::min(rf - 1, n_bt) : n_bt) + 7) / 8 * 8;
+  // groups of RB tiles in each order (the contiguous order runs below rf live tiles)
+  const int ng_c = ((use_list ? std::min(rf - 1, n_bt) : n_bt) + RB - 1) / RB, ng = (n_bt + RB - 1) / RB;
+  const int64_t nwg_c = ((n_kt + 1) / 2 * 2 * n_mg * ng_c + 7) / 8 * 8;
   const int KG = 1 << lkg, BG = 8 >> lkg;
-  const int64_t nwg_r = 8 * (((n_kt + 1) / 2 + KG - 1) / KG) * n_mg * ((n_bt + BG - 1) / BG) * 2;
+  const int64_t nwg_r = 8 * (((n_kt + 1) / 2 + KG - 1) / KG) * n_mg * ((ng + BG - 1) / BG) * 2;
   const int64_t nwg = use_list ? std::max(nwg_c, nwg_r) : n_bt < rf ? nwg_c : nwg_r;
   const int* list = use_list ? tl : nullptr;
   const int* cnt = use_list ? tl + n_bt : nullptr;
@@ -1014,11 +1051,11 @@ void launch_product_mfma(const C2<float>* Zh, const C2<float>* X, C2<float>* Y, 
     R3M_CHECK_HIP(hipGetLastError());
   }
   if (tr)
-    hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, true>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y, n,
-                       G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf, lkg);
+    hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, RB, true>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X,
+                       Y, n, G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf, lkg);
   else
-    hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, false>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X, Y,
-                       n, G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf, lkg);
+    hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, RB, false>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X,
+                       Y, n, G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf, lkg);
   R3M_CHECK_HIP(hipGetLastError());
 }
 
@@ -1037,11 +1074,13 @@ void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B
     C2<float>* yf = Y;
     const int rf = spec_rhs_first(plan), lkg = spec_kt_groups(plan);
     switch (spec_shape(plan)) {
-      case 1: return launch_product_mfma<1, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 2: return launch_product_mfma<2, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 3: return launch_product_mfma<2, 8>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 4: return launch_product_mfma<4, 4>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 5: return launch_product_mfma<1, 8>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 1: return launch_product_mfma<1, 4, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 2: return launch_product_mfma<2, 4, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 3: return launch_product_mfma<2, 8, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 4: return launch_product_mfma<4, 4, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 5: return launch_product_mfma<1, 8, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 6: return launch_product_mfma<2, 4, 2>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 7: return launch_product_mfma<1, 8, 2>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
       default: break;
     }
   }

@@ -563,7 +563,8 @@ def matvec_groups(ctx, store: Store, batch: Batch) -> int:
 PLAN_SPEC_TWO_PASS, PLAN_MFMA_FAR, PLAN_SPECTRAL = 1 << 12, 1 << 16, 1 << 17
 # frequency-product shapes of spectral stores: {frequencies per wave, columns
 # per staged chunk} of the matrix-core kernel; (0, 0) is the vector-unit kernel
-SPEC_SHAPES = ((0, 0), (1, 4), (2, 4), (2, 8), (4, 4), (1, 8))
+# (frequencies per wave, columns per staged chunk, 16-RHS tiles per workgroup); 0: vector units
+SPEC_SHAPES = ((0, 0, 0), (1, 4, 1), (2, 4, 1), (2, 8, 1), (4, 4, 1), (1, 8, 1), (2, 4, 2), (1, 8, 2))
 
 
 def spec_plan(shape: int, rhs_first: int = 8, two_pass: bool = False, kt_groups: int = 0) -> int:
@@ -584,7 +585,8 @@ def decode_plan(plan: int) -> dict:
     if plan & PLAN_SPECTRAL:
         k = plan & 15
         return {"kind": "spectral", "shape": k, "mfma": k != 0, "kpw": SPEC_SHAPES[k][0] if k < len(SPEC_SHAPES) else None,
-                "pc": SPEC_SHAPES[k][1] if k < len(SPEC_SHAPES) else None, "rhs_first": (plan >> 4) & 255,
+                "pc": SPEC_SHAPES[k][1] if k < len(SPEC_SHAPES) else None,
+                "rhs_tiles": SPEC_SHAPES[k][2] if k < len(SPEC_SHAPES) else None, "rhs_first": (plan >> 4) & 255,
                 "two_pass": bool(plan & PLAN_SPEC_TWO_PASS), "kt_groups": (plan >> 13) & 3}
     return {"kind": "compressed", "groups": plan & 0xFFFF, "mfma_far": bool(plan & PLAN_MFMA_FAR)}
 

@@ -1,8 +1,9 @@
 """Launch plans of the spectral matvec (r3m_matvec_plan, r3m_matvec_set_plan).
 
 The frequency product Y^(k) = Z^(k) X^(k) has several launch shapes: the
-vector-unit kernel and five matrix-core shapes (frequencies per wave, columns
-per staged chunk), and the matrix-core kernel has two workgroup orders chosen
+vector-unit kernel and seven matrix-core shapes (frequencies per wave, columns
+per staged chunk, 16-RHS tiles per workgroup), and the matrix-core kernel has
+two workgroup orders chosen
 by a live-tile threshold.  Every matrix-core shape sums each output over the
 columns in the same order (16x16x4 tiles of four consecutive columns, in
 increasing column order) and the order only decides which workgroup computes
@@ -22,7 +23,7 @@ from gpu_common import FREQ, rel_max, unit  # noqa: E402
 from workloads import codebooks as cb  # noqa: E402
 
 DEV = "cuda:0"
-MFMA_SHAPES = (1, 2, 3, 4, 5)
+MFMA_SHAPES = (1, 2, 3, 4, 5, 6, 7)
 
 
 @pytest.fixture(scope="module")
@@ -128,7 +129,7 @@ def test_plan_validation(lib):
     comp = pipeline.compressed_store(ctx, geom, L, 1, r3m.C128, r3m.C128, 1e-4, 40, DEV)
     batch = r3m.Batch.from_codebooks([cb.uniform(L, 2, 1)], [L], DEV)
     bad = [(s128, r3m.spec_plan(2, 8)),        # matrix cores need complex64 spectra
-           (s64, r3m.spec_plan(6, 8)),         # no such shape
+           (s64, r3m.spec_plan(len(r3m.SPEC_SHAPES), 8)),  # no such shape
            (s64, r3m.spec_plan(1, 0)),         # threshold below 1
            (s64, 4),                           # a compressed-store plan
            (comp, r3m.spec_plan(0, 8)),        # a spectral plan on a compressed store
@@ -144,7 +145,7 @@ def test_plan_validation(lib):
     # the default of an untuned pair: vector units for one right-hand side
     batch2 = r3m.Batch.from_codebooks([cb.uniform(L, 2, 2)], [L], DEV)
     assert r3m.decode_plan(r3m.matvec_plan(ctx, s64, batch2)) == {
-        "kind": "spectral", "shape": 0, "mfma": False, "kpw": 0, "pc": 0, "rhs_first": 8,
+        "kind": "spectral", "shape": 0, "mfma": False, "kpw": 0, "pc": 0, "rhs_tiles": 0, "rhs_first": 8,
         "two_pass": False, "kt_groups": 0}
 
 
