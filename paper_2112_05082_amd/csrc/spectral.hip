@@ -430,6 +430,10 @@ struct Fft2Args {
   // the workgroups then visit only their grids (the list replaces idle)
   const int* rl;
   int B;
+  // x and y by row (SoA): entry (unit u, row r) of RHS b at
+  // unit_off n_red + r units + u, so that a grid's gather and scatter touch
+  // consecutive units (written and read back by soa_transpose_kernel)
+  int soa;
 };
 
 __device__ __forceinline__ int at2(int gx, int gy, int Sx) { return gy * Sx + gx + (gx >> 4); }
@@ -598,7 +602,9 @@ __global__ void __launch_bounds__(fft2_threads<LG>()) fft2_kernel(Fft2Args A) {
         const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
         vv[i] = make_float2(0.f, 0.f);
         if (sv[i] == sc)
-          vv[i] = load_c2<VT>((const VT*)A.x + ((R.unit_off + (int64_t)gy * Lx + gx) * A.n_red + rc) * 2);
+          vv[i] = load_c2<VT>((const VT*)A.x +
+                              (A.soa ? R.unit_off * A.n_red + (int64_t)rc * Lx * Ly + (int64_t)gy * Lx + gx
+                                     : (R.unit_off + (int64_t)gy * Lx + gx) * A.n_red + rc) * 2);
       }
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
@@ -609,10 +615,9 @@ __global__ void __launch_bounds__(fft2_threads<LG>()) fft2_kernel(Fft2Args A) {
       line_stages<false, SGN, LG, false, false>(buf, tw, grid, Ly, G, G);
       line_stages<true, SGN, LG, false, true>(buf, tw, grid, G, Ly, G);
     } else {
-      line_stages<true, SGN, LG, true, false>(buf, tw, grid, G, G, Ly);
-      line_stages<false, SGN, LG, false, false>(buf, tw, grid, Ly, G, G);
-      // active rows of units gx < Lx, gy < Ly -> compact output (state
-      // bytes first, as for the input); masked shared rows receive zero
+      // active rows of units gx < Lx, gy < Ly -> compact output; the state
+      // bytes are loaded first, so that they arrive during the stages;
+      // masked shared rows receive zero
       int sv[kPer];
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
@@ -623,17 +628,81 @@ __global__ void __launch_bounds__(fft2_threads<LG>()) fft2_kernel(Fft2Args A) {
         else
           sv[i] = in ? (int)A.states[R.state_off + (int64_t)gy * Lx + gx] : -2;
       }
+      line_stages<true, SGN, LG, true, false>(buf, tw, grid, G, G, Ly);
+      line_stages<false, SGN, LG, false, false>(buf, tw, grid, Ly, G, G);
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
         const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
         if (sv[i] == sc || sv[i] == -3) {
           const float2 v = sv[i] == sc ? buf[at2(gx, gy, Sx)] : make_float2(0.f, 0.f);
-          store_c2<VT>((VT*)A.y + ((R.unit_off + (int64_t)gy * Lx + gx) * A.n_red + rc) * 2, v.x * scale,
+          store_c2<VT>((VT*)A.y + (A.soa ? R.unit_off * A.n_red + (int64_t)rc * Lx * Ly + (int64_t)gy * Lx + gx
+                                          : (R.unit_off + (int64_t)gy * Lx + gx) * A.n_red + rc) * 2,
+                       v.x * scale,
                        v.y * scale);
         }
       }
     }
   }
+}
+
+// Compact vectors between the unit-major layout of the library ([unit][n_red]
+// per RHS) and the row-major one of the fused transforms' gathers (SoA, see
+// Fft2Args::soa), one 64-unit x 16-row tile per work item through LDS; the
+// items of the right-hand sides of rl (a live list), else of every RHS whose
+// idle flag is clear.
+constexpr int kSoaU = 64, kSoaR = 16;
+// batches from this many compact entries on take the row-major copies (two
+// extra launches; on the 1,536-RHS batch the matvec takes 26.7 ms with them,
+// copies included, against 28.0 ms gathering from the unit-major vectors)
+constexpr int64_t kSoaMinEntries = (int64_t)1 << 20;
+__device__ __forceinline__ int rhs_count_list(const int* rl, int B) { return rl ? rl[B] : B; }
+template <typename VT, bool TO_SOA>
+__global__ void __launch_bounds__(256)
+soa_transpose_kernel(const RhsDev* __restrict__ rhs, const VT* __restrict__ in, VT* __restrict__ out, int n_red,
+                     int64_t per, int n_rc, const int* __restrict__ rl, const int* __restrict__ idle, int B) {
+  __shared__ VT tile[kSoaR][kSoaU + 1][2];
+  const int64_t items = per * rhs_count_list(rl, B);
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {  // uniform over the block
+    const int li = (int)(item / per);
+    const int64_t rem = item - (int64_t)li * per;
+    const int b = rl ? rl[li] : li;
+    if (!rl && idle && idle[b]) continue;
+    const RhsDev R = rhs[b];
+    const int64_t units = (int64_t)R.Lx * R.Ly;
+    const int64_t u0 = (rem / n_rc) * kSoaU;
+    const int r0 = (int)(rem % n_rc) * kSoaR;
+    if (u0 >= units) continue;
+    const int64_t base = R.unit_off * n_red;
+    __syncthreads();  // the previous item's tile reads are done
+    for (int e = threadIdx.x; e < kSoaU * kSoaR; e += blockDim.x) {
+      const int u = TO_SOA ? e / kSoaR : e % kSoaU, r = TO_SOA ? e % kSoaR : e / kSoaU;
+      if (u0 + u < units && r0 + r < n_red) {
+        const int64_t src = TO_SOA ? base + (u0 + u) * n_red + r0 + r : base + (int64_t)(r0 + r) * units + u0 + u;
+        tile[r][u][0] = in[2 * src];
+        tile[r][u][1] = in[2 * src + 1];
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < kSoaU * kSoaR; e += blockDim.x) {
+      const int u = TO_SOA ? e % kSoaU : e / kSoaR, r = TO_SOA ? e / kSoaU : e % kSoaR;
+      if (u0 + u < units && r0 + r < n_red) {
+        const int64_t dst = TO_SOA ? base + (int64_t)(r0 + r) * units + u0 + u : base + (u0 + u) * n_red + r0 + r;
+        out[2 * dst] = tile[r][u][0];
+        out[2 * dst + 1] = tile[r][u][1];
+      }
+    }
+  }
+}
+
+template <typename VT, bool TO_SOA>
+void soa_transpose(const BatchDesc& bd, const void* in, void* out, int n_red, const int* rl, const int* idle,
+                   hipStream_t s) {
+  const int n_rc = (n_red + kSoaR - 1) / kSoaR;
+  const int64_t per = (int64_t)((bd.max_units + kSoaU - 1) / kSoaU) * n_rc;
+  const int64_t items = per * bd.B;
+  hipLaunchKernelGGL((soa_transpose_kernel<VT, TO_SOA>), dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(items, 8192))),
+                     dim3(256), 0, s, bd.rhs, (const VT*)in, (VT*)out, n_red, per, n_rc, rl, idle, bd.B);
+  R3M_CHECK_HIP(hipGetLastError());
 }
 
 // square grids from 4 x 4 to 128 x 128
@@ -1212,6 +1281,14 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
     F.rl = rl;
     F.B = B;
     F.grid = (C2<float>*)X;
+    // wide batches gather from (and scatter to) row-major copies of the
+    // compact vectors: x's in the output grids' space (free until the
+    // product), y's in the input grids' space (free after it)
+    F.soa = (int64_t)bd.total_units * A.n_red >= kSoaMinEntries;
+    if (F.soa) {
+      soa_transpose<XT, true>(bd, x, Y, A.n_red, rl, idle, s);
+      F.x = Y;
+    }
     fft2_pass<false, XT>(F, s);
   } else {
     A.data = X;
@@ -1222,7 +1299,9 @@ void spectral_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t* stat
   product<T>((const C2<T>*)Z->far, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, plan);
   if (fused) {
     F.grid = (C2<float>*)Y;
+    if (F.soa) F.y = X;
     fft2_pass<true, YT>(F, s);
+    if (F.soa) soa_transpose<YT, false>(bd, X, y, A.n_red, rl, idle, s);
   } else {
     A.data = Y;
     fft_pass<T, kInvCols, YT>(A, lgGx, lgGy, ng, s);

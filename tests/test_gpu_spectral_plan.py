@@ -179,3 +179,36 @@ def test_fused_transforms_match_two_pass(lib, L):
         worst = max(worst, rel_max(ys[0], ys[1]))
     print(f"{L}x{L} store: fused vs two-pass transforms, max relative difference {worst:.1e}")
     assert worst <= 1e-6
+
+
+def test_fused_transforms_row_major_copies(lib):
+    """A batch wide enough (about 1.2 M compact entries) for the fused
+    transforms to gather from and scatter to row-major copies of x and y:
+    against the two-pass transforms on the same store and product plan, with
+    ragged arrays and one 1 x 1 array, complex128 and complex64 vectors."""
+    r3m, pipeline, ctx, geom = lib
+    L = 24
+    spec = pipeline.spectral_store(ctx, geom, L, 2, r3m.C64, DEV)
+    shapes = [(L, L), (L // 2, L), (L, L - 3), (1, 1)] * 20
+    rng = np.random.default_rng(4242)
+    books = [rng.integers(0, 2, lx * ly).astype(np.uint8) for lx, ly in shapes]
+    uoff = np.cumsum([0] + [lx * ly for lx, ly in shapes])[:-1].tolist()
+    batch = r3m.Batch(shapes, uoff, uoff, torch.from_numpy(np.concatenate(books)).to(DEV))
+    n1 = sum(lx * ly for lx, ly in shapes) * 40
+    assert n1 >= 1 << 20
+    x = torch.from_numpy(cb.random_complex(n1, 4243)).to(DEV)
+    worst = 0.0
+    for vt, xv in ((r3m.C128, x), (r3m.C64, x.to(torch.complex64))):
+        work = torch.empty(r3m.matvec_work_bytes(ctx, spec, batch, vt), dtype=torch.uint8, device=DEV)
+        ys = []
+        for two_pass in (False, True):
+            r3m.matvec_set_plan(ctx, spec, batch, r3m.spec_plan(6, 64, two_pass))
+            y = torch.zeros_like(xv)
+            r3m.r3m_retrieved_matvec(ctx, spec, batch, vt, xv, y, work)
+            torch.cuda.synchronize()
+            ys.append(y.to(torch.complex128).cpu().numpy())
+        assert np.abs(ys[0]).max() > 0
+        worst = max(worst, rel_max(ys[0], ys[1]))
+    print(f"wide batch ({n1} entries): fused transforms with row-major copies vs two-pass, "
+          f"max relative difference {worst:.1e}")
+    assert worst <= 1e-6
