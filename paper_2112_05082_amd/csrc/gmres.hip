@@ -270,9 +270,9 @@ __device__ double2 block_sum2(double2 v, double2* sh) {
 // The blocks stride over the items of the right-hand sides of rl (a live
 // list, see rhs_count), or of all B.  The consumer kernel sums the partials
 // itself (no grid-wide fence here).
-template <typename VB>
+template <typename VB, typename WB>
 __global__ void __launch_bounds__(kDotThreads)
-dots_partials_kernel(const VB* __restrict__ A, int64_t a_stride, const double2* __restrict__ Bv,
+dots_partials_kernel(const VB* __restrict__ A, int64_t a_stride, const WB* __restrict__ Bv,
                      const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
                      int* __restrict__ reset, const int* __restrict__ live, const int* __restrict__ idle,
                      const int* __restrict__ rl, int B) {
@@ -295,13 +295,13 @@ dots_partials_kernel(const VB* __restrict__ A, int64_t a_stride, const double2* 
     if (p >= P) continue;
     const int i0 = grp * kDotVec;
     const int nv = min(kDotVec, nvec - i0);
-    const double2* bb = Bv + r.off;
+    const WB* bb = Bv + r.off;
     const int64_t lo = (int64_t)p * kDotChunk + tid;
     double2 wv[kDotPer];
 #pragma unroll
     for (int e = 0; e < kDotPer; ++e) {
       const int64_t k = lo + (int64_t)e * kDotThreads;
-      wv[e] = k < r.N ? bb[k] : make_double2(0.0, 0.0);
+      wv[e] = k < r.N ? ld_b(bb + k) : make_double2(0.0, 0.0);
     }
     double2 av[kDotVec][kDotPer];
 #pragma unroll
@@ -400,9 +400,9 @@ finish_norm_kernel(const double* __restrict__ npart, int maxB, const RhsVec* __r
 // Blocks (of nsub runs, nb_max per RHS) are work items strided over by the
 // grid, for the right-hand sides of rl (see rhs_count).
 // Dynamic LDS: nvec double2.
-template <int KV, typename VB>
+template <int KV, typename VB, typename WB>
 __global__ void __launch_bounds__(256)
-gs_update_kernel(const VB* __restrict__ V, double2* __restrict__ w, const RhsVec* __restrict__ rv,
+gs_update_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* __restrict__ rv,
                  const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int n_part,
                  int nvec, int64_t ut, int do_norm, double* __restrict__ npart, int maxB, double2* __restrict__ H,
                  int m, int j, int mode, const int* __restrict__ run_prev, const int* __restrict__ idle,
@@ -456,7 +456,7 @@ gs_update_kernel(const VB* __restrict__ V, double2* __restrict__ w, const RhsVec
       double2 acc = make_double2(0.0, 0.0);
       // wave 0 reads w with the basis entries, so that the update after the
       // barrier does not wait for memory
-      const double2 wpre = q == 0 && live ? w[r.off + k] : make_double2(0.0, 0.0);
+      const double2 wpre = q == 0 && live ? ld_b(w + r.off + k) : make_double2(0.0, 0.0);
       double2 vv[KV > 0 ? KV : 1];
       if (KV > 0) {
         if (live) {
@@ -510,7 +510,7 @@ gs_update_kernel(const VB* __restrict__ V, double2* __restrict__ w, const RhsVec
         double2 wk = wpre;
         wk.x -= acc.x;
         wk.y -= acc.y;
-        w[r.off + k] = wk;
+        st_b(w + r.off + k, wk);
         nrm2 += wk.x * wk.x + wk.y * wk.y;
         if (KV > 0) wnew[e] = wk;
       }
@@ -555,9 +555,9 @@ gs_update_kernel(const VB* __restrict__ V, double2* __restrict__ w, const RhsVec
 // (MODE 2, block-Jacobi; a block holds whole units).  MODE 0 writes V only.
 // Blocks (nb_max per RHS) are work items strided over by the grid, for the
 // right-hand sides of rl (see rhs_count).
-template <typename OT, int MODE, typename VB>
+template <typename OT, int MODE, typename VB, typename WB>
 __global__ void __launch_bounds__(256)
-normalize_step_kernel(const double2* __restrict__ w, VB* __restrict__ V, const RhsVec* __restrict__ rv,
+normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec* __restrict__ rv,
                       RhsState* __restrict__ st, const double* __restrict__ npart, int maxB, int n_npart,
                       double2* __restrict__ H, double2* __restrict__ g, double* __restrict__ cs,
                       double2* __restrict__ sn, int m, int j, double tol, int* __restrict__ n_running,
@@ -609,7 +609,7 @@ normalize_step_kernel(const double2* __restrict__ w, VB* __restrict__ V, const R
     const bool in = k < r.N;
     double2 v = make_double2(0.0, 0.0);
     if (in) {
-      const double2 wk = w[r.off + k];
+      const double2 wk = ld_b(w + r.off + k);
       if (ok) v = make_double2(wk.x / nv, wk.y / nv);
       st_b(V + (int64_t)(j + 1) * ut + r.off + k, v);
     }
@@ -1143,16 +1143,24 @@ struct GmresRun {
     }
   }
 
+  // The Arnoldi vector w (the matvec output, orthogonalised in place) is
+  // kept in complex64 with a complex64 basis on spectral stores (the
+  // product it holds is an FP32 one; FP64 arithmetic throughout), in the
+  // first half of W.w
   void arnoldi_step(const r3m_store* Z, int j, double tol) {
-    if (vb32)
-      arnoldi_step_t<float2>(Z, j, tol);
+    if (vb32 && store_is_spectral(Z))
+      arnoldi_step_t<float2, float2>(Z, j, tol);
+    else if (vb32)
+      arnoldi_step_t<float2, double2>(Z, j, tol);
     else
-      arnoldi_step_t<double2>(Z, j, tol);
+      arnoldi_step_t<double2, double2>(Z, j, tol);
   }
 
-  template <typename VB>
+  template <typename VB, typename WB>
   void arnoldi_step_t(const r3m_store* Z, int j, double tol) {
     VB* V = reinterpret_cast<VB*>(W.V);
+    WB* wv = reinterpret_cast<WB*>(W.w);
+    constexpr bool wd = std::is_same<WB, double2>::value;
     const int* live = run_slot(j - 1);  // j = 0: set by the cycle start
     const VB* vj = V + (int64_t)j * ut;
     // the right-hand sides with work in this step (not idle at its start);
@@ -1162,13 +1170,15 @@ struct GmresRun {
       hipLaunchKernelGGL(live_rhs_kernel, dim3(1), dim3(1024), 0, s, (const int*)W.idle, B, W.rl);
       rl = W.rl;
     }
-    if (wts)
+    if (wts) {
+      R3M_REQUIRE(wd, R3M_ERR_UNSUPPORTED, "relaxed solves keep w in complex128");
       launch_spectral_ex(Z, *bd, batch->states, input_in_xs(Z) ? Z->near_dtype : R3M_C128,
                          input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, R3M_C128, W.w, W.mv_partial, s, live,
                          wts, tr, W.idle);
-    else
-      launch_matvec_pre(Z, *bd, batch->states, input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, W.w,
-                        W.mv_partial, lists_for(Z), G, s, live, W.idle, rl);
+    } else {
+      launch_matvec_pre(Z, *bd, batch->states, input_in_xs(Z) ? (const void*)W.xs : (const void*)vj, wv,
+                        W.mv_partial, lists_for(Z), G, s, live, W.idle, rl, wd ? R3M_C128 : R3M_C64);
+    }
     const int maxB = (int)((maxN + 63) / 64 + 1);
     // long vectors (more than 64 chunk partials per coefficient): sum the
     // partials once in their own launch rather than in every update block
@@ -1180,7 +1190,7 @@ struct GmresRun {
     const unsigned dgrid = stride_grid((int64_t)maxP * ngrp * B), ugrid = stride_grid(nb_u * B);
     const size_t ulds = (size_t)nvec * sizeof(double2);
     // CGS2, first pass: inner products with the basis, then the update
-    hipLaunchKernelGGL(dots_partials_kernel<VB>, dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, W.w, W.rv, nvec, maxP,
+    hipLaunchKernelGGL((dots_partials_kernel<VB, WB>), dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, wv, W.rv, nvec, maxP,
                        W.dpart, run_slot(j), live, W.idle, rl, B);
     if (long_vec)
       hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP, nvec,
@@ -1191,7 +1201,7 @@ struct GmresRun {
       // the first update also forms the second pass's inner products
       const int maxP2 = (int)fold_blocks(maxN);
 #define R3M_FOLDED(KV)                                                                                             \
-  hipLaunchKernelGGL((gs_update_kernel<KV, VB>), dim3(ugrid), dim3(256), ulds, s, V, W.w, W.rv, W.st, h0, h0P, h0n, nvec, \
+  hipLaunchKernelGGL((gs_update_kernel<KV, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, h0, h0P, h0n, nvec, \
                      ut, 0, W.npart, maxB, W.H, m, j, 0, live, W.idle, nsub, kDotChunk, W.dpart2, maxP2, rl, B, nb_u)
       if (nvec <= 8)
         R3M_FOLDED(2);
@@ -1201,21 +1211,21 @@ struct GmresRun {
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart2, maxP2,
                            nvec, W.rv, W.hsum, live, W.idle, 64 * nsub);
-      hipLaunchKernelGGL((gs_update_kernel<0, VB>), dim3(ugrid), dim3(256), ulds, s, V, W.w, W.rv, W.st,
+      hipLaunchKernelGGL((gs_update_kernel<0, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st,
                          long_vec ? (const double2*)W.hsum : (const double2*)W.dpart2, long_vec ? 1 : maxP2,
                          long_vec ? 1 : 0, nvec, ut, 1, W.npart, maxB, W.H, m, j, 1, live, W.idle, nsub, 64 * nsub,
                          (double2*)nullptr, 0, rl, B, nb_u);
     } else {
-      hipLaunchKernelGGL((gs_update_kernel<0, VB>), dim3(ugrid), dim3(256), ulds, s, V, W.w, W.rv, W.st, h0, h0P, h0n,
+      hipLaunchKernelGGL((gs_update_kernel<0, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, h0, h0P, h0n,
                          nvec, ut, 0, W.npart, maxB, W.H, m, j, 0, live, W.idle, nsub, kDotChunk, (double2*)nullptr, 0,
                          rl, B, nb_u);
       // CGS2, second pass
-      hipLaunchKernelGGL(dots_partials_kernel<VB>, dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, W.w, W.rv, nvec, maxP,
+      hipLaunchKernelGGL((dots_partials_kernel<VB, WB>), dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, wv, W.rv, nvec, maxP,
                          W.dpart, (int*)nullptr, live, W.idle, rl, B);
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
                            nvec, W.rv, W.hsum, live, W.idle, kDotChunk);
-      hipLaunchKernelGGL((gs_update_kernel<0, VB>), dim3(ugrid), dim3(256), ulds, s, V, W.w, W.rv, W.st, h0, h0P, h0n,
+      hipLaunchKernelGGL((gs_update_kernel<0, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, h0, h0P, h0n,
                          nvec, ut, 1, W.npart, maxB, W.H, m, j, 1, live, W.idle, nsub, kDotChunk, (double2*)nullptr, 0,
                          rl, B, nb_u);
     }
@@ -1234,14 +1244,14 @@ struct GmresRun {
     const size_t glds = glds0 + (stage ? (size_t)n_states * n_a * n_a * 8 : 0);
     const bool c64 = Z->near_dtype == R3M_C64;
 #define R3M_NORMALIZE(OT, MODE, XS)                                                                                  \
-  hipLaunchKernelGGL((normalize_step_kernel<OT, MODE, VB>), ngrid, dim3(nthr), glds, s, W.w, V, W.rv, W.st, np, npB,  \
+  hipLaunchKernelGGL((normalize_step_kernel<OT, MODE, VB, WB>), ngrid, dim3(nthr), glds, s, wv, V, W.rv, W.st, np, npB, \
                      npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states, W.soff, \
                      n_a, n_states, XS, pu, W.idle, rl, B, nb_n, stage)
     if (ilu_r) {
       // V_{j+1}, then the next step's input M^-1 V_{j+1} by the colour solves
       // (W.w, the matvec output, is free once normalised)
       R3M_NORMALIZE(double, 0, (double*)nullptr);
-      if constexpr (std::is_same<VB, double2>::value)
+      if constexpr (std::is_same<VB, double2>::value && std::is_same<WB, double2>::value)
         launch_ilu_apply(Z, *bd, ilu_r, W.ilu, V + (int64_t)(j + 1) * ut, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s,
                          run_slot(j), wts == nullptr);
     } else if (pre && c64) {

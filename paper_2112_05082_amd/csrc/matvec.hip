@@ -1765,11 +1765,12 @@ static void launch_typed(const r3m_store* Z, const BatchDesc& bd, const uint8_t*
 // the near retrieval lists (build_near_lists) must be current at lists
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
                        void* partial, const void* lists, int chunks, hipStream_t stream, const int* live,
-                       const int* idle, const int* rl) {
+                       const int* idle, const int* rl, r3m_dtype y_type) {
   if (store_is_spectral(Z)) {
-    launch_spectral(Z, bd, states, Z->near_dtype, xs, R3M_C128, y, partial, stream, live, idle, chunks, rl);
+    launch_spectral(Z, bd, states, Z->near_dtype, xs, y_type, y, partial, stream, live, idle, chunks, rl);
     return;
   }
+  R3M_REQUIRE(y_type == R3M_C128, R3M_ERR_UNSUPPORTED, "compressed stores write complex128 products");
   if (Z->near_dtype == R3M_C128)
     launch_core<double, double>(Z, bd, states, (const double*)xs, (double*)y, (char*)partial, lists, chunks, stream,
                                 live, idle);

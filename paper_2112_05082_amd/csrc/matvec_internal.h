@@ -76,10 +76,10 @@ void launch_matvec(r3m_ctx ctx, const r3m_store* Z, const BatchDesc& bd, const u
 // every right-hand side has converged); idle as above
 // rl (device, nullable): the right-hand sides with work, as a list (rl[0..n)
 // indices, rl[B] = n, every other one idle); the spectral transforms then
-// visit only their grids
+// visit only their grids; y_type: R3M_C128, or R3M_C64 on spectral stores
 void launch_matvec_pre(const r3m_store* Z, const BatchDesc& bd, const uint8_t* states, const void* xs, void* y,
                        void* partial, const void* lists, int chunks, hipStream_t stream, const int* live,
-                       const int* idle = nullptr, const int* rl = nullptr);
+                       const int* idle = nullptr, const int* rl = nullptr, r3m_dtype y_type = R3M_C128);
 
 // spectral stores (far_dtype R3M_SPEC_*): the whole product by FFT
 bool store_is_spectral(const r3m_store* Z);

@@ -1392,8 +1392,11 @@ void launch_spectral(const r3m_store* Z, const BatchDesc& bd, const uint8_t* sta
                      const void* x, r3m_dtype y_type, void* y, void* work, hipStream_t s, const int* live,
                      const int* idle, int plan, const int* rl) {
   const bool xd = x_type == R3M_C128, yd = y_type == R3M_C128;
-  if (Z->far_dtype == R3M_SPEC_C64 && !xd && yd) {  // the solver's form: the list reaches the transforms
-    spectral_typed<float, float, double>(Z, bd, states, x, y, work, s, live, nullptr, false, nullptr, idle, plan, rl);
+  if (Z->far_dtype == R3M_SPEC_C64 && !xd) {  // the solver's forms: the list reaches the transforms
+    if (yd)
+      spectral_typed<float, float, double>(Z, bd, states, x, y, work, s, live, nullptr, false, nullptr, idle, plan, rl);
+    else
+      spectral_typed<float, float, float>(Z, bd, states, x, y, work, s, live, nullptr, false, nullptr, idle, plan, rl);
     return;
   }
   launch_spectral_ex(Z, bd, states, x_type, x, y_type, y, work, s, live, nullptr, false, idle, plan);
