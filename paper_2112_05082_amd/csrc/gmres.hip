@@ -23,6 +23,11 @@ constexpr int kDotChunk = 1024;
 constexpr int kDotThreads = 256;
 constexpr int kDotPer = kDotChunk / kDotThreads;  // elements per thread in a chunk
 constexpr int kDotVec = 4;                        // basis vectors per fused-dot block
+// The folded Gram-Schmidt update keeps up to 4 basis entries per wave in
+// registers, so it takes steps with at most 16 basis vectors (with 8 per
+// wave its register count leaves three waves per SIMD, and it measured no
+// faster than the two separate passes).
+constexpr int kFoldMaxVec = 16;
 constexpr int kCheckEvery = 4;
 
 struct RhsVec {
@@ -546,6 +551,131 @@ gs_update_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* __r
   }
 }
 
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+
+// The update of gs_update_kernel for long vectors (blocks of four 64-element
+// runs): every thread takes its own element of the block and loops over the
+// basis vectors (loads issued in groups before the products), so that all
+// four waves stream at every basis size.  FOLD (nvec <= kFoldMaxVec): the
+// element's basis entries stay in registers for the second pass's inner
+// products, each wave sums them over its lanes and the block adds the waves
+// in a fixed order into partial2[b][i][block].  Same arguments and outputs as
+// gs_update_kernel with nsub = 4.
+template <bool FOLD, typename VB, typename WB>
+__global__ void __launch_bounds__(256)
+gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* __restrict__ rv,
+                    const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int n_part,
+                    int nvec, int64_t ut, int do_norm, double* __restrict__ npart, int maxB,
+                    double2* __restrict__ H, int m, int j, int mode, const int* __restrict__ run_prev,
+                    const int* __restrict__ idle, int part_chunk, double2* __restrict__ partial2, int maxP2,
+                    const int* __restrict__ rl, int B, int64_t nb_max) {
+  if (run_prev && *run_prev == 0) return;
+  constexpr int kEl = 256;  // elements per block: four 64-element runs
+  extern __shared__ double2 hb[];
+  __shared__ double2 sh[4];
+  __shared__ double2 red[4][kFoldMaxVec];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t items = nb_max * rhs_count(rl, B);
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {  // uniform over the block
+    const int li = (int)(item / nb_max);
+    const int64_t blk = item - li * nb_max;
+    const int b = rhs_at(rl, li);
+    if (!rl && idle && idle[b]) continue;
+    const RhsVec r = rv[b];
+    const int64_t nb = (r.N + kEl - 1) / kEl;
+    if (blk >= nb) continue;
+    const int P = n_part > 0 ? n_part : (int)((r.N + part_chunk - 1) / part_chunk);
+    __syncthreads();  // the previous item's reads of hb and red are done
+    for (int i = tid; i < nvec; i += blockDim.x) {
+      const double2* pp = partial + ((size_t)b * nvec + i) * maxP;
+      double2 t = make_double2(0.0, 0.0);
+      for (int p = 0; p < P; ++p) {
+        const double2 v = pp[p];
+        t.x += v.x;
+        t.y += v.y;
+      }
+      hb[i] = t;
+      if (blk == 0) {
+        double2* h = H + (size_t)b * (m + 1) * m + (size_t)i * m + j;
+        if (mode == 0) {
+          *h = t;
+        } else {
+          h->x += t.x;
+          h->y += t.y;
+        }
+      }
+    }
+    __syncthreads();
+    const int64_t k = blk * kEl + tid;
+    const bool live = k < r.N && st[b].active;
+    double2 wk = live ? ld_b(w + r.off + k) : make_double2(0.0, 0.0);
+    double nrm2 = 0.0;
+    VB vv[FOLD ? kFoldMaxVec : 8];
+    if (live) {
+      const VB* vk = V + r.off + k;
+      double2 acc = make_double2(0.0, 0.0);
+      if (FOLD) {
+#pragma unroll
+        for (int i = 0; i < kFoldMaxVec; ++i)
+          if (i < nvec) vv[i] = vk[(int64_t)i * ut];
+#pragma unroll
+        for (int i = 0; i < kFoldMaxVec; ++i)
+          if (i < nvec) {
+            const double2 c = cmul(hb[i], to_d2(vv[i]));
+            acc.x += c.x;
+            acc.y += c.y;
+          }
+      } else {
+        for (int i0 = 0; i0 < nvec; i0 += 8) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (i0 + u < nvec) vv[u] = vk[(int64_t)(i0 + u) * ut];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (i0 + u < nvec) {
+              const double2 c = cmul(hb[i0 + u], to_d2(vv[u]));
+              acc.x += c.x;
+              acc.y += c.y;
+            }
+        }
+      }
+      wk.x -= acc.x;
+      wk.y -= acc.y;
+      st_b(w + r.off + k, wk);
+      nrm2 = wk.x * wk.x + wk.y * wk.y;
+    }
+    if (FOLD) {
+#pragma unroll
+      for (int i = 0; i < kFoldMaxVec; ++i) {
+        if (i < nvec) {  // uniform over the block
+          double2 d = live ? cmulc(to_d2(vv[i]), wk) : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int o = 32; o >= 1; o >>= 1) {
+            d.x += __shfl_xor(d.x, o);
+            d.y += __shfl_xor(d.y, o);
+          }
+          if (lane == 0) red[wave][i] = d;
+        }
+      }
+      __syncthreads();
+      if (tid < nvec) {
+        double2 t = red[0][tid];
+#pragma unroll
+        for (int q = 1; q < 4; ++q) {
+          t.x += red[q][tid].x;
+          t.y += red[q][tid].y;
+        }
+        partial2[((size_t)b * nvec + tid) * maxP2 + blk] = t;
+      }
+    }
+    if (do_norm) {
+      const double2 t = block_sum2(make_double2(nrm2, 0.0), sh);
+      if (tid == 0) npart[(size_t)b * maxB + blk] = t.x;
+    }
+  }
+}
+
 // ||w|| from the per-block parts of the preceding gs_update_kernel (n_npart
 // of them; 0: one per 64 elements), summed by every block in the same fixed
 // order; block 0 sets H[j+1][j] = ||w|| and
@@ -966,11 +1096,6 @@ struct Work {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// The folded Gram-Schmidt update keeps up to 4 basis entries per wave in
-// registers, so it takes steps with at most 16 basis vectors (with 8 per
-// wave its register count leaves three waves per SIMD, and it measured no
-// faster than the two separate passes).
-constexpr int kFoldMaxVec = 16;
 // 64-element runs per update block: four for long vectors (more than 64
 // chunks of kDotChunk: a quarter of the workgroups, which matters once most
 // right-hand sides of a wide batch are idle and their workgroups only
@@ -1197,37 +1322,49 @@ struct GmresRun {
                          W.rv, W.hsum, live, W.idle, kDotChunk);
     const double2* h0 = long_vec ? (const double2*)W.hsum : (const double2*)W.dpart;
     const int h0P = long_vec ? 1 : maxP, h0n = long_vec ? 1 : 0;
+    // one Gram-Schmidt update (kv > 0: folding the second pass's inner
+    // products): the element-parallel kernel for long vectors
+    auto update = [&](int kv, const double2* hp, int hP, int hn, int do_norm, int mode, int pchunk, double2* p2,
+                      int mP2) {
+      if (nsub == 4 && kv > 0)
+        hipLaunchKernelGGL((gs_update_el_kernel<true, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, hp,
+                           hP, hn, nvec, ut, do_norm, W.npart, maxB, W.H, m, j, mode, live, W.idle, pchunk, p2, mP2, rl,
+                           B, nb_u);
+      else if (nsub == 4)
+        hipLaunchKernelGGL((gs_update_el_kernel<false, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st,
+                           hp, hP, hn, nvec, ut, do_norm, W.npart, maxB, W.H, m, j, mode, live, W.idle, pchunk, p2,
+                           mP2, rl, B, nb_u);
+      else if (kv == 2)
+        hipLaunchKernelGGL((gs_update_kernel<2, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, hp, hP,
+                           hn, nvec, ut, do_norm, W.npart, maxB, W.H, m, j, mode, live, W.idle, nsub, pchunk, p2, mP2,
+                           rl, B, nb_u);
+      else if (kv == 4)
+        hipLaunchKernelGGL((gs_update_kernel<4, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, hp, hP,
+                           hn, nvec, ut, do_norm, W.npart, maxB, W.H, m, j, mode, live, W.idle, nsub, pchunk, p2, mP2,
+                           rl, B, nb_u);
+      else
+        hipLaunchKernelGGL((gs_update_kernel<0, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, hp, hP,
+                           hn, nvec, ut, do_norm, W.npart, maxB, W.H, m, j, mode, live, W.idle, nsub, pchunk, p2, mP2,
+                           rl, B, nb_u);
+    };
     if (nvec <= kFoldMaxVec && W.dpart2) {
       // the first update also forms the second pass's inner products
       const int maxP2 = (int)fold_blocks(maxN);
-#define R3M_FOLDED(KV)                                                                                             \
-  hipLaunchKernelGGL((gs_update_kernel<KV, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, h0, h0P, h0n, nvec, \
-                     ut, 0, W.npart, maxB, W.H, m, j, 0, live, W.idle, nsub, kDotChunk, W.dpart2, maxP2, rl, B, nb_u)
-      if (nvec <= 8)
-        R3M_FOLDED(2);
-      else
-        R3M_FOLDED(4);
-#undef R3M_FOLDED
+      update(nvec <= 8 ? 2 : 4, h0, h0P, h0n, 0, 0, kDotChunk, W.dpart2, maxP2);
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart2, maxP2,
                            nvec, W.rv, W.hsum, live, W.idle, 64 * nsub);
-      hipLaunchKernelGGL((gs_update_kernel<0, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st,
-                         long_vec ? (const double2*)W.hsum : (const double2*)W.dpart2, long_vec ? 1 : maxP2,
-                         long_vec ? 1 : 0, nvec, ut, 1, W.npart, maxB, W.H, m, j, 1, live, W.idle, nsub, 64 * nsub,
-                         (double2*)nullptr, 0, rl, B, nb_u);
+      update(0, long_vec ? (const double2*)W.hsum : (const double2*)W.dpart2, long_vec ? 1 : maxP2, long_vec ? 1 : 0,
+             1, 1, 64 * nsub, (double2*)nullptr, 0);
     } else {
-      hipLaunchKernelGGL((gs_update_kernel<0, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, h0, h0P, h0n,
-                         nvec, ut, 0, W.npart, maxB, W.H, m, j, 0, live, W.idle, nsub, kDotChunk, (double2*)nullptr, 0,
-                         rl, B, nb_u);
+      update(0, h0, h0P, h0n, 0, 0, kDotChunk, (double2*)nullptr, 0);
       // CGS2, second pass
       hipLaunchKernelGGL((dots_partials_kernel<VB, WB>), dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, wv, W.rv, nvec, maxP,
                          W.dpart, (int*)nullptr, live, W.idle, rl, B);
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
                            nvec, W.rv, W.hsum, live, W.idle, kDotChunk);
-      hipLaunchKernelGGL((gs_update_kernel<0, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, h0, h0P, h0n,
-                         nvec, ut, 1, W.npart, maxB, W.H, m, j, 1, live, W.idle, nsub, kDotChunk, (double2*)nullptr, 0,
-                         rl, B, nb_u);
+      update(0, h0, h0P, h0n, 1, 1, kDotChunk, (double2*)nullptr, 0);
     }
     if (long_vec)
       hipLaunchKernelGGL(finish_norm_kernel, dim3(B), dim3(256), 0, s, (const double*)W.npart, maxB, W.rv, W.nsum,
