@@ -615,9 +615,10 @@ __global__ void __launch_bounds__(fft2_threads<LG>()) fft2_kernel(Fft2Args A) {
       line_stages<false, SGN, LG, false, false>(buf, tw, grid, Ly, G, G);
       line_stages<true, SGN, LG, false, true>(buf, tw, grid, G, Ly, G);
     } else {
-      // active rows of units gx < Lx, gy < Ly -> compact output; the state
-      // bytes are loaded first, so that they arrive during the stages;
-      // masked shared rows receive zero
+      line_stages<true, SGN, LG, true, false>(buf, tw, grid, G, G, Ly);
+      line_stages<false, SGN, LG, false, false>(buf, tw, grid, Ly, G, G);
+      // active rows of units gx < Lx, gy < Ly -> compact output (state
+      // bytes first, as for the input); masked shared rows receive zero
       int sv[kPer];
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
@@ -628,8 +629,6 @@ __global__ void __launch_bounds__(fft2_threads<LG>()) fft2_kernel(Fft2Args A) {
         else
           sv[i] = in ? (int)A.states[R.state_off + (int64_t)gy * Lx + gx] : -2;
       }
-      line_stages<true, SGN, LG, true, false>(buf, tw, grid, G, G, Ly);
-      line_stages<false, SGN, LG, false, false>(buf, tw, grid, Ly, G, G);
 #pragma unroll
       for (int i = 0; i < kPer; ++i) {
         const int t = threadIdx.x + i * kNT, gx = t & (G - 1), gy = t >> LG;
