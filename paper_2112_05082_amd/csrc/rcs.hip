@@ -132,62 +132,167 @@ __global__ void macro_radiation_kernel(GeomDev g, const double* __restrict__ dir
 }
 
 constexpr int kRcsThreads = 256;
+constexpr int kRcsDirs = 64;      // directions per block, one per lane
+constexpr int kRcsWaves = kRcsThreads / 64;
+constexpr int kRcsExact = 32;     // units between exact phase evaluations
 
-__global__ void __launch_bounds__(kRcsThreads)
-rcs_kernel(GeomDev g, const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states,
-           const double2* __restrict__ I, const double2* __restrict__ F, const double* __restrict__ dirs, int n_dir,
-           int n, int n_a, int n_v, int n_states, double k, double px, double py, double scale,
-           double* __restrict__ sigma) {
-  __shared__ double sh[kRcsThreads / 64][6];
-  const int d = blockIdx.x, b = blockIdx.y;
-  const RhsDev R = rhs[b];
-  const double th = dirs[2 * d], ph = dirs[2 * d + 1];
-  const double rx = sin(th) * cos(ph), ry = sin(th) * sin(ph), rz = cos(th);
+// Array sums of one item over all units of a RHS: for SH false, the compact
+// entries rc..rc+MC-1 of units in coding states s0..s0+NSG-1 (A[j][c] for
+// state s0 + j); for SH true, shared entries rc..rc+MC-1, zero where D_k
+// masks them.  The chunk of each unit is uniform across the wave (scalar
+// loads); the lane's phase
+// exp(j k r_hat . c_u) advances by one complex product per unit along x from
+// an exact value every kRcsExact units and at each row start.
+template <bool SH, int NSG, int MC>
+__device__ __forceinline__ void rcs_array_sums(const GeomDev& g, const RhsDev& R, const uint8_t* __restrict__ states,
+                                               const double2* __restrict__ I, int n_a, int n_v, int n_states,
+                                               int s0, int rc, int lane, double k, double rx, double ry, double px,
+                                               double py, double stx_r, double stx_i, double (&ar)[NSG][MC],
+                                               double (&ai)[NSG][MC]) {
+#pragma unroll
+  for (int j = 0; j < NSG; ++j)
+#pragma unroll
+    for (int c = 0; c < MC; ++c) ar[j][c] = ai[j][c] = 0.0;
+  int cls[MC];  // a shared entry's class decides where D_k masks it
+#pragma unroll
+  for (int c = 0; c < MC; ++c) cls[c] = (SH && rc + c >= n_a) ? g.common_ext[rc + c - n_a] : 0;
   const int64_t units = (int64_t)R.Lx * R.Ly;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  const double2* Fd = F + (size_t)d * n * 3;
-  for (int64_t u = threadIdx.x; u < units; u += blockDim.x) {
-    int s = states[R.state_off + u];
-    s = s < n_states ? s : n_states - 1;
-    const int64_t ix = u % R.Lx, iy = u / R.Lx;
-    const double cx = (double)ix * px, cy = (double)iy * py;
-    double sn, cs;
-    sincos(k * (rx * cx + ry * cy), &sn, &cs);
-    double loc[6] = {0, 0, 0, 0, 0, 0};
-    const double2* Iu = I + (R.unit_off + u) * n_v;
-    for (int m = 0; m < n_v; ++m) {
-      const int mm = compact_to_macro(g, n_a, s, m, ix, iy);
-      if (mm < 0) continue;  // a masked extended basis carries no current
-      const double2 cur = Iu[m];
-      const double2* f = Fd + (size_t)mm * 3;
-      for (int q = 0; q < 3; ++q) {
-        loc[2 * q] += cur.x * f[q].x - cur.y * f[q].y;
-        loc[2 * q + 1] += cur.x * f[q].y + cur.y * f[q].x;
+  const double2* Ip = I + R.unit_off * n_v + rc;
+  int ix = 0, iy = 0;
+  double pr = 0.0, pi = 0.0;
+  for (int64_t u0 = 0; u0 < units; u0 += 64) {
+    const int n_in = (int)min<int64_t>(64, units - u0);
+    const int st_l = (!SH && lane < n_in) ? (int)states[R.state_off + u0 + lane] : 0;
+    for (int i = 0; i < n_in; ++i, Ip += n_v) {
+      double2 cur[MC];
+#pragma unroll
+      for (int c = 0; c < MC; ++c) cur[c] = Ip[c];
+      if (ix % kRcsExact == 0) sincos(k * (rx * (double)ix * px + ry * (double)iy * py), &pi, &pr);
+      if (SH) {
+#pragma unroll
+        for (int c = 0; c < MC; ++c) {
+          const bool keep = !((cls[c] == 1 && ix == 0) || (cls[c] == 2 && iy == 0));
+          const double cx = keep ? cur[c].x : 0.0, cy = keep ? cur[c].y : 0.0;
+          ar[0][c] = fma(-pi, cy, fma(pr, cx, ar[0][c]));
+          ai[0][c] = fma(pi, cx, fma(pr, cy, ai[0][c]));
+        }
+      } else {
+        int s = __builtin_amdgcn_readlane(st_l, i);
+        s = s < n_states ? s : n_states - 1;
+#pragma unroll
+        for (int j = 0; j < NSG; ++j) {
+          if (s == s0 + j) {  // uniform
+#pragma unroll
+            for (int c = 0; c < MC; ++c) {
+              ar[j][c] = fma(-pi, cur[c].y, fma(pr, cur[c].x, ar[j][c]));
+              ai[j][c] = fma(pi, cur[c].x, fma(pr, cur[c].y, ai[j][c]));
+            }
+          }
+        }
+      }
+      const double t = pr * stx_r - pi * stx_i;
+      pi = pr * stx_i + pi * stx_r;
+      pr = t;
+      if (++ix == R.Lx) {
+        ix = 0;
+        ++iy;
       }
     }
-    for (int q = 0; q < 3; ++q) {
-      acc[2 * q] += loc[2 * q] * cs - loc[2 * q + 1] * sn;
-      acc[2 * q + 1] += loc[2 * q] * sn + loc[2 * q + 1] * cs;
+  }
+}
+
+// N(d) += sum over an item's entries of A F_{macro RWG}(d), entries r0..r_end-1 only
+template <bool SH, int NSG, int MC>
+__device__ __forceinline__ void rcs_combine(const GeomDev& g, const double2* __restrict__ Fd, int n_a,
+                                            int n_states, int s0, int rc, int r0, int r_end,
+                                            const double (&ar)[NSG][MC], const double (&ai)[NSG][MC],
+                                            double (&N)[6]) {
+#pragma unroll
+  for (int j = 0; j < NSG; ++j) {
+    if (s0 + j < n_states) {
+#pragma unroll
+      for (int c = 0; c < MC; ++c) {
+        const int r = rc + c;
+        if (r >= r0 && r < r_end) {
+          const int mm = SH ? g.n_st + (r - n_a) : (s0 + j) * n_a + r;
+          const double2* f = Fd + (size_t)mm * 3;
+          for (int q = 0; q < 3; ++q) {
+            N[2 * q] += ar[j][c] * f[q].x - ai[j][c] * f[q].y;
+            N[2 * q + 1] += ar[j][c] * f[q].y + ai[j][c] * f[q].x;
+          }
+        }
+      }
     }
   }
-  for (int q = 0; q < 6; ++q)
-    for (int o = 32; o >= 1; o >>= 1) acc[q] += __shfl_xor(acc[q], o);
-  if ((threadIdx.x & 63) == 0)
-    for (int q = 0; q < 6; ++q) sh[threadIdx.x >> 6][q] = acc[q];
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double N[6];
-    for (int q = 0; q < 6; ++q) {
-      N[q] = sh[0][q];
-      for (int w = 1; w < kRcsThreads / 64; ++w) N[q] += sh[w][q];
+}
+
+// Bistatic RCS of a batch, one block per (RHS, 64 directions), lane =
+// direction.  The sum over units is taken first, per compact entry r and
+// coding state s (array factor):
+//   A_{s,r}(d) = sum_{u in state s} exp(j k r_hat_d . c_u) I_{u,r},
+// then N(d) = sum_{s,r} A_{s,r}(d) F_{macro(s,r)}(d) (a shared basis of a
+// connected geometry has one A, over the units where D_k keeps it).  Items
+// of NSG states x MC contiguous entries are split over the block's waves; N
+// is summed over them in a fixed order.  The direction blocks of RHS b share
+// one XCD (and its L2 copy of I_b).
+template <int NSG, int MC>
+__global__ void __launch_bounds__(kRcsThreads, NSG == 4 ? 3 : 4)
+rcs_kernel(GeomDev g, const RhsDev* __restrict__ rhs, const uint8_t* __restrict__ states,
+           const double2* __restrict__ I, const double2* __restrict__ F, const double* __restrict__ dirs, int n_dir,
+           int n, int n_a, int n_v, int n_states, int B, int n_dblk, double k, double px, double py, double scale,
+           double* __restrict__ sigma) {
+  __shared__ double sh[kRcsWaves][6][kRcsDirs];
+  const int id = blockIdx.x, xcd = id % 8, slot = id / 8;
+  const int b = (slot / n_dblk) * 8 + xcd, dblk = slot % n_dblk;
+  if (b >= B) return;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int d_raw = dblk * kRcsDirs + lane;
+  const bool live = d_raw < n_dir;
+  const int d = live ? d_raw : n_dir - 1;
+  const double th = dirs[2 * d], ph = dirs[2 * d + 1];
+  const double rx = sin(th) * cos(ph), ry = sin(th) * sin(ph), rz = cos(th);
+  double stx_i, stx_r;
+  sincos(k * rx * px, &stx_i, &stx_r);  // phase step of one unit along x
+  const RhsDev R = rhs[b];
+  const int n_groups = (n_states + NSG - 1) / NSG;
+  const int n_chunks = (n_a + MC - 1) / MC;
+  const int n_state_items = n_groups * n_chunks;
+  const int n_items = n_state_items + (n_v - n_a + MC - 1) / MC;
+  const double2* Fd = F + (size_t)d * n * 3;
+  double N[6] = {0, 0, 0, 0, 0, 0};
+  for (int it = wave; it < n_items; it += kRcsWaves) {
+    // an item reads MC contiguous entries inside the unit's row: a ragged
+    // last chunk slides back, and its entries before r0 (another item's)
+    // stay out of N
+    if (it < n_state_items) {
+      const int s0 = (it / n_chunks) * NSG, r0 = (it % n_chunks) * MC;
+      const int rc = min(r0, n_v - MC);
+      double ar[NSG][MC], ai[NSG][MC];
+      rcs_array_sums<false, NSG, MC>(g, R, states, I, n_a, n_v, n_states, s0, rc, lane, k, rx, ry, px, py, stx_r,
+                                     stx_i, ar, ai);
+      rcs_combine<false, NSG, MC>(g, Fd, n_a, n_states, s0, rc, r0, n_a, ar, ai, N);
+    } else {
+      const int r0 = n_a + (it - n_state_items) * MC;
+      const int rc = min(r0, n_v - MC);
+      double ar[1][MC], ai[1][MC];
+      rcs_array_sums<true, 1, MC>(g, R, states, I, n_a, n_v, n_states, 0, rc, lane, k, rx, ry, px, py, stx_r,
+                                  stx_i, ar, ai);
+      rcs_combine<true, 1, MC>(g, Fd, n_a, n_states, 0, rc, r0, n_v, ar, ai, N);
     }
+  }
+  for (int q = 0; q < 6; ++q) sh[wave][q][lane] = N[q];
+  __syncthreads();
+  if (wave == 0 && live) {
+    for (int q = 0; q < 6; ++q)
+      for (int w = 1; w < kRcsWaves; ++w) N[q] += sh[w][q][lane];
     const double rr[3] = {rx, ry, rz};
     const double dre = N[0] * rx + N[2] * ry + N[4] * rz;
     const double dim = N[1] * rx + N[3] * ry + N[5] * rz;
     double p2 = 0.0;
     for (int q = 0; q < 3; ++q) {
-      const double pr = N[2 * q] - dre * rr[q], pi = N[2 * q + 1] - dim * rr[q];
-      p2 += pr * pr + pi * pi;
+      const double qr = N[2 * q] - dre * rr[q], qi = N[2 * q + 1] - dim * rr[q];
+      p2 += qr * qr + qi * qi;
     }
     sigma[(size_t)b * n_dir + d] = scale * p2;
   }
@@ -388,9 +493,26 @@ int r3m_rcs(r3m_ctx ctx, const r3m_unit_geom* geom, const r3m_batch* batch, cons
                        stream, g, ddev, n_dir, k, F);
     const double scale = k * k * kEta0 * kEta0 / (4.0 * kPi) / (e0 * e0);
     check_states(bd, batch->states, geom->n_states, deferred_word(ctx), kDeferredBadState, stream);
-    hipLaunchKernelGGL(rcs_kernel, dim3(n_dir, bd.B), dim3(kRcsThreads), 0, stream, g, bd.rhs, batch->states,
-                       (const double2*)I_dev, F, ddev, n_dir, geom->n_rwg, n_a, vec_per_unit(geom), geom->n_states,
-                       k, geom->period_x, geom->period_y, scale, sigma_dev);
+    // items of NSG coding states x MC contiguous compact entries (two per
+    // wave for the 1- and 2-bit units of 40 active bases)
+    const int n_dblk = ceil_div((size_t)n_dir, kRcsDirs);
+    R3M_REQUIRE((size_t)ceil_div((size_t)bd.B, 8) * 8 * n_dblk < (1ull << 31), R3M_ERR_INVALID_ARG,
+                "too many right-hand sides x directions for one RCS launch");
+    const dim3 grid(ceil_div((size_t)bd.B, 8) * 8 * n_dblk);
+    auto launch = [&](auto kern) {
+      hipLaunchKernelGGL(kern, grid, dim3(kRcsThreads), 0, stream, g, bd.rhs, batch->states, (const double2*)I_dev,
+                         (const double2*)F, (const double*)ddev, n_dir, geom->n_rwg, n_a, vec_per_unit(geom),
+                         geom->n_states, bd.B, n_dblk, k, geom->period_x, geom->period_y, scale, sigma_dev);
+    };
+    const int n_v = vec_per_unit(geom);
+    if (n_v < 5)
+      launch(rcs_kernel<1, 1>);
+    else if (geom->n_states == 1)
+      launch(rcs_kernel<1, 5>);
+    else if (geom->n_states == 2)
+      launch(rcs_kernel<2, 5>);
+    else
+      launch(rcs_kernel<4, 5>);
     R3M_CHECK_HIP(hipGetLastError());
     R3M_CHECK_HIP(hipStreamSynchronize(stream));
     tmp.release();

@@ -281,6 +281,34 @@ def test_plain_6x6_solve_and_rcs(r3m, ctx):
     assert rel_max(sig.cpu().numpy(), s_same) <= 1e-12
 
 
+@pytest.mark.parametrize("bits", [1, 2])
+def test_rcs_random_currents_vs_oracle(r3m, ctx, bits):
+    """Bistatic RCS of seeded random currents on three arrays (3 x 3, 5 x 5
+    and 9 x 9, the last over two 64-unit tiles) at 150 seeded directions
+    (three 64-direction blocks, the last ragged), 1-bit (two states) and
+    2-bit (four states) units, against the oracle's far field of the same
+    currents: rounding level."""
+    rng = np.random.default_rng(40 + bits)
+    Ls = [3, 5, 9]
+    books = [cb.bernoulli(L, 7 + L) if bits == 1 else cb.uniform(L, 4, 7 + L) for L in Ls]
+    g = geom(r3m, bits)
+    batch = batch_for(r3m, books, Ls)
+    n_a = unit(bits).n_a
+    N = sum(L * L for L in Ls) * n_a
+    I = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    n_dir = 150
+    dirs = np.column_stack([rng.uniform(0.0, 0.5 * np.pi, n_dir), rng.uniform(0.0, 2.0 * np.pi, n_dir)])
+    sig = torch.zeros(len(Ls) * n_dir, dtype=torch.float64, device=DEV)
+    r3m.r3m_rcs(ctx, g, batch, to_dev(I), dirs, 1.0, sig)
+    sig = sig.cpu().numpy()
+    off = 0
+    for b, L in enumerate(Ls):
+        n = L * L * n_a
+        ref = oracle_rcs(bits, books[b], L, I[off:off + n], dirs)
+        assert rel_max(sig[b * n_dir:(b + 1) * n_dir], ref) <= 1e-11, (bits, L)
+        off += n
+
+
 def test_oblique_excitation(r3m, ctx):
     states = cb.bernoulli(3, 2)
     g = geom(r3m, 1)
