@@ -22,12 +22,18 @@ constexpr int kTW = 8, kTH = 8;  // unit block of the matvec workgroups
 constexpr int kDotChunk = 1024;
 constexpr int kDotThreads = 256;
 constexpr int kDotPer = kDotChunk / kDotThreads;  // elements per thread in a chunk
-constexpr int kDotVec = 4;                        // basis vectors per fused-dot block
+// basis vectors per inner-product work item: 8 for a complex64 basis (w's
+// chunk read once per 8), 4 for complex128 (register count)
+template <typename VB>
+constexpr int dot_vec() { return sizeof(VB) == 8 ? 8 : 4; }
 // The folded Gram-Schmidt update keeps up to 4 basis entries per wave in
 // registers, so it takes steps with at most 16 basis vectors (with 8 per
 // wave its register count leaves three waves per SIMD, and it measured no
 // faster than the two separate passes).
 constexpr int kFoldMaxVec = 16;
+// The element-parallel update (long vectors) keeps one element's entries of
+// every basis vector and folds steps of up to 32 vectors.
+constexpr int kFoldMaxVecEl = 32;
 constexpr int kCheckEvery = 4;
 
 struct RhsVec {
@@ -269,20 +275,61 @@ __device__ double2 block_sum2(double2 v, double2* sh) {
   return t;
 }
 
+__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
+__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
+
+// Sums over the 64 lanes of a wave of NV complex values per lane (NV a power
+// of two up to 32), by exchanging half of the remaining values at each of the
+// first log2(NV) butterfly steps (lane bit 5 keeps the upper half, bit 4 the
+// upper quarter, ...) and plain butterfly steps after that: on return x[0] of
+// lane l is the total of value l >> (6 - log2 NV).  Fixed order; NV - 1 +
+// 6 - log2(NV) exchanges instead of 6 NV.
+// O0 < 32: the exchanges start at that lane distance (the steps above it
+// done by the caller).
+template <int NV, int O0 = 32>
+__device__ __forceinline__ void wave_transpose_sum(double2 (&x)[NV], int lane) {
+  constexpr int L = NV == 1 ? 0 : NV == 2 ? 1 : NV == 4 ? 2 : NV == 8 ? 3 : NV == 16 ? 4 : 5;
+  static_assert((1 << L) == NV, "NV must be a power of two up to 32");
+#pragma unroll
+  for (int st = 0; st < L; ++st) {
+    const int o = O0 >> st, half = NV >> (st + 1);
+    const bool hi = (lane & o) != 0;
+#pragma unroll
+    for (int t = 0; t < half; ++t) {
+      const double2 a = x[t], b = x[t + half];
+      const double2 send = hi ? a : b;
+      double2 keep = hi ? b : a;
+      keep.x += __shfl_xor(send.x, o);
+      keep.y += __shfl_xor(send.y, o);
+      x[t] = keep;
+    }
+  }
+#pragma unroll
+  for (int o = O0 >> L; o >= 1; o >>= 1) {
+    x[0].x += __shfl_xor(x[0].x, o);
+    x[0].y += __shfl_xor(x[0].y, o);
+  }
+}
+
 // Chunk partials of <A_i, B> for i < nvec: partial[b][i][p].  Work item
 // (b, grp, p) takes chunk p of RHS b against the kDotVec vectors of group
-// grp; B's chunk is loaded once and all loads are issued before the products.
-// The blocks stride over the items of the right-hand sides of rl (a live
-// list, see rhs_count), or of all B.  The consumer kernel sums the partials
-// itself (no grid-wide fence here).
+// grp (dot_vec); B's chunk is loaded once and all loads are issued before the products
+// (basis entries kept in their stored type).  Each wave sums its lanes'
+// products with wave_transpose_sum, then the block adds the waves in a fixed
+// order.  The blocks stride over the items of the right-hand sides of rl (a
+// live list, see rhs_count), or of all B.  The consumer kernel sums the
+// partials itself (no grid-wide fence here).
 template <typename VB, typename WB>
 __global__ void __launch_bounds__(kDotThreads)
 dots_partials_kernel(const VB* __restrict__ A, int64_t a_stride, const WB* __restrict__ Bv,
                      const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
                      int* __restrict__ reset, const int* __restrict__ live, const int* __restrict__ idle,
                      const int* __restrict__ rl, int B) {
+  constexpr int kDotVec = dot_vec<VB>();
+  constexpr int kShV = kDotVec == 4 ? 4 : kDotVec == 8 ? 3 : 2;  // lane >> kShV: the vector a lane totals
+  static_assert(kDotVec == 4 || kDotVec == 8 || kDotVec == 16, "kDotVec");
   __shared__ double2 sh[kDotThreads / 64][kDotVec];
-  const int tid = threadIdx.x, wave = tid >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   // this step's running count starts at zero (done before the exit test, so a
   // skipped step still leaves it zero for the next one)
   if (reset && blockIdx.x == 0 && tid == 0) *reset = 0;
@@ -308,35 +355,35 @@ dots_partials_kernel(const VB* __restrict__ A, int64_t a_stride, const WB* __res
       const int64_t k = lo + (int64_t)e * kDotThreads;
       wv[e] = k < r.N ? ld_b(bb + k) : make_double2(0.0, 0.0);
     }
-    double2 av[kDotVec][kDotPer];
+    VB av[kDotVec][kDotPer];
 #pragma unroll
     for (int q = 0; q < kDotVec; ++q) {
-      const VB* a = A + (int64_t)(i0 + min(q, nv - 1)) * a_stride + r.off;
+      if (q < nv) {  // uniform
+        const VB* a = A + (int64_t)(i0 + q) * a_stride + r.off;
 #pragma unroll
-      for (int e = 0; e < kDotPer; ++e) {
-        const int64_t k = lo + (int64_t)e * kDotThreads;
-        av[q][e] = k < r.N ? ld_b(a + k) : make_double2(0.0, 0.0);
+        for (int e = 0; e < kDotPer; ++e) {
+          const int64_t k = lo + (int64_t)e * kDotThreads;
+          av[q][e] = k < r.N ? a[k] : VB{};
+        }
       }
     }
     double2 acc[kDotVec];
 #pragma unroll
     for (int q = 0; q < kDotVec; ++q) {
       acc[q] = make_double2(0.0, 0.0);
+      if (q < nv) {
 #pragma unroll
-      for (int e = 0; e < kDotPer; ++e) {
-        const double2 t = cmulc(av[q][e], wv[e]);
-        acc[q].x += t.x;
-        acc[q].y += t.y;
-      }
-#pragma unroll
-      for (int o = 32; o >= 1; o >>= 1) {
-        acc[q].x += __shfl_xor(acc[q].x, o);
-        acc[q].y += __shfl_xor(acc[q].y, o);
+        for (int e = 0; e < kDotPer; ++e) {
+          const double2 t = cmulc(to_d2(av[q][e]), wv[e]);
+          acc[q].x += t.x;
+          acc[q].y += t.y;
+        }
       }
     }
-    if ((tid & 63) == 0) {
-#pragma unroll
-      for (int q = 0; q < kDotVec; ++q) sh[wave][q] = acc[q];
+    wave_transpose_sum<kDotVec>(acc, lane);
+    {
+      const int vi = lane >> kShV;
+      if ((lane & ((1 << kShV) - 1)) == 0) sh[wave][vi] = acc[0];
     }
     __syncthreads();
     if (tid < nv) {
@@ -551,18 +598,16 @@ gs_update_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* __r
   }
 }
 
-__device__ __forceinline__ double2 to_d2(double2 v) { return v; }
-__device__ __forceinline__ double2 to_d2(float2 v) { return make_double2(v.x, v.y); }
-
 // The update of gs_update_kernel for long vectors (blocks of four 64-element
 // runs): every thread takes its own element of the block and loops over the
 // basis vectors (loads issued in groups before the products), so that all
-// four waves stream at every basis size.  FOLD (nvec <= kFoldMaxVec): the
-// element's basis entries stay in registers for the second pass's inner
-// products, each wave sums them over its lanes and the block adds the waves
-// in a fixed order into partial2[b][i][block].  Same arguments and outputs as
-// gs_update_kernel with nsub = 4.
-template <bool FOLD, typename VB, typename WB>
+// four waves stream at every basis size.  NV > 0 folds the second pass's
+// inner products (nvec <= NV <= kFoldMaxVecEl): the element's basis entries
+// stay in registers, each wave sums conj(V_i) w over its lanes
+// (wave_transpose_sum) and the block adds the waves in a fixed order into
+// partial2[b][i][block].  Same arguments and outputs as gs_update_kernel with
+// nsub = 4.
+template <int NV, typename VB, typename WB>
 __global__ void __launch_bounds__(256)
 gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* __restrict__ rv,
                     const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int n_part,
@@ -571,10 +616,11 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
                     const int* __restrict__ idle, int part_chunk, double2* __restrict__ partial2, int maxP2,
                     const int* __restrict__ rl, int B, int64_t nb_max) {
   if (run_prev && *run_prev == 0) return;
+  constexpr bool FOLD = NV > 0;
   constexpr int kEl = 256;  // elements per block: four 64-element runs
   extern __shared__ double2 hb[];
   __shared__ double2 sh[4];
-  __shared__ double2 red[4][kFoldMaxVec];
+  __shared__ double2 red[4][FOLD ? NV : 1];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t items = nb_max * rhs_count(rl, B);
   for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {  // uniform over the block
@@ -611,16 +657,16 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
     const bool live = k < r.N && st[b].active;
     double2 wk = live ? ld_b(w + r.off + k) : make_double2(0.0, 0.0);
     double nrm2 = 0.0;
-    VB vv[FOLD ? kFoldMaxVec : 8];
+    VB vv[FOLD ? NV : 8];
     if (live) {
       const VB* vk = V + r.off + k;
       double2 acc = make_double2(0.0, 0.0);
       if (FOLD) {
 #pragma unroll
-        for (int i = 0; i < kFoldMaxVec; ++i)
+        for (int i = 0; i < (FOLD ? NV : 8); ++i)
           if (i < nvec) vv[i] = vk[(int64_t)i * ut];
 #pragma unroll
-        for (int i = 0; i < kFoldMaxVec; ++i)
+        for (int i = 0; i < (FOLD ? NV : 8); ++i)
           if (i < nvec) {
             const double2 c = cmul(hb[i], to_d2(vv[i]));
             acc.x += c.x;
@@ -646,16 +692,20 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
       nrm2 = wk.x * wk.x + wk.y * wk.y;
     }
     if (FOLD) {
+      constexpr int NF = FOLD ? NV : 1;
+      auto dot = [&](int i) { return (live && i < nvec) ? cmulc(to_d2(vv[i]), wk) : make_double2(0.0, 0.0); };
+      // up to 16 products at a time (32: two halves, fewer live registers)
+      constexpr int NH = NF > 16 ? 16 : NF;
+      constexpr int sh_v = NH == 1 ? 6 : NH == 2 ? 5 : NH == 4 ? 4 : NH == 8 ? 3 : 2;
 #pragma unroll
-      for (int i = 0; i < kFoldMaxVec; ++i) {
-        if (i < nvec) {  // uniform over the block
-          double2 d = live ? cmulc(to_d2(vv[i]), wk) : make_double2(0.0, 0.0);
+      for (int h0 = 0; h0 < NF; h0 += NH) {
+        if (h0 < nvec) {  // uniform
+          double2 d[NH];
 #pragma unroll
-          for (int o = 32; o >= 1; o >>= 1) {
-            d.x += __shfl_xor(d.x, o);
-            d.y += __shfl_xor(d.y, o);
-          }
-          if (lane == 0) red[wave][i] = d;
+          for (int i = 0; i < NH; ++i) d[i] = dot(h0 + i);
+          wave_transpose_sum<NH>(d, lane);
+          const int vi = h0 + (lane >> sh_v);  // the value this lane holds the total of
+          if ((lane & ((1 << sh_v) - 1)) == 0 && vi < nvec) red[wave][vi] = d[0];
         }
       }
       __syncthreads();
@@ -1102,6 +1152,11 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // return), else one (the single-RHS solve keeps enough workgroups, and
 // normalize_step_kernel sums their per-64 parts itself)
 int update_runs(int64_t maxN) { return (maxN + kDotChunk - 1) / kDotChunk > 64 ? 4 : 1; }
+// basis vectors a folded update takes: the element-parallel kernel (long
+// vectors) holds more
+int fold_max_vec(int64_t maxN, bool vb32) {
+  return update_runs(maxN) == 4 && vb32 ? kFoldMaxVecEl : kFoldMaxVec;
+}
 int64_t fold_blocks(int64_t maxN) {
   const int nsub = update_runs(maxN);
   return std::max<int64_t>(1, (maxN + 64 * nsub - 1) / (64 * nsub));
@@ -1143,7 +1198,7 @@ Work layout_work(char* base, const BatchDesc& bd, int n_a, int n_blocks, int m, 
   w.cs = (double*)take((size_t)B * m * 8);
   w.sn = (double2*)take((size_t)B * m * 16);
   w.dpart = (double2*)take((size_t)B * (m + 1) * std::max(maxP, 1) * 16);
-  w.dpart2 = (double2*)take((size_t)B * std::min(m + 1, kFoldMaxVec) * fold_blocks(maxN) * 16);
+  w.dpart2 = (double2*)take((size_t)B * std::min(m + 1, fold_max_vec(maxN, vb32)) * fold_blocks(maxN) * 16);
   w.hbuf = (double2*)take((size_t)B * (m + 1) * 16);
   w.hsum = (double2*)take((size_t)B * (m + 1) * 16);
   w.nsum = (double*)take((size_t)B * 8);
@@ -1310,7 +1365,7 @@ struct GmresRun {
     const bool long_vec = maxP > 64;
     const int nsub = update_runs(maxN);
     const int nvec = j + 1;
-    const int ngrp = (nvec + kDotVec - 1) / kDotVec;
+    const int ngrp = (nvec + dot_vec<VB>() - 1) / dot_vec<VB>();
     const int64_t nb_u = (maxN + 64 * nsub - 1) / (64 * nsub);
     const unsigned dgrid = stride_grid((int64_t)maxP * ngrp * B), ugrid = stride_grid(nb_u * B);
     const size_t ulds = (size_t)nvec * sizeof(double2);
@@ -1326,14 +1381,24 @@ struct GmresRun {
     // products): the element-parallel kernel for long vectors
     auto update = [&](int kv, const double2* hp, int hP, int hn, int do_norm, int mode, int pchunk, double2* p2,
                       int mP2) {
-      if (nsub == 4 && kv > 0)
-        hipLaunchKernelGGL((gs_update_el_kernel<true, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, hp,
-                           hP, hn, nvec, ut, do_norm, W.npart, maxB, W.H, m, j, mode, live, W.idle, pchunk, p2, mP2, rl,
-                           B, nb_u);
-      else if (nsub == 4)
-        hipLaunchKernelGGL((gs_update_el_kernel<false, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st,
-                           hp, hP, hn, nvec, ut, do_norm, W.npart, maxB, W.H, m, j, mode, live, W.idle, pchunk, p2,
-                           mP2, rl, B, nb_u);
+      auto el = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, hp, hP, hn, nvec, ut, do_norm,
+                           W.npart, maxB, W.H, m, j, mode, live, W.idle, pchunk, p2, mP2, rl, B, nb_u);
+      };
+      if (nsub == 4 && kv > 0) {
+        // the basis count padded to a power of two
+        if (nvec <= 2)
+          el(gs_update_el_kernel<2, VB, WB>);
+        else if (nvec <= 4)
+          el(gs_update_el_kernel<4, VB, WB>);
+        else if (nvec <= 8)
+          el(gs_update_el_kernel<8, VB, WB>);
+        else if (nvec <= 16 || sizeof(VB) != sizeof(float2))
+          el(gs_update_el_kernel<16, VB, WB>);
+        else
+          el(gs_update_el_kernel<32, VB, WB>);
+      } else if (nsub == 4)
+        el(gs_update_el_kernel<0, VB, WB>);
       else if (kv == 2)
         hipLaunchKernelGGL((gs_update_kernel<2, VB, WB>), dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, hp, hP,
                            hn, nvec, ut, do_norm, W.npart, maxB, W.H, m, j, mode, live, W.idle, nsub, pchunk, p2, mP2,
@@ -1347,7 +1412,7 @@ struct GmresRun {
                            hn, nvec, ut, do_norm, W.npart, maxB, W.H, m, j, mode, live, W.idle, nsub, pchunk, p2, mP2,
                            rl, B, nb_u);
     };
-    if (nvec <= kFoldMaxVec && W.dpart2) {
+    if (nvec <= fold_max_vec(maxN, sizeof(VB) == sizeof(float2)) && W.dpart2) {
       // the first update also forms the second pass's inner products
       const int maxP2 = (int)fold_blocks(maxN);
       update(nvec <= 8 ? 2 : 4, h0, h0P, h0n, 0, 0, kDotChunk, W.dpart2, maxP2);
