@@ -602,13 +602,14 @@ gs_update_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* __r
 // runs): every thread takes its own element of the block and loops over the
 // basis vectors (loads issued in groups before the products), so that all
 // four waves stream at every basis size.  NV > 0 folds the second pass's
-// inner products (nvec <= NV <= kFoldMaxVecEl): the element's basis entries
+// inner products (nvec <= NV <= kFoldMaxVecEl, NV a power of two up to 16 or
+// 20, 24 or 32): the element's basis entries
 // stay in registers, each wave sums conj(V_i) w over its lanes
 // (wave_transpose_sum) and the block adds the waves in a fixed order into
 // partial2[b][i][block].  Same arguments and outputs as gs_update_kernel with
 // nsub = 4.
 template <int NV, typename VB, typename WB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, NV == 20 ? 4 : 1)
 gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* __restrict__ rv,
                     const RhsState* __restrict__ st, const double2* __restrict__ partial, int maxP, int n_part,
                     int nvec, int64_t ut, int do_norm, double* __restrict__ npart, int maxB,
@@ -693,20 +694,26 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
     }
     if (FOLD) {
       constexpr int NF = FOLD ? NV : 1;
-      auto dot = [&](int i) { return (live && i < nvec) ? cmulc(to_d2(vv[i]), wk) : make_double2(0.0, 0.0); };
-      // up to 16 products at a time (32: two halves, fewer live registers)
-      constexpr int NH = NF > 16 ? 16 : NF;
-      constexpr int sh_v = NH == 1 ? 6 : NH == 2 ? 5 : NH == 4 ? 4 : NH == 8 ? 3 : 2;
+      auto dot = [&](int i) {
+        return (live && i < nvec && i < NF) ? cmulc(to_d2(vv[i < NF ? i : 0]), wk) : make_double2(0.0, 0.0);
+      };
+      // the first (up to) 16 products, then the rest padded to a power of
+      // two (fewer live registers than one sum over all of them)
+      auto fold_sum = [&](auto nh_c, int h0) {
+        constexpr int NH = decltype(nh_c)::value;
+        constexpr int sh_v = NH == 1 ? 6 : NH == 2 ? 5 : NH == 4 ? 4 : NH == 8 ? 3 : 2;
+        double2 d[NH];
 #pragma unroll
-      for (int h0 = 0; h0 < NF; h0 += NH) {
-        if (h0 < nvec) {  // uniform
-          double2 d[NH];
-#pragma unroll
-          for (int i = 0; i < NH; ++i) d[i] = dot(h0 + i);
-          wave_transpose_sum<NH>(d, lane);
-          const int vi = h0 + (lane >> sh_v);  // the value this lane holds the total of
-          if ((lane & ((1 << sh_v) - 1)) == 0 && vi < nvec) red[wave][vi] = d[0];
-        }
+        for (int i = 0; i < NH; ++i) d[i] = dot(h0 + i);
+        wave_transpose_sum<NH>(d, lane);
+        const int vi = h0 + (lane >> sh_v);  // the value this lane holds the total of
+        if ((lane & ((1 << sh_v) - 1)) == 0 && vi < nvec) red[wave][vi] = d[0];
+      };
+      constexpr int NA = NF > 16 ? 16 : NF, NR = NF - NA;
+      constexpr int NB = NR == 0 ? 1 : NR <= 2 ? 2 : NR <= 4 ? 4 : NR <= 8 ? 8 : 16;
+      fold_sum(std::integral_constant<int, NA>(), 0);
+      if constexpr (NR > 0) {
+        if (nvec > 16) fold_sum(std::integral_constant<int, NB>(), 16);  // uniform
       }
       __syncthreads();
       if (tid < nvec) {
@@ -1395,6 +1402,10 @@ struct GmresRun {
           el(gs_update_el_kernel<8, VB, WB>);
         else if (nvec <= 16 || sizeof(VB) != sizeof(float2))
           el(gs_update_el_kernel<16, VB, WB>);
+        else if (nvec <= 20)
+          el(gs_update_el_kernel<20, VB, WB>);
+        else if (nvec <= 24)
+          el(gs_update_el_kernel<24, VB, WB>);
         else
           el(gs_update_el_kernel<32, VB, WB>);
       } else if (nsub == 4)
