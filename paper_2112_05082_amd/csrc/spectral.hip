@@ -869,23 +869,36 @@ spec_product_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, 
 // few are left, the contiguous order spreads them over all eight XCDs,
 // where the RHS-first order would put each tile on one XCD.  The count from
 // which the RHS-first order is taken (rhs_first) is part of the plan.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f32x4 mfma_16x16x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma_16x16x4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
 constexpr int kPM = 80, kPB = 16;
 constexpr int kZP = kPM + 1, kXP = kPB + 1;
 
 // KPW frequencies per wave, 4 KPW per workgroup; PC columns per staged
 // chunk; RB tiles of 16 right-hand sides per workgroup (each staged chunk of
 // the spectra then feeds RB times the products)
-template <int KPW, int PC, int RB, bool TR>
+// T = double: the FP64 16x16x4 matrix-core product of complex128 spectra
+// (operands as FP32; the output rows of a lane interleave differently), one
+// complex128 frequency per 16-byte access.
+template <typename T, int KPW, int PC, int RB, bool TR>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(KPW == 2 && PC == 4 && RB == 1 ? 3 : KPW == 2 && RB == 2 ? 2
+    __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1
+                                       : KPW == 2 && PC == 4 && RB == 1 ? 3 : KPW == 2 && RB == 2 ? 2
                                        : KPW == 1 && PC == 8 && RB == 2 ? 3 : 1)))
-spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __restrict__ Xh, C2<float>* __restrict__ Yh,
+spec_product_mfma_kernel(const C2<T>* __restrict__ Zh, const C2<T>* __restrict__ Xh, C2<T>* __restrict__ Yh,
                          int n, int64_t K, int B, int n_mg, int n_bt, int64_t n_tiles, int lgGx, int lgGy,
                          const int* __restrict__ live, const int* __restrict__ idle,
                          const int* __restrict__ tile_list, const int* __restrict__ n_live, int rhs_first,
                          int lkg) {
   if (live && *live == 0) return;
-  typedef float v4 __attribute__((ext_vector_type(4)));
+  typedef T v4 __attribute__((ext_vector_type(4)));
   constexpr int PK = 4 * KPW;                   // frequencies per workgroup
   constexpr int LPK = PK == 8 ? 3 : PK == 16 ? 4 : 2;
   constexpr int YP = PK + 1;
@@ -898,8 +911,8 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
   constexpr int NB = kPB * RB, LNB = RB == 2 ? 5 : 4, XP = NB + 1;  // right-hand sides per workgroup
   // (a second staging buffer, which saves one barrier per chunk, measured
   // slower: 13.95 against 13.46 ms on the 1,536-RHS product)
-  __shared__ C2<float> Zs[PC * PK * kZP];  // [c][k][m]; reused as the output tile [b][m][k]
-  __shared__ C2<float> Xs[PC * PK * XP];   // [c][k][b]
+  __shared__ C2<T> Zs[PC * PK * kZP];  // [c][k][m]; reused as the output tile [b][m][k]
+  __shared__ C2<T> Xs[PC * PK * XP];   // [c][k][b]
   static_assert(16 * YB <= PC * PK * kZP, "output tile fits the staging buffer");
   // RHS tiles to cover: all n_bt, or the nl live ones of tile_list (the
   // launch is sized for both orders below), taken RB at a time
@@ -968,13 +981,14 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
     for (int t = 0; t < 5; ++t)
 #pragma unroll
       for (int r = 0; r < RB; ++r) are[q][t][r] = aim[q][t][r] = v4{0, 0, 0, 0};
-  // loads of a chunk: VW adjacent frequencies each (one 16-byte load of two;
-  // the transposed operator reads mirrored frequencies one at a time)
-  constexpr int VW = TR ? 1 : 2, LPKV = VW == 2 ? LPK - 1 : LPK;
+  // loads of a chunk: VW adjacent frequencies each (one 16-byte load of two
+  // complex64 values; the transposed operator reads mirrored frequencies one
+  // at a time)
+  constexpr int VW = TR || sizeof(T) == 8 ? 1 : 2, LPKV = VW == 2 ? LPK - 1 : LPK;
   constexpr int ZE = PC * PK * kPM / VW, XE = PC * PK * NB / VW;
   constexpr int NZ = (ZE + 255) / 256, NX = (XE + 255) / 256;
-  struct alignas(8 * VW) CV {
-    C2<float> v[VW];
+  struct alignas(sizeof(C2<T>) * VW) CV {
+    C2<T> v[VW];
   };
   CV zp[NZ], xp[NX];
   auto load_chunk = [&](int c0) {
@@ -985,13 +999,13 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
       const bool ok = e < ZE && m0 + m < n && c0 + c < n && k0 + k < K;
       if (TR) {
         zp[i].v[0] = ok ? Zh[((int64_t)(c0 + c) * n + m0 + m) * K + mirror_freq(k0 + k, lgGx, lgGy)]
-                        : C2<float>{0, 0};
+                        : C2<T>{0, 0};
       } else {
         const CV* src = reinterpret_cast<const CV*>(Zh + ((int64_t)(m0 + m) * n + c0 + c) * K + k0 + k);
         if (ok) zp[i] = *src;
         else
 #pragma unroll
-          for (int v = 0; v < VW; ++v) zp[i].v[v] = C2<float>{0, 0};
+          for (int v = 0; v < VW; ++v) zp[i].v[v] = C2<T>{0, 0};
       }
     }
 #pragma unroll
@@ -1005,7 +1019,7 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
       if (ok) xp[i] = *src;
       else
 #pragma unroll
-        for (int v = 0; v < VW; ++v) xp[i].v[v] = C2<float>{0, 0};
+        for (int v = 0; v < VW; ++v) xp[i].v[v] = C2<T>{0, 0};
     }
   };
   load_chunk(0);
@@ -1035,24 +1049,24 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
 #pragma unroll
       for (int q = 0; q < KPW; ++q) {
         const int kk = w * KPW + q;
-        C2<float> bv[RB];
+        C2<T> bv[RB];
 #pragma unroll
         for (int r = 0; r < RB; ++r) bv[r] = Xs[(c * PK + kk) * XP + r * 16 + (lane & 15)];
 #pragma unroll
         for (int t = 0; t < 5; ++t) {
-          const C2<float> av = Zs[(c * PK + kk) * kZP + t * 16 + (lane & 15)];
+          const C2<T> av = Zs[(c * PK + kk) * kZP + t * 16 + (lane & 15)];
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
-            are[q][t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv[r].re, are[q][t][r], 0, 0, 0);
-            are[q][t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-av.im, bv[r].im, are[q][t][r], 0, 0, 0);
-            aim[q][t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.re, bv[r].im, aim[q][t][r], 0, 0, 0);
-            aim[q][t][r] = __builtin_amdgcn_mfma_f32_16x16x4f32(av.im, bv[r].re, aim[q][t][r], 0, 0, 0);
+            are[q][t][r] = mfma_16x16x4(av.re, bv[r].re, are[q][t][r]);
+            are[q][t][r] = mfma_16x16x4(-av.im, bv[r].im, are[q][t][r]);
+            aim[q][t][r] = mfma_16x16x4(av.re, bv[r].im, aim[q][t][r]);
+            aim[q][t][r] = mfma_16x16x4(av.im, bv[r].re, aim[q][t][r]);
           }
         }
       }
     }
   }
-  C2<float>* Ys = Zs;  // [b 16 (stride YB)][m 16][k YP]
+  C2<T>* Ys = Zs;  // [b 16 (stride YB)][m 16][k YP]
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     if (b0[r] < 0) break;  // uniform over the workgroup
@@ -1063,19 +1077,25 @@ spec_product_mfma_kernel(const C2<float>* __restrict__ Zh, const C2<float>* __re
       for (int q = 0; q < KPW; ++q)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int m = 4 * (lane >> 4) + i, b = lane & 15;
+          // accumulator entry i of a lane: row 4 (lane / 16) + i (FP32) or
+          // 4 i + lane / 16 (FP64), column lane % 16
+          const int m = sizeof(T) == 4 ? 4 * (lane >> 4) + i : 4 * i + (lane >> 4), b = lane & 15;
           Ys[b * YB + m * YP + w * KPW + q] = {are[q][t][r][i], aim[q][t][r][i]};
         }
       __syncthreads();
-      // two adjacent frequencies per 16-byte store
+      // YW adjacent frequencies per 16-byte store
+      constexpr int YW = 16 / sizeof(C2<T>), LYW = YW == 2 ? 1 : 0;
 #pragma unroll
-      for (int i = 0; i < (16 * 16 * PK / 2 + 255) / 256; ++i) {
-        const int e = tid + 256 * i, k = (e & (PK / 2 - 1)) * 2, m = (e >> (LPK - 1)) & 15, b = e >> (LPK + 3);
+      for (int i = 0; i < (16 * 16 * PK / YW + 255) / 256; ++i) {
+        const int e = tid + 256 * i, k = (e & (PK / YW - 1)) * YW, m = (e >> (LPK - LYW)) & 15,
+                  b = e >> (LPK - LYW + 4);
         const int row = m0 + t * 16 + m;
-        if (e < 16 * 16 * PK / 2 && b0[r] + b < B && row < n && k0 + k < K) {
+        if (e < 16 * 16 * PK / YW && b0[r] + b < B && row < n && k0 + k < K) {
           struct alignas(16) Y2 {
-            C2<float> v[2];
-          } y2 = {{Ys[b * YB + m * YP + k], Ys[b * YB + m * YP + k + 1]}};
+            C2<T> v[YW];
+          } y2;
+#pragma unroll
+          for (int v = 0; v < YW; ++v) y2.v[v] = Ys[b * YB + m * YP + k + v];
           *reinterpret_cast<Y2*>(Yh + ((int64_t)(b0[r] + b) * n + row) * K + k0 + k) = y2;
         }
       }
@@ -1132,8 +1152,8 @@ void launch_product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2
 // used with idle flags on batches of at least rhs_first RHS tiles; with the
 // list the kernel picks the order from the live count, so the grid covers
 // both orders.
-template <int KPW, int PC, int RB>
-void launch_product_mfma(const C2<float>* Zh, const C2<float>* X, C2<float>* Y, int n, int64_t G2, int B, bool tr,
+template <typename T, int KPW, int PC, int RB>
+void launch_product_mfma(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B, bool tr,
                          int lgGx, int lgGy, hipStream_t s, const int* live, const int* idle, int* tl, int rf,
                          int lkg) {
   constexpr int PK = 4 * KPW;
@@ -1153,10 +1173,10 @@ void launch_product_mfma(const C2<float>* Zh, const C2<float>* X, C2<float>* Y, 
     R3M_CHECK_HIP(hipGetLastError());
   }
   if (tr)
-    hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, RB, true>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X,
+    hipLaunchKernelGGL((spec_product_mfma_kernel<T, KPW, PC, RB, true>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X,
                        Y, n, G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf, lkg);
   else
-    hipLaunchKernelGGL((spec_product_mfma_kernel<KPW, PC, RB, false>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X,
+    hipLaunchKernelGGL((spec_product_mfma_kernel<T, KPW, PC, RB, false>), dim3((unsigned)nwg), dim3(256), 0, s, Zh, X,
                        Y, n, G2, B, n_mg, n_bt, n_kt, lgGx, lgGy, live, idle, list, cnt, rf, lkg);
   R3M_CHECK_HIP(hipGetLastError());
 }
@@ -1176,15 +1196,21 @@ void product(const C2<T>* Zh, const C2<T>* X, C2<T>* Y, int n, int64_t G2, int B
     C2<float>* yf = Y;
     const int rf = spec_rhs_first(plan), lkg = spec_kt_groups(plan);
     switch (spec_shape(plan)) {
-      case 1: return launch_product_mfma<1, 4, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 2: return launch_product_mfma<2, 4, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 3: return launch_product_mfma<2, 8, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 4: return launch_product_mfma<4, 4, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 5: return launch_product_mfma<1, 8, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 6: return launch_product_mfma<2, 4, 2>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
-      case 7: return launch_product_mfma<1, 8, 2>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 1: return launch_product_mfma<float, 1, 4, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 2: return launch_product_mfma<float, 2, 4, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 3: return launch_product_mfma<float, 2, 8, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 4: return launch_product_mfma<float, 4, 4, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 5: return launch_product_mfma<float, 1, 8, 1>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 6: return launch_product_mfma<float, 2, 4, 2>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
+      case 7: return launch_product_mfma<float, 1, 8, 2>(zf, xf, yf, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl, rf, lkg);
       default: break;
     }
+  } else {
+    // complex128 spectra: the FP64 matrix cores at every batch width (one
+    // summation order per output, so a batched product matches its single
+    // right-hand sides bit for bit)
+    return launch_product_mfma<double, 1, 4, 1>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle, tl,
+                                                 spec_rhs_first(plan), spec_kt_groups(plan));
   }
   if (B == 1)
     launch_product<T, 2, 1>(Zh, X, Y, n, G2, B, tr, lgGx, lgGy, s, live, idle);
