@@ -742,7 +742,11 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
 // (MODE 2, block-Jacobi; a block holds whole units).  MODE 0 writes V only.
 // Blocks (nb_max per RHS) are work items strided over by the grid, for the
 // right-hand sides of rl (see rhs_count).
-template <typename OT, int MODE, typename VB, typename WB>
+// R2 (MODE 2 with staged inverses, n_a even): a block item holds twice the
+// units, each thread normalises two elements and then forms two consecutive
+// rows of its unit's product (one 16-byte read of the inverse and one read of
+// the unit's entry serve both rows).
+template <typename OT, int MODE, typename VB, typename WB, bool R2 = false>
 __global__ void __launch_bounds__(256)
 normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec* __restrict__ rv,
                       RhsState* __restrict__ st, const double* __restrict__ npart, int maxB, int n_npart,
@@ -754,7 +758,8 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
                       int* __restrict__ idle, const int* __restrict__ rl, int B, int64_t nb_max, int stage) {
   if (live && *live == 0) return;
   __shared__ double nv_s;
-  __shared__ double2 v_s[256];
+  __shared__ double2 v_s[R2 ? 1 : 256];
+  __shared__ float2 v2_s[R2 ? 512 : 1];
   extern __shared__ double2 glds[];
   const int64_t items = nb_max * rhs_count(rl, B);
   // stage: the block-Jacobi inverses of every state, rounded to complex64, in
@@ -780,7 +785,7 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
     }
     const RhsVec r = rv[b];
     const int64_t nb = (r.N + 63) / 64;
-    if (blk * blockDim.x >= r.N) continue;  // uniform over the block
+    if (blk * (R2 ? 2 : 1) * blockDim.x >= r.N) continue;  // uniform over the block
     __syncthreads();  // the previous item's reads of nv_s and v_s are done
     if (threadIdx.x < 64) {
       const double sum = wave_sum_partials(npart + (size_t)b * maxB, n_npart > 0 ? n_npart : (int)nb);
@@ -792,6 +797,47 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
     // changes to a value with the same outcome (jdone: -1 -> j + 1)
     const RhsState s0 = st[b];
     const bool ok = s0.active && (s0.jdone < 0 || s0.jdone == j + 1) && nv > 0.0;
+    if constexpr (R2) {
+      const int64_t base = blk * 2 * blockDim.x;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int64_t ke = base + e * blockDim.x + threadIdx.x;
+        double2 ve = make_double2(0.0, 0.0);
+        if (ke < r.N) {
+          const double2 wk = ld_b(w + r.off + ke);
+          if (ok) ve = make_double2(wk.x / nv, wk.y / nv);
+          st_b(V + (int64_t)(j + 1) * ut + r.off + ke, ve);
+        }
+        v2_s[e * blockDim.x + threadIdx.x] = make_float2((float)ve.x, (float)ve.y);
+      }
+      __syncthreads();
+      const int hp = n_a >> 1, ul = threadIdx.x / hp, p2 = 2 * (threadIdx.x - ul * hp);
+      const int64_t k0 = base + (int64_t)ul * n_a + p2;  // rows p2, p2 + 1 of local unit ul
+      if (k0 < r.N) {
+        const int64_t u = k0 / n_a;
+        const int64_t sidx = min((int)states[soff[b] + u], n_states - 1);
+        const float2* M = Ms + (size_t)sidx * n_a * n_a + p2;  // column-major
+        const float2* vu = v2_s + ul * n_a;
+        float a0x = 0.f, a0y = 0.f, a1x = 0.f, a1y = 0.f;
+        for (int c = 0; c < n_a; ++c) {
+          const float2 x = vu[c];
+          const float4 mm = *reinterpret_cast<const float4*>(M + (size_t)c * n_a);
+          a0x += mm.x * x.x - mm.y * x.y;
+          a0y += mm.x * x.y + mm.y * x.x;
+          a1x += mm.z * x.x - mm.w * x.y;
+          a1y += mm.z * x.y + mm.w * x.x;
+        }
+        xs[2 * (r.off + k0)] = (OT)a0x;
+        xs[2 * (r.off + k0) + 1] = (OT)a0y;
+        xs[2 * (r.off + k0) + 2] = (OT)a1x;
+        xs[2 * (r.off + k0) + 3] = (OT)a1y;
+      }
+      if (blk == 0) {  // uniform over the block
+        if (threadIdx.x == 0) wn[b] = nv;
+        givens_step_block(b, H, g, cs, sn, st, m, j, tol, n_running, nv, glds, idle);
+      }
+      continue;
+    }
     const int64_t k = blk * blockDim.x + threadIdx.x;
     const bool in = k < r.N;
     double2 v = make_double2(0.0, 0.0);
@@ -1467,6 +1513,13 @@ struct GmresRun {
       if constexpr (std::is_same<VB, double2>::value && std::is_same<WB, double2>::value)
         launch_ilu_apply(Z, *bd, ilu_r, W.ilu, V + (int64_t)(j + 1) * ut, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s,
                          run_slot(j), wts == nullptr);
+    } else if (pre && c64 && stage && n_a % 2 == 0) {
+      // two rows per thread: blocks of twice the units
+      const int64_t nb2 = ceil_div((size_t)maxN, 2 * nthr);
+      hipLaunchKernelGGL((normalize_step_kernel<float, 2, VB, WB, true>), dim3(stride_grid(nb2 * B)), dim3(nthr), glds,
+                         s, wv, V, W.rv, W.st, np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut,
+                         live, W.Minv, batch->states, W.soff, n_a, n_states, (float*)W.xs, pu, W.idle, rl, B, nb2,
+                         stage);
     } else if (pre && c64) {
       R3M_NORMALIZE(float, 2, (float*)W.xs);
     } else if (pre) {
