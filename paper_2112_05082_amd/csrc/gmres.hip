@@ -742,11 +742,11 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
 // (MODE 2, block-Jacobi; a block holds whole units).  MODE 0 writes V only.
 // Blocks (nb_max per RHS) are work items strided over by the grid, for the
 // right-hand sides of rl (see rhs_count).
-// R2 (MODE 2 with staged inverses, n_a even): a block item holds twice the
-// units, each thread normalises two elements and then forms two consecutive
-// rows of its unit's product (one 16-byte read of the inverse and one read of
-// the unit's entry serve both rows).
-template <typename OT, int MODE, typename VB, typename WB, bool R2 = false>
+// RW = 2 or 4 (MODE 2 with staged inverses, n_a a multiple of RW): a block
+// item holds RW times the units, each thread normalises RW elements and then
+// forms RW consecutive rows of its unit's product (one read of the unit's
+// entry and 8 RW bytes of the inverse per column serve all RW rows).
+template <typename OT, int MODE, typename VB, typename WB, int RW = 1>
 __global__ void __launch_bounds__(256)
 normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec* __restrict__ rv,
                       RhsState* __restrict__ st, const double* __restrict__ npart, int maxB, int n_npart,
@@ -758,8 +758,9 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
                       int* __restrict__ idle, const int* __restrict__ rl, int B, int64_t nb_max, int stage) {
   if (live && *live == 0) return;
   __shared__ double nv_s;
+  constexpr bool R2 = RW > 1;
   __shared__ double2 v_s[R2 ? 1 : 256];
-  __shared__ float2 v2_s[R2 ? 512 : 1];
+  __shared__ float2 v2_s[R2 ? 256 * RW : 1];
   extern __shared__ double2 glds[];
   const int64_t items = nb_max * rhs_count(rl, B);
   // stage: the block-Jacobi inverses of every state, rounded to complex64, in
@@ -785,7 +786,7 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
     }
     const RhsVec r = rv[b];
     const int64_t nb = (r.N + 63) / 64;
-    if (blk * (R2 ? 2 : 1) * blockDim.x >= r.N) continue;  // uniform over the block
+    if (blk * RW * blockDim.x >= r.N) continue;  // uniform over the block
     __syncthreads();  // the previous item's reads of nv_s and v_s are done
     if (threadIdx.x < 64) {
       const double sum = wave_sum_partials(npart + (size_t)b * maxB, n_npart > 0 ? n_npart : (int)nb);
@@ -798,9 +799,9 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
     const RhsState s0 = st[b];
     const bool ok = s0.active && (s0.jdone < 0 || s0.jdone == j + 1) && nv > 0.0;
     if constexpr (R2) {
-      const int64_t base = blk * 2 * blockDim.x;
+      const int64_t base = blk * RW * blockDim.x;
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
+      for (int e = 0; e < RW; ++e) {
         const int64_t ke = base + e * blockDim.x + threadIdx.x;
         double2 ve = make_double2(0.0, 0.0);
         if (ke < r.N) {
@@ -811,26 +812,32 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
         v2_s[e * blockDim.x + threadIdx.x] = make_float2((float)ve.x, (float)ve.y);
       }
       __syncthreads();
-      const int hp = n_a >> 1, ul = threadIdx.x / hp, p2 = 2 * (threadIdx.x - ul * hp);
-      const int64_t k0 = base + (int64_t)ul * n_a + p2;  // rows p2, p2 + 1 of local unit ul
+      const int hp = n_a / RW, ul = threadIdx.x / hp, p2 = RW * (threadIdx.x - ul * hp);
+      const int64_t k0 = base + (int64_t)ul * n_a + p2;  // rows p2 .. p2 + RW - 1 of local unit ul
       if (k0 < r.N) {
         const int64_t u = k0 / n_a;
         const int64_t sidx = min((int)states[soff[b] + u], n_states - 1);
         const float2* M = Ms + (size_t)sidx * n_a * n_a + p2;  // column-major
         const float2* vu = v2_s + ul * n_a;
-        float a0x = 0.f, a0y = 0.f, a1x = 0.f, a1y = 0.f;
+        float ax[RW], ay[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) ax[q] = ay[q] = 0.f;
         for (int c = 0; c < n_a; ++c) {
           const float2 x = vu[c];
-          const float4 mm = *reinterpret_cast<const float4*>(M + (size_t)c * n_a);
-          a0x += mm.x * x.x - mm.y * x.y;
-          a0y += mm.x * x.y + mm.y * x.x;
-          a1x += mm.z * x.x - mm.w * x.y;
-          a1y += mm.z * x.y + mm.w * x.x;
+#pragma unroll
+          for (int h = 0; h < RW / 2; ++h) {
+            const float4 mm = *reinterpret_cast<const float4*>(M + (size_t)c * n_a + 2 * h);
+            ax[2 * h] += mm.x * x.x - mm.y * x.y;
+            ay[2 * h] += mm.x * x.y + mm.y * x.x;
+            ax[2 * h + 1] += mm.z * x.x - mm.w * x.y;
+            ay[2 * h + 1] += mm.z * x.y + mm.w * x.x;
+          }
         }
-        xs[2 * (r.off + k0)] = (OT)a0x;
-        xs[2 * (r.off + k0) + 1] = (OT)a0y;
-        xs[2 * (r.off + k0) + 2] = (OT)a1x;
-        xs[2 * (r.off + k0) + 3] = (OT)a1y;
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+          xs[2 * (r.off + k0 + q)] = (OT)ax[q];
+          xs[2 * (r.off + k0 + q) + 1] = (OT)ay[q];
+        }
       }
       if (blk == 0) {  // uniform over the block
         if (threadIdx.x == 0) wn[b] = nv;
@@ -1514,12 +1521,17 @@ struct GmresRun {
         launch_ilu_apply(Z, *bd, ilu_r, W.ilu, V + (int64_t)(j + 1) * ut, W.w, c64 ? R3M_C64 : R3M_C128, W.xs, s,
                          run_slot(j), wts == nullptr);
     } else if (pre && c64 && stage && n_a % 2 == 0) {
-      // two rows per thread: blocks of twice the units
-      const int64_t nb2 = ceil_div((size_t)maxN, 2 * nthr);
-      hipLaunchKernelGGL((normalize_step_kernel<float, 2, VB, WB, true>), dim3(stride_grid(nb2 * B)), dim3(nthr), glds,
-                         s, wv, V, W.rv, W.st, np, npB, npN, W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut,
-                         live, W.Minv, batch->states, W.soff, n_a, n_states, (float*)W.xs, pu, W.idle, rl, B, nb2,
-                         stage);
+      // RW rows per thread: blocks of RW times the units
+      auto rows = [&](auto kern, int rw) {
+        const int64_t nbr = ceil_div((size_t)maxN, (size_t)rw * nthr);
+        hipLaunchKernelGGL(kern, dim3(stride_grid(nbr * B)), dim3(nthr), glds, s, wv, V, W.rv, W.st, np, npB, npN,
+                           W.H, W.g, W.cs, W.sn, m, j, tol, run_slot(j), W.wn, ut, live, W.Minv, batch->states,
+                           W.soff, n_a, n_states, (float*)W.xs, pu, W.idle, rl, B, nbr, stage);
+      };
+      if (n_a % 4 == 0)
+        rows(normalize_step_kernel<float, 2, VB, WB, 4>, 4);
+      else
+        rows(normalize_step_kernel<float, 2, VB, WB, 2>, 2);
     } else if (pre && c64) {
       R3M_NORMALIZE(float, 2, (float*)W.xs);
     } else if (pre) {
