@@ -1122,6 +1122,69 @@ __global__ void apply_precond_kernel(const double2* __restrict__ Minv, const uin
   out[2 * (r.off + k) + 1] = (OT)acc.y;
 }
 
+// apply_precond_kernel with the per-state inverses staged in LDS (as TM: float
+// for a complex64 output, double otherwise) once per workgroup, over a grid
+// strided across (RHS, item): an item holds RW nthr elements of whole units
+// (blockDim.x = nthr, a multiple of n_a), each thread loads RW of them and
+// then forms RW consecutive rows of its unit's product.  n_a % RW == 0.
+// Dynamic LDS: (n_states n_a^2 + RW blockDim.x) complex TM.
+template <typename TM, int RW, typename IT, typename OT>
+__global__ void __launch_bounds__(256)
+apply_precond_staged_kernel(const double2* __restrict__ Minv, const uint8_t* __restrict__ states,
+                            const int64_t* __restrict__ soff, const RhsVec* __restrict__ rv, int n_a, int n_states,
+                            const IT* __restrict__ in, OT* __restrict__ out, const RhsState* __restrict__ st, int B,
+                            int64_t nb_max) {
+  struct alignas(2 * sizeof(TM)) CT {
+    TM x, y;
+  };
+  extern __shared__ double2 lds_raw[];
+  CT* Ms = reinterpret_cast<CT*>(lds_raw);  // [state][column][row]
+  CT* vs = Ms + (size_t)n_states * n_a * n_a;
+  for (int t = threadIdx.x; t < n_states * n_a * n_a; t += blockDim.x) Ms[t] = CT{(TM)Minv[t].x, (TM)Minv[t].y};
+  const int64_t items = nb_max * B;
+  const int hp = n_a / RW, ul = threadIdx.x / hp, p = RW * (threadIdx.x - ul * hp);
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {  // uniform over the block
+    const int b = (int)(item / nb_max);
+    const int64_t blk = item - (int64_t)b * nb_max;
+    if (st && !st[b].active) continue;  // a right-hand side this cycle does not solve
+    const RhsVec r = rv[b];
+    const int64_t base = blk * RW * blockDim.x;
+    if (base >= r.N) continue;
+    __syncthreads();  // the staged inverses, or the previous item's reads of vs
+#pragma unroll
+    for (int e = 0; e < RW; ++e) {
+      const int64_t ke = base + e * blockDim.x + threadIdx.x;
+      const double2 v = ke < r.N ? ld_b(in + r.off + ke) : make_double2(0.0, 0.0);
+      vs[e * blockDim.x + threadIdx.x] = CT{(TM)v.x, (TM)v.y};
+    }
+    __syncthreads();
+    const int64_t k0 = base + (int64_t)ul * n_a + p;  // rows p .. p + RW - 1 of local unit ul
+    if (k0 < r.N) {
+      const int64_t u = k0 / n_a;
+      const int sidx = min((int)states[soff[b] + u], n_states - 1);
+      const CT* M = Ms + (size_t)sidx * n_a * n_a + p;
+      const CT* vu = vs + ul * n_a;
+      TM ax[RW], ay[RW];
+#pragma unroll
+      for (int q = 0; q < RW; ++q) ax[q] = ay[q] = (TM)0;
+      for (int c = 0; c < n_a; ++c) {
+        const CT x = vu[c];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+          const CT mm = M[(size_t)c * n_a + q];
+          ax[q] += mm.x * x.x - mm.y * x.y;
+          ay[q] += mm.x * x.y + mm.y * x.x;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RW; ++q) {
+        out[2 * (r.off + k0 + q)] = (OT)ax[q];
+        out[2 * (r.off + k0 + q) + 1] = (OT)ay[q];
+      }
+    }
+  }
+}
+
 template <typename OT, typename IT = double2>
 __global__ void convert_vec_kernel(const RhsVec* __restrict__ rv, const IT* __restrict__ in,
                                    OT* __restrict__ out, const int* __restrict__ live) {
@@ -1297,6 +1360,23 @@ struct GmresRun {
 
   dim3 vgrid() const { return dim3(ceil_div((size_t)maxN, 256), B); }
 
+  // out = M^-1 in per unit with the per-state inverses staged in LDS (OT
+  // float: complex64 products, four rows per thread; double: complex128, two);
+  // false where that form does not apply (the caller launches
+  // apply_precond_kernel)
+  template <typename OT, typename IT>
+  bool precond_staged(const IT* in, OT* out) {
+    constexpr int RW = sizeof(OT) == 4 ? 4 : 2;
+    const int nthr = (256 / n_a) * n_a;
+    const size_t es = 2 * sizeof(OT);
+    const size_t lds = ((size_t)n_states * n_a * n_a + (size_t)RW * nthr) * es;
+    if (pu || ilu_r || n_a % RW != 0 || nthr == 0 || lds > 64 * 1024) return false;
+    const int64_t nb = ceil_div((size_t)maxN, (size_t)RW * nthr);
+    hipLaunchKernelGGL((apply_precond_staged_kernel<OT, RW, IT, OT>), dim3(stride_grid(nb * B)), dim3(nthr), lds, s,
+                       W.Minv, batch->states, W.soff, W.rv, n_a, n_states, in, out, (const RhsState*)W.st, B, nb);
+    return true;
+  }
+
   void dots(const double2* A, int64_t a_stride, const double2* Bv, int nvec) {
     dim3 grid(maxP, nvec, B);
     hipLaunchKernelGGL(dots_kernel, grid, dim3(kDotThreads), 0, s, A, a_stride, Bv, W.rv, nvec,
@@ -1346,6 +1426,7 @@ struct GmresRun {
       launch_ilu_apply(Zsolve, *bd, ilu_r, W.ilu, in, out, R3M_C128, nullptr, s, nullptr, wts == nullptr);
       return;
     }
+    if (precond_staged(in, (double*)out)) return;
     hipLaunchKernelGGL(apply_precond_kernel<double>, vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff, W.rv,
                        n_a, n_states, in, (double*)out, (const int*)nullptr, pu, (const RhsState*)W.st);
   }
@@ -1370,13 +1451,16 @@ struct GmresRun {
       else
         R3M_REQUIRE(false, R3M_ERR_UNSUPPORTED, "a complex64 basis with the ILU preconditioner");
     } else if (pre) {
-      if (c64)
-        hipLaunchKernelGGL((apply_precond_kernel<float, VB>), vgrid(), dim3(256), 0, s, W.Minv, batch->states, W.soff,
-                           W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr, pu, (const RhsState*)W.st);
-      else
+      if (c64) {
+        if (!precond_staged(v, (float*)W.xs))
+          hipLaunchKernelGGL((apply_precond_kernel<float, VB>), vgrid(), dim3(256), 0, s, W.Minv, batch->states,
+                             W.soff, W.rv, n_a, n_states, v, (float*)W.xs, (const int*)nullptr, pu,
+                             (const RhsState*)W.st);
+      } else if (!precond_staged(v, (double*)W.xs)) {
         hipLaunchKernelGGL((apply_precond_kernel<double, VB>), vgrid(), dim3(256), 0, s, W.Minv, batch->states,
                            W.soff, W.rv, n_a, n_states, v, (double*)W.xs, (const int*)nullptr, pu,
                            (const RhsState*)W.st);
+      }
     } else if (c64) {
       hipLaunchKernelGGL((convert_vec_kernel<float, VB>), vgrid(), dim3(256), 0, s, W.rv, v, (float*)W.xs,
                          (const int*)nullptr);
