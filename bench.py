@@ -59,7 +59,7 @@ PROFILED_TRAFFIC = {
     "c1_matvec": {"bytes": 403.7e6, "groups": 128},
     # frequency product of the 1,536-RHS spectral matvec (spec_product_mfma_kernel,
     # shape 6: 2 frequencies per wave, 4 columns per chunk, two 16-RHS tiles)
-    "c2_product": {"bytes": 61.05e9, "shape": 6},
+    "c2_product": {"bytes": 61.33e9, "shape": 6},
 }
 
 
