@@ -633,6 +633,18 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
     const int64_t nb = (r.N + kEl - 1) / kEl;
     if (blk >= nb) continue;
     const int P = n_part > 0 ? n_part : (int)((r.N + part_chunk - 1) / part_chunk);
+    // this item's element of w and of the basis (the first 8 vectors without
+    // folding) are loaded before the coefficient sums, which do not need them
+    const int64_t k = blk * kEl + tid;
+    const bool live = k < r.N && st[b].active;
+    double2 wk = live ? ld_b(w + r.off + k) : make_double2(0.0, 0.0);
+    VB vv[FOLD ? NV : 8];
+    const VB* vk = V + r.off + k;
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < (FOLD ? NV : 8); ++i)
+        if (i < nvec) vv[i] = vk[(int64_t)i * ut];
+    }
     __syncthreads();  // the previous item's reads of hb and red are done
     for (int i = tid; i < nvec; i += blockDim.x) {
       const double2* pp = partial + ((size_t)b * nvec + i) * maxP;
@@ -654,18 +666,10 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
       }
     }
     __syncthreads();
-    const int64_t k = blk * kEl + tid;
-    const bool live = k < r.N && st[b].active;
-    double2 wk = live ? ld_b(w + r.off + k) : make_double2(0.0, 0.0);
     double nrm2 = 0.0;
-    VB vv[FOLD ? NV : 8];
     if (live) {
-      const VB* vk = V + r.off + k;
       double2 acc = make_double2(0.0, 0.0);
       if (FOLD) {
-#pragma unroll
-        for (int i = 0; i < (FOLD ? NV : 8); ++i)
-          if (i < nvec) vv[i] = vk[(int64_t)i * ut];
 #pragma unroll
         for (int i = 0; i < (FOLD ? NV : 8); ++i)
           if (i < nvec) {
@@ -675,9 +679,11 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
           }
       } else {
         for (int i0 = 0; i0 < nvec; i0 += 8) {
+          if (i0 > 0) {  // the first 8 were loaded above
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (i0 + u < nvec) vv[u] = vk[(int64_t)(i0 + u) * ut];
+            for (int u = 0; u < 8; ++u)
+              if (i0 + u < nvec) vv[u] = vk[(int64_t)(i0 + u) * ut];
+          }
 #pragma unroll
           for (int u = 0; u < 8; ++u)
             if (i0 + u < nvec) {
