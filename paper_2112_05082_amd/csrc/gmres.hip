@@ -804,6 +804,7 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
     // changes to a value with the same outcome (jdone: -1 -> j + 1)
     const RhsState s0 = st[b];
     const bool ok = s0.active && (s0.jdone < 0 || s0.jdone == j + 1) && nv > 0.0;
+    const double inv = ok ? 1.0 / nv : 0.0;  // one division per item, not per element
     if constexpr (R2) {
       const int64_t base = blk * RW * blockDim.x;
 #pragma unroll
@@ -812,7 +813,7 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
         double2 ve = make_double2(0.0, 0.0);
         if (ke < r.N) {
           const double2 wk = ld_b(w + r.off + ke);
-          if (ok) ve = make_double2(wk.x / nv, wk.y / nv);
+          if (ok) ve = make_double2(wk.x * inv, wk.y * inv);
           st_b(V + (int64_t)(j + 1) * ut + r.off + ke, ve);
         }
         v2_s[e * blockDim.x + threadIdx.x] = make_float2((float)ve.x, (float)ve.y);
@@ -856,7 +857,7 @@ normalize_step_kernel(const WB* __restrict__ w, VB* __restrict__ V, const RhsVec
     double2 v = make_double2(0.0, 0.0);
     if (in) {
       const double2 wk = ld_b(w + r.off + k);
-      if (ok) v = make_double2(wk.x / nv, wk.y / nv);
+      if (ok) v = make_double2(wk.x * inv, wk.y * inv);
       st_b(V + (int64_t)(j + 1) * ut + r.off + k, v);
     }
     if (MODE == 1 && in) {
@@ -999,8 +1000,9 @@ __global__ void cycle_start_kernel(const double2* __restrict__ r, VB* __restrict
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const double beta = sqrt(fmax(nrm2[b].x, 0.0));
   const bool act = st[b].active && beta > 0.0;
+  const double inv = act ? 1.0 / beta : 0.0;
   if (k < rr.N)
-    st_b(V + rr.off + k, act ? make_double2(r[rr.off + k].x / beta, r[rr.off + k].y / beta) : make_double2(0.0, 0.0));
+    st_b(V + rr.off + k, act ? make_double2(r[rr.off + k].x * inv, r[rr.off + k].y * inv) : make_double2(0.0, 0.0));
   if (k <= m) g[(size_t)b * (m + 1) + k] = (k == 0 && act) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
 }
 
