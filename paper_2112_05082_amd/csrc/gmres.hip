@@ -319,15 +319,15 @@ __device__ __forceinline__ void wave_transpose_sum(double2 (&x)[NV], int lane) {
 // order.  The blocks stride over the items of the right-hand sides of rl (a
 // live list, see rhs_count), or of all B.  The consumer kernel sums the
 // partials itself (no grid-wide fence here).
-template <typename VB, typename WB>
+template <typename VB, typename WB, int DV = dot_vec<VB>()>
 __global__ void __launch_bounds__(kDotThreads)
 dots_partials_kernel(const VB* __restrict__ A, int64_t a_stride, const WB* __restrict__ Bv,
                      const RhsVec* __restrict__ rv, int nvec, int maxP, double2* __restrict__ partial,
                      int* __restrict__ reset, const int* __restrict__ live, const int* __restrict__ idle,
                      const int* __restrict__ rl, int B) {
-  constexpr int kDotVec = dot_vec<VB>();
-  constexpr int kShV = kDotVec == 4 ? 4 : kDotVec == 8 ? 3 : 2;  // lane >> kShV: the vector a lane totals
-  static_assert(kDotVec == 4 || kDotVec == 8 || kDotVec == 16, "kDotVec");
+  constexpr int kDotVec = DV;  // vectors per item (fewer for small bases)
+  constexpr int kShV = kDotVec == 1 ? 6 : kDotVec == 2 ? 5 : kDotVec == 4 ? 4 : kDotVec == 8 ? 3 : 2;
+  static_assert(kDotVec == 1 || kDotVec == 2 || kDotVec == 4 || kDotVec == 8 || kDotVec == 16, "kDotVec");
   __shared__ double2 sh[kDotThreads / 64][kDotVec];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   // this step's running count starts at zero (done before the exit test, so a
@@ -1517,13 +1517,29 @@ struct GmresRun {
     const bool long_vec = maxP > 64;
     const int nsub = update_runs(maxN);
     const int nvec = j + 1;
-    const int ngrp = (nvec + dot_vec<VB>() - 1) / dot_vec<VB>();
+    // inner-product items of dv vectors: the basis count padded to a power of
+    // two up to dot_vec (the exchanges of the lane sums scale with dv)
+    const int dv = std::min(dot_vec<VB>(), nvec <= 1 ? 1 : nvec <= 2 ? 2 : nvec <= 4 ? 4 : 8);
+    const int ngrp = (nvec + dv - 1) / dv;
     const int64_t nb_u = (maxN + 64 * nsub - 1) / (64 * nsub);
     const unsigned dgrid = stride_grid((int64_t)maxP * ngrp * B), ugrid = stride_grid(nb_u * B);
     const size_t ulds = (size_t)nvec * sizeof(double2);
+    auto dots = [&](int* reset) {
+      auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, wv, W.rv, nvec, maxP, W.dpart, reset,
+                           live, W.idle, rl, B);
+      };
+      if (dv == 1)
+        go(dots_partials_kernel<VB, WB, 1>);
+      else if (dv == 2)
+        go(dots_partials_kernel<VB, WB, 2>);
+      else if (dv == 4)
+        go(dots_partials_kernel<VB, WB, 4>);
+      else
+        go(dots_partials_kernel<VB, WB, dot_vec<VB>()>);
+    };
     // CGS2, first pass: inner products with the basis, then the update
-    hipLaunchKernelGGL((dots_partials_kernel<VB, WB>), dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, wv, W.rv, nvec, maxP,
-                       W.dpart, run_slot(j), live, W.idle, rl, B);
+    dots(run_slot(j));
     if (long_vec)
       hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP, nvec,
                          W.rv, W.hsum, live, W.idle, kDotChunk);
@@ -1580,8 +1596,7 @@ struct GmresRun {
     } else {
       update(0, h0, h0P, h0n, 0, 0, kDotChunk, (double2*)nullptr, 0);
       // CGS2, second pass
-      hipLaunchKernelGGL((dots_partials_kernel<VB, WB>), dim3(dgrid), dim3(kDotThreads), 0, s, V, ut, wv, W.rv, nvec, maxP,
-                         W.dpart, (int*)nullptr, live, W.idle, rl, B);
+      dots((int*)nullptr);
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
                            nvec, W.rv, W.hsum, live, W.idle, kDotChunk);
