@@ -1228,6 +1228,62 @@ __global__ void combine_basis_kernel(const VB* __restrict__ V, const double2* __
   z[r.off + k] = acc;
 }
 
+// Residual of a finished cycle in its basis: with Givens rotations G_j = [c_j
+// s_j; -conj(s_j) c_j] and gamma = g[J] the last rotated entry (J = jdone),
+// b - A M^{-1} V y = V_{J+1} u, u = G_0^H ... G_{J-1}^H (gamma e_J):
+// u_J = c_{J-1} gamma, u_j = c_{j-1} t_j with t_j = (-s_j) t_{j+1}, t_J =
+// gamma, and u_0 = t_0.  One thread per right-hand side, u[b][0..J].
+__global__ void residual_coeffs_kernel(const double2* __restrict__ g, const double* __restrict__ cs,
+                                       const double2* __restrict__ sn, const RhsState* __restrict__ st, int B,
+                                       int m, double2* __restrict__ u) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B || !st[b].active) return;
+  const int J = st[b].jdone;
+  double2* ub = u + (size_t)b * (m + 1);
+  double2 t = g[(size_t)b * (m + 1) + J];
+  for (int j = J - 1; j >= 0; --j) {
+    const double c = cs[(size_t)b * m + j];
+    const double2 sj = sn[(size_t)b * m + j];
+    ub[j + 1] = make_double2(c * t.x, c * t.y);
+    t = make_double2(-(sj.x * t.x - sj.y * t.y), -(sj.x * t.y + sj.y * t.x));
+  }
+  ub[0] = t;
+}
+
+// combine_basis_kernel and, in the same pass over the basis, the cycle's
+// residual r = V_{J+1} u (u from residual_coeffs_kernel) for the restart;
+// right-hand sides the cycle did not solve keep their r
+template <typename VB>
+__global__ void combine_basis_res_kernel(const VB* __restrict__ V, const double2* __restrict__ g,
+                                         const double2* __restrict__ u, double2* __restrict__ z,
+                                         double2* __restrict__ res, const RhsVec* __restrict__ rv,
+                                         const RhsState* __restrict__ st, int m, int64_t ut) {
+  const int b = blockIdx.y;
+  const RhsVec r = rv[b];
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const RhsState s = st[b];
+  if (k >= r.N) return;
+  double2 acc = make_double2(0.0, 0.0);
+  if (s.active) {
+    const double2* y = g + (size_t)b * (m + 1);
+    const double2* ub = u + (size_t)b * (m + 1);
+    double2 ra = make_double2(0.0, 0.0);
+    for (int i = 0; i <= s.jdone; ++i) {
+      const double2 v = ld_b(V + (int64_t)i * ut + r.off + k);
+      if (i < s.jdone) {
+        const double2 t = cmul(y[i], v);
+        acc.x += t.x;
+        acc.y += t.y;
+      }
+      const double2 q = cmul(ub[i], v);
+      ra.x += q.x;
+      ra.y += q.y;
+    }
+    res[r.off + k] = ra;
+  }
+  z[r.off + k] = acc;
+}
+
 // idle[b] = 1 for a right-hand side that the last cycle did not solve: the
 // restart's residual skips it
 __global__ void idle_from_state_kernel(const RhsState* __restrict__ st, int B, int* __restrict__ idle) {
@@ -1705,6 +1761,7 @@ struct GmresRun {
     std::vector<RhsState> hst(B);
     std::vector<double> rnorm(B, 0.0);
     bool first = true;
+    bool r_from_basis = false;  // W.r holds the last cycle's residual from its basis
     while (true) {
       if (first && x_zero) {
         R3M_CHECK_HIP(hipMemcpyAsync(W.r, rhs, (size_t)ut * 16, hipMemcpyDeviceToDevice, s));
@@ -1712,11 +1769,13 @@ struct GmresRun {
         rnorm = rhs_norm;
       } else {
         // a restart: right-hand sides the last cycle did not solve keep their
-        // residual norm and are skipped by the matvec
-        if (!first)
+        // residual norm and are skipped by the matvec (or r is already the
+        // last cycle's residual from its basis)
+        if (!first && !r_from_basis)
           hipLaunchKernelGGL(idle_from_state_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, (const RhsState*)W.st, B,
                              W.idle);
-        residual(Z, rhs, sol, W.r, first ? nullptr : (const int*)W.idle);
+        if (first || !r_from_basis) residual(Z, rhs, sol, W.r, first ? nullptr : (const int*)W.idle);
+        r_from_basis = false;
         norms(W.r);
         std::vector<double2> nr(B);
         R3M_CHECK_HIP(hipMemcpyAsync(nr.data(), W.nrm, (size_t)B * 16, hipMemcpyDeviceToHost, s));
@@ -1772,10 +1831,15 @@ struct GmresRun {
       hipLaunchKernelGGL(backsolve_kernel, dim3(B), dim3(256), 0, s, W.H, W.g, W.st, m);
       if (pre) {
         // x += M^{-1} (V y)
-        if (vb32)
-          hipLaunchKernelGGL(combine_basis_kernel<float2>, vgrid(), dim3(256), 0, s, (const float2*)W.V, W.g, W.pz,
-                             W.rv, W.st, m, ut);
-        else
+        if (vb32) {
+          // with the next restart's residual from the cycle's own basis (the
+          // outer FP64 residual checks the solution)
+          hipLaunchKernelGGL(residual_coeffs_kernel, dim3(ceil_div(B, 64)), dim3(64), 0, s, (const double2*)W.g,
+                             (const double*)W.cs, (const double2*)W.sn, (const RhsState*)W.st, B, m, W.hbuf);
+          hipLaunchKernelGGL(combine_basis_res_kernel<float2>, vgrid(), dim3(256), 0, s, (const float2*)W.V, W.g,
+                             (const double2*)W.hbuf, W.pz, W.r, W.rv, W.st, m, ut);
+          r_from_basis = true;
+        } else
           hipLaunchKernelGGL(combine_basis_kernel<double2>, vgrid(), dim3(256), 0, s, (const double2*)W.V, W.g,
                              W.pz, W.rv, W.st, m, ut);
         precond(W.pz, W.w);
