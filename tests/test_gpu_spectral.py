@@ -195,6 +195,47 @@ def test_spectral_solves(lib, fullsize, pc):
     assert rep2[0][3] and rep2[0][2] <= 1e-9 and e_ref <= 1e-7
 
 
+def test_refined_solve_short_restarts(lib, fullsize):
+    """Complex64 inner GMRES(4) with block-Jacobi under complex128
+    refinement on the 2-bit 32x32 workload: every inner restart takes the
+    cycle's residual from its basis (Givens rotations, no residual matvec),
+    dozens of restarts per inner solve.  The refined solution must converge
+    to 1e-9 and give the RCS of the plain complex128 solve, and each inner
+    solve must take no more than twice the iterations of GMRES(4) on the
+    plain store (which forms each restart's residual with a matvec)."""
+    r3m, _, ctx = lib
+    geom, _, batch, s128, s64, plain = fullsize
+    N = 32 * 32 * 40
+    dirs = cb.phi0_cut(1.0)
+    b = torch.zeros(N, dtype=torch.complex128, device=DEV)
+    r3m.r3m_plane_wave_rhs(ctx, geom, batch, [[0.0, 0.0, 1.0]], b)
+
+    def solve(st, st64, m, tol, refine_tol):
+        x = torch.zeros_like(b)
+        work = torch.empty(r3m.gmres_work_bytes(ctx, st, batch, m, st64, precond=r3m.PRECOND_BLOCK_JACOBI),
+                           dtype=torch.uint8, device=DEV)
+        _, rep = r3m.r3m_gmres_solve(ctx, st, st64, batch, b, x, tol, m, 20000, work, refine_tol=refine_tol,
+                                     max_refine=40, precond=r3m.PRECOND_BLOCK_JACOBI)
+        sig = torch.zeros(len(dirs), dtype=torch.float64, device=DEV)
+        r3m.r3m_rcs(ctx, geom, batch, x, dirs, 1.0, sig)
+        torch.cuda.synchronize()
+        return sig.cpu().numpy(), rep
+
+    s_ref, rep_ref = solve(plain, None, 60, 1e-10, 0.0)
+    assert rep_ref[0][3]
+    _, rep_plain4 = solve(plain, None, 4, 1e-4, 0.0)
+    s_short, rep = solve(s64, s128, 4, 1e-4, 1e-9)
+    err = rel_l2(s_short, s_ref)
+    print(f"refined GMRES(4): inner iterations {rep[0][0]} (plain GMRES(4) to 1e-4: {rep_plain4[0][0]}), "
+          f"refinement steps {rep[0][1]}, residual {rep[0][2]:.2e}, RCS error {err:.2e}")
+    assert rep[0][3] and rep[0][2] <= 1e-9 and err <= 1e-7
+    assert rep[0][1] >= 1  # the refinement loop ran
+    # each inner solve is a GMRES(4) to 1e-4 on an operator within FP32
+    # rounding of the plain one: at most twice the plain solve's iterations
+    # per inner solve (refinement steps + 1 of them)
+    assert rep[0][0] <= 2 * (rep[0][1] + 1) * rep_plain4[0][0]
+
+
 @pytest.fixture(scope="module")
 def large(lib):
     from workloads.configs import large_128x128
