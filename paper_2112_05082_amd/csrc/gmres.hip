@@ -2090,8 +2090,15 @@ int r3m_gmres_solve(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z64,
       target = opts->refine_tol;
       const int max_refine = std::max(1, opts->max_refine);
       for (int step = 0; step <= max_refine; ++step) {
-        run.residual(Z64, b, x, run.W.ro);
-        std::vector<double> rn = run.host_norms(run.W.ro);
+        // x is zero at the first step: its residual is b itself
+        std::vector<double> rn;
+        if (step == 0) {
+          R3M_CHECK_HIP(hipMemcpyAsync(run.W.ro, b, (size_t)run.ut * 16, hipMemcpyDeviceToDevice, stream));
+          rn = bnorm;
+        } else {
+          run.residual(Z64, b, x, run.W.ro);
+          rn = run.host_norms(run.W.ro);
+        }
         std::vector<int> act(bd.B, 0);
         bool any = false;
         for (int i = 0; i < bd.B; ++i) {
