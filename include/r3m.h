@@ -451,7 +451,10 @@ size_t r3m_gmres_work_bytes(r3m_ctx ctx, const r3m_store* Z, const r3m_store* Z6
 
 /* Solves the retrieved systems Z_k x_b = b_b (C128 vectors) with restarted
  * GMRES(m): zero initial guess, Gram-Schmidt Arnoldi (classical, repeated
- * once) in FP64, complex Givens rotations in FP64, convergence flags on the
+ * once; on vectors above 65,536 entries per RHS the repetition runs only
+ * where the first pass kept less than a tenth of ||A v_j||, unless the
+ * environment sets R3M_CGS2_FULL=1) in FP64, complex Givens rotations in
+ * FP64, convergence flags on the
  * device.  Blocks of Arnoldi steps run as HIP graphs captured once per
  * (store, batch, workspace, m) and replayed on a context-owned stream that is
  * ordered after `stream`; the call returns with `stream` ordered after it.  The matvec runs in the precision of Z.  If Z64 (a C128 store of the

@@ -8,6 +8,7 @@
 // Gram-Schmidt with two reductions instead of j+1).  Reductions are two-stage
 // with fixed order (bitwise reproducible).  Convergence flags live on the
 // device and are read by the host once every few iterations.
+#include <cstdlib>
 #include "matvec_internal.h"
 #include "small_dense.h"
 
@@ -607,7 +608,14 @@ gs_update_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* __r
 // stay in registers, each wave sums conj(V_i) w over its lanes
 // (wave_transpose_sum) and the block adds the waves in a fixed order into
 // partial2[b][i][block].  Same arguments and outputs as gs_update_kernel with
-// nsub = 4.
+// nsub = 4.  skip_nsum (nullable; a second pass, mode 1): ||w||^2 after the
+// first pass per RHS; the pass then leaves w, its norm parts and H alone for
+// every RHS whose first pass kept ||w|| >= eta ||A v_j|| (with A v_j =
+// sum_i H[i][j] V_i + w: ||w||^2 >= eta^2 / (1 - eta^2) sum_i |H[i][j]|^2),
+// the criterion of Kahan and Parlett: after one projection the part of w
+// left in the basis's span is of the order of the rounding unit times
+// ||A v_j||, at most 1/eta times the rounding unit relative to ||w||.
+constexpr double kCgs2Eta = 0.1;
 template <int NV, typename VB, typename WB>
 __global__ void __launch_bounds__(256, NV == 20 ? 4 : 1)
 gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* __restrict__ rv,
@@ -615,7 +623,7 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
                     int nvec, int64_t ut, int do_norm, double* __restrict__ npart, int maxB,
                     double2* __restrict__ H, int m, int j, int mode, const int* __restrict__ run_prev,
                     const int* __restrict__ idle, int part_chunk, double2* __restrict__ partial2, int maxP2,
-                    const int* __restrict__ rl, int B, int64_t nb_max) {
+                    const int* __restrict__ rl, int B, int64_t nb_max, const double* __restrict__ skip_nsum) {
   if (run_prev && *run_prev == 0) return;
   constexpr bool FOLD = NV > 0;
   constexpr int kEl = 256;  // elements per block: four 64-element runs
@@ -632,6 +640,14 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
     const RhsVec r = rv[b];
     const int64_t nb = (r.N + kEl - 1) / kEl;
     if (blk >= nb) continue;
+    if (skip_nsum) {  // the same decision in every block of the RHS
+      double hh = 0.0;
+      for (int i = 0; i < nvec; ++i) {
+        const double2 h = H[(size_t)b * (m + 1) * m + (size_t)i * m + j];
+        hh += h.x * h.x + h.y * h.y;
+      }
+      if (skip_nsum[b] >= kCgs2Eta * kCgs2Eta / (1.0 - kCgs2Eta * kCgs2Eta) * hh) continue;  // uniform
+    }
     const int P = n_part > 0 ? n_part : (int)((r.N + part_chunk - 1) / part_chunk);
     // this item's element of w and of the basis (the first 8 vectors without
     // folding) are loaded before the coefficient sums, which do not need them
@@ -737,6 +753,17 @@ gs_update_el_kernel(const VB* __restrict__ V, WB* __restrict__ w, const RhsVec* 
       if (tid == 0) npart[(size_t)b * maxB + blk] = t.x;
     }
   }
+}
+
+// The second Gram-Schmidt pass of the folded updates is selective (see
+// gs_update_el_kernel's skip_nsum) unless R3M_CGS2_FULL=1 asks for it at
+// every step.
+bool selective_cgs2() {
+  static const bool sel = [] {
+    const char* env = std::getenv("R3M_CGS2_FULL");
+    return !(env && env[0] == '1');
+  }();
+  return sel;
 }
 
 // ||w|| from the per-block parts of the preceding gs_update_kernel (n_npart
@@ -1604,10 +1631,11 @@ struct GmresRun {
     // one Gram-Schmidt update (kv > 0: folding the second pass's inner
     // products): the element-parallel kernel for long vectors
     auto update = [&](int kv, const double2* hp, int hP, int hn, int do_norm, int mode, int pchunk, double2* p2,
-                      int mP2) {
+                      int mP2, const double* skip) {
+      R3M_REQUIRE(!skip || (nsub == 4 && kv == 0), R3M_ERR_UNSUPPORTED, "selective second pass on the element kernel");
       auto el = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(ugrid), dim3(256), ulds, s, V, wv, W.rv, W.st, hp, hP, hn, nvec, ut, do_norm,
-                           W.npart, maxB, W.H, m, j, mode, live, W.idle, pchunk, p2, mP2, rl, B, nb_u);
+                           W.npart, maxB, W.H, m, j, mode, live, W.idle, pchunk, p2, mP2, rl, B, nb_u, skip);
       };
       if (nsub == 4 && kv > 0) {
         // the basis count padded to a power of two
@@ -1641,22 +1669,29 @@ struct GmresRun {
                            rl, B, nb_u);
     };
     if (nvec <= fold_max_vec(maxN, sizeof(VB) == sizeof(float2)) && W.dpart2) {
-      // the first update also forms the second pass's inner products
+      // the first update also forms the second pass's inner products; on
+      // long vectors it also takes ||w||^2, and the second pass runs only
+      // where the first lost more than half of the squared norm (the first
+      // pass's norm parts then stand for the RHS that skip it)
       const int maxP2 = (int)fold_blocks(maxN);
-      update(nvec <= 8 ? 2 : 4, h0, h0P, h0n, 0, 0, kDotChunk, W.dpart2, maxP2);
+      const bool sel = long_vec && nsub == 4 && selective_cgs2();
+      update(nvec <= 8 ? 2 : 4, h0, h0P, h0n, sel ? 1 : 0, 0, kDotChunk, W.dpart2, maxP2, nullptr);
+      if (sel)
+        hipLaunchKernelGGL(finish_norm_kernel, dim3(B), dim3(256), 0, s, (const double*)W.npart, maxB, W.rv, W.nsum,
+                           live, W.idle, nsub);
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart2, maxP2,
                            nvec, W.rv, W.hsum, live, W.idle, 64 * nsub);
       update(0, long_vec ? (const double2*)W.hsum : (const double2*)W.dpart2, long_vec ? 1 : maxP2, long_vec ? 1 : 0,
-             1, 1, 64 * nsub, (double2*)nullptr, 0);
+             1, 1, 64 * nsub, (double2*)nullptr, 0, sel ? (const double*)W.nsum : nullptr);
     } else {
-      update(0, h0, h0P, h0n, 0, 0, kDotChunk, (double2*)nullptr, 0);
+      update(0, h0, h0P, h0n, 0, 0, kDotChunk, (double2*)nullptr, 0, nullptr);
       // CGS2, second pass
       dots((int*)nullptr);
       if (long_vec)
         hipLaunchKernelGGL(finish_partials_kernel, dim3(nvec, B), dim3(256), 0, s, (const double2*)W.dpart, maxP,
                            nvec, W.rv, W.hsum, live, W.idle, kDotChunk);
-      update(0, h0, h0P, h0n, 1, 1, kDotChunk, (double2*)nullptr, 0);
+      update(0, h0, h0P, h0n, 1, 1, kDotChunk, (double2*)nullptr, 0, nullptr);
     }
     if (long_vec)
       hipLaunchKernelGGL(finish_norm_kernel, dim3(B), dim3(256), 0, s, (const double*)W.npart, maxB, W.rv, W.nsum,
